@@ -1,0 +1,205 @@
+"""Plain CPU oracle for batches of group-by aggregates over a natural join.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU library
+never calls it and shares no code with it; the two meet only at the seeded
+input generators in ``workloads``.
+
+What it computes is the plain definition of the result, not the factorized
+method (section 2 of the paper, "LMFAO by Example"): D is the natural join of
+all relations of the schema, taken with bag semantics (every combination of
+matching tuples is one tuple of D); a query ``SELECT G, SUM(f_1), ..., SUM(f_m)
+FROM D WHERE P GROUP BY G`` maps every group value g that at least one tuple of
+D satisfying P carries to the sums over those tuples of each aggregate
+function.  Aggregate functions are products of attribute powers, which covers
+the aggregates section 3 lists for ridge regression (SUM(X_j*X_k), one-hot
+categoricals as group-by attributes), CART (SUM(1), SUM(Y), SUM(Y^2) under a
+conjunctive condition) and Rk-means (SUM(1) grouped by each attribute).
+
+Steps, in order:
+  1. materialise D by successive equi-joins along the join tree (bag
+     semantics; dangling tuples drop out) -- ``materialize_join``;
+  2. evaluate the predicate P per tuple of D;
+  3. group the qualifying tuples by G (``numpy.unique`` over the key columns,
+     so groups come out in lexicographic order);
+  4. per group and aggregate, add the FP64 product terms into an 80-bit
+     extended-precision accumulator (``numpy.longdouble``) and, separately,
+     the sum of absolute terms (used to bound cancellation when comparing
+     against a float kernel); counts are exact int64.
+
+Everything is FP64 (or wider) as the paper fixes no precision.  Pins that tie
+this code to something other than itself live in ``tests/test_oracle_pins.py``
+(brute force over tuple combinations, closed forms, invariants, library special
+cases); the parity readings it relies on are listed in the design doc.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["materialize_join", "evaluate", "evaluate_query", "evaluate_single",
+           "OPS"]
+
+OPS = {
+    "<=": np.less_equal, "<": np.less, ">": np.greater, ">=": np.greater_equal,
+    "==": np.equal, "!=": np.not_equal,
+}
+
+
+def _columns(problem, rel_index):
+    rel = problem["schema"][rel_index]
+    cols = problem["data"][rel["name"]]
+    return {a["name"]: np.asarray(cols[a["name"]]) for a in rel["attrs"]}
+
+
+def _equi_join(left: dict, right: dict, on: list) -> dict:
+    """Bag-semantics equi-join of two column dicts on the attribute names ``on``.
+
+    For every left tuple and every right tuple that agree on all ``on``
+    attributes, one output tuple.  Implemented with a sort of the right side and
+    range lookups; tuples without a partner drop out."""
+    n_left = len(next(iter(left.values()))) if left else 0
+    n_right = len(next(iter(right.values()))) if right else 0
+    if not on:  # cross product (disconnected pieces never occur in a tree, kept for completeness)
+        li = np.repeat(np.arange(n_left), n_right)
+        ri = np.tile(np.arange(n_right), n_left)
+    else:
+        # encode each key tuple as one int64 with a mixed radix over both sides
+        lk = np.zeros(n_left, dtype=np.int64)
+        rk = np.zeros(n_right, dtype=np.int64)
+        for a in on:
+            lv = left[a].astype(np.int64)
+            rv = right[a].astype(np.int64)
+            lo = min(lv.min(initial=0), rv.min(initial=0))
+            span = max(lv.max(initial=0), rv.max(initial=0)) - lo + 1
+            lk = lk * span + (lv - lo)
+            rk = rk * span + (rv - lo)
+        order = np.argsort(rk, kind="stable")
+        rk_sorted = rk[order]
+        lo_idx = np.searchsorted(rk_sorted, lk, side="left")
+        hi_idx = np.searchsorted(rk_sorted, lk, side="right")
+        cnt = hi_idx - lo_idx
+        li = np.repeat(np.arange(n_left), cnt)
+        start = np.repeat(lo_idx, cnt)
+        offs = np.arange(len(li)) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+        ri = order[start + offs]
+    out = {a: v[li] for a, v in left.items()}
+    for a, v in right.items():
+        if a not in out:
+            out[a] = v[ri]
+    return out
+
+
+def materialize_join(problem: dict, attrs=None) -> dict:
+    """Step 1: the natural join D of all relations, as a dict of columns.
+
+    Relations are joined in breadth-first order of the join tree starting at
+    relation 0; each join is on every attribute name the new relation shares
+    with what has been joined so far (the natural-join definition).  If
+    ``attrs`` is given, only those columns (plus join attributes) are carried."""
+    n = len(problem["schema"])
+    adj = {i: [] for i in range(n)}
+    for a, b in problem["tree"]:
+        adj[a].append(b)
+        adj[b].append(a)
+    seen = [0]
+    queue = [0]
+    while queue:
+        u = queue.pop(0)
+        for v in sorted(adj[u]):
+            if v not in seen:
+                seen.append(v)
+                queue.append(v)
+    if len(seen) != n:
+        raise ValueError("join tree does not connect every relation")
+    all_names = [{a["name"] for a in r["attrs"]} for r in problem["schema"]]
+    shared = set()
+    for i in range(n):
+        for j in range(i + 1, n):
+            shared |= all_names[i] & all_names[j]
+    keep = None if attrs is None else set(attrs) | shared
+    table = None
+    for i in seen:
+        cols = _columns(problem, i)
+        if keep is not None:
+            cols = {k: v for k, v in cols.items() if k in keep}
+        if table is None:
+            table = cols
+        else:
+            on = sorted(set(table) & set(cols))
+            table = _equi_join(table, cols, on)
+    return table
+
+
+def _mask(D, where, n):
+    m = np.ones(n, dtype=bool)
+    for attr, op, const in where:
+        m &= OPS[op](D[attr], const)
+    return m
+
+
+def _term(D, factors, sel):
+    t = np.ones(int(sel.sum()) if sel.dtype == bool else len(sel), dtype=np.float64)
+    for attr, power in factors:
+        v = D[attr][sel].astype(np.float64)
+        for _ in range(int(power)):
+            t = t * v
+    return t
+
+
+def evaluate_query(D: dict, query: dict) -> dict:
+    """Steps 2-4 for one query over the materialised join D.
+
+    Returns ``keys`` (int64, groups x |G|, lexicographically sorted), ``count``
+    (int64 join tuples per group), ``sum`` (FP64 rounding of the extended
+    precision sums, groups x aggregates) and ``abs`` (sum of |term|)."""
+    n = len(next(iter(D.values()))) if D else 0
+    sel = _mask(D, query.get("where", []), n)
+    G = list(query.get("groupby", []))
+    if G:
+        keycols = np.stack([D[g][sel].astype(np.int64) for g in G], axis=1)
+        if len(keycols):
+            keys, inv = np.unique(keycols, axis=0, return_inverse=True)
+            inv = inv.reshape(-1)
+        else:
+            keys, inv = np.zeros((0, len(G)), np.int64), np.zeros(0, np.int64)
+    else:
+        n_sel = int(sel.sum())
+        keys = np.zeros((1 if n_sel else 0, 0), dtype=np.int64)
+        inv = np.zeros(n_sel, dtype=np.int64)
+    n_groups = keys.shape[0]
+    count = np.bincount(inv, minlength=n_groups).astype(np.int64)
+    aggs = query["aggs"]
+    sums = np.zeros((n_groups, len(aggs)), dtype=np.float64)
+    abss = np.zeros((n_groups, len(aggs)), dtype=np.float64)
+    for k, factors in enumerate(aggs):
+        t = _term(D, factors, sel)
+        acc = np.zeros(n_groups, dtype=np.longdouble)
+        np.add.at(acc, inv, t.astype(np.longdouble))
+        sums[:, k] = acc.astype(np.float64)
+        abss[:, k] = np.bincount(inv, weights=np.abs(t), minlength=n_groups)
+    return {"keys": keys, "count": count, "sum": sums, "abs": abss}
+
+
+def evaluate(problem: dict, queries=None) -> list:
+    """Every query of the batch (or the listed query indices) over the
+    materialised join of ``problem``."""
+    batch = problem["batch"]
+    idx = range(len(batch)) if queries is None else queries
+    needed = set()
+    for i in idx:
+        q = batch[i]
+        needed |= set(q.get("groupby", []))
+        needed |= {w[0] for w in q.get("where", [])}
+        for f in q["aggs"]:
+            needed |= {a for a, _ in f}
+    D = materialize_join(problem, needed)
+    return [evaluate_query(D, batch[i]) for i in idx]
+
+
+def evaluate_single(problem: dict, qi: int, ai: int) -> dict:
+    """One aggregate of one query, materialising only the columns it needs
+    (used for sampled checks at full size)."""
+    q = dict(problem["batch"][qi])
+    q["aggs"] = [q["aggs"][ai]]
+    sub = dict(problem, batch=[q])
+    return evaluate(sub)[0]

@@ -1,0 +1,232 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each pin is chosen so that a plausible mistake in the oracle (a dropped join
+multiplicity, a wrong power, a group-key mix-up, a lost dangling tuple, an
+operand swap) fails at least one of them:
+
+* brute force: every combination of one tuple per relation is enumerated in
+  plain Python, kept iff all equally named attributes agree (the definition of
+  the natural join), and summed with ``math.fsum``;
+* closed forms: COUNT of a complete foreign-key star equals the fact size;
+* library special cases: a single relation's covariance batch equals ``X^T X``
+  (numpy matmul), a group-by on a key equals ``numpy.bincount``, a foreign-key
+  two-relation join equals fancy indexing;
+* invariants: group marginals add up to the ungrouped aggregate, SUM(a*b)
+  equals SUM(b*a).
+
+The planted-mistake tests at the end patch the oracle on the CPU and check that
+the pins notice.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+
+def brute_force(problem, qi):
+    """Reference by enumeration: sum over all tuple combinations that agree on
+    every shared attribute name."""
+    rels = problem["schema"]
+    data = problem["data"]
+    q = problem["batch"][qi]
+    groups = {}
+    ranges = [range(r["n_rows"]) for r in rels]
+    for combo in itertools.product(*ranges):
+        tup = {}
+        ok = True
+        for r, i in zip(rels, combo):
+            for a in r["attrs"]:
+                v = data[r["name"]][a["name"]][i]
+                v = int(v) if a["dtype"] == "i32" else float(v)
+                if a["name"] in tup and tup[a["name"]] != v:
+                    ok = False
+                    break
+                tup[a["name"]] = v
+            if not ok:
+                break
+        if not ok:
+            continue
+        if not all(oracle.OPS[op](tup[a], c) for a, op, c in q.get("where", [])):
+            continue
+        g = tuple(tup[a] for a in q.get("groupby", []))
+        slot = groups.setdefault(g, [0, [[] for _ in q["aggs"]]])
+        slot[0] += 1
+        for k, factors in enumerate(q["aggs"]):
+            t = 1.0
+            for a, p in factors:
+                t *= tup[a] ** p
+            slot[1][k].append(t)
+    keys = sorted(groups)
+    return keys, [groups[k][0] for k in keys], [[math.fsum(v) for v in groups[k][1]] for k in keys]
+
+
+def assert_matches_brute(problem):
+    res = oracle.evaluate(problem)
+    for qi, r in enumerate(res):
+        keys, counts, sums = brute_force(problem, qi)
+        assert [tuple(int(x) for x in k) for k in r["keys"]] == keys
+        assert list(r["count"]) == counts
+        if keys:
+            np.testing.assert_allclose(r["sum"], np.array(sums), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_force_random_many_to_many(seed):
+    p = W.random_acyclic(seed, n_rel=3 + seed % 2, max_rows=5, max_dom=3)
+    assert_matches_brute(p)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_random_foreign_keys(seed):
+    p = W.random_acyclic(100 + seed, n_rel=4, max_rows=6, max_dom=4, unique_dims=True)
+    assert_matches_brute(p)
+
+
+def test_brute_force_with_predicates():
+    p = W.random_acyclic(7, n_rel=3, max_rows=6, max_dom=3)
+    p["batch"] = [dict(q, where=[("x0", "<=", 0.1), ("c1", "!=", 1)]) for q in p["batch"]]
+    assert_matches_brute(p)
+
+
+def test_brute_force_worked_example_schema():
+    # the worked example's six-relation schema (Sales, Holidays, StoRes, Items,
+    # Transactions, Oil) with its three queries, on a tiny instance
+    p = W.favorita_example(0, n_sales=12)
+    # shrink the dimension grid so brute force stays small
+    assert_matches_brute(p)
+
+
+def test_count_equals_fact_size_closed_form():
+    p = W.tiny_star(seed=3, n_fact=5_000, n_stores=7, n_items=40)
+    r = oracle.evaluate(p, queries=[0])[0]
+    assert r["count"].tolist() == [5_000]
+    assert r["sum"][0, 0] == 5_000.0  # SUM(1) is the first aggregate
+
+
+def test_single_relation_is_xtx():
+    rng = np.random.default_rng(5)
+    n = 300
+    X = rng.standard_normal((n, 4))
+    schema = [{"name": "R", "n_rows": n, "attrs": [
+        {"name": f"x{j}", "dtype": "f64", "domain": 0, "key": False} for j in range(4)]}]
+    data = {"R": {f"x{j}": X[:, j] for j in range(4)}}
+    batch = W.covariance_batch([f"x{j}" for j in range(4)], ())
+    p = {"schema": schema, "tree": [], "batch": batch, "data": data}
+    r = oracle.evaluate(p)[0]
+    Xe = np.concatenate([np.ones((n, 1)), X], axis=1)
+    sigma = Xe.T @ Xe
+    want = [sigma[j, k] for j in range(5) for k in range(j, 5)]
+    np.testing.assert_allclose(r["sum"][0], want, rtol=1e-12, atol=1e-10)
+
+
+def test_groupby_key_is_bincount():
+    p = W.tiny_star(seed=1, n_fact=3_000, n_stores=9, n_items=30)
+    p["batch"] = [{"groupby": ["store"], "where": [], "aggs": [[], [("units", 1)]], "root": None}]
+    r = oracle.evaluate(p)[0]
+    s = p["data"]["S"]
+    cnt = np.bincount(s["store"], minlength=9)
+    present = np.nonzero(cnt)[0]
+    assert r["keys"][:, 0].tolist() == present.tolist()
+    assert r["count"].tolist() == cnt[present].tolist()
+    np.testing.assert_allclose(r["sum"][:, 1], np.bincount(s["store"], s["units"], 9)[present],
+                               rtol=1e-12)
+
+
+def test_fk_join_is_fancy_indexing():
+    p = W.tiny_star(seed=2, n_fact=2_000, n_stores=6, n_items=25)
+    p["batch"] = [{"groupby": [], "where": [], "root": None,
+                   "aggs": [[("units", 1), ("g2", 1)], [("f1", 1), ("g3", 1)], [("g1", 2)]]}]
+    r = oracle.evaluate(p)[0]
+    s, st, it = p["data"]["S"], p["data"]["Stores"], p["data"]["Items"]
+    g1, g2, g3 = (it[k][s["item"]] for k in ("g1", "g2", "g3"))
+    f1 = st["f1"][s["store"]]
+    want = [np.sum(s["units"] * g2), np.sum(f1 * g3), np.sum(g1 * g1)]
+    np.testing.assert_allclose(r["sum"][0], want, rtol=1e-11)
+
+
+def test_group_marginals_add_up():
+    p = W.tiny_star(seed=4, n_fact=4_000, n_stores=8, n_items=50)
+    r0, r1 = oracle.evaluate(p)
+    assert int(r1["count"].sum()) == int(r0["count"][0])
+    np.testing.assert_allclose(r1["sum"].sum(axis=0), r0["sum"][0], rtol=1e-9, atol=1e-9)
+
+
+def test_product_symmetry():
+    p = W.tiny_star(seed=6, n_fact=1_000, n_stores=5, n_items=20)
+    p["batch"] = [{"groupby": ["cat"], "where": [], "root": None,
+                   "aggs": [[("f2", 1), ("g1", 1)], [("g1", 1), ("f2", 1)]]}]
+    r = oracle.evaluate(p)[0]
+    np.testing.assert_array_equal(r["sum"][:, 0], r["sum"][:, 1])
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes: each one must be caught by a pin above
+# ---------------------------------------------------------------------------
+
+def _brute_mismatch(problem):
+    try:
+        assert_matches_brute(problem)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_planted_dropped_multiplicity_is_caught(monkeypatch):
+    real = oracle._equi_join
+
+    def dedup_join(left, right, on):  # keeps only the first partner of each tuple
+        out = real(left, right, on)
+        if not on:
+            return out
+        key = np.stack([out[a] for a in sorted(left)], axis=1)
+        _, first = np.unique(key, axis=0, return_index=True)
+        return {a: v[np.sort(first)] for a, v in out.items()}
+
+    monkeypatch.setattr(oracle, "_equi_join", dedup_join)
+    p = W.random_acyclic(3, n_rel=3, max_rows=6, max_dom=2)
+    assert _brute_mismatch(p)
+
+
+def test_planted_power_ignored_is_caught(monkeypatch):
+    def term_no_power(D, factors, sel):
+        t = np.ones(int(sel.sum()), dtype=np.float64)
+        for attr, _ in factors:
+            t = t * D[attr][sel].astype(np.float64)
+        return t
+
+    monkeypatch.setattr(oracle, "_term", term_no_power)
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((50, 2))
+    p = {"schema": [{"name": "R", "n_rows": 50, "attrs": [
+        {"name": "a", "dtype": "f64", "domain": 0, "key": False},
+        {"name": "b", "dtype": "f64", "domain": 0, "key": False}]}],
+        "tree": [], "data": {"R": {"a": X[:, 0], "b": X[:, 1]}},
+        "batch": W.covariance_batch(["a", "b"], ())}
+    r = oracle.evaluate(p)[0]
+    Xe = np.concatenate([np.ones((50, 1)), X], axis=1)
+    sigma = Xe.T @ Xe
+    want = [sigma[j, k] for j in range(3) for k in range(j, 3)]
+    assert not np.allclose(r["sum"][0], want)
+
+
+def test_planted_wrong_group_key_is_caught(monkeypatch):
+    real = oracle.evaluate_query
+
+    def swapped(D, query):
+        q = dict(query)
+        if q.get("groupby"):
+            q["groupby"] = ["store"]  # wrong attribute
+        return real(D, q)
+
+    monkeypatch.setattr(oracle, "evaluate_query", swapped)
+    p = W.tiny_star(seed=1, n_fact=2_000, n_stores=9, n_items=30)
+    r0, r1 = oracle.evaluate(p)
+    # marginals still add up, but the bincount pin on cat does not
+    it = p["data"]["Items"]
+    cat = it["cat"][p["data"]["S"]["item"]]
+    cnt = np.bincount(cat, minlength=20)
+    assert r1["count"].tolist() != cnt[np.nonzero(cnt)[0]].tolist()

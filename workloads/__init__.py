@@ -1,0 +1,407 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only *generates* inputs: relations (columns as numpy arrays), their
+schema, a join tree and a batch of group-by aggregate queries.  It holds none of
+the method's arithmetic: nothing here joins relations or evaluates aggregates.
+
+A problem is a plain dict:
+
+* ``schema``: list of relations ``{"name", "n_rows", "attrs": [{"name", "dtype",
+  "domain", "key"}]}``.  ``dtype`` is ``"i32"``, ``"f32"`` or ``"f64"``.
+  Integer attributes hold codes in ``[0, domain)``.  ``key`` marks the
+  relation's primary key (the underlined attributes of the paper's schema
+  figure).  Attributes with the same name in different relations are joined
+  (natural join).
+* ``tree``: list of ``(i, j)`` relation index pairs (the join tree).
+* ``batch``: list of queries ``{"groupby": [attr...], "where": [(attr, op,
+  const)...], "aggs": [[(attr, power)...], ...], "root": None | relation
+  name}``.  An empty factor list is ``SUM(1)``.
+* ``data``: ``{relation name: {attr name: numpy array}}``.
+* ``policy``: root-assignment policy the workload is meant to run with.
+
+Every random draw comes from ``numpy.random.Generator(PCG64)`` streams spawned
+from ``SeedSequence(seed)``, one stream per relation, so a given seed always
+yields byte-identical arrays.
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+
+import numpy as np
+
+__all__ = [
+    "zipf_keys", "tiny_star", "retail_snowflake", "grocery_star", "cart_node",
+    "rkmeans_chain", "favorita_example", "random_acyclic", "covariance_batch",
+    "problem_digest", "fact_prefix",
+]
+
+
+# --------------------------------------------------------------------------
+# samplers
+# --------------------------------------------------------------------------
+
+def zipf_keys(rng: np.random.Generator, n: int, support: int, s: float) -> np.ndarray:
+    """Keys k in [0, support) with P(k) proportional to (k+1)^-s (finite support,
+    no permutation of the ranks)."""
+    w = np.arange(1, support + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    u = rng.random(n)
+    k = np.searchsorted(cdf, u, side="right")
+    return np.minimum(k, support - 1).astype(np.int32)
+
+
+def _attr(name, dtype, domain=0, key=False):
+    return {"name": name, "dtype": dtype, "domain": int(domain), "key": bool(key)}
+
+
+def _rel(name, n_rows, attrs):
+    return {"name": name, "n_rows": int(n_rows), "attrs": attrs}
+
+
+def _spawn(seed: int, n: int):
+    return [np.random.Generator(np.random.PCG64(s))
+            for s in np.random.SeedSequence(seed).spawn(n)]
+
+
+# --------------------------------------------------------------------------
+# batches
+# --------------------------------------------------------------------------
+
+def covariance_batch(continuous, categorical=(), pairs=True, groupby_cont=True):
+    """Aggregates of the ridge-regression covariance matrix with one-hot
+    categoricals (section 3, linear regression):
+
+    * SUM(x_j * x_k) for j <= k over ``[1] + continuous`` (the intercept x_1 = 1
+      turns the first row into COUNT and SUM(x_k)),
+    * for every categorical c: SELECT c, SUM(x_k) GROUP BY c for x_k in
+      ``[1] + continuous``,
+    * for every pair of categoricals: SELECT c, c', SUM(1) GROUP BY c, c'.
+    """
+    feats = [None] + list(continuous)
+    aggs = []
+    for j in range(len(feats)):
+        for k in range(j, len(feats)):
+            fj, fk = feats[j], feats[k]
+            if fj is None and fk is None:
+                aggs.append([])
+            elif fj is None:
+                aggs.append([(fk, 1)])
+            elif fj == fk:
+                aggs.append([(fj, 2)])
+            else:
+                aggs.append([(fj, 1), (fk, 1)])
+    batch = [{"groupby": [], "where": [], "aggs": aggs, "root": None}]
+    if groupby_cont:
+        for c in categorical:
+            batch.append({"groupby": [c], "where": [],
+                          "aggs": [[]] + [[(x, 1)] for x in continuous],
+                          "root": None})
+    if pairs:
+        for a, b in itertools.combinations(categorical, 2):
+            batch.append({"groupby": [a, b], "where": [], "aggs": [[]],
+                          "root": None})
+    return batch
+
+
+# --------------------------------------------------------------------------
+# configurations
+# --------------------------------------------------------------------------
+
+def tiny_star(seed: int = 0, n_fact: int = 100_000, n_stores: int = 50,
+              n_items: int = 2_000, zipf_s: float = 1.1):
+    """Tiny star join, FP64: S(store, item, units) with Zipf(1.1) keys,
+    Stores(store, f1..f4 ~ N(0,1)), Items(item, g1..g3 ~ N(0,1), cat in [0,20)).
+    Batch: COUNT, SUM(x_i), SUM(x_i*x_j) over the 8 continuous features, and the
+    same 45 aggregates grouped by cat."""
+    r_s, r_st, r_it = _spawn(seed, 3)
+    data = {
+        "S": {
+            "store": zipf_keys(r_s, n_fact, n_stores, zipf_s),
+            "item": zipf_keys(r_s, n_fact, n_items, zipf_s),
+            "units": r_s.lognormal(0.0, 1.0, n_fact),
+        },
+        "Stores": {"store": np.arange(n_stores, dtype=np.int32)},
+        "Items": {"item": np.arange(n_items, dtype=np.int32)},
+    }
+    for j in range(1, 5):
+        data["Stores"][f"f{j}"] = r_st.standard_normal(n_stores)
+    for j in range(1, 4):
+        data["Items"][f"g{j}"] = r_it.standard_normal(n_items)
+    data["Items"]["cat"] = r_it.integers(0, 20, n_items).astype(np.int32)
+    schema = [
+        _rel("S", n_fact, [_attr("store", "i32", n_stores), _attr("item", "i32", n_items),
+                           _attr("units", "f64")]),
+        _rel("Stores", n_stores, [_attr("store", "i32", n_stores, True)]
+             + [_attr(f"f{j}", "f64") for j in range(1, 5)]),
+        _rel("Items", n_items, [_attr("item", "i32", n_items, True)]
+             + [_attr(f"g{j}", "f64") for j in range(1, 4)] + [_attr("cat", "i32", 20)]),
+    ]
+    cont = ["units", "f1", "f2", "f3", "f4", "g1", "g2", "g3"]
+    ungrouped = covariance_batch(cont, (), pairs=False, groupby_cont=False)[0]
+    grouped = dict(ungrouped, groupby=["cat"])
+    return {"name": "tiny_star", "schema": schema, "tree": [(0, 1), (0, 2)],
+            "batch": [ungrouped, grouped], "data": data, "policy": "fact",
+            "precision": "f64"}
+
+
+def retail_snowflake(seed: int = 0, n_inv: int = 84_000_000, n_locn: int = 1_300,
+                     n_dates: int = 124, n_ksn: int = 5_600, n_weather_dates: int = 846,
+                     zipf_s: float = 1.0, dtype: str = "f32"):
+    """Snowflake with 5 relations shaped like a retail inventory workload:
+    Inv(locn, date, ksn, units) with locn and date uniform and ksn Zipf(1.0);
+    Items(ksn, i1..i5, icat1, icat2); Stores(locn, zip, s1..s30, scat1, scat2);
+    Demog(zip, d1..d15); Weather(locn, date, w1..w8, wcat1, wcat2) over the
+    full (locn, date) grid.  Join tree Inv-Items, Inv-Weather, Inv-Stores,
+    Stores-Demog.  Batch: ridge covariance over 43 continuous features plus 6
+    one-hot categoricals (COUNT/SUM/products, categorical group-bys, pairs)."""
+    npdt = np.float32 if dtype == "f32" else np.float64
+    r_inv, r_it, r_st, r_dm, r_we = _spawn(seed, 5)
+    inv = {
+        "locn": r_inv.integers(0, n_locn, n_inv, dtype=np.int32),
+        "date": r_inv.integers(0, n_dates, n_inv, dtype=np.int32),
+        "ksn": zipf_keys(r_inv, n_inv, n_ksn, zipf_s),
+        "units": r_inv.lognormal(0.0, 1.0, n_inv).astype(npdt),
+    }
+    items = {"ksn": np.arange(n_ksn, dtype=np.int32)}
+    for j in range(1, 6):
+        items[f"i{j}"] = r_it.standard_normal(n_ksn).astype(npdt)
+    items["icat1"] = r_it.integers(0, 10, n_ksn, dtype=np.int32)
+    items["icat2"] = r_it.integers(0, 8, n_ksn, dtype=np.int32)
+    stores = {"locn": np.arange(n_locn, dtype=np.int32),
+              "zip": r_st.integers(0, n_locn, n_locn, dtype=np.int32)}
+    for j in range(1, 31):
+        stores[f"s{j}"] = r_st.standard_normal(n_locn).astype(npdt)
+    stores["scat1"] = r_st.integers(0, 5, n_locn, dtype=np.int32)
+    stores["scat2"] = r_st.integers(0, 4, n_locn, dtype=np.int32)
+    demog = {"zip": np.arange(n_locn, dtype=np.int32)}
+    for j in range(1, 16):
+        demog[f"d{j}"] = r_dm.standard_normal(n_locn).astype(npdt)
+    n_w = n_locn * n_weather_dates
+    weather = {"locn": np.repeat(np.arange(n_locn, dtype=np.int32), n_weather_dates),
+               "date": np.tile(np.arange(n_weather_dates, dtype=np.int32), n_locn)}
+    for j in range(1, 9):
+        weather[f"w{j}"] = r_we.standard_normal(n_w).astype(npdt)
+    weather["wcat1"] = r_we.integers(0, 3, n_w, dtype=np.int32)
+    weather["wcat2"] = r_we.integers(0, 2, n_w, dtype=np.int32)
+    data = {"Inv": inv, "Items": items, "Stores": stores, "Demog": demog, "Weather": weather}
+    f = dtype
+    schema = [
+        _rel("Inv", n_inv, [_attr("locn", "i32", n_locn), _attr("date", "i32", n_weather_dates),
+                            _attr("ksn", "i32", n_ksn), _attr("units", f)]),
+        _rel("Items", n_ksn, [_attr("ksn", "i32", n_ksn, True)]
+             + [_attr(f"i{j}", f) for j in range(1, 6)]
+             + [_attr("icat1", "i32", 10), _attr("icat2", "i32", 8)]),
+        _rel("Stores", n_locn, [_attr("locn", "i32", n_locn, True), _attr("zip", "i32", n_locn)]
+             + [_attr(f"s{j}", f) for j in range(1, 31)]
+             + [_attr("scat1", "i32", 5), _attr("scat2", "i32", 4)]),
+        _rel("Demog", n_locn, [_attr("zip", "i32", n_locn, True)]
+             + [_attr(f"d{j}", f) for j in range(1, 16)]),
+        _rel("Weather", n_w, [_attr("locn", "i32", n_locn, True),
+                              _attr("date", "i32", n_weather_dates, True)]
+             + [_attr(f"w{j}", f) for j in range(1, 9)]
+             + [_attr("wcat1", "i32", 3), _attr("wcat2", "i32", 2)]),
+    ]
+    cont = (["units"] + [f"i{j}" for j in range(1, 6)] + [f"s{j}" for j in range(1, 15)]
+            + [f"d{j}" for j in range(1, 16)] + [f"w{j}" for j in range(1, 9)])
+    cats = ["icat1", "icat2", "scat1", "scat2", "wcat1", "wcat2"]
+    return {"name": "retail_snowflake", "schema": schema,
+            "tree": [(0, 1), (0, 4), (0, 2), (2, 3)],
+            "batch": covariance_batch(cont, cats), "data": data, "policy": "fact",
+            "precision": dtype}
+
+
+def grocery_star(seed: int = 0, n_sales: int = 120_000_000, n_stores: int = 54,
+                 n_items: int = 4_000, n_dates: int = 1_537, n_oil: int = 1_200,
+                 n_hol: int = 350, dtype: str = "f32"):
+    """Star join with 6 relations shaped like grocery sales (the schema of the
+    paper's worked example): Sales(date, store, item, unit_sales, onpromo),
+    Items(item, family, class, perishable), Stores(store, city, state, stype,
+    cluster), Trans(date, store, txns), Oil(date, price), Holidays(date, htype,
+    locale).  Join tree Sales-Trans, Trans-Stores, Trans-Oil, Sales-Items,
+    Sales-Holidays.  Sales dates are drawn from the holiday dates so that every
+    fact row joins."""
+    npdt = np.float32 if dtype == "f32" else np.float64
+    r_sa, r_it, r_st, r_tr, r_oi, r_ho = _spawn(seed, 6)
+    oil_dates = np.sort(r_oi.choice(n_dates, n_oil, replace=False)).astype(np.int32)
+    hol_dates = np.sort(r_ho.choice(oil_dates, n_hol, replace=False)).astype(np.int32)
+    sales = {
+        "date": hol_dates[r_sa.integers(0, n_hol, n_sales)].astype(np.int32),
+        "store": r_sa.integers(0, n_stores, n_sales, dtype=np.int32),
+        "item": zipf_keys(r_sa, n_sales, n_items, 1.0),
+        "unit_sales": r_sa.lognormal(0.0, 1.0, n_sales).astype(npdt),
+        "onpromo": (r_sa.random(n_sales) < 0.1).astype(np.int32),
+    }
+    cls = r_it.integers(0, 337, n_items, dtype=np.int32)
+    items = {"item": np.arange(n_items, dtype=np.int32), "class": cls,
+             "family": (cls % 33).astype(np.int32),
+             "perishable": (r_it.random(n_items) < 0.25).astype(np.int32)}
+    city = r_st.integers(0, 22, n_stores, dtype=np.int32)
+    stores = {"store": np.arange(n_stores, dtype=np.int32), "city": city,
+              "state": (city % 16).astype(np.int32),
+              "stype": r_st.integers(0, 5, n_stores, dtype=np.int32),
+              "cluster": r_st.integers(0, 17, n_stores, dtype=np.int32)}
+    trans = {"date": np.repeat(np.arange(n_dates, dtype=np.int32), n_stores),
+             "store": np.tile(np.arange(n_stores, dtype=np.int32), n_dates)}
+    trans["txns"] = r_tr.lognormal(7.0, 0.5, n_dates * n_stores).astype(npdt)
+    oil = {"date": oil_dates, "price": r_oi.uniform(30.0, 110.0, n_oil).astype(npdt)}
+    hol = {"date": hol_dates, "htype": r_ho.integers(0, 6, n_hol, dtype=np.int32),
+           "locale": r_ho.integers(0, 3, n_hol, dtype=np.int32)}
+    data = {"Sales": sales, "Trans": trans, "Stores": stores, "Oil": oil,
+            "Items": items, "Holidays": hol}
+    f = dtype
+    schema = [
+        _rel("Sales", n_sales, [_attr("date", "i32", n_dates), _attr("store", "i32", n_stores),
+                                _attr("item", "i32", n_items), _attr("unit_sales", f),
+                                _attr("onpromo", "i32", 2)]),
+        _rel("Trans", n_dates * n_stores, [_attr("date", "i32", n_dates, True),
+                                           _attr("store", "i32", n_stores, True),
+                                           _attr("txns", f)]),
+        _rel("Stores", n_stores, [_attr("store", "i32", n_stores, True), _attr("city", "i32", 22),
+                                  _attr("state", "i32", 16), _attr("stype", "i32", 5),
+                                  _attr("cluster", "i32", 17)]),
+        _rel("Oil", n_oil, [_attr("date", "i32", n_dates, True), _attr("price", f)]),
+        _rel("Items", n_items, [_attr("item", "i32", n_items, True), _attr("family", "i32", 33),
+                                _attr("class", "i32", 337), _attr("perishable", "i32", 2)]),
+        _rel("Holidays", n_hol, [_attr("date", "i32", n_dates, True), _attr("htype", "i32", 6),
+                                 _attr("locale", "i32", 3)]),
+    ]
+    cont = ["unit_sales", "txns", "price"]
+    cats = ["onpromo", "family", "class", "perishable", "city", "state", "stype",
+            "cluster", "htype", "locale"]
+    return {"name": "grocery_star", "schema": schema,
+            "tree": [(0, 1), (1, 2), (1, 3), (0, 4), (0, 5)],
+            "batch": covariance_batch(cont, cats), "data": data, "policy": "fact",
+            "precision": dtype}
+
+
+def favorita_example(seed: int = 0, n_sales: int = 40):
+    """Tiny instance of the worked example's schema (Sales, Holidays, StoRes,
+    Items, Transactions, Oil) with the three example queries (Q2 and Q3 use
+    plain attributes in place of the user-defined functions g and h).  Used for
+    the planner's structural tests and brute-force oracle pins."""
+    r = _spawn(seed, 6)
+    n_dates, n_stores, n_items = 4, 3, 5
+    sales = {"date": r[0].integers(0, n_dates, n_sales, dtype=np.int32),
+             "store": r[0].integers(0, n_stores, n_sales, dtype=np.int32),
+             "item": r[0].integers(0, n_items, n_sales, dtype=np.int32),
+             "units": r[0].lognormal(0, 1, n_sales),
+             "promo": r[0].integers(0, 2, n_sales, dtype=np.int32)}
+    hol = {"date": np.arange(n_dates, dtype=np.int32), "htype": r[1].integers(0, 3, n_dates, dtype=np.int32)}
+    stores = {"store": np.arange(n_stores, dtype=np.int32), "city": r[2].integers(0, 2, n_stores, dtype=np.int32)}
+    items = {"item": np.arange(n_items, dtype=np.int32),
+             "class": r[3].integers(0, 3, n_items, dtype=np.int32),
+             "g": r[3].standard_normal(n_items)}
+    trans = {"date": np.repeat(np.arange(n_dates, dtype=np.int32), n_stores),
+             "store": np.tile(np.arange(n_stores, dtype=np.int32), n_dates),
+             "txns": r[4].lognormal(0, 1, n_dates * n_stores)}
+    oil = {"date": np.arange(n_dates, dtype=np.int32), "price": r[5].uniform(1, 2, n_dates),
+           "h": r[5].standard_normal(n_dates)}
+    data = {"Sales": sales, "Holidays": hol, "StoRes": stores, "Items": items,
+            "Transactions": trans, "Oil": oil}
+    schema = [
+        _rel("Sales", n_sales, [_attr("date", "i32", n_dates), _attr("store", "i32", n_stores),
+                                _attr("item", "i32", n_items), _attr("units", "f64"),
+                                _attr("promo", "i32", 2)]),
+        _rel("Holidays", n_dates, [_attr("date", "i32", n_dates, True), _attr("htype", "i32", 3)]),
+        _rel("StoRes", n_stores, [_attr("store", "i32", n_stores, True), _attr("city", "i32", 2)]),
+        _rel("Items", n_items, [_attr("item", "i32", n_items, True), _attr("class", "i32", 3),
+                                _attr("g", "f64")]),
+        _rel("Transactions", n_dates * n_stores, [_attr("date", "i32", n_dates, True),
+                                                  _attr("store", "i32", n_stores, True),
+                                                  _attr("txns", "f64")]),
+        _rel("Oil", n_dates, [_attr("date", "i32", n_dates, True), _attr("price", "f64"),
+                              _attr("h", "f64")]),
+    ]
+    # join tree of the example: S-T, T-R, T-O, S-I, S-H
+    tree = [(0, 4), (4, 2), (4, 5), (0, 3), (0, 1)]
+    batch = [
+        {"groupby": [], "where": [], "aggs": [[("units", 1)]], "root": None},
+        {"groupby": ["store"], "where": [], "aggs": [[("g", 1), ("h", 1)]], "root": None},
+        {"groupby": ["class"], "where": [], "aggs": [[("units", 1), ("price", 1)]], "root": None},
+    ]
+    return {"name": "favorita_example", "schema": schema, "tree": tree, "batch": batch,
+            "data": data, "policy": "groupby", "precision": "f64"}
+
+
+def random_acyclic(seed: int, n_rel: int = 4, max_rows: int = 6, max_dom: int = 3,
+                   dangling: bool = True, unique_dims: bool = False, n_queries: int = 4):
+    """Small random acyclic schema for property tests: a random tree over
+    ``n_rel`` relations, each edge joined on one fresh shared integer attribute
+    (domain ``max_dom``), plus one float feature and one categorical per
+    relation.  Join keys may repeat (many-to-many) and may dangle.  With
+    ``unique_dims`` every non-root relation is keyed by its parent edge
+    attribute, so each child row appears at most once per key (FK joins)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    parent = [-1] + [int(rng.integers(0, i)) for i in range(1, n_rel)]
+    tree = [(parent[i], i) for i in range(1, n_rel)]
+    attrs = [[] for _ in range(n_rel)]
+    for i in range(1, n_rel):
+        ja = f"k{i}"
+        attrs[parent[i]].append(_attr(ja, "i32", max_dom))
+        attrs[i].append(_attr(ja, "i32", max_dom, key=unique_dims))
+    schema, data = [], {}
+    for i in range(n_rel):
+        name = f"R{i}"
+        if unique_dims and i > 0:
+            n = max_dom if not dangling else int(rng.integers(1, max_dom + 1))
+        else:
+            n = int(rng.integers(1, max_rows + 1))
+        cols = {}
+        for a in attrs[i]:
+            if unique_dims and i > 0 and a["key"]:
+                cols[a["name"]] = rng.permutation(max_dom)[:n].astype(np.int32)
+            else:
+                cols[a["name"]] = rng.integers(0, max_dom, n).astype(np.int32)
+        cols[f"x{i}"] = np.round(rng.standard_normal(n), 3)
+        cols[f"c{i}"] = rng.integers(0, 3, n).astype(np.int32)
+        full = attrs[i] + [_attr(f"x{i}", "f64"), _attr(f"c{i}", "i32", 3)]
+        schema.append(_rel(name, n, full))
+        data[name] = cols
+    feats = [f"x{i}" for i in range(n_rel)]
+    cats = [f"c{i}" for i in range(n_rel)]
+    batch = []
+    for _ in range(n_queries):
+        g = list(rng.choice(cats, size=int(rng.integers(0, 3)), replace=False))
+        aggs = [[]]
+        for _ in range(3):
+            deg = int(rng.integers(1, 3))
+            fs = list(rng.choice(feats, size=deg, replace=True))
+            if deg == 2 and fs[0] == fs[1]:
+                aggs.append([(str(fs[0]), 2)])
+            else:
+                aggs.append([(str(f), 1) for f in fs])
+        batch.append({"groupby": [str(x) for x in g], "where": [], "aggs": aggs, "root": None})
+    return {"name": f"random_acyclic_{seed}", "schema": schema, "tree": tree,
+            "batch": batch, "data": data, "policy": "groupby", "precision": "f64"}
+
+
+def fact_prefix(problem: dict, rel: str, n: int) -> dict:
+    """Copy of ``problem`` whose relation ``rel`` keeps only its first ``n`` rows
+    (used for bounded CPU-baseline samples)."""
+    out = dict(problem)
+    out["data"] = dict(problem["data"])
+    out["data"][rel] = {k: v[:n] for k, v in problem["data"][rel].items()}
+    out["schema"] = [dict(r, n_rows=(n if r["name"] == rel else r["n_rows"]))
+                     for r in problem["schema"]]
+    return out
+
+
+def problem_digest(problem: dict) -> str:
+    """SHA-256 over every generated column (determinism check and cache key)."""
+    h = hashlib.sha256()
+    for rname in sorted(problem["data"]):
+        for aname in sorted(problem["data"][rname]):
+            h.update(f"{rname}.{aname}".encode())
+            h.update(np.ascontiguousarray(problem["data"][rname][aname]).tobytes())
+    return h.hexdigest()
+
+
+# remaining configurations are added as their hot-path rows are built
+def cart_node(*a, **k):  # pragma: no cover - placeholder until the CART row is built
+    raise NotImplementedError("CART node batch generator is not built yet")
+
+
+def rkmeans_chain(*a, **k):  # pragma: no cover
+    raise NotImplementedError("Rk-means chain generator is not built yet")
