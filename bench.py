@@ -1,0 +1,156 @@
+#!/usr/bin/env python
+"""Benchmark of the aggregate-batch hot path on one MI355X.
+
+Workload (default): the retail-shaped snowflake -- Inv(locn, date, ksn, units)
+84M rows (locn uniform over 1.3k, date uniform over 124, ksn Zipf(1.0) over
+5.6k), Items 5.6k, Stores 1.3k, Demog 1.3k, Weather 1.1M (full locn x date
+grid) -- with the ridge covariance batch over 43 continuous features plus 6
+one-hot categoricals: 1,269 aggregate queries (one SUM each), FP32 scans,
+FP64 merges and results.  Synthetic data, seed 0.
+
+One step = one ``lmfao_run``: every view and every query of the plan, on the
+GPU, inputs already resident in HBM (prepare -- sorting and trie pieces -- is
+done once before the timed region and reported separately).
+
+metric: join-tuple-aggregates/s = |D| * A / t_step, with |D| = 84M join tuples
+(every fact row joins exactly once) and A = 1,269 SUM expressions.
+
+Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits: this
+build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+
+def _cpu_baseline(problem, n_rows, budget_s):
+    """The oracle, as it stands, on a bounded prefix of the fact table."""
+    import oracle
+    import workloads as W
+    fact = max(problem["schema"], key=lambda r: r["n_rows"])["name"]
+    sample = W.fact_prefix(problem, fact, n_rows)
+    t0 = time.perf_counter()
+    res = oracle.evaluate(sample)
+    dt = time.perf_counter() - t0
+    n_aggs = sum(len(q["aggs"]) for q in problem["batch"])
+    return {"value": n_rows * n_aggs / dt, "unit": "join-tuple-aggregates/s", "cores": 1,
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"first {n_rows} of {problem['schema'][0]['n_rows']} {fact} rows, full dimension "
+                      f"tables, all {len(problem['batch'])} queries (numpy FP64 with 80-bit accumulation, "
+                      f"single thread)"}, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="retail", choices=["retail", "tiny"])
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the fact table (testing only)")
+    ap.add_argument("--cpu-rows", type=int, default=150_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2008_08657_amd as E
+
+    E.load_library()
+    t_gen = time.perf_counter()
+    if args.config == "retail":
+        n_inv = int(84_000_000 * args.scale)
+        problem = W.retail_snowflake(seed=0, n_inv=n_inv)
+        precision, workload = "f32", "retail-shaped snowflake (Inv 84M x 5 relations), covariance + 6 one-hot categoricals"
+    else:
+        problem = W.tiny_star(seed=0)
+        precision, workload = "f64", "tiny star (S 100k x 3 relations), covariance grouped by cat"
+    fact = max(problem["schema"], key=lambda r: r["n_rows"])
+    n_join = fact["n_rows"]   # every fact row joins exactly once (complete foreign keys)
+    n_aggs = sum(len(q["aggs"]) for q in problem["batch"])
+    t_gen = time.perf_counter() - t_gen
+
+    plan = E.Plan(problem, precision=precision, policy=problem["policy"])
+    cols = E.device_columns(problem)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter()
+    prep = E.Prepared(plan, cols)
+    t_prep = time.perf_counter() - t_prep
+    del cols
+    torch.cuda.empty_cache()
+
+    for _ in range(args.warmup):
+        prep.run(sync=False)
+    prep.run(sync=True)   # checks the kernels' error flags once
+    torch.cuda.synchronize()
+
+    prep.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prep.run(sync=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    prep.set_timing(False)
+    timing = prep.timing()          # mean ms per timed launch over the timed steps
+    desc = prep.describe()
+    ms_per_step = 1e3 * t / args.steps
+
+    # dominant kernel: the timed launch with the largest mean duration
+    steps = {s["name"]: s for s in desc["steps"]}
+    kern = max((x for x in timing if x[0] != "run"), key=lambda x: x[1])
+    kd = steps[kern[0]]
+    kern_ms = kern[1]
+    alg_bytes = kd["alg_read_bytes"] + kd["alg_write_bytes"]
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(achieved / 8000.0, 4), "traffic": None,
+                "kernel": kern[0], "kernel_ms": round(kern_ms, 4),
+                "alg_bytes": int(alg_bytes)}
+
+    # sanity on the GPU results: COUNT equals |D| (closed form)
+    check = {}
+    if not args.no_check:
+        r0 = prep.result(0)
+        check["count_equals_join_size"] = bool(int(r0["count"][0]) == n_join
+                                                and float(r0["sum"][0, 0]) == float(n_join))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, _ = _cpu_baseline(problem, min(args.cpu_rows, n_join), 30.0)
+
+    out = {
+        "metric": "join-tuple-aggregates/s",
+        "value": n_join * n_aggs / (ms_per_step * 1e-3),
+        "unit": "join-tuple*aggregates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if precision == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "join_tuples": n_join, "aggregates": n_aggs,
+                   "queries": len(problem["batch"]), "precision": precision,
+                   "form": "fused", "root_policy": problem["policy"], "seed": 0,
+                   "prepare_s": round(t_prep, 2), "generate_s": round(t_gen, 2)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels_ms": {k: round(v, 4) for k, v in timing},
+        "check": check,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

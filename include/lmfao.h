@@ -1,0 +1,244 @@
+/*
+ * lmfao.h -- C ABI of the MI355X (gfx950) engine for batches of group-by
+ * aggregates over the natural join of several relations.
+ *
+ * The operation (paper, section 2 "LMFAO by Example", and section 3 "From
+ * Learning to Aggregates"): given a database schema, a join tree over its
+ * relations and a batch of queries
+ *
+ *     SELECT G, SUM(f_1), ..., SUM(f_m) FROM D WHERE P GROUP BY G
+ *
+ * where D is the natural join of all relations (bag semantics), compute every
+ * query's result.  The engine follows the paper's plan: each query gets a root
+ * relation and is decomposed into one view per join-tree edge, views with the
+ * same direction, group-by attributes and condition are merged, views and
+ * queries leaving the same relation are grouped, and each group is computed
+ * in one pass over its relation sorted by a total order of its join
+ * attributes, with lookups into the incoming views and partial aggregates
+ * factored out of the inner loops (section 2, view generation and
+ * multi-output optimization layers; Figure 2 and Figure 3).
+ *
+ * Supported query class (anything else returns LMFAO_EUNSUPPORTED from
+ * lmfao_plan):
+ *   - aggregate functions are products of attribute powers of total degree
+ *     <= 2 (COUNT = the empty product), the forms section 3 lists for ridge
+ *     regression, CART split statistics and Rk-means;
+ *   - at most 2 group-by attributes per query, each an integer attribute with
+ *     a domain hint (values in [0, domain));
+ *   - every join attribute is an integer attribute with a domain hint;
+ *   - conditions (WHERE) are accepted by the planner but not yet executed on
+ *     the GPU (LMFAO_EUNSUPPORTED from lmfao_plan when present).
+ *
+ * Conventions for every entry point:
+ *   - all pointers to schema, tree, batch and option structs are host
+ *     pointers, read during the call only; the library copies what it keeps;
+ *   - relation column pointers passed to lmfao_prepare are DEVICE pointers
+ *     (HIP global memory on the current device), one contiguous column per
+ *     attribute, int32 / float32 / float64 as declared; they are read during
+ *     lmfao_prepare only (the library keeps sorted device copies);
+ *   - `stream` arguments are hipStream_t handles passed as void* (NULL = the
+ *     default stream); all device work of a call is enqueued on that stream;
+ *   - status codes are returned, never exceptions; on failure
+ *     lmfao_last_error() returns a thread-local, NUL-terminated description
+ *     valid until the next call on the same thread;
+ *   - handles (plan, prepared, result) are opaque and owned by the library;
+ *     free them with the matching *_free call.  A plan is immutable and may be
+ *     shared; a prepared handle serializes its runs (one run at a time).
+ */
+#ifndef LMFAO_H
+#define LMFAO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lmfao_status;
+enum {
+  LMFAO_OK = 0,
+  LMFAO_EINVAL = 1,        /* malformed input: bad tree, unknown attribute, ...   */
+  LMFAO_ENOMEM = 2,        /* device or host allocation failed                    */
+  LMFAO_EHIP = 3,          /* a HIP runtime call failed (text in last_error)       */
+  LMFAO_EUNSUPPORTED = 4,  /* valid input outside the supported query class        */
+  LMFAO_EOVERFLOW = 5      /* a group-by table could not be sized                  */
+};
+
+enum { LMFAO_I32 = 0, LMFAO_F32 = 1, LMFAO_F64 = 2 };
+
+/* One attribute of a relation.  `domain` > 0 declares integer values in
+ * [0, domain) -- the paper's cardinality constraints ("sizes of relations and
+ * attribute domains", section 2, view generation layer).  `is_key` marks the
+ * relation's primary key (underlined attributes in the schema of Figure 2);
+ * the engine relies on it only to know that a relation has at most one tuple
+ * per key value, and checks that during lmfao_run (LMFAO_EINVAL on a
+ * duplicate key). */
+typedef struct {
+  const char* name;
+  int32_t dtype;    /* LMFAO_I32 / LMFAO_F32 / LMFAO_F64 */
+  int64_t domain;   /* integer attributes: values in [0, domain); 0 = none */
+  int32_t is_key;
+} lmfao_attr;
+
+typedef struct {
+  const char* name;
+  int64_t n_rows;
+  int32_t n_attrs;
+  const lmfao_attr* attrs;
+} lmfao_relation;
+
+typedef struct {
+  int32_t n_relations;
+  const lmfao_relation* relations;
+} lmfao_schema;
+
+/* Join tree: undirected edges between relation indices.  It must connect all
+ * relations, be acyclic, and satisfy the running-intersection property (the
+ * relations holding an attribute form a connected subtree).  Two adjacent
+ * relations join on every attribute name they share (natural join). */
+typedef struct { int32_t a, b; } lmfao_edge;
+typedef struct {
+  int32_t n_edges;
+  const lmfao_edge* edges;
+} lmfao_join_tree;
+
+/* An aggregate function: the product of `attr`^`power` over its factors;
+ * n_factors == 0 is SUM(1).  power is 1 or 2. */
+typedef struct { const char* attr; int32_t power; } lmfao_factor;
+typedef struct {
+  int32_t n_factors;
+  const lmfao_factor* factors;
+} lmfao_aggregate;
+
+enum { LMFAO_LE = 0, LMFAO_LT = 1, LMFAO_GT = 2, LMFAO_GE = 3, LMFAO_EQ = 4, LMFAO_NE = 5 };
+typedef struct { const char* attr; int32_t op; double constant; } lmfao_condition;
+
+typedef struct {
+  int32_t n_groupby;
+  const char* const* groupby;
+  int32_t n_conditions;
+  const lmfao_condition* conditions;
+  int32_t n_aggregates;
+  const lmfao_aggregate* aggregates;
+  int32_t root;        /* relation index, or -1 for the root heuristic */
+} lmfao_query;
+
+typedef struct {
+  int32_t n_queries;
+  const lmfao_query* queries;
+} lmfao_batch;
+
+enum { LMFAO_PREC_F64 = 0, LMFAO_PREC_F32 = 1 };
+enum { LMFAO_FORM_FUSED = 0, LMFAO_FORM_PER_VIEW = 1 };
+/* Root heuristics.  GROUPBY: the relation holding every group-by attribute,
+ * the largest such relation (reproduces the roots of the worked example);
+ * FACT: the largest relation from which every group-by attribute is reached
+ * through primary-key joins (carried as a code by single-valued views), and
+ * queries over the attributes of a single relation are rooted there. */
+enum { LMFAO_ROOT_GROUPBY = 0, LMFAO_ROOT_FACT = 1 };
+
+typedef struct {
+  int32_t precision;     /* LMFAO_PREC_*: arithmetic of the scans and views;
+                            merges and query results are always FP64        */
+  int32_t form;          /* LMFAO_FORM_*                                     */
+  int32_t root_policy;   /* LMFAO_ROOT_*                                     */
+  /* optional attribute order per relation: order[r] lists n_order[r] join
+   * attribute names of relation r, outermost first (NULL = heuristic) */
+  const int32_t* n_order;
+  const char* const* const* order;
+  int32_t min_segment;   /* cut level: shortest average segment the factorized
+                            scan accepts (0 = default 64)                    */
+  int64_t row_piece_max; /* relations with at most this many rows are
+                            contracted row by row without a scan
+                            (0 = default 2^21; -1 = always scan)             */
+} lmfao_options;
+
+typedef struct lmfao_plan_s* lmfao_plan_t;
+typedef struct lmfao_prepared_s* lmfao_prepared_t;
+typedef struct lmfao_result_s* lmfao_result_t;
+
+/* Fills `opts` with the defaults (F64, FUSED, GROUPBY, heuristic orders). */
+void lmfao_default_options(lmfao_options* opts);
+
+/* Validates schema, tree and batch and builds the plan on the host (no device
+ * work): root per query, views per edge, merged views, groups and their
+ * dependency levels, attribute orders, factorized per-group programs.
+ * Errors: LMFAO_EINVAL (malformed), LMFAO_EUNSUPPORTED (outside the class). */
+lmfao_status lmfao_plan(const lmfao_schema* schema, const lmfao_join_tree* tree,
+                        const lmfao_batch* batch, const lmfao_options* opts,
+                        lmfao_plan_t* out);
+
+/* JSON description of the plan (roots, views, groups, dependency edges,
+ * orders, per-group programs).  Writes at most `cap` bytes including the NUL
+ * into `buf` (may be NULL when cap == 0) and the full size into *need. */
+lmfao_status lmfao_plan_describe(lmfao_plan_t plan, char* buf, size_t cap, size_t* need);
+
+/* Device bytes lmfao_prepare and lmfao_run will hold for this plan and these
+ * relation sizes (estimate, excluding data-dependent piece tables). */
+lmfao_status lmfao_plan_workspace_bytes(lmfao_plan_t plan, size_t* bytes);
+
+/* Copies and sorts the relations each factorized group scans (by the group's
+ * attribute order, on the GPU), builds their segment ("trie level") tables
+ * and allocates every view and result buffer.  `columns[r][a]` is the device
+ * pointer of attribute a of relation r (schema order).  Synchronizes
+ * `stream` before returning.  The caller's columns may be freed afterwards. */
+lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns,
+                           void* stream, lmfao_prepared_t* out);
+
+/* Evaluates the whole batch: every view and query of the plan, level by
+ * level, on `stream`.  Enqueue only: returns once the work is queued unless
+ * `sync` is nonzero (then it synchronizes and checks key-uniqueness and
+ * kernel error flags).  Results live in device buffers owned by `prep` and
+ * are overwritten by the next lmfao_run on the same handle. */
+lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, int32_t sync);
+
+/* Result of query q after a completed run: number of present groups (groups
+ * with at least one join tuple; lexicographic key order), number of group-by
+ * attributes and aggregates. */
+lmfao_status lmfao_result_shape(lmfao_prepared_t prep, int32_t q, int64_t* n_groups,
+                                int32_t* n_keys, int32_t* n_aggs);
+
+/* Copies query q's result to HOST buffers: keys (n_groups x n_keys int64, may
+ * be NULL), counts (n_groups int64, may be NULL), values (n_groups x n_aggs
+ * double, may be NULL).  Synchronizes the device. */
+lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys,
+                               int64_t* counts, double* values);
+
+/* Intermediate view v (plan description order) after a completed run: its
+ * dense key domain size, value columns and code columns; and a copy to HOST
+ * buffers: counts (n_keys int64), values (n_keys x n_vals double, converted
+ * from the view's storage precision), codes (n_keys x n_codes int32).  Any
+ * pointer may be NULL.  Synchronizes the device. */
+lmfao_status lmfao_view_shape(lmfao_prepared_t prep, int32_t v, int64_t* n_keys, int32_t* n_vals,
+                              int32_t* n_codes);
+lmfao_status lmfao_view_copy(lmfao_prepared_t prep, int32_t v, int64_t* counts, double* values,
+                             int32_t* codes);
+
+/* Kernel timing.  While timing is on, every lmfao_run records HIP events on
+ * its stream around the whole run and around each scan and contraction
+ * launch.  lmfao_run_timing synchronizes the device and returns, for the runs
+ * recorded since its previous call, the mean milliseconds of the whole run
+ * (entry 0, name "run") and of each timed launch (entries 1..), filling up to
+ * `cap` names/ms (names stay valid while `prep` lives) and the count in *n. */
+lmfao_status lmfao_set_timing(lmfao_prepared_t prep, int32_t on);
+lmfao_status lmfao_run_timing(lmfao_prepared_t prep, int32_t cap, const char** names,
+                              float* ms, int32_t* n);
+
+/* JSON description of the prepared launch sequence: per step its name, kind,
+ * rows and pieces, and the algorithmic bytes read / written and arithmetic
+ * (flop) the step must do at minimum (computed on the host from sizes), plus
+ * the bytes zero-filled at the start of each run.  Same buffer convention as
+ * lmfao_plan_describe. */
+lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t cap, size_t* need);
+
+void lmfao_plan_free(lmfao_plan_t plan);
+void lmfao_prepared_free(lmfao_prepared_t prep);
+
+/* Thread-local text of the last error (empty string if none). */
+const char* lmfao_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMFAO_H */

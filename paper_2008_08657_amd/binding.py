@@ -1,0 +1,329 @@
+"""ctypes binding of ``liblmfao.so`` (argument marshalling only).
+
+The functions mirror the C ABI in ``include/lmfao.h``; every step of the
+evaluation runs in the library's HIP kernels.  PyTorch only provides device
+memory for the input columns and the stream handle.  The library must have
+been built (``python -m paper_2008_08657_amd.build``); loading fails loudly
+otherwise -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblmfao.so")
+
+I32, F32, F64 = 0, 1, 2
+PREC_F64, PREC_F32 = 0, 1
+FORM_FUSED, FORM_PER_VIEW = 0, 1
+ROOT_GROUPBY, ROOT_FACT = 0, 1
+OPS = {"<=": 0, "<": 1, ">": 2, ">=": 3, "==": 4, "!=": 5}
+_DTYPES = {"i32": I32, "f32": F32, "f64": F64}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED", 5: "EOVERFLOW"}
+
+
+class lmfao_attr(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("dtype", C.c_int32), ("domain", C.c_int64), ("is_key", C.c_int32)]
+
+
+class lmfao_relation(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("n_rows", C.c_int64), ("n_attrs", C.c_int32),
+                ("attrs", C.POINTER(lmfao_attr))]
+
+
+class lmfao_schema(C.Structure):
+    _fields_ = [("n_relations", C.c_int32), ("relations", C.POINTER(lmfao_relation))]
+
+
+class lmfao_edge(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32)]
+
+
+class lmfao_join_tree(C.Structure):
+    _fields_ = [("n_edges", C.c_int32), ("edges", C.POINTER(lmfao_edge))]
+
+
+class lmfao_factor(C.Structure):
+    _fields_ = [("attr", C.c_char_p), ("power", C.c_int32)]
+
+
+class lmfao_aggregate(C.Structure):
+    _fields_ = [("n_factors", C.c_int32), ("factors", C.POINTER(lmfao_factor))]
+
+
+class lmfao_condition(C.Structure):
+    _fields_ = [("attr", C.c_char_p), ("op", C.c_int32), ("constant", C.c_double)]
+
+
+class lmfao_query(C.Structure):
+    _fields_ = [("n_groupby", C.c_int32), ("groupby", C.POINTER(C.c_char_p)),
+                ("n_conditions", C.c_int32), ("conditions", C.POINTER(lmfao_condition)),
+                ("n_aggregates", C.c_int32), ("aggregates", C.POINTER(lmfao_aggregate)),
+                ("root", C.c_int32)]
+
+
+class lmfao_batch(C.Structure):
+    _fields_ = [("n_queries", C.c_int32), ("queries", C.POINTER(lmfao_query))]
+
+
+class lmfao_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("form", C.c_int32), ("root_policy", C.c_int32),
+                ("n_order", C.POINTER(C.c_int32)), ("order", C.POINTER(C.POINTER(C.c_char_p))),
+                ("min_segment", C.c_int32), ("row_piece_max", C.c_int64)]
+
+
+class LmfaoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads the engine library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2008_08657_amd.build`")
+    # PyTorch ships its own HIP runtime with the same soname; load it first so
+    # the process holds one runtime, shared by torch's tensors and this library
+    import torch  # noqa: F401
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.lmfao_default_options.argtypes = [C.POINTER(lmfao_options)]
+    lib.lmfao_default_options.restype = None
+    lib.lmfao_plan.argtypes = [C.POINTER(lmfao_schema), C.POINTER(lmfao_join_tree), C.POINTER(lmfao_batch),
+                               C.POINTER(lmfao_options), C.POINTER(vp)]
+    lib.lmfao_plan.restype = C.c_int32
+    lib.lmfao_plan_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.lmfao_plan_describe.restype = C.c_int32
+    lib.lmfao_plan_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.lmfao_plan_workspace_bytes.restype = C.c_int32
+    lib.lmfao_prepare.argtypes = [vp, C.POINTER(C.POINTER(vp)), vp, C.POINTER(vp)]
+    lib.lmfao_prepare.restype = C.c_int32
+    lib.lmfao_run.argtypes = [vp, vp, vp, C.c_int32]
+    lib.lmfao_run.restype = C.c_int32
+    lib.lmfao_result_shape.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]
+    lib.lmfao_result_shape.restype = C.c_int32
+    lib.lmfao_result_copy.argtypes = [vp, C.c_int32, vp, vp, vp]
+    lib.lmfao_result_copy.restype = C.c_int32
+    lib.lmfao_view_shape.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)]
+    lib.lmfao_view_shape.restype = C.c_int32
+    lib.lmfao_view_copy.argtypes = [vp, C.c_int32, vp, vp, vp]
+    lib.lmfao_view_copy.restype = C.c_int32
+    lib.lmfao_set_timing.argtypes = [vp, C.c_int32]
+    lib.lmfao_set_timing.restype = C.c_int32
+    lib.lmfao_run_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_float),
+                                     C.POINTER(C.c_int32)]
+    lib.lmfao_run_timing.restype = C.c_int32
+    lib.lmfao_prepared_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.lmfao_prepared_describe.restype = C.c_int32
+    lib.lmfao_plan_free.argtypes = [vp]
+    lib.lmfao_plan_free.restype = None
+    lib.lmfao_prepared_free.argtypes = [vp]
+    lib.lmfao_prepared_free.restype = None
+    lib.lmfao_last_error.argtypes = []
+    lib.lmfao_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(lib, st):
+    if st != 0:
+        raise LmfaoError(st, lib.lmfao_last_error().decode(errors="replace"))
+
+
+class _Keep:
+    """Owns the ctypes buffers passed to one call."""
+
+    def __init__(self):
+        self.refs = []
+
+    def s(self, x: str):
+        b = x.encode()
+        self.refs.append(b)
+        return b
+
+    def arr(self, ctype, items):
+        a = (ctype * max(1, len(items)))(*items)
+        self.refs.append(a)
+        return a
+
+
+def marshal_problem(problem, keep: _Keep):
+    """schema / tree / batch dicts -> ctypes structs (host pointers)."""
+    rels = []
+    names = [r["name"] for r in problem["schema"]]
+    for r in problem["schema"]:
+        attrs = [lmfao_attr(keep.s(a["name"]), _DTYPES[a["dtype"]], int(a.get("domain", 0)),
+                            1 if a.get("key") else 0) for a in r["attrs"]]
+        arr = keep.arr(lmfao_attr, attrs)
+        rels.append(lmfao_relation(keep.s(r["name"]), int(r["n_rows"]), len(attrs), arr))
+    schema = lmfao_schema(len(rels), keep.arr(lmfao_relation, rels))
+    edges = [lmfao_edge(int(a), int(b)) for a, b in problem["tree"]]
+    tree = lmfao_join_tree(len(edges), keep.arr(lmfao_edge, edges))
+    queries = []
+    for q in problem["batch"]:
+        gb = keep.arr(C.c_char_p, [keep.s(g) for g in q.get("groupby", [])])
+        conds = keep.arr(lmfao_condition, [lmfao_condition(keep.s(a), OPS[op], float(c))
+                                           for a, op, c in q.get("where", [])])
+        aggs = []
+        for f in q["aggs"]:
+            fs = keep.arr(lmfao_factor, [lmfao_factor(keep.s(a), int(p)) for a, p in f])
+            aggs.append(lmfao_aggregate(len(f), fs))
+        root = q.get("root")
+        root_i = -1 if root is None else (names.index(root) if isinstance(root, str) else int(root))
+        queries.append(lmfao_query(len(q.get("groupby", [])), gb, len(q.get("where", [])), conds,
+                                   len(aggs), keep.arr(lmfao_aggregate, aggs), root_i))
+    batch = lmfao_batch(len(queries), keep.arr(lmfao_query, queries))
+    keep.refs += [schema, tree, batch]
+    return schema, tree, batch
+
+
+class Plan:
+    """A plan handle (``lmfao_plan``)."""
+
+    def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
+                 min_segment=0, row_piece_max=0):
+        self.lib = load_library()
+        self.problem = problem
+        keep = _Keep()
+        schema, tree, batch = marshal_problem(problem, keep)
+        opts = lmfao_options()
+        self.lib.lmfao_default_options(C.byref(opts))
+        opts.precision = PREC_F64 if precision == "f64" else PREC_F32
+        opts.form = FORM_FUSED if form == "fused" else FORM_PER_VIEW
+        pol = policy if policy is not None else problem.get("policy", "groupby")
+        opts.root_policy = ROOT_FACT if pol == "fact" else ROOT_GROUPBY
+        opts.min_segment = int(min_segment)
+        opts.row_piece_max = int(row_piece_max)
+        if order:
+            names = [r["name"] for r in problem["schema"]]
+            n_order = [len(order.get(n, [])) for n in names]
+            lists = [keep.arr(C.c_char_p, [keep.s(a) for a in order.get(n, [])]) for n in names]
+            opts.n_order = keep.arr(C.c_int32, n_order)
+            ptrs = keep.arr(C.POINTER(C.c_char_p), [C.cast(l, C.POINTER(C.c_char_p)) for l in lists])
+            opts.order = C.cast(ptrs, C.POINTER(C.POINTER(C.c_char_p)))
+        h = C.c_void_p()
+        _check(self.lib, self.lib.lmfao_plan(C.byref(schema), C.byref(tree), C.byref(batch),
+                                             C.byref(opts), C.byref(h)))
+        self.handle = h
+        self.precision = precision
+
+    def describe(self) -> dict:
+        need = C.c_size_t()
+        _check(self.lib, self.lib.lmfao_plan_describe(self.handle, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        _check(self.lib, self.lib.lmfao_plan_describe(self.handle, buf, need.value, C.byref(need)))
+        return json.loads(buf.value.decode())
+
+    def workspace_bytes(self) -> int:
+        b = C.c_size_t()
+        _check(self.lib, self.lib.lmfao_plan_workspace_bytes(self.handle, C.byref(b)))
+        return b.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.lmfao_plan_free(h)
+            self.handle = None
+
+
+class Prepared:
+    """Sorted relations, pieces and buffers for one plan (``lmfao_prepare``).
+
+    ``columns`` maps relation name -> attribute name -> device tensor (torch,
+    contiguous, int32 / float32 / float64 as declared).  The plan must outlive
+    this object."""
+
+    def __init__(self, plan: Plan, columns: dict, stream=None):
+        self.plan = plan
+        self.lib = plan.lib
+        keep = _Keep()
+        per_rel = []
+        for r in plan.problem["schema"]:
+            ptrs = [C.c_void_p(int(columns[r["name"]][a["name"]].data_ptr())) for a in r["attrs"]]
+            per_rel.append(C.cast(keep.arr(C.c_void_p, ptrs), C.POINTER(C.c_void_p)))
+        cols = keep.arr(C.POINTER(C.c_void_p), per_rel)
+        self.stream = C.c_void_p(stream) if stream else C.c_void_p()
+        h = C.c_void_p()
+        _check(self.lib, self.lib.lmfao_prepare(plan.handle, cols, self.stream, C.byref(h)))
+        self.handle = h
+
+    def run(self, sync=True, stream=None):
+        s = C.c_void_p(stream) if stream is not None else self.stream
+        _check(self.lib, self.lib.lmfao_run(self.plan.handle, self.handle, s, 1 if sync else 0))
+
+    def set_timing(self, on=True):
+        _check(self.lib, self.lib.lmfao_set_timing(self.handle, 1 if on else 0))
+
+    def describe(self) -> dict:
+        need = C.c_size_t()
+        _check(self.lib, self.lib.lmfao_prepared_describe(self.handle, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        _check(self.lib, self.lib.lmfao_prepared_describe(self.handle, buf, need.value, C.byref(need)))
+        return json.loads(buf.value.decode())
+
+    def timing(self):
+        n = C.c_int32()
+        _check(self.lib, self.lib.lmfao_run_timing(self.handle, 0, None, None, C.byref(n)))
+        names = (C.c_char_p * max(1, n.value))()
+        ms = (C.c_float * max(1, n.value))()
+        _check(self.lib, self.lib.lmfao_run_timing(self.handle, n.value, names, ms, C.byref(n)))
+        return [(names[i].decode(), ms[i]) for i in range(n.value)]
+
+    def result(self, q: int) -> dict:
+        import numpy as np
+        ng, nk, na = C.c_int64(), C.c_int32(), C.c_int32()
+        _check(self.lib, self.lib.lmfao_result_shape(self.handle, q, C.byref(ng), C.byref(nk), C.byref(na)))
+        keys = np.zeros((ng.value, nk.value), dtype=np.int64)
+        cnt = np.zeros(ng.value, dtype=np.int64)
+        vals = np.zeros((ng.value, na.value), dtype=np.float64)
+        _check(self.lib, self.lib.lmfao_result_copy(
+            self.handle, q, keys.ctypes.data_as(C.c_void_p), cnt.ctypes.data_as(C.c_void_p),
+            vals.ctypes.data_as(C.c_void_p)))
+        return {"keys": keys, "count": cnt, "sum": vals}
+
+    def view(self, v: int) -> dict:
+        """Dense contents of intermediate view v: counts, values, codes per key."""
+        import numpy as np
+        nk, nv, nc = C.c_int64(), C.c_int32(), C.c_int32()
+        _check(self.lib, self.lib.lmfao_view_shape(self.handle, v, C.byref(nk), C.byref(nv), C.byref(nc)))
+        cnt = np.zeros(nk.value, dtype=np.int64)
+        vals = np.zeros((nk.value, nv.value), dtype=np.float64)
+        codes = np.zeros((nk.value, nc.value), dtype=np.int32)
+        _check(self.lib, self.lib.lmfao_view_copy(self.handle, v, cnt.ctypes.data_as(C.c_void_p),
+                                                  vals.ctypes.data_as(C.c_void_p),
+                                                  codes.ctypes.data_as(C.c_void_p)))
+        return {"count": cnt, "values": vals, "codes": codes}
+
+    def results(self):
+        return [self.result(q) for q in range(len(self.plan.problem["batch"]))]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.lmfao_prepared_free(h)
+            self.handle = None
+
+
+def device_columns(problem, device="cuda:0"):
+    """Copies every generated column to the device as a torch tensor."""
+    import numpy as np
+    import torch
+    out = {}
+    for r in problem["schema"]:
+        cols = {}
+        for a in r["attrs"]:
+            v = problem["data"][r["name"]][a["name"]]
+            dt = {"i32": np.int32, "f32": np.float32, "f64": np.float64}[a["dtype"]]
+            cols[a["name"]] = torch.from_numpy(np.ascontiguousarray(v, dtype=dt)).to(device)
+        out[r["name"]] = cols
+    return out

@@ -1,0 +1,70 @@
+// Launch entry points of the HIP kernels (host side) and the descriptors
+// that only the kernels and the runtime share.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "engine.hpp"
+
+namespace lmfao {
+
+struct DViewBuild {
+  int64_t n_rows;
+  DCol cols[kMaxPieceCols];  // relation columns referenced (original row order)
+  int32_t nkey;
+  int32_t key_col[kMaxKey];
+  int64_t key_stride[kMaxKey];
+  int32_t n_views;
+  DView views[kMaxViews];    // key_src = positions in cols
+  int32_t n_vals;
+  int32_t val_kind[64], val_src[64], val_slot[64];
+  int32_t n_codes;
+  int32_t code_kind[8], code_src[8], code_slot[8];
+  int64_t* out_cnt;
+  void* out_vals;
+  int32_t* out_codes;
+  int32_t* err_flag;
+};
+
+struct DKeyCols {
+  int32_t n;
+  const void* cols[kMaxKey * 2];
+  int64_t dom[kMaxKey * 2];
+  int32_t* err_flag;
+};
+
+struct DTableReduce {
+  int64_t n;            // elements of this count table
+  int32_t n_blocks;
+  int64_t stride;       // partial row stride (elements per block)
+  int64_t off;          // offset of the table inside a partial row
+  const int64_t* part_i;
+  int64_t* dst_cnt;
+};
+
+void launch_fill(void* p, int64_t bytes, hipStream_t s);
+void launch_view_build(const DViewBuild* d, int64_t n_rows, bool f64, hipStream_t s);
+void launch_make_keys(const DKeyCols* d, uint64_t* keys, uint32_t* idx, int64_t n, hipStream_t s);
+void launch_sort(uint64_t* keys, uint32_t* idx, uint64_t* keys_tmp, uint32_t* idx_tmp, int64_t n, int bits,
+                 uint32_t* hist, hipStream_t s, bool* swapped);
+int sort_tile();
+void launch_gather(const void* src, const uint32_t* perm, void* dst, int64_t n, int elem_bytes, hipStream_t s);
+void launch_segment_starts(const uint64_t* keys, int64_t n, uint64_t div, unsigned long long* count,
+                           int64_t* pos, uint64_t* pkey, int64_t cap, hipStream_t s);
+void launch_validate(const int32_t* col, int64_t n, int64_t dom, int32_t* err_flag, hipStream_t s);
+
+int scan_lds_bytes(const DScan& S, bool f64);
+void launch_scan(const DScan* d, int na, bool f64, int grid, int lds, hipStream_t s);
+int scan_waves_per_block();
+
+int contract_lds_bytes(const DContract& C, bool f64);
+int contract_tiles(int nf, int ng);
+int contract_threads();
+int contract_max_int_cells();
+void launch_contract(const DContract* d, bool f64, int grid_x, int grid_y, int lds, hipStream_t s);
+
+void launch_merge_cells(const DCell* cells, int64_t n_cells, const double* part_f, const int64_t* part_i,
+                        int n_blocks, int NF, int NG, int NFI, int NGI, hipStream_t s);
+void launch_table_reduce(const DTableReduce* d, int64_t n, hipStream_t s);
+
+}  // namespace lmfao

@@ -1,0 +1,1210 @@
+// Host planner: the view generation and multi-output optimization layers of
+// the paper (section 2, Figure 1), followed by this engine's physical
+// planning of each group into a factorized scan + contraction program.
+//
+//  1. validate schema / join tree / batch;
+//  2. assign a root to every query (section 2: one root per query, chosen by a
+//     heuristic; two heuristics here, see lmfao.h);
+//  3. decompose every query top-down from its root into one view per edge
+//     (section 2: the view on an edge leaving node n is the query restricted
+//     to the attributes of the subtree rooted at n, over the join of n's
+//     relation and its incoming views; group-by attributes of the subtree are
+//     carried along);
+//  4. merge views with the same direction, group-by attributes and condition;
+//  5. group the views and queries leaving the same node by dependency level
+//     (this reproduces the seven groups and the dependency graph of Figure 2);
+//  6. pick a total attribute order per node and compile each group into the
+//     program the GPU runs: per-tuple inner factors and codes, per-piece
+//     partial sums (the running sums of Figure 3), per-piece outer features
+//     and the contraction that multiplies them (the partial aggregates of
+//     Figure 3 pushed past the inner loops).
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <numeric>
+#include <queue>
+#include <sstream>
+
+#include "engine.hpp"
+
+namespace lmfao {
+
+static void fail(int st, const std::string& m) { throw PlanError{st, m}; }
+
+std::vector<int> join_attrs(const Plan& P, int a, int b) {
+  std::vector<int> out;
+  for (int x : P.rels[a].attrs)
+    if (P.rels[b].has(x)) out.push_back(x);
+  std::sort(out.begin(), out.end());
+  return out;
+}
+
+static std::string mono_str(const Plan& P, const Mono& m) {
+  if (m.empty()) return "1";
+  std::string s;
+  for (size_t i = 0; i < m.size(); ++i) {
+    if (i) s += "*";
+    s += P.attrs[m[i]].name;
+  }
+  return s;
+}
+
+static std::string json_escape(const std::string& s) {
+  std::string o;
+  for (char c : s) {
+    if (c == '"' || c == '\\') o += '\\';
+    o += c;
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// 1. validation and intake
+// ---------------------------------------------------------------------------
+static void intake(Plan& P, const lmfao_schema* schema, const lmfao_join_tree* tree,
+                   const lmfao_batch* batch) {
+  if (!schema || schema->n_relations <= 0 || !schema->relations) fail(LMFAO_EINVAL, "empty schema");
+  int n = schema->n_relations;
+  if (n > 31) fail(LMFAO_EUNSUPPORTED, "more than 31 relations");
+  P.rels.resize(n);
+  for (int r = 0; r < n; ++r) {
+    const lmfao_relation& R = schema->relations[r];
+    RelDef& D = P.rels[r];
+    D.name = R.name ? R.name : ("R" + std::to_string(r));
+    if (R.n_rows < 0) fail(LMFAO_EINVAL, "negative row count for " + D.name);
+    D.n_rows = R.n_rows;
+    if (R.n_attrs <= 0 || !R.attrs) fail(LMFAO_EINVAL, "relation " + D.name + " has no attributes");
+    for (int a = 0; a < R.n_attrs; ++a) {
+      const lmfao_attr& A = R.attrs[a];
+      if (!A.name || !*A.name) fail(LMFAO_EINVAL, "unnamed attribute in " + D.name);
+      if (A.dtype < LMFAO_I32 || A.dtype > LMFAO_F64) fail(LMFAO_EINVAL, std::string("bad dtype for ") + A.name);
+      int id;
+      auto it = P.attr_id.find(A.name);
+      if (it == P.attr_id.end()) {
+        id = (int)P.attrs.size();
+        P.attr_id[A.name] = id;
+        P.attrs.push_back(AttrDef{A.name, A.dtype, A.domain});
+      } else {
+        id = it->second;
+        AttrDef& G = P.attrs[id];
+        if (G.dtype != A.dtype)
+          fail(LMFAO_EINVAL, std::string("attribute ") + A.name + " has different dtypes across relations");
+        G.domain = std::max(G.domain, A.domain);
+      }
+      if (D.has(id)) fail(LMFAO_EINVAL, std::string("duplicate attribute ") + A.name + " in " + D.name);
+      D.col[id] = (int)D.attrs.size();
+      D.attrs.push_back(id);
+      D.dtypes.push_back(A.dtype);
+      D.is_key.push_back(A.is_key ? 1 : 0);
+    }
+  }
+  // join tree
+  P.adj.assign(n, {});
+  int ne = tree ? tree->n_edges : 0;
+  if (ne != n - 1) fail(LMFAO_EINVAL, "join tree must have n_relations-1 edges");
+  for (int e = 0; e < ne; ++e) {
+    int a = tree->edges[e].a, b = tree->edges[e].b;
+    if (a < 0 || b < 0 || a >= n || b >= n || a == b) fail(LMFAO_EINVAL, "bad join tree edge");
+    P.edges.push_back({a, b});
+    P.adj[a].push_back(b);
+    P.adj[b].push_back(a);
+  }
+  for (auto& v : P.adj) std::sort(v.begin(), v.end());
+  {  // connected (n-1 edges + connected => tree)
+    std::vector<char> seen(n, 0);
+    std::vector<int> st{0};
+    seen[0] = 1;
+    while (!st.empty()) {
+      int u = st.back();
+      st.pop_back();
+      for (int v : P.adj[u])
+        if (!seen[v]) { seen[v] = 1; st.push_back(v); }
+    }
+    for (int r = 0; r < n; ++r)
+      if (!seen[r]) fail(LMFAO_EINVAL, "join tree does not connect relation " + P.rels[r].name);
+  }
+  for (auto& e : P.edges)
+    if (join_attrs(P, e.first, e.second).empty())
+      fail(LMFAO_EINVAL, "join tree edge " + P.rels[e.first].name + "-" + P.rels[e.second].name +
+                             " shares no attribute");
+  // running intersection: relations holding an attribute are connected
+  for (int a = 0; a < (int)P.attrs.size(); ++a) {
+    std::vector<int> holders;
+    for (int r = 0; r < n; ++r)
+      if (P.rels[r].has(a)) holders.push_back(r);
+    if (holders.size() < 2) continue;
+    std::vector<char> seen(n, 0);
+    std::vector<int> st{holders[0]};
+    seen[holders[0]] = 1;
+    while (!st.empty()) {
+      int u = st.back();
+      st.pop_back();
+      for (int v : P.adj[u])
+        if (!seen[v] && P.rels[v].has(a)) { seen[v] = 1; st.push_back(v); }
+    }
+    for (int h : holders)
+      if (!seen[h])
+        fail(LMFAO_EINVAL, "attribute " + P.attrs[a].name + " violates the running-intersection property");
+    if (P.attrs[a].dtype != LMFAO_I32 || P.attrs[a].domain <= 0)
+      fail(LMFAO_EUNSUPPORTED, "join attribute " + P.attrs[a].name + " needs an integer domain");
+  }
+  // batch
+  if (!batch || batch->n_queries <= 0) fail(LMFAO_EINVAL, "empty batch");
+  for (int qi = 0; qi < batch->n_queries; ++qi) {
+    const lmfao_query& Q = batch->queries[qi];
+    QueryDef q;
+    auto lookup = [&](const char* nm) {
+      if (!nm) fail(LMFAO_EINVAL, "null attribute name in query " + std::to_string(qi));
+      auto it = P.attr_id.find(nm);
+      if (it == P.attr_id.end()) fail(LMFAO_EINVAL, std::string("unknown attribute ") + nm);
+      return it->second;
+    };
+    if (Q.n_groupby < 0 || Q.n_groupby > 2)
+      fail(LMFAO_EUNSUPPORTED, "query " + std::to_string(qi) + ": at most 2 group-by attributes");
+    for (int g = 0; g < Q.n_groupby; ++g) {
+      int a = lookup(Q.groupby[g]);
+      if (P.attrs[a].dtype != LMFAO_I32 || P.attrs[a].domain <= 0)
+        fail(LMFAO_EUNSUPPORTED, "group-by attribute " + P.attrs[a].name + " needs an integer domain");
+      if (std::find(q.groupby.begin(), q.groupby.end(), a) != q.groupby.end())
+        fail(LMFAO_EINVAL, "repeated group-by attribute");
+      q.groupby.push_back(a);
+    }
+    for (int c = 0; c < Q.n_conditions; ++c) {
+      const lmfao_condition& C = Q.conditions[c];
+      if (C.op < LMFAO_LE || C.op > LMFAO_NE) fail(LMFAO_EINVAL, "bad condition operator");
+      q.conds.push_back(Cond{lookup(C.attr), C.op, C.constant});
+    }
+    std::sort(q.conds.begin(), q.conds.end());
+    if (Q.n_aggregates <= 0) fail(LMFAO_EINVAL, "query without aggregates");
+    for (int k = 0; k < Q.n_aggregates; ++k) {
+      const lmfao_aggregate& A = Q.aggregates[k];
+      Mono m;
+      for (int f = 0; f < A.n_factors; ++f) {
+        int a = lookup(A.factors[f].attr);
+        int p = A.factors[f].power;
+        if (p < 1 || p > 2) fail(LMFAO_EUNSUPPORTED, "factor power must be 1 or 2");
+        for (int i = 0; i < p; ++i) m.push_back(a);
+      }
+      if (m.size() > 2) fail(LMFAO_EUNSUPPORTED, "aggregate of degree > 2");
+      std::sort(m.begin(), m.end());
+      q.aggs.push_back(m);
+    }
+    q.root = Q.root;
+    if (q.root < -1 || q.root >= n) fail(LMFAO_EINVAL, "bad root override");
+    P.queries.push_back(q);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// uniqueness of directed edge views: V_{n->p} has at most one subtree join
+// tuple per key value iff n's primary key is inside the edge's join
+// attributes and every view into n from below is unique as well.
+// ---------------------------------------------------------------------------
+static void compute_uniqueness(Plan& P) {
+  int n = (int)P.rels.size();
+  P.uniq.assign(n, std::vector<char>(n, 0));
+  std::function<bool(int, int)> uq = [&](int u, int p) -> bool {
+    const RelDef& R = P.rels[u];
+    bool has_key = false;
+    std::vector<int> J = join_attrs(P, u, p);
+    for (size_t i = 0; i < R.attrs.size(); ++i) {
+      if (!R.is_key[i]) continue;
+      has_key = true;
+      if (!std::binary_search(J.begin(), J.end(), R.attrs[i])) return false;
+    }
+    if (!has_key) return false;
+    for (int c : P.adj[u])
+      if (c != p && !uq(c, u)) return false;
+    return true;
+  };
+  for (auto& e : P.edges) {
+    P.uniq[e.first][e.second] = uq(e.first, e.second);
+    P.uniq[e.second][e.first] = uq(e.second, e.first);
+  }
+}
+
+// relations reachable from r in direction away from `par`
+static void subtree(const Plan& P, int u, int par, std::vector<int>& out) {
+  out.push_back(u);
+  for (int v : P.adj[u])
+    if (v != par) subtree(P, v, u, out);
+}
+
+// owner of an attribute w.r.t. a root: the relation holding it closest to the root
+static std::vector<int> owners_from(const Plan& P, int root, std::vector<int>& parent) {
+  int n = (int)P.rels.size();
+  parent.assign(n, -1);
+  std::vector<int> order{root};
+  std::vector<char> seen(n, 0);
+  seen[root] = 1;
+  for (size_t i = 0; i < order.size(); ++i)
+    for (int v : P.adj[order[i]])
+      if (!seen[v]) { seen[v] = 1; parent[v] = order[i]; order.push_back(v); }
+  std::vector<int> owner(P.attrs.size(), -1);
+  for (int u : order)
+    for (int a : P.rels[u].attrs)
+      if (owner[a] < 0) owner[a] = u;
+  return owner;
+}
+
+// ---------------------------------------------------------------------------
+// 2. roots
+// ---------------------------------------------------------------------------
+static int root_groupby(const Plan& P, const QueryDef& q) {
+  int n = (int)P.rels.size();
+  int best = -1;
+  for (int r = 0; r < n; ++r) {
+    bool all = true;
+    for (int g : q.groupby) all &= P.rels[r].has(g);
+    if (!all) continue;
+    if (best < 0 || P.rels[r].n_rows > P.rels[best].n_rows) best = r;
+  }
+  if (best >= 0) return best;
+  // no relation holds all of them: the relation holding the group-by
+  // attribute with the largest domain
+  int ga = q.groupby[0];
+  for (int g : q.groupby)
+    if (P.attrs[g].domain > P.attrs[ga].domain) ga = g;
+  for (int r = 0; r < n; ++r)
+    if (P.rels[r].has(ga) && (best < 0 || P.rels[r].n_rows > P.rels[best].n_rows)) best = r;
+  return best;
+}
+
+// is attribute a single-valued for every tuple of r (reached through unique views)?
+static bool fd_reachable(const Plan& P, int r, int a) {
+  if (P.rels[r].has(a)) return true;
+  for (int c : P.adj[r]) {
+    std::vector<int> sub;
+    subtree(P, c, r, sub);
+    for (int u : sub)
+      if (P.rels[u].has(a)) return P.uniq[c][r] != 0;
+  }
+  return false;
+}
+
+static int root_fact(const Plan& P, const QueryDef& q) {
+  int n = (int)P.rels.size();
+  std::set<int> attrs(q.groupby.begin(), q.groupby.end());
+  for (auto& m : q.aggs) attrs.insert(m.begin(), m.end());
+  for (auto& c : q.conds) attrs.insert(c.attr);
+  // a query over the attributes of a single relation is rooted there
+  if (!attrs.empty()) {
+    int best = -1;
+    for (int r = 0; r < n; ++r) {
+      bool all = true;
+      for (int a : attrs) all &= P.rels[r].has(a);
+      if (all && (best < 0 || P.rels[r].n_rows < P.rels[best].n_rows)) best = r;
+    }
+    if (best >= 0) return best;
+  }
+  int best = -1;
+  for (int r = 0; r < n; ++r) {
+    bool ok = true;
+    for (int g : q.groupby) ok &= fd_reachable(P, r, g);
+    if (ok && (best < 0 || P.rels[r].n_rows > P.rels[best].n_rows)) best = r;
+  }
+  if (best >= 0) return best;
+  return root_groupby(P, q);
+}
+
+// ---------------------------------------------------------------------------
+// 3-5. views, merging, levels, groups
+// ---------------------------------------------------------------------------
+struct ViewKey {
+  int from, to;
+  std::vector<int> carried;
+  std::vector<Cond> conds;
+  bool operator<(const ViewKey& o) const {
+    return std::tie(from, to, carried, conds) < std::tie(o.from, o.to, o.carried, o.conds);
+  }
+};
+
+static void generate_views(Plan& P) {
+  int n = (int)P.rels.size();
+  std::map<ViewKey, int> index;
+  for (size_t qi = 0; qi < P.queries.size(); ++qi) {
+    QueryDef& q = P.queries[qi];
+    if (q.root < 0) {
+      if (q.groupby.empty()) {
+        // no group-by: the FACT heuristic still roots single-relation queries there
+        q.root = (P.opts.root_policy == LMFAO_ROOT_FACT) ? root_fact(P, q) : -1;
+        if (q.root < 0) {
+          int best = 0;
+          for (int r = 1; r < n; ++r)
+            if (P.rels[r].n_rows > P.rels[best].n_rows) best = r;
+          q.root = best;
+        }
+      } else {
+        q.root = (P.opts.root_policy == LMFAO_ROOT_FACT) ? root_fact(P, q) : root_groupby(P, q);
+      }
+    }
+    std::vector<int> parent;
+    std::vector<int> owner = owners_from(P, q.root, parent);
+    for (int g : q.groupby)
+      if (owner[g] < 0) fail(LMFAO_EINVAL, "group-by attribute not in schema");
+    // bottom-up over nodes: children first so dependencies exist
+    std::vector<int> bfs{q.root};
+    for (size_t i = 0; i < bfs.size(); ++i)
+      for (int v : P.adj[bfs[i]])
+        if (v != parent[bfs[i]]) bfs.push_back(v);
+    std::vector<int> vid(n, -1);
+    for (int i = (int)bfs.size() - 1; i >= 1; --i) {
+      int u = bfs[i], p = parent[u];
+      std::vector<int> sub;
+      subtree(P, u, p, sub);
+      std::set<int> subset(sub.begin(), sub.end());
+      auto owned = [&](int a) { return subset.count(owner[a]) != 0; };
+      ViewKey k{u, p, {}, {}};
+      std::vector<int> carried;
+      for (int g : q.groupby)
+        if (owned(g)) carried.push_back(g);
+      std::sort(carried.begin(), carried.end());
+      // a single-valued view determines its carried attributes from its key,
+      // so views that differ only in them are one view storing all of them
+      if (!P.uniq[u][p]) k.carried = carried;
+      for (auto& c : q.conds)
+        if (owned(c.attr)) k.conds.push_back(c);
+      int id;
+      auto it = index.find(k);
+      if (it == index.end()) {
+        id = (int)P.views.size();
+        ViewDef V;
+        V.id = id;
+        V.from = u;
+        V.to = p;
+        V.key = join_attrs(P, u, p);
+        V.carried = carried;
+        V.conds = k.conds;
+        V.unique = P.uniq[u][p] != 0;
+        P.views.push_back(V);
+        index[k] = id;
+      } else {
+        id = it->second;
+      }
+      ViewDef& V = P.views[id];
+      for (int g : carried)
+        if (std::find(V.carried.begin(), V.carried.end(), g) == V.carried.end()) V.carried.push_back(g);
+      std::sort(V.carried.begin(), V.carried.end());
+      for (auto& m : q.aggs) {
+        Mono r;
+        for (int a : m)
+          if (owned(a)) r.push_back(a);
+        if (!r.empty()) V.comps.insert(r);
+      }
+      for (int c : P.adj[u])
+        if (c != p) V.deps.insert(vid[c]);
+      vid[u] = id;
+    }
+    for (int c : P.adj[q.root]) q.in_view[c] = vid[c];
+  }
+  // levels (dependencies form a DAG by construction)
+  std::function<int(int)> lvl = [&](int v) -> int {
+    ViewDef& V = P.views[v];
+    if (V.level > 0 || V.deps.empty()) return V.level;
+    int m = 0;
+    for (int d : V.deps) m = std::max(m, lvl(d) + 1);
+    V.level = m;
+    return m;
+  };
+  for (auto& V : P.views) lvl(V.id);
+  for (auto& q : P.queries) {
+    int m = 0;
+    for (auto& kv : q.in_view) m = std::max(m, P.views[kv.second].level + 1);
+    q.level = m;
+  }
+  // groups: outputs leaving the same node at the same dependency level
+  std::map<std::pair<int, int>, int> gidx;
+  auto group_of = [&](int node, int level) {
+    auto k = std::make_pair(level, node);
+    auto it = gidx.find(k);
+    if (it != gidx.end()) return it->second;
+    int id = (int)P.groups.size();
+    GroupDef G;
+    G.node = node;
+    G.level = level;
+    P.groups.push_back(G);
+    gidx[k] = id;
+    return id;
+  };
+  // deterministic numbering: by level, then node
+  std::vector<std::pair<std::pair<int, int>, OutRef>> all;
+  for (auto& V : P.views) all.push_back({{V.level, V.from}, OutRef{1, V.id}});
+  for (size_t i = 0; i < P.queries.size(); ++i)
+    all.push_back({{P.queries[i].level, P.queries[i].root}, OutRef{0, (int)i}});
+  std::stable_sort(all.begin(), all.end(),
+                   [](const auto& a, const auto& b) { return a.first < b.first; });
+  for (auto& e : all) {
+    int g = group_of(e.first.second, e.first.first);
+    P.groups[g].outs.push_back(e.second);
+    if (e.second.kind == 1) P.views[e.second.id].group = g;
+    else P.queries[e.second.id].group = g;
+  }
+  auto compute_deps = [&]() {
+    for (auto& G : P.groups) {
+      G.deps.clear();
+      for (auto& o : G.outs) {
+        if (o.kind == 1)
+          for (int d : P.views[o.id].deps) G.deps.insert(P.views[d].group);
+        else
+          for (auto& kv : P.queries[o.id].in_view) G.deps.insert(P.views[kv.second].group);
+      }
+    }
+  };
+  compute_deps();
+  // one scan per relation where possible: two groups of the same node with no
+  // dependency path between them become one group (no cycle can arise)
+  for (bool merged = true; merged;) {
+    merged = false;
+    int ng = (int)P.groups.size();
+    std::vector<std::vector<char>> reach(ng, std::vector<char>(ng, 0));
+    for (int a = 0; a < ng; ++a) {
+      std::vector<int> st(P.groups[a].deps.begin(), P.groups[a].deps.end());
+      while (!st.empty()) {
+        int u = st.back();
+        st.pop_back();
+        if (reach[a][u]) continue;
+        reach[a][u] = 1;   // a depends on u
+        for (int d : P.groups[u].deps) st.push_back(d);
+      }
+    }
+    for (int a = 0; a < ng && !merged; ++a)
+      for (int b = a + 1; b < ng && !merged; ++b) {
+        if (P.groups[a].node != P.groups[b].node || reach[a][b] || reach[b][a]) continue;
+        // merge b into a, renumber
+        for (auto& o : P.groups[b].outs) P.groups[a].outs.push_back(o);
+        P.groups.erase(P.groups.begin() + b);
+        for (auto& V : P.views)
+          if (V.group == b) V.group = a; else if (V.group > b) V.group--;
+        for (auto& q : P.queries)
+          if (q.group == b) q.group = a; else if (q.group > b) q.group--;
+        compute_deps();
+        merged = true;
+      }
+  }
+  // levels: longest dependency path
+  std::function<int(int)> glevel = [&](int g) -> int {
+    int m = 0;
+    for (int d : P.groups[g].deps) m = std::max(m, glevel(d) + 1);
+    return m;
+  };
+  for (size_t g = 0; g < P.groups.size(); ++g) P.groups[g].level = glevel((int)g);
+  for (auto& V : P.views) V.level = P.groups[V.group].level;
+  for (auto& q : P.queries) q.level = P.groups[q.group].level;
+  for (auto& G : P.groups) P.n_levels = std::max(P.n_levels, G.level + 1);
+}
+
+// ---------------------------------------------------------------------------
+// 6a. view layouts and attribute orders
+// ---------------------------------------------------------------------------
+static void view_layouts(Plan& P) {
+  bool f64 = P.opts.precision == LMFAO_PREC_F64;
+  for (auto& V : P.views) {
+    V.n_keys = 1;
+    for (int a : V.key) V.n_keys *= P.attrs[a].domain;
+    if (V.unique) {
+      std::set<int> s;
+      for (auto& m : V.comps) s.insert(m.begin(), m.end());
+      V.val_attrs.assign(s.begin(), s.end());
+      V.code_attrs = V.carried;
+      V.vals_f64 = f64;
+    } else {
+      V.val_monos.assign(V.comps.begin(), V.comps.end());
+      V.vals_f64 = true;   // produced by a merged contraction (FP64)
+      if (!V.carried.empty()) {
+        P.supported = false;
+        P.unsupported_reason = "a group-by attribute is carried through a view that is not "
+                               "single-valued on its join key (multi-valued lookup)";
+      }
+    }
+    if (!V.conds.empty()) {
+      P.supported = false;
+      P.unsupported_reason = "conditions are not executed on the GPU yet";
+    }
+  }
+}
+
+static void attribute_orders(Plan& P) {
+  int n = (int)P.rels.size();
+  P.order.assign(n, {});
+  for (int r = 0; r < n; ++r) {
+    if (P.opts.order && P.opts.n_order && P.opts.n_order[r] > 0) {
+      for (int i = 0; i < P.opts.n_order[r]; ++i) {
+        auto it = P.attr_id.find(P.opts.order[r][i]);
+        if (it == P.attr_id.end() || !P.rels[r].has(it->second))
+          fail(LMFAO_EINVAL, "attribute order names an attribute not in " + P.rels[r].name);
+        P.order[r].push_back(it->second);
+      }
+      // the order must cover every join attribute of the relation
+      for (int c : P.adj[r])
+        for (int a : join_attrs(P, r, c))
+          if (std::find(P.order[r].begin(), P.order[r].end(), a) == P.order[r].end())
+            fail(LMFAO_EINVAL, "attribute order of " + P.rels[r].name + " misses join attribute " +
+                                   P.attrs[a].name);
+      continue;
+    }
+    // heuristic: edges with the largest neighbouring subtree first, so the
+    // biggest incoming views are looked up once per outer segment and the
+    // smallest (cache-resident) ones per tuple; inside an edge, attributes
+    // shared with more edges first, then smaller domains first
+    std::vector<std::pair<int64_t, int>> edges;
+    for (int c : P.adj[r]) {
+      std::vector<int> sub;
+      subtree(P, c, r, sub);
+      int64_t sz = 0;
+      for (int u : sub) sz += P.rels[u].n_rows;
+      edges.push_back({-sz, c});
+    }
+    std::sort(edges.begin(), edges.end());
+    std::map<int, int> shared;
+    for (int c : P.adj[r])
+      for (int a : join_attrs(P, r, c)) shared[a]++;
+    for (auto& e : edges) {
+      std::vector<int> J = join_attrs(P, r, e.second);
+      std::sort(J.begin(), J.end(), [&](int x, int y) {
+        if (shared[x] != shared[y]) return shared[x] > shared[y];
+        if (P.attrs[x].domain != P.attrs[y].domain) return P.attrs[x].domain < P.attrs[y].domain;
+        return x < y;
+      });
+      for (int a : J)
+        if (std::find(P.order[r].begin(), P.order[r].end(), a) == P.order[r].end())
+          P.order[r].push_back(a);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 6b. group programs
+// ---------------------------------------------------------------------------
+struct ProgBuilder {
+  Plan& P;
+  GroupDef& G;
+  GroupProgram& g;
+  int node;
+  int L;
+  std::map<int, int> pos;              // attribute -> order position (1-based)
+  std::map<int, int> view_index;       // view id -> program view index
+  std::map<AtomRef, int> in_atom_idx, out_atom_idx, in_code_idx, out_code_idx;
+  std::map<int, int> scan_col_idx, piece_col_idx;   // relation column / order pos -> position
+  std::map<FeatDef, int> feat_idx;
+  std::map<ColDef, int> col_idx;
+  std::map<std::tuple<int, int, uint32_t>, int> pf_idx;
+  std::map<uint32_t, int> pi_idx;
+  std::map<std::tuple<int, int, int, int, uint32_t>, int> hist_idx;
+  std::vector<std::pair<std::pair<int, int>, CellDst>> cells;
+
+  ProgBuilder(Plan& P_, GroupDef& G_) : P(P_), G(G_), g(G_.prog), node(G_.node) {}
+
+  int view_level(int vid) {
+    int lv = 0;
+    for (int a : P.views[vid].key) lv = std::max(lv, pos.at(a));
+    return lv;
+  }
+  int add_view(int vid) {
+    auto it = view_index.find(vid);
+    if (it != view_index.end()) return it->second;
+    int k = (int)g.views.size();
+    if (k >= kMaxViews) fail(LMFAO_EUNSUPPORTED, "too many incoming views in one group");
+    g.views.push_back(vid);
+    int lv = view_level(vid);
+    g.view_level.push_back(lv);
+    g.view_outer.push_back(g.row_pieces || lv <= g.cut ? 1 : 0);
+    view_index[vid] = k;
+    return k;
+  }
+  bool attr_outer(int a) {   // local attribute
+    if (g.row_pieces) return true;
+    auto it = pos.find(a);
+    return it != pos.end() && it->second <= g.cut;
+  }
+  int scan_col(int c) {
+    auto it = scan_col_idx.find(c);
+    if (it != scan_col_idx.end()) return it->second;
+    int k = (int)g.scan_cols.size();
+    if (k >= kMaxScanCols) fail(LMFAO_EUNSUPPORTED, "too many scanned columns");
+    g.scan_cols.push_back(c);
+    scan_col_idx[c] = k;
+    return k;
+  }
+  // piece columns: row pieces -> relation column index; cut pieces -> order position
+  int piece_col(int key) {
+    auto it = piece_col_idx.find(key);
+    if (it != piece_col_idx.end()) return it->second;
+    int k = (int)g.piece_cols.size();
+    if (k >= kMaxPieceCols) fail(LMFAO_EUNSUPPORTED, "too many piece columns");
+    g.piece_cols.push_back(key);
+    piece_col_idx[key] = k;
+    return k;
+  }
+  int local_piece_col(int a) {
+    if (g.row_pieces) return piece_col(P.rels[node].col.at(a));
+    return piece_col(pos.at(a) - 1);
+  }
+  int atom(bool outer, AtomRef r) {
+    auto& idx = outer ? out_atom_idx : in_atom_idx;
+    auto& vec = outer ? g.out_atoms : g.in_atoms;
+    auto it = idx.find(r);
+    if (it != idx.end()) return it->second;
+    int k = (int)vec.size();
+    vec.push_back(r);
+    idx[r] = k;
+    return k;
+  }
+  int code(bool outer, CodeRef r) {
+    auto& idx = outer ? out_code_idx : in_code_idx;
+    auto& vec = outer ? g.out_codes : g.in_codes;
+    auto it = idx.find(r);
+    if (it != idx.end()) return it->second;
+    int k = (int)vec.size();
+    vec.push_back(r);
+    idx[r] = k;
+    return k;
+  }
+  int feat(const FeatDef& f) {
+    auto it = feat_idx.find(f);
+    if (it != feat_idx.end()) return it->second;
+    int k = (int)feat_idx.size();
+    feat_idx[f] = k;
+    return k;
+  }
+  int col(const ColDef& c) {
+    auto it = col_idx.find(c);
+    if (it != col_idx.end()) return it->second;
+    int k = (int)col_idx.size();
+    col_idx[c] = k;
+    return k;
+  }
+  int pi_entry(uint32_t mask) {
+    auto it = pi_idx.find(mask);
+    if (it != pi_idx.end()) return it->second;
+    int k = (int)g.psi_i.size();
+    g.psi_i.push_back(mask);
+    pi_idx[mask] = k;
+    return k;
+  }
+  int pf_entry(int ai, int aj, uint32_t mask) {
+    if (ai > aj) std::swap(ai, aj);
+    auto key = std::make_tuple(ai, aj, mask);
+    auto it = pf_idx.find(key);
+    if (it != pf_idx.end()) return it->second;
+    int k = (int)g.psi_f.size();
+    g.psi_f.push_back(PsiEntryF{ai, aj, mask});
+    pf_idx[key] = k;
+    return k;
+  }
+  int hist(int code, int is_float, int ai, int aj, uint32_t mask) {
+    if (ai > aj) std::swap(ai, aj);
+    auto key = std::make_tuple(code, is_float, ai, aj, mask);
+    auto it = hist_idx.find(key);
+    if (it != hist_idx.end()) return it->second;
+    int k = (int)g.hists.size();
+    HistDef h;
+    h.code = code;
+    h.dom = (int)P.attrs[attr_of_code(code)].domain;
+    h.is_float = is_float;
+    h.ai = ai;
+    h.aj = aj;
+    h.imask = mask;
+    g.hists.push_back(h);
+    hist_idx[key] = k;
+    return k;
+  }
+  std::vector<int> in_code_attr;   // inner code index -> attribute
+  int attr_of_code(int c) { return in_code_attr.at(c); }
+
+  // one factor source of an output: atoms and the view it comes from
+  struct Part {
+    bool outer;
+    int atom;      // atom index (outer or inner list)
+    int view;      // program view index or -1 (local)
+  };
+
+  void build();
+};
+
+void ProgBuilder::build() {
+  const RelDef& R = P.rels[node];
+  g.node = node;
+  g.order = P.order[node];
+  L = (int)g.order.size();
+  for (int i = 0; i < L; ++i) pos[g.order[i]] = i + 1;
+  // cut level: small relations are contracted row by row; large ones are
+  // scanned with per-piece partial sums at the deepest level whose average
+  // segment is still long
+  int64_t min_seg = P.opts.min_segment > 0 ? P.opts.min_segment : 64;
+  const int64_t kRowPieceMax = P.opts.row_piece_max == 0 ? (int64_t)1 << 21 : P.opts.row_piece_max;
+  if (R.n_rows <= kRowPieceMax) {
+    g.row_pieces = true;
+    g.cut = L + 1;
+  } else {
+    g.row_pieces = false;
+    g.cut = 0;
+    double prod = 1;
+    for (int l = 1; l <= L; ++l) {
+      prod *= (double)P.attrs[g.order[l - 1]].domain;
+      double seg = (double)R.n_rows / std::min<double>(prod, (double)R.n_rows);
+      if (seg >= (double)min_seg) g.cut = l;
+      else break;
+    }
+  }
+  // outputs of the program: queries and non-unique views
+  std::vector<OutRef> outs;
+  for (auto& o : G.outs) {
+    if (o.kind == 1 && P.views[o.id].unique) G.unique_views.push_back(o.id);
+    else outs.push_back(o);
+  }
+  if (outs.empty()) return;
+  G.has_program = true;
+  for (size_t oi = 0; oi < outs.size(); ++oi) {
+    OutRef o = outs[oi];
+    // incoming views and cells of this output
+    std::vector<int> invs;
+    std::vector<int> keyattrs;
+    std::vector<Mono> monos;
+    int excluded = -1;
+    if (o.kind == 0) {
+      const QueryDef& q = P.queries[o.id];
+      for (auto& kv : q.in_view) invs.push_back(kv.second);
+      keyattrs = q.groupby;
+      monos = q.aggs;
+    } else {
+      const ViewDef& V = P.views[o.id];
+      invs.assign(V.deps.begin(), V.deps.end());
+      keyattrs = V.key;
+      for (int a : V.carried) keyattrs.push_back(a);
+      monos = V.val_monos;
+      excluded = V.to;
+    }
+    (void)excluded;
+    uint32_t omask = 0, imask = 0;
+    std::map<int, int> side_view;   // neighbour -> program view index
+    for (int vid : invs) {
+      int k = add_view(vid);
+      side_view[P.views[vid].from] = k;
+      if (g.view_outer[k]) omask |= 1u << k;
+      else imask |= 1u << k;
+    }
+    // where does an attribute come from at this node?
+    auto source_view = [&](int a) -> int {
+      for (auto& kv : side_view) {
+        std::vector<int> sub;
+        subtree(P, kv.first, node, sub);
+        for (int u : sub)
+          if (P.rels[u].has(a)) return kv.second;
+      }
+      fail(LMFAO_EINVAL, "attribute " + P.attrs[a].name + " unreachable from " + R.name);
+      return -1;
+    };
+    // codes of the key
+    ProgOutput po;
+    po.ref = o;
+    po.dst_is_view = o.kind == 1;
+    std::vector<int> kcode;
+    std::vector<char> kouter;
+    for (int a : keyattrs) {
+      bool outer;
+      CodeRef cr;
+      if (R.has(a)) {
+        outer = attr_outer(a);
+        cr = outer ? CodeRef{SRC_COL, local_piece_col(a), 0}
+                   : CodeRef{SRC_COL, scan_col(R.col.at(a)), 0};
+      } else {
+        int vk = source_view(a);
+        const ViewDef& V = P.views[g.views[vk]];
+        int slot = V.slot_of_code(a);
+        if (slot < 0) fail(LMFAO_EUNSUPPORTED, "group-by attribute " + P.attrs[a].name +
+                                                   " is not single-valued at " + R.name);
+        outer = g.view_outer[vk] != 0;
+        cr = CodeRef{SRC_VIEW, vk, slot};
+      }
+      int ci = code(outer, cr);
+      if (!outer) {
+        if ((int)in_code_attr.size() <= ci) in_code_attr.resize(ci + 1, -1);
+        in_code_attr[ci] = a;
+      }
+      kcode.push_back(ci);
+      kouter.push_back(outer);
+      po.key_codes.push_back(ci);
+      po.key_codes_outer.push_back(outer);
+    }
+    po.n_rows = 1;
+    std::vector<int64_t> dom;
+    for (int a : keyattrs) dom.push_back(P.attrs[a].domain);
+    po.key_stride.assign(keyattrs.size(), 1);
+    for (int i = (int)keyattrs.size() - 1; i >= 0; --i) {
+      po.key_stride[i] = po.n_rows;
+      po.n_rows *= dom[i];
+    }
+    po.n_comps = (int)monos.size();
+    // split every component monomial into atoms (outer / inner)
+    struct Split {
+      std::vector<Part> parts;
+    };
+    std::vector<Split> splits;
+    for (auto& m : monos) {
+      Split s;
+      std::map<int, Mono> per_view;   // program view -> restricted monomial
+      for (int a : m) {
+        if (R.has(a)) {
+          bool outer = attr_outer(a);
+          AtomRef ar = outer ? AtomRef{SRC_COL, local_piece_col(a), 0}
+                             : AtomRef{SRC_COL, scan_col(R.col.at(a)), 0};
+          s.parts.push_back(Part{outer, atom(outer, ar), -1});
+        } else {
+          per_view[source_view(a)].push_back(a);
+        }
+      }
+      for (auto& kv : per_view) {
+        int vk = kv.first;
+        const ViewDef& V = P.views[g.views[vk]];
+        bool outer = g.view_outer[vk] != 0;
+        if (V.unique) {
+          for (int a : kv.second) {
+            int slot = V.slot_of_attr(a);
+            if (slot < 0) fail(LMFAO_EINVAL, "internal: view lacks attribute " + P.attrs[a].name);
+            s.parts.push_back(Part{outer, atom(outer, AtomRef{SRC_VIEW, vk, slot}), vk});
+          }
+        } else {
+          Mono mm = kv.second;
+          std::sort(mm.begin(), mm.end());
+          int slot = V.slot_of_mono(mm);
+          if (slot < 0) fail(LMFAO_EINVAL, "internal: view lacks component " + mono_str(P, mm));
+          s.parts.push_back(Part{outer, atom(outer, AtomRef{SRC_VIEW, vk, slot}), vk});
+        }
+      }
+      splits.push_back(s);
+    }
+    // multiplicity masks: non-unique views that contribute a value carry
+    // their own multiplicity, so they leave the mask of that cell
+    auto masks_for = [&](const Split& s, uint32_t& om, uint32_t& im) {
+      om = omask;
+      im = imask;
+      for (auto& p : s.parts)
+        if (p.view >= 0 && !P.views[g.views[p.view]].unique) {
+          if (p.outer) om &= ~(1u << p.view);
+          else im &= ~(1u << p.view);
+        }
+    };
+    // mode
+    std::vector<int> inner_codes, outer_codes;
+    for (size_t i = 0; i < kcode.size(); ++i) (kouter[i] ? outer_codes : inner_codes).push_back((int)i);
+    bool any_outer_atom = false;
+    for (auto& s : splits)
+      for (auto& p : s.parts) any_outer_atom |= p.outer;
+    int64_t outer_prod = 1;
+    for (int i : outer_codes) outer_prod *= dom[i];
+    bool outer_small = outer_prod <= kOneHotMax;
+    bool counts_only = monos.empty();
+    bool pure_inner = outer_codes.empty() && !any_outer_atom;
+    if (inner_codes.empty()) {
+      po.mode = outer_small ? 0 : 1;
+    } else if (pure_inner && (counts_only || inner_codes.size() > 1 || dom[inner_codes[0]] > kHistMax)) {
+      po.mode = 2;   // direct table: no outer factor to multiply later
+    } else if (inner_codes.size() == 1 && dom[inner_codes[0]] <= kHistMax && outer_small) {
+      po.mode = 0;   // per-piece histogram, contracted with the outer features
+    } else {
+      fail(LMFAO_EUNSUPPORTED, std::string(o.kind == 0 ? "query " : "view ") + std::to_string(o.id) +
+                                   " at " + R.name + " mixes large inner group-by keys with outer factors");
+    }
+    if (g.row_pieces && po.mode == 2) po.mode = 1;   // row pieces: every code is outer
+    po.omask = omask;
+    int out_index = (int)g.outs.size();
+    // enumerate cells
+    int ncomp = (int)monos.size();
+    for (int ci = -1; ci < ncomp; ++ci) {
+      Split s = ci < 0 ? Split{} : splits[ci];
+      uint32_t om, im;
+      masks_for(s, om, im);
+      std::vector<int> oat, iat;
+      for (auto& p : s.parts) (p.outer ? oat : iat).push_back(p.atom);
+      if (oat.size() > 2 || iat.size() > 2) fail(LMFAO_EUNSUPPORTED, "component of degree > 2");
+      if (po.mode == 2) {   // table: inner codes only, inner atoms only
+        TableComp tc;
+        tc.comp = ci;
+        tc.ai = iat.size() > 0 ? iat[0] : -1;
+        tc.aj = iat.size() > 1 ? iat[1] : -1;
+        tc.imask = im;
+        po.tcomps.push_back(tc);
+        if (om) { g.needs_mu_out_in_scan = true; g.tables_outer_mask |= om; }
+        po.omask = om;
+        continue;
+      }
+      // enumerate key values
+      int nk = (int)kcode.size();
+      std::vector<int> val(nk, 0);
+      std::function<void(int)> rec = [&](int d) {
+        if (d < nk) {
+          bool expand = po.mode == 0;   // scatter: codes give the row, not features
+          if (expand) {
+            for (int v = 0; v < dom[d]; ++v) { val[d] = v; rec(d + 1); }
+          } else {
+            val[d] = 0;
+            rec(d + 1);
+          }
+          return;
+        }
+        // inner part
+        int icode = -1, ibin = 0;
+        for (int i : inner_codes) { icode = kcode[i]; ibin = val[i]; }
+        std::vector<std::pair<int, int>> ocodes;   // (outer code index, value)
+        if (po.mode == 0)
+          for (int i : outer_codes) ocodes.push_back({kcode[i], val[i]});
+        bool inner_trivial = icode < 0 && iat.empty();
+        FeatDef f;
+        f.mask = om;
+        ColDef c;
+        if (!inner_trivial) {
+          if (g.row_pieces) fail(LMFAO_EINVAL, "internal: inner part with row pieces");
+          if (icode >= 0) {
+            int h = hist(icode, iat.empty() ? 0 : 1, iat.size() > 0 ? iat[0] : -1,
+                         iat.size() > 1 ? iat[1] : -1, im);
+            c.kind = iat.empty() ? B_PSI_I : B_PSI_F;
+            c.entry = h;   // resolved to a row position later
+            c.bin = ibin;
+          } else {
+            c.kind = B_PSI_F;
+            c.entry = pf_entry(iat.size() > 0 ? iat[0] : -1, iat.size() > 1 ? iat[1] : -1, im);
+            c.bin = -1;
+          }
+          if (ocodes.size() > 0) { f.c1 = ocodes[0].first; f.v1 = ocodes[0].second; }
+          if (ocodes.size() > 1) { f.c2 = ocodes[1].first; f.v2 = ocodes[1].second; }
+          if (oat.size() > 0) f.a1 = oat[0];
+          if (oat.size() > 1) f.a2 = oat[1];
+        } else {
+          c.kind = B_CNTF;
+          c.entry = pi_entry(g.row_pieces ? 0u : im);
+          c.bin = -1;
+          // the feature takes one outer part (a code, else a factor), the
+          // column the rest, so features and columns stay single factors
+          std::vector<std::pair<int, int>> rc = ocodes;
+          std::vector<int> ra = oat;
+          if (!rc.empty()) {
+            f.c1 = rc[0].first;
+            f.v1 = rc[0].second;
+            rc.erase(rc.begin());
+          } else if (!ra.empty()) {
+            f.a1 = ra[0];
+            ra.erase(ra.begin());
+          }
+          if (rc.size() > 0) { c.feat.c1 = rc[0].first; c.feat.v1 = rc[0].second; }
+          if (rc.size() > 1) { c.feat.c2 = rc[1].first; c.feat.v2 = rc[1].second; }
+          if (ra.size() > 0) c.feat.a1 = ra[0];
+          if (ra.size() > 1) c.feat.a2 = ra[1];
+          if (c.feat.a1 > c.feat.a2 && c.feat.a2 >= 0) std::swap(c.feat.a1, c.feat.a2);
+        }
+        if (f.a1 > f.a2 && f.a2 >= 0) std::swap(f.a1, f.a2);
+        int fi = feat(f);
+        int gi = col(c);
+        if (po.mode == 0) {
+          int64_t row = 0;
+          for (int i = 0; i < nk; ++i) row += val[i] * po.key_stride[i];
+          cells.push_back({{fi, gi}, CellDst{out_index, row, ci}});
+        } else {
+          g.scatter.push_back(ScatterCell{out_index, ci, fi, gi});
+        }
+      };
+      rec(0);
+    }
+    g.outs.push_back(po);
+  }
+  // inner masks list
+  std::set<uint32_t> ms;
+  for (auto m : g.psi_i) ms.insert(m);
+  for (auto& e : g.psi_f) ms.insert(e.imask);
+  for (auto& h : g.hists) ms.insert(h.imask);
+  for (auto& o : g.outs)
+    for (auto& t : o.tcomps) ms.insert(t.imask);
+  g.in_masks.assign(ms.begin(), ms.end());
+  // histogram block offsets
+  g.hist_f_bins = g.hist_i_bins = 0;
+  for (auto& h : g.hists) {
+    if (h.is_float) { h.offset = g.hist_f_bins; g.hist_f_bins += h.dom; }
+    else { h.offset = g.hist_i_bins; g.hist_i_bins += h.dom; }
+  }
+  // order features and columns: integer ones first
+  std::vector<FeatDef> fv(feat_idx.size());
+  for (auto& kv : feat_idx) fv[kv.second] = kv.first;
+  std::vector<ColDef> cv(col_idx.size());
+  for (auto& kv : col_idx) cv[kv.second] = kv.first;
+  std::vector<int> fperm(fv.size()), cperm(cv.size());
+  std::vector<int> fo(fv.size()), co(cv.size());
+  std::iota(fo.begin(), fo.end(), 0);
+  std::iota(co.begin(), co.end(), 0);
+  std::stable_sort(fo.begin(), fo.end(), [&](int a, int b) { return fv[a].is_int() > fv[b].is_int(); });
+  std::stable_sort(co.begin(), co.end(), [&](int a, int b) { return cv[a].is_int() > cv[b].is_int(); });
+  g.feats.clear();
+  g.cols.clear();
+  for (size_t i = 0; i < fo.size(); ++i) { fperm[fo[i]] = (int)i; g.feats.push_back(fv[fo[i]]); }
+  for (size_t i = 0; i < co.size(); ++i) { cperm[co[i]] = (int)i; g.cols.push_back(cv[co[i]]); }
+  g.n_feat_int = 0;
+  for (auto& f : g.feats) g.n_feat_int += f.is_int();
+  g.n_col_int = 0;
+  for (auto& c : g.cols) g.n_col_int += c.is_int();
+  // resolve psi row positions of columns
+  int pf_n = (int)g.psi_f.size();
+  int pi_n = (int)g.psi_i.size();
+  for (auto& c : g.cols) {
+    if (c.kind == B_PSI_F) {
+      if (c.bin < 0) c.entry = c.entry;                       // float entry slot
+      else c.entry = pf_n + g.hists[c.entry].offset + c.bin;  // float histogram bin
+    } else if (c.kind == B_PSI_I) {
+      c.entry = pi_n + g.hists[c.entry].offset + c.bin;       // count histogram bin
+    }
+    c.bin = 0;
+  }
+  for (auto& cl : cells) {
+    cl.first.first = fperm[cl.first.first];
+    cl.first.second = cperm[cl.first.second];
+  }
+  for (auto& s : g.scatter) {
+    s.f = fperm[s.f];
+    s.g = cperm[s.g];
+  }
+  g.gemm_cells = cells;
+}
+
+static void build_programs(Plan& P) {
+  for (auto& G : P.groups) {
+    ProgBuilder b(P, G);
+    b.build();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plan description (JSON)
+// ---------------------------------------------------------------------------
+static std::string describe(const Plan& P) {
+  std::ostringstream o;
+  auto attrs_json = [&](const std::vector<int>& v) {
+    std::string s = "[";
+    for (size_t i = 0; i < v.size(); ++i) {
+      if (i) s += ",";
+      s += "\"" + json_escape(P.attrs[v[i]].name) + "\"";
+    }
+    return s + "]";
+  };
+  o << "{\"relations\":[";
+  for (size_t r = 0; r < P.rels.size(); ++r) {
+    if (r) o << ",";
+    o << "{\"name\":\"" << json_escape(P.rels[r].name) << "\",\"order\":" << attrs_json(P.order[r]) << "}";
+  }
+  o << "],\"queries\":[";
+  for (size_t i = 0; i < P.queries.size(); ++i) {
+    const QueryDef& q = P.queries[i];
+    if (i) o << ",";
+    o << "{\"root\":\"" << json_escape(P.rels[q.root].name) << "\",\"group\":" << q.group
+      << ",\"level\":" << q.level << ",\"groupby\":" << attrs_json(q.groupby) << ",\"views\":[";
+    bool first = true;
+    for (auto& kv : q.in_view) {
+      if (!first) o << ",";
+      first = false;
+      o << kv.second;
+    }
+    o << "]}";
+  }
+  o << "],\"views\":[";
+  for (size_t i = 0; i < P.views.size(); ++i) {
+    const ViewDef& V = P.views[i];
+    if (i) o << ",";
+    o << "{\"id\":" << V.id << ",\"from\":\"" << json_escape(P.rels[V.from].name) << "\",\"to\":\""
+      << json_escape(P.rels[V.to].name) << "\",\"key\":" << attrs_json(V.key)
+      << ",\"carried\":" << attrs_json(V.carried) << ",\"unique\":" << (V.unique ? "true" : "false")
+      << ",\"level\":" << V.level << ",\"group\":" << V.group << ",\"components\":[";
+    bool first = true;
+    for (auto& m : V.comps) {
+      if (!first) o << ",";
+      first = false;
+      o << "\"" << json_escape(mono_str(P, m)) << "\"";
+    }
+    o << "],\"deps\":[";
+    first = true;
+    for (int d : V.deps) {
+      if (!first) o << ",";
+      first = false;
+      o << d;
+    }
+    o << "]}";
+  }
+  o << "],\"groups\":[";
+  for (size_t i = 0; i < P.groups.size(); ++i) {
+    const GroupDef& G = P.groups[i];
+    if (i) o << ",";
+    o << "{\"id\":" << i << ",\"node\":\"" << json_escape(P.rels[G.node].name) << "\",\"level\":" << G.level
+      << ",\"outputs\":[";
+    for (size_t k = 0; k < G.outs.size(); ++k) {
+      if (k) o << ",";
+      o << "{\"kind\":\"" << (G.outs[k].kind == 0 ? "query" : "view") << "\",\"id\":" << G.outs[k].id << "}";
+    }
+    o << "],\"deps\":[";
+    bool first = true;
+    for (int d : G.deps) {
+      if (!first) o << ",";
+      first = false;
+      o << d;
+    }
+    o << "]";
+    if (G.has_program) {
+      const GroupProgram& g = G.prog;
+      o << ",\"program\":{\"cut\":" << g.cut << ",\"row_pieces\":" << (g.row_pieces ? "true" : "false")
+        << ",\"views\":[";
+      for (size_t k = 0; k < g.views.size(); ++k) {
+        if (k) o << ",";
+        o << "{\"view\":" << g.views[k] << ",\"level\":" << g.view_level[k]
+          << ",\"outer\":" << (g.view_outer[k] ? "true" : "false") << "}";
+      }
+      o << "],\"inner_atoms\":" << g.in_atoms.size() << ",\"inner_codes\":" << g.in_codes.size()
+        << ",\"outer_atoms\":" << g.out_atoms.size() << ",\"outer_codes\":" << g.out_codes.size()
+        << ",\"psi_float\":" << g.psi_f.size() << ",\"psi_count\":" << g.psi_i.size()
+        << ",\"hist_float_bins\":" << g.hist_f_bins << ",\"hist_count_bins\":" << g.hist_i_bins
+        << ",\"features\":" << g.feats.size() << ",\"columns\":" << g.cols.size()
+        << ",\"gemm_cells\":" << g.gemm_cells.size() << ",\"scatter_cells\":" << g.scatter.size()
+        << ",\"feature_list\":[";
+      for (size_t k = 0; k < g.feats.size(); ++k) {
+        const FeatDef& f = g.feats[k];
+        if (k) o << ",";
+        o << "[" << f.mask << "," << f.c1 << "," << f.v1 << "," << f.c2 << "," << f.v2 << "," << f.a1 << "," << f.a2 << "]";
+      }
+      o << "]"
+        << ",\"outputs\":[";
+      for (size_t k = 0; k < g.outs.size(); ++k) {
+        if (k) o << ",";
+        const ProgOutput& po = g.outs[k];
+        o << "{\"kind\":\"" << (po.ref.kind == 0 ? "query" : "view") << "\",\"id\":" << po.ref.id
+          << ",\"mode\":\"" << (po.mode == 0 ? "gemm" : po.mode == 1 ? "scatter" : "table")
+          << "\",\"rows\":" << po.n_rows << "}";
+      }
+      o << "]}";
+    }
+    o << ",\"unique_views\":[";
+    for (size_t k = 0; k < G.unique_views.size(); ++k) {
+      if (k) o << ",";
+      o << G.unique_views[k];
+    }
+    o << "]}";
+  }
+  o << "],\"levels\":" << P.n_levels << ",\"supported\":" << (P.supported ? "true" : "false");
+  if (!P.supported) o << ",\"unsupported\":\"" << json_escape(P.unsupported_reason) << "\"";
+  o << "}";
+  return o.str();
+}
+
+Plan* build_plan(const lmfao_schema* schema, const lmfao_join_tree* tree, const lmfao_batch* batch,
+                 const lmfao_options* opts) {
+  Plan* P = new Plan();
+  try {
+    if (opts) P->opts = *opts;
+    else lmfao_default_options(&P->opts);
+    intake(*P, schema, tree, batch);
+    compute_uniqueness(*P);
+    generate_views(*P);
+    view_layouts(*P);
+    attribute_orders(*P);
+    if (P->supported) build_programs(*P);
+    P->json = describe(*P);
+  } catch (...) {
+    delete P;
+    throw;
+  }
+  return P;
+}
+
+}  // namespace lmfao

@@ -1,0 +1,1264 @@
+// Runtime and C ABI: plan handles, prepare (validation, sorting by the
+// attribute order, trie-level pieces, device descriptors, buffers) and run
+// (every group of the plan, dependency level by level, on one HIP stream).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "kernels.hpp"
+#include "lmfao.h"
+
+namespace lmfao {
+
+static thread_local std::string g_last_error;
+
+struct HipError {
+  std::string msg;
+};
+
+#define HIP_OK(x)                                                                                       \
+  do {                                                                                                  \
+    hipError_t e_ = (x);                                                                                \
+    if (e_ != hipSuccess) throw HipError{std::string(#x) + ": " + hipGetErrorString(e_)};               \
+  } while (0)
+
+static constexpr int64_t kPieceMax = 8192;    // rows of one piece at most
+static constexpr int64_t kPieceMaxF64 = 64;   // FP64 plans: short (uncompensated) histogram chains
+static constexpr int64_t kItemRows = 4096;    // rows one wavefront takes per work item
+static constexpr int64_t kLdsTableMax = 12288;   // int32 count entries privatized in LDS
+
+struct OutBuf {
+  int64_t* cnt = nullptr;
+  void* vals = nullptr;
+  int32_t* codes = nullptr;
+  int64_t n_rows = 0;
+  int n_vals = 0;
+  int n_codes = 0;
+  bool f64 = true;
+};
+
+struct NodeData {
+  bool sorted = false;
+  std::vector<void*> sorted_col;   // per relation column (nullptr = not gathered)
+  std::vector<void*> raw_col;      // library copy of the original columns (row pieces, view builds)
+  int64_t n_pieces = 0;
+  int64_t* piece_begin = nullptr;
+  int32_t* piece_key = nullptr;
+  int32_t* item_piece = nullptr;
+  int n_items = 0;
+  int cut = 0;
+  uint32_t* perm = nullptr;        // sort permutation, kept until prepare ends
+};
+
+struct Step {
+  std::string name;
+  int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract, 5 merge
+  void* dev = nullptr;
+  int64_t n = 0;
+  int na = 0;
+  int grid = 0, grid_y = 0, lds = 0;
+  int64_t bytes = 0;
+  // merge
+  const double* part_f = nullptr;
+  const int64_t* part_i = nullptr;
+  int n_blocks = 0, NF = 0, NG = 0, NFI = 0, NGI = 0;
+  // accounting (host-computed): bytes the step must move, arithmetic it must do
+  double alg_read = 0, alg_write = 0, alg_flop = 0;
+  int64_t rows = 0, pieces = 0;
+};
+
+}  // namespace lmfao
+
+struct lmfao_plan_s {
+  lmfao::Plan* P = nullptr;
+};
+
+struct lmfao_prepared_s {
+  lmfao::Plan* P = nullptr;
+  bool f64 = true;
+  std::vector<lmfao::OutBuf> qout, vout;
+  std::vector<lmfao::NodeData> nodes;
+  std::vector<void*> allocs;
+  std::vector<lmfao::Step> steps;   // the run, in launch order
+  int32_t* err_flag = nullptr;
+  bool timing = false;
+  std::vector<hipEvent_t> ev;       // event pool: per timed run, a (start, stop) per timed step + run
+  int timed_runs = 0;               // runs recorded since the last lmfao_run_timing
+  std::vector<float> step_ms;
+  hipStream_t stream = nullptr;
+  ~lmfao_prepared_s() {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace lmfao {
+
+using Prep = lmfao_prepared_s;
+
+static void* dalloc(Prep& S, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) throw HipError{"hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e)};
+  S.allocs.push_back(p);
+  return p;
+}
+
+template <typename D>
+static D* upload(Prep& S, const D& h, hipStream_t st) {
+  D* d = (D*)dalloc(S, sizeof(D));
+  HIP_OK(hipMemcpyAsync(d, &h, sizeof(D), hipMemcpyHostToDevice, st));
+  return d;
+}
+template <typename D>
+static D* upload_vec(Prep& S, const std::vector<D>& h, hipStream_t st) {
+  D* d = (D*)dalloc(S, std::max<size_t>(1, h.size()) * sizeof(D));
+  if (!h.empty()) HIP_OK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(D), hipMemcpyHostToDevice, st));
+  return d;
+}
+
+static int dtype_bytes(int dt) { return dt == LMFAO_F64 ? 8 : 4; }
+
+static void add_fill(Prep& S, void* p, int64_t bytes, const std::string& name) {
+  Step s;
+  s.name = name;
+  s.kind = 0;
+  s.dev = p;
+  s.bytes = bytes;
+  S.steps.push_back(s);
+}
+
+// strides of a dense key over attribute list (last attribute fastest)
+static std::vector<int64_t> strides_of(const Plan& P, const std::vector<int>& attrs) {
+  std::vector<int64_t> st(attrs.size(), 1);
+  int64_t m = 1;
+  for (int i = (int)attrs.size() - 1; i >= 0; --i) {
+    st[i] = m;
+    m *= P.attrs[attrs[i]].domain;
+  }
+  return st;
+}
+
+static DView dview_of(const Prep& S, int vid) {
+  const Plan& P = *S.P;
+  const ViewDef& V = P.views[vid];
+  const OutBuf& B = S.vout[vid];
+  DView d{};
+  d.cnt = B.cnt;
+  d.vals = B.vals;
+  d.codes = B.codes;
+  d.vals_f64 = B.f64 ? 1 : 0;
+  d.n_vals = B.n_vals;
+  d.n_codes = B.n_codes;
+  d.nkey = (int)V.key.size();
+  if (d.nkey > kMaxKey) throw PlanError{LMFAO_EUNSUPPORTED, "view key with more than 4 attributes"};
+  std::vector<int64_t> st = strides_of(P, V.key);
+  for (int k = 0; k < d.nkey; ++k) d.key_stride[k] = st[k];
+  d.n_keys = V.n_keys;
+  return d;
+}
+
+// library copy of an original relation column (for row pieces and view builds)
+static void* raw_column(Prep& S, int r, int c, const void* const* const* cols, hipStream_t st) {
+  NodeData& N = S.nodes[r];
+  if (N.raw_col[c]) return N.raw_col[c];
+  const RelDef& R = S.P->rels[r];
+  size_t bytes = (size_t)R.n_rows * dtype_bytes(R.dtypes[c]);
+  void* p = dalloc(S, bytes);
+  if (bytes) HIP_OK(hipMemcpyAsync(p, cols[r][c], bytes, hipMemcpyDeviceToDevice, st));
+  N.raw_col[c] = p;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// prepare: sort a relation by its attribute order and cut it into pieces
+// ---------------------------------------------------------------------------
+static void prepare_node(Prep& S, int r, int cut, const std::vector<int>& need_cols,
+                         const void* const* const* cols, hipStream_t st) {
+  const Plan& P = *S.P;
+  const RelDef& R = P.rels[r];
+  NodeData& N = S.nodes[r];
+  const std::vector<int>& order = P.order[r];
+  int64_t n = R.n_rows;
+  N.cut = cut;
+  if (!N.sorted) {
+    double bits_d = 0;
+    for (int a : order) bits_d += std::log2((double)P.attrs[a].domain);
+    int bits = (int)std::ceil(bits_d - 1e-9);
+    if (bits > 64) throw PlanError{LMFAO_EUNSUPPORTED, "attribute order of " + R.name + " needs more than 64 key bits"};
+    if (bits < 1) bits = 1;
+    if (n > (int64_t)UINT32_MAX) throw PlanError{LMFAO_EUNSUPPORTED, "relation larger than 2^32 rows"};
+    DKeyCols kc{};
+    kc.n = (int)order.size();
+    if (kc.n > kMaxKey * 2) throw PlanError{LMFAO_EUNSUPPORTED, "attribute order longer than 8"};
+    for (int i = 0; i < kc.n; ++i) {
+      kc.cols[i] = cols[r][R.col.at(order[i])];
+      kc.dom[i] = P.attrs[order[i]].domain;
+    }
+    kc.err_flag = S.err_flag;
+    DKeyCols* dkc = upload(S, kc, st);
+    uint64_t *keys, *keys2;
+    uint32_t *idx, *idx2, *hist;
+    HIP_OK(hipMalloc(&keys, std::max<int64_t>(n, 1) * 8));
+    HIP_OK(hipMalloc(&keys2, std::max<int64_t>(n, 1) * 8));
+    HIP_OK(hipMalloc(&idx, std::max<int64_t>(n, 1) * 4));
+    HIP_OK(hipMalloc(&idx2, std::max<int64_t>(n, 1) * 4));
+    int nblocks = (int)((n + sort_tile() - 1) / sort_tile());
+    HIP_OK(hipMalloc(&hist, (size_t)256 * std::max(nblocks, 1) * 4));
+    if (n > 0) {
+      launch_make_keys(dkc, keys, idx, n, st);
+      bool swapped = false;
+      launch_sort(keys, idx, keys2, idx2, n, bits, hist, st, &swapped);
+      if (swapped) {
+        std::swap(keys, keys2);
+        std::swap(idx, idx2);
+      }
+    }
+    N.sorted_col.assign(R.attrs.size(), nullptr);
+    // segments at the cut level
+    uint64_t div = 1;
+    for (int i = cut; i < (int)order.size(); ++i) div *= (uint64_t)P.attrs[order[i]].domain;
+    int64_t cap = std::min<int64_t>(std::max<int64_t>(n, 1), 1 << 22);
+    std::vector<int64_t> hpos;
+    std::vector<uint64_t> hkey;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      unsigned long long* dcount;
+      int64_t* dpos;
+      uint64_t* dkey;
+      HIP_OK(hipMalloc(&dcount, 8));
+      HIP_OK(hipMalloc(&dpos, cap * 8));
+      HIP_OK(hipMalloc(&dkey, cap * 8));
+      HIP_OK(hipMemsetAsync(dcount, 0, 8, st));
+      if (n > 0) launch_segment_starts(keys, n, div, dcount, dpos, dkey, cap, st);
+      unsigned long long cnt = 0;
+      HIP_OK(hipMemcpyAsync(&cnt, dcount, 8, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      if ((int64_t)cnt <= cap) {
+        hpos.resize(cnt);
+        hkey.resize(cnt);
+        if (cnt) {
+          HIP_OK(hipMemcpy(hpos.data(), dpos, cnt * 8, hipMemcpyDeviceToHost));
+          HIP_OK(hipMemcpy(hkey.data(), dkey, cnt * 8, hipMemcpyDeviceToHost));
+        }
+        (void)hipFree(dcount);
+        (void)hipFree(dpos);
+        (void)hipFree(dkey);
+        break;
+      }
+      cap = (int64_t)cnt;
+      (void)hipFree(dcount);
+      (void)hipFree(dpos);
+      (void)hipFree(dkey);
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    (void)hipFree(keys);
+    (void)hipFree(keys2);
+    (void)hipFree(idx2);
+    (void)hipFree(hist);
+    N.perm = idx;
+    // pieces: segments in row order, split at kPieceMax rows
+    std::vector<size_t> ord(hpos.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return hpos[a] < hpos[b]; });
+    std::vector<int64_t> pb;
+    std::vector<std::vector<int32_t>> pk(cut);
+    for (size_t i = 0; i < ord.size(); ++i) {
+      int64_t b = hpos[ord[i]];
+      int64_t e = (i + 1 < ord.size()) ? hpos[ord[i + 1]] : n;
+      uint64_t key = hkey[ord[i]];
+      std::vector<int32_t> vals(cut);
+      for (int l = cut - 1; l >= 0; --l) {
+        uint64_t d = (uint64_t)P.attrs[order[l]].domain;
+        vals[l] = (int32_t)(key % d);
+        key /= d;
+      }
+      const int64_t pmax = S.f64 ? kPieceMaxF64 : kPieceMax;
+      for (int64_t x = b; x < e; x += pmax) {
+        pb.push_back(x);
+        for (int l = 0; l < cut; ++l) pk[l].push_back(vals[l]);
+      }
+    }
+    N.n_pieces = (int64_t)pb.size();
+    pb.push_back(n);
+    std::vector<int32_t> items{0};
+    int64_t acc = 0;
+    for (int64_t p = 0; p < N.n_pieces; ++p) {
+      acc += pb[p + 1] - pb[p];
+      if (acc >= kItemRows) {
+        items.push_back((int32_t)(p + 1));
+        acc = 0;
+      }
+    }
+    if (items.back() != (int32_t)N.n_pieces) items.push_back((int32_t)N.n_pieces);
+    N.n_items = (int)items.size() - 1;
+    N.piece_begin = upload_vec(S, pb, st);
+    std::vector<int32_t> flat;
+    for (int l = 0; l < cut; ++l) flat.insert(flat.end(), pk[l].begin(), pk[l].end());
+    N.piece_key = upload_vec(S, flat, st);
+    N.item_piece = upload_vec(S, items, st);
+    N.sorted = true;
+  }
+  for (int c : need_cols) {
+    if (N.sorted_col[c]) continue;
+    int eb = dtype_bytes(R.dtypes[c]);
+    void* p = dalloc(S, (size_t)std::max<int64_t>(n, 1) * eb);
+    if (n > 0) launch_gather(cols[r][c], N.perm, p, n, eb, st);
+    N.sorted_col[c] = p;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// descriptors of one group program
+// ---------------------------------------------------------------------------
+static void build_group(Prep& S, int gi, const void* const* const* cols, hipStream_t st) {
+  Plan& P = *S.P;
+  GroupDef& G = P.groups[gi];
+  const int r = G.node;
+  const RelDef& R = P.rels[r];
+  NodeData& N = S.nodes[r];
+  const bool f64 = S.f64;
+  const std::string gname = "g" + std::to_string(gi) + ":" + R.name;
+
+  // --- unique views: direct builds
+  for (int vid : G.unique_views) {
+    const ViewDef& V = P.views[vid];
+    DViewBuild b{};
+    b.n_rows = R.n_rows;
+    std::vector<int> colpos;   // relation columns referenced
+    auto cpos = [&](int c) {
+      for (size_t i = 0; i < colpos.size(); ++i)
+        if (colpos[i] == c) return (int)i;
+      if ((int)colpos.size() >= kMaxPieceCols) throw PlanError{LMFAO_EUNSUPPORTED, "too many columns in a view build"};
+      colpos.push_back(c);
+      return (int)colpos.size() - 1;
+    };
+    b.nkey = (int)V.key.size();
+    std::vector<int64_t> kst = strides_of(P, V.key);
+    for (int k = 0; k < b.nkey; ++k) {
+      b.key_col[k] = cpos(R.col.at(V.key[k]));
+      b.key_stride[k] = kst[k];
+    }
+    std::vector<int> deps(V.deps.begin(), V.deps.end());
+    b.n_views = (int)deps.size();
+    if (b.n_views > kMaxViews) throw PlanError{LMFAO_EUNSUPPORTED, "too many views in a view build"};
+    for (int i = 0; i < b.n_views; ++i) {
+      b.views[i] = dview_of(S, deps[i]);
+      const ViewDef& C = P.views[deps[i]];
+      for (int k = 0; k < (int)C.key.size(); ++k) b.views[i].key_src[k] = cpos(R.col.at(C.key[k]));
+    }
+    auto from_view = [&](int a, bool code) {
+      for (int i = 0; i < b.n_views; ++i) {
+        const ViewDef& C = P.views[deps[i]];
+        if ((code ? C.slot_of_code(a) : C.slot_of_attr(a)) >= 0) return i;
+      }
+      return -1;
+    };
+    b.n_vals = (int)V.val_attrs.size();
+    if (b.n_vals > 64) throw PlanError{LMFAO_EUNSUPPORTED, "view with more than 64 values"};
+    for (int s = 0; s < b.n_vals; ++s) {
+      int a = V.val_attrs[s];
+      if (R.has(a)) {
+        b.val_kind[s] = SRC_COL;
+        b.val_src[s] = cpos(R.col.at(a));
+        b.val_slot[s] = 0;
+      } else {
+        int i = from_view(a, false);
+        if (i < 0) throw PlanError{LMFAO_EINVAL, "internal: value source of view"};
+        b.val_kind[s] = SRC_VIEW;
+        b.val_src[s] = i;
+        b.val_slot[s] = P.views[deps[i]].slot_of_attr(a);
+      }
+    }
+    b.n_codes = (int)V.code_attrs.size();
+    if (b.n_codes > 8) throw PlanError{LMFAO_EUNSUPPORTED, "view with more than 8 codes"};
+    for (int s = 0; s < b.n_codes; ++s) {
+      int a = V.code_attrs[s];
+      if (R.has(a)) {
+        b.code_kind[s] = SRC_COL;
+        b.code_src[s] = cpos(R.col.at(a));
+      } else {
+        int i = from_view(a, true);
+        if (i < 0) throw PlanError{LMFAO_EINVAL, "internal: code source of view"};
+        b.code_kind[s] = SRC_VIEW;
+        b.code_src[s] = i;
+        b.code_slot[s] = P.views[deps[i]].slot_of_code(a);
+      }
+    }
+    for (size_t i = 0; i < colpos.size(); ++i) {
+      b.cols[i].ptr = raw_column(S, r, colpos[i], cols, st);
+      b.cols[i].dtype = R.dtypes[colpos[i]];
+    }
+    const OutBuf& O = S.vout[vid];
+    b.out_cnt = O.cnt;
+    b.out_vals = O.vals;
+    b.out_codes = O.codes;
+    b.err_flag = S.err_flag;
+    Step s;
+    s.name = gname + ":view_build:V" + std::to_string(vid);
+    s.kind = 1;
+    s.dev = upload(S, b, st);
+    s.n = R.n_rows;
+    S.steps.push_back(s);
+  }
+  if (!G.has_program) return;
+  GroupProgram& g = G.prog;
+
+  // program view index -> device descriptors
+  std::vector<int> scan_view(g.views.size(), -1), con_view(g.views.size(), -1);
+  int n_in = 0, n_out = 0;
+  for (size_t k = 0; k < g.views.size(); ++k) {
+    if (g.view_outer[k]) con_view[k] = n_out++;
+    else scan_view[k] = n_in++;
+  }
+  auto remap_mask = [&](uint32_t m, const std::vector<int>& map) {
+    uint32_t o = 0;
+    for (size_t k = 0; k < map.size(); ++k)
+      if ((m >> k) & 1u) {
+        if (map[k] < 0) throw PlanError{LMFAO_EINVAL, "internal: mask view on wrong side"};
+        o |= 1u << map[k];
+      }
+    return o;
+  };
+
+  void* psi_f = nullptr;
+  int32_t* psi_i = nullptr;
+  int psi_f_stride = 0, psi_i_stride = 0;
+  std::vector<int> pcols_key;   // contract piece columns (order positions or relation columns)
+  pcols_key = g.piece_cols;
+
+  if (!g.row_pieces) {
+    // ---- scan descriptor
+    std::vector<int> scols = g.scan_cols;
+    auto scol = [&](int c) {
+      for (size_t i = 0; i < scols.size(); ++i)
+        if (scols[i] == c) return (int)i;
+      if ((int)scols.size() >= kMaxScanCols) throw PlanError{LMFAO_EUNSUPPORTED, "too many scanned columns"};
+      scols.push_back(c);
+      return (int)scols.size() - 1;
+    };
+    DScan d{};
+    d.n_views = n_in;
+    for (size_t k = 0; k < g.views.size(); ++k) {
+      if (scan_view[k] < 0) continue;
+      DView v = dview_of(S, g.views[k]);
+      const ViewDef& V = P.views[g.views[k]];
+      for (int q = 0; q < (int)V.key.size(); ++q) v.key_src[q] = scol(R.col.at(V.key[q]));
+      d.views[scan_view[k]] = v;
+    }
+    if (g.in_masks.size() > (size_t)kMaxMasks) throw PlanError{LMFAO_EUNSUPPORTED, "too many inner masks"};
+    d.n_masks = (int)g.in_masks.size();
+    auto mask_idx = [&](uint32_t m) {
+      for (size_t i = 0; i < g.in_masks.size(); ++i)
+        if (g.in_masks[i] == m) return (int)i;
+      throw PlanError{LMFAO_EINVAL, "internal: unknown mask"};
+    };
+    for (int i = 0; i < d.n_masks; ++i) d.masks[i] = remap_mask(g.in_masks[i], scan_view);
+    // atoms, with duplicates where two float entries need one triangle slot under different masks
+    std::vector<AtomRef> atoms = g.in_atoms;
+    std::vector<std::pair<int, int>> ent(g.psi_f.size());
+    std::map<std::pair<int, int>, int> taken;   // (ai,aj) -> mask idx
+    for (size_t e = 0; e < g.psi_f.size(); ++e) {
+      int ai = g.psi_f[e].ai, aj = g.psi_f[e].aj;
+      int mi = mask_idx(g.psi_f[e].imask);
+      auto it = taken.find({ai, aj});
+      if (it != taken.end() && it->second != mi) {
+        int src = aj >= 0 ? aj : ai;
+        atoms.push_back(atoms[src]);
+        int dup = (int)atoms.size() - 1;
+        if (aj >= 0) aj = dup; else ai = dup;
+        if (ai > aj) std::swap(ai, aj);
+      }
+      taken[{ai, aj}] = mi;
+      ent[e] = {ai, aj};
+    }
+    const int NA = (int)atoms.size();
+    if (NA > kMaxAtoms) throw PlanError{LMFAO_EUNSUPPORTED, "more than 8 inner factors at " + R.name};
+    d.n_atoms = NA;
+    // column atoms already hold their position in the scanned-column list
+    auto atom_dev = [&](const AtomRef& a) {
+      DAtom x{};
+      x.kind = a.kind;
+      x.src = a.kind == SRC_COL ? a.src : scan_view[a.src];
+      x.slot = a.slot;
+      return x;
+    };
+    for (int i = 0; i < NA; ++i) d.atoms[i] = atom_dev(atoms[i]);
+    if (g.in_codes.size() > (size_t)kMaxCodes) throw PlanError{LMFAO_EUNSUPPORTED, "too many inner codes"};
+    d.n_codes = (int)g.in_codes.size();
+    for (int i = 0; i < d.n_codes; ++i) d.codes[i] = atom_dev(g.in_codes[i]);
+    // float entries on the extended triangle (index 0 = constant 1)
+    auto tri = [&](int i, int j) { return i * (NA + 1) - i * (i - 1) / 2 + (j - i); };
+    d.pf_need = 0;
+    for (int t = 0; t < kTriangle; ++t) { d.pf_slot[t] = -1; d.pf_mask[t] = 0; }
+    bool uniform = true;
+    int first_mask = -1;
+    for (size_t e = 0; e < g.psi_f.size(); ++e) {
+      int t = tri(ent[e].first + 1, ent[e].second + 1);
+      if (t == 0 || t >= 64) throw PlanError{LMFAO_EINVAL, "internal: float entry index"};
+      d.pf_need |= 1ull << t;
+      d.pf_slot[t] = (int)e;
+      int mi = mask_idx(g.psi_f[e].imask);
+      d.pf_mask[t] = (int8_t)mi;
+      if (first_mask < 0) first_mask = mi;
+      uniform &= mi == first_mask;
+    }
+    d.pf_uniform = uniform ? 1 : 0;
+    d.pf_mask_idx = first_mask < 0 ? 0 : first_mask;
+    d.pf_n = (int)g.psi_f.size();
+    if (g.psi_i.size() > (size_t)kMaxMasks) throw PlanError{LMFAO_EUNSUPPORTED, "too many count entries"};
+    d.n_pi = (int)g.psi_i.size();
+    for (int i = 0; i < d.n_pi; ++i) d.pi_mask_idx[i] = mask_idx(g.psi_i[i]);
+    if (g.hists.size() > (size_t)kMaxHists) throw PlanError{LMFAO_EUNSUPPORTED, "too many histograms"};
+    d.n_hists = (int)g.hists.size();
+    for (int i = 0; i < d.n_hists; ++i) {
+      const HistDef& h = g.hists[i];
+      d.hists[i] = DHist{h.code, h.dom, h.is_float, h.ai, h.aj, mask_idx(h.imask), h.offset, 0};
+    }
+    d.hist_i_bins = g.hist_i_bins;
+    d.hist_f_bins = g.hist_f_bins;
+    // direct tables
+    int ntab = 0;
+    int lds_used = 0;
+    uint32_t tab_omask = 0;
+    bool tab_omask_set = false;
+    std::vector<std::pair<int, int>> lds_tables;   // (output index, lds offset)
+    for (size_t oi = 0; oi < g.outs.size(); ++oi) {
+      const ProgOutput& po = g.outs[oi];
+      if (po.mode != 2) continue;
+      if (ntab >= kMaxTables) throw PlanError{LMFAO_EUNSUPPORTED, "too many direct group-by tables"};
+      DTable& T = d.tables[ntab++];
+      T.ncode = (int)po.key_codes.size();
+      if (T.ncode > 3) throw PlanError{LMFAO_EUNSUPPORTED, "table key with more than 3 attributes"};
+      for (int k = 0; k < T.ncode; ++k) {
+        T.code[k] = po.key_codes[k];
+        T.stride[k] = po.key_stride[k];
+      }
+      T.n_rows = po.n_rows;
+      if (po.tcomps.size() > (size_t)kMaxTableComps) throw PlanError{LMFAO_EUNSUPPORTED, "too many table components"};
+      T.n_tcomps = (int)po.tcomps.size();
+      for (int q = 0; q < T.n_tcomps; ++q) {
+        T.tcomp[q] = po.tcomps[q].comp;
+        T.tai[q] = po.tcomps[q].ai;
+        T.taj[q] = po.tcomps[q].aj;
+        T.tmask[q] = mask_idx(po.tcomps[q].imask);
+      }
+      const OutBuf& O = po.ref.kind == 0 ? S.qout[po.ref.id] : S.vout[po.ref.id];
+      T.cnt = O.cnt;
+      T.vals = O.vals;
+      T.vals_f64 = O.f64 ? 1 : 0;
+      T.n_vals = O.n_vals;
+      if (lds_used + po.n_rows <= kLdsTableMax) {
+        T.lds = 1;
+        T.lds_off = lds_used;
+        lds_tables.push_back({(int)oi, lds_used});
+        lds_used += (int)po.n_rows;
+      }
+      if (po.omask) {
+        if (tab_omask_set && tab_omask != po.omask)
+          throw PlanError{LMFAO_EUNSUPPORTED, "direct tables with different outer multiplicities"};
+        tab_omask = po.omask;
+        tab_omask_set = true;
+      }
+    }
+    d.n_tables = ntab;
+    d.lds_tab_i = lds_used;
+    d.mu_out_views = 0;
+    for (size_t k = 0; k < g.views.size(); ++k) {
+      if (!((tab_omask >> k) & 1u)) continue;
+      DView v = dview_of(S, g.views[k]);
+      const ViewDef& V = P.views[g.views[k]];
+      std::vector<int> pos(V.key.size());
+      for (int q = 0; q < (int)V.key.size(); ++q) {
+        auto it = std::find(g.order.begin(), g.order.end(), V.key[q]);
+        v.key_src[q] = (int)(it - g.order.begin());
+      }
+      d.outer_views[d.mu_out_views++] = v;
+    }
+    // columns and pieces
+    std::vector<int> need = scols;
+    prepare_node(S, r, g.cut, need, cols, st);
+    d.n_cols = (int)scols.size();
+    for (int i = 0; i < d.n_cols; ++i) {
+      d.cols[i].ptr = N.sorted_col[scols[i]];
+      d.cols[i].dtype = R.dtypes[scols[i]];
+    }
+    d.piece_key = N.piece_key;
+    d.n_piece_key = g.cut;
+    d.n_pieces = N.n_pieces;
+    d.piece_begin = N.piece_begin;
+    d.item_piece = N.item_piece;
+    d.n_items = N.n_items;
+    psi_f_stride = d.pf_n + d.hist_f_bins;
+    psi_i_stride = d.n_pi + d.hist_i_bins;
+    d.psi_f_stride = psi_f_stride;
+    d.psi_i_stride = psi_i_stride;
+    psi_f = dalloc(S, (size_t)std::max<int64_t>(1, N.n_pieces) * std::max(1, psi_f_stride) * (f64 ? 8 : 4));
+    psi_i = (int32_t*)dalloc(S, (size_t)std::max<int64_t>(1, N.n_pieces) * std::max(1, psi_i_stride) * 4);
+    d.psi_f = psi_f;
+    d.psi_i = psi_i;
+    int waves = scan_waves_per_block();
+    int grid = (int)std::min<int64_t>((N.n_items + waves - 1) / waves, 2048);
+    grid = std::max(grid, 1);
+    d.part_i = (int64_t*)dalloc(S, (size_t)grid * std::max(1, lds_used) * 8);
+    d.err_flag = S.err_flag;
+    int lds = scan_lds_bytes(d, f64);
+    if (lds > 160 * 1024) throw PlanError{LMFAO_EUNSUPPORTED, "scan needs more LDS than a CU has"};
+    Step s;
+    s.name = gname + ":scan";
+    s.kind = 2;
+    s.dev = upload(S, d, st);
+    s.na = NA;
+    s.grid = grid;
+    s.lds = lds;
+    // bytes the scan must move: each scanned column once, the piece offsets,
+    // each inner view's rows once, the per-piece partial sums, table partials
+    s.rows = R.n_rows;
+    s.pieces = N.n_pieces;
+    for (int i = 0; i < d.n_cols; ++i) s.alg_read += (double)R.n_rows * (d.cols[i].dtype == LMFAO_F64 ? 8 : 4);
+    s.alg_read += (double)(N.n_pieces + 1) * 8 + (double)(N.n_items + 1) * 4;
+    for (int v = 0; v < d.n_views; ++v)
+      s.alg_read += (double)d.views[v].n_keys * (8 + d.views[v].n_vals * (d.views[v].vals_f64 ? 8 : 4) +
+                                                  d.views[v].n_codes * 4);
+    s.alg_write += (double)N.n_pieces * (psi_f_stride * (f64 ? 8 : 4) + psi_i_stride * 4);
+    s.alg_write += (double)grid * lds_used * 8;
+    s.alg_flop = (double)R.n_rows * 2 * (double)std::max(1, d.pf_n);
+    S.steps.push_back(s);
+    for (auto& lt : lds_tables) {
+      const ProgOutput& po = g.outs[lt.first];
+      const OutBuf& O = po.ref.kind == 0 ? S.qout[po.ref.id] : S.vout[po.ref.id];
+      DTableReduce tr{};
+      tr.n = po.n_rows;
+      tr.n_blocks = grid;
+      tr.stride = lds_used;
+      tr.off = lt.second;
+      tr.part_i = d.part_i;
+      tr.dst_cnt = O.cnt;
+      Step t;
+      t.name = gname + ":table_reduce";
+      t.kind = 3;
+      t.dev = upload(S, tr, st);
+      t.n = po.n_rows;
+      S.steps.push_back(t);
+    }
+  }
+
+  // ---- contraction
+  if (g.feats.empty() && g.scatter.empty()) return;
+  DContract c{};
+  std::vector<int> pk = pcols_key;
+  auto pcol = [&](int key) {
+    for (size_t i = 0; i < pk.size(); ++i)
+      if (pk[i] == key) return (int)i;
+    if ((int)pk.size() >= kMaxPieceCols) throw PlanError{LMFAO_EUNSUPPORTED, "too many piece columns"};
+    pk.push_back(key);
+    return (int)pk.size() - 1;
+  };
+  c.n_views = n_out;
+  for (size_t k = 0; k < g.views.size(); ++k) {
+    if (con_view[k] < 0) continue;
+    DView v = dview_of(S, g.views[k]);
+    const ViewDef& V = P.views[g.views[k]];
+    for (int q = 0; q < (int)V.key.size(); ++q) {
+      int a = V.key[q];
+      int key;
+      if (g.row_pieces) key = R.col.at(a);
+      else key = (int)(std::find(g.order.begin(), g.order.end(), a) - g.order.begin());
+      v.key_src[q] = pcol(key);
+    }
+    c.views[con_view[k]] = v;
+  }
+  // masks of the features
+  std::vector<uint32_t> cmasks;
+  auto cmask_idx = [&](uint32_t m) {
+    for (size_t i = 0; i < cmasks.size(); ++i)
+      if (cmasks[i] == m) return (int)i;
+    cmasks.push_back(m);
+    return (int)cmasks.size() - 1;
+  };
+  std::vector<DFeat> feats;
+  for (auto& f : g.feats)
+    feats.push_back(DFeat{cmask_idx(f.mask), f.c1, f.v1, f.c2, f.v2, f.a1, f.a2, 0});
+  if (cmasks.empty()) cmask_idx(0);
+  if (cmasks.size() > (size_t)kMaxMasks * 4) throw PlanError{LMFAO_EUNSUPPORTED, "too many outer masks"};
+  c.n_masks = (int)cmasks.size();
+  for (int i = 0; i < c.n_masks; ++i) c.masks[i] = remap_mask(cmasks[i], con_view);
+  std::vector<DColB> colsb;
+  for (auto& cd : g.cols) {
+    DColB b{};
+    b.kind = cd.kind;
+    b.entry = cd.entry;
+    b.bin = 0;
+    b.feat = DFeat{0, cd.feat.c1, cd.feat.v1, cd.feat.c2, cd.feat.v2, cd.feat.a1, cd.feat.a2, 0};
+    colsb.push_back(b);
+  }
+  if (g.out_atoms.size() > (size_t)kMaxOuterAtoms) throw PlanError{LMFAO_EUNSUPPORTED, "too many outer factors"};
+  if (g.out_codes.size() > (size_t)kMaxOuterCodes) throw PlanError{LMFAO_EUNSUPPORTED, "too many outer codes"};
+  // column atoms and codes already hold their position in the piece-column list
+  c.n_atoms = (int)g.out_atoms.size();
+  for (int i = 0; i < c.n_atoms; ++i) {
+    const AtomRef& a = g.out_atoms[i];
+    c.atoms[i] = DAtom{a.kind, a.kind == SRC_COL ? a.src : con_view[a.src], a.slot, 0};
+  }
+  c.n_codes = (int)g.out_codes.size();
+  for (int i = 0; i < c.n_codes; ++i) {
+    const AtomRef& a = g.out_codes[i];
+    c.codes[i] = DAtom{a.kind, a.kind == SRC_COL ? a.src : con_view[a.src], a.slot, 0};
+  }
+  int64_t n_pieces;
+  if (g.row_pieces) {
+    n_pieces = R.n_rows;
+    c.n_pcols = (int)pk.size();
+    for (int i = 0; i < c.n_pcols; ++i) {
+      c.pcols[i].ptr = raw_column(S, r, pk[i], cols, st);
+      c.pcols[i].dtype = R.dtypes[pk[i]];
+    }
+    c.row_pieces = 1;
+  } else {
+    n_pieces = N.n_pieces;
+    c.n_pcols = (int)pk.size();
+    for (int i = 0; i < c.n_pcols; ++i) {
+      c.pcols[i].ptr = N.piece_key + (int64_t)pk[i] * N.n_pieces;
+      c.pcols[i].dtype = LMFAO_I32;
+    }
+    c.row_pieces = 0;
+    c.psi_f = psi_f;
+    c.psi_i = psi_i;
+    c.psi_f_stride = psi_f_stride;
+    c.psi_i_stride = psi_i_stride;
+  }
+  c.n_pieces = n_pieces;
+  c.n_feat = (int)feats.size();
+  c.n_feat_int = g.n_feat_int;
+  c.n_col = (int)colsb.size();
+  c.n_col_int = g.n_col_int;
+
+  c.feats = upload_vec(S, feats, st);
+  c.cols = upload_vec(S, colsb, st);
+  int64_t ppb = std::max<int64_t>(256, (n_pieces + 511) / 512);
+  ppb = std::min<int64_t>(ppb, 4096);
+  int grid_x = (int)std::max<int64_t>(1, (n_pieces + ppb - 1) / ppb);
+  int tiles = contract_tiles(c.n_feat, c.n_col);
+  int64_t icells = (int64_t)c.n_feat_int * c.n_col_int;
+  int grid_y = std::max(1, (tiles + contract_threads() - 1) / contract_threads());
+  grid_y = std::max<int>(grid_y, (int)((icells + contract_max_int_cells() - 1) / contract_max_int_cells()));
+  c.pieces_per_block = (int32_t)ppb;
+  c.part_f = (double*)dalloc(S, (size_t)grid_x * std::max(1, c.n_feat * c.n_col) * 8);
+  c.part_i = (int64_t*)dalloc(S, (size_t)grid_x * std::max(1, c.n_feat_int * c.n_col_int) * 8);
+  // scatter
+  std::vector<int32_t> sc_out, sc_comp, sc_f, sc_g;
+  for (auto& sc : g.scatter) {
+    sc_out.push_back(sc.out);
+    sc_comp.push_back(sc.comp);
+    sc_f.push_back(sc.f);
+    sc_g.push_back(sc.g);
+  }
+  c.n_scatter = (int)g.scatter.size();
+  c.sc_out = upload_vec(S, sc_out, st);
+  c.sc_comp = upload_vec(S, sc_comp, st);
+  c.sc_f = upload_vec(S, sc_f, st);
+  c.sc_g = upload_vec(S, sc_g, st);
+  std::vector<int64_t> so_stride;
+  std::vector<int32_t> so_code, so_ncomp, so_f64;
+  std::vector<int64_t*> so_cnt;
+  std::vector<void*> so_vals;
+  for (auto& po : g.outs) {
+    const OutBuf& O = po.ref.kind == 0 ? S.qout[po.ref.id] : S.vout[po.ref.id];
+    for (int k = 0; k < 3; ++k) {
+      if (po.mode == 1 && k < (int)po.key_codes.size()) {
+        so_code.push_back(po.key_codes[k]);
+        so_stride.push_back(po.key_stride[k]);
+      } else {
+        so_code.push_back(-1);
+        so_stride.push_back(0);
+      }
+    }
+    if (po.mode == 1 && po.key_codes.size() > 3) throw PlanError{LMFAO_EUNSUPPORTED, "scatter key with > 3 codes"};
+    so_ncomp.push_back(O.n_vals);
+    so_f64.push_back(O.f64 ? 1 : 0);
+    so_cnt.push_back(O.cnt);
+    so_vals.push_back(O.vals);
+  }
+  c.so_stride = upload_vec(S, so_stride, st);
+  c.so_code = upload_vec(S, so_code, st);
+  c.so_ncomp = upload_vec(S, so_ncomp, st);
+  c.so_vals_f64 = upload_vec(S, so_f64, st);
+  c.so_cnt = upload_vec(S, so_cnt, st);
+  c.so_vals = upload_vec(S, so_vals, st);
+  int lds = contract_lds_bytes(c, f64);
+  if (lds > 160 * 1024) throw PlanError{LMFAO_EUNSUPPORTED, "contraction needs more LDS than a CU has"};
+  Step s;
+  s.name = gname + ":contract";
+  s.kind = 4;
+  s.dev = upload(S, c, st);
+  s.grid = grid_x;
+  s.grid_y = grid_y;
+  s.lds = lds;
+  s.pieces = n_pieces;
+  s.rows = g.row_pieces ? R.n_rows : N.n_pieces;
+  for (int i = 0; i < c.n_pcols; ++i) s.alg_read += (double)n_pieces * (c.pcols[i].dtype == LMFAO_F64 ? 8 : 4);
+  s.alg_read += (double)n_pieces * (psi_f_stride * (f64 ? 8 : 4) + psi_i_stride * 4);
+  for (int v = 0; v < c.n_views; ++v)
+    s.alg_read += (double)std::min<int64_t>(c.views[v].n_keys, n_pieces) *
+                  (8 + c.views[v].n_vals * (c.views[v].vals_f64 ? 8 : 4) + c.views[v].n_codes * 4);
+  s.alg_write += (double)grid_x * ((double)c.n_feat * c.n_col * 8 + (double)icells * 8);
+  s.alg_flop = 2.0 * (double)n_pieces * c.n_feat * c.n_col;
+  S.steps.push_back(s);
+  // merge cells
+  if (!g.gemm_cells.empty()) {
+    std::vector<DCell> cells;
+    for (auto& gc : g.gemm_cells) {
+      const ProgOutput& po = g.outs[gc.second.out];
+      const OutBuf& O = po.ref.kind == 0 ? S.qout[po.ref.id] : S.vout[po.ref.id];
+      DCell x{};
+      x.f = gc.first.first;
+      x.g = gc.first.second;
+      x.is_int = (x.f < c.n_feat_int && x.g < c.n_col_int) ? 1 : 0;
+      x.vals_f64 = O.f64 ? 1 : 0;
+      if (gc.second.comp < 0) {
+        if (!x.is_int) throw PlanError{LMFAO_EINVAL, "internal: count cell not integral"};
+        x.cnt = O.cnt;
+        x.vals = nullptr;
+        x.idx = gc.second.row;
+      } else {
+        x.cnt = nullptr;
+        x.vals = O.vals;
+        x.idx = gc.second.row * O.n_vals + gc.second.comp;
+      }
+      cells.push_back(x);
+    }
+    Step m;
+    m.name = gname + ":merge";
+    m.kind = 5;
+    m.dev = upload_vec(S, cells, st);
+    m.n = (int64_t)cells.size();
+    m.part_f = c.part_f;
+    m.part_i = c.part_i;
+    m.n_blocks = grid_x;
+    m.NF = c.n_feat;
+    m.NG = c.n_col;
+    m.NFI = c.n_feat_int;
+    m.NGI = c.n_col_int;
+    S.steps.push_back(m);
+  }
+}
+
+static void prepare_all(Prep& S, const void* const* const* cols, hipStream_t st) {
+  Plan& P = *S.P;
+  S.nodes.assign(P.rels.size(), NodeData{});
+  for (size_t r = 0; r < P.rels.size(); ++r) S.nodes[r].raw_col.assign(P.rels[r].attrs.size(), nullptr);
+  S.err_flag = (int32_t*)dalloc(S, 8);
+  HIP_OK(hipMemsetAsync(S.err_flag, 0, 8, st));
+  // validate integer columns against their domains
+  for (size_t r = 0; r < P.rels.size(); ++r) {
+    const RelDef& R = P.rels[r];
+    for (size_t c = 0; c < R.attrs.size(); ++c) {
+      const AttrDef& A = P.attrs[R.attrs[c]];
+      if (R.dtypes[c] == LMFAO_I32 && A.domain > 0 && R.n_rows > 0) {
+        if (!cols[r][c]) throw PlanError{LMFAO_EINVAL, "null column " + A.name + " of " + R.name};
+        launch_validate((const int32_t*)cols[r][c], R.n_rows, A.domain, S.err_flag, st);
+      }
+      if (R.n_rows > 0 && !cols[r][c]) throw PlanError{LMFAO_EINVAL, "null column " + A.name + " of " + R.name};
+    }
+  }
+  int32_t flag = 0;
+  HIP_OK(hipMemcpyAsync(&flag, S.err_flag, 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (flag & 2) throw PlanError{LMFAO_EINVAL, "an integer column holds a value outside its declared domain"};
+  // output buffers: every view and query result lives in one arena that a
+  // single fill zeroes at the start of each run
+  S.vout.resize(P.views.size());
+  S.qout.resize(P.queries.size());
+  std::vector<std::pair<void**, size_t>> carve;
+  for (auto& V : P.views) {
+    OutBuf& B = S.vout[V.id];
+    B.n_rows = V.n_keys;
+    B.f64 = V.unique ? S.f64 : true;
+    B.n_vals = V.unique ? (int)V.val_attrs.size() : (int)V.val_monos.size();
+    B.n_codes = V.unique ? (int)V.code_attrs.size() : 0;
+    carve.push_back({(void**)&B.cnt, (size_t)B.n_rows * 8});
+    carve.push_back({&B.vals, (size_t)B.n_rows * B.n_vals * (B.f64 ? 8 : 4)});
+    carve.push_back({(void**)&B.codes, (size_t)B.n_rows * B.n_codes * 4});
+  }
+  for (size_t q = 0; q < P.queries.size(); ++q) {
+    const QueryDef& Q = P.queries[q];
+    OutBuf& B = S.qout[q];
+    B.n_rows = 1;
+    for (int a : Q.groupby) B.n_rows *= P.attrs[a].domain;
+    if (B.n_rows > ((int64_t)1 << 31)) throw PlanError{LMFAO_EUNSUPPORTED, "group-by domain too large for a dense table"};
+    B.f64 = true;
+    B.n_vals = (int)Q.aggs.size();
+    carve.push_back({(void**)&B.cnt, (size_t)B.n_rows * 8});
+    carve.push_back({&B.vals, (size_t)B.n_rows * B.n_vals * 8});
+  }
+  size_t arena = 0;
+  for (auto& c : carve) arena += (c.second + 255) & ~(size_t)255;
+  char* base = (char*)dalloc(S, std::max<size_t>(arena, 256));
+  size_t off = 0;
+  for (auto& c : carve) {
+    *c.first = base + off;
+    off += (c.second + 255) & ~(size_t)255;
+  }
+  add_fill(S, base, (int64_t)arena, "zero");
+  // groups in dependency-level order
+  std::vector<int> gorder(P.groups.size());
+  std::iota(gorder.begin(), gorder.end(), 0);
+  std::stable_sort(gorder.begin(), gorder.end(),
+                   [&](int a, int b) { return P.groups[a].level < P.groups[b].level; });
+  for (int gi : gorder) build_group(S, gi, cols, st);
+  HIP_OK(hipStreamSynchronize(st));
+  for (auto& N : S.nodes)
+    if (N.perm) {
+      (void)hipFree(N.perm);
+      N.perm = nullptr;
+    }
+}
+
+// timed steps: scans and contractions (the kernels that move the data); the
+// whole run is timed as well.  Slot 0 of a run = whole run.
+static bool timed_step(const Step& s) { return s.kind == 2 || s.kind == 4; }
+static int timed_slots(const Prep& S) {
+  int n = 1;
+  for (auto& s : S.steps) n += timed_step(s);
+  return n;
+}
+
+static void enqueue_run(Prep& S, hipStream_t st) {
+  int base = 0;
+  if (S.timing) {
+    int slots = timed_slots(S);
+    base = S.timed_runs * slots * 2;
+    size_t need = (size_t)base + slots * 2;
+    while (S.ev.size() < need) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      S.ev.push_back(e);
+    }
+    HIP_OK(hipEventRecord(S.ev[base], st));
+  }
+  int slot = 1;
+  for (size_t i = 0; i < S.steps.size(); ++i) {
+    Step& s = S.steps[i];
+    bool t = S.timing && timed_step(s);
+    if (t) HIP_OK(hipEventRecord(S.ev[base + 2 * slot], st));
+    switch (s.kind) {
+      case 0: launch_fill(s.dev, s.bytes, st); break;
+      case 1: launch_view_build((const DViewBuild*)s.dev, s.n, S.f64, st); break;
+      case 2: launch_scan((const DScan*)s.dev, s.na, S.f64, s.grid, s.lds, st); break;
+      case 3: launch_table_reduce((const DTableReduce*)s.dev, s.n, st); break;
+      case 4: launch_contract((const DContract*)s.dev, S.f64, s.grid, s.grid_y, s.lds, st); break;
+      case 5:
+        launch_merge_cells((const DCell*)s.dev, s.n, s.part_f, s.part_i, s.n_blocks, s.NF, s.NG, s.NFI, s.NGI, st);
+        break;
+    }
+    if (t) {
+      HIP_OK(hipEventRecord(S.ev[base + 2 * slot + 1], st));
+      ++slot;
+    }
+  }
+  if (S.timing) {
+    HIP_OK(hipEventRecord(S.ev[base + 1], st));
+    S.timed_runs++;
+  }
+  HIP_OK(hipGetLastError());
+}
+
+}  // namespace lmfao
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace lmfao;
+
+static lmfao_status set_err(lmfao_status st, const std::string& m) {
+  g_last_error = m;
+  return st;
+}
+
+extern "C" {
+
+void lmfao_default_options(lmfao_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = LMFAO_PREC_F64;
+  o->form = LMFAO_FORM_FUSED;
+  o->root_policy = LMFAO_ROOT_GROUPBY;
+  o->n_order = nullptr;
+  o->order = nullptr;
+  o->min_segment = 0;
+}
+
+lmfao_status lmfao_plan(const lmfao_schema* schema, const lmfao_join_tree* tree, const lmfao_batch* batch,
+                        const lmfao_options* opts, lmfao_plan_t* out) {
+  g_last_error.clear();
+  if (!out) return set_err(LMFAO_EINVAL, "null output handle");
+  *out = nullptr;
+  try {
+    Plan* P = build_plan(schema, tree, batch, opts);
+    if (!P->supported) {
+      std::string why = P->unsupported_reason;
+      delete P;
+      return set_err(LMFAO_EUNSUPPORTED, why);
+    }
+    lmfao_plan_s* h = new lmfao_plan_s;
+    h->P = P;
+    *out = h;
+    return LMFAO_OK;
+  } catch (const PlanError& e) {
+    return set_err(e.status, e.msg);
+  } catch (const std::exception& e) {
+    return set_err(LMFAO_EINVAL, e.what());
+  }
+}
+
+lmfao_status lmfao_plan_describe(lmfao_plan_t plan, char* buf, size_t cap, size_t* need) {
+  if (!plan) return set_err(LMFAO_EINVAL, "null plan");
+  const std::string& j = plan->P->json;
+  if (need) *need = j.size() + 1;
+  if (buf && cap) {
+    size_t n = std::min(cap - 1, j.size());
+    std::memcpy(buf, j.data(), n);
+    buf[n] = 0;
+  }
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_plan_workspace_bytes(lmfao_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return set_err(LMFAO_EINVAL, "null argument");
+  const Plan& P = *plan->P;
+  size_t b = 0;
+  bool f64 = P.opts.precision == LMFAO_PREC_F64;
+  for (auto& V : P.views)
+    b += (size_t)V.n_keys * (8 + (V.unique ? V.val_attrs.size() * (f64 ? 8 : 4) + V.code_attrs.size() * 4
+                                           : V.val_monos.size() * 8));
+  for (auto& Q : P.queries) {
+    size_t rows = 1;
+    for (int a : Q.groupby) rows *= (size_t)P.attrs[a].domain;
+    b += rows * (8 + Q.aggs.size() * 8);
+  }
+  for (auto& G : P.groups)
+    if (G.has_program && !G.prog.row_pieces) {
+      const RelDef& R = P.rels[G.node];
+      for (int c : G.prog.scan_cols) b += (size_t)R.n_rows * (R.dtypes[c] == LMFAO_F64 ? 8 : 4);
+    }
+  *bytes = b;
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns, void* stream,
+                           lmfao_prepared_t* out) {
+  g_last_error.clear();
+  if (!plan || !columns || !out) return set_err(LMFAO_EINVAL, "null argument");
+  *out = nullptr;
+  std::unique_ptr<lmfao_prepared_s> S(new lmfao_prepared_s);
+  S->P = plan->P;
+  S->f64 = plan->P->opts.precision == LMFAO_PREC_F64;
+  S->stream = (hipStream_t)stream;
+  for (size_t r = 0; r < plan->P->rels.size(); ++r)
+    if (!columns[r]) return set_err(LMFAO_EINVAL, "null column list of relation " + plan->P->rels[r].name);
+  try {
+    prepare_all(*S, columns, (hipStream_t)stream);
+  } catch (const PlanError& e) {
+    return set_err(e.status, e.msg);
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  *out = S.release();
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, int32_t sync) {
+  g_last_error.clear();
+  if (!plan || !prep || prep->P != plan->P) return set_err(LMFAO_EINVAL, "plan and prepared handle do not match");
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    enqueue_run(*prep, st);
+    if (sync) {
+      HIP_OK(hipStreamSynchronize(st));
+      int32_t flag = 0;
+      HIP_OK(hipMemcpy(&flag, prep->err_flag, 4, hipMemcpyDeviceToHost));
+      if (flag & 1) return set_err(LMFAO_EINVAL, "a relation has duplicate values of its declared primary key");
+      if (flag & 2) return set_err(LMFAO_EINVAL, "an integer column holds a value outside its declared domain");
+    }
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_result_shape(lmfao_prepared_t prep, int32_t q, int64_t* n_groups, int32_t* n_keys,
+                                int32_t* n_aggs) {
+  if (!prep || q < 0 || q >= (int)prep->qout.size()) return set_err(LMFAO_EINVAL, "bad query index");
+  const OutBuf& B = prep->qout[q];
+  std::vector<int64_t> cnt(B.n_rows);
+  try {
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(cnt.data(), B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  int64_t g = 0;
+  for (int64_t c : cnt) g += c > 0;
+  if (n_groups) *n_groups = g;
+  if (n_keys) *n_keys = (int32_t)prep->P->queries[q].groupby.size();
+  if (n_aggs) *n_aggs = B.n_vals;
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, int64_t* counts, double* values) {
+  if (!prep || q < 0 || q >= (int)prep->qout.size()) return set_err(LMFAO_EINVAL, "bad query index");
+  const Plan& P = *prep->P;
+  const QueryDef& Q = P.queries[q];
+  const OutBuf& B = prep->qout[q];
+  std::vector<int64_t> cnt(B.n_rows);
+  std::vector<double> vals((size_t)B.n_rows * B.n_vals);
+  try {
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(cnt.data(), B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
+    if (!vals.empty()) HIP_OK(hipMemcpy(vals.data(), B.vals, vals.size() * 8, hipMemcpyDeviceToHost));
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  int nk = (int)Q.groupby.size();
+  std::vector<int64_t> dom(nk);
+  for (int i = 0; i < nk; ++i) dom[i] = P.attrs[Q.groupby[i]].domain;
+  int64_t g = 0;
+  for (int64_t row = 0; row < B.n_rows; ++row) {
+    if (cnt[row] <= 0) continue;
+    if (keys) {
+      int64_t x = row;
+      for (int i = nk - 1; i >= 0; --i) {
+        keys[g * nk + i] = x % dom[i];
+        x /= dom[i];
+      }
+    }
+    if (counts) counts[g] = cnt[row];
+    if (values)
+      for (int k = 0; k < B.n_vals; ++k) values[g * B.n_vals + k] = vals[(size_t)row * B.n_vals + k];
+    ++g;
+  }
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_view_shape(lmfao_prepared_t prep, int32_t v, int64_t* n_keys, int32_t* n_vals,
+                              int32_t* n_codes) {
+  if (!prep || v < 0 || v >= (int)prep->vout.size()) return set_err(LMFAO_EINVAL, "bad view index");
+  const OutBuf& B = prep->vout[v];
+  if (n_keys) *n_keys = B.n_rows;
+  if (n_vals) *n_vals = B.n_vals;
+  if (n_codes) *n_codes = B.n_codes;
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_view_copy(lmfao_prepared_t prep, int32_t v, int64_t* counts, double* values, int32_t* codes) {
+  if (!prep || v < 0 || v >= (int)prep->vout.size()) return set_err(LMFAO_EINVAL, "bad view index");
+  const OutBuf& B = prep->vout[v];
+  try {
+    HIP_OK(hipDeviceSynchronize());
+    if (counts) HIP_OK(hipMemcpy(counts, B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
+    if (values && B.n_vals) {
+      size_t n = (size_t)B.n_rows * B.n_vals;
+      if (B.f64) {
+        HIP_OK(hipMemcpy(values, B.vals, n * 8, hipMemcpyDeviceToHost));
+      } else {
+        std::vector<float> tmp(n);
+        HIP_OK(hipMemcpy(tmp.data(), B.vals, n * 4, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i) values[i] = tmp[i];
+      }
+    }
+    if (codes && B.n_codes) HIP_OK(hipMemcpy(codes, B.codes, (size_t)B.n_rows * B.n_codes * 4, hipMemcpyDeviceToHost));
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_set_timing(lmfao_prepared_t prep, int32_t on) {
+  if (!prep) return set_err(LMFAO_EINVAL, "null prepared handle");
+  prep->timing = on != 0;
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_run_timing(lmfao_prepared_t prep, int32_t cap, const char** names, float* ms, int32_t* n) {
+  if (!prep) return set_err(LMFAO_EINVAL, "null prepared handle");
+  int slots = timed_slots(*prep);
+  if (prep->timed_runs > 0) {
+    // mean over the runs recorded since the last call; entry 0 = whole run
+    prep->step_ms.assign(slots, 0.f);
+    try {
+      HIP_OK(hipDeviceSynchronize());
+      for (int r = 0; r < prep->timed_runs; ++r)
+        for (int k = 0; k < slots; ++k) {
+          float x = 0;
+          int b = r * slots * 2;
+          HIP_OK(hipEventElapsedTime(&x, prep->ev[b + 2 * k], prep->ev[b + 2 * k + 1]));
+          prep->step_ms[k] += x / prep->timed_runs;
+        }
+    } catch (const HipError& e) {
+      return set_err(LMFAO_EHIP, e.msg);
+    }
+    prep->timed_runs = 0;
+  }
+  int32_t k = (int32_t)prep->step_ms.size();
+  if (n) *n = k;
+  static const char* whole = "run";
+  std::vector<const char*> nm{whole};
+  for (auto& s : prep->steps)
+    if (timed_step(s)) nm.push_back(s.name.c_str());
+  for (int32_t i = 0; i < std::min(cap, k); ++i) {
+    if (names) names[i] = nm[i];
+    if (ms) ms[i] = prep->step_ms[i];
+  }
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t cap, size_t* need) {
+  if (!prep) return set_err(LMFAO_EINVAL, "null prepared handle");
+  std::string j = "{\"steps\":[";
+  bool first = true;
+  for (auto& s : prep->steps) {
+    if (s.kind == 0) continue;
+    if (!first) j += ",";
+    first = false;
+    static const char* kinds[] = {"fill", "view_build", "scan", "table_reduce", "contract", "merge"};
+    char tmp[512];
+    snprintf(tmp, sizeof(tmp),
+             "{\"name\":\"%s\",\"kind\":\"%s\",\"rows\":%lld,\"pieces\":%lld,\"alg_read_bytes\":%.0f,"
+             "\"alg_write_bytes\":%.0f,\"alg_flop\":%.0f,\"grid\":%d,\"grid_y\":%d,\"lds\":%d}",
+             s.name.c_str(), kinds[s.kind], (long long)s.rows, (long long)s.pieces, s.alg_read, s.alg_write,
+             s.alg_flop, s.grid, s.grid_y, s.lds);
+    j += tmp;
+  }
+  int64_t fill_bytes = 0;
+  for (auto& s : prep->steps)
+    if (s.kind == 0) fill_bytes += s.bytes;
+  j += "],\"fill_bytes\":" + std::to_string(fill_bytes) + "}";
+  if (need) *need = j.size() + 1;
+  if (buf && cap) {
+    size_t n = std::min(cap - 1, j.size());
+    std::memcpy(buf, j.data(), n);
+    buf[n] = 0;
+  }
+  return LMFAO_OK;
+}
+
+void lmfao_plan_free(lmfao_plan_t plan) {
+  if (!plan) return;
+  delete plan->P;
+  delete plan;
+}
+
+void lmfao_prepared_free(lmfao_prepared_t prep) { delete prep; }
+
+const char* lmfao_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

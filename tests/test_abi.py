@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every function ``include/lmfao.h``
+declares; host-side argument checks return status codes (no device work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lmfao.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lmfao_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lmfao_plan", "lmfao_prepare", "lmfao_run", "lmfao_result_copy",
+                     "lmfao_plan_describe", "lmfao_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2008_08657_amd as E
+    lib = E.load_library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_default_options():
+    import paper_2008_08657_amd as E
+    from paper_2008_08657_amd.binding import lmfao_options
+    lib = E.load_library()
+    o = lmfao_options()
+    lib.lmfao_default_options(ctypes.byref(o))
+    assert (o.precision, o.form, o.root_policy, o.min_segment, o.row_piece_max) == (0, 0, 0, 0, 0)
+
+
+def test_null_arguments_are_rejected_before_device_work():
+    import paper_2008_08657_amd as E
+    lib = E.load_library()
+    h = ctypes.c_void_p()
+    assert lib.lmfao_plan(None, None, None, None, ctypes.byref(h)) == 1
+    assert lib.lmfao_last_error()
+    assert lib.lmfao_prepare(None, None, None, ctypes.byref(h)) == 1
+    assert lib.lmfao_run(None, None, None, 0) == 1
+
+
+def test_describe_buffer_convention():
+    import paper_2008_08657_amd as E
+    import workloads as W
+    pl = E.Plan(W.tiny_star(n_fact=50), policy="fact")
+    need = ctypes.c_size_t()
+    assert pl.lib.lmfao_plan_describe(pl.handle, None, 0, ctypes.byref(need)) == 0
+    small = ctypes.create_string_buffer(8)
+    assert pl.lib.lmfao_plan_describe(pl.handle, small, 8, ctypes.byref(need)) == 0
+    assert len(small.value) == 7 and need.value > 8

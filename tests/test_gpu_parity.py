@@ -1,0 +1,138 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every case runs the whole batch on the GPU and compares every query result
+with the oracle, element by element (keys and counts exact, floats within the
+tolerance of ``tests/parity.py``).  Sizes span several pieces and work items
+and a ragged tail; the factorized scan is forced on small relations through
+``row_piece_max=-1`` and shallow cut levels through ``min_segment``.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+from parity import compare_all
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2008_08657_amd as E
+    E.load_library()
+    return E
+
+
+def run_engine(E, problem, **kw):
+    plan = E.Plan(problem, **kw)
+    cols = E.device_columns(problem)
+    prep = E.Prepared(plan, cols)
+    prep.run(sync=True)
+    res = prep.results()
+    return plan, prep, res
+
+
+def check(E, problem, tol, name, allow_unsupported=False, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+    try:
+        plan, prep, res = run_engine(E, problem, **kw)
+    except E.LmfaoError as e:
+        if allow_unsupported and e.status == 4:
+            print(f"[case] {name}: outside the supported class ({e})", flush=True)
+            return None, None
+        raise
+    ref = oracle.evaluate(problem)
+    return compare_all(res, ref, tol, name), plan
+
+
+def test_worked_example(eng):
+    p = W.favorita_example(0, n_sales=200)
+    worst, plan = check(eng, p, F64_TOL, "favorita_example", policy="groupby")
+    d = plan.describe()
+    assert len(d["groups"]) == 7
+
+
+def test_worked_example_forced_scan(eng):
+    p = W.favorita_example(1, n_sales=5_000)
+    check(eng, p, F64_TOL, "favorita_scan", policy="groupby", row_piece_max=-1, min_segment=1)
+
+
+@pytest.mark.parametrize("policy", ["fact", "groupby"])
+def test_tiny_star_rows(eng, policy):
+    p = W.tiny_star(seed=0, n_fact=30_000)
+    check(eng, p, F64_TOL, "tiny_star_rows", policy=policy)
+
+
+@pytest.mark.parametrize("min_segment", [1, 10_000_000])
+def test_tiny_star_scan(eng, min_segment):
+    # min_segment=1 cuts at the item level (pieces = item segments);
+    # a huge min_segment cuts at level 0 (pieces = fixed-size chunks)
+    p = W.tiny_star(seed=1, n_fact=50_001)
+    check(eng, p, F64_TOL, "tiny_star_scan", policy="fact", row_piece_max=-1, min_segment=min_segment)
+
+
+def test_tiny_star_full_size(eng):
+    # the 100k-row tiny star configuration, seed 0, FP64, in the bench's launch configuration
+    p = W.tiny_star(seed=0)
+    check(eng, p, F64_TOL, "tiny_star_full", policy="fact", row_piece_max=-1, min_segment=1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_foreign_keys(eng, seed):
+    p = W.random_acyclic(200 + seed, n_rel=4, max_rows=400, max_dom=30, unique_dims=True, n_queries=6)
+    # the fact heuristic keeps every group-by single-valued, so it always plans
+    check(eng, p, F64_TOL, f"random_fk_{seed}_fact", policy="fact")
+    check(eng, p, F64_TOL, f"random_fk_{seed}_fact_scan", policy="fact", row_piece_max=-1, min_segment=1)
+    # the group-by heuristic may carry a group-by through a multi-valued view
+    check(eng, p, F64_TOL, f"random_fk_{seed}_groupby", allow_unsupported=True, policy="groupby")
+    check(eng, p, F64_TOL, f"random_fk_{seed}_groupby_scan", allow_unsupported=True, policy="groupby",
+          row_piece_max=-1, min_segment=1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_many_to_many(eng, seed):
+    p = W.random_acyclic(300 + seed, n_rel=3, max_rows=300, max_dom=20, n_queries=6)
+    # group-bys only on the root's own attributes keep every view keyed by join attributes
+    p["batch"] = [dict(q, groupby=[g for g in q["groupby"] if g == "c0"], root="R0") for q in p["batch"]]
+    check(eng, p, F64_TOL, f"random_m2m_{seed}", policy="groupby")
+    check(eng, p, F64_TOL, f"random_m2m_{seed}_scan", policy="groupby", row_piece_max=-1, min_segment=1)
+
+
+def test_retail_snowflake_small(eng):
+    p = W.retail_snowflake(seed=0, n_inv=300_007, n_locn=60, n_dates=20, n_ksn=400,
+                           n_weather_dates=30)
+    check(eng, p, F32_TOL, "retail_small_f32", precision="f32", policy="fact", row_piece_max=5_000,
+          min_segment=16)
+
+
+def test_retail_snowflake_small_f64(eng):
+    p = W.retail_snowflake(seed=1, n_inv=120_000, n_locn=40, n_dates=12, n_ksn=300,
+                           n_weather_dates=15, dtype="f64")
+    check(eng, p, F64_TOL, "retail_small_f64", precision="f64", policy="fact", row_piece_max=5_000,
+          min_segment=16)
+
+
+def test_grocery_star_small(eng):
+    p = W.grocery_star(seed=0, n_sales=200_003, n_stores=9, n_items=300, n_dates=80, n_oil=60,
+                       n_hol=30)
+    check(eng, p, F32_TOL, "grocery_small_f32", precision="f32", policy="fact", row_piece_max=5_000,
+          min_segment=16)
+
+
+def test_repeat_runs_identical_counts(eng):
+    p = W.tiny_star(seed=2, n_fact=40_000)
+    plan = eng.Plan(p, policy="fact", row_piece_max=-1, min_segment=1)
+    prep = eng.Prepared(plan, eng.device_columns(p))
+    prep.run()
+    a = prep.results()
+    prep.run()
+    b = prep.results()
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x["keys"], y["keys"])
+        np.testing.assert_array_equal(x["count"], y["count"])

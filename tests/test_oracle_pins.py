@@ -103,8 +103,9 @@ def test_brute_force_worked_example_schema():
 def test_count_equals_fact_size_closed_form():
     p = W.tiny_star(seed=3, n_fact=5_000, n_stores=7, n_items=40)
     r = oracle.evaluate(p, queries=[0])[0]
+    assert p["batch"][0]["aggs"] == [[]]  # SUM(1) is the first query
     assert r["count"].tolist() == [5_000]
-    assert r["sum"][0, 0] == 5_000.0  # SUM(1) is the first aggregate
+    assert r["sum"][0, 0] == 5_000.0
 
 
 def test_single_relation_is_xtx():
@@ -114,7 +115,7 @@ def test_single_relation_is_xtx():
     schema = [{"name": "R", "n_rows": n, "attrs": [
         {"name": f"x{j}", "dtype": "f64", "domain": 0, "key": False} for j in range(4)]}]
     data = {"R": {f"x{j}": X[:, j] for j in range(4)}}
-    batch = W.covariance_batch([f"x{j}" for j in range(4)], ())
+    batch = W.covariance_batch([f"x{j}" for j in range(4)], (), split=False)
     p = {"schema": schema, "tree": [], "batch": batch, "data": data}
     r = oracle.evaluate(p)[0]
     Xe = np.concatenate([np.ones((n, 1)), X], axis=1)
@@ -150,9 +151,13 @@ def test_fk_join_is_fancy_indexing():
 
 def test_group_marginals_add_up():
     p = W.tiny_star(seed=4, n_fact=4_000, n_stores=8, n_items=50)
-    r0, r1 = oracle.evaluate(p)
-    assert int(r1["count"].sum()) == int(r0["count"][0])
-    np.testing.assert_allclose(r1["sum"].sum(axis=0), r0["sum"][0], rtol=1e-9, atol=1e-9)
+    res = oracle.evaluate(p)
+    half = len(p["batch"]) // 2
+    for k in range(half):
+        r0, r1 = res[k], res[half + k]
+        assert p["batch"][half + k]["groupby"] == ["cat"]
+        assert int(r1["count"].sum()) == int(r0["count"][0])
+        np.testing.assert_allclose(r1["sum"].sum(axis=0), r0["sum"][0], rtol=1e-9, atol=1e-9)
 
 
 def test_product_symmetry():
@@ -205,7 +210,7 @@ def test_planted_power_ignored_is_caught(monkeypatch):
         {"name": "a", "dtype": "f64", "domain": 0, "key": False},
         {"name": "b", "dtype": "f64", "domain": 0, "key": False}]}],
         "tree": [], "data": {"R": {"a": X[:, 0], "b": X[:, 1]}},
-        "batch": W.covariance_batch(["a", "b"], ())}
+        "batch": W.covariance_batch(["a", "b"], (), split=False)}
     r = oracle.evaluate(p)[0]
     Xe = np.concatenate([np.ones((50, 1)), X], axis=1)
     sigma = Xe.T @ Xe
@@ -224,7 +229,8 @@ def test_planted_wrong_group_key_is_caught(monkeypatch):
 
     monkeypatch.setattr(oracle, "evaluate_query", swapped)
     p = W.tiny_star(seed=1, n_fact=2_000, n_stores=9, n_items=30)
-    r0, r1 = oracle.evaluate(p)
+    res = oracle.evaluate(p)
+    r1 = res[len(p["batch"]) // 2]   # first query grouped by cat
     # marginals still add up, but the bincount pin on cat does not
     it = p["data"]["Items"]
     cat = it["cat"][p["data"]["S"]["item"]]

@@ -1,0 +1,164 @@
+"""Host-only tests of the planner through the C ABI (no GPU needed).
+
+Structural pins from the paper's worked example (section 2, Figure 2 and
+Figure 3): with Sales and Items as roots the batch decomposes into exactly the
+six directional views V_{T->S}, V_{R->T}, V_{O->T}, V_{H->S}, V_{I->S},
+V_{S->I}; the views and queries fall into seven groups whose dependency graph
+has the edges G1->G5, G2->G5, G5->G6, G3->G6, G4->G6, G6->G7; with the
+attribute order item < date < store at Sales, V_{I->S} is looked up at the
+item level, V_{H->S} at the date level and V_{T->S} at the store level.
+"""
+import json
+
+import pytest
+
+import workloads as W
+
+E = pytest.importorskip("paper_2008_08657_amd")
+
+
+def plan(problem, **kw):
+    return E.Plan(problem, **kw).describe()
+
+
+def views_by_edge(d):
+    return {(v["from"], v["to"]): v for v in d["views"]}
+
+
+def test_worked_example_views_and_groups():
+    p = W.favorita_example()
+    d = plan(p, policy="groupby")
+    # roots of the example: Q1, Q2 at Sales, Q3 at Items
+    assert [q["root"] for q in d["queries"]] == ["Sales", "Sales", "Items"]
+    edges = set(views_by_edge(d))
+    assert edges == {("Transactions", "Sales"), ("StoRes", "Transactions"), ("Oil", "Transactions"),
+                     ("Holidays", "Sales"), ("Items", "Sales"), ("Sales", "Items")}
+    assert len(d["views"]) == 6
+    groups = d["groups"]
+    assert len(groups) == 7
+
+    def gid(node, kind, target=None):
+        for g in groups:
+            if g["node"] != node:
+                continue
+            for o in g["outputs"]:
+                if o["kind"] == "view" and kind == "view":
+                    v = d["views"][o["id"]]
+                    if v["to"] == target:
+                        return g["id"]
+                if o["kind"] == "query" and kind == "query":
+                    return g["id"]
+        raise KeyError((node, kind, target))
+
+    g1 = gid("StoRes", "view", "Transactions")
+    g2 = gid("Oil", "view", "Transactions")
+    g3 = gid("Holidays", "view", "Sales")
+    g4 = gid("Items", "view", "Sales")
+    g5 = gid("Transactions", "view", "Sales")
+    g6 = gid("Sales", "query")
+    g7 = gid("Items", "query")
+    assert g4 != g7
+    # group 6 holds Q1, Q2 and V_{S->I}
+    out6 = groups[g6]["outputs"]
+    assert sorted(o["kind"] for o in out6) == ["query", "query", "view"]
+    dag = {(dep, g["id"]) for g in groups for dep in g["deps"]}
+    assert dag == {(g1, g5), (g2, g5), (g5, g6), (g3, g6), (g4, g6), (g6, g7)}
+
+
+def test_worked_example_merged_components():
+    d = plan(W.favorita_example(), policy="groupby")
+    v = views_by_edge(d)
+    # V_{T->S} serves Q2 (h from Oil) and Q3 (price from Oil): one view, two components
+    assert sorted(v[("Transactions", "Sales")]["components"]) == ["h", "price"]
+    assert v[("Sales", "Items")]["components"] == ["units*price"]
+    assert v[("Items", "Sales")]["components"] == ["g"]
+
+
+def test_worked_example_attribute_order_levels():
+    p = W.favorita_example()
+    d = plan(p, policy="groupby", order={"Sales": ["item", "date", "store"]},
+             row_piece_max=-1, min_segment=1)
+    sales = [g for g in d["groups"] if g["node"] == "Sales"][0]
+    assert d["relations"][0]["order"] == ["item", "date", "store"]
+    lv = {}
+    for pv in sales["program"]["views"]:
+        v = d["views"][pv["view"]]
+        lv[v["from"]] = pv["level"]
+    # looked up once per item, per date, per (date, store) respectively
+    assert lv == {"Items": 1, "Holidays": 2, "Transactions": 3}
+
+
+def test_fact_policy_roots_group_by_at_fact():
+    d = plan(W.favorita_example(), policy="fact")
+    # class is reached from Sales through the Items key, so Q3 stays at Sales
+    assert [q["root"] for q in d["queries"]] == ["Sales", "Sales", "Sales"]
+
+
+def test_root_override():
+    p = W.favorita_example()
+    p["batch"][0] = dict(p["batch"][0], root="Transactions")
+    d = plan(p, policy="groupby")
+    assert d["queries"][0]["root"] == "Transactions"
+
+
+def test_retail_plan_shape():
+    p = W.retail_snowflake(n_inv=1000)
+    for r in p["schema"]:
+        if r["name"] == "Inv":
+            r["n_rows"] = 84_000_000
+    d = plan(p, precision="f32", policy="fact")
+    assert len(d["queries"]) == 1269
+    v = views_by_edge(d)
+    assert v[("Items", "Inv")]["unique"] and v[("Weather", "Inv")]["unique"]
+    assert v[("Stores", "Inv")]["unique"] and v[("Demog", "Stores")]["unique"]
+    assert not v[("Inv", "Items")]["unique"]
+    inv = [g for g in d["groups"] if g["node"] == "Inv" and "program" in g]
+    assert len(inv) == 1, "the fact relation is scanned once"
+    prog = inv[0]["program"]
+    assert prog["cut"] == 2 and not prog["row_pieces"]
+    assert d["relations"][0]["order"] == ["locn", "date", "ksn"]
+    outer = {d["views"][x["view"]]["from"]: x["outer"] for x in prog["views"]}
+    assert outer == {"Weather": True, "Stores": True, "Items": False}
+
+
+def test_rk_means_step1_batch_is_n_queries():
+    # step 1 of Rk-means: one SUM(1) GROUP BY X_j query per attribute
+    p = W.tiny_star(n_fact=100)
+    attrs = ["store", "item", "cat"]
+    p["batch"] = [{"groupby": [a], "where": [], "aggs": [[]], "root": None} for a in attrs]
+    d = plan(p, policy="groupby")
+    assert len(d["queries"]) == len(attrs)
+
+
+@pytest.mark.parametrize("mutate, status", [
+    (lambda p: p.update(tree=[(0, 1)]), "EINVAL"),                                   # not connected
+    (lambda p: p.update(tree=[(0, 1), (0, 2), (1, 2)]), "EINVAL"),                   # cycle
+    (lambda p: p["batch"].append({"groupby": [], "where": [], "aggs": [[("nope", 1)]], "root": None}), "EINVAL"),
+    (lambda p: p["batch"].append({"groupby": [], "where": [], "aggs": [[("units", 2), ("f1", 1)]], "root": None}),
+     "EUNSUPPORTED"),                                                                # degree 3
+    (lambda p: p["batch"].append({"groupby": ["store", "item", "cat"], "where": [], "aggs": [[]], "root": None}),
+     "EUNSUPPORTED"),                                                                # 3 group-bys
+    (lambda p: p["batch"].append({"groupby": ["units"], "where": [], "aggs": [[]], "root": None}),
+     "EUNSUPPORTED"),                                                                # float group-by
+])
+def test_validation_errors(mutate, status):
+    p = W.tiny_star(n_fact=100)
+    mutate(p)
+    with pytest.raises(E.LmfaoError) as ei:
+        E.Plan(p, policy="fact")
+    assert str(ei.value).startswith(status)
+
+
+def test_running_intersection_violation():
+    p = W.tiny_star(n_fact=100)
+    # give Stores an attribute 'cat' too: Items and Stores are not adjacent
+    p["schema"][1]["attrs"].append({"name": "cat", "dtype": "i32", "domain": 20, "key": False})
+    with pytest.raises(E.LmfaoError) as ei:
+        E.Plan(p, policy="fact")
+    assert "running-intersection" in str(ei.value)
+
+
+def test_plan_json_roundtrip():
+    d = plan(W.tiny_star(n_fact=100), policy="fact")
+    assert json.loads(json.dumps(d)) == d
+    assert d["supported"] is True

@@ -69,15 +69,19 @@ def _spawn(seed: int, n: int):
 # batches
 # --------------------------------------------------------------------------
 
-def covariance_batch(continuous, categorical=(), pairs=True, groupby_cont=True):
+def covariance_batch(continuous, categorical=(), pairs=True, groupby_cont=True, split=True):
     """Aggregates of the ridge-regression covariance matrix with one-hot
-    categoricals (section 3, linear regression):
+    categoricals (section 3, linear regression), each entry one query as in
+    the paper:
 
-    * SUM(x_j * x_k) for j <= k over ``[1] + continuous`` (the intercept x_1 = 1
-      turns the first row into COUNT and SUM(x_k)),
+    * SELECT SUM(x_j * x_k) for j <= k over ``[1] + continuous`` (the intercept
+      x_1 = 1 turns the first row into COUNT and SUM(x_k)),
     * for every categorical c: SELECT c, SUM(x_k) GROUP BY c for x_k in
       ``[1] + continuous``,
     * for every pair of categoricals: SELECT c, c', SUM(1) GROUP BY c, c'.
+
+    With ``split=False`` the aggregates sharing a group-by are packed into one
+    multi-aggregate query instead (same cells).
     """
     feats = [None] + list(continuous)
     aggs = []
@@ -92,16 +96,19 @@ def covariance_batch(continuous, categorical=(), pairs=True, groupby_cont=True):
                 aggs.append([(fj, 2)])
             else:
                 aggs.append([(fj, 1), (fk, 1)])
-    batch = [{"groupby": [], "where": [], "aggs": aggs, "root": None}]
+    groups = [([], aggs)]
     if groupby_cont:
         for c in categorical:
-            batch.append({"groupby": [c], "where": [],
-                          "aggs": [[]] + [[(x, 1)] for x in continuous],
-                          "root": None})
+            groups.append(([c], [[]] + [[(x, 1)] for x in continuous]))
     if pairs:
         for a, b in itertools.combinations(categorical, 2):
-            batch.append({"groupby": [a, b], "where": [], "aggs": [[]],
-                          "root": None})
+            groups.append(([a, b], [[]]))
+    batch = []
+    for g, ag in groups:
+        if split:
+            batch += [{"groupby": list(g), "where": [], "aggs": [a], "root": None} for a in ag]
+        else:
+            batch.append({"groupby": list(g), "where": [], "aggs": ag, "root": None})
     return batch
 
 
@@ -139,10 +146,10 @@ def tiny_star(seed: int = 0, n_fact: int = 100_000, n_stores: int = 50,
              + [_attr(f"g{j}", "f64") for j in range(1, 4)] + [_attr("cat", "i32", 20)]),
     ]
     cont = ["units", "f1", "f2", "f3", "f4", "g1", "g2", "g3"]
-    ungrouped = covariance_batch(cont, (), pairs=False, groupby_cont=False)[0]
-    grouped = dict(ungrouped, groupby=["cat"])
+    ungrouped = covariance_batch(cont, (), pairs=False, groupby_cont=False)
+    grouped = [dict(q, groupby=["cat"]) for q in ungrouped]
     return {"name": "tiny_star", "schema": schema, "tree": [(0, 1), (0, 2)],
-            "batch": [ungrouped, grouped], "data": data, "policy": "fact",
+            "batch": ungrouped + grouped, "data": data, "policy": "fact",
             "precision": "f64"}
 
 
