@@ -151,7 +151,7 @@ typedef struct {
                             scan accepts (0 = default 64)                    */
   int64_t row_piece_max; /* relations with at most this many rows are
                             contracted row by row without a scan
-                            (0 = default 2^21; -1 = always scan)             */
+                            (0 = default 2^16; -1 = always scan)             */
 } lmfao_options;
 
 typedef struct lmfao_plan_s* lmfao_plan_t;

@@ -22,6 +22,9 @@ constexpr int kMaxPieceCols = 64;  // per-piece columns of a contraction
 constexpr int kMaxOuterAtoms = 64;
 constexpr int kMaxOuterCodes = 16;
 constexpr int kMaxViews = 8;       // views one kernel looks up
+constexpr int kMaxInnerViews = 4;  // views the scan looks up per tuple
+constexpr int kMaxWeights = 16;    // weights pre-aggregated over runs (registers)
+constexpr int kMaxWeightTable = 64;  // distinct histogram / table weights of a scan
 constexpr int kMaxKey = 4;         // attributes of one view key
 constexpr int kMaxAtoms = 8;       // inner factors of the fast scan
 constexpr int kMaxMasks = 4;       // distinct multiplicity masks in a scan
@@ -293,7 +296,11 @@ struct DAtom {
 };
 
 struct DHist {
-  int32_t code, dom, is_float, ai, aj, mask_idx, offset, pad;
+  int32_t code, dom, is_float, wi, offset, pad;   // wi: weight index
+};
+
+struct DWeight {   // per-tuple weight mu(mask) [* a_i * a_j for float weights]
+  int32_t is_float, ai, aj, mask_idx;
 };
 
 struct DTable {
@@ -303,7 +310,7 @@ struct DTable {
   int64_t n_rows;
   int32_t n_tcomps;
   int32_t tcomp[kMaxTableComps];   // -1 count, else value column
-  int32_t tai[kMaxTableComps], taj[kMaxTableComps], tmask[kMaxTableComps];
+  int32_t twi[kMaxTableComps];     // weight index of each component
   int64_t* cnt;                 // destination counts (int64)
   void* vals;                   // destination values
   int32_t vals_f64;
@@ -312,17 +319,67 @@ struct DTable {
   int32_t lds_off;              // offset of the count table in the block's LDS area
 };
 
+// packed per-key image of an inner view for one scan: the scan's factor
+// slots (T each), then its code slots and the view count (int32 each),
+// padded to 16 bytes; slots of factors / codes from elsewhere hold zero
+struct DImage {
+  const DView* view_dev;   // unused on the device; host bookkeeping
+  void* img;               // [n_keys x width_dw] dwords
+  int32_t width_dw;        // dwords per key row (multiple of 4)
+  int32_t code_off;        // first code dword
+  int32_t cnt_off;         // count dword
+  int32_t key_col;         // scan column of the (single-attribute) key, -1 = composite
+};
+
+struct DImageBuild {
+  DView view;              // source view
+  void* img;
+  int64_t n_keys;
+  int32_t width_dw, code_off, cnt_off, t_f64;
+  int32_t n_atoms;
+  int32_t atom_slot[kMaxAtoms];   // view value slot per scan factor (-1: not from this view)
+  int32_t n_codes;
+  int32_t code_slot[kMaxCodes];   // view code slot per scan code (-1: not from this view)
+};
+
+constexpr int kFastHists = 16;
+constexpr int kFastTables = 2;
+
+// hoisted form of a lean scan (all loop-invariant, read once per kernel)
+struct DFast {
+  const void* fcol[kMaxAtoms];     // factor columns in the compute type (null: factor from an image)
+  const int32_t* ccol[4];          // code columns (null: code from an image)
+  const void* img[2];              // inner view images (null: no view)
+  const int32_t* kcol[2];          // key column of each image
+  int32_t n_hist;
+  uint32_t hword[kFastHists];      // code(2) | mask(2) | float(1) | ai+1(4) | aj+1(4) | offset(16)
+  int32_t n_tab;
+  int32_t tab_ncode[kFastTables];
+  int32_t tab_code[kFastTables][3];
+  int32_t tab_stride[kFastTables][3];
+  int32_t tab_mask[kFastTables];   // count weight mask
+  int32_t tab_lds[kFastTables];    // 1: LDS offset valid, else global counts
+  int32_t tab_off[kFastTables];
+  int64_t* tab_cnt[kFastTables];
+};
+
 struct DScan {
+  int32_t fast;                    // lean kernel: images, <= 4 codes, direct atomics
+  DFast F;
+  DImage imgs[kMaxInnerViews];
   int32_t n_cols;
   DCol cols[kMaxScanCols];
   int32_t n_views;
-  DView views[kMaxViews];
+  DView views[kMaxInnerViews];
   int32_t n_masks;
   uint32_t masks[kMaxMasks];
   int32_t n_atoms;
   DAtom atoms[kMaxAtoms];
   int32_t n_codes;
   DAtom codes[kMaxCodes];
+  int32_t n_weights;
+  DWeight weights[kMaxWeightTable];
+  uint32_t run_codes;          // codes that key histograms / tables (run detection)
   // float entries over the extended-atom upper triangle: index t(i,j), i<=j in [0,NA]
   uint64_t pf_need;            // bit t set if the triangle entry is accumulated
   int32_t pf_mask_idx;         // mask of every float entry when pf_uniform
@@ -351,7 +408,7 @@ struct DScan {
   int32_t psi_f_stride, psi_i_stride;   // per piece
   void* psi_f;                     // [n_pieces x psi_f_stride] (T)
   int32_t* psi_i;                  // [n_pieces x psi_i_stride]
-  int64_t* part_i;                 // LDS table partials [grid x lds_tab_i]
+  int32_t* part_i;                 // LDS table partials [grid x lds_tab_i]
   int32_t* err_flag;
 };
 

@@ -306,6 +306,25 @@ __global__ void k_gather(const E* __restrict__ src, const uint32_t* __restrict__
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[perm[i]];
 }
+template <typename D>
+__global__ void k_gather_to(const void* __restrict__ src, int src_dtype, const uint32_t* __restrict__ perm, D* dst,
+                            int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t j = perm[i];
+    D x;
+    if (src_dtype == LMFAO_F32) x = (D)((const float*)src)[j];
+    else if (src_dtype == LMFAO_F64) x = (D)((const double*)src)[j];
+    else x = (D)((const int32_t*)src)[j];
+    dst[i] = x;
+  }
+}
+void launch_gather_convert(const void* src, int src_dtype, const uint32_t* perm, void* dst, int64_t n, bool to_f64,
+                           hipStream_t s) {
+  int grid = (int)std::min<int64_t>((n + 255) / 256, 16384);
+  if (to_f64) hipLaunchKernelGGL(k_gather_to<double>, dim3(grid), dim3(256), 0, s, src, src_dtype, perm, (double*)dst, n);
+  else hipLaunchKernelGGL(k_gather_to<float>, dim3(grid), dim3(256), 0, s, src, src_dtype, perm, (float*)dst, n);
+}
+
 void launch_gather(const void* src, const uint32_t* perm, void* dst, int64_t n, int elem_bytes, hipStream_t s) {
   int grid = (int)std::min<int64_t>((n + 255) / 256, 16384);
   if (elem_bytes == 8)
@@ -334,42 +353,62 @@ void launch_segment_starts(const uint64_t* keys, int64_t n, uint64_t div, unsign
 // ---------------------------------------------------------------------------
 // node scan
 // ---------------------------------------------------------------------------
-constexpr int kScanWaves = 4;   // wavefronts per block
+constexpr int kScanWaves = 8;   // wavefronts per block
 
 __device__ __forceinline__ int tri_index(int i, int j, int n) {
   // extended atoms 0..n (0 = constant 1), i <= j; row-major upper triangle
   return i * (n + 1) - i * (i - 1) / 2 + (j - i);
 }
 
+// select one of four per-lane values by a wave-uniform index (no private array)
+template <typename X>
+__device__ __forceinline__ X sel4(int i, X a, X b, X c, X d) {
+  return i == 0 ? a : (i == 1 ? b : (i == 2 ? c : d));
+}
+
+// One wavefront per work item (a run of pieces).  Lanes take consecutive rows
+// of a piece, so equal group-by codes of the sorted relation sit in runs of
+// neighbouring lanes; each run is summed with a segmented lane scan and only
+// its last lane issues the LDS atomics of the histograms and direct tables.
+// Per-lane values that histograms / tables address by a runtime index (codes,
+// run totals) go through a per-wave LDS slot area, never a private array.
 template <typename T, int NA>
 __global__ __launch_bounds__(kScanWaves * 64) void k_scan(const DScan* __restrict__ S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   constexpr int NT = (NA + 1) * (NA + 2) / 2;
-  // LDS: block count tables (int32), then per-wave histogram bins
   int32_t* tab_i = (int32_t*)smem;
   unsigned char* wbase = (unsigned char*)smem + (((size_t)S->lds_tab_i * 4 + 15) & ~(size_t)15);
   const int hist_i_bytes = (S->hist_i_bins * 4 + 7) & ~7;
   const int hist_bytes = hist_i_bytes + S->hist_f_bins * (int)sizeof(T);
-  const int hist_stride = (hist_bytes + 15) & ~15;
-  int32_t* hist_i = (int32_t*)(wbase + wid * hist_stride);
-  T* hist_f = (T*)((unsigned char*)hist_i + hist_i_bytes);
+  const int slot_bytes = (S->n_codes * 4 + (S->n_weights <= kMaxWeights ? S->n_weights * 8 : 0)) * 64;
+  const int wave_stride = (((hist_bytes + 15) & ~15) + slot_bytes + 15) & ~15;
+  unsigned char* wmem = wbase + wid * wave_stride;
+  int32_t* hist_i = (int32_t*)wmem;
+  T* hist_f = (T*)(wmem + hist_i_bytes);
+  int32_t* slot_c = (int32_t*)(wmem + ((hist_bytes + 15) & ~15));   // [n_codes][64]
+  double* slot_w = (double*)(slot_c + S->n_codes * 64);             // [n_weights][64] (int or T, as double bits)
 
   for (int i = threadIdx.x; i < S->lds_tab_i; i += blockDim.x) tab_i[i] = 0;
   __syncthreads();
 
   const int n_views = S->n_views;
   const int n_masks = S->n_masks;
+  const int n_codes = S->n_codes;
+  const int n_w = S->n_weights;
+  const bool runs = (S->n_hists + S->n_tables) > 0;
+  const bool direct = n_w > kMaxWeights;   // too many weights to pre-aggregate in registers
   const uint64_t need = S->pf_need;
   const int pf_mask = S->pf_mask_idx;
+  const uint32_t m0b = n_masks > 0 ? S->masks[0] : 0, m1b = n_masks > 1 ? S->masks[1] : 0;
+  const uint32_t m2b = n_masks > 2 ? S->masks[2] : 0, m3b = n_masks > 3 ? S->masks[3] : 0;
 
   for (int item = blockIdx.x * kScanWaves + wid; item < S->n_items; item += gridDim.x * kScanWaves) {
     const int p0 = S->item_piece[item], p1 = S->item_piece[item + 1];
     for (int p = p0; p < p1; ++p) {
       const int64_t rb = S->piece_begin[p], re = S->piece_begin[p + 1];
-      // outer multiplicity of direct tables
-      int64_t mu_out = 1;
+      int64_t mu_out = 1;   // outer multiplicity of the direct tables
       for (int v = 0; v < S->mu_out_views; ++v) {
         const DView& V = S->outer_views[v];
         int64_t vr = 0;
@@ -388,59 +427,50 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(const DScan* __restric
 #pragma unroll
       for (int m = 0; m < kMaxMasks; ++m) cacc[m] = 0;
 
-      for (int64_t r = rb + lane; r < re; r += 64) {
-        // inner views
-        int64_t vrow[kMaxViews];
-        int64_t vcnt[kMaxViews];
+      for (int64_t r0 = rb; r0 < re; r0 += 64) {
+        const int64_t r = r0 + lane;
+        const bool valid = r < re;
+        const int64_t rr = valid ? r : rb;   // in-bounds row for invalid lanes
+        int64_t mu0 = valid, mu1 = valid, mu2 = valid, mu3 = valid;   // multiplicity per mask
+        T av[NA + 1];
+        av[0] = (T)1;
+        int32_t cv[kMaxCodes];
 #pragma unroll
-        for (int v = 0; v < kMaxViews; ++v) {
+        for (int a = 0; a < NA; ++a) {
+          av[a + 1] = (T)0;
+          if (S->atoms[a].kind == SRC_COL) av[a + 1] = ld_val<T>(S->cols[S->atoms[a].src], rr);
+        }
+#pragma unroll
+        for (int c = 0; c < kMaxCodes; ++c) {
+          cv[c] = 0;
+          if (c < n_codes && S->codes[c].kind == SRC_COL) cv[c] = (int32_t)ld_int(S->cols[S->codes[c].src], rr);
+        }
+        // inner views: looked up once per tuple, consumed in place
+#pragma unroll
+        for (int v = 0; v < kMaxInnerViews; ++v) {
           if (v < n_views) {
             const DView& V = S->views[v];
             int64_t vr = 0;
-            for (int k = 0; k < V.nkey; ++k) vr += ld_int(S->cols[V.key_src[k]], r) * V.key_stride[k];
-            vrow[v] = vr;
-            vcnt[v] = V.cnt[vr];
-          } else {
-            vrow[v] = 0;
-            vcnt[v] = 1;
+            for (int k = 0; k < V.nkey; ++k) vr += ld_int(S->cols[V.key_src[k]], rr) * V.key_stride[k];
+            const int64_t vc = valid ? V.cnt[vr] : 0;
+            const uint32_t bit = 1u << v;
+            if (m0b & bit) mu0 *= vc;
+            if (m1b & bit) mu1 *= vc;
+            if (m2b & bit) mu2 *= vc;
+            if (m3b & bit) mu3 *= vc;
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+              if (S->atoms[a].kind == SRC_VIEW && S->atoms[a].src == v)
+                av[a + 1] = view_val<T>(V, vr, S->atoms[a].slot);
+#pragma unroll
+            for (int c = 0; c < kMaxCodes; ++c)
+              if (c < n_codes && S->codes[c].kind == SRC_VIEW && S->codes[c].src == v)
+                cv[c] = V.codes[vr * V.n_codes + S->codes[c].slot];
           }
         }
-        int64_t mu[kMaxMasks];
-#pragma unroll
-        for (int m = 0; m < kMaxMasks; ++m) {
-          int64_t x = 1;
-          if (m < n_masks) {
-            uint32_t bits = S->masks[m];
-#pragma unroll
-            for (int v = 0; v < kMaxViews; ++v)
-              if (bits & (1u << v)) x *= vcnt[v];
-          }
-          mu[m] = x;
-        }
-        // inner factors
-        T av[NA + 1];
-        av[0] = (T)1;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          const DAtom& A = S->atoms[a];
-          T x;
-          if (A.kind == SRC_COL) {
-            x = ld_val<T>(S->cols[A.src], r);
-          } else {
-            int64_t vr = 0;
-#pragma unroll
-            for (int v = 0; v < kMaxViews; ++v)
-              if (A.src == v) vr = vrow[v];
-            x = view_val<T>(S->views[A.src], vr, A.slot);
-          }
-          av[a + 1] = x;
-        }
+        // float partial sums over the extended-atom triangle
         if (S->pf_uniform) {
-          int64_t muf = 1;
-#pragma unroll
-          for (int m = 0; m < kMaxMasks; ++m)
-            if (m == pf_mask) muf = mu[m];
-          const T muT = (T)muf;
+          const T muT = (T)sel4(pf_mask, mu0, mu1, mu2, mu3);
 #pragma unroll
           for (int i = 0; i <= NA; ++i) {
             const T xi = muT * av[i];
@@ -456,103 +486,149 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(const DScan* __restric
 #pragma unroll
             for (int j = i; j <= NA; ++j) {
               const int t = tri_index(i, j, NA);
-              if (t > 0 && ((need >> t) & 1ull)) {
-                int mi = S->pf_mask[t];
-                int64_t x = 1;
-#pragma unroll
-                for (int q = 0; q < kMaxMasks; ++q)
-                  if (q == mi) x = mu[q];
-                kadd(acc[t], cmp[t], (T)x * av[i] * av[j]);
-              }
+              if (t > 0 && ((need >> t) & 1ull))
+                kadd(acc[t], cmp[t], (T)sel4((int)S->pf_mask[t], mu0, mu1, mu2, mu3) * av[i] * av[j]);
             }
           }
         }
 #pragma unroll
         for (int m = 0; m < kMaxMasks; ++m)
-          if (m < S->n_pi) {
-            int mi = S->pi_mask_idx[m];
-            int64_t x = 1;
+          if (m < S->n_pi) cacc[m] += sel4(S->pi_mask_idx[m], mu0, mu1, mu2, mu3);
+        if (!runs) continue;
+        // codes to the lane slots
 #pragma unroll
-            for (int q = 0; q < kMaxMasks; ++q)
-              if (q == mi) x = mu[q];
-            cacc[m] += x;
-          }
-        // codes
-        int32_t cv[kMaxCodes];
+        for (int c = 0; c < kMaxCodes; ++c)
+          if (c < n_codes) slot_c[c * 64 + lane] = cv[c];
+        if (direct) {
+          // each tuple updates the histograms / tables itself
+          if (valid) {
+            for (int h = 0; h < S->n_hists; ++h) {
+              const DHist& H = S->hists[h];
+              const DWeight& W = S->weights[H.wi];
+              const int32_t code = slot_c[H.code * 64 + lane];
+              int64_t m = sel4(W.mask_idx, mu0, mu1, mu2, mu3);
+              if (!m) continue;
+              if (!H.is_float) {
+                atomicAdd(&hist_i[H.offset + code], (int32_t)m);
+              } else {
+                T x = (T)m;
 #pragma unroll
-        for (int c = 0; c < kMaxCodes; ++c) {
-          cv[c] = 0;
-          if (c < S->n_codes) {
-            const DAtom& C = S->codes[c];
-            if (C.kind == SRC_COL) {
-              cv[c] = (int32_t)ld_int(S->cols[C.src], r);
-            } else {
-              int64_t vr = 0;
-#pragma unroll
-              for (int v = 0; v < kMaxViews; ++v)
-                if (C.src == v) vr = vrow[v];
-              const DView& V = S->views[C.src];
-              cv[c] = V.codes[vr * V.n_codes + C.slot];
-            }
-          }
-        }
-        // per-piece histograms
-        for (int h = 0; h < S->n_hists; ++h) {
-          const DHist& H = S->hists[h];
-          int32_t code = 0;
-#pragma unroll
-          for (int c = 0; c < kMaxCodes; ++c)
-            if (c == H.code) code = cv[c];
-          int64_t m = 1;
-#pragma unroll
-          for (int q = 0; q < kMaxMasks; ++q)
-            if (q == H.mask_idx) m = mu[q];
-          if (m == 0) continue;
-          if (!H.is_float) {
-            atomicAdd(&hist_i[H.offset + code], (int32_t)m);
-          } else {
-            T w = (T)m;
-#pragma unroll
-            for (int a = 0; a <= NA; ++a) {
-              if (a == H.ai + 1) w *= av[a];
-              if (a == H.aj + 1) w *= av[a];
-            }
-            atomicAdd(&hist_f[H.offset + code], w);
-          }
-        }
-        // direct group-by tables
-        for (int tb = 0; tb < S->n_tables; ++tb) {
-          const DTable& TB = S->tables[tb];
-          int64_t row = 0;
-          for (int k = 0; k < TB.ncode; ++k) {
-            int32_t code = 0;
-#pragma unroll
-            for (int c = 0; c < kMaxCodes; ++c)
-              if (c == TB.code[k]) code = cv[c];
-            row += (int64_t)code * TB.stride[k];
-          }
-          for (int q = 0; q < TB.n_tcomps; ++q) {
-            int64_t m = mu_out;
-#pragma unroll
-            for (int z = 0; z < kMaxMasks; ++z)
-              if (z == TB.tmask[q]) m *= mu[z];
-            if (m == 0) continue;
-            if (TB.tcomp[q] < 0) {
-              if (TB.lds) atomicAdd(&tab_i[TB.lds_off + row], (int32_t)m);
-              else atomic_add_i64(&TB.cnt[row], m);
-            } else {
-              T w = (T)m;
-#pragma unroll
-              for (int a = 0; a <= NA; ++a) {
-                if (a == TB.tai[q] + 1) w *= av[a];
-                if (a == TB.taj[q] + 1) w *= av[a];
+                for (int a = 1; a <= NA; ++a) {
+                  if (a == W.ai + 1) x *= av[a];
+                  if (a == W.aj + 1) x *= av[a];
+                }
+                atomicAdd(&hist_f[H.offset + code], x);
               }
-              int64_t di = row * TB.n_vals + TB.tcomp[q];
-              if (TB.vals_f64) atomic_add_f64(&((double*)TB.vals)[di], (double)w);
-              else atomicAdd(&((float*)TB.vals)[di], (float)w);
+            }
+            for (int tb = 0; tb < S->n_tables; ++tb) {
+              const DTable& TB = S->tables[tb];
+              int64_t row = 0;
+              for (int k = 0; k < TB.ncode; ++k) row += (int64_t)slot_c[TB.code[k] * 64 + lane] * TB.stride[k];
+              for (int q = 0; q < TB.n_tcomps; ++q) {
+                const DWeight& W = S->weights[TB.twi[q]];
+                int64_t m = mu_out * sel4(W.mask_idx, mu0, mu1, mu2, mu3);
+                if (!m) continue;
+                if (TB.tcomp[q] < 0) {
+                  if (TB.lds) atomicAdd(&tab_i[TB.lds_off + row], (int32_t)m);
+                  else atomic_add_i64(&TB.cnt[row], m);
+                } else {
+                  T x = (T)m;
+#pragma unroll
+                  for (int a = 1; a <= NA; ++a) {
+                    if (a == W.ai + 1) x *= av[a];
+                    if (a == W.aj + 1) x *= av[a];
+                  }
+                  int64_t di = row * TB.n_vals + TB.tcomp[q];
+                  if (TB.vals_f64) atomic_add_f64(&((double*)TB.vals)[di], (double)x);
+                  else atomicAdd(&((float*)TB.vals)[di], (float)x);
+                }
+              }
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+          continue;
+        }
+        // runs of equal keyed codes across neighbouring lanes
+        bool head = (lane == 0) || !valid;
+#pragma unroll
+        for (int c = 0; c < kMaxCodes; ++c)
+          if (c < n_codes && ((S->run_codes >> c) & 1u)) {
+            int32_t up = __shfl_up(cv[c], 1, 64);
+            head |= (lane > 0) && up != cv[c];
+          }
+        int start = head ? lane : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          int s2 = __shfl_up(start, d, 64);
+          if (lane >= d) start = max(start, s2);
+        }
+        const bool next_head = __shfl_down((int)head, 1, 64) != 0;
+        const bool tail = valid && (lane == 63 || next_head);
+        // per-run totals of every weight (segmented inclusive scan) to the lane slots
+#pragma unroll
+        for (int w = 0; w < kMaxWeights; ++w) {
+          if (w < n_w) {
+            const DWeight& W = S->weights[w];
+            const int64_t m = sel4(W.mask_idx, mu0, mu1, mu2, mu3);
+            if (!W.is_float) {
+              int32_t x = (int32_t)m;
+#pragma unroll
+              for (int d = 1; d < 64; d <<= 1) {
+                int32_t x2 = __shfl_up(x, d, 64);
+                if (lane - d >= start) x += x2;
+              }
+              ((int32_t*)slot_w)[(w * 64 + lane) * 2] = x;
+            } else {
+              T x = (T)m;
+#pragma unroll
+              for (int a = 1; a <= NA; ++a) {
+                if (a == W.ai + 1) x *= av[a];
+                if (a == W.aj + 1) x *= av[a];
+              }
+#pragma unroll
+              for (int d = 1; d < 64; d <<= 1) {
+                T x2 = __shfl_up(x, d, 64);
+                if (lane - d >= start) x += x2;
+              }
+              slot_w[w * 64 + lane] = (double)x;
             }
           }
         }
+        __builtin_amdgcn_wave_barrier();
+        if (tail) {
+          for (int h = 0; h < S->n_hists; ++h) {
+            const DHist& H = S->hists[h];
+            const int32_t code = slot_c[H.code * 64 + lane];
+            if (!H.is_float) {
+              int32_t x = ((const int32_t*)slot_w)[(H.wi * 64 + lane) * 2];
+              if (x) atomicAdd(&hist_i[H.offset + code], x);
+            } else {
+              T x = (T)slot_w[H.wi * 64 + lane];
+              if (x != (T)0) atomicAdd(&hist_f[H.offset + code], x);
+            }
+          }
+          for (int tb = 0; tb < S->n_tables; ++tb) {
+            const DTable& TB = S->tables[tb];
+            int64_t row = 0;
+            for (int k = 0; k < TB.ncode; ++k) row += (int64_t)slot_c[TB.code[k] * 64 + lane] * TB.stride[k];
+            for (int q = 0; q < TB.n_tcomps; ++q) {
+              const int w = TB.twi[q];
+              if (TB.tcomp[q] < 0) {
+                int64_t x = mu_out * (int64_t)((const int32_t*)slot_w)[(w * 64 + lane) * 2];
+                if (!x) continue;
+                if (TB.lds) atomicAdd(&tab_i[TB.lds_off + row], (int32_t)x);
+                else atomic_add_i64(&TB.cnt[row], x);
+              } else {
+                T x = (T)mu_out * (T)slot_w[w * 64 + lane];
+                if (x == (T)0) continue;
+                int64_t di = row * TB.n_vals + TB.tcomp[q];
+                if (TB.vals_f64) atomic_add_f64(&((double*)TB.vals)[di], (double)x);
+                else atomicAdd(&((float*)TB.vals)[di], (float)x);
+              }
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
       }
       // close the piece: reduce the lanes' partial sums and store the psi row
       T* prow = (T*)S->psi_f + (int64_t)p * S->psi_f_stride;
@@ -560,15 +636,15 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(const DScan* __restric
 #pragma unroll
       for (int t = 1; t < NT; ++t) {
         if ((need >> t) & 1ull) {
-          T s = wave_sum_comp(acc[t], cmp[t]);
-          if (lane == 0) prow[S->pf_slot[t]] = s;
+          T sm = wave_sum_comp(acc[t], cmp[t]);
+          if (lane == 0) prow[S->pf_slot[t]] = sm;
         }
       }
 #pragma unroll
       for (int m = 0; m < kMaxMasks; ++m)
         if (m < S->n_pi) {
-          int64_t s = wave_sum_i64(cacc[m]);
-          if (lane == 0) irow[m] = (int32_t)s;
+          int64_t sm = wave_sum_i64(cacc[m]);
+          if (lane == 0) irow[m] = (int32_t)sm;
         }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -577,20 +653,306 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(const DScan* __restric
       __builtin_amdgcn_wave_barrier();
     }
   }
-  // flush LDS-privatized tables as block partials
+  // flush LDS-privatized count tables as block partials
   __syncthreads();
   for (int i = threadIdx.x; i < S->lds_tab_i; i += blockDim.x)
     S->part_i[(int64_t)blockIdx.x * S->lds_tab_i + i] = tab_i[i];
 }
 
-int scan_lds_bytes(const DScan& S, bool f64) {
-  int hist_bytes = ((S.hist_i_bins * 4 + 7) & ~7) + S.hist_f_bins * (f64 ? 8 : 4);
-  int hist_stride = (hist_bytes + 15) & ~15;
-  return (int)(((S.lds_tab_i * 4 + 15) & ~15) + kScanWaves * hist_stride);
-}
-
 static void allow_lds(const void* fn, int lds) {
   if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+// ---------------------------------------------------------------------------
+// lean scan: inner views read through per-key images
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ImgLayout {
+  static constexpr int s = sizeof(T) / 4;   // dwords per factor slot
+};
+template <typename T, int NA>
+struct ImgShape {
+  static constexpr int code_off = NA * ImgLayout<T>::s;
+  static constexpr int cnt_off = code_off + 4;
+  static constexpr int width = ((cnt_off + 1) + 3) & ~3;
+};
+
+int image_width_dw(int na, bool f64) {
+  int code_off = na * (f64 ? 2 : 1);
+  return ((code_off + 5) + 3) & ~3;
+}
+int image_code_off(int na, bool f64) { return na * (f64 ? 2 : 1); }
+
+template <typename T>
+__global__ void k_build_image(const DImageBuild* __restrict__ B) {
+  const DView& V = B->view;
+  const int W = B->width_dw;
+  constexpr int s = sizeof(T) / 4;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < B->n_keys;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t* row = (uint32_t*)B->img + k * W;
+    const int64_t cnt = V.cnt[k];
+    for (int i = 0; i < W; ++i) row[i] = 0u;
+    for (int a = 0; a < B->n_atoms; ++a) {
+      int slot = B->atom_slot[a];
+      if (slot < 0 || cnt == 0) continue;
+      T x = view_val<T>(V, k, slot);
+      if (s == 1) {
+        row[a] = __float_as_uint((float)x);
+      } else {
+        double d = (double)x;
+        uint64_t u = (uint64_t)__double_as_longlong(d);
+        row[2 * a] = (uint32_t)u;
+        row[2 * a + 1] = (uint32_t)(u >> 32);
+      }
+    }
+    for (int c = 0; c < B->n_codes; ++c) {
+      int slot = B->code_slot[c];
+      if (slot >= 0 && cnt != 0) row[B->code_off + c] = (uint32_t)V.codes[k * V.n_codes + slot];
+    }
+    row[B->cnt_off] = (uint32_t)cnt;
+  }
+}
+void launch_build_image(const DImageBuild* d, int64_t n_keys, bool f64, hipStream_t s) {
+  if (n_keys <= 0) return;
+  int grid = (int)std::min<int64_t>((n_keys + 255) / 256, 8192);
+  if (f64) hipLaunchKernelGGL(k_build_image<double>, dim3(grid), dim3(256), 0, s, d);
+  else hipLaunchKernelGGL(k_build_image<float>, dim3(grid), dim3(256), 0, s, d);
+}
+
+template <typename T>
+__device__ __forceinline__ T img_val(const uint32_t* dw, int a) {
+  if constexpr (sizeof(T) == 4) return __uint_as_float(dw[a]);
+  else return __longlong_as_double((long long)(((uint64_t)dw[2 * a + 1] << 32) | dw[2 * a]));
+}
+
+// Per tuple: column loads, one vector load per inner view image, factor
+// products into per-lane partial sums, direct LDS atomics for histograms and
+// direct tables.  Everything the row loop needs is hoisted into registers
+// before it; private arrays are indexed at compile time only.
+template <typename T, int NA>
+__global__ __launch_bounds__(kScanWaves * 64) void k_scan_fast(const DScan* __restrict__ S) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using Shape = ImgShape<T, NA>;
+  constexpr int W = Shape::width;
+  constexpr int NT = (NA + 1) * (NA + 2) / 2;
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  int32_t* tab_i = (int32_t*)smem;
+  unsigned char* wbase = (unsigned char*)smem + (((size_t)S->lds_tab_i * 4 + 15) & ~(size_t)15);
+  const int hist_i_bytes = (S->hist_i_bins * 4 + 7) & ~7;
+  const int hist_bytes = hist_i_bytes + S->hist_f_bins * (int)sizeof(T);
+  const int wave_stride = ((hist_bytes + 15) & ~15) + (NA + 1 + 4) * 64 * (int)sizeof(T);
+  int32_t* hist_i = (int32_t*)(wbase + wid * wave_stride);
+  T* hist_f = (T*)((unsigned char*)hist_i + hist_i_bytes);
+  // per-lane slots: factors 0..NA (0 = 1) then codes, read back by histogram index
+  T* slot_a = (T*)(wbase + wid * wave_stride + ((hist_bytes + 15) & ~15));
+  int32_t* slot_c = (int32_t*)(slot_a + (NA + 1) * 64);
+
+  for (int i = threadIdx.x; i < S->lds_tab_i; i += blockDim.x) tab_i[i] = 0;
+  __syncthreads();
+
+  const int n_hist = S->F.n_hist;
+  const int n_tab = S->F.n_tab;
+  const uint64_t need = S->pf_need;
+  const bool pf_uniform = S->pf_uniform != 0;
+  const int pf_mask = S->pf_mask_idx;
+  const int n_masks = S->n_masks;
+  const uint32_t m0b = n_masks > 0 ? S->masks[0] : 0, m1b = n_masks > 1 ? S->masks[1] : 0;
+  const uint32_t m2b = n_masks > 2 ? S->masks[2] : 0, m3b = n_masks > 3 ? S->masks[3] : 0;
+  const int n_pi = S->n_pi;
+  const int pim0 = S->pi_mask_idx[0], pim1 = S->pi_mask_idx[1], pim2 = S->pi_mask_idx[2], pim3 = S->pi_mask_idx[3];
+  const int32_t* pb = (const int32_t*)nullptr;
+  (void)pb;
+
+  for (int item = blockIdx.x * kScanWaves + wid; item < S->n_items; item += gridDim.x * kScanWaves) {
+    const int p0 = S->item_piece[item], p1 = S->item_piece[item + 1];
+    for (int p = p0; p < p1; ++p) {
+      const int rb = (int)S->piece_begin[p], re = (int)S->piece_begin[p + 1];
+      int mu_out = 1;
+      for (int v = 0; v < S->mu_out_views; ++v) {
+        const DView& V = S->outer_views[v];
+        int64_t vr = 0;
+        for (int k = 0; k < V.nkey; ++k)
+          vr += (int64_t)S->piece_key[(int64_t)V.key_src[k] * S->n_pieces + p] * V.key_stride[k];
+        mu_out *= (int)V.cnt[vr];
+      }
+      for (int i = lane; i < S->hist_i_bins; i += 64) hist_i[i] = 0;
+      for (int i = lane; i < S->hist_f_bins; i += 64) hist_f[i] = (T)0;
+      __builtin_amdgcn_wave_barrier();
+      T acc[NT];
+      T cmp[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) { acc[t] = (T)0; cmp[t] = (T)0; }
+      int cacc0 = 0, cacc1 = 0, cacc2 = 0, cacc3 = 0;
+
+      for (int r0 = rb; r0 < re; r0 += 64) {
+        const int r = r0 + lane;
+        const bool valid = r < re;
+        const int rr = valid ? r : rb;
+        T av[NA + 1];
+        av[0] = (T)1;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          const T* fc = (const T*)S->F.fcol[a];
+          av[a + 1] = fc ? fc[rr] : (T)0;
+        }
+        int c0 = S->F.ccol[0] ? S->F.ccol[0][rr] : 0;
+        int c1 = S->F.ccol[1] ? S->F.ccol[1][rr] : 0;
+        int c2 = S->F.ccol[2] ? S->F.ccol[2][rr] : 0;
+        int c3 = S->F.ccol[3] ? S->F.ccol[3][rr] : 0;
+        int mu0 = valid, mu1 = valid, mu2 = valid, mu3 = valid;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const uint4* img = (const uint4*)S->F.img[v];
+          const int32_t* kc = S->F.kcol[v];
+          if (img) {
+            const int key = kc[rr];
+            const uint4* q = img + (int64_t)key * (W / 4);
+            uint32_t dw[W];
+#pragma unroll
+            for (int j = 0; j < W / 4; ++j) {
+              uint4 x = q[j];
+              dw[4 * j] = x.x;
+              dw[4 * j + 1] = x.y;
+              dw[4 * j + 2] = x.z;
+              dw[4 * j + 3] = x.w;
+            }
+#pragma unroll
+            for (int a = 0; a < NA; ++a) av[a + 1] += img_val<T>(dw, a);
+            c0 += (int)dw[Shape::code_off];
+            c1 += (int)dw[Shape::code_off + 1];
+            c2 += (int)dw[Shape::code_off + 2];
+            c3 += (int)dw[Shape::code_off + 3];
+            const int vc = valid ? (int)dw[Shape::cnt_off] : 0;
+            const uint32_t bit = 1u << v;
+            if (m0b & bit) mu0 *= vc;
+            if (m1b & bit) mu1 *= vc;
+            if (m2b & bit) mu2 *= vc;
+            if (m3b & bit) mu3 *= vc;
+          }
+        }
+        if (pf_uniform) {
+          const T muT = (T)sel4(pf_mask, mu0, mu1, mu2, mu3);
+#pragma unroll
+          for (int i = 0; i <= NA; ++i) {
+            const T xi = muT * av[i];
+#pragma unroll
+            for (int j = i; j <= NA; ++j) {
+              const int t = tri_index(i, j, NA);
+              if (t > 0 && ((need >> t) & 1ull)) kadd(acc[t], cmp[t], xi * av[j]);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i <= NA; ++i) {
+#pragma unroll
+            for (int j = i; j <= NA; ++j) {
+              const int t = tri_index(i, j, NA);
+              if (t > 0 && ((need >> t) & 1ull))
+                kadd(acc[t], cmp[t], (T)sel4((int)S->pf_mask[t], mu0, mu1, mu2, mu3) * av[i] * av[j]);
+            }
+          }
+        }
+        if (n_pi > 0) cacc0 += sel4(pim0, mu0, mu1, mu2, mu3);
+        if (n_pi > 1) cacc1 += sel4(pim1, mu0, mu1, mu2, mu3);
+        if (n_pi > 2) cacc2 += sel4(pim2, mu0, mu1, mu2, mu3);
+        if (n_pi > 3) cacc3 += sel4(pim3, mu0, mu1, mu2, mu3);
+        if (n_hist > 0) {
+#pragma unroll
+          for (int a = 0; a <= NA; ++a) slot_a[a * 64 + lane] = av[a];
+          slot_c[lane] = c0;
+          slot_c[64 + lane] = c1;
+          slot_c[128 + lane] = c2;
+          slot_c[192 + lane] = c3;
+          __builtin_amdgcn_wave_barrier();
+          for (int h = 0; h < n_hist; ++h) {
+            const uint32_t w = S->F.hword[h];
+            const int code = slot_c[(int)(w & 3u) * 64 + lane];
+            const int m = sel4((int)((w >> 2) & 3u), mu0, mu1, mu2, mu3);
+            const int off = (int)(w >> 13);
+            if (!m) continue;
+            if ((w >> 4) & 1u) {
+              const int ai = (int)((w >> 5) & 15u), aj = (int)((w >> 9) & 15u);
+              const T x = (T)m * slot_a[ai * 64 + lane] * slot_a[aj * 64 + lane];
+              atomicAdd(&hist_f[off + code], x);
+            } else {
+              atomicAdd(&hist_i[off + code], m);
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int tb = 0; tb < kFastTables; ++tb) {
+          if (tb < n_tab) {
+            int row = 0;
+            for (int k = 0; k < S->F.tab_ncode[tb]; ++k)
+              row += sel4(S->F.tab_code[tb][k], c0, c1, c2, c3) * S->F.tab_stride[tb][k];
+            const int m = mu_out * sel4(S->F.tab_mask[tb], mu0, mu1, mu2, mu3);
+            if (m) {
+              if (S->F.tab_lds[tb]) atomicAdd(&tab_i[S->F.tab_off[tb] + row], m);
+              else atomic_add_i64(&S->F.tab_cnt[tb][row], (int64_t)m);
+            }
+          }
+        }
+      }
+      // close the piece
+      T* prow = (T*)S->psi_f + (int64_t)p * S->psi_f_stride;
+      int32_t* irow = S->psi_i + (int64_t)p * S->psi_i_stride;
+#pragma unroll
+      for (int t = 1; t < NT; ++t) {
+        if ((need >> t) & 1ull) {
+          T sm = wave_sum_comp(acc[t], cmp[t]);
+          if (lane == 0) prow[S->pf_slot[t]] = sm;
+        }
+      }
+      if (n_pi > 0) { int sm = wave_sum((int)cacc0); if (lane == 0) irow[0] = sm; }
+      if (n_pi > 1) { int sm = wave_sum((int)cacc1); if (lane == 0) irow[1] = sm; }
+      if (n_pi > 2) { int sm = wave_sum((int)cacc2); if (lane == 0) irow[2] = sm; }
+      if (n_pi > 3) { int sm = wave_sum((int)cacc3); if (lane == 0) irow[3] = sm; }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      for (int i = lane; i < S->hist_i_bins; i += 64) irow[n_pi + i] = hist_i[i];
+      for (int i = lane; i < S->hist_f_bins; i += 64) prow[S->pf_n + i] = hist_f[i];
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < S->lds_tab_i; i += blockDim.x)
+    S->part_i[(int64_t)blockIdx.x * S->lds_tab_i + i] = tab_i[i];
+}
+
+int scan_fast_lds_bytes(const DScan& S, bool f64) {
+  int hist_bytes = ((S.hist_i_bins * 4 + 7) & ~7) + S.hist_f_bins * (f64 ? 8 : 4);
+  int wave_stride = ((hist_bytes + 15) & ~15) + (S.n_atoms + 1 + 4) * 64 * (f64 ? 8 : 4);
+  return (int)(((S.lds_tab_i * 4 + 15) & ~15) + kScanWaves * wave_stride);
+}
+
+int scan_lds_bytes(const DScan& S, bool f64) {
+  int hist_bytes = ((S.hist_i_bins * 4 + 7) & ~7) + S.hist_f_bins * (f64 ? 8 : 4);
+  int slot_bytes = (S.n_codes * 4 + (S.n_weights <= kMaxWeights ? S.n_weights * 8 : 0)) * 64;
+  int wave_stride = (((hist_bytes + 15) & ~15) + slot_bytes + 15) & ~15;
+  return (int)(((S.lds_tab_i * 4 + 15) & ~15) + kScanWaves * wave_stride);
+}
+
+
+template <typename T>
+static void launch_scan_fast_t(const DScan* d, int na, int grid, int lds, hipStream_t s) {
+  dim3 b(kScanWaves * 64);
+  switch (na) {
+#define CASE(N)                                                         \
+  case N:                                                               \
+    allow_lds((const void*)&k_scan_fast<T, N>, lds);                    \
+    hipLaunchKernelGGL((k_scan_fast<T, N>), dim3(grid), b, lds, s, d);  \
+    break;
+    CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: break;
+  }
+}
+void launch_scan_fast(const DScan* d, int na, bool f64, int grid, int lds, hipStream_t s) {
+  if (f64) launch_scan_fast_t<double>(d, na, grid, lds, s);
+  else launch_scan_fast_t<float>(d, na, grid, lds, s);
 }
 
 template <typename T>
@@ -827,21 +1189,20 @@ __global__ __launch_bounds__(kCThreads) void k_contract(const DContract* __restr
     __syncthreads();
   }
   // partials
+  // partials are cell-major: the merge reads each cell's block partials contiguously
+  const int64_t nb = gridDim.x;
   if (has_tile) {
-    double* part = C->part_f + (int64_t)blockIdx.x * NF * NG;
 #pragma unroll
     for (int i = 0; i < kTile; ++i)
 #pragma unroll
       for (int j = 0; j < kTile; ++j)
-        if (f0 + i < NF && g0 + j < NG) part[(int64_t)(f0 + i) * NG + g0 + j] = acc[i][j] + cmp[i][j];
+        if (f0 + i < NF && g0 + j < NG)
+          C->part_f[((int64_t)(f0 + i) * NG + g0 + j) * nb + blockIdx.x] = acc[i][j] + cmp[i][j];
   }
-  {
-    int64_t* part = C->part_i + (int64_t)blockIdx.x * NFI * NGI + icell0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      int cell = threadIdx.x + q * kCThreads;
-      if (cell < n_icells) part[cell] = iacc[q];
-    }
+  for (int q = 0; q < 8; ++q) {
+    int cell = threadIdx.x + q * kCThreads;
+    if (cell < n_icells) C->part_i[(int64_t)(icell0 + cell) * nb + blockIdx.x] = iacc[q];
   }
 }
 
@@ -871,32 +1232,45 @@ void launch_contract(const DContract* d, bool f64, int grid_x, int grid_y, int l
 // ---------------------------------------------------------------------------
 // deterministic merges
 // ---------------------------------------------------------------------------
-__global__ void k_merge_cells(const DCell* __restrict__ cells, int64_t n_cells, const double* __restrict__ part_f,
-                              const int64_t* __restrict__ part_i, int n_blocks, int NF, int NG, int NFI, int NGI) {
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n_cells; c += (int64_t)gridDim.x * blockDim.x) {
+// one wavefront per cell: lanes read the cell's block partials (contiguous),
+// fixed-order lane sums and a fixed butterfly -> deterministic
+__global__ __launch_bounds__(256) void k_merge_cells(const DCell* __restrict__ cells, int64_t n_cells,
+                                                     const double* __restrict__ part_f,
+                                                     const int64_t* __restrict__ part_i, int n_blocks, int NF,
+                                                     int NG, int NFI, int NGI) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t c = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); c < n_cells; c += waves) {
     const DCell& X = cells[c];
     if (X.is_int) {
+      const int64_t* src = part_i + ((int64_t)X.f * NGI + X.g) * n_blocks;
       int64_t s = 0;
-      for (int b = 0; b < n_blocks; ++b) s += part_i[(int64_t)b * NFI * NGI + (int64_t)X.f * NGI + X.g];
-      if (X.vals) {
-        if (X.vals_f64) ((double*)X.vals)[X.idx] += (double)s;
-        else ((float*)X.vals)[X.idx] += (float)s;
-      } else {
-        X.cnt[X.idx] += s;
+      for (int b = lane; b < n_blocks; b += 64) s += src[b];
+      s = wave_sum_i64(s);
+      if (lane == 0) {
+        if (X.vals) {
+          if (X.vals_f64) ((double*)X.vals)[X.idx] += (double)s;
+          else ((float*)X.vals)[X.idx] += (float)s;
+        } else {
+          X.cnt[X.idx] += s;
+        }
       }
     } else {
-      double s = 0, c = 0;
-      for (int b = 0; b < n_blocks; ++b) kadd(s, c, part_f[(int64_t)b * NF * NG + (int64_t)X.f * NG + X.g]);
-      s += c;
-      if (X.vals_f64) ((double*)X.vals)[X.idx] += s;
-      else ((float*)X.vals)[X.idx] += (float)s;
+      const double* src = part_f + ((int64_t)X.f * NG + X.g) * n_blocks;
+      double s = 0, cc = 0;
+      for (int b = lane; b < n_blocks; b += 64) kadd(s, cc, src[b]);
+      s = wave_sum_comp(s, cc);
+      if (lane == 0) {
+        if (X.vals_f64) ((double*)X.vals)[X.idx] += s;
+        else ((float*)X.vals)[X.idx] += (float)s;
+      }
     }
   }
 }
 void launch_merge_cells(const DCell* cells, int64_t n_cells, const double* part_f, const int64_t* part_i,
                         int n_blocks, int NF, int NG, int NFI, int NGI, hipStream_t s) {
   if (n_cells <= 0) return;
-  int grid = (int)std::min<int64_t>((n_cells + 255) / 256, 4096);
+  int grid = (int)std::min<int64_t>((n_cells + 3) / 4, 4096);
   hipLaunchKernelGGL(k_merge_cells, dim3(grid), dim3(256), 0, s, cells, n_cells, part_f, part_i, n_blocks, NF, NG,
                      NFI, NGI);
 }

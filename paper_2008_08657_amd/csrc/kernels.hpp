@@ -38,7 +38,7 @@ struct DTableReduce {
   int32_t n_blocks;
   int64_t stride;       // partial row stride (elements per block)
   int64_t off;          // offset of the table inside a partial row
-  const int64_t* part_i;
+  const int32_t* part_i;
   int64_t* dst_cnt;
 };
 
@@ -49,11 +49,18 @@ void launch_sort(uint64_t* keys, uint32_t* idx, uint64_t* keys_tmp, uint32_t* id
                  uint32_t* hist, hipStream_t s, bool* swapped);
 int sort_tile();
 void launch_gather(const void* src, const uint32_t* perm, void* dst, int64_t n, int elem_bytes, hipStream_t s);
+void launch_gather_convert(const void* src, int src_dtype, const uint32_t* perm, void* dst, int64_t n, bool to_f64,
+                           hipStream_t s);
 void launch_segment_starts(const uint64_t* keys, int64_t n, uint64_t div, unsigned long long* count,
                            int64_t* pos, uint64_t* pkey, int64_t cap, hipStream_t s);
 void launch_validate(const int32_t* col, int64_t n, int64_t dom, int32_t* err_flag, hipStream_t s);
 
 int scan_lds_bytes(const DScan& S, bool f64);
+int scan_fast_lds_bytes(const DScan& S, bool f64);
+void launch_scan_fast(const DScan* d, int na, bool f64, int grid, int lds, hipStream_t s);
+int image_width_dw(int na, bool f64);
+int image_code_off(int na, bool f64);
+void launch_build_image(const DImageBuild* d, int64_t n_keys, bool f64, hipStream_t s);
 void launch_scan(const DScan* d, int na, bool f64, int grid, int lds, hipStream_t s);
 int scan_waves_per_block();
 

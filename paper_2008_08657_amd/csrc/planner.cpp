@@ -731,7 +731,7 @@ void ProgBuilder::build() {
   // scanned with per-piece partial sums at the deepest level whose average
   // segment is still long
   int64_t min_seg = P.opts.min_segment > 0 ? P.opts.min_segment : 64;
-  const int64_t kRowPieceMax = P.opts.row_piece_max == 0 ? (int64_t)1 << 21 : P.opts.row_piece_max;
+  const int64_t kRowPieceMax = P.opts.row_piece_max == 0 ? (int64_t)1 << 16 : P.opts.row_piece_max;
   if (R.n_rows <= kRowPieceMax) {
     g.row_pieces = true;
     g.cut = L + 1;

@@ -57,11 +57,14 @@ struct NodeData {
   int n_items = 0;
   int cut = 0;
   uint32_t* perm = nullptr;        // sort permutation, kept until prepare ends
+  std::vector<void*> typed_col;    // sorted copies in the compute type (factor columns of lean scans)
+  std::vector<const void*> raw_src;  // caller's columns, valid during prepare only
 };
 
 struct Step {
   std::string name;
-  int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract, 5 merge
+  int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract, 5 merge, 6 image build
+  int fast = 0;
   void* dev = nullptr;
   int64_t n = 0;
   int na = 0;
@@ -317,6 +320,19 @@ static void prepare_node(Prep& S, int r, int cut, const std::vector<int>& need_c
   }
 }
 
+// sorted copy of a column converted to the compute type (needs the sort permutation)
+static void* typed_sorted_column(Prep& S, int r, int c, hipStream_t st) {
+  NodeData& N = S.nodes[r];
+  if (N.typed_col.empty()) N.typed_col.assign(S.P->rels[r].attrs.size(), nullptr);
+  if (N.typed_col[c]) return N.typed_col[c];
+  const RelDef& R = S.P->rels[r];
+  if (!N.perm) throw PlanError{LMFAO_EINVAL, "internal: typed column without permutation"};
+  void* p = dalloc(S, (size_t)std::max<int64_t>(R.n_rows, 1) * (S.f64 ? 8 : 4));
+  if (R.n_rows > 0) launch_gather_convert(N.raw_src[c], R.dtypes[c], N.perm, p, R.n_rows, S.f64, st);
+  N.typed_col[c] = p;
+  return p;
+}
+
 // ---------------------------------------------------------------------------
 // descriptors of one group program
 // ---------------------------------------------------------------------------
@@ -447,6 +463,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
       return (int)scols.size() - 1;
     };
     DScan d{};
+    if (n_in > kMaxInnerViews) throw PlanError{LMFAO_EUNSUPPORTED, "more than 4 views looked up per tuple"};
     d.n_views = n_in;
     for (size_t k = 0; k < g.views.size(); ++k) {
       if (scan_view[k] < 0) continue;
@@ -518,11 +535,26 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     if (g.psi_i.size() > (size_t)kMaxMasks) throw PlanError{LMFAO_EUNSUPPORTED, "too many count entries"};
     d.n_pi = (int)g.psi_i.size();
     for (int i = 0; i < d.n_pi; ++i) d.pi_mask_idx[i] = mask_idx(g.psi_i[i]);
+    // distinct per-tuple weights of histograms and direct tables
+    std::vector<DWeight> weights;
+    auto weight_idx = [&](int is_float, int ai, int aj, int mi) {
+      if (ai > aj) std::swap(ai, aj);
+      for (size_t i = 0; i < weights.size(); ++i)
+        if (weights[i].is_float == is_float && weights[i].ai == ai && weights[i].aj == aj &&
+            weights[i].mask_idx == mi)
+          return (int)i;
+      if ((int)weights.size() >= kMaxWeightTable) throw PlanError{LMFAO_EUNSUPPORTED, "too many distinct scan weights"};
+      weights.push_back(DWeight{is_float, ai, aj, mi});
+      return (int)weights.size() - 1;
+    };
+    uint32_t run_codes = 0;
     if (g.hists.size() > (size_t)kMaxHists) throw PlanError{LMFAO_EUNSUPPORTED, "too many histograms"};
     d.n_hists = (int)g.hists.size();
     for (int i = 0; i < d.n_hists; ++i) {
       const HistDef& h = g.hists[i];
-      d.hists[i] = DHist{h.code, h.dom, h.is_float, h.ai, h.aj, mask_idx(h.imask), h.offset, 0};
+      int wi = h.is_float ? weight_idx(1, h.ai, h.aj, mask_idx(h.imask)) : weight_idx(0, -1, -1, mask_idx(h.imask));
+      d.hists[i] = DHist{h.code, h.dom, h.is_float, wi, h.offset, 0};
+      run_codes |= 1u << h.code;
     }
     d.hist_i_bins = g.hist_i_bins;
     d.hist_f_bins = g.hist_f_bins;
@@ -547,11 +579,12 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
       if (po.tcomps.size() > (size_t)kMaxTableComps) throw PlanError{LMFAO_EUNSUPPORTED, "too many table components"};
       T.n_tcomps = (int)po.tcomps.size();
       for (int q = 0; q < T.n_tcomps; ++q) {
-        T.tcomp[q] = po.tcomps[q].comp;
-        T.tai[q] = po.tcomps[q].ai;
-        T.taj[q] = po.tcomps[q].aj;
-        T.tmask[q] = mask_idx(po.tcomps[q].imask);
+        const TableComp& tc = po.tcomps[q];
+        T.tcomp[q] = tc.comp;
+        T.twi[q] = tc.comp < 0 ? weight_idx(0, -1, -1, mask_idx(tc.imask))
+                               : weight_idx(1, tc.ai, tc.aj, mask_idx(tc.imask));
       }
+      for (int k = 0; k < T.ncode; ++k) run_codes |= 1u << T.code[k];
       const OutBuf& O = po.ref.kind == 0 ? S.qout[po.ref.id] : S.vout[po.ref.id];
       T.cnt = O.cnt;
       T.vals = O.vals;
@@ -572,6 +605,9 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     }
     d.n_tables = ntab;
     d.lds_tab_i = lds_used;
+    d.n_weights = (int)weights.size();
+    for (size_t i = 0; i < weights.size(); ++i) d.weights[i] = weights[i];
+    d.run_codes = run_codes;
     d.mu_out_views = 0;
     for (size_t k = 0; k < g.views.size(); ++k) {
       if (!((tab_omask >> k) & 1u)) continue;
@@ -607,15 +643,96 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     d.psi_f = psi_f;
     d.psi_i = psi_i;
     int waves = scan_waves_per_block();
-    int grid = (int)std::min<int64_t>((N.n_items + waves - 1) / waves, 2048);
+    int grid = (int)std::min<int64_t>((N.n_items + waves - 1) / waves, 512);
     grid = std::max(grid, 1);
-    d.part_i = (int64_t*)dalloc(S, (size_t)grid * std::max(1, lds_used) * 8);
+    d.part_i = (int32_t*)dalloc(S, (size_t)grid * std::max(1, lds_used) * 4);
     d.err_flag = S.err_flag;
-    int lds = scan_lds_bytes(d, f64);
+    // lean kernel: inner views through per-key images (single-attribute keys),
+    // at most 2 inner views, 4 codes, 16 histograms, 2 count-only direct tables
+    bool fast = n_in <= 2 && d.n_codes <= 4 && d.n_masks <= 4 && d.n_pi <= 4 && R.n_rows < ((int64_t)1 << 31) &&
+                d.n_hists <= kFastHists && d.n_tables <= kFastTables;
+    d.n_atoms = NA;
+    for (int v = 0; v < n_in; ++v)
+      fast = fast && d.views[v].n_keys < ((int64_t)1 << 31) && d.views[v].nkey == 1;
+    for (int i = 0; i < d.n_hists; ++i) fast = fast && d.hists[i].offset + d.hists[i].dom < (1 << 19);
+    for (int t = 0; t < d.n_tables; ++t) {
+      fast = fast && d.tables[t].n_tcomps == 1 && d.tables[t].tcomp[0] < 0 && d.tables[t].ncode <= 3 &&
+             d.tables[t].n_rows < ((int64_t)1 << 31);
+    }
+    d.fast = fast ? 1 : 0;
+    if (fast) {
+      DFast& F = d.F;
+      for (int a = 0; a < NA; ++a)
+        F.fcol[a] = atoms[a].kind == SRC_COL ? typed_sorted_column(S, r, scols[atoms[a].src], st) : nullptr;
+      for (int c = 0; c < 4; ++c)
+        F.ccol[c] = (c < d.n_codes && g.in_codes[c].kind == SRC_COL)
+                        ? (const int32_t*)N.sorted_col[scols[g.in_codes[c].src]] : (const int32_t*)nullptr;
+      F.n_hist = d.n_hists;
+      for (int i = 0; i < d.n_hists; ++i) {
+        const DHist& H = d.hists[i];
+        const DWeight& Wt = weights[H.wi];
+        // factor slots: 0 is the constant 1, so an absent factor multiplies by 1
+        uint32_t w = (uint32_t)H.code | ((uint32_t)Wt.mask_idx << 2) | ((uint32_t)(H.is_float ? 1 : 0) << 4);
+        if (H.is_float) w |= ((uint32_t)(Wt.ai + 1) << 5) | ((uint32_t)(Wt.aj + 1) << 9);
+        w |= (uint32_t)H.offset << 13;
+        F.hword[i] = w;
+      }
+      F.n_tab = d.n_tables;
+      for (int t = 0; t < d.n_tables; ++t) {
+        const DTable& TB = d.tables[t];
+        F.tab_ncode[t] = TB.ncode;
+        for (int k = 0; k < TB.ncode; ++k) {
+          F.tab_code[t][k] = TB.code[k];
+          F.tab_stride[t][k] = (int32_t)TB.stride[k];
+        }
+        F.tab_mask[t] = weights[TB.twi[0]].mask_idx;
+        F.tab_lds[t] = TB.lds;
+        F.tab_off[t] = TB.lds_off;
+        F.tab_cnt[t] = TB.cnt;
+      }
+      const int W = image_width_dw(NA, f64);
+      const int code_off = image_code_off(NA, f64);
+      for (size_t k = 0; k < g.views.size(); ++k) {
+        int v = scan_view[k];
+        if (v < 0) continue;
+        const DView& V = d.views[v];
+        DImageBuild ib{};
+        ib.view = V;
+        ib.n_keys = V.n_keys;
+        ib.width_dw = W;
+        ib.code_off = code_off;
+        ib.cnt_off = code_off + 4;
+        ib.t_f64 = f64 ? 1 : 0;
+        ib.n_atoms = NA;
+        for (int a = 0; a < NA; ++a)
+          ib.atom_slot[a] = (atoms[a].kind == SRC_VIEW && atoms[a].src == (int)k) ? atoms[a].slot : -1;
+        ib.n_codes = d.n_codes;
+        for (int c = 0; c < d.n_codes; ++c)
+          ib.code_slot[c] = (g.in_codes[c].kind == SRC_VIEW && g.in_codes[c].src == (int)k) ? g.in_codes[c].slot : -1;
+        ib.img = dalloc(S, (size_t)V.n_keys * W * 4);
+        d.imgs[v].img = ib.img;
+        d.imgs[v].width_dw = W;
+        d.imgs[v].code_off = code_off;
+        d.imgs[v].cnt_off = code_off + 4;
+        d.imgs[v].key_col = V.nkey == 1 ? V.key_src[0] : -1;
+        F.img[v] = ib.img;
+        F.kcol[v] = (const int32_t*)N.sorted_col[scols[V.key_src[0]]];
+        Step b;
+        b.name = gname + ":image";
+        b.kind = 6;
+        b.dev = upload(S, ib, st);
+        b.n = V.n_keys;
+        b.alg_read = (double)V.n_keys * (8 + V.n_vals * (V.vals_f64 ? 8 : 4) + V.n_codes * 4);
+        b.alg_write = (double)V.n_keys * W * 4;
+        S.steps.push_back(b);
+      }
+    }
+    int lds = fast ? scan_fast_lds_bytes(d, f64) : scan_lds_bytes(d, f64);
     if (lds > 160 * 1024) throw PlanError{LMFAO_EUNSUPPORTED, "scan needs more LDS than a CU has"};
     Step s;
     s.name = gname + ":scan";
     s.kind = 2;
+    s.fast = fast ? 1 : 0;
     s.dev = upload(S, d, st);
     s.na = NA;
     s.grid = grid;
@@ -627,10 +744,11 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     for (int i = 0; i < d.n_cols; ++i) s.alg_read += (double)R.n_rows * (d.cols[i].dtype == LMFAO_F64 ? 8 : 4);
     s.alg_read += (double)(N.n_pieces + 1) * 8 + (double)(N.n_items + 1) * 4;
     for (int v = 0; v < d.n_views; ++v)
-      s.alg_read += (double)d.views[v].n_keys * (8 + d.views[v].n_vals * (d.views[v].vals_f64 ? 8 : 4) +
-                                                  d.views[v].n_codes * 4);
+      s.alg_read += fast ? (double)d.views[v].n_keys * d.imgs[v].width_dw * 4
+                         : (double)d.views[v].n_keys * (8 + d.views[v].n_vals * (d.views[v].vals_f64 ? 8 : 4) +
+                                                        d.views[v].n_codes * 4);
     s.alg_write += (double)N.n_pieces * (psi_f_stride * (f64 ? 8 : 4) + psi_i_stride * 4);
-    s.alg_write += (double)grid * lds_used * 8;
+    s.alg_write += (double)grid * lds_used * 4;
     s.alg_flop = (double)R.n_rows * 2 * (double)std::max(1, d.pf_n);
     S.steps.push_back(s);
     for (auto& lt : lds_tables) {
@@ -744,8 +862,8 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
 
   c.feats = upload_vec(S, feats, st);
   c.cols = upload_vec(S, colsb, st);
-  int64_t ppb = std::max<int64_t>(256, (n_pieces + 511) / 512);
-  ppb = std::min<int64_t>(ppb, 4096);
+  // about one block row per CU; the FP64 accumulators make long chains safe
+  int64_t ppb = std::max<int64_t>(64, (n_pieces + 255) / 256);
   int grid_x = (int)std::max<int64_t>(1, (n_pieces + ppb - 1) / ppb);
   int tiles = contract_tiles(c.n_feat, c.n_col);
   int64_t icells = (int64_t)c.n_feat_int * c.n_col_int;
@@ -855,7 +973,10 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
 static void prepare_all(Prep& S, const void* const* const* cols, hipStream_t st) {
   Plan& P = *S.P;
   S.nodes.assign(P.rels.size(), NodeData{});
-  for (size_t r = 0; r < P.rels.size(); ++r) S.nodes[r].raw_col.assign(P.rels[r].attrs.size(), nullptr);
+  for (size_t r = 0; r < P.rels.size(); ++r) {
+    S.nodes[r].raw_col.assign(P.rels[r].attrs.size(), nullptr);
+    S.nodes[r].raw_src.assign(cols[r], cols[r] + P.rels[r].attrs.size());
+  }
   S.err_flag = (int32_t*)dalloc(S, 8);
   HIP_OK(hipMemsetAsync(S.err_flag, 0, 8, st));
   // validate integer columns against their domains
@@ -953,7 +1074,11 @@ static void enqueue_run(Prep& S, hipStream_t st) {
     switch (s.kind) {
       case 0: launch_fill(s.dev, s.bytes, st); break;
       case 1: launch_view_build((const DViewBuild*)s.dev, s.n, S.f64, st); break;
-      case 2: launch_scan((const DScan*)s.dev, s.na, S.f64, s.grid, s.lds, st); break;
+      case 2:
+        if (s.fast) launch_scan_fast((const DScan*)s.dev, s.na, S.f64, s.grid, s.lds, st);
+        else launch_scan((const DScan*)s.dev, s.na, S.f64, s.grid, s.lds, st);
+        break;
+      case 6: launch_build_image((const DImageBuild*)s.dev, s.n, S.f64, st); break;
       case 3: launch_table_reduce((const DTableReduce*)s.dev, s.n, st); break;
       case 4: launch_contract((const DContract*)s.dev, S.f64, s.grid, s.grid_y, s.lds, st); break;
       case 5:
@@ -1229,7 +1354,7 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     if (s.kind == 0) continue;
     if (!first) j += ",";
     first = false;
-    static const char* kinds[] = {"fill", "view_build", "scan", "table_reduce", "contract", "merge"};
+    static const char* kinds[] = {"fill", "view_build", "scan", "table_reduce", "contract", "merge", "image"};
     char tmp[512];
     snprintf(tmp, sizeof(tmp),
              "{\"name\":\"%s\",\"kind\":\"%s\",\"rows\":%lld,\"pieces\":%lld,\"alg_read_bytes\":%.0f,"
