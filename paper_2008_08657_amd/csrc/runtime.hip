@@ -33,7 +33,8 @@ struct HipError {
 
 static constexpr int64_t kPieceMax = 8192;    // rows of one piece at most
 static constexpr int64_t kPieceMaxF64 = 64;   // FP64 plans: short (uncompensated) histogram chains
-static constexpr int64_t kItemRows = 4096;    // rows one wavefront takes per work item
+static constexpr int64_t kItemRows = 4096;    // rows one wavefront takes per work item, at most
+static constexpr int64_t kTargetItems = 16384; // work items wanted per scan: ~4 per resident wavefront
 static constexpr int64_t kLdsTableMax = 12288;   // int32 count entries privatized in LDS
 
 struct OutBuf {
@@ -269,7 +270,11 @@ static void prepare_node(Prep& S, int r, int cut, const std::vector<int>& need_c
     (void)hipFree(idx2);
     (void)hipFree(hist);
     N.perm = idx;
-    // pieces: segments in row order, split at kPieceMax rows
+    // pieces: segments in row order, split so that the scan has about
+    // kTargetItems work items of whole 64-row chunks (small relations get
+    // short pieces instead of a handful of long ones)
+    const int64_t item_rows =
+        std::min<int64_t>(kItemRows, std::max<int64_t>(64, ((n + kTargetItems - 1) / kTargetItems + 63) / 64 * 64));
     std::vector<size_t> ord(hpos.size());
     std::iota(ord.begin(), ord.end(), 0);
     std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return hpos[a] < hpos[b]; });
@@ -285,7 +290,7 @@ static void prepare_node(Prep& S, int r, int cut, const std::vector<int>& need_c
         vals[l] = (int32_t)(key % d);
         key /= d;
       }
-      const int64_t pmax = S.f64 ? kPieceMaxF64 : kPieceMax;
+      const int64_t pmax = std::min<int64_t>(S.f64 ? kPieceMaxF64 : kPieceMax, item_rows);
       for (int64_t x = b; x < e; x += pmax) {
         pb.push_back(x);
         for (int l = 0; l < cut; ++l) pk[l].push_back(vals[l]);
@@ -297,7 +302,7 @@ static void prepare_node(Prep& S, int r, int cut, const std::vector<int>& need_c
     int64_t acc = 0;
     for (int64_t p = 0; p < N.n_pieces; ++p) {
       acc += pb[p + 1] - pb[p];
-      if (acc >= kItemRows) {
+      if (acc >= item_rows) {
         items.push_back((int32_t)(p + 1));
         acc = 0;
       }
