@@ -137,6 +137,14 @@ enum { LMFAO_FORM_FUSED = 0, LMFAO_FORM_PER_VIEW = 1 };
  * through primary-key joins (carried as a code by single-valued views), and
  * queries over the attributes of a single relation are rooted there. */
 enum { LMFAO_ROOT_GROUPBY = 0, LMFAO_ROOT_FACT = 1 };
+/* Kernel for the segment-level contraction sum over pieces of (outer
+ * features) x (inner partial sums).  MFMA: the features and columns of each
+ * piece are staged in FP64 and multiplied on the matrix cores
+ * (v_mfma_f64_16x16x4f64), split over K with a deterministic merge; integer
+ * cells are exact while they stay below 2^53 (LMFAO_EOVERFLOW from lmfao_run
+ * with sync otherwise).  VALU: one fused kernel with FP64 register tiles and
+ * compensated sums, integer cells in int64. */
+enum { LMFAO_CONTRACT_MFMA = 0, LMFAO_CONTRACT_VALU = 1 };
 
 typedef struct {
   int32_t precision;     /* LMFAO_PREC_*: arithmetic of the scans and views;
@@ -152,6 +160,7 @@ typedef struct {
   int64_t row_piece_max; /* relations with at most this many rows are
                             contracted row by row without a scan
                             (0 = default 2^16; -1 = always scan)             */
+  int32_t contraction;   /* LMFAO_CONTRACT_* (0 = matrix cores)              */
 } lmfao_options;
 
 typedef struct lmfao_plan_s* lmfao_plan_t;

@@ -71,7 +71,8 @@ class lmfao_batch(C.Structure):
 class lmfao_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("form", C.c_int32), ("root_policy", C.c_int32),
                 ("n_order", C.POINTER(C.c_int32)), ("order", C.POINTER(C.POINTER(C.c_char_p))),
-                ("min_segment", C.c_int32), ("row_piece_max", C.c_int64)]
+                ("min_segment", C.c_int32), ("row_piece_max", C.c_int64),
+                ("contraction", C.c_int32)]
 
 
 class LmfaoError(RuntimeError):
@@ -191,7 +192,7 @@ class Plan:
     """A plan handle (``lmfao_plan``)."""
 
     def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
-                 min_segment=0, row_piece_max=0):
+                 min_segment=0, row_piece_max=0, contraction="mfma"):
         self.lib = load_library()
         self.problem = problem
         keep = _Keep()
@@ -204,6 +205,9 @@ class Plan:
         opts.root_policy = ROOT_FACT if pol == "fact" else ROOT_GROUPBY
         opts.min_segment = int(min_segment)
         opts.row_piece_max = int(row_piece_max)
+        if contraction not in ("mfma", "valu"):
+            raise ValueError(f"contraction must be 'mfma' or 'valu', not {contraction!r}")
+        opts.contraction = 0 if contraction == "mfma" else 1
         if order:
             names = [r["name"] for r in problem["schema"]]
             n_order = [len(order.get(n, [])) for n in names]

@@ -342,7 +342,7 @@ struct DImageBuild {
   int32_t code_slot[kMaxCodes];   // view code slot per scan code (-1: not from this view)
 };
 
-constexpr int kFastHists = 16;
+constexpr int kFastHists = 32;
 constexpr int kFastTables = 2;
 
 // hoisted form of a lean scan (all loop-invariant, read once per kernel)
@@ -350,7 +350,8 @@ struct DFast {
   const void* fcol[kMaxAtoms];     // factor columns in the compute type (null: factor from an image)
   const int32_t* ccol[4];          // code columns (null: code from an image)
   const void* img[2];              // inner view images (null: no view)
-  const int32_t* kcol[2];          // key column of each image
+  const int32_t* kcol[2][2];       // key columns of each image (second: null for one-attribute keys)
+  int32_t kmul[2][2];              // dense key = sum of key column * kmul
   int32_t n_hist;
   uint32_t hword[kFastHists];      // code(2) | mask(2) | float(1) | ai+1(4) | aj+1(4) | offset(16)
   int32_t n_tab;
@@ -441,6 +442,14 @@ struct DContract {
   const int32_t* psi_i;
   int32_t psi_f_stride, psi_i_stride;
   int32_t row_pieces;
+  // staged operands of the matrix-core contraction (null: the VALU kernel
+  // contracts in place): F [n_pieces x ldf] and B [n_pieces x ldg], FP64,
+  // pad columns zero; integer features and columns are stored exactly and
+  // checked against 2^53 (err_flag code 3)
+  double* fmat;
+  double* bmat;
+  int32_t ldf, ldg;
+  int32_t* err_flag;
   // outputs: partial GEMM blocks
   double* part_f;                  // [n_blocks x n_feat x n_col] f64 (T accumulated, stored f64)
   int64_t* part_i;                 // [n_blocks x n_feat_int x n_col_int]
@@ -458,6 +467,17 @@ struct DContract {
   int64_t* const* so_cnt;
   void* const* so_vals;            // f64 (or view dtype)
   const int32_t* so_vals_f64;
+};
+
+// split-K product of the staged operands on the matrix cores:
+// part[b][f * ng + g] = sum over the pieces of block b of F[p][f] * B[p][g]
+struct DGemm {
+  const double* F;
+  const double* B;
+  int64_t n;                       // pieces (K)
+  int32_t ldf, ldg, nf, ng;
+  int64_t k_per_block;             // multiple of the LDS chunk
+  double* part;                    // [gridDim.x][nf * ng], block-major
 };
 
 // gemm cell merge: dst value = sum over blocks of part[(b, f, g)]

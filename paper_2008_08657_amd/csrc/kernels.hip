@@ -720,10 +720,50 @@ void launch_build_image(const DImageBuild* d, int64_t n_keys, bool f64, hipStrea
   else hipLaunchKernelGGL(k_build_image<float>, dim3(grid), dim3(256), 0, s, d);
 }
 
+// loads through global (address space 1) pointers: the descriptor holds
+// generic pointers, which would otherwise become flat loads
+template <typename T>
+__device__ __forceinline__ T gld(const T* p, int64_t i) {
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 gld4(const uint4* p, int64_t i) {
+  return ((const __attribute__((address_space(1))) u32x4*)p)[i];
+}
+
 template <typename T>
 __device__ __forceinline__ T img_val(const uint32_t* dw, int a) {
   if constexpr (sizeof(T) == 4) return __uint_as_float(dw[a]);
   else return __longlong_as_double((long long)(((uint64_t)dw[2 * a + 1] << 32) | dw[2 * a]));
+}
+
+// Per-row inputs of the lean scan that come from the sorted relation itself:
+// factor columns (absent: 0, the factor comes from an image), code columns
+// (absent: 0) and the dense key of each inner view image.
+template <typename T, int NA>
+struct RowCols {
+  T f[NA > 0 ? NA : 1];
+  int c[4];
+  int k[2];
+};
+template <typename T, int NA>
+__device__ __forceinline__ void load_row_cols(const DScan* __restrict__ S, int rr, RowCols<T, NA>& o) {
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    const T* fc = (const T*)S->F.fcol[a];
+    o.f[a] = fc ? gld(fc, rr) : (T)0;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) o.c[c] = S->F.ccol[c] ? gld(S->F.ccol[c], rr) : 0;
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    int key = 0;
+    if (S->F.img[v]) {
+      key = gld(S->F.kcol[v][0], rr) * S->F.kmul[v][0];
+      if (S->F.kcol[v][1]) key += gld(S->F.kcol[v][1], rr) * S->F.kmul[v][1];
+    }
+    o.k[v] = key;
+  }
 }
 
 // Per tuple: column loads, one vector load per inner view image, factor
@@ -755,7 +795,6 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan_fast(const DScan* __re
   const int n_hist = S->F.n_hist;
   const int n_tab = S->F.n_tab;
   const uint64_t need = S->pf_need;
-  const bool pf_uniform = S->pf_uniform != 0;
   const int pf_mask = S->pf_mask_idx;
   const int n_masks = S->n_masks;
   const uint32_t m0b = n_masks > 0 ? S->masks[0] : 0, m1b = n_masks > 1 ? S->masks[1] : 0;
@@ -780,43 +819,41 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan_fast(const DScan* __re
       for (int i = lane; i < S->hist_i_bins; i += 64) hist_i[i] = 0;
       for (int i = lane; i < S->hist_f_bins; i += 64) hist_f[i] = (T)0;
       __builtin_amdgcn_wave_barrier();
+      // per-lane sums: FP64 pieces hold at most 64 rows (one term per lane),
+      // FP32 pieces are reduced in FP64 afterwards, so no compensation here
       T acc[NT];
-      T cmp[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) { acc[t] = (T)0; cmp[t] = (T)0; }
+      for (int t = 0; t < NT; ++t) acc[t] = (T)0;
       int cacc0 = 0, cacc1 = 0, cacc2 = 0, cacc3 = 0;
 
+      // the next 64-row chunk's columns are loaded while the current one is
+      // combined with its view images (one chunk of prefetch per wavefront)
+      RowCols<T, NA> nx;
+      load_row_cols<T, NA>(S, rb + lane < re ? rb + lane : rb, nx);
       for (int r0 = rb; r0 < re; r0 += 64) {
         const int r = r0 + lane;
         const bool valid = r < re;
-        const int rr = valid ? r : rb;
+        const RowCols<T, NA> cu = nx;
+        if (r0 + 64 < re) load_row_cols<T, NA>(S, r + 64 < re ? r + 64 : rb, nx);
         T av[NA + 1];
         av[0] = (T)1;
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          const T* fc = (const T*)S->F.fcol[a];
-          av[a + 1] = fc ? fc[rr] : (T)0;
-        }
-        int c0 = S->F.ccol[0] ? S->F.ccol[0][rr] : 0;
-        int c1 = S->F.ccol[1] ? S->F.ccol[1][rr] : 0;
-        int c2 = S->F.ccol[2] ? S->F.ccol[2][rr] : 0;
-        int c3 = S->F.ccol[3] ? S->F.ccol[3][rr] : 0;
+        for (int a = 0; a < NA; ++a) av[a + 1] = cu.f[a];
+        int c0 = cu.c[0], c1 = cu.c[1], c2 = cu.c[2], c3 = cu.c[3];
         int mu0 = valid, mu1 = valid, mu2 = valid, mu3 = valid;
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           const uint4* img = (const uint4*)S->F.img[v];
-          const int32_t* kc = S->F.kcol[v];
           if (img) {
-            const int key = kc[rr];
-            const uint4* q = img + (int64_t)key * (W / 4);
+            const uint4* q = img + (int64_t)cu.k[v] * (W / 4);
             uint32_t dw[W];
 #pragma unroll
             for (int j = 0; j < W / 4; ++j) {
-              uint4 x = q[j];
-              dw[4 * j] = x.x;
-              dw[4 * j + 1] = x.y;
-              dw[4 * j + 2] = x.z;
-              dw[4 * j + 3] = x.w;
+              const u32x4 x = gld4(q, j);
+              dw[4 * j] = x[0];
+              dw[4 * j + 1] = x[1];
+              dw[4 * j + 2] = x[2];
+              dw[4 * j + 3] = x[3];
             }
 #pragma unroll
             for (int a = 0; a < NA; ++a) av[a + 1] += img_val<T>(dw, a);
@@ -832,7 +869,10 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan_fast(const DScan* __re
             if (m3b & bit) mu3 *= vc;
           }
         }
-        if (pf_uniform) {
+        {
+          // every monomial of degree <= 2 of the row's factors, without a
+          // branch per monomial: the needed ones are written when the piece
+          // closes (one multiplicity mask for all of them)
           const T muT = (T)sel4(pf_mask, mu0, mu1, mu2, mu3);
 #pragma unroll
           for (int i = 0; i <= NA; ++i) {
@@ -840,17 +880,7 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan_fast(const DScan* __re
 #pragma unroll
             for (int j = i; j <= NA; ++j) {
               const int t = tri_index(i, j, NA);
-              if (t > 0 && ((need >> t) & 1ull)) kadd(acc[t], cmp[t], xi * av[j]);
-            }
-          }
-        } else {
-#pragma unroll
-          for (int i = 0; i <= NA; ++i) {
-#pragma unroll
-            for (int j = i; j <= NA; ++j) {
-              const int t = tri_index(i, j, NA);
-              if (t > 0 && ((need >> t) & 1ull))
-                kadd(acc[t], cmp[t], (T)sel4((int)S->pf_mask[t], mu0, mu1, mu2, mu3) * av[i] * av[j]);
+              if (t > 0) acc[t] += xi * av[j];
             }
           }
         }
@@ -902,7 +932,7 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan_fast(const DScan* __re
 #pragma unroll
       for (int t = 1; t < NT; ++t) {
         if ((need >> t) & 1ull) {
-          T sm = wave_sum_comp(acc[t], cmp[t]);
+          T sm = wave_sum_comp(acc[t], (T)0);
           if (lane == 0) prow[S->pf_slot[t]] = sm;
         }
       }
@@ -1227,6 +1257,314 @@ void launch_contract(const DContract* d, bool f64, int grid_x, int grid_y, int l
     allow_lds((const void*)&k_contract<float>, lds);
     hipLaunchKernelGGL(k_contract<float>, dim3(grid_x, grid_y), dim3(kCThreads), lds, s, d);
   }
+}
+
+// ---------------------------------------------------------------------------
+// contraction on the matrix cores.  Stage 1 writes, per piece, the outer
+// feature row F[p] and the column row B[p] (both FP64; integer entries are
+// exact below 2^53).  Stage 2 is the segment-level product sum_p F[p]^T B[p]
+// as a split-K FP64 MFMA GEMM (v_mfma_f64_16x16x4f64) with block-major
+// partials, merged deterministically afterwards.
+// ---------------------------------------------------------------------------
+constexpr int kSPieces = 64;                       // pieces per staging round
+constexpr double kExactInt = 9007199254740992.0;   // 2^53
+
+__device__ __forceinline__ double feat_d(const DFeat& F, const int64_t* mu, const int32_t* codes,
+                                         const double* atoms, bool is_int) {
+  const int64_t m = feat_int(F, mu, codes);
+  double x = (double)m;
+  if (!is_int) {
+    if (F.a1 >= 0) x *= atoms[F.a1];
+    if (F.a2 >= 0) x *= atoms[F.a2];
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ double col_d(const DContract* C, const DColB& B, int64_t p, const int32_t* codes,
+                                        const double* atoms) {
+  if (B.kind == B_PSI_F) return (double)((const T*)C->psi_f)[p * C->psi_f_stride + B.entry];
+  const int64_t cnt = C->row_pieces ? 1 : C->psi_i[p * C->psi_i_stride + B.entry];
+  if (B.kind == B_PSI_I) return (double)cnt;
+  const DFeat& F = B.feat;
+  int64_t m = cnt;
+  if (F.c1 >= 0 && codes[F.c1] != F.v1) m = 0;
+  if (F.c2 >= 0 && codes[F.c2] != F.v2) m = 0;
+  double x = (double)m;
+  if (F.a1 >= 0) x *= atoms[F.a1];
+  if (F.a2 >= 0) x *= atoms[F.a2];
+  return x;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_contract_stage(const DContract* __restrict__ C) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int NF = C->n_feat, NG = C->n_col, NFI = C->n_feat_int;
+  const int NA = C->n_atoms, NC = C->n_codes, NM = C->n_masks, NV = C->n_views;
+  const int ldf = C->ldf, ldg = C->ldg;
+  int64_t* vrow_s = (int64_t*)smem;                       // [kSPieces][kMaxViews]
+  int64_t* vcnt_s = vrow_s + kSPieces * kMaxViews;        // [kSPieces][kMaxViews]
+  int64_t* mu_s = vcnt_s + kSPieces * kMaxViews;          // [kSPieces][NM]
+  double* atom_s = (double*)(mu_s + kSPieces * NM);       // [kSPieces][NA]
+  int32_t* code_s = (int32_t*)(atom_s + kSPieces * NA);   // [kSPieces][NC]
+  bool over = false;
+  for (int64_t cb = (int64_t)blockIdx.x * kSPieces; cb < C->n_pieces; cb += (int64_t)gridDim.x * kSPieces) {
+    const int np = (int)std::min<int64_t>(kSPieces, C->n_pieces - cb);
+    for (int t = threadIdx.x; t < np * NV; t += blockDim.x) {
+      const int pi = t / NV, v = t % NV;
+      const DView& V = C->views[v];
+      int64_t vr = 0;
+      for (int k = 0; k < V.nkey; ++k) vr += ld_int(C->pcols[V.key_src[k]], cb + pi) * V.key_stride[k];
+      vrow_s[pi * kMaxViews + v] = vr;
+      vcnt_s[pi * kMaxViews + v] = V.cnt[vr];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < np * NM; t += blockDim.x) {
+      const int pi = t / NM, m = t % NM;
+      const uint32_t bits = C->masks[m];
+      int64_t x = 1;
+      for (int v = 0; v < NV; ++v)
+        if (bits & (1u << v)) x *= vcnt_s[pi * kMaxViews + v];
+      mu_s[pi * NM + m] = x;
+    }
+    for (int t = threadIdx.x; t < np * NA; t += blockDim.x) {
+      const int pi = t / NA, a = t % NA;
+      const DAtom& At = C->atoms[a];
+      T x;
+      if (At.kind == SRC_COL) x = ld_val<T>(C->pcols[At.src], cb + pi);
+      else {
+        const int v = At.src;
+        x = vcnt_s[pi * kMaxViews + v] ? view_val<T>(C->views[v], vrow_s[pi * kMaxViews + v], At.slot) : (T)0;
+      }
+      atom_s[pi * NA + a] = (double)x;
+    }
+    for (int t = threadIdx.x; t < np * NC; t += blockDim.x) {
+      const int pi = t / NC, c = t % NC;
+      const DAtom& Cd = C->codes[c];
+      int32_t x;
+      if (Cd.kind == SRC_COL) x = (int32_t)ld_int(C->pcols[Cd.src], cb + pi);
+      else {
+        const int v = Cd.src;
+        const DView& V = C->views[v];
+        x = vcnt_s[pi * kMaxViews + v] ? V.codes[vrow_s[pi * kMaxViews + v] * V.n_codes + Cd.slot] : -1;
+      }
+      code_s[pi * NC + c] = x;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < np * ldf; t += blockDim.x) {
+      const int pi = t / ldf, f = t % ldf;
+      double x = 0.0;
+      if (f < NF) {
+        x = feat_d(C->feats[f], mu_s + pi * NM, code_s + pi * NC, atom_s + pi * NA, f < NFI);
+        if (f < NFI && !(x < kExactInt)) over = true;
+      }
+      C->fmat[(cb + pi) * ldf + f] = x;
+    }
+    for (int t = threadIdx.x; t < np * ldg; t += blockDim.x) {
+      const int pi = t / ldg, g = t % ldg;
+      C->bmat[(cb + pi) * ldg + g] =
+          g < NG ? col_d<T>(C, C->cols[g], cb + pi, code_s + pi * NC, atom_s + pi * NA) : 0.0;
+    }
+    // scatter cells (outputs keyed by outer codes too large for the dense block)
+    const int n_sc = C->n_scatter;
+    for (int t = threadIdx.x; t < np * n_sc; t += blockDim.x) {
+      const int pi = t / n_sc, sc = t % n_sc;
+      const int o = C->sc_out[sc];
+      int64_t row = 0;
+      bool ok = true;
+      for (int k = 0; k < 3; ++k) {
+        const int cidx = C->so_code[o * 3 + k];
+        if (cidx < 0) continue;
+        const int32_t cval = code_s[pi * NC + cidx];
+        if (cval < 0) ok = false;
+        row += (int64_t)cval * C->so_stride[o * 3 + k];
+      }
+      if (!ok) continue;
+      const int f = C->sc_f[sc], g = C->sc_g[sc];
+      const int comp = C->sc_comp[sc];
+      const DColB& B = C->cols[g];
+      if (comp < 0) {
+        int64_t v = feat_int(C->feats[f], mu_s + pi * NM, code_s + pi * NC);
+        int64_t cnt = C->row_pieces ? 1 : C->psi_i[(cb + pi) * C->psi_i_stride + B.entry];
+        if (B.kind == B_CNTF) {
+          const DFeat& F = B.feat;
+          if (F.c1 >= 0 && code_s[pi * NC + F.c1] != F.v1) cnt = 0;
+          if (F.c2 >= 0 && code_s[pi * NC + F.c2] != F.v2) cnt = 0;
+        }
+        v *= cnt;
+        if (v) atomic_add_i64(&C->so_cnt[o][row], v);
+      } else {
+        const double a = feat_d(C->feats[f], mu_s + pi * NM, code_s + pi * NC, atom_s + pi * NA, f < NFI);
+        const double b = col_d<T>(C, B, cb + pi, code_s + pi * NC, atom_s + pi * NA);
+        const double v = a * b;
+        if (v != 0.0) {
+          const int64_t idx = row * C->so_ncomp[o] + comp;
+          if (C->so_vals_f64[o]) atomic_add_f64(&((double*)C->so_vals[o])[idx], v);
+          else atomicAdd(&((float*)C->so_vals[o])[idx], (float)v);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (over) atomicOr(C->err_flag, 4);
+}
+
+int contract_stage_lds_bytes(const DContract& C) {
+  return (int)((int64_t)kSPieces * (2 * kMaxViews * 8 + C.n_masks * 8 + C.n_atoms * 8 + C.n_codes * 4) + 16);
+}
+int contract_stage_pieces() { return kSPieces; }
+
+void launch_contract_stage(const DContract* d, bool f64, int grid, int lds, hipStream_t s) {
+  if (f64) {
+    allow_lds((const void*)&k_contract_stage<double>, lds);
+    hipLaunchKernelGGL(k_contract_stage<double>, dim3(grid), dim3(256), lds, s, d);
+  } else {
+    allow_lds((const void*)&k_contract_stage<float>, lds);
+    hipLaunchKernelGGL(k_contract_stage<float>, dim3(grid), dim3(256), lds, s, d);
+  }
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kGemmKC = 32;   // pieces per LDS chunk
+constexpr int kGemmMT = 64;   // features per block: 4 wavefronts x 16 rows
+
+// Block (x, y): K range x, output macro-tile y = (feature tile, column tile).
+// Wavefront w owns feature rows [16w, 16w + 16) of the macro-tile and TN
+// column tiles of 16.  Operand fragments (16x4 of F^T, 4x16 of B) are read
+// from LDS rows padded so that the four K rows of a fragment fall in
+// different bank halves.  Output lane l, register i of a 16x16 tile holds
+// row (l >> 4) + 4 i, column l & 15.
+template <int TN>
+__global__ __launch_bounds__(256) void k_gemm_f64(const DGemm* __restrict__ G) {
+  constexpr int NT = 16 * TN;
+  constexpr int SA = kGemmMT + 16;
+  constexpr int SB = (NT % 32 == 0) ? NT + 16 : NT;
+  __shared__ __align__(16) double As[kGemmKC * SA];
+  __shared__ __align__(16) double Bs[kGemmKC * SB];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n_ntiles = (G->ng + NT - 1) / NT;
+  const int f0 = (blockIdx.y / n_ntiles) * kGemmMT;
+  const int g0 = (blockIdx.y % n_ntiles) * NT;
+  const int64_t kb = (int64_t)blockIdx.x * G->k_per_block;
+  const int64_t ke = std::min<int64_t>(G->n, kb + G->k_per_block);
+  const int ldf = G->ldf, ldg = G->ldg;
+  f64x4 acc[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = kb; k0 < ke; k0 += kGemmKC) {
+    // F chunk: kGemmKC rows x 64 features, as double2 (ldf and f0 are even)
+#pragma unroll
+    for (int j = 0; j < (kGemmKC * kGemmMT / 2) / 256; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      const int r = e / (kGemmMT / 2), c2 = e % (kGemmMT / 2);
+      const int f = f0 + 2 * c2;
+      double2 x = double2{0.0, 0.0};
+      if (k0 + r < ke && f < ldf) x = *(const double2*)(G->F + (k0 + r) * ldf + f);
+      *(double2*)(As + r * SA + 2 * c2) = x;
+    }
+#pragma unroll
+    for (int j = 0; j < (kGemmKC * NT / 2 + 255) / 256; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      if (e < kGemmKC * NT / 2) {
+        const int r = e / (NT / 2), c2 = e % (NT / 2);
+        const int g = g0 + 2 * c2;
+        double2 x = double2{0.0, 0.0};
+        if (k0 + r < ke && g < ldg) x = *(const double2*)(G->B + (k0 + r) * ldg + g);
+        *(double2*)(Bs + r * SB + 2 * c2) = x;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmKC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double a = As[kr * SA + 16 * w + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const double b = Bs[kr * SB + 16 * j + (lane & 15)];
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t ncell = (int64_t)G->nf * G->ng;
+  double* out = G->part + (int64_t)blockIdx.x * ncell;
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int g = g0 + 16 * j + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int f = f0 + 16 * w + (lane >> 4) + 4 * i;
+      if (f < G->nf && g < G->ng) out[(int64_t)f * G->ng + g] = acc[j][i];
+    }
+  }
+}
+
+int gemm_tile_cols(int ng) { return std::min(8, std::max(1, (ng + 15) / 16)); }
+int gemm_macro_tiles(int nf, int ng) {
+  const int nt = 16 * gemm_tile_cols(ng);
+  return ((nf + kGemmMT - 1) / kGemmMT) * ((ng + nt - 1) / nt);
+}
+int gemm_k_chunk() { return kGemmKC; }
+
+void launch_gemm_f64(const DGemm* d, int tn, int grid_x, int grid_y, hipStream_t s) {
+  dim3 g(grid_x, grid_y), b(256);
+  switch (tn) {
+#define CASE(N) \
+  case N: hipLaunchKernelGGL(k_gemm_f64<N>, g, b, 0, s, d); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: break;
+  }
+}
+
+// Block-major partial merge: block x takes 16 consecutive cells (one 128-byte
+// line per partial row) and 16 lanes' worth of partial blocks per cell; each
+// thread sums its blocks in order (compensated), then the 16 partial sums of a
+// cell are combined in a fixed order.  Integer cells are sums of exact
+// integers below 2^53 and are converted exactly (err_flag code 4 otherwise).
+__global__ __launch_bounds__(256) void k_merge_bm(const DCell* __restrict__ cells, int64_t n_cells,
+                                                  const double* __restrict__ part, int n_blocks, int ng,
+                                                  int64_t ncell, int32_t* err_flag) {
+  __shared__ double ps[16][17], pc[16][17];
+  const int cl = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int64_t c = (int64_t)blockIdx.x * 16 + cl;
+  double s = 0.0, cc = 0.0;
+  int64_t off = 0;
+  if (c < n_cells) {
+    off = (int64_t)cells[c].f * ng + cells[c].g;
+    for (int b = grp; b < n_blocks; b += 16) kadd(s, cc, part[(int64_t)b * ncell + off]);
+  }
+  ps[grp][cl] = s;
+  pc[grp][cl] = cc;
+  __syncthreads();
+  if (grp == 0 && c < n_cells) {
+    double t = 0.0, tc = 0.0;
+    for (int j = 0; j < 16; ++j) {
+      kadd(t, tc, ps[j][cl]);
+      kadd(t, tc, pc[j][cl]);
+    }
+    t += tc;
+    const DCell& X = cells[c];
+    if (X.is_int) {
+      if (!(fabs(t) < kExactInt)) atomicOr(err_flag, 4);
+      const int64_t v = (int64_t)llrint(t);
+      if (X.vals) {
+        if (X.vals_f64) ((double*)X.vals)[X.idx] += (double)v;
+        else ((float*)X.vals)[X.idx] += (float)v;
+      } else {
+        X.cnt[X.idx] += v;
+      }
+    } else {
+      if (X.vals_f64) ((double*)X.vals)[X.idx] += t;
+      else ((float*)X.vals)[X.idx] += (float)t;
+    }
+  }
+}
+void launch_merge_bm(const DCell* cells, int64_t n_cells, const double* part, int n_blocks, int ng, int64_t ncell,
+                     int32_t* err_flag, hipStream_t s) {
+  if (n_cells <= 0) return;
+  const int grid = (int)((n_cells + 15) / 16);
+  hipLaunchKernelGGL(k_merge_bm, dim3(grid), dim3(256), 0, s, cells, n_cells, part, n_blocks, ng, ncell, err_flag);
 }
 
 // ---------------------------------------------------------------------------

@@ -64,7 +64,8 @@ struct NodeData {
 
 struct Step {
   std::string name;
-  int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract, 5 merge, 6 image build
+  int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract (VALU), 5 merge, 6 image build,
+              // 7 contraction staging, 8 MFMA contraction, 9 block-major merge
   int fast = 0;
   void* dev = nullptr;
   int64_t n = 0;
@@ -341,6 +342,114 @@ static void* typed_sorted_column(Prep& S, int r, int c, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // descriptors of one group program
 // ---------------------------------------------------------------------------
+// Contraction on the matrix cores: a staging launch writes F and B per piece
+// (FP64), a split-K MFMA launch multiplies them into block-major partials,
+// and a merge adds the partials of every cell of the plan into its output.
+static void build_contract_mfma(Prep& S, const GroupProgram& g, const std::string& gname, DContract& c,
+                                int64_t n_pieces, int psi_f_stride, int psi_i_stride, bool f64, hipStream_t st) {
+  const int NF = c.n_feat, NG = c.n_col;
+  c.ldf = std::max(16, (NF + 15) / 16 * 16);
+  c.ldg = std::max(16, (NG + 15) / 16 * 16);
+  const int64_t np1 = std::max<int64_t>(1, n_pieces);
+  c.fmat = (double*)dalloc(S, (size_t)np1 * c.ldf * 8);
+  c.bmat = (double*)dalloc(S, (size_t)np1 * c.ldg * 8);
+  c.err_flag = S.err_flag;
+  c.part_f = nullptr;
+  c.part_i = nullptr;
+  c.pieces_per_block = 0;
+  const int lds = contract_stage_lds_bytes(c);
+  if (lds > 160 * 1024) throw PlanError{LMFAO_EUNSUPPORTED, "contraction staging needs more LDS than a CU has"};
+  const int64_t chunks = (n_pieces + contract_stage_pieces() - 1) / contract_stage_pieces();
+  Step st1;
+  st1.name = gname + ":stage";
+  st1.kind = 7;
+  st1.dev = upload(S, c, st);
+  st1.grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, 2048));
+  st1.lds = lds;
+  st1.pieces = n_pieces;
+  st1.rows = n_pieces;
+  for (int i = 0; i < c.n_pcols; ++i) st1.alg_read += (double)n_pieces * (c.pcols[i].dtype == LMFAO_F64 ? 8 : 4);
+  st1.alg_read += (double)n_pieces * (psi_f_stride * (f64 ? 8 : 4) + psi_i_stride * 4);
+  for (int v = 0; v < c.n_views; ++v)
+    st1.alg_read += (double)std::min<int64_t>(c.views[v].n_keys, n_pieces) *
+                    (8 + c.views[v].n_vals * (c.views[v].vals_f64 ? 8 : 4) + c.views[v].n_codes * 4);
+  st1.alg_write = (double)n_pieces * (c.ldf + c.ldg) * 8;
+  S.steps.push_back(st1);
+  if (NF == 0 || NG == 0 || g.gemm_cells.empty()) return;
+
+  const int tn = gemm_tile_cols(NG);
+  const int gy = gemm_macro_tiles(NF, NG);
+  const int64_t kc = gemm_k_chunk();
+  const int64_t want = std::max(1, 512 / gy);   // K splits: ~2 blocks per CU in all
+  int64_t kpb = (n_pieces + want - 1) / want;
+  kpb = std::max<int64_t>(kc, (kpb + kc - 1) / kc * kc);
+  const int gx = (int)std::max<int64_t>(1, (n_pieces + kpb - 1) / kpb);
+  const int64_t ncell = (int64_t)NF * NG;
+  double* part = (double*)dalloc(S, (size_t)gx * ncell * 8);
+  DGemm gm{};
+  gm.F = c.fmat;
+  gm.B = c.bmat;
+  gm.n = n_pieces;
+  gm.ldf = c.ldf;
+  gm.ldg = c.ldg;
+  gm.nf = NF;
+  gm.ng = NG;
+  gm.k_per_block = kpb;
+  gm.part = part;
+  Step st2;
+  st2.name = gname + ":gemm";
+  st2.kind = 8;
+  st2.dev = upload(S, gm, st);
+  st2.grid = gx;
+  st2.grid_y = gy;
+  st2.na = tn;
+  st2.pieces = n_pieces;
+  st2.rows = n_pieces;
+  // the staged operands are this launch's input; the partials its output
+  st2.alg_read = (double)n_pieces * (c.ldf + c.ldg) * 8;
+  st2.alg_write = (double)gx * ncell * 8;
+  st2.alg_flop = 2.0 * (double)n_pieces * NF * NG;
+  S.steps.push_back(st2);
+
+  std::vector<DCell> cells;
+  for (auto& gc : g.gemm_cells) {
+    const ProgOutput& po = g.outs[gc.second.out];
+    const OutBuf& O = po.ref.kind == 0 ? S.qout[po.ref.id] : S.vout[po.ref.id];
+    DCell x{};
+    x.f = gc.first.first;
+    x.g = gc.first.second;
+    x.is_int = (x.f < c.n_feat_int && x.g < c.n_col_int) ? 1 : 0;
+    x.vals_f64 = O.f64 ? 1 : 0;
+    if (gc.second.comp < 0) {
+      if (!x.is_int) throw PlanError{LMFAO_EINVAL, "internal: count cell not integral"};
+      x.cnt = O.cnt;
+      x.vals = nullptr;
+      x.idx = gc.second.row;
+    } else {
+      x.cnt = nullptr;
+      x.vals = O.vals;
+      x.idx = gc.second.row * O.n_vals + gc.second.comp;
+    }
+    cells.push_back(x);
+  }
+  // partial rows are read a 128-byte line of consecutive cells at a time
+  std::stable_sort(cells.begin(), cells.end(), [](const DCell& a, const DCell& b) {
+    return a.f != b.f ? a.f < b.f : a.g < b.g;
+  });
+  Step m;
+  m.name = gname + ":merge";
+  m.kind = 9;
+  m.dev = upload_vec(S, cells, st);
+  m.n = (int64_t)cells.size();
+  m.part_f = part;
+  m.n_blocks = gx;
+  m.NF = NF;
+  m.NG = NG;
+  m.alg_read = (double)gx * cells.size() * 8;
+  m.alg_write = (double)cells.size() * 8;
+  S.steps.push_back(m);
+}
+
 static void build_group(Prep& S, int gi, const void* const* const* cols, hipStream_t st) {
   Plan& P = *S.P;
   GroupDef& G = P.groups[gi];
@@ -655,10 +764,10 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     // lean kernel: inner views through per-key images (single-attribute keys),
     // at most 2 inner views, 4 codes, 16 histograms, 2 count-only direct tables
     bool fast = n_in <= 2 && d.n_codes <= 4 && d.n_masks <= 4 && d.n_pi <= 4 && R.n_rows < ((int64_t)1 << 31) &&
-                d.n_hists <= kFastHists && d.n_tables <= kFastTables;
+                d.n_hists <= kFastHists && d.n_tables <= kFastTables && d.pf_uniform;
     d.n_atoms = NA;
     for (int v = 0; v < n_in; ++v)
-      fast = fast && d.views[v].n_keys < ((int64_t)1 << 31) && d.views[v].nkey == 1;
+      fast = fast && d.views[v].n_keys < ((int64_t)1 << 31) && d.views[v].nkey <= 2;
     for (int i = 0; i < d.n_hists; ++i) fast = fast && d.hists[i].offset + d.hists[i].dom < (1 << 19);
     for (int t = 0; t < d.n_tables; ++t) {
       fast = fast && d.tables[t].n_tcomps == 1 && d.tables[t].tcomp[0] < 0 && d.tables[t].ncode <= 3 &&
@@ -721,7 +830,10 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
         d.imgs[v].cnt_off = code_off + 4;
         d.imgs[v].key_col = V.nkey == 1 ? V.key_src[0] : -1;
         F.img[v] = ib.img;
-        F.kcol[v] = (const int32_t*)N.sorted_col[scols[V.key_src[0]]];
+        for (int k = 0; k < 2; ++k) {
+          F.kcol[v][k] = k < V.nkey ? (const int32_t*)N.sorted_col[scols[V.key_src[k]]] : nullptr;
+          F.kmul[v][k] = k < V.nkey ? (int32_t)V.key_stride[k] : 0;
+        }
         Step b;
         b.name = gname + ":image";
         b.kind = 6;
@@ -875,8 +987,6 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
   int grid_y = std::max(1, (tiles + contract_threads() - 1) / contract_threads());
   grid_y = std::max<int>(grid_y, (int)((icells + contract_max_int_cells() - 1) / contract_max_int_cells()));
   c.pieces_per_block = (int32_t)ppb;
-  c.part_f = (double*)dalloc(S, (size_t)grid_x * std::max(1, c.n_feat * c.n_col) * 8);
-  c.part_i = (int64_t*)dalloc(S, (size_t)grid_x * std::max(1, c.n_feat_int * c.n_col_int) * 8);
   // scatter
   std::vector<int32_t> sc_out, sc_comp, sc_f, sc_g;
   for (auto& sc : g.scatter) {
@@ -917,6 +1027,12 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
   c.so_vals_f64 = upload_vec(S, so_f64, st);
   c.so_cnt = upload_vec(S, so_cnt, st);
   c.so_vals = upload_vec(S, so_vals, st);
+  if (S.P->opts.contraction == LMFAO_CONTRACT_MFMA) {
+    build_contract_mfma(S, g, gname, c, n_pieces, psi_f_stride, psi_i_stride, f64, st);
+    return;
+  }
+  c.part_f = (double*)dalloc(S, (size_t)grid_x * std::max(1, c.n_feat * c.n_col) * 8);
+  c.part_i = (int64_t*)dalloc(S, (size_t)grid_x * std::max(1, c.n_feat_int * c.n_col_int) * 8);
   int lds = contract_lds_bytes(c, f64);
   if (lds > 160 * 1024) throw PlanError{LMFAO_EUNSUPPORTED, "contraction needs more LDS than a CU has"};
   Step s;
@@ -1051,7 +1167,7 @@ static void prepare_all(Prep& S, const void* const* const* cols, hipStream_t st)
 
 // timed steps: scans and contractions (the kernels that move the data); the
 // whole run is timed as well.  Slot 0 of a run = whole run.
-static bool timed_step(const Step& s) { return s.kind == 2 || s.kind == 4; }
+static bool timed_step(const Step& s) { return s.kind == 2 || s.kind == 4 || s.kind == 7 || s.kind == 8; }
 static int timed_slots(const Prep& S) {
   int n = 1;
   for (auto& s : S.steps) n += timed_step(s);
@@ -1088,6 +1204,11 @@ static void enqueue_run(Prep& S, hipStream_t st) {
       case 4: launch_contract((const DContract*)s.dev, S.f64, s.grid, s.grid_y, s.lds, st); break;
       case 5:
         launch_merge_cells((const DCell*)s.dev, s.n, s.part_f, s.part_i, s.n_blocks, s.NF, s.NG, s.NFI, s.NGI, st);
+        break;
+      case 7: launch_contract_stage((const DContract*)s.dev, S.f64, s.grid, s.lds, st); break;
+      case 8: launch_gemm_f64((const DGemm*)s.dev, s.na, s.grid, s.grid_y, st); break;
+      case 9:
+        launch_merge_bm((const DCell*)s.dev, s.n, s.part_f, s.n_blocks, s.NG, (int64_t)s.NF * s.NG, S.err_flag, st);
         break;
     }
     if (t) {
@@ -1218,6 +1339,9 @@ lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, i
       HIP_OK(hipMemcpy(&flag, prep->err_flag, 4, hipMemcpyDeviceToHost));
       if (flag & 1) return set_err(LMFAO_EINVAL, "a relation has duplicate values of its declared primary key");
       if (flag & 2) return set_err(LMFAO_EINVAL, "an integer column holds a value outside its declared domain");
+      if (flag & 4)
+        return set_err(LMFAO_EOVERFLOW, "an integer aggregate reached 2^53 in the FP64 matrix-core contraction "
+                                        "(use the VALU contraction)");
     }
   } catch (const HipError& e) {
     return set_err(LMFAO_EHIP, e.msg);
@@ -1359,7 +1483,9 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     if (s.kind == 0) continue;
     if (!first) j += ",";
     first = false;
-    static const char* kinds[] = {"fill", "view_build", "scan", "table_reduce", "contract", "merge", "image"};
+    static const char* kinds[] = {"fill", "view_build", "scan",  "table_reduce", "contract",
+                                  "merge", "image",      "stage", "gemm",         "merge"};
+    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 10, "one name per step kind");
     char tmp[512];
     snprintf(tmp, sizeof(tmp),
              "{\"name\":\"%s\",\"kind\":\"%s\",\"rows\":%lld,\"pieces\":%lld,\"alg_read_bytes\":%.0f,"

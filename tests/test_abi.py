@@ -36,7 +36,7 @@ def test_default_options():
     lib = E.load_library()
     o = lmfao_options()
     lib.lmfao_default_options(ctypes.byref(o))
-    assert (o.precision, o.form, o.root_policy, o.min_segment, o.row_piece_max) == (0, 0, 0, 0, 0)
+    assert (o.precision, o.form, o.root_policy, o.min_segment, o.row_piece_max, o.contraction) == (0, 0, 0, 0, 0, 0)
 
 
 def test_null_arguments_are_rejected_before_device_work():

@@ -77,10 +77,12 @@ def test_tiny_star_scan(eng, min_segment):
     check(eng, p, F64_TOL, "tiny_star_scan", policy="fact", row_piece_max=-1, min_segment=min_segment)
 
 
-def test_tiny_star_full_size(eng):
+@pytest.mark.parametrize("contraction", ["mfma", "valu"])
+def test_tiny_star_full_size(eng, contraction):
     # the 100k-row tiny star configuration, seed 0, FP64, in the bench's launch configuration
     p = W.tiny_star(seed=0)
-    check(eng, p, F64_TOL, "tiny_star_full", policy="fact", row_piece_max=-1, min_segment=1)
+    check(eng, p, F64_TOL, "tiny_star_full", policy="fact", row_piece_max=-1, min_segment=1,
+          contraction=contraction)
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -102,13 +104,15 @@ def test_random_many_to_many(eng, seed):
     p["batch"] = [dict(q, groupby=[g for g in q["groupby"] if g == "c0"], root="R0") for q in p["batch"]]
     check(eng, p, F64_TOL, f"random_m2m_{seed}", policy="groupby")
     check(eng, p, F64_TOL, f"random_m2m_{seed}_scan", policy="groupby", row_piece_max=-1, min_segment=1)
+    check(eng, p, F64_TOL, f"random_m2m_{seed}_valu", policy="groupby", contraction="valu")
 
 
-def test_retail_snowflake_small(eng):
+@pytest.mark.parametrize("contraction", ["mfma", "valu"])
+def test_retail_snowflake_small(eng, contraction):
     p = W.retail_snowflake(seed=0, n_inv=300_007, n_locn=60, n_dates=20, n_ksn=400,
                            n_weather_dates=30)
     check(eng, p, F32_TOL, "retail_small_f32", precision="f32", policy="fact", row_piece_max=5_000,
-          min_segment=16)
+          min_segment=16, contraction=contraction)
 
 
 def test_retail_snowflake_small_f64(eng):
