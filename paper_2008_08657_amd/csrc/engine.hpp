@@ -20,7 +20,7 @@ namespace lmfao {
 constexpr int kMaxScanCols = 16;   // sorted columns a scan reads per tuple
 constexpr int kMaxPieceCols = 64;  // per-piece columns of a contraction
 constexpr int kMaxOuterAtoms = 64;
-constexpr int kMaxOuterCodes = 16;
+constexpr int kMaxOuterCodes = 64;
 constexpr int kMaxViews = 8;       // views one kernel looks up
 constexpr int kMaxInnerViews = 4;  // views the scan looks up per tuple
 constexpr int kMaxWeights = 16;    // weights pre-aggregated over runs (registers)
@@ -28,7 +28,7 @@ constexpr int kMaxWeightTable = 64;  // distinct histogram / table weights of a 
 constexpr int kMaxKey = 4;         // attributes of one view key
 constexpr int kMaxAtoms = 8;       // inner factors of the fast scan
 constexpr int kMaxMasks = 4;       // distinct multiplicity masks in a scan
-constexpr int kMaxCodes = 8;       // inner codes of a scan
+constexpr int kMaxCodes = 16;      // inner codes of a scan
 constexpr int kMaxHists = 64;      // per-piece histograms in a scan
 constexpr int kMaxTables = 8;      // direct group-by tables written by a scan
 constexpr int kMaxTableComps = 8;
@@ -50,6 +50,7 @@ struct AttrDef {
 struct RelDef {
   std::string name;
   int64_t n_rows = 0;
+  int n_input_attrs = 0;           // columns the caller passes; derived columns follow
   std::vector<int> attrs;          // global attribute ids, schema order
   std::vector<int> dtypes;
   std::vector<char> is_key;
@@ -241,6 +242,24 @@ struct GroupDef {
   GroupProgram prog;
 };
 
+// A bucket code derived from attribute `src` of relation `rel`: the number of
+// thresholds below the value (kind 0: t < x, for x <= t and x > t) or at most
+// the value (kind 1: t <= x, for x < t and x >= t).  Thresholds are rounded to
+// the attribute's comparison type (FP32 columns compare in FP32) and sorted.
+struct DerivedAttr {
+  int attr = -1, src = -1, rel = -1, kind = 0;
+  std::vector<double> thr;
+};
+
+// A query of the caller's batch: either one planned query, or the sum over a
+// range of bucket (or code) values of a planned query that groups by them too.
+struct UserQuery {
+  int internal = -1;
+  bool range = false;
+  int64_t lo = 0, hi = 0, ex = -1;   // buckets [lo, hi) except ex
+  int64_t nb = 1;                    // bucket domain (last key of the planned query)
+};
+
 struct Plan {
   std::vector<AttrDef> attrs;
   std::map<std::string, int> attr_id;
@@ -251,6 +270,9 @@ struct Plan {
   std::vector<ViewDef> views;
   std::vector<GroupDef> groups;
   std::vector<std::vector<int>> order;   // attribute order per relation
+  std::vector<Cond> filter;              // conditions every planned query shares
+  std::vector<DerivedAttr> derived;
+  std::vector<UserQuery> user;           // caller's queries, in batch order
   int n_levels = 0;
   lmfao_options opts;
   bool supported = true;
@@ -365,6 +387,7 @@ struct DFast {
 };
 
 struct DScan {
+  const int32_t* w;                // filter weight per sorted row (null: no filter)
   int32_t fast;                    // lean kernel: images, <= 4 codes, direct atomics
   DFast F;
   DImage imgs[kMaxInnerViews];
@@ -422,6 +445,7 @@ struct DColB {
 };
 
 struct DContract {
+  const int32_t* w;                // row pieces: filter weight per row (null: no filter)
   int64_t n_pieces;
   int32_t n_pcols;
   DCol pcols[kMaxPieceCols];       // per-piece columns

@@ -109,6 +109,84 @@ void launch_fill(void* p, int64_t bytes, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// conditions: per-row filter weights and bucket codes of thresholds
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ld_cmp(const DCol& c, int64_t r) {
+  if (c.dtype == LMFAO_I32) return (double)((const int32_t*)c.ptr)[r];
+  if (c.dtype == LMFAO_F32) return (double)((const float*)c.ptr)[r];
+  return ((const double*)c.ptr)[r];
+}
+__device__ __forceinline__ bool cond_holds(double x, int op, double c) {
+  switch (op) {
+    case LMFAO_LE: return x <= c;
+    case LMFAO_LT: return x < c;
+    case LMFAO_GT: return x > c;
+    case LMFAO_GE: return x >= c;
+    case LMFAO_EQ: return x == c;
+    default: return x != c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_filter(const DFilter* __restrict__ F) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < F->n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    int w = 1;
+    for (int k = 0; k < F->n_conds; ++k) w &= cond_holds(ld_cmp(F->cols[k], r), F->op[k], F->c[k]) ? 1 : 0;
+    F->out[r] = w;
+  }
+}
+void launch_filter(const DFilter* d, int64_t n_rows, hipStream_t s) {
+  if (n_rows <= 0) return;
+  const int grid = (int)std::min<int64_t>((n_rows + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_filter, dim3(grid), dim3(256), 0, s, d);
+}
+
+// bucket = number of thresholds below the value (kind 0) or at most the value
+// (kind 1); thresholds sorted ascending, in the column's comparison type
+__global__ __launch_bounds__(256) void k_bucketize(DCol src, int64_t n, const double* __restrict__ thr, int n_thr,
+                                                   int kind, int32_t* __restrict__ out) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const double x = ld_cmp(src, r);
+    int lo = 0, hi = n_thr;   // first index whose threshold is not below (kind 0) / above (kind 1) x
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const bool before = kind == 0 ? thr[mid] < x : thr[mid] <= x;
+      if (before) lo = mid + 1;
+      else hi = mid;
+    }
+    out[r] = lo;
+  }
+}
+void launch_bucketize(const void* src, int dtype, int64_t n, const double* thr, int n_thr, int kind, int32_t* out,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  DCol c{src, dtype, 0};
+  hipLaunchKernelGGL(k_bucketize, dim3(grid), dim3(256), 0, s, c, n, thr, n_thr, kind, out);
+}
+
+// block per range query, thread per destination row; buckets in order
+__global__ __launch_bounds__(256) void k_finalize(const DFinalize* __restrict__ D) {
+  const DFinalize& F = D[blockIdx.x];
+  for (int64_t r = threadIdx.x; r < F.n_rows; r += blockDim.x) {
+    int64_t cnt = 0;
+    for (int64_t b = F.lo; b < F.hi; ++b)
+      if (b != F.ex) cnt += F.src_cnt[r * F.nb + b];
+    F.dst_cnt[r] = cnt;
+    for (int k = 0; k < F.n_vals; ++k) {
+      double v = 0.0, cc = 0.0;
+      for (int64_t b = F.lo; b < F.hi; ++b)
+        if (b != F.ex) kadd(v, cc, F.src_vals[(r * F.nb + b) * F.n_vals + k]);
+      F.dst_vals[r * F.n_vals + k] = v + cc;
+    }
+  }
+}
+void launch_finalize(const DFinalize* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_finalize, dim3(n), dim3(256), 0, s, d);
+}
+
+// ---------------------------------------------------------------------------
 // view build for single-valued subtrees
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -127,6 +205,7 @@ __global__ __launch_bounds__(256) void k_view_build(const DViewBuild* __restrict
       vrow[v] = vr;
       mu *= V.cnt[vr];
     }
+    if (B->w) mu *= B->w[r];
     if (mu == 0) continue;
     unsigned long long old = atomicAdd((unsigned long long*)&B->out_cnt[row], (unsigned long long)mu);
     if (old != 0 || mu != 1) atomicOr(B->err_flag, 1);   // key not unique
@@ -431,7 +510,9 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(const DScan* __restric
         const int64_t r = r0 + lane;
         const bool valid = r < re;
         const int64_t rr = valid ? r : rb;   // in-bounds row for invalid lanes
-        int64_t mu0 = valid, mu1 = valid, mu2 = valid, mu3 = valid;   // multiplicity per mask
+        // multiplicity per mask; a row failing the filter has multiplicity 0
+        const int64_t w0 = valid ? (S->w ? (int64_t)S->w[rr] : 1) : 0;
+        int64_t mu0 = w0, mu1 = w0, mu2 = w0, mu3 = w0;
         T av[NA + 1];
         av[0] = (T)1;
         int32_t cv[kMaxCodes];
@@ -745,6 +826,7 @@ struct RowCols {
   T f[NA > 0 ? NA : 1];
   int c[4];
   int k[2];
+  int w;   // filter weight
 };
 template <typename T, int NA>
 __device__ __forceinline__ void load_row_cols(const DScan* __restrict__ S, int rr, RowCols<T, NA>& o) {
@@ -764,6 +846,7 @@ __device__ __forceinline__ void load_row_cols(const DScan* __restrict__ S, int r
     }
     o.k[v] = key;
   }
+  o.w = S->w ? gld(S->w, rr) : 1;
 }
 
 // Per tuple: column loads, one vector load per inner view image, factor
@@ -840,7 +923,8 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan_fast(const DScan* __re
 #pragma unroll
         for (int a = 0; a < NA; ++a) av[a + 1] = cu.f[a];
         int c0 = cu.c[0], c1 = cu.c[1], c2 = cu.c[2], c3 = cu.c[3];
-        int mu0 = valid, mu1 = valid, mu2 = valid, mu3 = valid;
+        const int wv = valid ? cu.w : 0;
+        int mu0 = wv, mu1 = wv, mu2 = wv, mu3 = wv;
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           const uint4* img = (const uint4*)S->F.img[v];
@@ -1132,10 +1216,10 @@ __global__ __launch_bounds__(kCThreads) void k_contract(const DContract* __restr
       if (B.kind == B_PSI_F) {
         x = ((const T*)C->psi_f)[p * C->psi_f_stride + B.entry];
       } else if (B.kind == B_PSI_I) {
-        xi = C->row_pieces ? 1 : C->psi_i[p * C->psi_i_stride + B.entry];
+        xi = C->row_pieces ? (C->w ? C->w[p] : 1) : C->psi_i[p * C->psi_i_stride + B.entry];
         x = (T)xi;
       } else {
-        int64_t cnt = C->row_pieces ? 1 : C->psi_i[p * C->psi_i_stride + B.entry];
+        int64_t cnt = C->row_pieces ? (C->w ? C->w[p] : 1) : C->psi_i[p * C->psi_i_stride + B.entry];
         // feature without multiplicity (the A side carries it)
         DFeat F = B.feat;
         int64_t m = cnt;
@@ -1199,7 +1283,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract(const DContract* __restr
         int64_t v = feat_int(C->feats[f], mu_s + pi * NM, code_s + pi * NC);
         // column value as integer
         const DColB& B = C->cols[g];
-        int64_t cnt = C->row_pieces ? 1 : C->psi_i[(cb + pi) * C->psi_i_stride + B.entry];
+        int64_t cnt = C->row_pieces ? (C->w ? C->w[cb + pi] : 1) : C->psi_i[(cb + pi) * C->psi_i_stride + B.entry];
         if (B.kind == B_CNTF) {
           const DFeat& F = B.feat;
           if (F.c1 >= 0 && code_s[pi * NC + F.c1] != F.v1) cnt = 0;
@@ -1284,7 +1368,7 @@ template <typename T>
 __device__ __forceinline__ double col_d(const DContract* C, const DColB& B, int64_t p, const int32_t* codes,
                                         const double* atoms) {
   if (B.kind == B_PSI_F) return (double)((const T*)C->psi_f)[p * C->psi_f_stride + B.entry];
-  const int64_t cnt = C->row_pieces ? 1 : C->psi_i[p * C->psi_i_stride + B.entry];
+  const int64_t cnt = C->row_pieces ? (C->w ? C->w[p] : 1) : C->psi_i[p * C->psi_i_stride + B.entry];
   if (B.kind == B_PSI_I) return (double)cnt;
   const DFeat& F = B.feat;
   int64_t m = cnt;
@@ -1385,7 +1469,7 @@ __global__ __launch_bounds__(256) void k_contract_stage(const DContract* __restr
       const DColB& B = C->cols[g];
       if (comp < 0) {
         int64_t v = feat_int(C->feats[f], mu_s + pi * NM, code_s + pi * NC);
-        int64_t cnt = C->row_pieces ? 1 : C->psi_i[(cb + pi) * C->psi_i_stride + B.entry];
+        int64_t cnt = C->row_pieces ? (C->w ? C->w[cb + pi] : 1) : C->psi_i[(cb + pi) * C->psi_i_stride + B.entry];
         if (B.kind == B_CNTF) {
           const DFeat& F = B.feat;
           if (F.c1 >= 0 && code_s[pi * NC + F.c1] != F.v1) cnt = 0;

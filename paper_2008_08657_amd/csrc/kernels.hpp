@@ -19,11 +19,35 @@ struct DViewBuild {
   int32_t n_vals;
   int32_t val_kind[64], val_src[64], val_slot[64];
   int32_t n_codes;
-  int32_t code_kind[8], code_src[8], code_slot[8];
+  int32_t code_kind[kMaxOuterCodes], code_src[kMaxOuterCodes], code_slot[kMaxOuterCodes];
   int64_t* out_cnt;
   void* out_vals;
   int32_t* out_codes;
   int32_t* err_flag;
+  const int32_t* w;          // filter weight per row (null: no filter)
+};
+
+// conjunction of conditions on one relation's columns -> 0/1 weight per row
+constexpr int kMaxFilterConds = 8;
+struct DFilter {
+  int64_t n_rows;
+  int32_t n_conds;
+  DCol cols[kMaxFilterConds];
+  int32_t op[kMaxFilterConds];
+  double c[kMaxFilterConds];   // constant, already in the column's comparison type
+  int32_t* out;
+};
+
+// one range query of the caller's batch: sums of a planned query's buckets
+struct DFinalize {
+  const int64_t* src_cnt;
+  const double* src_vals;
+  int64_t* dst_cnt;
+  double* dst_vals;
+  int64_t n_rows;            // rows of the destination (base group-by keys)
+  int64_t nb;                // buckets per destination row (last key of the source)
+  int32_t n_vals;
+  int64_t lo, hi, ex;        // buckets [lo, hi) except ex
 };
 
 struct DKeyCols {
@@ -43,6 +67,10 @@ struct DTableReduce {
 };
 
 void launch_fill(void* p, int64_t bytes, hipStream_t s);
+void launch_filter(const DFilter* d, int64_t n_rows, hipStream_t s);
+void launch_bucketize(const void* src, int dtype, int64_t n, const double* thr, int n_thr, int kind, int32_t* out,
+                      hipStream_t s);
+void launch_finalize(const DFinalize* d, int n, hipStream_t s);
 void launch_view_build(const DViewBuild* d, int64_t n_rows, bool f64, hipStream_t s);
 void launch_make_keys(const DKeyCols* d, uint64_t* keys, uint32_t* idx, int64_t n, hipStream_t s);
 void launch_sort(uint64_t* keys, uint32_t* idx, uint64_t* keys_tmp, uint32_t* idx_tmp, int64_t n, int bits,

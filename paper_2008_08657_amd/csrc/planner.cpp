@@ -19,8 +19,12 @@
 //     and the contraction that multiplies them (the partial aggregates of
 //     Figure 3 pushed past the inner loops).
 #include <algorithm>
+#include <cmath>
+#include <iterator>
+#include <tuple>
 #include <cstring>
 #include <functional>
+#include <iomanip>
 #include <numeric>
 #include <queue>
 #include <sstream>
@@ -61,6 +65,8 @@ static std::string json_escape(const std::string& s) {
 // ---------------------------------------------------------------------------
 // 1. validation and intake
 // ---------------------------------------------------------------------------
+static void rewrite_conditions(Plan& P);
+
 static void intake(Plan& P, const lmfao_schema* schema, const lmfao_join_tree* tree,
                    const lmfao_batch* batch) {
   if (!schema || schema->n_relations <= 0 || !schema->relations) fail(LMFAO_EINVAL, "empty schema");
@@ -97,6 +103,7 @@ static void intake(Plan& P, const lmfao_schema* schema, const lmfao_join_tree* t
       D.dtypes.push_back(A.dtype);
       D.is_key.push_back(A.is_key ? 1 : 0);
     }
+    D.n_input_attrs = (int)D.attrs.size();
   }
   // join tree
   P.adj.assign(n, {});
@@ -175,6 +182,7 @@ static void intake(Plan& P, const lmfao_schema* schema, const lmfao_join_tree* t
       q.conds.push_back(Cond{lookup(C.attr), C.op, C.constant});
     }
     std::sort(q.conds.begin(), q.conds.end());
+    q.conds.erase(std::unique(q.conds.begin(), q.conds.end()), q.conds.end());
     if (Q.n_aggregates <= 0) fail(LMFAO_EINVAL, "query without aggregates");
     for (int k = 0; k < Q.n_aggregates; ++k) {
       const lmfao_aggregate& A = Q.aggregates[k];
@@ -192,6 +200,144 @@ static void intake(Plan& P, const lmfao_schema* schema, const lmfao_join_tree* t
     q.root = Q.root;
     if (q.root < -1 || q.root >= n) fail(LMFAO_EINVAL, "bad root override");
     P.queries.push_back(q);
+  }
+  rewrite_conditions(P);
+}
+
+// ---------------------------------------------------------------------------
+// conditions.  The conjunction every query of the batch shares becomes one
+// filter applied to the relations (a tuple failing it has multiplicity 0).
+// A query may carry one more condition on a single attribute -- the split
+// candidates of a CART node batch (section 3, decision trees): X op t with a
+// threshold, or X = c / X != c on an integer attribute.  Such queries are
+// planned as one query grouped by a bucket code of X (or by X itself) whose
+// buckets are summed over the range the condition selects, so a batch of many
+// thresholds on one attribute is one group-by instead of many filters.
+// ---------------------------------------------------------------------------
+static double cmp_value(const AttrDef& A, double c) {
+  // the comparison happens in the column's type for FP32 columns
+  return A.dtype == LMFAO_F32 ? (double)(float)c : c;
+}
+
+static void rewrite_conditions(Plan& P) {
+  const std::vector<QueryDef> given = P.queries;
+  const int nq = (int)given.size();
+  std::vector<Cond> common = given[0].conds;
+  for (int i = 1; i < nq; ++i) {
+    std::vector<Cond> x;
+    std::set_intersection(common.begin(), common.end(), given[i].conds.begin(), given[i].conds.end(),
+                          std::back_inserter(x));
+    common = x;
+  }
+  for (auto& c : common)
+    if (P.attrs[c.attr].dtype == LMFAO_F32) c.c = cmp_value(P.attrs[c.attr], c.c);
+  P.filter = common;
+  P.queries.clear();
+  P.user.assign(nq, UserQuery{});
+  // candidate conditions per (attribute, threshold kind)
+  struct Cand {
+    int q;
+    Cond c;
+  };
+  std::vector<Cand> cands;
+  std::map<std::pair<int, int>, std::set<double>> thr;   // (attr, kind) -> thresholds
+  for (int i = 0; i < nq; ++i) {
+    std::vector<Cond> extra;
+    std::set_difference(given[i].conds.begin(), given[i].conds.end(), common.begin(), common.end(),
+                        std::back_inserter(extra));
+    if (extra.empty()) {
+      QueryDef q = given[i];
+      q.conds = common;
+      P.user[i].internal = (int)P.queries.size();
+      P.queries.push_back(q);
+      continue;
+    }
+    if (extra.size() > 1)
+      fail(LMFAO_EUNSUPPORTED, "query " + std::to_string(i) +
+                                   ": more than one condition beyond those every query of the batch shares");
+    const Cond& c = extra[0];
+    const AttrDef& A = P.attrs[c.attr];
+    if (given[i].groupby.size() > 1)
+      fail(LMFAO_EUNSUPPORTED, "query " + std::to_string(i) + ": a condition of its own and 2 group-by attributes");
+    if (std::find(given[i].groupby.begin(), given[i].groupby.end(), c.attr) != given[i].groupby.end())
+      fail(LMFAO_EUNSUPPORTED, "query " + std::to_string(i) + ": condition on its own group-by attribute");
+    if (c.op == LMFAO_EQ || c.op == LMFAO_NE) {
+      if (A.dtype != LMFAO_I32 || A.domain <= 0)
+        fail(LMFAO_EUNSUPPORTED, "query " + std::to_string(i) + ": = / != needs an integer attribute with a domain");
+    } else {
+      thr[{c.attr, (c.op == LMFAO_LE || c.op == LMFAO_GT) ? 0 : 1}].insert(cmp_value(A, c.c));
+    }
+    cands.push_back(Cand{i, c});
+  }
+  // derived bucket attributes, on the first relation holding the attribute
+  std::map<std::pair<int, int>, int> dattr;
+  for (auto& kv : thr) {
+    DerivedAttr D;
+    D.src = kv.first.first;
+    D.kind = kv.first.second;
+    D.thr.assign(kv.second.begin(), kv.second.end());
+    for (size_t r = 0; r < P.rels.size() && D.rel < 0; ++r)
+      if (P.rels[r].has(D.src)) D.rel = (int)r;
+    std::string name = P.attrs[D.src].name + (D.kind == 0 ? "#le" : "#lt");
+    if (P.attr_id.count(name)) fail(LMFAO_EINVAL, "attribute name " + name + " is reserved");
+    D.attr = (int)P.attrs.size();
+    P.attr_id[name] = D.attr;
+    P.attrs.push_back(AttrDef{name, LMFAO_I32, (int64_t)D.thr.size() + 1});
+    RelDef& R = P.rels[D.rel];
+    R.col[D.attr] = (int)R.attrs.size();
+    R.attrs.push_back(D.attr);
+    R.dtypes.push_back(LMFAO_I32);
+    R.is_key.push_back(0);
+    dattr[kv.first] = (int)P.derived.size();
+    P.derived.push_back(D);
+  }
+  // planned queries grouped by the bucket (or code) attribute, shared by
+  // every candidate with the same group-by and aggregates
+  std::map<std::tuple<std::vector<int>, std::vector<Mono>, int>, int> planned;
+  for (auto& cd : cands) {
+    const QueryDef& g = given[cd.q];
+    const Cond& c = cd.c;
+    int key_attr = c.attr;
+    int64_t nb = P.attrs[c.attr].domain;
+    UserQuery& U = P.user[cd.q];
+    U.range = true;
+    if (c.op == LMFAO_EQ || c.op == LMFAO_NE) {
+      const double v = c.c;
+      const bool integral = v == std::floor(v) && v >= 0 && v < (double)nb;
+      if (c.op == LMFAO_EQ) {
+        U.lo = integral ? (int64_t)v : 0;
+        U.hi = integral ? (int64_t)v + 1 : 0;
+      } else {
+        U.lo = 0;
+        U.hi = nb;
+        U.ex = integral ? (int64_t)v : -1;
+      }
+    } else {
+      const int kind = (c.op == LMFAO_LE || c.op == LMFAO_GT) ? 0 : 1;
+      const DerivedAttr& D = P.derived[dattr.at({c.attr, kind})];
+      key_attr = D.attr;
+      nb = (int64_t)D.thr.size() + 1;
+      const double t = cmp_value(P.attrs[c.attr], c.c);
+      const int64_t k = std::lower_bound(D.thr.begin(), D.thr.end(), t) - D.thr.begin();
+      // bucket b counts thresholds below (kind 0) or at most (kind 1) the
+      // value: x <= t_k (x < t_k) iff b <= k
+      const bool below = c.op == LMFAO_LE || c.op == LMFAO_LT;
+      U.lo = below ? 0 : k + 1;
+      U.hi = below ? k + 1 : nb;
+    }
+    U.nb = nb;
+    std::vector<int> gb = g.groupby;
+    gb.push_back(key_attr);
+    auto key = std::make_tuple(gb, g.aggs, g.root);
+    auto it = planned.find(key);
+    if (it == planned.end()) {
+      QueryDef q = g;
+      q.groupby = gb;
+      q.conds = common;
+      it = planned.emplace(key, (int)P.queries.size()).first;
+      P.queries.push_back(q);
+    }
+    U.internal = it->second;
   }
 }
 
@@ -515,10 +661,6 @@ static void view_layouts(Plan& P) {
         P.unsupported_reason = "a group-by attribute is carried through a view that is not "
                                "single-valued on its join key (multi-valued lookup)";
       }
-    }
-    if (!V.conds.empty()) {
-      P.supported = false;
-      P.unsupported_reason = "conditions are not executed on the GPU yet";
     }
   }
 }
@@ -1100,6 +1242,30 @@ static std::string describe(const Plan& P) {
       o << kv.second;
     }
     o << "]}";
+  }
+  static const char* ops[] = {"<=", "<", ">", ">=", "==", "!="};
+  o << std::setprecision(17);
+  o << "],\"filter\":[";
+  for (size_t i = 0; i < P.filter.size(); ++i) {
+    if (i) o << ",";
+    o << "[\"" << json_escape(P.attrs[P.filter[i].attr].name) << "\",\"" << ops[P.filter[i].op] << "\","
+      << P.filter[i].c << "]";
+  }
+  o << "],\"derived\":[";
+  for (size_t i = 0; i < P.derived.size(); ++i) {
+    const DerivedAttr& D = P.derived[i];
+    if (i) o << ",";
+    o << "{\"name\":\"" << json_escape(P.attrs[D.attr].name) << "\",\"source\":\""
+      << json_escape(P.attrs[D.src].name) << "\",\"relation\":\"" << json_escape(P.rels[D.rel].name)
+      << "\",\"kind\":" << D.kind << ",\"thresholds\":" << D.thr.size() << "}";
+  }
+  o << "],\"user_queries\":[";
+  for (size_t i = 0; i < P.user.size(); ++i) {
+    const UserQuery& U = P.user[i];
+    if (i) o << ",";
+    o << "{\"planned\":" << U.internal;
+    if (U.range) o << ",\"lo\":" << U.lo << ",\"hi\":" << U.hi << ",\"except\":" << U.ex;
+    o << "}";
   }
   o << "],\"views\":[";
   for (size_t i = 0; i < P.views.size(); ++i) {

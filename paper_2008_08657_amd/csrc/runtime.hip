@@ -65,7 +65,7 @@ struct NodeData {
 struct Step {
   std::string name;
   int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract (VALU), 5 merge, 6 image build,
-              // 7 contraction staging, 8 MFMA contraction, 9 block-major merge
+              // 7 contraction staging, 8 MFMA contraction, 9 block-major merge, 10 filter, 11 finalize
   int fast = 0;
   void* dev = nullptr;
   int64_t n = 0;
@@ -91,6 +91,11 @@ struct lmfao_prepared_s {
   lmfao::Plan* P = nullptr;
   bool f64 = true;
   std::vector<lmfao::OutBuf> qout, vout;
+  std::vector<lmfao::OutBuf> uout;                   // range queries of the caller's batch
+  std::vector<std::vector<const void*>> ecols;       // caller's columns, then derived bucket codes
+  std::vector<const void* const*> ecol_ptrs;
+  std::vector<int32_t*> w_raw, w_sorted;             // filter weights per relation (lazily built)
+  std::vector<char> w_raw_done, w_sorted_done;
   std::vector<lmfao::NodeData> nodes;
   std::vector<void*> allocs;
   std::vector<lmfao::Step> steps;   // the run, in launch order
@@ -450,6 +455,58 @@ static void build_contract_mfma(Prep& S, const GroupProgram& g, const std::strin
   S.steps.push_back(m);
 }
 
+// Filter weights of relation r (0/1 per row, raw or sorted row order) for the
+// batch-wide conditions on its attributes; null when none applies.  Built once
+// per prepared plan as a step of the run, ahead of its first consumer.
+static const int32_t* filter_weights(Prep& S, int r, bool sorted, const void* const* const* cols,
+                                     hipStream_t st) {
+  const Plan& P = *S.P;
+  auto& cache = sorted ? S.w_sorted : S.w_raw;
+  auto& done = sorted ? S.w_sorted_done : S.w_raw_done;
+  if (done[r]) return cache[r];
+  done[r] = 1;
+  const RelDef& R = P.rels[r];
+  DFilter f{};
+  f.n_rows = R.n_rows;
+  for (const Cond& c : P.filter) {
+    if (!R.has(c.attr)) continue;
+    if (f.n_conds >= kMaxFilterConds) throw PlanError{LMFAO_EUNSUPPORTED, "too many conditions on " + R.name};
+    const int col = R.col.at(c.attr);
+    const void* ptr;
+    if (sorted) {
+      NodeData& N = S.nodes[r];
+      if (!N.sorted_col[col]) {
+        if (!N.perm) throw PlanError{LMFAO_EINVAL, "internal: filter column without permutation"};
+        const int eb = dtype_bytes(R.dtypes[col]);
+        void* q = dalloc(S, (size_t)std::max<int64_t>(R.n_rows, 1) * eb);
+        if (R.n_rows > 0) launch_gather(cols[r][col], N.perm, q, R.n_rows, eb, st);
+        N.sorted_col[col] = q;
+      }
+      ptr = N.sorted_col[col];
+    } else {
+      ptr = raw_column(S, r, col, cols, st);
+    }
+    f.cols[f.n_conds] = DCol{ptr, R.dtypes[col], 0};
+    f.op[f.n_conds] = c.op;
+    f.c[f.n_conds] = c.c;
+    f.n_conds++;
+  }
+  if (f.n_conds == 0) return nullptr;
+  f.out = (int32_t*)dalloc(S, (size_t)std::max<int64_t>(R.n_rows, 1) * 4);
+  Step s;
+  s.name = "filter:" + R.name + (sorted ? ":sorted" : ":raw");
+  s.kind = 10;
+  s.dev = upload(S, f, st);
+  s.n = R.n_rows;
+  s.rows = R.n_rows;
+  s.alg_read = 0;
+  for (int k = 0; k < f.n_conds; ++k) s.alg_read += (double)R.n_rows * dtype_bytes(f.cols[k].dtype);
+  s.alg_write = (double)R.n_rows * 4;
+  S.steps.push_back(s);
+  cache[r] = f.out;
+  return f.out;
+}
+
 static void build_group(Prep& S, int gi, const void* const* const* cols, hipStream_t st) {
   Plan& P = *S.P;
   GroupDef& G = P.groups[gi];
@@ -464,6 +521,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     const ViewDef& V = P.views[vid];
     DViewBuild b{};
     b.n_rows = R.n_rows;
+    b.w = filter_weights(S, r, false, cols, st);
     std::vector<int> colpos;   // relation columns referenced
     auto cpos = [&](int c) {
       for (size_t i = 0; i < colpos.size(); ++i)
@@ -510,7 +568,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
       }
     }
     b.n_codes = (int)V.code_attrs.size();
-    if (b.n_codes > 8) throw PlanError{LMFAO_EUNSUPPORTED, "view with more than 8 codes"};
+    if (b.n_codes > kMaxOuterCodes) throw PlanError{LMFAO_EUNSUPPORTED, "view with more than 64 codes"};
     for (int s = 0; s < b.n_codes; ++s) {
       int a = V.code_attrs[s];
       if (R.has(a)) {
@@ -737,6 +795,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     // columns and pieces
     std::vector<int> need = scols;
     prepare_node(S, r, g.cut, need, cols, st);
+    d.w = filter_weights(S, r, true, cols, st);   // needs the sort permutation
     d.n_cols = (int)scols.size();
     for (int i = 0; i < d.n_cols; ++i) {
       d.cols[i].ptr = N.sorted_col[scols[i]];
@@ -952,6 +1011,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
   int64_t n_pieces;
   if (g.row_pieces) {
     n_pieces = R.n_rows;
+    c.w = filter_weights(S, r, false, cols, st);
     c.n_pcols = (int)pk.size();
     for (int i = 0; i < c.n_pcols; ++i) {
       c.pcols[i].ptr = raw_column(S, r, pk[i], cols, st);
@@ -1091,15 +1151,39 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
   }
 }
 
-static void prepare_all(Prep& S, const void* const* const* cols, hipStream_t st) {
+static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_t st) {
   Plan& P = *S.P;
   S.nodes.assign(P.rels.size(), NodeData{});
+  S.w_raw.assign(P.rels.size(), nullptr);
+  S.w_sorted.assign(P.rels.size(), nullptr);
+  S.w_raw_done.assign(P.rels.size(), 0);
+  S.w_sorted_done.assign(P.rels.size(), 0);
+  S.err_flag = (int32_t*)dalloc(S, 8);
+  HIP_OK(hipMemsetAsync(S.err_flag, 0, 8, st));
+  // the caller's columns, then the derived bucket codes of condition thresholds
+  S.ecols.assign(P.rels.size(), {});
+  S.ecol_ptrs.assign(P.rels.size(), nullptr);
+  for (size_t r = 0; r < P.rels.size(); ++r) {
+    const RelDef& R = P.rels[r];
+    S.ecols[r].assign(R.attrs.size(), nullptr);
+    for (int c = 0; c < R.n_input_attrs; ++c) S.ecols[r][c] = user_cols[r][c];
+  }
+  for (const DerivedAttr& D : P.derived) {
+    const RelDef& R = P.rels[D.rel];
+    const int sc = R.col.at(D.src), dc = R.col.at(D.attr);
+    if (R.n_rows > 0 && !S.ecols[D.rel][sc])
+      throw PlanError{LMFAO_EINVAL, "null column " + P.attrs[D.src].name + " of " + R.name};
+    int32_t* out = (int32_t*)dalloc(S, (size_t)std::max<int64_t>(R.n_rows, 1) * 4);
+    const double* thr = upload_vec(S, D.thr, st);
+    launch_bucketize(S.ecols[D.rel][sc], R.dtypes[sc], R.n_rows, thr, (int)D.thr.size(), D.kind, out, st);
+    S.ecols[D.rel][dc] = out;
+  }
+  for (size_t r = 0; r < P.rels.size(); ++r) S.ecol_ptrs[r] = S.ecols[r].data();
+  const void* const* const* cols = S.ecol_ptrs.data();
   for (size_t r = 0; r < P.rels.size(); ++r) {
     S.nodes[r].raw_col.assign(P.rels[r].attrs.size(), nullptr);
     S.nodes[r].raw_src.assign(cols[r], cols[r] + P.rels[r].attrs.size());
   }
-  S.err_flag = (int32_t*)dalloc(S, 8);
-  HIP_OK(hipMemsetAsync(S.err_flag, 0, 8, st));
   // validate integer columns against their domains
   for (size_t r = 0; r < P.rels.size(); ++r) {
     const RelDef& R = P.rels[r];
@@ -1142,6 +1226,18 @@ static void prepare_all(Prep& S, const void* const* const* cols, hipStream_t st)
     carve.push_back({(void**)&B.cnt, (size_t)B.n_rows * 8});
     carve.push_back({&B.vals, (size_t)B.n_rows * B.n_vals * 8});
   }
+  S.uout.resize(P.user.size());
+  for (size_t u = 0; u < P.user.size(); ++u) {
+    const UserQuery& U = P.user[u];
+    if (!U.range) continue;
+    const OutBuf& Q = S.qout[U.internal];
+    OutBuf& B = S.uout[u];
+    B.n_rows = Q.n_rows / U.nb;
+    B.f64 = true;
+    B.n_vals = Q.n_vals;
+    carve.push_back({(void**)&B.cnt, (size_t)B.n_rows * 8});
+    carve.push_back({&B.vals, (size_t)B.n_rows * B.n_vals * 8});
+  }
   size_t arena = 0;
   for (auto& c : carve) arena += (c.second + 255) & ~(size_t)255;
   char* base = (char*)dalloc(S, std::max<size_t>(arena, 256));
@@ -1157,6 +1253,34 @@ static void prepare_all(Prep& S, const void* const* const* cols, hipStream_t st)
   std::stable_sort(gorder.begin(), gorder.end(),
                    [&](int a, int b) { return P.groups[a].level < P.groups[b].level; });
   for (int gi : gorder) build_group(S, gi, cols, st);
+  // range queries: sums over the bucket ranges their conditions select
+  std::vector<DFinalize> fin;
+  for (size_t u = 0; u < P.user.size(); ++u) {
+    const UserQuery& U = P.user[u];
+    if (!U.range) continue;
+    const OutBuf& Q = S.qout[U.internal];
+    const OutBuf& B = S.uout[u];
+    DFinalize d{};
+    d.src_cnt = Q.cnt;
+    d.src_vals = (const double*)Q.vals;
+    d.dst_cnt = B.cnt;
+    d.dst_vals = (double*)B.vals;
+    d.n_rows = B.n_rows;
+    d.nb = U.nb;
+    d.n_vals = B.n_vals;
+    d.lo = U.lo;
+    d.hi = U.hi;
+    d.ex = U.ex;
+    fin.push_back(d);
+  }
+  if (!fin.empty()) {
+    Step s;
+    s.name = "finalize";
+    s.kind = 11;
+    s.dev = upload_vec(S, fin, st);
+    s.n = (int64_t)fin.size();
+    S.steps.push_back(s);
+  }
   HIP_OK(hipStreamSynchronize(st));
   for (auto& N : S.nodes)
     if (N.perm) {
@@ -1210,6 +1334,8 @@ static void enqueue_run(Prep& S, hipStream_t st) {
       case 9:
         launch_merge_bm((const DCell*)s.dev, s.n, s.part_f, s.n_blocks, s.NG, (int64_t)s.NF * s.NG, S.err_flag, st);
         break;
+      case 10: launch_filter((const DFilter*)s.dev, s.n, st); break;
+      case 11: launch_finalize((const DFinalize*)s.dev, (int)s.n, st); break;
     }
     if (t) {
       HIP_OK(hipEventRecord(S.ev[base + 2 * slot + 1], st));
@@ -1349,10 +1475,24 @@ lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, i
   return LMFAO_OK;
 }
 
+// the output buffer and group-by attributes of query q of the caller's batch
+static const OutBuf& user_out(const lmfao_prepared_s* prep, int q, int* n_keys) {
+  const Plan& P = *prep->P;
+  const UserQuery& U = P.user[q];
+  const int nk = (int)P.queries[U.internal].groupby.size();
+  if (U.range) {
+    *n_keys = nk - 1;   // the bucket attribute is the planned query's last key
+    return prep->uout[q];
+  }
+  *n_keys = nk;
+  return prep->qout[U.internal];
+}
+
 lmfao_status lmfao_result_shape(lmfao_prepared_t prep, int32_t q, int64_t* n_groups, int32_t* n_keys,
                                 int32_t* n_aggs) {
-  if (!prep || q < 0 || q >= (int)prep->qout.size()) return set_err(LMFAO_EINVAL, "bad query index");
-  const OutBuf& B = prep->qout[q];
+  if (!prep || q < 0 || q >= (int)prep->P->user.size()) return set_err(LMFAO_EINVAL, "bad query index");
+  int nk = 0;
+  const OutBuf& B = user_out(prep, q, &nk);
   std::vector<int64_t> cnt(B.n_rows);
   try {
     HIP_OK(hipDeviceSynchronize());
@@ -1363,16 +1503,17 @@ lmfao_status lmfao_result_shape(lmfao_prepared_t prep, int32_t q, int64_t* n_gro
   int64_t g = 0;
   for (int64_t c : cnt) g += c > 0;
   if (n_groups) *n_groups = g;
-  if (n_keys) *n_keys = (int32_t)prep->P->queries[q].groupby.size();
+  if (n_keys) *n_keys = nk;
   if (n_aggs) *n_aggs = B.n_vals;
   return LMFAO_OK;
 }
 
 lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, int64_t* counts, double* values) {
-  if (!prep || q < 0 || q >= (int)prep->qout.size()) return set_err(LMFAO_EINVAL, "bad query index");
+  if (!prep || q < 0 || q >= (int)prep->P->user.size()) return set_err(LMFAO_EINVAL, "bad query index");
   const Plan& P = *prep->P;
-  const QueryDef& Q = P.queries[q];
-  const OutBuf& B = prep->qout[q];
+  const QueryDef& Q = P.queries[P.user[q].internal];
+  int nk = 0;
+  const OutBuf& B = user_out(prep, q, &nk);
   std::vector<int64_t> cnt(B.n_rows);
   std::vector<double> vals((size_t)B.n_rows * B.n_vals);
   try {
@@ -1382,7 +1523,6 @@ lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, 
   } catch (const HipError& e) {
     return set_err(LMFAO_EHIP, e.msg);
   }
-  int nk = (int)Q.groupby.size();
   std::vector<int64_t> dom(nk);
   for (int i = 0; i < nk; ++i) dom[i] = P.attrs[Q.groupby[i]].domain;
   int64_t g = 0;
@@ -1483,9 +1623,9 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     if (s.kind == 0) continue;
     if (!first) j += ",";
     first = false;
-    static const char* kinds[] = {"fill", "view_build", "scan",  "table_reduce", "contract",
-                                  "merge", "image",      "stage", "gemm",         "merge"};
-    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 10, "one name per step kind");
+    static const char* kinds[] = {"fill",  "view_build", "scan", "table_reduce", "contract", "merge",
+                                  "image", "stage",      "gemm", "merge",        "filter",   "finalize"};
+    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 12, "one name per step kind");
     char tmp[512];
     snprintf(tmp, sizeof(tmp),
              "{\"name\":\"%s\",\"kind\":\"%s\",\"rows\":%lld,\"pieces\":%lld,\"alg_read_bytes\":%.0f,"

@@ -140,3 +140,50 @@ def test_repeat_runs_identical_counts(eng):
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x["keys"], y["keys"])
         np.testing.assert_array_equal(x["count"], y["count"])
+
+
+def _with_conditions(p, seed):
+    """A batch-wide filter (one condition per relation feature) plus one private
+    condition per query, of every operator."""
+    rng = np.random.default_rng(seed)
+    n_rel = len(p["schema"])
+    shared = [(f"x{i}", "<=" if i % 2 else ">", float(rng.normal(0, 0.8))) for i in range(1, n_rel)]
+    shared.append(("c0", "!=", int(rng.integers(0, 3))))
+    ops = ["<=", "<", ">", ">=", "==", "!="]
+    out = []
+    for k, q in enumerate(p["batch"]):
+        if len(q["groupby"]) > 1:
+            q = dict(q, groupby=q["groupby"][:1])
+        op = ops[k % len(ops)]
+        i = int(rng.integers(0, n_rel))
+        if op in ("==", "!="):
+            attr, const = f"c{i}", int(rng.integers(0, 3))
+        else:
+            attr, const = f"x{i}", float(rng.normal(0, 1))
+        if attr in q["groupby"]:
+            attr, const, op = f"x{i}", float(rng.normal(0, 1)), "<="
+        out.append(dict(q, where=shared + [(attr, op, const)]))
+        out.append(dict(q, where=list(shared)))
+    p["batch"] = out
+    return p
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_conditions(eng, seed):
+    p = _with_conditions(W.random_acyclic(500 + seed, n_rel=3, max_rows=400, max_dom=25, unique_dims=True,
+                                          n_queries=6), seed)
+    check(eng, p, F64_TOL, f"random_cond_{seed}", policy="fact")
+    # two inner group-by codes next to outer factors are outside the planned class at some seeds
+    check(eng, p, F64_TOL, f"random_cond_{seed}_scan", allow_unsupported=True, policy="fact", row_piece_max=-1,
+          min_segment=1)
+
+
+def test_cart_node_rows(eng):
+    # node condition as a filter, 840 thresholds as bucket group-bys; Inv small enough for row pieces
+    p = W.cart_node(seed=0, n_inv=20_000, n_locn=40, n_dates=12, n_ksn=300, n_weather_dates=15)
+    check(eng, p, F32_TOL, "cart_rows_f32", precision="f32", policy="fact")
+
+
+def test_cart_node_scan(eng):
+    p = W.cart_node(seed=1, n_inv=150_001, n_locn=50, n_dates=16, n_ksn=400, n_weather_dates=20)
+    check(eng, p, F32_TOL, "cart_scan_f32", precision="f32", policy="fact", row_piece_max=5_000, min_segment=16)

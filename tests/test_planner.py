@@ -162,3 +162,51 @@ def test_plan_json_roundtrip():
     d = plan(W.tiny_star(n_fact=100), policy="fact")
     assert json.loads(json.dumps(d)) == d
     assert d["supported"] is True
+
+
+def _cart_small(**kw):
+    return W.cart_node(seed=0, n_inv=2_000, n_locn=12, n_dates=6, n_ksn=50, n_weather_dates=8, **kw)
+
+
+def test_cart_candidates_become_bucket_group_bys():
+    p = _cart_small()
+    d = plan(p, precision="f32", policy="fact")
+    # the node condition is the batch-wide filter
+    assert sorted(c[0] for c in d["filter"]) == sorted(c[0] for c in p["node"])
+    # one derived bucket attribute per thresholded feature, in its owner relation
+    assert len(d["derived"]) == 42
+    owner = {a["name"]: r["name"] for r in p["schema"] for a in r["attrs"]}
+    for x in d["derived"]:
+        assert x["kind"] == 0 and x["thresholds"] <= 20 and x["relation"] == owner[x["source"]]
+    uq = d["user_queries"]
+    assert len(uq) == len(p["batch"]) == 2544
+    # X <= t_k selects buckets [0, k]: ranges of one feature's thresholds are nested
+    first = [u for u, q in zip(uq, p["batch"]) if len(q["where"]) > len(p["node"])
+             and q["where"][-1][0] == "i1" and q["aggs"] == [[]]]
+    his = [u["hi"] for u in first]
+    assert all(u["lo"] == 0 for u in first) and his == sorted(his)
+    # one planned query per (feature, statistic), shared by all its thresholds
+    assert len({u["planned"] for u in first}) == 1
+
+
+def test_condition_rewrite_ops():
+    p = W.tiny_star(n_fact=100)
+    base = {"groupby": [], "aggs": [[("units", 1)]], "root": None}
+    p["batch"] = [dict(base, where=[("f1", op, 0.25)]) for op in ("<=", "<", ">", ">=")]
+    p["batch"] += [dict(base, where=[("cat", op, 3)]) for op in ("==", "!=")]
+    d = plan(p, policy="fact")
+    uq = d["user_queries"]
+    assert [u["lo"] for u in uq[:4]] == [0, 0, 1, 1] and [u["hi"] for u in uq[:4]] == [1, 1, 2, 2]
+    assert (uq[4]["lo"], uq[4]["hi"], uq[4]["except"]) == (3, 4, -1)
+    assert (uq[5]["lo"], uq[5]["hi"], uq[5]["except"]) == (0, 20, 3)
+    assert sorted(x["kind"] for x in d["derived"]) == [0, 1]
+    assert d["filter"] == []
+
+
+def test_two_private_conditions_are_unsupported():
+    p = W.tiny_star(n_fact=100)
+    p["batch"] = [{"groupby": [], "aggs": [[]], "root": None, "where": [("f1", "<=", 0.0), ("g1", ">", 0.0)]},
+                  {"groupby": [], "aggs": [[]], "root": None, "where": []}]
+    with pytest.raises(E.LmfaoError) as ei:
+        E.Plan(p, policy="fact")
+    assert str(ei.value).startswith("EUNSUPPORTED")

@@ -31,7 +31,7 @@ import itertools
 import numpy as np
 
 __all__ = [
-    "zipf_keys", "tiny_star", "retail_snowflake", "grocery_star", "cart_node",
+    "zipf_keys", "tiny_star", "retail_snowflake", "grocery_star", "cart_node", "quantile_thresholds",
     "rkmeans_chain", "favorita_example", "random_acyclic", "covariance_batch",
     "problem_digest", "fact_prefix",
 ]
@@ -405,9 +405,57 @@ def problem_digest(problem: dict) -> str:
     return h.hexdigest()
 
 
-# remaining configurations are added as their hot-path rows are built
-def cart_node(*a, **k):  # pragma: no cover - placeholder until the CART row is built
-    raise NotImplementedError("CART node batch generator is not built yet")
+def quantile_thresholds(values, n_thr: int = 20):
+    """Split thresholds of a continuous feature: the data values at the
+    nearest-rank quantiles k/(n_thr+1), k = 1..n_thr, of its base column."""
+    v = np.sort(np.asarray(values))
+    n = len(v)
+    idx = np.ceil(np.arange(1, n_thr + 1) * n / (n_thr + 1)).astype(np.int64) - 1
+    return [float(x) for x in v[np.clip(idx, 0, n - 1)]]
+
+
+def cart_node(seed: int = 0, n_inv: int = 84_000_000, n_thr: int = 20, n_node_conds: int = 3,
+              label: str = "units", **retail_kw):
+    """One node of a regression tree grown by CART on the retail-shaped
+    snowflake (section 3, decision trees): for every split candidate the
+    statistics SUM(1), SUM(y), SUM(y^2) of y = units under the node's path
+    condition.  Candidates: X <= t for each of the 42 non-label continuous
+    features and its ``n_thr`` quantile thresholds, and a group-by on each
+    categorical attribute (the 6 one-hot categoricals and ksn) for = / !=
+    splits; plus the node totals.  The path condition is ``n_node_conds``
+    random conditions (continuous: <= or > one of its thresholds; categorical:
+    = or != a random code)."""
+    p = retail_snowflake(seed=seed, n_inv=n_inv, **retail_kw)
+    owner = {}
+    for r in p["schema"]:
+        for a in r["attrs"]:
+            owner.setdefault(a["name"], r["name"])
+    dom = {a["name"]: a["domain"] for r in p["schema"] for a in r["attrs"]}
+    cont = [x for x in (["units"] + [f"i{j}" for j in range(1, 6)] + [f"s{j}" for j in range(1, 15)]
+                        + [f"d{j}" for j in range(1, 16)] + [f"w{j}" for j in range(1, 9)]) if x != label]
+    cats = ["icat1", "icat2", "scat1", "scat2", "wcat1", "wcat2"]
+    thr = {x: quantile_thresholds(p["data"][owner[x]][x], n_thr) for x in cont}
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 4])))
+    node = []
+    for _ in range(n_node_conds):
+        k = int(rng.integers(0, len(cont) + len(cats)))
+        if k < len(cont):
+            x = cont[k]
+            node.append((x, "<=" if rng.random() < 0.5 else ">", thr[x][int(rng.integers(0, n_thr))]))
+        else:
+            c = cats[k - len(cont)]
+            node.append((c, "==" if rng.random() < 0.5 else "!=", int(rng.integers(0, dom[c]))))
+    stats = [[], [(label, 1)], [(label, 2)]]
+    batch = []
+    for x in cont:
+        for t in thr[x]:
+            batch += [{"groupby": [], "where": node + [(x, "<=", t)], "aggs": [a], "root": None} for a in stats]
+    for c in cats + ["ksn"]:
+        batch += [{"groupby": [c], "where": list(node), "aggs": [a], "root": None} for a in stats]
+    batch += [{"groupby": [], "where": list(node), "aggs": [a], "root": None} for a in stats]
+    p.update(name="cart_node", batch=batch, thresholds=thr, node=node)
+    return p
+
 
 
 def rkmeans_chain(*a, **k):  # pragma: no cover
