@@ -27,10 +27,11 @@ Steps, in order:
      the sum of absolute terms (used to bound cancellation when comparing
      against a float kernel); counts are exact int64.
 
-Everything is FP64 (or wider) as the paper fixes no precision.  Pins that tie
-this code to something other than itself live in ``tests/test_oracle_pins.py``
-(brute force over tuple combinations, closed forms, invariants, library special
-cases); the parity readings it relies on are listed in the design doc.
+Everything is FP64 (or wider) as the paper fixes no precision.  A condition's
+constant is compared in the column's own type (numpy's rule for a Python float
+against a float32 array).  Pins that tie this code to something other than
+itself live in ``tests/test_oracle_pins.py`` (brute force over tuple
+combinations, closed forms, invariants, library special cases).
 """
 from __future__ import annotations
 
