@@ -241,6 +241,34 @@ lmfao_status lmfao_run_timing(lmfao_prepared_t prep, int32_t cap, const char** n
  * lmfao_plan_describe. */
 lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t cap, size_t* need);
 
+/* Ridge linear regression over the batch's results (paper, section 3,
+ * "Linear Regression"): x = (1, continuous..., one-hot blocks of the
+ * categoricals over their whole domains); Sigma = sum over D of x x^T.
+ *
+ * lmfao_ridge_sigma assembles Sigma (dim x dim, row-major FP64, DEVICE
+ * buffer `sigma` owned by the caller) from the results of the last lmfao_run
+ * of `prep`: SUM(x_j*x_k) queries (intercept = SUM of the other factor or
+ * COUNT), per-categorical group-by sums and counts, and categorical-pair
+ * counts -- the queries of the covariance batch.  A query with a range
+ * condition of its own is not used.  With sigma == NULL only *dim_out is set
+ * (dim = 1 + n_cont + sum of the categorical domains, at most 2048).
+ * LMFAO_EINVAL if an attribute is unknown or the batch lacks an entry.
+ * Enqueued on `stream` and synchronised before returning.
+ *
+ * lmfao_ridge_bgd runs batch gradient descent on the free parameters (every
+ * index except `label`, whose parameter is fixed at -1):
+ *     theta_F <- theta_F - eta * (Sigma theta / |D| + lambda theta)_F,
+ * |D| = Sigma[0][0], theta starting at 0; it stops when ||grad_F||_2 <= tol
+ * or after max_iter steps.  eta <= 0 selects eta = 1/L, L the largest
+ * eigenvalue of Sigma_FF/|D| + lambda I by 100 power-iteration steps from the
+ * all-ones vector.  `sigma` and `theta` (dim doubles, written) are DEVICE
+ * pointers; `stats` is a HOST array of 3 doubles receiving {steps, final
+ * ||grad_F||, eta}.  All FP64, one workgroup, synchronised before return. */
+lmfao_status lmfao_ridge_sigma(lmfao_prepared_t prep, int32_t n_cont, const char* const* cont, int32_t n_cat,
+                               const char* const* cat, double* sigma, int32_t* dim_out, void* stream);
+lmfao_status lmfao_ridge_bgd(const double* sigma, int32_t dim, int32_t label, double lambda, double eta,
+                             int32_t max_iter, double tol, double* theta, double* stats, void* stream);
+
 void lmfao_plan_free(lmfao_plan_t plan);
 void lmfao_prepared_free(lmfao_prepared_t prep);
 

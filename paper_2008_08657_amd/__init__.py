@@ -4,7 +4,7 @@ The planner, runtime and HIP kernels live in the shared library
 ``liblmfao.so`` (C ABI: ``include/lmfao.h``); ``binding`` marshals Python
 descriptions of a schema, join tree and aggregate batch into that ABI.
 """
-from .binding import (LmfaoError, Plan, Prepared, device_columns, load_library,  # noqa: F401
+from .binding import (LmfaoError, Plan, Prepared, device_columns, load_library, ridge_bgd,  # noqa: F401
                       marshal_problem)
 
-__all__ = ["LmfaoError", "Plan", "Prepared", "device_columns", "load_library", "marshal_problem"]
+__all__ = ["LmfaoError", "Plan", "Prepared", "device_columns", "load_library", "marshal_problem", "ridge_bgd"]

@@ -311,11 +311,41 @@ class Prepared:
     def results(self):
         return [self.result(q) for q in range(len(self.plan.problem["batch"]))]
 
+    def ridge_sigma(self, continuous, categorical=()):
+        """Sigma = sum over D of x x^T assembled on the device from the last
+        run's results (``lmfao_ridge_sigma``); a (dim, dim) FP64 torch tensor."""
+        import torch
+        keep = _Keep()
+        cont = keep.arr(C.c_char_p, [keep.s(a) for a in continuous])
+        cats = keep.arr(C.c_char_p, [keep.s(a) for a in categorical])
+        dim = C.c_int32()
+        _check(self.lib, self.lib.lmfao_ridge_sigma(self.handle, len(continuous), cont, len(categorical), cats,
+                                                    None, C.byref(dim), self.stream))
+        sig = torch.empty((dim.value, dim.value), dtype=torch.float64, device="cuda")
+        _check(self.lib, self.lib.lmfao_ridge_sigma(self.handle, len(continuous), cont, len(categorical), cats,
+                                                    C.c_void_p(sig.data_ptr()), C.byref(dim), self.stream))
+        return sig
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
             self.lib.lmfao_prepared_free(h)
             self.handle = None
+
+
+def ridge_bgd(sigma, label: int, lam: float, eta: float = 0.0, max_iter: int = 20_000, tol: float = 1e-10,
+              stream=None):
+    """Batch gradient descent for ridge regression on a device Sigma
+    (``lmfao_ridge_bgd``).  Returns (theta tensor, steps, ||grad||, eta)."""
+    import torch
+    lib = load_library()
+    dim = int(sigma.shape[0])
+    theta = torch.empty(dim, dtype=torch.float64, device=sigma.device)
+    stats = (C.c_double * 3)()
+    _check(lib, lib.lmfao_ridge_bgd(C.c_void_p(sigma.data_ptr()), dim, int(label), C.c_double(lam),
+                                    C.c_double(eta), int(max_iter), C.c_double(tol),
+                                    C.c_void_p(theta.data_ptr()), stats, C.c_void_p(stream) if stream else None))
+    return theta, int(stats[0]), float(stats[1]), float(stats[2])
 
 
 def device_columns(problem, device="cuda:0"):

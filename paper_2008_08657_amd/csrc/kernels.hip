@@ -186,6 +186,113 @@ void launch_finalize(const DFinalize* d, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(n), dim3(256), 0, s, d);
 }
 
+static void allow_lds(const void* fn, int lds) {
+  if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+// ---------------------------------------------------------------------------
+// ridge regression (section 3, linear regression): the covariance matrix
+// from the batch's results, then batch gradient descent in FP64
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sigma_assemble(const DSigmaEntry* __restrict__ e, int64_t n,
+                                                        double* __restrict__ S, int dim) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = *e[i].src;
+    S[(int64_t)e[i].a * dim + e[i].b] = v;
+    S[(int64_t)e[i].b * dim + e[i].a] = v;
+  }
+}
+void launch_sigma_assemble(const DSigmaEntry* e, int64_t n, double* sigma, int dim, hipStream_t s) {
+  const int64_t cells = (int64_t)dim * dim;
+  launch_fill(sigma, cells * 8, s);
+  if (n <= 0) return;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_sigma_assemble, dim3(grid), dim3(256), 0, s, e, n, sigma, dim);
+}
+
+constexpr int kRidgeThreads = 1024;
+
+// fixed-order block sum (every thread gets the result)
+__device__ double block_sum(double x, double* red) {
+  red[threadIdx.x] = x;
+  __syncthreads();
+  for (int w = kRidgeThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// y_i = (Sigma_i. x)/n + lam x_i on the free entries (0 at the label)
+__device__ void ridge_apply(const double* S, int dim, int label, double inv_n, double lam, const double* x,
+                            double* y) {
+  for (int i = threadIdx.x; i < dim; i += kRidgeThreads) {
+    double acc = 0.0;
+    const double* row = S + (int64_t)i * dim;
+    for (int j = 0; j < dim; ++j) acc += row[j] * x[j];
+    y[i] = i == label ? 0.0 : acc * inv_n + lam * x[i];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kRidgeThreads) void k_ridge_bgd(const double* __restrict__ S, int dim, int label,
+                                                              double lam, double eta, int max_iter, double tol,
+                                                              double* __restrict__ theta, double* __restrict__ out) {
+  extern __shared__ double sm[];
+  double* th = sm;               // [dim]
+  double* g = th + dim;          // [dim]
+  double* red = g + dim;         // [kRidgeThreads]
+  const double inv_n = 1.0 / S[0];
+  if (eta <= 0.0) {
+    // power iteration on A = Sigma_FF/n + lam I from the all-ones vector
+    const double v0 = 1.0 / sqrt((double)(dim - 1));
+    for (int i = threadIdx.x; i < dim; i += kRidgeThreads) th[i] = i == label ? 0.0 : v0;
+    __syncthreads();
+    for (int it = 0; it < 100; ++it) {
+      ridge_apply(S, dim, label, inv_n, lam, th, g);
+      double p = 0.0;
+      for (int i = threadIdx.x; i < dim; i += kRidgeThreads) p += g[i] * g[i];
+      const double nrm = sqrt(block_sum(p, red));
+      for (int i = threadIdx.x; i < dim; i += kRidgeThreads) th[i] = g[i] / nrm;
+      __syncthreads();
+    }
+    ridge_apply(S, dim, label, inv_n, lam, th, g);
+    double p = 0.0;
+    for (int i = threadIdx.x; i < dim; i += kRidgeThreads) p += th[i] * g[i];
+    eta = 1.0 / block_sum(p, red);
+  }
+  for (int i = threadIdx.x; i < dim; i += kRidgeThreads) th[i] = i == label ? -1.0 : 0.0;
+  __syncthreads();
+  int steps = 0;
+  double gn = 0.0;
+  for (;;) {
+    ridge_apply(S, dim, label, inv_n, lam, th, g);
+    double p = 0.0;
+    for (int i = threadIdx.x; i < dim; i += kRidgeThreads) p += g[i] * g[i];
+    gn = sqrt(block_sum(p, red));
+    if (gn <= tol || steps >= max_iter) break;
+    for (int i = threadIdx.x; i < dim; i += kRidgeThreads)
+      if (i != label) th[i] -= eta * g[i];
+    __syncthreads();
+    ++steps;
+  }
+  for (int i = threadIdx.x; i < dim; i += kRidgeThreads) theta[i] = th[i];
+  if (threadIdx.x == 0) {
+    out[0] = (double)steps;
+    out[1] = gn;
+    out[2] = eta;
+  }
+}
+void launch_ridge_bgd(const double* sigma, int dim, int label, double lam, double eta, int max_iter, double tol,
+                      double* theta, double* out, hipStream_t s) {
+  const int lds = (2 * dim + kRidgeThreads) * 8;
+  allow_lds((const void*)&k_ridge_bgd, lds);
+  hipLaunchKernelGGL(k_ridge_bgd, dim3(1), dim3(kRidgeThreads), lds, s, sigma, dim, label, lam, eta, max_iter, tol,
+                     theta, out);
+}
+
 // ---------------------------------------------------------------------------
 // view build for single-valued subtrees
 // ---------------------------------------------------------------------------
@@ -740,9 +847,6 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(const DScan* __restric
     S->part_i[(int64_t)blockIdx.x * S->lds_tab_i + i] = tab_i[i];
 }
 
-static void allow_lds(const void* fn, int lds) {
-  if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-}
 
 // ---------------------------------------------------------------------------
 // lean scan: inner views read through per-key images

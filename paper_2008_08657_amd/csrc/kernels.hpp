@@ -71,6 +71,17 @@ void launch_filter(const DFilter* d, int64_t n_rows, hipStream_t s);
 void launch_bucketize(const void* src, int dtype, int64_t n, const double* thr, int n_thr, int kind, int32_t* out,
                       hipStream_t s);
 void launch_finalize(const DFinalize* d, int n, hipStream_t s);
+
+// covariance-matrix assembly entry: Sigma[a][b] = Sigma[b][a] = *src
+struct DSigmaEntry {
+  const double* src;
+  int32_t a, b;
+};
+void launch_sigma_assemble(const DSigmaEntry* e, int64_t n, double* sigma, int dim, hipStream_t s);
+// ridge batch gradient descent on Sigma (one workgroup); out = {steps, ||grad||, eta}
+void launch_ridge_bgd(const double* sigma, int dim, int label, double lam, double eta, int max_iter, double tol,
+                      double* theta, double* out, hipStream_t s);
+constexpr int kRidgeMaxDim = 2048;
 void launch_view_build(const DViewBuild* d, int64_t n_rows, bool f64, hipStream_t s);
 void launch_make_keys(const DKeyCols* d, uint64_t* keys, uint32_t* idx, int64_t n, hipStream_t s);
 void launch_sort(uint64_t* keys, uint32_t* idx, uint64_t* keys_tmp, uint32_t* idx_tmp, int64_t n, int bits,

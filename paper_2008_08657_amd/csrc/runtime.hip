@@ -1543,6 +1543,120 @@ lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, 
   return LMFAO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// ridge regression over the batch's results (section 3, linear regression)
+// ---------------------------------------------------------------------------
+lmfao_status lmfao_ridge_sigma(lmfao_prepared_t prep, int32_t n_cont, const char* const* cont, int32_t n_cat,
+                               const char* const* cat, double* sigma, int32_t* dim_out, void* stream) {
+  g_last_error.clear();
+  if (!prep || n_cont < 0 || n_cat < 0 || (n_cont && !cont) || (n_cat && !cat))
+    return set_err(LMFAO_EINVAL, "null argument");
+  const Plan& P = *prep->P;
+  auto lookup = [&](const char* nm, int& id) {
+    if (!nm) return false;
+    auto it = P.attr_id.find(nm);
+    if (it == P.attr_id.end()) return false;
+    id = it->second;
+    return true;
+  };
+  std::vector<int> ca(n_cont), ka(n_cat);
+  for (int i = 0; i < n_cont; ++i)
+    if (!lookup(cont[i], ca[i])) return set_err(LMFAO_EINVAL, "unknown continuous attribute");
+  std::vector<int64_t> off(n_cat);
+  int64_t dim = 1 + n_cont;
+  for (int i = 0; i < n_cat; ++i) {
+    if (!lookup(cat[i], ka[i]) || P.attrs[ka[i]].dtype != LMFAO_I32 || P.attrs[ka[i]].domain <= 0)
+      return set_err(LMFAO_EINVAL, "categorical attribute unknown or without a domain");
+    off[i] = dim;
+    dim += P.attrs[ka[i]].domain;
+  }
+  if (dim > kRidgeMaxDim) return set_err(LMFAO_EUNSUPPORTED, "covariance matrix larger than 2048 x 2048");
+  if (dim_out) *dim_out = (int32_t)dim;
+  if (!sigma) return LMFAO_OK;
+  // (group-by attributes, monomial) -> output values of a planned query without a range
+  std::map<std::pair<std::vector<int>, Mono>, std::pair<const OutBuf*, int>> have;
+  for (size_t u = 0; u < P.user.size(); ++u) {
+    if (P.user[u].range) continue;
+    const QueryDef& Q = P.queries[P.user[u].internal];
+    for (size_t k = 0; k < Q.aggs.size(); ++k)
+      have.emplace(std::make_pair(Q.groupby, Q.aggs[k]), std::make_pair(&prep->qout[P.user[u].internal], (int)k));
+  }
+  std::vector<DSigmaEntry> ent;
+  std::string missing;
+  auto find = [&](std::vector<int> gb, Mono m, int64_t row, int a, int b) {
+    std::sort(m.begin(), m.end());
+    auto it = have.find({gb, m});
+    if (it == have.end()) {
+      missing = "the batch has no query for a covariance entry";
+      return;
+    }
+    const OutBuf* B = it->second.first;
+    ent.push_back(DSigmaEntry{(const double*)B->vals + row * B->n_vals + it->second.second, a, b});
+  };
+  // continuous block, the intercept first
+  for (int i = 0; i <= n_cont; ++i)
+    for (int j = i; j <= n_cont; ++j) {
+      Mono m;
+      if (i) m.push_back(ca[i - 1]);
+      if (j) m.push_back(ca[j - 1]);
+      find({}, m, 0, i, j);
+    }
+  for (int c = 0; c < n_cat; ++c) {
+    const int64_t dc = P.attrs[ka[c]].domain;
+    for (int64_t v = 0; v < dc; ++v) {
+      for (int i = 0; i <= n_cont; ++i) {
+        Mono m;
+        if (i) m.push_back(ca[i - 1]);
+        find({ka[c]}, m, v, (int)(off[c] + v), i);
+      }
+      find({ka[c]}, {}, v, (int)(off[c] + v), (int)(off[c] + v));
+    }
+    for (int c2 = c + 1; c2 < n_cat; ++c2) {
+      const int64_t d2 = P.attrs[ka[c2]].domain;
+      const bool fwd = have.count({{ka[c], ka[c2]}, Mono{}}) != 0;
+      for (int64_t v = 0; v < dc; ++v)
+        for (int64_t w = 0; w < d2; ++w) {
+          if (fwd) find({ka[c], ka[c2]}, {}, v * d2 + w, (int)(off[c] + v), (int)(off[c2] + w));
+          else find({ka[c2], ka[c]}, {}, w * dc + v, (int)(off[c] + v), (int)(off[c2] + w));
+        }
+    }
+  }
+  if (!missing.empty()) return set_err(LMFAO_EINVAL, missing);
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    DSigmaEntry* d = nullptr;
+    HIP_OK(hipMalloc(&d, std::max<size_t>(1, ent.size()) * sizeof(DSigmaEntry)));
+    HIP_OK(hipMemcpyAsync(d, ent.data(), ent.size() * sizeof(DSigmaEntry), hipMemcpyHostToDevice, st));
+    launch_sigma_assemble(d, (int64_t)ent.size(), sigma, (int)dim, st);
+    HIP_OK(hipStreamSynchronize(st));
+    HIP_OK(hipFree(d));
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_ridge_bgd(const double* sigma, int32_t dim, int32_t label, double lambda, double eta,
+                             int32_t max_iter, double tol, double* theta, double* stats, void* stream) {
+  g_last_error.clear();
+  if (!sigma || !theta || !stats) return set_err(LMFAO_EINVAL, "null argument");
+  if (dim < 2 || dim > kRidgeMaxDim || label < 0 || label >= dim || max_iter < 0 || !(lambda >= 0))
+    return set_err(LMFAO_EINVAL, "bad dimension, label, iteration count or lambda");
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    double* out = nullptr;
+    HIP_OK(hipMalloc(&out, 3 * sizeof(double)));
+    launch_ridge_bgd(sigma, dim, label, lambda, eta, max_iter, tol, theta, out, st);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(stats, out, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    HIP_OK(hipFree(out));
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
 lmfao_status lmfao_view_shape(lmfao_prepared_t prep, int32_t v, int64_t* n_keys, int32_t* n_vals,
                               int32_t* n_codes) {
   if (!prep || v < 0 || v >= (int)prep->vout.size()) return set_err(LMFAO_EINVAL, "bad view index");
