@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=150_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--form", default="fused", choices=["fused", "per_view"],
+                    help="fused: one pass per group of outputs (the method); per_view: one pass per output")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
@@ -78,7 +80,7 @@ def main():
     n_aggs = sum(len(q["aggs"]) for q in problem["batch"])
     t_gen = time.perf_counter() - t_gen
 
-    plan = E.Plan(problem, precision=precision, policy=problem["policy"])
+    plan = E.Plan(problem, precision=precision, policy=problem["policy"], form=args.form)
     cols = E.device_columns(problem)
     torch.cuda.synchronize()
     t_prep = time.perf_counter()
@@ -149,7 +151,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "join_tuples": n_join, "aggregates": n_aggs,
                    "queries": len(problem["batch"]), "precision": precision,
-                   "form": "fused", "root_policy": problem["policy"], "seed": 0,
+                   "form": args.form, "root_policy": problem["policy"], "seed": 0,
                    "prepare_s": round(t_prep, 2), "generate_s": round(t_gen, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,

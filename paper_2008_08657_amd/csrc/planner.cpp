@@ -560,8 +560,12 @@ static void generate_views(Plan& P) {
   }
   // groups: outputs leaving the same node at the same dependency level
   std::map<std::pair<int, int>, int> gidx;
+  // fused form: the outputs leaving a node at a level share one pass;
+  // per-view form: every output is computed by a pass of its own
+  const bool per_view = P.opts.form == LMFAO_FORM_PER_VIEW;
+  int solo = 0;
   auto group_of = [&](int node, int level) {
-    auto k = std::make_pair(level, node);
+    auto k = std::make_pair(level, per_view ? -1 - solo++ * (int)P.rels.size() - node : node);
     auto it = gidx.find(k);
     if (it != gidx.end()) return it->second;
     int id = (int)P.groups.size();
@@ -599,7 +603,7 @@ static void generate_views(Plan& P) {
   compute_deps();
   // one scan per relation where possible: two groups of the same node with no
   // dependency path between them become one group (no cycle can arise)
-  for (bool merged = true; merged;) {
+  for (bool merged = !per_view; merged;) {
     merged = false;
     int ng = (int)P.groups.size();
     std::vector<std::vector<char>> reach(ng, std::vector<char>(ng, 0));

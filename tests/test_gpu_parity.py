@@ -187,3 +187,12 @@ def test_cart_node_rows(eng):
 def test_cart_node_scan(eng):
     p = W.cart_node(seed=1, n_inv=150_001, n_locn=50, n_dates=16, n_ksn=400, n_weather_dates=20)
     check(eng, p, F32_TOL, "cart_scan_f32", precision="f32", policy="fact", row_piece_max=5_000, min_segment=16)
+
+
+@pytest.mark.parametrize("form", ["fused", "per_view"])
+def test_forms_agree(eng, form):
+    # the plain per-view form (one pass per output) and the fused form give the same results
+    p = W.retail_snowflake(seed=2, n_inv=80_000, n_locn=30, n_dates=10, n_ksn=250, n_weather_dates=12)
+    p["batch"] = p["batch"][::7]
+    check(eng, p, F32_TOL, f"retail_{form}", precision="f32", policy="fact", form=form, row_piece_max=5_000,
+          min_segment=16)

@@ -210,3 +210,13 @@ def test_two_private_conditions_are_unsupported():
     with pytest.raises(E.LmfaoError) as ei:
         E.Plan(p, policy="fact")
     assert str(ei.value).startswith("EUNSUPPORTED")
+
+
+def test_per_view_form_has_one_output_per_group():
+    p = W.favorita_example()
+    fused = plan(p, policy="groupby")
+    solo = plan(p, policy="groupby", form="per_view")
+    assert len(fused["groups"]) == 7
+    assert all(len(g["outputs"]) == 1 for g in solo["groups"])
+    n_out = len(solo["views"]) + len(solo["queries"])
+    assert len(solo["groups"]) == n_out == 9
