@@ -161,6 +161,10 @@ typedef struct {
                             contracted row by row without a scan
                             (0 = default 2^16; -1 = always scan)             */
   int32_t contraction;   /* LMFAO_CONTRACT_* (0 = matrix cores)              */
+  int32_t codegen;       /* 0: scans of the lean class are generated per
+                            group and compiled with hipRTC at prepare time
+                            (falls back to the built-in kernel if that
+                            fails); 1: built-in kernels only               */
 } lmfao_options;
 
 typedef struct lmfao_plan_s* lmfao_plan_t;
@@ -240,6 +244,11 @@ lmfao_status lmfao_run_timing(lmfao_prepared_t prep, int32_t cap, const char** n
  * the bytes zero-filled at the start of each run.  Same buffer convention as
  * lmfao_plan_describe. */
 lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t cap, size_t* need);
+/* Source of the i-th scan kernel generated for this prepared plan (section 2,
+ * code generation layer: code specialised to one group's plan), first line the
+ * group's name; the count is "generated_scans" in lmfao_prepared_describe.
+ * Same buffer convention as lmfao_plan_describe; LMFAO_EINVAL for a bad i. */
+lmfao_status lmfao_prepared_kernel_source(lmfao_prepared_t prep, int32_t i, char* buf, size_t cap, size_t* need);
 
 /* Ridge linear regression over the batch's results (paper, section 3,
  * "Linear Regression"): x = (1, continuous..., one-hot blocks of the

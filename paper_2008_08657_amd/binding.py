@@ -72,7 +72,7 @@ class lmfao_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("form", C.c_int32), ("root_policy", C.c_int32),
                 ("n_order", C.POINTER(C.c_int32)), ("order", C.POINTER(C.POINTER(C.c_char_p))),
                 ("min_segment", C.c_int32), ("row_piece_max", C.c_int64),
-                ("contraction", C.c_int32)]
+                ("contraction", C.c_int32), ("codegen", C.c_int32)]
 
 
 class LmfaoError(RuntimeError):
@@ -192,7 +192,7 @@ class Plan:
     """A plan handle (``lmfao_plan``)."""
 
     def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
-                 min_segment=0, row_piece_max=0, contraction="mfma"):
+                 min_segment=0, row_piece_max=0, contraction="mfma", codegen=True):
         self.lib = load_library()
         self.problem = problem
         keep = _Keep()
@@ -208,6 +208,7 @@ class Plan:
         if contraction not in ("mfma", "valu"):
             raise ValueError(f"contraction must be 'mfma' or 'valu', not {contraction!r}")
         opts.contraction = 0 if contraction == "mfma" else 1
+        opts.codegen = 0 if codegen else 1
         if order:
             names = [r["name"] for r in problem["schema"]]
             n_order = [len(order.get(n, [])) for n in names]
@@ -310,6 +311,17 @@ class Prepared:
 
     def results(self):
         return [self.result(q) for q in range(len(self.plan.problem["batch"]))]
+
+    def kernel_sources(self):
+        """Sources of the scan kernels generated for this plan."""
+        out = []
+        for i in range(self.describe().get("generated_scans", 0)):
+            need = C.c_size_t()
+            _check(self.lib, self.lib.lmfao_prepared_kernel_source(self.handle, i, None, 0, C.byref(need)))
+            buf = C.create_string_buffer(need.value)
+            _check(self.lib, self.lib.lmfao_prepared_kernel_source(self.handle, i, buf, need.value, C.byref(need)))
+            out.append(buf.value.decode())
+        return out
 
     def ridge_sigma(self, continuous, categorical=()):
         """Sigma = sum over D of x x^T assembled on the device from the last

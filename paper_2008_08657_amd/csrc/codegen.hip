@@ -1,0 +1,359 @@
+// Code generation of scan kernels specialised to one group's program.
+//
+// The paper's engine compiles the multi-output plan of every group into code
+// specialised to the schema and the join tree (section 2, code generation
+// layer).  This is the GPU form of that step: from a lean scan descriptor
+// (one pass over the sorted relation: per-row factor columns, up to two
+// inner view images, the monomials of the inner factors, code histograms,
+// direct count tables) it emits HIP source whose loops over factors, masks,
+// histograms and tables are unrolled into straight-line code with every
+// offset, stride and mask a literal, compiles it with hipRTC for gfx950 and
+// caches the function by source text for the life of the process.  The
+// kernel computes exactly what the generic lean scan computes.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "codegen.hpp"
+
+namespace lmfao {
+
+namespace {
+
+constexpr int kGenWaves = 8;   // wavefronts per workgroup
+
+struct Emit {
+  std::ostringstream o;
+  template <typename X>
+  Emit& operator<<(const X& x) {
+    o << x;
+    return *this;
+  }
+};
+
+std::string hex64(uint64_t v) {
+  char b[32];
+  snprintf(b, sizeof b, "0x%llxull", (unsigned long long)v);
+  return b;
+}
+
+// value of multiplicity mask m (0..3) in the generated code
+std::string mu(int m) { return "mu" + std::to_string(m); }
+
+}  // namespace
+
+bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::string& why) {
+  const DFast& F = d.F;
+  if (!d.fast) {
+    why = "not a lean scan";
+    return false;
+  }
+  const char* T = f64 ? "double" : "float";
+  const int s = f64 ? 2 : 1;                       // dwords per factor slot in an image
+  const int code_off = NA * s, cnt_off = code_off + 4;
+  const int W = ((cnt_off + 1) + 3) & ~3;
+  const int tsz = f64 ? 8 : 4;
+  std::vector<uint64_t> args;
+  auto arg = [&](uint64_t v) {
+    args.push_back(v);
+    return (int)args.size() - 1;
+  };
+  Emit e;
+  e << "// generated scan kernel\n";
+  e << "typedef " << T << " T;\n";
+  e << "__device__ __forceinline__ T wsum(T x) {\n"
+       "  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);\n  return x;\n}\n";
+  e << "__device__ __forceinline__ int wsumi(int x) {\n"
+       "  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);\n  return x;\n}\n";
+  if (f64) {
+    // TwoSum butterfly: every combining add is error-free transformed
+    e << "__device__ __forceinline__ double wsumc(double s) {\n"
+         "  double c = 0.0;\n"
+         "  for (int o = 32; o > 0; o >>= 1) {\n"
+         "    double s2 = __shfl_xor(s, o, 64), c2 = __shfl_xor(c, o, 64);\n"
+         "    double t = s + s2, bb = t - s, er = (s - (t - bb)) + (s2 - bb);\n"
+         "    s = t; c = c + c2 + er;\n  }\n  return s + c;\n}\n";
+  } else {
+    e << "__device__ __forceinline__ float wsumc(float s) { return wsum(s); }\n";
+  }
+  e << "extern \"C\" __global__ __launch_bounds__(" << kGenWaves * 64
+    << ") void lmfao_gen_scan(const unsigned long long* __restrict__ A) {\n";
+  e << "  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];\n";
+  e << "  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;\n";
+  // arguments
+  e << "  const long long* __restrict__ piece_begin = (const long long*)A[" << arg((uint64_t)d.piece_begin) << "];\n";
+  e << "  const int* __restrict__ item_piece = (const int*)A[" << arg((uint64_t)d.item_piece) << "];\n";
+  e << "  const int n_items = (int)A[" << arg((uint64_t)d.n_items) << "];\n";
+  e << "  T* __restrict__ psi_f = (T*)A[" << arg((uint64_t)d.psi_f) << "];\n";
+  e << "  int* __restrict__ psi_i = (int*)A[" << arg((uint64_t)d.psi_i) << "];\n";
+  std::vector<int> fcol_arg(NA, -1);
+  for (int a = 0; a < NA; ++a)
+    if (F.fcol[a]) {
+      fcol_arg[a] = arg((uint64_t)F.fcol[a]);
+      e << "  const T* __restrict__ fc" << a << " = (const T*)A[" << fcol_arg[a] << "];\n";
+    }
+  for (int c = 0; c < 4; ++c)
+    if (F.ccol[c]) e << "  const int* __restrict__ cc" << c << " = (const int*)A[" << arg((uint64_t)F.ccol[c]) << "];\n";
+  for (int v = 0; v < 2; ++v) {
+    if (!F.img[v]) continue;
+    e << "  const uint4* __restrict__ img" << v << " = (const uint4*)A[" << arg((uint64_t)F.img[v]) << "];\n";
+    for (int k = 0; k < 2; ++k)
+      if (F.kcol[v][k])
+        e << "  const int* __restrict__ kc" << v << k << " = (const int*)A[" << arg((uint64_t)F.kcol[v][k]) << "];\n";
+  }
+  if (d.w) e << "  const int* __restrict__ wf = (const int*)A[" << arg((uint64_t)d.w) << "];\n";
+  const bool has_mu_out = d.mu_out_views > 0;
+  if (has_mu_out) {
+    e << "  const int* __restrict__ pkey = (const int*)A[" << arg((uint64_t)d.piece_key) << "];\n";
+    for (int v = 0; v < d.mu_out_views; ++v)
+      e << "  const long long* __restrict__ ov" << v << " = (const long long*)A["
+        << arg((uint64_t)d.outer_views[v].cnt) << "];\n";
+  }
+  bool any_global_tab = false;
+  for (int t = 0; t < F.n_tab; ++t)
+    if (!F.tab_lds[t]) {
+      any_global_tab = true;
+      e << "  unsigned long long* __restrict__ tab" << t << " = (unsigned long long*)A[" << arg((uint64_t)F.tab_cnt[t])
+        << "];\n";
+    }
+  (void)any_global_tab;
+  if (d.lds_tab_i > 0) e << "  int* __restrict__ part_i = (int*)A[" << arg((uint64_t)d.part_i) << "];\n";
+
+  // LDS: count tables (block), then a histogram area per wavefront
+  const int tab_bytes = (d.lds_tab_i * 4 + 15) & ~15;
+  const int hist_i_bytes = (d.hist_i_bins * 4 + 7) & ~7;
+  const int hist_bytes = hist_i_bytes + d.hist_f_bins * tsz;
+  const int wave_stride = (hist_bytes + 15) & ~15;
+  const int lds = tab_bytes + kGenWaves * wave_stride;
+  if (lds > 65536) {
+    why = "generated scan would need more than 64 KB of LDS";
+    return false;
+  }
+  e << "  int* tab_i = (int*)smem;\n";
+  e << "  int* hist_i = (int*)(smem + " << tab_bytes << " + wid * " << wave_stride << ");\n";
+  e << "  T* hist_f = (T*)((unsigned char*)hist_i + " << hist_i_bytes << ");\n";
+  if (d.lds_tab_i > 0) {
+    e << "  for (int i = threadIdx.x; i < " << d.lds_tab_i << "; i += " << kGenWaves * 64 << ") tab_i[i] = 0;\n";
+  }
+  e << "  __syncthreads();\n";
+
+  // row loader: factor columns, code columns, image keys, filter weight
+  auto emit_load = [&](const char* pre, const char* row) {
+    for (int a = 0; a < NA; ++a)
+      if (F.fcol[a]) e << "      " << pre << "f" << a << " = fc" << a << "[" << row << "];\n";
+    for (int c = 0; c < 4; ++c)
+      if (F.ccol[c]) e << "      " << pre << "c" << c << " = cc" << c << "[" << row << "];\n";
+    for (int v = 0; v < 2; ++v) {
+      if (!F.img[v]) continue;
+      e << "      " << pre << "k" << v << " = kc" << v << "0[" << row << "] * " << F.kmul[v][0];
+      if (F.kcol[v][1]) e << " + kc" << v << "1[" << row << "] * " << F.kmul[v][1];
+      e << ";\n";
+    }
+    if (d.w) e << "      " << pre << "w = wf[" << row << "];\n";
+  };
+  auto emit_decl = [&](const char* pre) {
+    for (int a = 0; a < NA; ++a)
+      if (F.fcol[a]) e << "      T " << pre << "f" << a << ";\n";
+    for (int c = 0; c < 4; ++c)
+      if (F.ccol[c]) e << "      int " << pre << "c" << c << ";\n";
+    for (int v = 0; v < 2; ++v)
+      if (F.img[v]) e << "      int " << pre << "k" << v << ";\n";
+    if (d.w) e << "      int " << pre << "w;\n";
+  };
+
+  // needed monomials: triangle index t(i, j) over the extended factors (0 = 1)
+  auto tri = [&](int i, int j) { return i * (NA + 1) - i * (i - 1) / 2 + (j - i); };
+  std::vector<std::pair<int, int>> terms;   // (i, j) of each needed entry, in triangle order
+  for (int i = 0; i <= NA; ++i)
+    for (int j = i; j <= NA; ++j) {
+      const int t = tri(i, j);
+      if (t > 0 && ((d.pf_need >> t) & 1ull)) terms.push_back({i, j});
+    }
+  const int n_masks = d.n_masks;
+
+  e << "  for (int item = blockIdx.x * " << kGenWaves << " + wid; item < n_items; item += gridDim.x * " << kGenWaves
+    << ") {\n";
+  e << "    const int p0 = item_piece[item], p1 = item_piece[item + 1];\n";
+  e << "    for (int p = p0; p < p1; ++p) {\n";
+  e << "      const int rb = (int)piece_begin[p], re = (int)piece_begin[p + 1];\n";
+  if (has_mu_out) {
+    e << "      int mu_out = 1;\n";
+    for (int v = 0; v < d.mu_out_views; ++v) {
+      const DView& V = d.outer_views[v];
+      e << "      { long long vr = 0;\n";
+      for (int k = 0; k < V.nkey; ++k)
+        e << "        vr += (long long)pkey[" << (int64_t)V.key_src[k] * d.n_pieces << "ll + p] * " << V.key_stride[k]
+          << "ll;\n";
+      e << "        mu_out *= (int)ov" << v << "[vr]; }\n";
+    }
+  }
+  if (d.hist_i_bins > 0) e << "      for (int i = lane; i < " << d.hist_i_bins << "; i += 64) hist_i[i] = 0;\n";
+  if (d.hist_f_bins > 0) e << "      for (int i = lane; i < " << d.hist_f_bins << "; i += 64) hist_f[i] = (T)0;\n";
+  e << "      __builtin_amdgcn_wave_barrier();\n";
+  for (size_t k = 0; k < terms.size(); ++k) e << "      T acc" << k << " = (T)0;\n";
+  for (int k = 0; k < d.n_pi; ++k) e << "      int cnt" << k << " = 0;\n";
+  emit_decl("n");
+  e << "      {\n        const int r = rb + lane < re ? rb + lane : rb;\n";
+  emit_load("n", "r");
+  e << "      }\n";
+  e << "      for (int r0 = rb; r0 < re; r0 += 64) {\n";
+  e << "        const int r = r0 + lane;\n        const bool valid = r < re;\n";
+  // current row values = prefetched ones
+  for (int a = 0; a < NA; ++a)
+    if (F.fcol[a]) e << "        const T cf" << a << " = nf" << a << ";\n";
+  for (int c = 0; c < 4; ++c)
+    if (F.ccol[c]) e << "        const int cc_" << c << " = nc" << c << ";\n";
+  for (int v = 0; v < 2; ++v)
+    if (F.img[v]) e << "        const int ck" << v << " = nk" << v << ";\n";
+  if (d.w) e << "        const int cw = nw;\n";
+  e << "        if (r0 + 64 < re) {\n          const int rn = r + 64 < re ? r + 64 : rb;\n";
+  emit_load("  n", "rn");
+  e << "        }\n";
+  // factor values: a0 = 1, column part + image parts
+  e << "        const T a0 = (T)1;\n";
+  for (int a = 0; a < NA; ++a) e << "        T a" << a + 1 << " = " << (F.fcol[a] ? "cf" + std::to_string(a) : "(T)0") << ";\n";
+  for (int c = 0; c < 4; ++c) e << "        int c" << c << " = " << (F.ccol[c] ? "cc_" + std::to_string(c) : "0") << ";\n";
+  e << "        const int wv = valid ? " << (d.w ? "cw" : "1") << " : 0;\n";
+  for (int m = 0; m < 4; ++m) e << "        int " << mu(m) << " = wv;\n";
+  for (int v = 0; v < 2; ++v) {
+    if (!F.img[v]) continue;
+    e << "        {\n          const uint4* q = img" << v << " + (long long)ck" << v << " * " << W / 4 << ";\n";
+    for (int j = 0; j < W / 4; ++j) e << "          const uint4 x" << j << " = q[" << j << "];\n";
+    auto dw = [&](int i) {
+      static const char* comp[] = {"x", "y", "z", "w"};
+      return "x" + std::to_string(i / 4) + "." + comp[i % 4];
+    };
+    for (int a = 0; a < NA; ++a) {
+      if (f64)
+        e << "          a" << a + 1 << " += __longlong_as_double((long long)(((unsigned long long)" << dw(2 * a + 1)
+          << " << 32) | " << dw(2 * a) << "));\n";
+      else
+        e << "          a" << a + 1 << " += __uint_as_float(" << dw(a) << ");\n";
+    }
+    for (int c = 0; c < 4; ++c) e << "          c" << c << " += (int)" << dw(code_off + c) << ";\n";
+    e << "          const int vc = valid ? (int)" << dw(cnt_off) << " : 0;\n";
+    for (int m = 0; m < n_masks; ++m)
+      if (d.masks[m] & (1u << v)) e << "          " << mu(m) << " *= vc;\n";
+    e << "        }\n";
+  }
+  // monomials (one multiplicity mask for all of them)
+  if (!terms.empty()) {
+    e << "        const T mt = (T)" << mu(d.pf_mask_idx) << ";\n";
+    std::vector<char> xi(NA + 1, 0);
+    for (auto& ij : terms) xi[ij.first] = 1;
+    for (int i = 0; i <= NA; ++i)
+      if (xi[i]) e << "        const T x" << i << " = mt * a" << i << ";\n";
+    for (size_t k = 0; k < terms.size(); ++k)
+      e << "        acc" << k << " += x" << terms[k].first << " * a" << terms[k].second << ";\n";
+  }
+  for (int k = 0; k < d.n_pi; ++k) e << "        cnt" << k << " += " << mu(d.pi_mask_idx[k]) << ";\n";
+  // histograms
+  for (int h = 0; h < F.n_hist; ++h) {
+    const uint32_t w = F.hword[h];
+    const int code = (int)(w & 3u), m = (int)((w >> 2) & 3u), off = (int)(w >> 13);
+    if ((w >> 4) & 1u) {
+      const int ai = (int)((w >> 5) & 15u), aj = (int)((w >> 9) & 15u);
+      e << "        if (" << mu(m) << ") atomicAdd(&hist_f[" << off << " + c" << code << "], (T)" << mu(m) << " * a" << ai
+        << " * a" << aj << ");\n";
+    } else {
+      e << "        if (" << mu(m) << ") atomicAdd(&hist_i[" << off << " + c" << code << "], " << mu(m) << ");\n";
+    }
+  }
+  // direct count tables
+  for (int t = 0; t < F.n_tab; ++t) {
+    e << "        {\n          const int row = 0";
+    for (int k = 0; k < F.tab_ncode[t]; ++k) e << " + c" << F.tab_code[t][k] << " * " << F.tab_stride[t][k];
+    e << ";\n          const int m = " << (has_mu_out ? "mu_out * " : "") << mu(F.tab_mask[t]) << ";\n";
+    if (F.tab_lds[t])
+      e << "          if (m) atomicAdd(&tab_i[" << F.tab_off[t] << " + row], m);\n";
+    else
+      e << "          if (m) atomicAdd(&tab" << t << "[row], (unsigned long long)(long long)m);\n";
+    e << "        }\n";
+  }
+  e << "      }\n";
+  // close the piece
+  e << "      T* prow = psi_f + (long long)p * " << d.psi_f_stride << ";\n";
+  e << "      int* irow = psi_i + (long long)p * " << d.psi_i_stride << ";\n";
+  for (size_t k = 0; k < terms.size(); ++k) {
+    const int t = tri(terms[k].first, terms[k].second);
+    e << "      { const T sm = wsumc(acc" << k << "); if (lane == 0) prow[" << d.pf_slot[t] << "] = sm; }\n";
+  }
+  for (int k = 0; k < d.n_pi; ++k)
+    e << "      { const int sm = wsumi(cnt" << k << "); if (lane == 0) irow[" << k << "] = sm; }\n";
+  e << "      __builtin_amdgcn_wave_barrier();\n      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");\n";
+  if (d.hist_i_bins > 0)
+    e << "      for (int i = lane; i < " << d.hist_i_bins << "; i += 64) irow[" << d.n_pi << " + i] = hist_i[i];\n";
+  if (d.hist_f_bins > 0)
+    e << "      for (int i = lane; i < " << d.hist_f_bins << "; i += 64) prow[" << d.pf_n << " + i] = hist_f[i];\n";
+  e << "      __builtin_amdgcn_wave_barrier();\n";
+  e << "    }\n  }\n";
+  if (d.lds_tab_i > 0) {
+    e << "  __syncthreads();\n";
+    e << "  for (int i = threadIdx.x; i < " << d.lds_tab_i << "; i += " << kGenWaves * 64 << ") part_i[(long long)blockIdx.x * "
+      << d.lds_tab_i << " + i] = tab_i[i];\n";
+  }
+  e << "}\n";
+
+  std::string src = e.o.str();
+  // the source holds no pointer values (they travel as arguments), so equal
+  // programs share one compiled function
+  static std::mutex mtx;
+  static std::map<std::string, hipFunction_t> cache;
+  std::lock_guard<std::mutex> lock(mtx);
+  auto it = cache.find(src);
+  if (it == cache.end()) {
+    hipFunction_t fn = nullptr;
+    if (!compile_kernel(src, "lmfao_gen_scan", fn, why)) return false;
+    it = cache.emplace(src, fn).first;
+  }
+  out.fn = it->second;
+  out.args = args;
+  out.lds = lds;
+  out.block = kGenWaves * 64;
+  out.source = src;
+  return true;
+}
+
+bool compile_kernel(const std::string& src, const char* name, hipFunction_t& fn, std::string& why) {
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "lmfao_gen.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+    why = "hiprtcCreateProgram failed";
+    return false;
+  }
+  // packed FP32 instructions stay off, as in the library's own kernels
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-munsafe-fp-atomics", "-Xclang", "-target-feature",
+                        "-Xclang", "-packed-fp32-ops"};
+  const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    why = std::string("hipRTC compile failed: ") + hiprtcGetErrorString(r) + "\n" + log;
+    hiprtcDestroyProgram(&prog);
+    return false;
+  }
+  size_t n = 0;
+  hiprtcGetCodeSize(prog, &n);
+  std::vector<char> code(n);
+  hiprtcGetCode(prog, code.data());
+  hiprtcDestroyProgram(&prog);
+  hipModule_t mod;
+  if (hipModuleLoadData(&mod, code.data()) != hipSuccess) {
+    why = "hipModuleLoadData failed";
+    return false;
+  }
+  if (hipModuleGetFunction(&fn, mod, name) != hipSuccess) {
+    why = "hipModuleGetFunction failed";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace lmfao

@@ -365,7 +365,7 @@ struct DImageBuild {
 };
 
 constexpr int kFastHists = 32;
-constexpr int kFastTables = 2;
+constexpr int kFastTables = 4;
 
 // hoisted form of a lean scan (all loop-invariant, read once per kernel)
 struct DFast {

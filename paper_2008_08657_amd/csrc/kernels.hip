@@ -1807,6 +1807,7 @@ __global__ void k_table_reduce(const DTableReduce* __restrict__ R) {
     int64_t s = 0;
     for (int b = 0; b < R->n_blocks; ++b) s += R->part_i[(int64_t)b * R->stride + R->off + i];
     R->dst_cnt[i] += s;
+    for (int k = 0; k < R->n_copy; ++k) R->copy_vals[i * R->copy_nv + R->copy_comp[k]] += (double)s;
   }
 }
 void launch_table_reduce(const DTableReduce* d, int64_t n, hipStream_t s) {

@@ -64,6 +64,11 @@ struct DTableReduce {
   int64_t off;          // offset of the table inside a partial row
   const int32_t* part_i;
   int64_t* dst_cnt;
+  // SUM(1) components of the table, equal to its count: written from it
+  double* copy_vals;         // destination values (FP64 rows of copy_nv columns)
+  int32_t copy_nv;
+  int32_t n_copy;
+  int32_t copy_comp[kMaxTableComps];
 };
 
 void launch_fill(void* p, int64_t bytes, hipStream_t s);

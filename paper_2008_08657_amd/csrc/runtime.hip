@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "engine.hpp"
+#include "codegen.hpp"
 #include "kernels.hpp"
 #include "lmfao.h"
 
@@ -64,6 +65,9 @@ struct NodeData {
 
 struct Step {
   std::string name;
+  hipFunction_t gen_fn = nullptr;   // generated kernel (scan steps), else a built-in kernel
+  const uint64_t* gen_args = nullptr;
+  int gen_block = 0;
   int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract (VALU), 5 merge, 6 image build,
               // 7 contraction staging, 8 MFMA contraction, 9 block-major merge, 10 filter, 11 finalize
   int fast = 0;
@@ -92,6 +96,7 @@ struct lmfao_prepared_s {
   bool f64 = true;
   std::vector<lmfao::OutBuf> qout, vout;
   std::vector<lmfao::OutBuf> uout;                   // range queries of the caller's batch
+  std::vector<std::string> gen_sources, gen_failures; // generated scan kernels (and why not)
   std::vector<std::vector<const void*>> ecols;       // caller's columns, then derived bucket codes
   std::vector<const void* const*> ecol_ptrs;
   std::vector<int32_t*> w_raw, w_sorted;             // filter weights per relation (lazily built)
@@ -736,6 +741,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     uint32_t tab_omask = 0;
     bool tab_omask_set = false;
     std::vector<std::pair<int, int>> lds_tables;   // (output index, lds offset)
+    std::map<int, std::vector<int>> table_copies;    // output index -> SUM(1) components copied from the count
     for (size_t oi = 0; oi < g.outs.size(); ++oi) {
       const ProgOutput& po = g.outs[oi];
       if (po.mode != 2) continue;
@@ -749,20 +755,32 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
       }
       T.n_rows = po.n_rows;
       if (po.tcomps.size() > (size_t)kMaxTableComps) throw PlanError{LMFAO_EUNSUPPORTED, "too many table components"};
-      T.n_tcomps = (int)po.tcomps.size();
-      for (int q = 0; q < T.n_tcomps; ++q) {
-        const TableComp& tc = po.tcomps[q];
-        T.tcomp[q] = tc.comp;
-        T.twi[q] = tc.comp < 0 ? weight_idx(0, -1, -1, mask_idx(tc.imask))
-                               : weight_idx(1, tc.ai, tc.aj, mask_idx(tc.imask));
-      }
-      for (int k = 0; k < T.ncode; ++k) run_codes |= 1u << T.code[k];
       const OutBuf& O = po.ref.kind == 0 ? S.qout[po.ref.id] : S.vout[po.ref.id];
+      const bool in_lds = lds_used + po.n_rows <= kLdsTableMax;
+      // a SUM(1) component under the count's mask equals the count: an LDS
+      // table writes it from the reduced counts instead of accumulating it
+      uint32_t count_mask = 0;
+      for (const TableComp& tc : po.tcomps)
+        if (tc.comp < 0) count_mask = tc.imask;
+      std::vector<int> copies;
+      T.n_tcomps = 0;
+      for (const TableComp& tc : po.tcomps) {
+        if (in_lds && tc.comp >= 0 && tc.ai < 0 && tc.aj < 0 && tc.imask == count_mask && O.f64) {
+          copies.push_back(tc.comp);
+          continue;
+        }
+        T.tcomp[T.n_tcomps] = tc.comp;
+        T.twi[T.n_tcomps] = tc.comp < 0 ? weight_idx(0, -1, -1, mask_idx(tc.imask))
+                                        : weight_idx(1, tc.ai, tc.aj, mask_idx(tc.imask));
+        T.n_tcomps++;
+      }
+      table_copies[(int)oi] = copies;
+      for (int k = 0; k < T.ncode; ++k) run_codes |= 1u << T.code[k];
       T.cnt = O.cnt;
       T.vals = O.vals;
       T.vals_f64 = O.f64 ? 1 : 0;
       T.n_vals = O.n_vals;
-      if (lds_used + po.n_rows <= kLdsTableMax) {
+      if (in_lds) {
         T.lds = 1;
         T.lds_off = lds_used;
         lds_tables.push_back({(int)oi, lds_used});
@@ -910,6 +928,19 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     s.kind = 2;
     s.fast = fast ? 1 : 0;
     s.dev = upload(S, d, st);
+    if (fast && S.P->opts.codegen == 0) {
+      GenKernel gk;
+      std::string why;
+      if (gen_scan_kernel(d, NA, f64, gk, why)) {
+        s.gen_fn = gk.fn;
+        s.gen_args = upload_vec(S, gk.args, st);
+        s.gen_block = gk.block;
+        lds = gk.lds;
+        S.gen_sources.push_back(gname + "\n" + gk.source);
+      } else {
+        S.gen_failures.push_back(gname + ": " + why);
+      }
+    }
     s.na = NA;
     s.grid = grid;
     s.lds = lds;
@@ -937,6 +968,11 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
       tr.off = lt.second;
       tr.part_i = d.part_i;
       tr.dst_cnt = O.cnt;
+      const std::vector<int>& cp = table_copies[lt.first];
+      tr.copy_vals = (double*)O.vals;
+      tr.copy_nv = O.n_vals;
+      tr.n_copy = (int)cp.size();
+      for (size_t k = 0; k < cp.size(); ++k) tr.copy_comp[k] = cp[k];
       Step t;
       t.name = gname + ":table_reduce";
       t.kind = 3;
@@ -1320,8 +1356,14 @@ static void enqueue_run(Prep& S, hipStream_t st) {
       case 0: launch_fill(s.dev, s.bytes, st); break;
       case 1: launch_view_build((const DViewBuild*)s.dev, s.n, S.f64, st); break;
       case 2:
-        if (s.fast) launch_scan_fast((const DScan*)s.dev, s.na, S.f64, s.grid, s.lds, st);
-        else launch_scan((const DScan*)s.dev, s.na, S.f64, s.grid, s.lds, st);
+        if (s.gen_fn) {
+          void* params[] = {(void*)&s.gen_args};
+          HIP_OK(hipModuleLaunchKernel(s.gen_fn, s.grid, 1, 1, s.gen_block, 1, 1, s.lds, st, params, nullptr));
+        } else if (s.fast) {
+          launch_scan_fast((const DScan*)s.dev, s.na, S.f64, s.grid, s.lds, st);
+        } else {
+          launch_scan((const DScan*)s.dev, s.na, S.f64, s.grid, s.lds, st);
+        }
         break;
       case 6: launch_build_image((const DImageBuild*)s.dev, s.n, S.f64, st); break;
       case 3: launch_table_reduce((const DTableReduce*)s.dev, s.n, st); break;
@@ -1729,6 +1771,19 @@ lmfao_status lmfao_run_timing(lmfao_prepared_t prep, int32_t cap, const char** n
   return LMFAO_OK;
 }
 
+lmfao_status lmfao_prepared_kernel_source(lmfao_prepared_t prep, int32_t i, char* buf, size_t cap, size_t* need) {
+  if (!prep) return set_err(LMFAO_EINVAL, "null prepared handle");
+  if (i < 0 || i >= (int)prep->gen_sources.size()) return set_err(LMFAO_EINVAL, "no generated kernel with that index");
+  const std::string& j = prep->gen_sources[i];
+  if (need) *need = j.size() + 1;
+  if (buf && cap) {
+    size_t n = std::min(cap - 1, j.size());
+    std::memcpy(buf, j.data(), n);
+    buf[n] = 0;
+  }
+  return LMFAO_OK;
+}
+
 lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t cap, size_t* need) {
   if (!prep) return set_err(LMFAO_EINVAL, "null prepared handle");
   std::string j = "{\"steps\":[";
@@ -1743,15 +1798,27 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     char tmp[512];
     snprintf(tmp, sizeof(tmp),
              "{\"name\":\"%s\",\"kind\":\"%s\",\"rows\":%lld,\"pieces\":%lld,\"alg_read_bytes\":%.0f,"
-             "\"alg_write_bytes\":%.0f,\"alg_flop\":%.0f,\"grid\":%d,\"grid_y\":%d,\"lds\":%d}",
+             "\"alg_write_bytes\":%.0f,\"alg_flop\":%.0f,\"grid\":%d,\"grid_y\":%d,\"lds\":%d,\"lean\":%d}",
              s.name.c_str(), kinds[s.kind], (long long)s.rows, (long long)s.pieces, s.alg_read, s.alg_write,
-             s.alg_flop, s.grid, s.grid_y, s.lds);
+             s.alg_flop, s.grid, s.grid_y, s.lds, s.gen_fn ? 2 : s.fast);
     j += tmp;
   }
   int64_t fill_bytes = 0;
   for (auto& s : prep->steps)
     if (s.kind == 0) fill_bytes += s.bytes;
-  j += "],\"fill_bytes\":" + std::to_string(fill_bytes) + "}";
+  j += "],\"fill_bytes\":" + std::to_string(fill_bytes) + ",\"codegen_failures\":[";
+  for (size_t i = 0; i < prep->gen_failures.size(); ++i) {
+    if (i) j += ",";
+    std::string m;
+    for (char ch : prep->gen_failures[i]) {
+      if (ch == '"' || ch == '\\') m += '\\';
+      if (ch == '\n') { m += "\\n"; continue; }
+      if ((unsigned char)ch < 0x20) continue;
+      m += ch;
+    }
+    j += "\"" + m + "\"";
+  }
+  j += "],\"generated_scans\":" + std::to_string(prep->gen_sources.size()) + "}";
   if (need) *need = j.size() + 1;
   if (buf && cap) {
     size_t n = std::min(cap - 1, j.size());
