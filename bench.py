@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=150_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     ap.add_argument("--form", default="fused", choices=["fused", "per_view"],
                     help="fused: one pass per group of outputs (the method); per_view: one pass per output")
     args = ap.parse_args()
@@ -65,6 +67,18 @@ def main():
     import torch
     import workloads as W
     import paper_2008_08657_amd as E
+
+    if args.calibrate_copy:
+        # a copy of known size: its FETCH_SIZE / WRITE_SIZE counters read the
+        # bytes moved, giving the scale of those counters on this device
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
+        return
 
     E.load_library()
     t_gen = time.perf_counter()

@@ -67,10 +67,32 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::stri
   Emit e;
   e << "// generated scan kernel\n";
   e << "typedef " << T << " T;\n";
-  e << "__device__ __forceinline__ T wsum(T x) {\n"
-       "  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);\n  return x;\n}\n";
+  // wave sums on the DPP path (no LDS traffic): prefix sums inside rows of
+  // 16 lanes, then the row totals broadcast into the next rows; lane 63 holds
+  // the total, which readlane hands to every lane
+  e << "__device__ __forceinline__ int dppi(int v, int ctrl, int rows) {\n"
+       "  switch (ctrl) {\n"
+       "    case 1: return __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);\n"
+       "    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);\n"
+       "    case 4: return __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);\n"
+       "    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);\n"
+       "    case 15: return __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);\n"
+       "    default: return __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);\n"
+       "  }\n}\n";
   e << "__device__ __forceinline__ int wsumi(int x) {\n"
-       "  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);\n  return x;\n}\n";
+       "  x += dppi(x, 1, 0); x += dppi(x, 2, 0); x += dppi(x, 4, 0); x += dppi(x, 8, 0);\n"
+       "  x += dppi(x, 15, 0); x += dppi(x, 31, 0);\n"
+       "  return __builtin_amdgcn_readlane(x, 63);\n}\n";
+  if (f64) {
+    e << "__device__ __forceinline__ T wsum(T x) {\n"
+         "  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);\n  return x;\n}\n";
+  } else {
+    e << "__device__ __forceinline__ float wsum(float x) {\n"
+         "  x += __int_as_float(dppi(__float_as_int(x), 1, 0)); x += __int_as_float(dppi(__float_as_int(x), 2, 0));\n"
+         "  x += __int_as_float(dppi(__float_as_int(x), 4, 0)); x += __int_as_float(dppi(__float_as_int(x), 8, 0));\n"
+         "  x += __int_as_float(dppi(__float_as_int(x), 15, 0)); x += __int_as_float(dppi(__float_as_int(x), 31, 0));\n"
+         "  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));\n}\n";
+  }
   if (f64) {
     // TwoSum butterfly: every combining add is error-free transformed
     e << "__device__ __forceinline__ double wsumc(double s) {\n"
@@ -125,10 +147,15 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::stri
   (void)any_global_tab;
   if (d.lds_tab_i > 0) e << "  int* __restrict__ part_i = (int*)A[" << arg((uint64_t)d.part_i) << "];\n";
 
-  // LDS: count tables (block), then a histogram area per wavefront
+  // LDS: count tables (block), then a histogram area per wavefront.  Each
+  // histogram is kept in kRep copies, lane & (kRep-1) choosing the copy, so
+  // that lanes adding to the same bin mostly meet in different copies; the
+  // copies are summed when the piece closes.
+  constexpr int kRep = 4;
+  const int hib = d.hist_i_bins, hfb = d.hist_f_bins;
   const int tab_bytes = (d.lds_tab_i * 4 + 15) & ~15;
-  const int hist_i_bytes = (d.hist_i_bins * 4 + 7) & ~7;
-  const int hist_bytes = hist_i_bytes + d.hist_f_bins * tsz;
+  const int hist_i_bytes = (kRep * hib * 4 + 7) & ~7;
+  const int hist_bytes = hist_i_bytes + kRep * hfb * tsz;
   const int wave_stride = (hist_bytes + 15) & ~15;
   const int lds = tab_bytes + kGenWaves * wave_stride;
   if (lds > 65536) {
@@ -193,8 +220,12 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::stri
       e << "        mu_out *= (int)ov" << v << "[vr]; }\n";
     }
   }
-  if (d.hist_i_bins > 0) e << "      for (int i = lane; i < " << d.hist_i_bins << "; i += 64) hist_i[i] = 0;\n";
-  if (d.hist_f_bins > 0) e << "      for (int i = lane; i < " << d.hist_f_bins << "; i += 64) hist_f[i] = (T)0;\n";
+  if (hib > 0) e << "      for (int i = lane; i < " << kRep * hib << "; i += 64) hist_i[i] = 0;\n";
+  if (hfb > 0) e << "      for (int i = lane; i < " << kRep * hfb << "; i += 64) hist_f[i] = (T)0;\n";
+  if (hib > 0 || hfb > 0) {
+    e << "      const int rep_i = (lane & " << kRep - 1 << ") * " << hib << ";\n";
+    e << "      const int rep_f = (lane & " << kRep - 1 << ") * " << hfb << ";\n";
+  }
   e << "      __builtin_amdgcn_wave_barrier();\n";
   for (size_t k = 0; k < terms.size(); ++k) e << "      T acc" << k << " = (T)0;\n";
   for (int k = 0; k < d.n_pi; ++k) e << "      int cnt" << k << " = 0;\n";
@@ -259,10 +290,10 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::stri
     const int code = (int)(w & 3u), m = (int)((w >> 2) & 3u), off = (int)(w >> 13);
     if ((w >> 4) & 1u) {
       const int ai = (int)((w >> 5) & 15u), aj = (int)((w >> 9) & 15u);
-      e << "        if (" << mu(m) << ") atomicAdd(&hist_f[" << off << " + c" << code << "], (T)" << mu(m) << " * a" << ai
-        << " * a" << aj << ");\n";
+      e << "        if (" << mu(m) << ") atomicAdd(&hist_f[rep_f + " << off << " + c" << code << "], (T)" << mu(m)
+        << " * a" << ai << " * a" << aj << ");\n";
     } else {
-      e << "        if (" << mu(m) << ") atomicAdd(&hist_i[" << off << " + c" << code << "], " << mu(m) << ");\n";
+      e << "        if (" << mu(m) << ") atomicAdd(&hist_i[rep_i + " << off << " + c" << code << "], " << mu(m) << ");\n";
     }
   }
   // direct count tables
@@ -287,10 +318,16 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::stri
   for (int k = 0; k < d.n_pi; ++k)
     e << "      { const int sm = wsumi(cnt" << k << "); if (lane == 0) irow[" << k << "] = sm; }\n";
   e << "      __builtin_amdgcn_wave_barrier();\n      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");\n";
-  if (d.hist_i_bins > 0)
-    e << "      for (int i = lane; i < " << d.hist_i_bins << "; i += 64) irow[" << d.n_pi << " + i] = hist_i[i];\n";
-  if (d.hist_f_bins > 0)
-    e << "      for (int i = lane; i < " << d.hist_f_bins << "; i += 64) prow[" << d.pf_n << " + i] = hist_f[i];\n";
+  if (hib > 0) {
+    e << "      for (int i = lane; i < " << hib << "; i += 64) irow[" << d.n_pi << " + i] = hist_i[i]";
+    for (int r = 1; r < kRep; ++r) e << " + hist_i[" << r * hib << " + i]";
+    e << ";\n";
+  }
+  if (hfb > 0) {
+    e << "      for (int i = lane; i < " << hfb << "; i += 64) prow[" << d.pf_n << " + i] = hist_f[i]";
+    for (int r = 1; r < kRep; ++r) e << " + hist_f[" << r * hfb << " + i]";
+    e << ";\n";
+  }
   e << "      __builtin_amdgcn_wave_barrier();\n";
   e << "    }\n  }\n";
   if (d.lds_tab_i > 0) {
