@@ -83,6 +83,22 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::stri
        "  x += dppi(x, 1, 0); x += dppi(x, 2, 0); x += dppi(x, 4, 0); x += dppi(x, 8, 0);\n"
        "  x += dppi(x, 15, 0); x += dppi(x, 31, 0);\n"
        "  return __builtin_amdgcn_readlane(x, 63);\n}\n";
+  // inclusive prefix sum over the wave (the same DPP steps as the sum)
+  e << "__device__ __forceinline__ int wscani(int x) {\n"
+       "  x += dppi(x, 1, 0); x += dppi(x, 2, 0); x += dppi(x, 4, 0); x += dppi(x, 8, 0);\n"
+       "  x += dppi(x, 15, 0); x += dppi(x, 31, 0);\n  return x;\n}\n";
+  // Adjacent lanes adding to the same bin (sorted keys make runs) combine:
+  // the last lane of each run adds the run's total, taken as a difference of
+  // the exact integer prefix sums.  Returns the amount this lane must add.
+  e << "__device__ __forceinline__ int run_total(int bin, int m, int lane) {\n"
+       "  const int P = wscani(m);\n"
+       "  const int prev = __builtin_amdgcn_update_dpp(-1, bin, 0x138, 0xf, 0xf, false);\n"
+       "  const unsigned long long H = __ballot(lane == 0 || prev != bin);\n"
+       "  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);\n"
+       "  const int start = 63 - __clzll(H & upto);\n"
+       "  const int before = __shfl(P, start > 0 ? start - 1 : 0, 64);\n"
+       "  const bool tail = lane == 63 || ((H >> (lane + 1)) & 1ull);\n"
+       "  return tail ? P - (start > 0 ? before : 0) : 0;\n}\n";
   if (f64) {
     e << "__device__ __forceinline__ T wsum(T x) {\n"
          "  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);\n  return x;\n}\n";
@@ -293,14 +309,16 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::stri
       e << "        if (" << mu(m) << ") atomicAdd(&hist_f[rep_f + " << off << " + c" << code << "], (T)" << mu(m)
         << " * a" << ai << " * a" << aj << ");\n";
     } else {
-      e << "        if (" << mu(m) << ") atomicAdd(&hist_i[rep_i + " << off << " + c" << code << "], " << mu(m) << ");\n";
+      e << "        { const int rt = run_total(c" << code << ", " << mu(m) << ", lane);\n"
+        << "          if (rt) atomicAdd(&hist_i[rep_i + " << off << " + c" << code << "], rt); }\n";
     }
   }
   // direct count tables
   for (int t = 0; t < F.n_tab; ++t) {
     e << "        {\n          const int row = 0";
     for (int k = 0; k < F.tab_ncode[t]; ++k) e << " + c" << F.tab_code[t][k] << " * " << F.tab_stride[t][k];
-    e << ";\n          const int m = " << (has_mu_out ? "mu_out * " : "") << mu(F.tab_mask[t]) << ";\n";
+    e << ";\n          const int m = run_total(row, " << (has_mu_out ? "mu_out * " : "") << mu(F.tab_mask[t])
+      << ", lane);\n";
     if (F.tab_lds[t])
       e << "          if (m) atomicAdd(&tab_i[" << F.tab_off[t] << " + row], m);\n";
     else
