@@ -1802,18 +1802,25 @@ void launch_merge_cells(const DCell* cells, int64_t n_cells, const double* part_
 }
 
 // table partials: dst[i] += sum_b part[b * stride + off + i]
+// block y sums a slice of the partial rows; slices meet in integer atomics
+// (exact, so the order does not matter)
+constexpr int kReduceSlice = 16;   // partial rows per thread
 __global__ void k_table_reduce(const DTableReduce* __restrict__ R) {
+  const int b0 = blockIdx.y * kReduceSlice;
+  const int b1 = min(R->n_blocks, b0 + kReduceSlice);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < R->n; i += (int64_t)gridDim.x * blockDim.x) {
     int64_t s = 0;
-    for (int b = 0; b < R->n_blocks; ++b) s += R->part_i[(int64_t)b * R->stride + R->off + i];
-    R->dst_cnt[i] += s;
-    for (int k = 0; k < R->n_copy; ++k) R->copy_vals[i * R->copy_nv + R->copy_comp[k]] += (double)s;
+    for (int b = b0; b < b1; ++b) s += R->part_i[(int64_t)b * R->stride + R->off + i];
+    if (s == 0) continue;
+    atomic_add_i64(&R->dst_cnt[i], s);
+    for (int k = 0; k < R->n_copy; ++k) atomic_add_f64(&R->copy_vals[i * R->copy_nv + R->copy_comp[k]], (double)s);
   }
 }
-void launch_table_reduce(const DTableReduce* d, int64_t n, hipStream_t s) {
+void launch_table_reduce(const DTableReduce* d, int64_t n, int n_blocks, hipStream_t s) {
   if (n <= 0) return;
-  int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_table_reduce, dim3(grid), dim3(256), 0, s, d);
+  const int gy = std::max(1, (n_blocks + kReduceSlice - 1) / kReduceSlice);
+  const int gx = (int)std::min<int64_t>((n + 255) / 256, std::max<int64_t>(1, 8192 / gy));
+  hipLaunchKernelGGL(k_table_reduce, dim3(gx, gy), dim3(256), 0, s, d);
 }
 
 }  // namespace lmfao

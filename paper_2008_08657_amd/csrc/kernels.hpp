@@ -125,6 +125,6 @@ void launch_merge_bm(const DCell* cells, int64_t n_cells, const double* part, in
 
 void launch_merge_cells(const DCell* cells, int64_t n_cells, const double* part_f, const int64_t* part_i,
                         int n_blocks, int NF, int NG, int NFI, int NGI, hipStream_t s);
-void launch_table_reduce(const DTableReduce* d, int64_t n, hipStream_t s);
+void launch_table_reduce(const DTableReduce* d, int64_t n, int n_blocks, hipStream_t s);
 
 }  // namespace lmfao

@@ -978,6 +978,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
       t.kind = 3;
       t.dev = upload(S, tr, st);
       t.n = po.n_rows;
+      t.n_blocks = grid;
       S.steps.push_back(t);
     }
   }
@@ -1366,7 +1367,7 @@ static void enqueue_run(Prep& S, hipStream_t st) {
         }
         break;
       case 6: launch_build_image((const DImageBuild*)s.dev, s.n, S.f64, st); break;
-      case 3: launch_table_reduce((const DTableReduce*)s.dev, s.n, st); break;
+      case 3: launch_table_reduce((const DTableReduce*)s.dev, s.n, s.n_blocks, st); break;
       case 4: launch_contract((const DContract*)s.dev, S.f64, s.grid, s.grid_y, s.lds, st); break;
       case 5:
         launch_merge_cells((const DCell*)s.dev, s.n, s.part_f, s.part_i, s.n_blocks, s.NF, s.NG, s.NFI, s.NGI, st);
