@@ -165,6 +165,10 @@ typedef struct {
                             group and compiled with hipRTC at prepare time
                             (falls back to the built-in kernel if that
                             fails); 1: built-in kernels only               */
+  int64_t hash_slots;    /* initial slots of every hash table (outputs whose
+                            dense key space exceeds 2^24 cells); 0 = twice
+                            the most groups the query can have.  A run with
+                            sync grows a table that overflowed and repeats */
 } lmfao_options;
 
 typedef struct lmfao_plan_s* lmfao_plan_t;

@@ -72,7 +72,7 @@ class lmfao_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("form", C.c_int32), ("root_policy", C.c_int32),
                 ("n_order", C.POINTER(C.c_int32)), ("order", C.POINTER(C.POINTER(C.c_char_p))),
                 ("min_segment", C.c_int32), ("row_piece_max", C.c_int64),
-                ("contraction", C.c_int32), ("codegen", C.c_int32)]
+                ("contraction", C.c_int32), ("codegen", C.c_int32), ("hash_slots", C.c_int64)]
 
 
 class LmfaoError(RuntimeError):
@@ -192,7 +192,7 @@ class Plan:
     """A plan handle (``lmfao_plan``)."""
 
     def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
-                 min_segment=0, row_piece_max=0, contraction="mfma", codegen=True):
+                 min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0):
         self.lib = load_library()
         self.problem = problem
         keep = _Keep()
@@ -209,6 +209,7 @@ class Plan:
             raise ValueError(f"contraction must be 'mfma' or 'valu', not {contraction!r}")
         opts.contraction = 0 if contraction == "mfma" else 1
         opts.codegen = 0 if codegen else 1
+        opts.hash_slots = int(hash_slots)
         if order:
             names = [r["name"] for r in problem["schema"]]
             n_order = [len(order.get(n, [])) for n in names]

@@ -35,6 +35,7 @@ constexpr int kMaxTableComps = 8;
 constexpr int kOneHotMax = 64;     // largest code domain expanded one-hot
 constexpr int kHistMax = 1024;     // largest code domain kept per piece
 constexpr int kTriangle = (kMaxAtoms + 1) * (kMaxAtoms + 2) / 2;  // incl. (1,1)
+constexpr int64_t kDenseRowsMax = (int64_t)1 << 24;  // larger key spaces go to hash tables
 
 // ---------------------------------------------------------------------------
 // logical plan
@@ -184,6 +185,7 @@ struct ProgOutput {
   uint32_t omask = 0;                 // table mode: outer mask
   std::vector<TableComp> tcomps;      // table mode
   bool dst_is_view = false;           // writes vals as view table (f32/f64 by view)
+  bool hashed = false;                // scatter mode into a hash table (key space > kDenseRowsMax)
 };
 
 struct PsiEntryF {
@@ -444,6 +446,17 @@ struct DColB {
   DFeat feat;
 };
 
+// open-addressing hash table of one output whose key space is too large to
+// be dense: keys hold row + 1 (0 = empty), counts and values per slot
+struct DHashOut {
+  unsigned long long* keys;
+  int64_t* cnt;
+  double* vals;                    // [cap x n_vals]
+  int64_t mask;                    // capacity - 1 (power of two)
+  int32_t* ovf;                    // set when an insert found no slot
+  int32_t n_vals, pad;
+};
+
 struct DContract {
   const int32_t* w;                // row pieces: filter weight per row (null: no filter)
   int64_t n_pieces;
@@ -466,14 +479,7 @@ struct DContract {
   const int32_t* psi_i;
   int32_t psi_f_stride, psi_i_stride;
   int32_t row_pieces;
-  // staged operands of the matrix-core contraction (null: the VALU kernel
-  // contracts in place): F [n_pieces x ldf] and B [n_pieces x ldg], FP64,
-  // pad columns zero; integer features and columns are stored exactly and
-  // checked against 2^53 (err_flag code 3)
-  double* fmat;
-  double* bmat;
-  int32_t ldf, ldg;
-  int32_t* err_flag;
+  int32_t* err_flag;               // code 4: an integer feature reached 2^53 (matrix-core path)
   // outputs: partial GEMM blocks
   double* part_f;                  // [n_blocks x n_feat x n_col] f64 (T accumulated, stored f64)
   int64_t* part_i;                 // [n_blocks x n_feat_int x n_col_int]
@@ -491,15 +497,15 @@ struct DContract {
   int64_t* const* so_cnt;
   void* const* so_vals;            // f64 (or view dtype)
   const int32_t* so_vals_f64;
+  const int32_t* so_hash_idx;      // per output: hash table index, -1 dense
+  const DHashOut* hash_tab;        // hash tables of the prepared plan
 };
 
-// split-K product of the staged operands on the matrix cores:
+// split-K shape of the matrix-core contraction:
 // part[b][f * ng + g] = sum over the pieces of block b of F[p][f] * B[p][g]
 struct DGemm {
-  const double* F;
-  const double* B;
   int64_t n;                       // pieces (K)
-  int32_t ldf, ldg, nf, ng;
+  int32_t nf, ng;
   int64_t k_per_block;             // multiple of the LDS chunk
   double* part;                    // [gridDim.x][nf * ng], block-major
 };

@@ -84,6 +84,62 @@ __device__ __forceinline__ void atomic_add_i64(int64_t* p, int64_t v) {
 }
 
 // ---------------------------------------------------------------------------
+// scatter targets: dense rows, or a hash table for large key spaces
+// ---------------------------------------------------------------------------
+constexpr int kMaxProbe = 256;   // linear probes before an insert reports overflow
+
+__device__ __forceinline__ int64_t hash_find(const DHashOut& H, int64_t row) {
+  const unsigned long long k = (unsigned long long)row + 1ull;
+  unsigned long long h = k * 0x9E3779B97F4A7C15ull;
+  h ^= h >> 31;
+  int64_t slot = (int64_t)(h & (unsigned long long)H.mask);
+  for (int probe = 0; probe < kMaxProbe; ++probe) {
+    const unsigned long long cur = __hip_atomic_load(&H.keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == k) return slot;
+    if (cur == 0ull) {
+      const unsigned long long prev = atomicCAS(&H.keys[slot], 0ull, k);
+      if (prev == 0ull || prev == k) return slot;
+    }
+    slot = (slot + 1) & H.mask;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ void scatter_count(const DContract* C, int o, int64_t row, int64_t v) {
+  const int hi = C->so_hash_idx ? C->so_hash_idx[o] : -1;
+  if (hi < 0) {
+    atomic_add_i64(&C->so_cnt[o][row], v);
+    return;
+  }
+  const DHashOut& H = C->hash_tab[hi];
+  const int64_t slot = hash_find(H, row);
+  if (slot < 0) {
+    atomicOr(H.ovf, 1);
+    atomicOr(C->err_flag, 8);
+    return;
+  }
+  atomic_add_i64(&H.cnt[slot], v);
+}
+
+__device__ __forceinline__ void scatter_value(const DContract* C, int o, int64_t row, int comp, double v) {
+  const int hi = C->so_hash_idx ? C->so_hash_idx[o] : -1;
+  if (hi < 0) {
+    const int64_t idx = row * C->so_ncomp[o] + comp;
+    if (C->so_vals_f64[o]) atomic_add_f64(&((double*)C->so_vals[o])[idx], v);
+    else atomicAdd(&((float*)C->so_vals[o])[idx], (float)v);
+    return;
+  }
+  const DHashOut& H = C->hash_tab[hi];
+  const int64_t slot = hash_find(H, row);
+  if (slot < 0) {
+    atomicOr(H.ovf, 1);
+    atomicOr(C->err_flag, 8);
+    return;
+  }
+  atomic_add_f64(&H.vals[slot * H.n_vals + comp], v);
+}
+
+// ---------------------------------------------------------------------------
 // fill
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
@@ -1394,14 +1450,10 @@ __global__ __launch_bounds__(kCThreads) void k_contract(const DContract* __restr
           if (F.c2 >= 0 && code_s[pi * NC + F.c2] != F.v2) cnt = 0;
         }
         v *= cnt;
-        if (v) atomic_add_i64(&C->so_cnt[o][row], v);
+        if (v) scatter_count(C, o, row, v);
       } else {
         T v = A[pi * NF + f] * Bm[pi * NG + g];
-        if (v != (T)0) {
-          int64_t idx = row * C->so_ncomp[o] + comp;
-          if (C->so_vals_f64[o]) atomic_add_f64(&((double*)C->so_vals[o])[idx], (double)v);
-          else atomicAdd(&((float*)C->so_vals[o])[idx], (float)v);
-        }
+        if (v != (T)0) scatter_value(C, o, row, comp, (double)v);
       }
     }
     __syncthreads();
@@ -1484,20 +1536,71 @@ __device__ __forceinline__ double col_d(const DContract* C, const DColB& B, int6
   return x;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_contract_stage(const DContract* __restrict__ C) {
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kGemmMT = 64;   // features per block: 4 wavefronts x 16 rows
+
+int gemm_tile_cols(int ng) { return std::min(8, std::max(1, (ng + 15) / 16)); }
+int gemm_macro_tiles(int nf, int ng) {
+  const int nt = 16 * gemm_tile_cols(ng);
+  return ((nf + kGemmMT - 1) / kGemmMT) * ((ng + nt - 1) / nt);
+}
+
+// Fused contraction: per chunk of kFKC pieces the block stages the pieces
+// outer view rows, multiplicities, factors and codes in LDS, builds its slice
+// of F (features x pieces) and B (columns x pieces) there, and multiplies them
+// on the matrix cores; F and B never travel through HBM.  Block (x, y): K
+// range x, macro-tile y (64 features x 16*TN columns).  Scatter cells are
+// evaluated by the y == 0 blocks.
+constexpr int kFKC = 16;
+
+int contract_fused_lds_bytes(const DContract& C, int tn) {
+  const int nt = 16 * tn;
+  const int sb = (nt % 32 == 0) ? nt + 16 : nt;
+  int64_t b = (int64_t)kFKC * (kGemmMT + 16) * 8 + (int64_t)kFKC * sb * 8;
+  b += (int64_t)kFKC * (2 * kMaxViews * 8 + C.n_masks * 8 + C.n_atoms * 8) + (int64_t)kFKC * C.n_codes * 4;
+  b = (b + 15) & ~(int64_t)15;
+  b += (int64_t)kGemmMT * sizeof(DFeat) + (int64_t)nt * sizeof(DColB);
+  return (int)((b + 15) & ~(int64_t)15);
+}
+int contract_fused_chunk() { return kFKC; }
+
+template <typename T, int TN>
+__global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restrict__ C, const DGemm* __restrict__ G) {
+  constexpr int NT = 16 * TN;
+  constexpr int SA = kGemmMT + 16;
+  constexpr int SB = (NT % 32 == 0) ? NT + 16 : NT;
   extern __shared__ __align__(16) unsigned char smem[];
+  double* As = (double*)smem;                              // [kFKC][SA]
+  double* Bs = As + kFKC * SA;                             // [kFKC][SB]
+  int64_t* vrow_s = (int64_t*)(Bs + kFKC * SB);            // [kFKC][kMaxViews]
+  int64_t* vcnt_s = vrow_s + kFKC * kMaxViews;
   const int NF = C->n_feat, NG = C->n_col, NFI = C->n_feat_int;
   const int NA = C->n_atoms, NC = C->n_codes, NM = C->n_masks, NV = C->n_views;
-  const int ldf = C->ldf, ldg = C->ldg;
-  int64_t* vrow_s = (int64_t*)smem;                       // [kSPieces][kMaxViews]
-  int64_t* vcnt_s = vrow_s + kSPieces * kMaxViews;        // [kSPieces][kMaxViews]
-  int64_t* mu_s = vcnt_s + kSPieces * kMaxViews;          // [kSPieces][NM]
-  double* atom_s = (double*)(mu_s + kSPieces * NM);       // [kSPieces][NA]
-  int32_t* code_s = (int32_t*)(atom_s + kSPieces * NA);   // [kSPieces][NC]
+  int64_t* mu_s = vcnt_s + kFKC * kMaxViews;               // [kFKC][NM]
+  double* atom_s = (double*)(mu_s + kFKC * NM);            // [kFKC][NA]
+  int32_t* code_s = (int32_t*)(atom_s + kFKC * NA);        // [kFKC][NC]
+  unsigned char* dp = (unsigned char*)(code_s + kFKC * NC);
+  dp = (unsigned char*)(((uintptr_t)dp + 15) & ~(uintptr_t)15);
+  DFeat* feat_s = (DFeat*)dp;                              // this block's features
+  DColB* col_s = (DColB*)(feat_s + kGemmMT);               // this block's columns
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n_ntiles = (NG + NT - 1) / NT;
+  const int f0 = (blockIdx.y / n_ntiles) * kGemmMT;
+  const int g0 = (blockIdx.y % n_ntiles) * NT;
+  for (int i = threadIdx.x; i < kGemmMT; i += blockDim.x)
+    if (f0 + i < NF) feat_s[i] = C->feats[f0 + i];
+  for (int i = threadIdx.x; i < NT; i += blockDim.x)
+    if (g0 + i < NG) col_s[i] = C->cols[g0 + i];
+  const int64_t kb = (int64_t)blockIdx.x * G->k_per_block;
+  const int64_t ke = std::min<int64_t>(G->n, kb + G->k_per_block);
+  const bool do_scatter = blockIdx.y == 0;
   bool over = false;
-  for (int64_t cb = (int64_t)blockIdx.x * kSPieces; cb < C->n_pieces; cb += (int64_t)gridDim.x * kSPieces) {
-    const int np = (int)std::min<int64_t>(kSPieces, C->n_pieces - cb);
+  f64x4 acc[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  for (int64_t cb = kb; cb < ke; cb += kFKC) {
+    const int np = (int)std::min<int64_t>(kFKC, ke - cb);
     for (int t = threadIdx.x; t < np * NV; t += blockDim.x) {
       const int pi = t / NV, v = t % NV;
       const DView& V = C->views[v];
@@ -1539,131 +1642,61 @@ __global__ __launch_bounds__(256) void k_contract_stage(const DContract* __restr
       code_s[pi * NC + c] = x;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < np * ldf; t += blockDim.x) {
-      const int pi = t / ldf, f = t % ldf;
+    // the F and B slices of the chunk; rows past the chunk and columns past
+    // the matrix are zero
+    for (int t = threadIdx.x; t < kFKC * kGemmMT; t += blockDim.x) {
+      const int pi = t / kGemmMT, fl = t % kGemmMT, f = f0 + fl;
       double x = 0.0;
-      if (f < NF) {
-        x = feat_d(C->feats[f], mu_s + pi * NM, code_s + pi * NC, atom_s + pi * NA, f < NFI);
+      if (pi < np && f < NF) {
+        x = feat_d(feat_s[fl], mu_s + pi * NM, code_s + pi * NC, atom_s + pi * NA, f < NFI);
         if (f < NFI && !(x < kExactInt)) over = true;
       }
-      C->fmat[(cb + pi) * ldf + f] = x;
+      As[pi * SA + fl] = x;
     }
-    for (int t = threadIdx.x; t < np * ldg; t += blockDim.x) {
-      const int pi = t / ldg, g = t % ldg;
-      C->bmat[(cb + pi) * ldg + g] =
-          g < NG ? col_d<T>(C, C->cols[g], cb + pi, code_s + pi * NC, atom_s + pi * NA) : 0.0;
+    for (int t = threadIdx.x; t < kFKC * NT; t += blockDim.x) {
+      const int pi = t / NT, gl = t % NT, g = g0 + gl;
+      Bs[pi * SB + gl] =
+          (pi < np && g < NG) ? col_d<T>(C, col_s[gl], cb + pi, code_s + pi * NC, atom_s + pi * NA) : 0.0;
     }
-    // scatter cells (outputs keyed by outer codes too large for the dense block)
-    const int n_sc = C->n_scatter;
-    for (int t = threadIdx.x; t < np * n_sc; t += blockDim.x) {
-      const int pi = t / n_sc, sc = t % n_sc;
-      const int o = C->sc_out[sc];
-      int64_t row = 0;
-      bool ok = true;
-      for (int k = 0; k < 3; ++k) {
-        const int cidx = C->so_code[o * 3 + k];
-        if (cidx < 0) continue;
-        const int32_t cval = code_s[pi * NC + cidx];
-        if (cval < 0) ok = false;
-        row += (int64_t)cval * C->so_stride[o * 3 + k];
-      }
-      if (!ok) continue;
-      const int f = C->sc_f[sc], g = C->sc_g[sc];
-      const int comp = C->sc_comp[sc];
-      const DColB& B = C->cols[g];
-      if (comp < 0) {
-        int64_t v = feat_int(C->feats[f], mu_s + pi * NM, code_s + pi * NC);
-        int64_t cnt = C->row_pieces ? (C->w ? C->w[cb + pi] : 1) : C->psi_i[(cb + pi) * C->psi_i_stride + B.entry];
-        if (B.kind == B_CNTF) {
-          const DFeat& F = B.feat;
-          if (F.c1 >= 0 && code_s[pi * NC + F.c1] != F.v1) cnt = 0;
-          if (F.c2 >= 0 && code_s[pi * NC + F.c2] != F.v2) cnt = 0;
+    if (do_scatter) {
+      const int n_sc = C->n_scatter;
+      for (int t = threadIdx.x; t < np * n_sc; t += blockDim.x) {
+        const int pi = t / n_sc, sc = t % n_sc;
+        const int o = C->sc_out[sc];
+        int64_t row = 0;
+        bool ok = true;
+        for (int k = 0; k < 3; ++k) {
+          const int cidx = C->so_code[o * 3 + k];
+          if (cidx < 0) continue;
+          const int32_t cval = code_s[pi * NC + cidx];
+          if (cval < 0) ok = false;
+          row += (int64_t)cval * C->so_stride[o * 3 + k];
         }
-        v *= cnt;
-        if (v) atomic_add_i64(&C->so_cnt[o][row], v);
-      } else {
-        const double a = feat_d(C->feats[f], mu_s + pi * NM, code_s + pi * NC, atom_s + pi * NA, f < NFI);
-        const double b = col_d<T>(C, B, cb + pi, code_s + pi * NC, atom_s + pi * NA);
-        const double v = a * b;
-        if (v != 0.0) {
-          const int64_t idx = row * C->so_ncomp[o] + comp;
-          if (C->so_vals_f64[o]) atomic_add_f64(&((double*)C->so_vals[o])[idx], v);
-          else atomicAdd(&((float*)C->so_vals[o])[idx], (float)v);
+        if (!ok) continue;
+        const int f = C->sc_f[sc], g = C->sc_g[sc];
+        const int comp = C->sc_comp[sc];
+        const DColB& B = C->cols[g];
+        if (comp < 0) {
+          int64_t v = feat_int(C->feats[f], mu_s + pi * NM, code_s + pi * NC);
+          int64_t cnt = C->row_pieces ? (C->w ? C->w[cb + pi] : 1) : C->psi_i[(cb + pi) * C->psi_i_stride + B.entry];
+          if (B.kind == B_CNTF) {
+            const DFeat& F = B.feat;
+            if (F.c1 >= 0 && code_s[pi * NC + F.c1] != F.v1) cnt = 0;
+            if (F.c2 >= 0 && code_s[pi * NC + F.c2] != F.v2) cnt = 0;
+          }
+          v *= cnt;
+          if (v) scatter_count(C, o, row, v);
+        } else {
+          const double a = feat_d(C->feats[f], mu_s + pi * NM, code_s + pi * NC, atom_s + pi * NA, f < NFI);
+          const double b = col_d<T>(C, B, cb + pi, code_s + pi * NC, atom_s + pi * NA);
+          const double v = a * b;
+          if (v != 0.0) scatter_value(C, o, row, comp, v);
         }
       }
     }
     __syncthreads();
-  }
-  if (over) atomicOr(C->err_flag, 4);
-}
-
-int contract_stage_lds_bytes(const DContract& C) {
-  return (int)((int64_t)kSPieces * (2 * kMaxViews * 8 + C.n_masks * 8 + C.n_atoms * 8 + C.n_codes * 4) + 16);
-}
-int contract_stage_pieces() { return kSPieces; }
-
-void launch_contract_stage(const DContract* d, bool f64, int grid, int lds, hipStream_t s) {
-  if (f64) {
-    allow_lds((const void*)&k_contract_stage<double>, lds);
-    hipLaunchKernelGGL(k_contract_stage<double>, dim3(grid), dim3(256), lds, s, d);
-  } else {
-    allow_lds((const void*)&k_contract_stage<float>, lds);
-    hipLaunchKernelGGL(k_contract_stage<float>, dim3(grid), dim3(256), lds, s, d);
-  }
-}
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int kGemmKC = 32;   // pieces per LDS chunk
-constexpr int kGemmMT = 64;   // features per block: 4 wavefronts x 16 rows
-
-// Block (x, y): K range x, output macro-tile y = (feature tile, column tile).
-// Wavefront w owns feature rows [16w, 16w + 16) of the macro-tile and TN
-// column tiles of 16.  Operand fragments (16x4 of F^T, 4x16 of B) are read
-// from LDS rows padded so that the four K rows of a fragment fall in
-// different bank halves.  Output lane l, register i of a 16x16 tile holds
-// row (l >> 4) + 4 i, column l & 15.
-template <int TN>
-__global__ __launch_bounds__(256) void k_gemm_f64(const DGemm* __restrict__ G) {
-  constexpr int NT = 16 * TN;
-  constexpr int SA = kGemmMT + 16;
-  constexpr int SB = (NT % 32 == 0) ? NT + 16 : NT;
-  __shared__ __align__(16) double As[kGemmKC * SA];
-  __shared__ __align__(16) double Bs[kGemmKC * SB];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int n_ntiles = (G->ng + NT - 1) / NT;
-  const int f0 = (blockIdx.y / n_ntiles) * kGemmMT;
-  const int g0 = (blockIdx.y % n_ntiles) * NT;
-  const int64_t kb = (int64_t)blockIdx.x * G->k_per_block;
-  const int64_t ke = std::min<int64_t>(G->n, kb + G->k_per_block);
-  const int ldf = G->ldf, ldg = G->ldg;
-  f64x4 acc[TN];
 #pragma unroll
-  for (int j = 0; j < TN; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t k0 = kb; k0 < ke; k0 += kGemmKC) {
-    // F chunk: kGemmKC rows x 64 features, as double2 (ldf and f0 are even)
-#pragma unroll
-    for (int j = 0; j < (kGemmKC * kGemmMT / 2) / 256; ++j) {
-      const int e = threadIdx.x + 256 * j;
-      const int r = e / (kGemmMT / 2), c2 = e % (kGemmMT / 2);
-      const int f = f0 + 2 * c2;
-      double2 x = double2{0.0, 0.0};
-      if (k0 + r < ke && f < ldf) x = *(const double2*)(G->F + (k0 + r) * ldf + f);
-      *(double2*)(As + r * SA + 2 * c2) = x;
-    }
-#pragma unroll
-    for (int j = 0; j < (kGemmKC * NT / 2 + 255) / 256; ++j) {
-      const int e = threadIdx.x + 256 * j;
-      if (e < kGemmKC * NT / 2) {
-        const int r = e / (NT / 2), c2 = e % (NT / 2);
-        const int g = g0 + 2 * c2;
-        double2 x = double2{0.0, 0.0};
-        if (k0 + r < ke && g < ldg) x = *(const double2*)(G->B + (k0 + r) * ldg + g);
-        *(double2*)(Bs + r * SB + 2 * c2) = x;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kGemmKC; kk += 4) {
+    for (int kk = 0; kk < kFKC; kk += 4) {
       const int kr = kk + (lane >> 4);
       const double a = As[kr * SA + 16 * w + (lane & 15)];
 #pragma unroll
@@ -1674,7 +1707,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const DGemm* __restrict__ G) {
     }
     __syncthreads();
   }
-  const int64_t ncell = (int64_t)G->nf * G->ng;
+  if (over) atomicOr(C->err_flag, 4);
+  const int64_t ncell = (int64_t)NF * NG;
   double* out = G->part + (int64_t)blockIdx.x * ncell;
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
@@ -1682,27 +1716,30 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const DGemm* __restrict__ G) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int f = f0 + 16 * w + (lane >> 4) + 4 * i;
-      if (f < G->nf && g < G->ng) out[(int64_t)f * G->ng + g] = acc[j][i];
+      if (f < NF && g < NG) out[(int64_t)f * NG + g] = acc[j][i];
     }
   }
 }
 
-int gemm_tile_cols(int ng) { return std::min(8, std::max(1, (ng + 15) / 16)); }
-int gemm_macro_tiles(int nf, int ng) {
-  const int nt = 16 * gemm_tile_cols(ng);
-  return ((nf + kGemmMT - 1) / kGemmMT) * ((ng + nt - 1) / nt);
-}
-int gemm_k_chunk() { return kGemmKC; }
-
-void launch_gemm_f64(const DGemm* d, int tn, int grid_x, int grid_y, hipStream_t s) {
-  dim3 g(grid_x, grid_y), b(256);
+template <typename T>
+static void launch_contract_fused_t(const DContract* c, const DGemm* g, int tn, int gx, int gy, int lds,
+                                    hipStream_t s) {
+  dim3 grid(gx, gy), b(256);
   switch (tn) {
-#define CASE(N) \
-  case N: hipLaunchKernelGGL(k_gemm_f64<N>, g, b, 0, s, d); break;
+#define CASE(N)                                                               \
+  case N:                                                                     \
+    allow_lds((const void*)&k_contract_fused<T, N>, lds);                     \
+    hipLaunchKernelGGL((k_contract_fused<T, N>), grid, b, lds, s, c, g);      \
+    break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: break;
   }
+}
+void launch_contract_fused(const DContract* c, const DGemm* g, bool f64, int tn, int gx, int gy, int lds,
+                           hipStream_t s) {
+  if (f64) launch_contract_fused_t<double>(c, g, tn, gx, gy, lds, s);
+  else launch_contract_fused_t<float>(c, g, tn, gx, gy, lds, s);
 }
 
 // Block-major partial merge: block x takes 16 consecutive cells (one 128-byte

@@ -113,13 +113,12 @@ int contract_tiles(int nf, int ng);
 int contract_threads();
 int contract_max_int_cells();
 void launch_contract(const DContract* d, bool f64, int grid_x, int grid_y, int lds, hipStream_t s);
-int contract_stage_lds_bytes(const DContract& C);
-int contract_stage_pieces();
-void launch_contract_stage(const DContract* d, bool f64, int grid, int lds, hipStream_t s);
 int gemm_tile_cols(int ng);
 int gemm_macro_tiles(int nf, int ng);
-int gemm_k_chunk();
-void launch_gemm_f64(const DGemm* d, int tn, int grid_x, int grid_y, hipStream_t s);
+int contract_fused_lds_bytes(const DContract& C, int tn);
+int contract_fused_chunk();
+void launch_contract_fused(const DContract* c, const DGemm* g, bool f64, int tn, int gx, int gy, int lds,
+                           hipStream_t s);
 void launch_merge_bm(const DCell* cells, int64_t n_cells, const double* part, int n_blocks, int ng, int64_t ncell,
                      int32_t* err_flag, hipStream_t s);
 

@@ -878,7 +878,18 @@ void ProgBuilder::build() {
   // segment is still long
   int64_t min_seg = P.opts.min_segment > 0 ? P.opts.min_segment : 64;
   const int64_t kRowPieceMax = P.opts.row_piece_max == 0 ? (int64_t)1 << 16 : P.opts.row_piece_max;
-  if (R.n_rows <= kRowPieceMax) {
+  // an output whose dense key space is too large is kept in a hash table; its
+  // group is evaluated row by row, where every output's cells are scattered
+  bool hashed = false;
+  for (auto& o : G.outs) {
+    const std::vector<int>& gb = o.kind == 0 ? P.queries[o.id].groupby : P.views[o.id].carried;
+    double cells = 1;
+    for (int a : gb) cells *= (double)P.attrs[a].domain;
+    if (o.kind == 1)
+      for (int a : P.views[o.id].key) cells *= (double)P.attrs[a].domain;
+    hashed |= cells > (double)kDenseRowsMax;
+  }
+  if (R.n_rows <= kRowPieceMax || hashed) {
     g.row_pieces = true;
     g.cut = L + 1;
   } else {
@@ -980,6 +991,9 @@ void ProgBuilder::build() {
       po.key_stride[i] = po.n_rows;
       po.n_rows *= dom[i];
     }
+    po.hashed = po.n_rows > kDenseRowsMax;
+    if (po.hashed && o.kind == 1)
+      fail(LMFAO_EUNSUPPORTED, "view " + std::to_string(o.id) + " at " + R.name + ": key space too large for a dense view");
     po.n_comps = (int)monos.size();
     // split every component monomial into atoms (outer / inner)
     struct Split {

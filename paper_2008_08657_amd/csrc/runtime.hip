@@ -42,10 +42,23 @@ struct OutBuf {
   int64_t* cnt = nullptr;
   void* vals = nullptr;
   int32_t* codes = nullptr;
-  int64_t n_rows = 0;
+  int64_t n_rows = 0;              // dense rows (the key space)
   int n_vals = 0;
   int n_codes = 0;
   bool f64 = true;
+  int hash = -1;                   // index of the hash table holding this output, -1 dense
+};
+
+// a hash table of one query output (key space larger than a dense table)
+struct HashBuf {
+  int query = -1;
+  int64_t cap = 0;                 // slots (power of two)
+  int64_t bound = 0;               // most groups there can be (distinct keys)
+  unsigned long long* keys = nullptr;
+  int64_t* cnt = nullptr;
+  double* vals = nullptr;
+  int n_vals = 0;
+  int fill_step = -1;              // index of its zeroing steps (keys, cnt, vals)
 };
 
 struct NodeData {
@@ -68,8 +81,9 @@ struct Step {
   hipFunction_t gen_fn = nullptr;   // generated kernel (scan steps), else a built-in kernel
   const uint64_t* gen_args = nullptr;
   int gen_block = 0;
+  void* dev2 = nullptr;             // second descriptor (fused contraction: the product's)
   int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract (VALU), 5 merge, 6 image build,
-              // 7 contraction staging, 8 MFMA contraction, 9 block-major merge, 10 filter, 11 finalize
+              // 7 (unused), 8 MFMA contraction, 9 block-major merge, 10 filter, 11 finalize
   int fast = 0;
   void* dev = nullptr;
   int64_t n = 0;
@@ -97,6 +111,10 @@ struct lmfao_prepared_s {
   std::vector<lmfao::OutBuf> qout, vout;
   std::vector<lmfao::OutBuf> uout;                   // range queries of the caller's batch
   std::vector<std::string> gen_sources, gen_failures; // generated scan kernels (and why not)
+  std::vector<lmfao::HashBuf> hashes;
+  lmfao::DHashOut* hash_dev = nullptr;                // device copy of the hash descriptors
+  int hash_regrowths = 0;                             // runs repeated after a hash overflow
+  int32_t* hash_ovf = nullptr;                        // per table overflow flag
   std::vector<std::vector<const void*>> ecols;       // caller's columns, then derived bucket codes
   std::vector<const void* const*> ecol_ptrs;
   std::vector<int32_t*> w_raw, w_sorted;             // filter weights per relation (lazily built)
@@ -113,6 +131,9 @@ struct lmfao_prepared_s {
   ~lmfao_prepared_s() {
     for (auto& e : ev) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
+    for (auto& H : hashes)
+      for (void* p : {(void*)H.keys, (void*)H.cnt, (void*)H.vals})
+        if (p) (void)hipFree(p);
   }
 };
 
@@ -352,74 +373,54 @@ static void* typed_sorted_column(Prep& S, int r, int c, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // descriptors of one group program
 // ---------------------------------------------------------------------------
-// Contraction on the matrix cores: a staging launch writes F and B per piece
-// (FP64), a split-K MFMA launch multiplies them into block-major partials,
-// and a merge adds the partials of every cell of the plan into its output.
+// Contraction on the matrix cores: one launch stages the features F and the
+// columns B of each chunk of pieces in LDS and multiplies them on the matrix
+// cores into block-major partials; a merge adds the partials of every cell of
+// the plan into its output.
 static void build_contract_mfma(Prep& S, const GroupProgram& g, const std::string& gname, DContract& c,
                                 int64_t n_pieces, int psi_f_stride, int psi_i_stride, bool f64, hipStream_t st) {
   const int NF = c.n_feat, NG = c.n_col;
-  c.ldf = std::max(16, (NF + 15) / 16 * 16);
-  c.ldg = std::max(16, (NG + 15) / 16 * 16);
-  const int64_t np1 = std::max<int64_t>(1, n_pieces);
-  c.fmat = (double*)dalloc(S, (size_t)np1 * c.ldf * 8);
-  c.bmat = (double*)dalloc(S, (size_t)np1 * c.ldg * 8);
   c.err_flag = S.err_flag;
   c.part_f = nullptr;
   c.part_i = nullptr;
   c.pieces_per_block = 0;
-  const int lds = contract_stage_lds_bytes(c);
-  if (lds > 160 * 1024) throw PlanError{LMFAO_EUNSUPPORTED, "contraction staging needs more LDS than a CU has"};
-  const int64_t chunks = (n_pieces + contract_stage_pieces() - 1) / contract_stage_pieces();
-  Step st1;
-  st1.name = gname + ":stage";
-  st1.kind = 7;
-  st1.dev = upload(S, c, st);
-  st1.grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, 2048));
-  st1.lds = lds;
-  st1.pieces = n_pieces;
-  st1.rows = n_pieces;
-  for (int i = 0; i < c.n_pcols; ++i) st1.alg_read += (double)n_pieces * (c.pcols[i].dtype == LMFAO_F64 ? 8 : 4);
-  st1.alg_read += (double)n_pieces * (psi_f_stride * (f64 ? 8 : 4) + psi_i_stride * 4);
-  for (int v = 0; v < c.n_views; ++v)
-    st1.alg_read += (double)std::min<int64_t>(c.views[v].n_keys, n_pieces) *
-                    (8 + c.views[v].n_vals * (c.views[v].vals_f64 ? 8 : 4) + c.views[v].n_codes * 4);
-  st1.alg_write = (double)n_pieces * (c.ldf + c.ldg) * 8;
-  S.steps.push_back(st1);
-  if (NF == 0 || NG == 0 || g.gemm_cells.empty()) return;
-
-  const int tn = gemm_tile_cols(NG);
-  const int gy = gemm_macro_tiles(NF, NG);
-  const int64_t kc = gemm_k_chunk();
+  const int tn = gemm_tile_cols(std::max(1, NG));
+  const int gy = gemm_macro_tiles(std::max(1, NF), std::max(1, NG));
+  const int64_t kc = contract_fused_chunk();
   const int64_t want = std::max(1, 512 / gy);   // K splits: ~2 blocks per CU in all
   int64_t kpb = (n_pieces + want - 1) / want;
   kpb = std::max<int64_t>(kc, (kpb + kc - 1) / kc * kc);
   const int gx = (int)std::max<int64_t>(1, (n_pieces + kpb - 1) / kpb);
-  const int64_t ncell = (int64_t)NF * NG;
+  const int64_t ncell = (int64_t)std::max(1, NF) * std::max(1, NG);
   double* part = (double*)dalloc(S, (size_t)gx * ncell * 8);
+  const int lds = contract_fused_lds_bytes(c, tn);
+  if (lds > 160 * 1024) throw PlanError{LMFAO_EUNSUPPORTED, "contraction needs more LDS than a CU has"};
   DGemm gm{};
-  gm.F = c.fmat;
-  gm.B = c.bmat;
   gm.n = n_pieces;
-  gm.ldf = c.ldf;
-  gm.ldg = c.ldg;
   gm.nf = NF;
   gm.ng = NG;
   gm.k_per_block = kpb;
   gm.part = part;
   Step st2;
-  st2.name = gname + ":gemm";
+  st2.name = gname + ":contract";
   st2.kind = 8;
-  st2.dev = upload(S, gm, st);
+  st2.dev = upload(S, c, st);
+  st2.dev2 = upload(S, gm, st);
   st2.grid = gx;
   st2.grid_y = gy;
   st2.na = tn;
+  st2.lds = lds;
   st2.pieces = n_pieces;
   st2.rows = n_pieces;
-  // the staged operands are this launch's input; the partials its output
-  st2.alg_read = (double)n_pieces * (c.ldf + c.ldg) * 8;
-  st2.alg_write = (double)gx * ncell * 8;
+  for (int i = 0; i < c.n_pcols; ++i) st2.alg_read += (double)n_pieces * (c.pcols[i].dtype == LMFAO_F64 ? 8 : 4);
+  st2.alg_read += (double)n_pieces * (psi_f_stride * (f64 ? 8 : 4) + psi_i_stride * 4);
+  for (int v = 0; v < c.n_views; ++v)
+    st2.alg_read += (double)std::min<int64_t>(c.views[v].n_keys, n_pieces) *
+                    (8 + c.views[v].n_vals * (c.views[v].vals_f64 ? 8 : 4) + c.views[v].n_codes * 4);
+  st2.alg_write = (double)gx * NF * NG * 8;
   st2.alg_flop = 2.0 * (double)n_pieces * NF * NG;
   S.steps.push_back(st2);
+  if (NF == 0 || NG == 0 || g.gemm_cells.empty()) return;
 
   std::vector<DCell> cells;
   for (auto& gc : g.gemm_cells) {
@@ -1098,7 +1099,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
   c.sc_f = upload_vec(S, sc_f, st);
   c.sc_g = upload_vec(S, sc_g, st);
   std::vector<int64_t> so_stride;
-  std::vector<int32_t> so_code, so_ncomp, so_f64;
+  std::vector<int32_t> so_code, so_ncomp, so_f64, so_hash;
   std::vector<int64_t*> so_cnt;
   std::vector<void*> so_vals;
   for (auto& po : g.outs) {
@@ -1117,7 +1118,12 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     so_f64.push_back(O.f64 ? 1 : 0);
     so_cnt.push_back(O.cnt);
     so_vals.push_back(O.vals);
+    so_hash.push_back(po.ref.kind == 0 ? O.hash : -1);
+    if (O.hash >= 0 && po.mode != 1)
+      throw PlanError{LMFAO_EINVAL, "internal: hashed output not in scatter mode"};
   }
+  c.so_hash_idx = upload_vec(S, so_hash, st);
+  c.hash_tab = S.hash_dev;
   c.so_stride = upload_vec(S, so_stride, st);
   c.so_code = upload_vec(S, so_code, st);
   c.so_ncomp = upload_vec(S, so_ncomp, st);
@@ -1188,6 +1194,22 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
   }
 }
 
+// (re)allocates the slots of a hash table; old slots are released
+static void alloc_hash(Prep& S, HashBuf& H) {
+  for (void* p : {(void*)H.keys, (void*)H.cnt, (void*)H.vals})
+    if (p) (void)hipFree(p);
+  auto get = [&](size_t bytes) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) throw PlanError{LMFAO_ENOMEM, "hash table of " + std::to_string(H.cap) + " slots: " +
+                                                        hipGetErrorString(e)};
+    return p;
+  };
+  H.keys = (unsigned long long*)get(H.cap * 8);
+  H.cnt = (int64_t*)get(H.cap * 8);
+  H.vals = (double*)get(H.cap * 8 * std::max(1, H.n_vals));
+}
+
 static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_t st) {
   Plan& P = *S.P;
   S.nodes.assign(P.rels.size(), NodeData{});
@@ -1255,11 +1277,27 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
   for (size_t q = 0; q < P.queries.size(); ++q) {
     const QueryDef& Q = P.queries[q];
     OutBuf& B = S.qout[q];
+    double dense = 1;
     B.n_rows = 1;
-    for (int a : Q.groupby) B.n_rows *= P.attrs[a].domain;
-    if (B.n_rows > ((int64_t)1 << 31)) throw PlanError{LMFAO_EUNSUPPORTED, "group-by domain too large for a dense table"};
+    for (int a : Q.groupby) {
+      dense *= (double)P.attrs[a].domain;
+      B.n_rows = dense > 9e18 ? INT64_MAX : B.n_rows * P.attrs[a].domain;
+    }
     B.f64 = true;
     B.n_vals = (int)Q.aggs.size();
+    if (dense > (double)kDenseRowsMax) {
+      // hash table: at most one group per tuple of the root relation
+      HashBuf H;
+      H.query = (int)q;
+      H.bound = (int64_t)std::min<double>(dense, (double)std::max<int64_t>(1, P.rels[Q.root].n_rows));
+      H.n_vals = B.n_vals;
+      int64_t want = P.opts.hash_slots > 0 ? P.opts.hash_slots : std::max<int64_t>(1024, 2 * H.bound);
+      H.cap = 1;
+      while (H.cap < want) H.cap <<= 1;
+      B.hash = (int)S.hashes.size();
+      S.hashes.push_back(H);
+      continue;
+    }
     carve.push_back({(void**)&B.cnt, (size_t)B.n_rows * 8});
     carve.push_back({&B.vals, (size_t)B.n_rows * B.n_vals * 8});
   }
@@ -1268,6 +1306,7 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
     const UserQuery& U = P.user[u];
     if (!U.range) continue;
     const OutBuf& Q = S.qout[U.internal];
+    if (Q.hash >= 0) throw PlanError{LMFAO_EUNSUPPORTED, "a range condition on a query kept in a hash table"};
     OutBuf& B = S.uout[u];
     B.n_rows = Q.n_rows / U.nb;
     B.f64 = true;
@@ -1284,6 +1323,22 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
     off += (c.second + 255) & ~(size_t)255;
   }
   add_fill(S, base, (int64_t)arena, "zero");
+  add_fill(S, S.err_flag, 8, "flags");
+  if (!S.hashes.empty()) {
+    S.hash_ovf = (int32_t*)dalloc(S, S.hashes.size() * 4);
+    add_fill(S, S.hash_ovf, (int64_t)S.hashes.size() * 4, "hash flags");
+    std::vector<DHashOut> hd(S.hashes.size());
+    for (size_t i = 0; i < S.hashes.size(); ++i) {
+      HashBuf& H = S.hashes[i];
+      alloc_hash(S, H);
+      H.fill_step = (int)S.steps.size();
+      add_fill(S, H.keys, H.cap * 8, "hash keys");
+      add_fill(S, H.cnt, H.cap * 8, "hash counts");
+      add_fill(S, H.vals, H.cap * 8 * std::max(1, H.n_vals), "hash values");
+      hd[i] = DHashOut{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0};
+    }
+    S.hash_dev = upload_vec(S, hd, st);
+  }
   // groups in dependency-level order
   std::vector<int> gorder(P.groups.size());
   std::iota(gorder.begin(), gorder.end(), 0);
@@ -1328,7 +1383,7 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
 
 // timed steps: scans and contractions (the kernels that move the data); the
 // whole run is timed as well.  Slot 0 of a run = whole run.
-static bool timed_step(const Step& s) { return s.kind == 2 || s.kind == 4 || s.kind == 7 || s.kind == 8; }
+static bool timed_step(const Step& s) { return s.kind == 2 || s.kind == 4 || s.kind == 8; }
 static int timed_slots(const Prep& S) {
   int n = 1;
   for (auto& s : S.steps) n += timed_step(s);
@@ -1372,8 +1427,10 @@ static void enqueue_run(Prep& S, hipStream_t st) {
       case 5:
         launch_merge_cells((const DCell*)s.dev, s.n, s.part_f, s.part_i, s.n_blocks, s.NF, s.NG, s.NFI, s.NGI, st);
         break;
-      case 7: launch_contract_stage((const DContract*)s.dev, S.f64, s.grid, s.lds, st); break;
-      case 8: launch_gemm_f64((const DGemm*)s.dev, s.na, s.grid, s.grid_y, st); break;
+      case 8:
+        launch_contract_fused((const DContract*)s.dev, (const DGemm*)s.dev2, S.f64, s.na, s.grid, s.grid_y, s.lds,
+                              st);
+        break;
       case 9:
         launch_merge_bm((const DCell*)s.dev, s.n, s.part_f, s.n_blocks, s.NG, (int64_t)s.NF * s.NG, S.err_flag, st);
         break;
@@ -1496,6 +1553,34 @@ lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns,
   return LMFAO_OK;
 }
 
+// Grows every hash table whose inserts overflowed (x4, up to twice its bound)
+// and refreshes the descriptors the kernels read.  Returns false when a
+// table is already at its largest size.
+static bool grow_hashes(Prep& S, hipStream_t st) {
+  std::vector<int32_t> ovf(S.hashes.size(), 0);
+  HIP_OK(hipMemcpy(ovf.data(), S.hash_ovf, ovf.size() * 4, hipMemcpyDeviceToHost));
+  bool grown = false;
+  for (size_t i = 0; i < S.hashes.size(); ++i) {
+    if (!ovf[i]) continue;
+    HashBuf& H = S.hashes[i];
+    int64_t top = 1;
+    while (top < 2 * H.bound) top <<= 1;
+    if (H.cap >= std::max<int64_t>(top, 1024)) return false;
+    H.cap = std::min(H.cap * 4, std::max<int64_t>(top, 1024));
+    alloc_hash(S, H);
+    S.steps[H.fill_step].dev = H.keys;
+    S.steps[H.fill_step].bytes = H.cap * 8;
+    S.steps[H.fill_step + 1].dev = H.cnt;
+    S.steps[H.fill_step + 1].bytes = H.cap * 8;
+    S.steps[H.fill_step + 2].dev = H.vals;
+    S.steps[H.fill_step + 2].bytes = H.cap * 8 * std::max(1, H.n_vals);
+    DHashOut d{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0};
+    HIP_OK(hipMemcpy(S.hash_dev + i, &d, sizeof d, hipMemcpyHostToDevice));
+    grown = true;
+  }
+  return grown;
+}
+
 lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, int32_t sync) {
   g_last_error.clear();
   if (!plan || !prep || prep->P != plan->P) return set_err(LMFAO_EINVAL, "plan and prepared handle do not match");
@@ -1506,6 +1591,15 @@ lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, i
       HIP_OK(hipStreamSynchronize(st));
       int32_t flag = 0;
       HIP_OK(hipMemcpy(&flag, prep->err_flag, 4, hipMemcpyDeviceToHost));
+      // a hash table that was sized too small: enlarge it and run again
+      while (flag & 8) {
+        if (!grow_hashes(*prep, st))
+          return set_err(LMFAO_EOVERFLOW, "a hash table at its largest size still overflowed");
+        prep->hash_regrowths++;
+        enqueue_run(*prep, st);
+        HIP_OK(hipStreamSynchronize(st));
+        HIP_OK(hipMemcpy(&flag, prep->err_flag, 4, hipMemcpyDeviceToHost));
+      }
       if (flag & 1) return set_err(LMFAO_EINVAL, "a relation has duplicate values of its declared primary key");
       if (flag & 2) return set_err(LMFAO_EINVAL, "an integer column holds a value outside its declared domain");
       if (flag & 4)
@@ -1514,6 +1608,39 @@ lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, i
     }
   } catch (const HipError& e) {
     return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
+// dense image of a hashed output: rows with their counts and values, in row order
+struct Gathered {
+  std::vector<int64_t> rows, cnt;
+  std::vector<double> vals;
+};
+static lmfao_status gather_hash(const lmfao_prepared_s* prep, const OutBuf& B, Gathered& g) {
+  const HashBuf& H = prep->hashes[B.hash];
+  std::vector<unsigned long long> keys(H.cap);
+  std::vector<int64_t> cnt(H.cap);
+  std::vector<double> vals((size_t)H.cap * std::max(1, H.n_vals));
+  try {
+    int32_t flag = 0;
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(&flag, prep->err_flag, 4, hipMemcpyDeviceToHost));
+    if (flag & 8) return set_err(LMFAO_EOVERFLOW, "a hash table overflowed in the last run (run with sync)");
+    HIP_OK(hipMemcpy(keys.data(), H.keys, H.cap * 8, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(cnt.data(), H.cnt, H.cap * 8, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(vals.data(), H.vals, vals.size() * 8, hipMemcpyDeviceToHost));
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  std::vector<int64_t> order;
+  for (int64_t i = 0; i < H.cap; ++i)
+    if (keys[i] && cnt[i] > 0) order.push_back(i);
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return keys[a] < keys[b]; });
+  for (int64_t i : order) {
+    g.rows.push_back((int64_t)keys[i] - 1);
+    g.cnt.push_back(cnt[i]);
+    for (int k = 0; k < H.n_vals; ++k) g.vals.push_back(vals[(size_t)i * H.n_vals + k]);
   }
   return LMFAO_OK;
 }
@@ -1536,15 +1663,22 @@ lmfao_status lmfao_result_shape(lmfao_prepared_t prep, int32_t q, int64_t* n_gro
   if (!prep || q < 0 || q >= (int)prep->P->user.size()) return set_err(LMFAO_EINVAL, "bad query index");
   int nk = 0;
   const OutBuf& B = user_out(prep, q, &nk);
-  std::vector<int64_t> cnt(B.n_rows);
-  try {
-    HIP_OK(hipDeviceSynchronize());
-    HIP_OK(hipMemcpy(cnt.data(), B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
-  } catch (const HipError& e) {
-    return set_err(LMFAO_EHIP, e.msg);
-  }
   int64_t g = 0;
-  for (int64_t c : cnt) g += c > 0;
+  if (B.hash >= 0) {
+    Gathered gh;
+    lmfao_status st = gather_hash(prep, B, gh);
+    if (st) return st;
+    g = (int64_t)gh.rows.size();
+  } else {
+    std::vector<int64_t> cnt(B.n_rows);
+    try {
+      HIP_OK(hipDeviceSynchronize());
+      HIP_OK(hipMemcpy(cnt.data(), B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
+    } catch (const HipError& e) {
+      return set_err(LMFAO_EHIP, e.msg);
+    }
+    for (int64_t c : cnt) g += c > 0;
+  }
   if (n_groups) *n_groups = g;
   if (n_keys) *n_keys = nk;
   if (n_aggs) *n_aggs = B.n_vals;
@@ -1557,6 +1691,27 @@ lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, 
   const QueryDef& Q = P.queries[P.user[q].internal];
   int nk = 0;
   const OutBuf& B = user_out(prep, q, &nk);
+  std::vector<int64_t> dom(nk);
+  for (int i = 0; i < nk; ++i) dom[i] = P.attrs[Q.groupby[i]].domain;
+  auto emit = [&](int64_t g, int64_t row, int64_t c, const double* v) {
+    if (keys) {
+      int64_t x = row;
+      for (int i = nk - 1; i >= 0; --i) {
+        keys[g * nk + i] = x % dom[i];
+        x /= dom[i];
+      }
+    }
+    if (counts) counts[g] = c;
+    if (values)
+      for (int k = 0; k < B.n_vals; ++k) values[g * B.n_vals + k] = v[k];
+  };
+  if (B.hash >= 0) {
+    Gathered gh;
+    lmfao_status st = gather_hash(prep, B, gh);
+    if (st) return st;
+    for (size_t i = 0; i < gh.rows.size(); ++i) emit((int64_t)i, gh.rows[i], gh.cnt[i], gh.vals.data() + i * B.n_vals);
+    return LMFAO_OK;
+  }
   std::vector<int64_t> cnt(B.n_rows);
   std::vector<double> vals((size_t)B.n_rows * B.n_vals);
   try {
@@ -1566,22 +1721,10 @@ lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, 
   } catch (const HipError& e) {
     return set_err(LMFAO_EHIP, e.msg);
   }
-  std::vector<int64_t> dom(nk);
-  for (int i = 0; i < nk; ++i) dom[i] = P.attrs[Q.groupby[i]].domain;
   int64_t g = 0;
   for (int64_t row = 0; row < B.n_rows; ++row) {
     if (cnt[row] <= 0) continue;
-    if (keys) {
-      int64_t x = row;
-      for (int i = nk - 1; i >= 0; --i) {
-        keys[g * nk + i] = x % dom[i];
-        x /= dom[i];
-      }
-    }
-    if (counts) counts[g] = cnt[row];
-    if (values)
-      for (int k = 0; k < B.n_vals; ++k) values[g * B.n_vals + k] = vals[(size_t)row * B.n_vals + k];
-    ++g;
+    emit(g++, row, cnt[row], vals.data() + (size_t)row * B.n_vals);
   }
   return LMFAO_OK;
 }
@@ -1619,7 +1762,7 @@ lmfao_status lmfao_ridge_sigma(lmfao_prepared_t prep, int32_t n_cont, const char
   // (group-by attributes, monomial) -> output values of a planned query without a range
   std::map<std::pair<std::vector<int>, Mono>, std::pair<const OutBuf*, int>> have;
   for (size_t u = 0; u < P.user.size(); ++u) {
-    if (P.user[u].range) continue;
+    if (P.user[u].range || prep->qout[P.user[u].internal].hash >= 0) continue;
     const QueryDef& Q = P.queries[P.user[u].internal];
     for (size_t k = 0; k < Q.aggs.size(); ++k)
       have.emplace(std::make_pair(Q.groupby, Q.aggs[k]), std::make_pair(&prep->qout[P.user[u].internal], (int)k));
@@ -1793,8 +1936,8 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     if (s.kind == 0) continue;
     if (!first) j += ",";
     first = false;
-    static const char* kinds[] = {"fill",  "view_build", "scan", "table_reduce", "contract", "merge",
-                                  "image", "stage",      "gemm", "merge",        "filter",   "finalize"};
+    static const char* kinds[] = {"fill",  "view_build", "scan",     "table_reduce", "contract", "merge",
+                                  "image", "stage",      "contract", "merge",        "filter",   "finalize"};
     static_assert(sizeof(kinds) / sizeof(kinds[0]) == 12, "one name per step kind");
     char tmp[512];
     snprintf(tmp, sizeof(tmp),
@@ -1819,7 +1962,14 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     }
     j += "\"" + m + "\"";
   }
-  j += "],\"generated_scans\":" + std::to_string(prep->gen_sources.size()) + "}";
+  j += "],\"generated_scans\":" + std::to_string(prep->gen_sources.size());
+  j += ",\"hash_tables\":[";
+  for (size_t i = 0; i < prep->hashes.size(); ++i) {
+    if (i) j += ",";
+    j += "{\"query\":" + std::to_string(prep->hashes[i].query) + ",\"slots\":" + std::to_string(prep->hashes[i].cap) +
+         ",\"bound\":" + std::to_string(prep->hashes[i].bound) + "}";
+  }
+  j += "],\"hash_regrowths\":" + std::to_string(prep->hash_regrowths) + "}";
   if (need) *need = j.size() + 1;
   if (buf && cap) {
     size_t n = std::min(cap - 1, j.size());

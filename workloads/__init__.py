@@ -458,5 +458,48 @@ def cart_node(seed: int = 0, n_inv: int = 84_000_000, n_thr: int = 20, n_node_co
 
 
 
-def rkmeans_chain(*a, **k):  # pragma: no cover
-    raise NotImplementedError("Rk-means chain generator is not built yet")
+def rkmeans_chain(seed: int = 0, n1: int = 50_000_000, n2: int = 5_000_000, n3: int = 200_000,
+                  n_x: int = 40, n_y: int = 30, n_z: int = 30, max_dom: int = 1_000_000):
+    """Step 1 of Rk-means (section 3, Rk-means) on a chain join R1(a, b, x*) -
+    R2(b, c, y*) - R3(c, z*) with foreign keys b and c (every R1 row joins
+    exactly once).  Attribute j takes values k ~ U[0, d_j) with d_j =
+    round(10^U(1, log10 max_dom)); the values are integers, stored as int32
+    codes with domain d_j.  Batch: SUM(1) GROUP BY X_j for each of the
+    n_x + n_y + n_z attributes, plus SUM(1) GROUP BY X_i, X_j for 10 pairs
+    (4 within R1, 2 within R2, 1 within R3, 2 across R1 x R2, 1 across
+    R1 x R3) picked by seed from domain-sorted attributes so that their group
+    counts spread from small to large."""
+    r1, r2, r3, rd = _spawn(seed, 4)
+    top = np.log10(max_dom)
+    names = ([f"x{j}" for j in range(1, n_x + 1)] + [f"y{j}" for j in range(1, n_y + 1)]
+             + [f"z{j}" for j in range(1, n_z + 1)])
+    dom = {a: int(max(2, round(10 ** rd.uniform(1, top)))) for a in names}
+    R1 = {"a": np.arange(n1, dtype=np.int32), "b": r1.integers(0, n2, n1, dtype=np.int32)}
+    R2 = {"b": np.arange(n2, dtype=np.int32), "c": r2.integers(0, n3, n2, dtype=np.int32)}
+    R3 = {"c": np.arange(n3, dtype=np.int32)}
+    for rel, rng, pre, cnt, n in ((R1, r1, "x", n_x, n1), (R2, r2, "y", n_y, n2), (R3, r3, "z", n_z, n3)):
+        for j in range(1, cnt + 1):
+            a = f"{pre}{j}"
+            rel[a] = rng.integers(0, dom[a], n, dtype=np.int32)
+    schema = [
+        _rel("R1", n1, [_attr("a", "i32"), _attr("b", "i32", n2)]
+             + [_attr(f"x{j}", "i32", dom[f"x{j}"]) for j in range(1, n_x + 1)]),
+        _rel("R2", n2, [_attr("b", "i32", n2, True), _attr("c", "i32", n3)]
+             + [_attr(f"y{j}", "i32", dom[f"y{j}"]) for j in range(1, n_y + 1)]),
+        _rel("R3", n3, [_attr("c", "i32", n3, True)]
+             + [_attr(f"z{j}", "i32", dom[f"z{j}"]) for j in range(1, n_z + 1)]),
+    ]
+    batch = [{"groupby": [a], "where": [], "aggs": [[]], "root": None} for a in names]
+    xs = sorted((a for a in names if a[0] == "x"), key=lambda a: dom[a])
+    ys = sorted((a for a in names if a[0] == "y"), key=lambda a: dom[a])
+    zs = sorted((a for a in names if a[0] == "z"), key=lambda a: dom[a])
+
+    # pairs by domain rank: small x small up to the two largest domains
+    m = len(xs) // 2
+    pairs = [(xs[0], xs[1]), (xs[m], xs[m + 1]), (xs[-1], xs[0]), (xs[-1], xs[-2]),
+             (ys[0], ys[1]), (ys[-1], ys[-2]), (zs[0], zs[-1]),
+             (xs[0], ys[-1]), (xs[-1], ys[0]), (xs[m], zs[len(zs) // 2])]
+    batch += [{"groupby": [a, b], "where": [], "aggs": [[]], "root": None} for a, b in pairs]
+    data = {"R1": R1, "R2": R2, "R3": R3}
+    return {"name": "rkmeans_chain", "schema": schema, "tree": [(0, 1), (1, 2)], "batch": batch,
+            "data": data, "policy": "fact", "precision": "f32", "domains": dom, "pairs": pairs}
