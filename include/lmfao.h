@@ -166,10 +166,40 @@ typedef struct {
                             (falls back to the built-in kernel if that
                             fails); 1: built-in kernels only               */
   int64_t hash_slots;    /* initial slots of every hash table (outputs whose
-                            dense key space exceeds 2^24 cells); 0 = twice
-                            the most groups the query can have.  A run with
-                            sync grows a table that overflowed and repeats */
+                            dense key space exceeds 2^24 cells); 0 = sized
+                            by `sizing`.  A run with sync grows a table that
+                            overflowed (x4) and repeats, so results never
+                            depend on the initial size                     */
+  int32_t sizing;        /* LMFAO_SIZING_*                                    */
+  const float* estimator;/* HOST estimator blob (layout below), copied by
+                            lmfao_plan; NULL = none                          */
+  int64_t estimator_len; /* floats in `estimator`                            */
 } lmfao_options;
+
+/* Initial capacity of a hash table.  BOUND: twice the most groups the output
+ * can have -- the product over its key attributes of their distinct counts
+ * (counted on the GPU at prepare time), the dense key space, and, when every
+ * relation joins the query's root through a primary key (so D has at most one
+ * tuple per root tuple), the root's row count.  LEARNED: the group count the
+ * estimator predicts, 2^(y + margin) - 1, at half occupancy, never above the
+ * BOUND capacity and never below 1024 slots.  Both round up to a power of
+ * two.  LEARNED without an estimator blob behaves as BOUND. */
+enum { LMFAO_SIZING_BOUND = 0, LMFAO_SIZING_LEARNED = 1 };
+
+/* Estimator blob: {version = 1, d = LMFAO_EST_FEATURES, h, margin},
+ * then d feature means, d feature standard deviations, then the
+ * lmfao_mlp_size(d, h) network parameters (layout of lmfao_mlp_train).  The
+ * network maps standardized features (x - mean) / std to log2(1 + groups).
+ * Features of an output with key attributes K, in order (log2 means
+ * log2(1 + value); per-key slots follow K's order, zero past |K| or past 3):
+ *   0 log2 rows of the query's root relation   1 log2 total rows of all relations
+ *   2 number of relations                      3 |K|
+ *   4..6 log2 distinct count of each key       7..9 log2 domain of each key
+ *   10..12 tree distance from the root to the nearest relation holding the key
+ *   13 log2 product of the distinct counts     14 log2 of the BOUND group count
+ *   15 1 if D has at most one tuple per root tuple, else 0
+ *   16 number of conditions of the batch-wide filter */
+#define LMFAO_EST_FEATURES 17
 
 typedef struct lmfao_plan_s* lmfao_plan_t;
 typedef struct lmfao_prepared_s* lmfao_prepared_t;
@@ -281,6 +311,43 @@ lmfao_status lmfao_ridge_sigma(lmfao_prepared_t prep, int32_t n_cont, const char
                                const char* const* cat, double* sigma, int32_t* dim_out, void* stream);
 lmfao_status lmfao_ridge_bgd(const double* sigma, int32_t dim, int32_t label, double lambda, double eta,
                              int32_t max_iter, double tol, double* theta, double* stats, void* stream);
+
+/* Estimator features (layout above) of query q of the caller's batch as
+ * prepared (distinct counts are counted on the GPU on first use, on the
+ * prepared stream, which is synchronised).  `feats` is a HOST array of
+ * LMFAO_EST_FEATURES floats.  LMFAO_EINVAL for a bad q or a query without
+ * group-by attributes. */
+lmfao_status lmfao_prepared_features(lmfao_prepared_t prep, int32_t q, float* feats);
+
+/* Group-count estimator (not part of the paper's method; it sizes the hash
+ * tables of outputs whose dense key space is too large, with overflow
+ * regrowth as the exact fallback).  A perceptron x (d features) ->
+ * relu(x W1 + b1) (h) -> relu(. W2 + b2) (h) -> . w3 + b3, in FP32, trained on
+ * the mean squared error with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * `params` is one flat FP32 array of lmfao_mlp_size(d, h) values in the order
+ * W1 (d x h, row-major), b1, W2 (h x h, row-major), b2, w3, b3.  X (n x d,
+ * row-major FP32), t (n FP32 targets), params, grad, y and order are DEVICE
+ * pointers owned by the caller; `loss` and `loss_trace` are HOST pointers
+ * (may be NULL).  Each call allocates its own scratch, runs on `stream` and
+ * synchronises before returning.  LMFAO_EINVAL for non-positive sizes or a
+ * NULL required pointer, LMFAO_ENOMEM if scratch cannot be allocated.
+ *
+ * lmfao_mlp_grad: gradient of the batch's mean squared error (written to
+ * grad, same layout as params) and the loss.
+ * lmfao_mlp_predict: y = network(X).
+ * lmfao_mlp_train: n_steps Adam steps at learning rate lr; step s uses the
+ * rows order[s*batch .. s*batch+batch) of X and t (int32 indices below n,
+ * n_steps*batch of them, drawn by the caller; an index outside [0, n) gives
+ * LMFAO_EINVAL before any step); loss_trace[s] receives the
+ * mean squared error of step s's batch before its update. */
+lmfao_status lmfao_mlp_size(int32_t d, int32_t h, int64_t* n_params);
+lmfao_status lmfao_mlp_grad(int32_t d, int32_t h, const float* params, const float* X, const float* t, int32_t n,
+                            float* grad, float* loss, void* stream);
+lmfao_status lmfao_mlp_predict(int32_t d, int32_t h, const float* params, const float* X, int32_t n, float* y,
+                               void* stream);
+lmfao_status lmfao_mlp_train(int32_t d, int32_t h, float* params, const float* X, const float* t, int32_t n,
+                             const int32_t* order, int32_t n_steps, int32_t batch, float lr, float* loss_trace,
+                             void* stream);
 
 void lmfao_plan_free(lmfao_plan_t plan);
 void lmfao_prepared_free(lmfao_prepared_t prep);

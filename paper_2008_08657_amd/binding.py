@@ -72,7 +72,8 @@ class lmfao_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("form", C.c_int32), ("root_policy", C.c_int32),
                 ("n_order", C.POINTER(C.c_int32)), ("order", C.POINTER(C.POINTER(C.c_char_p))),
                 ("min_segment", C.c_int32), ("row_piece_max", C.c_int64),
-                ("contraction", C.c_int32), ("codegen", C.c_int32), ("hash_slots", C.c_int64)]
+                ("contraction", C.c_int32), ("codegen", C.c_int32), ("hash_slots", C.c_int64),
+                ("sizing", C.c_int32), ("estimator", C.POINTER(C.c_float)), ("estimator_len", C.c_int64)]
 
 
 class LmfaoError(RuntimeError):
@@ -192,7 +193,8 @@ class Plan:
     """A plan handle (``lmfao_plan``)."""
 
     def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
-                 min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0):
+                 min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0,
+                 sizing="bound", estimator=None):
         self.lib = load_library()
         self.problem = problem
         keep = _Keep()
@@ -210,6 +212,18 @@ class Plan:
         opts.contraction = 0 if contraction == "mfma" else 1
         opts.codegen = 0 if codegen else 1
         opts.hash_slots = int(hash_slots)
+        if sizing not in ("bound", "learned"):
+            raise ValueError(f"sizing must be 'bound' or 'learned', not {sizing!r}")
+        opts.sizing = 0 if sizing == "bound" else 1
+        if sizing == "learned" and estimator is None:
+            from . import estimator as _est
+            estimator = _est.load()
+        if estimator is not None:
+            import numpy as np
+            blob = np.ascontiguousarray(estimator, dtype=np.float32)
+            keep.refs.append(blob)
+            opts.estimator = blob.ctypes.data_as(C.POINTER(C.c_float))
+            opts.estimator_len = int(blob.size)
         if order:
             names = [r["name"] for r in problem["schema"]]
             n_order = [len(order.get(n, [])) for n in names]
@@ -276,6 +290,15 @@ class Prepared:
         buf = C.create_string_buffer(need.value)
         _check(self.lib, self.lib.lmfao_prepared_describe(self.handle, buf, need.value, C.byref(need)))
         return json.loads(buf.value.decode())
+
+    def features(self, q: int):
+        """Estimator features of query q (``lmfao_prepared_features``), or None
+        for a query without group-by attributes."""
+        f = (C.c_float * 17)()
+        st = self.lib.lmfao_prepared_features(self.handle, int(q), f)
+        if st != 0:
+            return None
+        return list(f)
 
     def timing(self):
         n = C.c_int32()
@@ -359,6 +382,66 @@ def ridge_bgd(sigma, label: int, lam: float, eta: float = 0.0, max_iter: int = 2
                                     C.c_double(eta), int(max_iter), C.c_double(tol),
                                     C.c_void_p(theta.data_ptr()), stats, C.c_void_p(stream) if stream else None))
     return theta, int(stats[0]), float(stats[1]), float(stats[2])
+
+
+def _stream_arg(stream):
+    return C.c_void_p(stream) if stream else None
+
+
+def mlp_size(d: int, h: int) -> int:
+    """Number of FP32 parameters of the estimator network (``lmfao_mlp_size``)."""
+    lib = load_library()
+    n = C.c_int64()
+    _check(lib, lib.lmfao_mlp_size(int(d), int(h), C.byref(n)))
+    return int(n.value)
+
+
+def _f32_dev(x, name):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    return C.c_void_p(x.data_ptr())
+
+
+def mlp_grad(params, X, t, h: int, stream=None):
+    """Gradient and loss of the mean squared error on device tensors
+    (``lmfao_mlp_grad``).  Returns (grad tensor, loss)."""
+    import torch
+    lib = load_library()
+    n, d = int(X.shape[0]), int(X.shape[1])
+    grad = torch.empty_like(params)
+    loss = C.c_float()
+    _check(lib, lib.lmfao_mlp_grad(d, int(h), _f32_dev(params, "params"), _f32_dev(X, "X"), _f32_dev(t, "t"), n,
+                                   _f32_dev(grad, "grad"), C.byref(loss), _stream_arg(stream)))
+    return grad, float(loss.value)
+
+
+def mlp_predict(params, X, h: int, stream=None):
+    """Network outputs for the rows of X (``lmfao_mlp_predict``)."""
+    import torch
+    lib = load_library()
+    n, d = int(X.shape[0]), int(X.shape[1])
+    y = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib, lib.lmfao_mlp_predict(d, int(h), _f32_dev(params, "params"), _f32_dev(X, "X"), n,
+                                      _f32_dev(y, "y"), _stream_arg(stream)))
+    return y
+
+
+def mlp_train(params, X, t, order, batch: int, h: int, lr: float = 1e-3, stream=None):
+    """Adam steps in place on ``params`` (``lmfao_mlp_train``); ``order`` is an
+    int32 device tensor of n_steps*batch row indices.  Returns the per-step
+    batch losses."""
+    import torch
+    lib = load_library()
+    n, d = int(X.shape[0]), int(X.shape[1])
+    if not (order.is_cuda and order.dtype == torch.int32 and order.is_contiguous()):
+        raise TypeError("order must be a contiguous int32 CUDA tensor")
+    steps = int(order.numel()) // int(batch)
+    trace = (C.c_float * max(steps, 1))()
+    _check(lib, lib.lmfao_mlp_train(d, int(h), _f32_dev(params, "params"), _f32_dev(X, "X"), _f32_dev(t, "t"), n,
+                                    C.c_void_p(order.data_ptr()), steps, int(batch), C.c_float(lr), trace,
+                                    _stream_arg(stream)))
+    return list(trace)[:steps]
 
 
 def device_columns(problem, device="cuda:0"):

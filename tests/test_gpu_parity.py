@@ -196,3 +196,28 @@ def test_forms_agree(eng, form):
     p["batch"] = p["batch"][::7]
     check(eng, p, F32_TOL, f"retail_{form}", precision="f32", policy="fact", form=form, row_piece_max=5_000,
           min_segment=16)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+@pytest.mark.parametrize("hash_slots", [0, 1024])
+def test_rkmeans_chain(eng, seed, hash_slots):
+    # step 1 of Rk-means: SUM(1) grouped by each attribute and by pairs; pairs whose key
+    # space is too large for a dense table go to hash tables (sized small on purpose
+    # in the second case, so that the run must grow them and repeat)
+    p = W.rkmeans_chain(seed=seed, n1=30_000, n2=3_000, n3=300, n_x=8, n_y=6, n_z=6, max_dom=30_000)
+    print(f"[case] rkmeans seed {seed} hash_slots {hash_slots}", flush=True)
+    plan = eng.Plan(p, precision="f32", policy="fact", hash_slots=hash_slots)
+    prep = eng.Prepared(plan, eng.device_columns(p))
+    prep.run(sync=True)
+    res = prep.results()
+    compare_all(res, oracle.evaluate(p), F32_TOL, f"rkmeans_{seed}_{hash_slots}")
+    d = prep.describe()
+    assert len(d["hash_tables"]) >= 1
+    if hash_slots:
+        assert d["hash_regrowths"] >= 1
+    # a second run reuses the grown tables and gives the same groups
+    prep.run(sync=True)
+    again = prep.results()
+    for x, y in zip(res, again):
+        np.testing.assert_array_equal(x["keys"], y["keys"])
+        np.testing.assert_array_equal(x["count"], y["count"])
