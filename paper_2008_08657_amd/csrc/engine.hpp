@@ -277,6 +277,7 @@ struct Plan {
   std::vector<UserQuery> user;           // caller's queries, in batch order
   int n_levels = 0;
   lmfao_options opts;
+  std::vector<float> estimator;          // copy of the estimator blob (empty = none)
   bool supported = true;
   std::string unsupported_reason;
   std::vector<std::vector<char>> uniq;   // uniq[n][p]: V_{n->p} unique (adjacency)

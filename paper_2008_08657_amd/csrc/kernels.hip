@@ -538,6 +538,35 @@ void launch_validate(const int32_t* col, int64_t n, int64_t dom, int32_t* err_fl
   hipLaunchKernelGGL(k_validate, dim3(grid), dim3(256), 0, s, col, n, dom, err_flag);
 }
 
+// distinct values of an integer column with values in [0, dom): one bit per
+// value, then a population count of the bitmap.  Values were validated
+// against the domain at prepare time.
+__global__ void k_mark_values(const int32_t* __restrict__ col, int64_t n, uint32_t* __restrict__ bits) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = (uint32_t)col[i];
+    atomicOr(bits + (v >> 5), 1u << (v & 31));
+  }
+}
+__global__ void k_popcount(const uint32_t* __restrict__ bits, int64_t words, unsigned long long* __restrict__ out) {
+  unsigned long long c = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+    c += __popc(bits[i]);
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+void launch_distinct(const int32_t* col, int64_t n, int64_t dom, uint32_t* bits, unsigned long long* out,
+                     hipStream_t s) {
+  const int64_t words = (dom + 31) / 32;
+  (void)hipMemsetAsync(bits, 0, (size_t)std::max<int64_t>(words, 1) * 4, s);
+  (void)hipMemsetAsync(out, 0, 8, s);
+  if (n > 0) {
+    int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_mark_values, dim3(grid), dim3(256), 0, s, col, n, bits);
+  }
+  int grid = (int)std::min<int64_t>((words + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_popcount, dim3(std::max(grid, 1)), dim3(256), 0, s, bits, words, out);
+}
+
 void launch_make_keys(const DKeyCols* d, uint64_t* keys, uint32_t* idx, int64_t n, hipStream_t s) {
   int grid = (int)std::min<int64_t>((n + 255) / 256, 16384);
   hipLaunchKernelGGL(k_make_keys, dim3(grid), dim3(256), 0, s, d, keys, idx, n);

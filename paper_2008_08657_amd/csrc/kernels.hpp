@@ -98,6 +98,10 @@ void launch_gather_convert(const void* src, int src_dtype, const uint32_t* perm,
 void launch_segment_starts(const uint64_t* keys, int64_t n, uint64_t div, unsigned long long* count,
                            int64_t* pos, uint64_t* pkey, int64_t cap, hipStream_t s);
 void launch_validate(const int32_t* col, int64_t n, int64_t dom, int32_t* err_flag, hipStream_t s);
+// number of distinct values of an integer column with values in [0, dom);
+// bits: (dom + 31) / 32 words of scratch, out: one device counter
+void launch_distinct(const int32_t* col, int64_t n, int64_t dom, uint32_t* bits, unsigned long long* out,
+                     hipStream_t s);
 
 int scan_lds_bytes(const DScan& S, bool f64);
 int scan_fast_lds_bytes(const DScan& S, bool f64);

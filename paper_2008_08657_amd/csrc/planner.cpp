@@ -1377,6 +1377,18 @@ Plan* build_plan(const lmfao_schema* schema, const lmfao_join_tree* tree, const 
   try {
     if (opts) P->opts = *opts;
     else lmfao_default_options(&P->opts);
+    if (P->opts.estimator && P->opts.estimator_len > 0) {
+      const float* e = P->opts.estimator;
+      const int64_t len = P->opts.estimator_len;
+      if (len < 4 || e[0] != 1.f || e[1] != (float)LMFAO_EST_FEATURES || !(e[2] >= 1.f && e[2] <= 4096.f))
+        throw PlanError{LMFAO_EINVAL, "estimator blob: bad header"};
+      const int64_t d = LMFAO_EST_FEATURES, h = (int64_t)e[2];
+      const int64_t n = d * h + h + h * h + h + h + 1;
+      if (len != 4 + 2 * d + n) throw PlanError{LMFAO_EINVAL, "estimator blob: length does not match its header"};
+      P->estimator.assign(e, e + len);
+    }
+    P->opts.estimator = nullptr;
+    P->opts.estimator_len = 0;
     intake(*P, schema, tree, batch);
     compute_uniqueness(*P);
     generate_views(*P);

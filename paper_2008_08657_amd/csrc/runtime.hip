@@ -54,6 +54,7 @@ struct HashBuf {
   int query = -1;
   int64_t cap = 0;                 // slots (power of two)
   int64_t bound = 0;               // most groups there can be (distinct keys)
+  double est = -1;                 // groups the estimator predicted (-1 = not used)
   unsigned long long* keys = nullptr;
   int64_t* cnt = nullptr;
   double* vals = nullptr;
@@ -114,6 +115,7 @@ struct lmfao_prepared_s {
   std::vector<lmfao::HashBuf> hashes;
   lmfao::DHashOut* hash_dev = nullptr;                // device copy of the hash descriptors
   int hash_regrowths = 0;                             // runs repeated after a hash overflow
+  std::map<int, int64_t> distinct;                    // distinct values per integer attribute
   int32_t* hash_ovf = nullptr;                        // per table overflow flag
   std::vector<std::vector<const void*>> ecols;       // caller's columns, then derived bucket codes
   std::vector<const void* const*> ecol_ptrs;
@@ -1194,6 +1196,128 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
   }
 }
 
+// Distinct values of an integer attribute, counted on the GPU in the
+// smallest relation that holds it (every value of D is among them).
+static int64_t distinct_of(Prep& S, int a, hipStream_t st) {
+  auto it = S.distinct.find(a);
+  if (it != S.distinct.end()) return it->second;
+  Plan& P = *S.P;
+  const AttrDef& A = P.attrs[a];
+  int best = -1, bc = -1;
+  for (size_t r = 0; r < P.rels.size(); ++r) {
+    auto c = P.rels[r].col.find(a);
+    if (c == P.rels[r].col.end() || P.rels[r].dtypes[c->second] != LMFAO_I32) continue;
+    if (best < 0 || P.rels[r].n_rows < P.rels[best].n_rows) best = (int)r, bc = c->second;
+  }
+  int64_t d = A.domain > 0 ? A.domain : INT64_MAX;
+  if (best >= 0 && A.domain > 0) {
+    const int64_t words = (A.domain + 31) / 32;
+    void *bits = nullptr, *cnt = nullptr;
+    HIP_OK(hipMalloc(&bits, (size_t)words * 4));
+    if (hipMalloc(&cnt, 8) != hipSuccess) {
+      (void)hipFree(bits);
+      throw PlanError{LMFAO_ENOMEM, "distinct-count counter"};
+    }
+    launch_distinct((const int32_t*)S.ecols[best][bc], P.rels[best].n_rows, A.domain, (uint32_t*)bits,
+                    (unsigned long long*)cnt, st);
+    unsigned long long h = 0;
+    hipError_t e = hipMemcpyAsync(&h, cnt, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(bits);
+    (void)hipFree(cnt);
+    if (e != hipSuccess) throw PlanError{LMFAO_EHIP, std::string("distinct count: ") + hipGetErrorString(e)};
+    d = (int64_t)h;
+  }
+  S.distinct[a] = d;
+  return d;
+}
+
+// D has at most one tuple per tuple of the root when every relation joins
+// toward the root through its primary key
+static bool root_bounded(const Plan& P, int root) {
+  for (int c : P.adj[root])
+    if (!P.uniq[c][root]) return false;
+  return true;
+}
+
+// most groups a query can have: dense key space, product of distinct counts,
+// and the root's rows when D has at most one tuple per root tuple
+static double query_bound(Prep& S, const QueryDef& Q, hipStream_t st) {
+  const Plan& P = *S.P;
+  double dense = 1, pd = 1;
+  for (int a : Q.groupby) {
+    dense *= (double)P.attrs[a].domain;
+    pd *= (double)distinct_of(S, a, st);
+  }
+  double b = std::min(dense, pd);
+  if (root_bounded(P, Q.root)) b = std::min(b, (double)std::max<int64_t>(1, P.rels[Q.root].n_rows));
+  return std::max(1.0, b);
+}
+
+// estimator features of a query (layout declared with LMFAO_EST_FEATURES)
+static void query_features(Prep& S, const QueryDef& Q, float* f, hipStream_t st) {
+  const Plan& P = *S.P;
+  auto lg = [](double x) { return (float)std::log2(1.0 + std::max(0.0, x)); };
+  for (int i = 0; i < LMFAO_EST_FEATURES; ++i) f[i] = 0.f;
+  double total = 0;
+  for (const RelDef& R : P.rels) total += (double)R.n_rows;
+  f[0] = lg((double)P.rels[Q.root].n_rows);
+  f[1] = lg(total);
+  f[2] = (float)P.rels.size();
+  f[3] = (float)Q.groupby.size();
+  // tree distances from the root
+  std::vector<int> dist(P.rels.size(), -1), queue{Q.root};
+  dist[Q.root] = 0;
+  for (size_t i = 0; i < queue.size(); ++i)
+    for (int v : P.adj[queue[i]])
+      if (dist[v] < 0) dist[v] = dist[queue[i]] + 1, queue.push_back(v);
+  double pd = 1;
+  for (size_t k = 0; k < Q.groupby.size(); ++k) {
+    const int a = Q.groupby[k];
+    const double dc = (double)distinct_of(S, a, st);
+    pd *= dc;
+    if (k >= 3) continue;
+    int near = 1 << 20;
+    for (size_t r = 0; r < P.rels.size(); ++r)
+      if (P.rels[r].col.count(a) && dist[r] >= 0) near = std::min(near, dist[r]);
+    f[4 + k] = lg(dc);
+    f[7 + k] = lg((double)P.attrs[a].domain);
+    f[10 + k] = (float)(near == (1 << 20) ? 0 : near);
+  }
+  f[13] = lg(pd);
+  f[14] = lg(query_bound(S, Q, st));
+  f[15] = root_bounded(P, Q.root) ? 1.f : 0.f;
+  f[16] = (float)P.filter.size();
+}
+
+// log2(1 + groups) the estimator predicts from the features (FP32, host)
+static double estimate_log2_groups(const std::vector<float>& blob, const float* x) {
+  const int d = LMFAO_EST_FEATURES, h = (int)blob[2];
+  const float* mean = blob.data() + 4;
+  const float* sd = mean + d;
+  const float* W1 = sd + d;
+  const float* b1 = W1 + (size_t)d * h;
+  const float* W2 = b1 + h;
+  const float* b2 = W2 + (size_t)h * h;
+  const float* w3 = b2 + h;
+  const float* b3 = w3 + h;
+  std::vector<float> z(d), h1(h), h2(h);
+  for (int i = 0; i < d; ++i) z[i] = (x[i] - mean[i]) / (sd[i] > 0.f ? sd[i] : 1.f);
+  for (int j = 0; j < h; ++j) {
+    float a = b1[j];
+    for (int i = 0; i < d; ++i) a += z[i] * W1[(size_t)i * h + j];
+    h1[j] = a > 0.f ? a : 0.f;
+  }
+  for (int j = 0; j < h; ++j) {
+    float a = b2[j];
+    for (int i = 0; i < h; ++i) a += h1[i] * W2[(size_t)i * h + j];
+    h2[j] = a > 0.f ? a : 0.f;
+  }
+  float y = b3[0];
+  for (int j = 0; j < h; ++j) y += h2[j] * w3[j];
+  return (double)y;
+}
+
 // (re)allocates the slots of a hash table; old slots are released
 static void alloc_hash(Prep& S, HashBuf& H) {
   for (void* p : {(void*)H.keys, (void*)H.cnt, (void*)H.vals})
@@ -1259,6 +1383,9 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
   HIP_OK(hipMemcpyAsync(&flag, S.err_flag, 4, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   if (flag & 2) throw PlanError{LMFAO_EINVAL, "an integer column holds a value outside its declared domain"};
+  // column statistics: distinct counts of every group-by attribute
+  for (const QueryDef& Q : P.queries)
+    for (int a : Q.groupby) distinct_of(S, a, st);
   // output buffers: every view and query result lives in one arena that a
   // single fill zeroes at the start of each run
   S.vout.resize(P.views.size());
@@ -1289,9 +1416,20 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
       // hash table: at most one group per tuple of the root relation
       HashBuf H;
       H.query = (int)q;
-      H.bound = (int64_t)std::min<double>(dense, (double)std::max<int64_t>(1, P.rels[Q.root].n_rows));
+      H.bound = (int64_t)std::min(query_bound(S, Q, st), 4e18);
       H.n_vals = B.n_vals;
-      int64_t want = P.opts.hash_slots > 0 ? P.opts.hash_slots : std::max<int64_t>(1024, 2 * H.bound);
+      int64_t top = 1;
+      while (top < std::max<int64_t>(1024, 2 * H.bound)) top <<= 1;
+      int64_t want = top;
+      if (P.opts.hash_slots > 0) {
+        want = P.opts.hash_slots;
+      } else if (P.opts.sizing == LMFAO_SIZING_LEARNED && !P.estimator.empty()) {
+        float f[LMFAO_EST_FEATURES];
+        query_features(S, Q, f, st);
+        const double y = estimate_log2_groups(P.estimator, f) + (double)P.estimator[3];
+        H.est = std::exp2(std::min(y, 62.0)) - 1.0;
+        want = (int64_t)std::min<double>((double)top, std::max(1024.0, 2.0 * H.est));
+      }
       H.cap = 1;
       while (H.cap < want) H.cap <<= 1;
       B.hash = (int)S.hashes.size();
@@ -1915,6 +2053,22 @@ lmfao_status lmfao_run_timing(lmfao_prepared_t prep, int32_t cap, const char** n
   return LMFAO_OK;
 }
 
+lmfao_status lmfao_prepared_features(lmfao_prepared_t prep, int32_t q, float* feats) {
+  if (!prep || !feats) return set_err(LMFAO_EINVAL, "null argument");
+  const Plan& P = *prep->P;
+  if (q < 0 || q >= (int)P.user.size()) return set_err(LMFAO_EINVAL, "query index out of range");
+  const QueryDef& Q = P.queries[P.user[q].internal];
+  if (Q.groupby.empty()) return set_err(LMFAO_EINVAL, "query has no group-by attributes");
+  try {
+    query_features(*prep, Q, feats, prep->stream);
+  } catch (const PlanError& e) {
+    return set_err(e.status, e.msg);
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
 lmfao_status lmfao_prepared_kernel_source(lmfao_prepared_t prep, int32_t i, char* buf, size_t cap, size_t* need) {
   if (!prep) return set_err(LMFAO_EINVAL, "null prepared handle");
   if (i < 0 || i >= (int)prep->gen_sources.size()) return set_err(LMFAO_EINVAL, "no generated kernel with that index");
@@ -1966,8 +2120,14 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
   j += ",\"hash_tables\":[";
   for (size_t i = 0; i < prep->hashes.size(); ++i) {
     if (i) j += ",";
-    j += "{\"query\":" + std::to_string(prep->hashes[i].query) + ",\"slots\":" + std::to_string(prep->hashes[i].cap) +
-         ",\"bound\":" + std::to_string(prep->hashes[i].bound) + "}";
+    const HashBuf& H = prep->hashes[i];
+    int user = -1;
+    for (size_t u = 0; u < prep->P->user.size() && user < 0; ++u)
+      if (prep->P->user[u].internal == H.query) user = (int)u;
+    char tmp[160];
+    snprintf(tmp, sizeof tmp, "{\"query\":%d,\"slots\":%lld,\"bound\":%lld,\"est_groups\":%.17g}", user,
+             (long long)H.cap, (long long)H.bound, H.est);
+    j += tmp;
   }
   j += "],\"hash_regrowths\":" + std::to_string(prep->hash_regrowths) + "}";
   if (need) *need = j.size() + 1;

@@ -1,0 +1,132 @@
+"""Learned hash-table sizing on the GPU: the estimator's input features
+(row counts, distinct counts counted on the GPU, domains, tree distances,
+bounds) against numpy; results under learned sizing identical to the bound
+sizing, also when the estimate is far too small (overflow regrowth); and the
+gain test on held-out Rk-means chains."""
+import os
+
+import numpy as np
+import pytest
+
+import paper_2008_08657_amd as lm
+from paper_2008_08657_amd import estimator as est
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _expected_features(p, plan_desc, q):
+    rels = {r["name"]: r for r in p["schema"]}
+    names = [r["name"] for r in p["schema"]]
+    adj = {i: [] for i in range(len(names))}
+    for a, b in p["tree"]:
+        adj[a].append(b)
+        adj[b].append(a)
+    query = p["batch"][q]
+    root = names.index(plan_desc["queries"][plan_desc["user_queries"][q]["planned"]]["root"])
+    dist = {root: 0}
+    order = [root]
+    for u in order:
+        for v in adj[u]:
+            if v not in dist:
+                dist[v] = dist[u] + 1
+                order.append(v)
+    lg = lambda x: np.log2(1.0 + x)  # noqa: E731
+    f = np.zeros(est.D)
+    f[0] = lg(rels[names[root]]["n_rows"])
+    f[1] = lg(sum(r["n_rows"] for r in p["schema"]))
+    f[2] = len(names)
+    f[3] = len(query["groupby"])
+    prod = 1.0
+    dense = 1.0
+    for k, a in enumerate(query["groupby"]):
+        holders = [i for i, r in enumerate(p["schema"]) if any(x["name"] == a for x in r["attrs"])]
+        small = min(holders, key=lambda i: (p["schema"][i]["n_rows"], i))
+        dc = len(np.unique(p["data"][names[small]][a]))
+        dom = next(x["domain"] for x in p["schema"][small]["attrs"] if x["name"] == a)
+        prod *= dc
+        dense *= dom
+        if k < 3:
+            f[4 + k] = lg(dc)
+            f[7 + k] = lg(dom)
+            f[10 + k] = min(dist[i] for i in holders)
+    f[13] = lg(prod)
+    # D has at most one tuple per root tuple iff every relation joins toward the
+    # root on its primary key
+    bounded = True
+    for u in order[1:]:
+        par = next(v for v in adj[u] if dist[v] == dist[u] - 1)
+        shared = {x["name"] for x in p["schema"][u]["attrs"]} & {x["name"] for x in p["schema"][par]["attrs"]}
+        keys = {x["name"] for x in p["schema"][u]["attrs"] if x["key"]}
+        bounded &= bool(keys) and keys <= shared
+    bound = min(dense, prod)
+    if bounded:
+        bound = min(bound, max(1, rels[names[root]]["n_rows"]))
+    f[14] = lg(max(1.0, bound))
+    f[15] = 1.0 if bounded else 0.0
+    f[16] = 0
+    return f
+
+
+@pytest.mark.parametrize("seed", [3, 4, 11, 17])
+def test_features_match_numpy(seed):
+    p = W.estimator_workload(seed, max_rows=60_000)
+    print(f"[case] features seed {seed} {p['name']}", flush=True)
+    plan = lm.Plan(p, precision="f32", policy="fact", codegen=False)
+    prep = lm.Prepared(plan, lm.device_columns(p))
+    desc = plan.describe()
+    for q in range(len(p["batch"])):
+        got = np.asarray(prep.features(q), np.float64)
+        want = _expected_features(p, desc, q)
+        np.testing.assert_allclose(got, want, rtol=1e-6, atol=1e-6, err_msg=f"query {q} {p['batch'][q]}")
+
+
+def _chain(seed, n1=30_000):
+    return W.rkmeans_chain(seed=seed, n1=n1, n2=n1 // 10, n3=n1 // 100, n_x=8, n_y=6, n_z=6, max_dom=1_000_000)
+
+
+def _run(p, **kw):
+    plan = lm.Plan(p, precision="f32", policy="fact", **kw)
+    prep = lm.Prepared(plan, lm.device_columns(p))
+    prep.run(sync=True)
+    return prep.results(), prep.describe()
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x["keys"], y["keys"])
+        np.testing.assert_array_equal(x["count"], y["count"])
+
+
+def test_underestimate_falls_back_to_regrowth():
+    # an estimator whose prediction is 0 groups: every table starts at 1024
+    # slots, overflows, grows and the run repeats; results are unchanged
+    p = _chain(5)
+    h = 4
+    zero = est.pack(np.zeros(est.D), np.ones(est.D), np.zeros(lm.mlp_size(est.D, h)), h, 0.0)
+    ref, dref = _run(p)
+    got, dgot = _run(p, sizing="learned", estimator=zero)
+    _same(ref, got)
+    assert len(dgot["hash_tables"]) >= 1
+    assert all(t["slots"] == 1024 or t["est_groups"] == 0 for t in dgot["hash_tables"])
+    assert dgot["hash_regrowths"] >= 1
+
+
+@pytest.mark.skipif(not os.path.exists(est.WEIGHTS), reason="no trained estimator weights in the package")
+@pytest.mark.parametrize("seed", [101, 102])
+def test_learned_sizing_gain_on_held_out_chain(seed):
+    # the gain test: Rk-means chains are never drawn for the corpus; learned
+    # sizing gives the same groups and counts as the bound sizing with no more
+    # hash slots in total
+    p = _chain(seed, n1=200_000)
+    print(f"[case] gain seed {seed}", flush=True)
+    ref, dref = _run(p)
+    got, dgot = _run(p, sizing="learned")
+    _same(ref, got)
+    s_bound = sum(t["slots"] for t in dref["hash_tables"])
+    s_learned = sum(t["slots"] for t in dgot["hash_tables"])
+    groups = {t["query"]: len(ref[t["query"]]["keys"]) for t in dref["hash_tables"]}
+    print(f"[gain] slots bound {s_bound} learned {s_learned} regrowths {dgot['hash_regrowths']} "
+          f"groups {sorted(groups.values())} est {[round(t['est_groups']) for t in dgot['hash_tables']]}",
+          flush=True)
+    assert s_learned <= s_bound

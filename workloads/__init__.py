@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "zipf_keys", "tiny_star", "retail_snowflake", "grocery_star", "cart_node", "quantile_thresholds",
     "rkmeans_chain", "favorita_example", "random_acyclic", "covariance_batch",
-    "problem_digest", "fact_prefix",
+    "problem_digest", "fact_prefix", "estimator_workload",
 ]
 
 
@@ -503,3 +503,82 @@ def rkmeans_chain(seed: int = 0, n1: int = 50_000_000, n2: int = 5_000_000, n3: 
     data = {"R1": R1, "R2": R2, "R3": R3}
     return {"name": "rkmeans_chain", "schema": schema, "tree": [(0, 1), (1, 2)], "batch": batch,
             "data": data, "policy": "fact", "precision": "f32", "domains": dom, "pairs": pairs}
+
+
+def estimator_workload(seed: int, max_rows: int = 1_000_000):
+    """A random small acyclic join for the group-count estimator's corpus.
+
+    Shape (star, chain or snowflake) over 2-5 relations; relation 0 has
+    10^U(4, log10 max_rows) rows, every other relation up to as many as its
+    parent.  An edge is a foreign key into the child (probability 0.7: the
+    child's key attribute is 0..n-1, the parent's reference uniform or Zipf) or
+    a many-to-many join on an attribute with domain 10^U(1, 4).  Every relation
+    has 1-3 integer attributes with domains 10^U(1, 6), uniform or Zipf(s in
+    [0.8, 1.5]).  Batch: SUM(1) grouped by each such attribute and by up to 6
+    random pairs of them that one relation reaches through foreign keys."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0x5eed])))
+    n_rel = int(g.integers(2, 6))
+    shape = ["star", "chain", "snowflake"][int(g.integers(0, 3))]
+    parent = [-1] + [0 if shape == "star" else i - 1 if shape == "chain" else int(g.integers(0, i))
+                     for i in range(1, n_rel)]
+    rows = [int(10 ** g.uniform(4, np.log10(max_rows)))]
+    for i in range(1, n_rel):
+        rows.append(max(10, int(10 ** g.uniform(1, np.log10(rows[parent[i]])))))
+
+    def values(n, dom):
+        if g.random() < 0.5:
+            return g.integers(0, dom, n, dtype=np.int32)
+        z = zipf_keys(g, n, dom, float(g.uniform(0.8, 1.5)))
+        return g.permutation(dom).astype(np.int32)[z] if dom <= 1 << 20 else z
+
+    attrs = [[] for _ in range(n_rel)]
+    data = [{} for _ in range(n_rel)]
+    fk = [False] * n_rel
+    for c in range(1, n_rel):
+        p, k = parent[c], f"k{c}"
+        if g.random() < 0.7:
+            fk[c] = True
+            attrs[c].append(_attr(k, "i32", rows[c], True))
+            data[c][k] = np.arange(rows[c], dtype=np.int32)
+            attrs[p].append(_attr(k, "i32", rows[c]))
+            data[p][k] = values(rows[p], rows[c])
+        else:
+            dk = int(10 ** g.uniform(1, 4))
+            attrs[c].append(_attr(k, "i32", dk))
+            data[c][k] = values(rows[c], dk)
+            attrs[p].append(_attr(k, "i32", dk))
+            data[p][k] = values(rows[p], dk)
+    feats, owned = [], [[] for _ in range(n_rel)]
+    for r in range(n_rel):
+        for j in range(int(g.integers(1, 4))):
+            a, dom = f"v{r}_{j}", int(10 ** g.uniform(1, 6))
+            attrs[r].append(_attr(a, "i32", dom))
+            data[r][a] = values(rows[r], dom)
+            feats.append(a)
+            owned[r].append(a)
+    batch = [{"groupby": [a], "where": [], "aggs": [[]], "root": None} for a in feats]
+    # pairs of attributes that one relation reaches through foreign keys (so
+    # that every tuple of the join below it carries one value of each)
+    closed = fk[:]   # the edge into c and every edge below c are foreign keys
+    for c in range(n_rel - 1, 0, -1):
+        closed[c] = fk[c] and all(closed[d] for d in range(c + 1, n_rel) if parent[d] == c)
+    pairs = set()
+    for _ in range(6):
+        r = int(g.integers(0, n_rel))
+        reach, stack = [r], [r]
+        while stack:
+            u = stack.pop()
+            for c in range(1, n_rel):
+                if parent[c] == u and closed[c]:
+                    reach.append(c)
+                    stack.append(c)
+        cand = [a for u in reach for a in owned[u]]
+        if len(cand) > 1:
+            i, j = sorted(g.choice(len(cand), 2, replace=False).tolist())
+            pairs.add((cand[i], cand[j]))
+    batch += [{"groupby": [a, b], "where": [], "aggs": [[]], "root": None} for a, b in sorted(pairs)]
+    names = [f"T{r}" for r in range(n_rel)]
+    schema = [_rel(names[r], rows[r], attrs[r]) for r in range(n_rel)]
+    return {"name": f"estimator_{shape}_{seed}", "schema": schema,
+            "tree": [(parent[c], c) for c in range(1, n_rel)], "batch": batch,
+            "data": {names[r]: data[r] for r in range(n_rel)}, "policy": "fact", "precision": "f32"}
