@@ -15,8 +15,12 @@ done once before the timed region and reported separately).
 metric: join-tuple-aggregates/s = |D| * A / t_step, with |D| = 84M join tuples
 (every fact row joins exactly once) and A = 1,269 SUM expressions.
 
-Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits: this
-build measures one GPU.
+Other workloads: ``--config grocery`` (BF16x3 contraction), ``cart`` (CART
+node batch), ``chain`` (Rk-means step 1 with learned hash-table sizing),
+``tiny``.  ``--plain-steps K`` also times the plain per-view form.
+
+Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits: the
+benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -49,7 +53,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="retail", choices=["retail", "tiny", "grocery", "cart"])
+    ap.add_argument("--config", default="retail", choices=["retail", "tiny", "grocery", "cart", "chain"])
+    ap.add_argument("--precision", default=None, choices=["f64", "f32", "bf16x3", "bf16x6"],
+                    help="arithmetic (default: the configuration's own)")
+    ap.add_argument("--sizing", default=None, choices=["bound", "learned"],
+                    help="hash-table sizing (default: learned for chain, bound otherwise)")
+    ap.add_argument("--plain-steps", type=int, default=0,
+                    help="also time this many steps of the plain per-view form on the same input")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the fact table (testing only)")
     ap.add_argument("--cpu-rows", type=int, default=150_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -60,7 +70,7 @@ def main():
                     help="fused: one pass per group of outputs (the method); per_view: one pass per output")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -89,21 +99,28 @@ def main():
     elif args.config == "grocery":
         n_sales = int(120_000_000 * args.scale)
         problem = W.grocery_star(seed=0, n_sales=n_sales)
-        precision, workload = "f32", "grocery-shaped star (Sales 120M x 6 relations), covariance + 10 categoricals"
+        precision, workload = "bf16x3", "grocery-shaped star (Sales 120M x 6 relations), covariance + 10 categoricals"
     elif args.config == "cart":
         n_inv = int(84_000_000 * args.scale)
         problem = W.cart_node(seed=0, n_inv=n_inv)
         precision, workload = "f32", ("CART node on the retail snowflake (Inv 84M): 840 thresholds + 7 "
                                       "categorical group-bys x {SUM(1), SUM(y), SUM(y^2)} under a 3-condition path")
+    elif args.config == "chain":
+        n1 = int(50_000_000 * args.scale)
+        problem = W.rkmeans_chain(seed=0, n1=n1, n2=max(1000, n1 // 10), n3=max(100, n1 // 250))
+        precision, workload = "f32", ("Rk-means step 1 on a 3-relation chain (R1 50M, R2 5M, R3 200k; 100 "
+                                      "attributes, domains 10..1e6): SUM(1) by each attribute and 10 pairs")
     else:
         problem = W.tiny_star(seed=0)
         precision, workload = "f64", "tiny star (S 100k x 3 relations), covariance grouped by cat"
+    precision = args.precision or precision
+    sizing = args.sizing or ("learned" if args.config == "chain" else "bound")
     fact = max(problem["schema"], key=lambda r: r["n_rows"])
     n_join = fact["n_rows"]   # every fact row joins exactly once (complete foreign keys)
     n_aggs = sum(len(q["aggs"]) for q in problem["batch"])
     t_gen = time.perf_counter() - t_gen
 
-    plan = E.Plan(problem, precision=precision, policy=problem["policy"], form=args.form)
+    plan = E.Plan(problem, precision=precision, policy=problem["policy"], form=args.form, sizing=sizing)
     cols = E.device_columns(problem)
     torch.cuda.synchronize()
     t_prep = time.perf_counter()
@@ -150,10 +167,35 @@ def main():
 
     # sanity on the GPU results: COUNT equals |D| (closed form)
     check = {}
-    if not args.no_check and not problem["batch"][0]["where"]:
+    if not args.no_check and not problem["batch"][0]["where"] and not problem["batch"][0]["groupby"]:
         r0 = prep.result(0)
         check["count_equals_join_size"] = bool(int(r0["count"][0]) == n_join
                                                 and float(r0["sum"][0, 0]) == float(n_join))
+
+    hashes = desc.get("hash_tables", [])
+    sizing_info = {"tables": len(hashes), "slots": sum(h["slots"] for h in hashes),
+                   "regrowths": desc.get("hash_regrowths", 0)} if hashes else None
+
+    plain = None
+    if args.plain_steps > 0 and args.form == "fused":
+        # the plain form on the same input: one pass per output, no sharing
+        del prep
+        torch.cuda.empty_cache()
+        cols = E.device_columns(problem)
+        pplan = E.Plan(problem, precision=precision, policy=problem["policy"], form="per_view", sizing=sizing)
+        pprep = E.Prepared(pplan, cols)
+        del cols
+        torch.cuda.empty_cache()
+        pprep.run(sync=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            pprep.run(sync=False)
+        torch.cuda.synchronize()
+        pms = 1e3 * (time.perf_counter() - t0) / args.plain_steps
+        plain = {"form": "per_view", "steps": args.plain_steps, "ms_per_step": round(pms, 4),
+                 "value": n_join * n_aggs / (pms * 1e-3), "fused_speedup": round(pms / ms_per_step, 2)}
+        del pprep, pplan
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -170,15 +212,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if precision == "f32" else "f64",
+        "dtype": precision,
         "data": "synthetic",
         "config": {"workload": workload, "join_tuples": n_join, "aggregates": n_aggs,
                    "queries": len(problem["batch"]), "precision": precision,
-                   "form": args.form, "root_policy": problem["policy"], "seed": 0,
+                   "form": args.form, "root_policy": problem["policy"], "seed": 0, "sizing": sizing,
                    "prepare_s": round(t_prep, 2), "generate_s": round(t_gen, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels_ms": {k: round(v, 4) for k, v in timing},
+        "plain": plain,
+        "hash_sizing": sizing_info,
         "check": check,
     }
     print(json.dumps(out), flush=True)

@@ -129,7 +129,17 @@ typedef struct {
   const lmfao_query* queries;
 } lmfao_batch;
 
-enum { LMFAO_PREC_F64 = 0, LMFAO_PREC_F32 = 1 };
+/* F64 and F32: arithmetic of the scans, views and contraction.  BF16X3:
+ * scans and views in FP32; in the matrix-core contraction each tile without
+ * integer cells splits its FP32 operands x into hi = bf16(x) and
+ * lo = bf16(x - hi) and sums hi*hi' + hi*lo' + lo*hi' on the bf16 matrix
+ * cores (v_mfma_f32_16x16x16_bf16), in FP32 within a chunk of 16 pieces and
+ * FP64 across chunks; tiles with integer cells stay exact in FP64.  Each
+ * product is then within about 2^-16 of exact, so a float result is within
+ * 2^-16 of the sum of its terms' magnitudes (relative 1e-5 unless the sum
+ * cancels).  BF16X6: three parts (hi, mid, lo) and six products, FP32
+ * accuracy.  Both require LMFAO_CONTRACT_MFMA. */
+enum { LMFAO_PREC_F64 = 0, LMFAO_PREC_F32 = 1, LMFAO_PREC_BF16X3 = 2, LMFAO_PREC_BF16X6 = 3 };
 enum { LMFAO_FORM_FUSED = 0, LMFAO_FORM_PER_VIEW = 1 };
 /* Root heuristics.  GROUPBY: the relation holding every group-by attribute,
  * the largest such relation (reproduces the roots of the worked example);
@@ -177,13 +187,14 @@ typedef struct {
 } lmfao_options;
 
 /* Initial capacity of a hash table.  BOUND: twice the most groups the output
- * can have -- the product over its key attributes of their distinct counts
- * (counted on the GPU at prepare time), the dense key space, and, when every
- * relation joins the query's root through a primary key (so D has at most one
- * tuple per root tuple), the root's row count.  LEARNED: the group count the
+ * can have -- the least of the product over its key attributes of their
+ * distinct counts (counted on the GPU at prepare time), the dense key space,
+ * and the rows of any relation whose tuple determines every key attribute
+ * (holds it, or reaches its holder through joins on primary keys).  LEARNED: the group count the
  * estimator predicts, 2^(y + margin) - 1, at half occupancy, never above the
  * BOUND capacity and never below 1024 slots.  Both round up to a power of
- * two.  LEARNED without an estimator blob behaves as BOUND. */
+ * two and start at most at 2^26 slots; regrowth goes up to the BOUND
+ * capacity.  LEARNED without an estimator blob behaves as BOUND. */
 enum { LMFAO_SIZING_BOUND = 0, LMFAO_SIZING_LEARNED = 1 };
 
 /* Estimator blob: {version = 1, d = LMFAO_EST_FEATURES, h, margin},
@@ -197,7 +208,7 @@ enum { LMFAO_SIZING_BOUND = 0, LMFAO_SIZING_LEARNED = 1 };
  *   4..6 log2 distinct count of each key       7..9 log2 domain of each key
  *   10..12 tree distance from the root to the nearest relation holding the key
  *   13 log2 product of the distinct counts     14 log2 of the BOUND group count
- *   15 1 if D has at most one tuple per root tuple, else 0
+ *   15 1 if some relation's tuple determines every key attribute, else 0
  *   16 number of conditions of the batch-wide filter */
 #define LMFAO_EST_FEATURES 17
 

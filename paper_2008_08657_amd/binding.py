@@ -201,7 +201,9 @@ class Plan:
         schema, tree, batch = marshal_problem(problem, keep)
         opts = lmfao_options()
         self.lib.lmfao_default_options(C.byref(opts))
-        opts.precision = PREC_F64 if precision == "f64" else PREC_F32
+        if precision not in ("f64", "f32", "bf16x3", "bf16x6"):
+            raise ValueError(f"precision must be 'f64', 'f32', 'bf16x3' or 'bf16x6', not {precision!r}")
+        opts.precision = {"f64": PREC_F64, "f32": PREC_F32, "bf16x3": 2, "bf16x6": 3}[precision]
         opts.form = FORM_FUSED if form == "fused" else FORM_PER_VIEW
         pol = policy if policy is not None else problem.get("policy", "groupby")
         opts.root_policy = ROOT_FACT if pol == "fact" else ROOT_GROUPBY

@@ -1593,7 +1593,30 @@ int contract_fused_lds_bytes(const DContract& C, int tn) {
 }
 int contract_fused_chunk() { return kFKC; }
 
-template <typename T, int TN>
+// BF16x3 split of a value: hi = bf16(x) and lo = bf16(x - hi), both rounded
+// to nearest even from FP32; hi*hi' + hi*lo' + lo*hi' leaves out lo*lo' and
+// the residues below lo, about 2^-16 of the product at most.
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+// NS = 3 adds mid: x = hi + mid + lo to 24 bits, and the six products
+// hi*hi' + hi*mid' + mid*hi' + hi*lo' + mid*mid' + lo*hi' reach FP32 accuracy
+template <int NS>
+__device__ __forceinline__ void bf16_split(double x, uint16_t* part) {
+  float r = (float)x;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    part[k] = bf16_rne(r);
+    r -= __uint_as_float((uint32_t)part[k] << 16);
+  }
+}
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBKS = kFKC + 4;   // bf16 row stride of the split tiles (8-byte aligned rows of 40 bytes)
+
+template <typename T, int TN, int NS>
 __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restrict__ C, const DGemm* __restrict__ G) {
   constexpr int NT = 16 * TN;
   constexpr int SA = kGemmMT + 16;
@@ -1623,6 +1646,11 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
   const int64_t kb = (int64_t)blockIdx.x * G->k_per_block;
   const int64_t ke = std::min<int64_t>(G->n, kb + G->k_per_block);
   const bool do_scatter = blockIdx.y == 0;
+  // BF16x3 tiles hold no integer cell (integer features and columns come
+  // first); the others stay on the exact FP64 path
+  const bool split = NS > 0 && (f0 >= C->n_feat_int || g0 >= C->n_col_int);
+  uint16_t* Asp = (uint16_t*)As;                           // NS planes of [kGemmMT][kBKS]
+  uint16_t* Bsp = (uint16_t*)Bs;                           // NS planes of [NT][kBKS]
   bool over = false;
   f64x4 acc[TN];
 #pragma unroll
@@ -1673,6 +1701,26 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
     __syncthreads();
     // the F and B slices of the chunk; rows past the chunk and columns past
     // the matrix are zero
+    if (split) {
+      for (int t = threadIdx.x; t < kFKC * kGemmMT; t += blockDim.x) {
+        const int pi = t % kFKC, fl = t / kFKC, f = f0 + fl;
+        double x = 0.0;
+        if (pi < np && f < NF) x = feat_d(feat_s[fl], mu_s + pi * NM, code_s + pi * NC, atom_s + pi * NA, f < NFI);
+        uint16_t part[NS > 0 ? NS : 1];
+        bf16_split<NS>(x, part);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) Asp[k * kGemmMT * kBKS + fl * kBKS + pi] = part[k];
+      }
+      for (int t = threadIdx.x; t < kFKC * NT; t += blockDim.x) {
+        const int pi = t % kFKC, gl = t / kFKC, g = g0 + gl;
+        const double x =
+            (pi < np && g < NG) ? col_d<T>(C, col_s[gl], cb + pi, code_s + pi * NC, atom_s + pi * NA) : 0.0;
+        uint16_t part[NS > 0 ? NS : 1];
+        bf16_split<NS>(x, part);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) Bsp[k * NT * kBKS + gl * kBKS + pi] = part[k];
+      }
+    } else {
     for (int t = threadIdx.x; t < kFKC * kGemmMT; t += blockDim.x) {
       const int pi = t / kGemmMT, fl = t % kGemmMT, f = f0 + fl;
       double x = 0.0;
@@ -1686,6 +1734,7 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
       const int pi = t / NT, gl = t % NT, g = g0 + gl;
       Bs[pi * SB + gl] =
           (pi < np && g < NG) ? col_d<T>(C, col_s[gl], cb + pi, code_s + pi * NC, atom_s + pi * NA) : 0.0;
+    }
     }
     if (do_scatter) {
       const int n_sc = C->n_scatter;
@@ -1724,6 +1773,30 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
       }
     }
     __syncthreads();
+    if (split) {
+      // one K=16 step per chunk: lane l holds rows l%16, k = 4*(l/16)..+3
+      const int ko = 4 * (lane >> 4);
+      bf16x4 a[NS > 0 ? NS : 1];
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        a[k] = *(const bf16x4*)(Asp + k * kGemmMT * kBKS + (16 * w + (lane & 15)) * kBKS + ko);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        bf16x4 b[NS > 0 ? NS : 1];
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          b[k] = *(const bf16x4*)(Bsp + k * NT * kBKS + (16 * j + (lane & 15)) * kBKS + ko);
+        // smallest products first; every pair whose parts sum to at most NS - 1
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int sum = NS - 1; sum >= 0; --sum)
+#pragma unroll
+          for (int i = 0; i <= sum; ++i)
+            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[sum - i], c, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[j][i] += (double)c[i];
+      }
+    } else {
 #pragma unroll
     for (int kk = 0; kk < kFKC; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -1733,6 +1806,7 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
         const double b = Bs[kr * SB + 16 * j + (lane & 15)];
         acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
       }
+    }
     }
     __syncthreads();
   }
@@ -1744,31 +1818,35 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
     const int g = g0 + 16 * j + (lane & 15);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int f = f0 + 16 * w + (lane >> 4) + 4 * i;
+      // output rows of lane l: (l/16) + 4i for the FP64 16x16x4 product,
+      // 4(l/16) + i for the bf16 16x16x16 one
+      const int f = f0 + 16 * w + (split ? 4 * (lane >> 4) + i : (lane >> 4) + 4 * i);
       if (f < NF && g < NG) out[(int64_t)f * NG + g] = acc[j][i];
     }
   }
 }
 
-template <typename T>
+template <typename T, int NS>
 static void launch_contract_fused_t(const DContract* c, const DGemm* g, int tn, int gx, int gy, int lds,
                                     hipStream_t s) {
   dim3 grid(gx, gy), b(256);
   switch (tn) {
 #define CASE(N)                                                               \
   case N:                                                                     \
-    allow_lds((const void*)&k_contract_fused<T, N>, lds);                     \
-    hipLaunchKernelGGL((k_contract_fused<T, N>), grid, b, lds, s, c, g);      \
+    allow_lds((const void*)&k_contract_fused<T, N, NS>, lds);                 \
+    hipLaunchKernelGGL((k_contract_fused<T, N, NS>), grid, b, lds, s, c, g);  \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: break;
   }
 }
-void launch_contract_fused(const DContract* c, const DGemm* g, bool f64, int tn, int gx, int gy, int lds,
-                           hipStream_t s) {
-  if (f64) launch_contract_fused_t<double>(c, g, tn, gx, gy, lds, s);
-  else launch_contract_fused_t<float>(c, g, tn, gx, gy, lds, s);
+void launch_contract_fused(const DContract* c, const DGemm* g, bool f64, int bf16_parts, int tn, int gx, int gy,
+                           int lds, hipStream_t s) {
+  if (f64) launch_contract_fused_t<double, 0>(c, g, tn, gx, gy, lds, s);
+  else if (bf16_parts == 2) launch_contract_fused_t<float, 2>(c, g, tn, gx, gy, lds, s);
+  else if (bf16_parts == 3) launch_contract_fused_t<float, 3>(c, g, tn, gx, gy, lds, s);
+  else launch_contract_fused_t<float, 0>(c, g, tn, gx, gy, lds, s);
 }
 
 // Block-major partial merge: block x takes 16 consecutive cells (one 128-byte

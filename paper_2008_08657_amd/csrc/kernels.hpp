@@ -121,8 +121,11 @@ int gemm_tile_cols(int ng);
 int gemm_macro_tiles(int nf, int ng);
 int contract_fused_lds_bytes(const DContract& C, int tn);
 int contract_fused_chunk();
-void launch_contract_fused(const DContract* c, const DGemm* g, bool f64, int tn, int gx, int gy, int lds,
-                           hipStream_t s);
+// bf16_parts 2 or 3: float-only tiles of the FP32 form on the bf16 matrix
+// cores (operands split into 2 or 3 bf16 parts, 3 or 6 products, FP32 within
+// a chunk of pieces, FP64 across); 0: FP64 matrix cores
+void launch_contract_fused(const DContract* c, const DGemm* g, bool f64, int bf16_parts, int tn, int gx, int gy,
+                           int lds, hipStream_t s);
 void launch_merge_bm(const DCell* cells, int64_t n_cells, const double* part, int n_blocks, int ng, int64_t ncell,
                      int32_t* err_flag, hipStream_t s);
 

@@ -1232,16 +1232,40 @@ static int64_t distinct_of(Prep& S, int a, hipStream_t st) {
   return d;
 }
 
-// D has at most one tuple per tuple of the root when every relation joins
-// toward the root through its primary key
-static bool root_bounded(const Plan& P, int root) {
-  for (int c : P.adj[root])
-    if (!P.uniq[c][root]) return false;
-  return true;
+// Fewest rows of a relation whose tuple determines every key attribute: the
+// relation holds the attribute, or the attribute lies in a subtree that joins
+// it on primary keys (at most one subtree tuple per tuple of the relation).
+// Every tuple of D contains one tuple of that relation and its key is a
+// function of it, so there are at most that many groups.  -1 if none.
+static int64_t determining_rows(const Plan& P, const std::vector<int>& keys) {
+  int64_t best = -1;
+  const int n = (int)P.rels.size();
+  for (int s = 0; s < n; ++s) {
+    std::vector<char> det(n, 0);
+    det[s] = 1;
+    std::vector<std::pair<int, int>> todo;
+    for (int c : P.adj[s]) todo.push_back({c, s});
+    while (!todo.empty()) {
+      const auto [u, par] = todo.back();
+      todo.pop_back();
+      if (!P.uniq[u][par]) continue;
+      det[u] = 1;
+      for (int v : P.adj[u])
+        if (v != par) todo.push_back({v, u});
+    }
+    bool all = true;
+    for (int a : keys) {
+      bool held = false;
+      for (int r = 0; r < n && !held; ++r) held = det[r] && P.rels[r].col.count(a);
+      all = all && held;
+    }
+    if (all && (best < 0 || P.rels[s].n_rows < best)) best = P.rels[s].n_rows;
+  }
+  return best;
 }
 
 // most groups a query can have: dense key space, product of distinct counts,
-// and the root's rows when D has at most one tuple per root tuple
+// rows of a relation that determines the key
 static double query_bound(Prep& S, const QueryDef& Q, hipStream_t st) {
   const Plan& P = *S.P;
   double dense = 1, pd = 1;
@@ -1250,7 +1274,8 @@ static double query_bound(Prep& S, const QueryDef& Q, hipStream_t st) {
     pd *= (double)distinct_of(S, a, st);
   }
   double b = std::min(dense, pd);
-  if (root_bounded(P, Q.root)) b = std::min(b, (double)std::max<int64_t>(1, P.rels[Q.root].n_rows));
+  const int64_t dr = determining_rows(P, Q.groupby);
+  if (dr >= 0) b = std::min(b, (double)dr);
   return std::max(1.0, b);
 }
 
@@ -1286,7 +1311,7 @@ static void query_features(Prep& S, const QueryDef& Q, float* f, hipStream_t st)
   }
   f[13] = lg(pd);
   f[14] = lg(query_bound(S, Q, st));
-  f[15] = root_bounded(P, Q.root) ? 1.f : 0.f;
+  f[15] = determining_rows(P, Q.groupby) >= 0 ? 1.f : 0.f;
   f[16] = (float)P.filter.size();
 }
 
@@ -1317,6 +1342,10 @@ static double estimate_log2_groups(const std::vector<float>& blob, const float* 
   for (int j = 0; j < h; ++j) y += h2[j] * w3[j];
   return (double)y;
 }
+
+// largest initial hash table (2^26 slots, 1.5 GiB with one value); larger
+// ones are reached by regrowth when the groups are really there
+constexpr int64_t kHashInitSlots = (int64_t)1 << 26;
 
 // (re)allocates the slots of a hash table; old slots are released
 static void alloc_hash(Prep& S, HashBuf& H) {
@@ -1420,6 +1449,7 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
       H.n_vals = B.n_vals;
       int64_t top = 1;
       while (top < std::max<int64_t>(1024, 2 * H.bound)) top <<= 1;
+      top = std::min(top, kHashInitSlots);
       int64_t want = top;
       if (P.opts.hash_slots > 0) {
         want = P.opts.hash_slots;
@@ -1566,8 +1596,11 @@ static void enqueue_run(Prep& S, hipStream_t st) {
         launch_merge_cells((const DCell*)s.dev, s.n, s.part_f, s.part_i, s.n_blocks, s.NF, s.NG, s.NFI, s.NGI, st);
         break;
       case 8:
-        launch_contract_fused((const DContract*)s.dev, (const DGemm*)s.dev2, S.f64, s.na, s.grid, s.grid_y, s.lds,
-                              st);
+        launch_contract_fused((const DContract*)s.dev, (const DGemm*)s.dev2, S.f64,
+                              S.P->opts.precision == LMFAO_PREC_BF16X3   ? 2
+                              : S.P->opts.precision == LMFAO_PREC_BF16X6 ? 3
+                                                                         : 0,
+                              s.na, s.grid, s.grid_y, s.lds, st);
         break;
       case 9:
         launch_merge_bm((const DCell*)s.dev, s.n, s.part_f, s.n_blocks, s.NG, (int64_t)s.NF * s.NG, S.err_flag, st);

@@ -39,7 +39,7 @@ FEATURES = [
     "log2_distinct_0", "log2_distinct_1", "log2_distinct_2",
     "log2_domain_0", "log2_domain_1", "log2_domain_2",
     "distance_0", "distance_1", "distance_2",
-    "log2_distinct_product", "log2_bound", "root_bounded", "n_filter_conditions",
+    "log2_distinct_product", "log2_bound", "key_determined", "n_filter_conditions",
 ]
 D = len(FEATURES)
 
@@ -92,9 +92,34 @@ def corpus(problems, device="cuda:0", log=None, total=None):
     of each problem, from one run of the engine per problem."""
     from . import binding
     X, t, tag = [], [], []
+    skipped = 0
     for k, p in enumerate(problems):
-        plan = binding.Plan(p, precision="f32", codegen=False, policy=p.get("policy"))
-        prep = binding.Prepared(plan, binding.device_columns(p, device))
+        try:
+            plan = binding.Plan(p, precision="f32", codegen=False, policy=p.get("policy"))
+        except binding.LmfaoError as e:
+            if e.status != 4:
+                raise
+            # keep the queries the engine plans on their own
+            keep = []
+            for q in p["batch"]:
+                try:
+                    binding.Plan(dict(p, batch=[q]), precision="f32", codegen=False, policy=p.get("policy"))
+                    keep.append(q)
+                except binding.LmfaoError as e1:
+                    if e1.status != 4:
+                        raise
+                    skipped += 1
+            if not keep:
+                continue
+            p = dict(p, batch=keep)
+            plan = binding.Plan(p, precision="f32", codegen=False, policy=p.get("policy"))
+        try:
+            prep = binding.Prepared(plan, binding.device_columns(p, device))
+        except binding.LmfaoError as e:
+            if e.status != 4:
+                raise
+            skipped += len(p["batch"])
+            continue
         prep.run(sync=True)
         res = prep.results()
         for q, query in enumerate(p["batch"]):
@@ -108,7 +133,7 @@ def corpus(problems, device="cuda:0", log=None, total=None):
             tag.append(p["name"])
         del prep, plan
         if log and (k + 1) % 20 == 0:
-            log(f"corpus: {k + 1}/{total or '?'} workloads, {len(X)} outputs")
+            log(f"corpus: {k + 1}/{total or '?'} workloads, {len(X)} outputs, {skipped} queries unsupported")
     return np.asarray(X, np.float32), np.asarray(t, np.float32), tag
 
 

@@ -51,19 +51,36 @@ def _expected_features(p, plan_desc, q):
             f[7 + k] = lg(dom)
             f[10 + k] = min(dist[i] for i in holders)
     f[13] = lg(prod)
-    # D has at most one tuple per root tuple iff every relation joins toward the
-    # root on its primary key
-    bounded = True
-    for u in order[1:]:
-        par = next(v for v in adj[u] if dist[v] == dist[u] - 1)
-        shared = {x["name"] for x in p["schema"][u]["attrs"]} & {x["name"] for x in p["schema"][par]["attrs"]}
-        keys = {x["name"] for x in p["schema"][u]["attrs"] if x["key"]}
-        bounded &= bool(keys) and keys <= shared
+    # a relation's tuple determines an attribute it holds, and every attribute
+    # of a neighbouring subtree that joins it on primary keys only
+    attrs_of = [{x["name"] for x in r["attrs"]} for r in p["schema"]]
+    keys_of = [{x["name"] for x in r["attrs"] if x["key"]} for r in p["schema"]]
+
+    def unique(u, par):
+        return (bool(keys_of[u]) and keys_of[u] <= (attrs_of[u] & attrs_of[par])
+                and all(unique(v, u) for v in adj[u] if v != par))
+
+    def subtree(u, par):
+        out = [u]
+        for v in adj[u]:
+            if v != par:
+                out += subtree(v, u)
+        return out
+
+    det_rows = []
+    for s_ in range(len(names)):
+        det = {s_}
+        for c in adj[s_]:
+            if unique(c, s_):
+                det |= set(subtree(c, s_))
+        held = set().union(*(attrs_of[r] for r in det))
+        if set(query["groupby"]) <= held:
+            det_rows.append(p["schema"][s_]["n_rows"])
     bound = min(dense, prod)
-    if bounded:
-        bound = min(bound, max(1, rels[names[root]]["n_rows"]))
+    if det_rows:
+        bound = min(bound, min(det_rows))
     f[14] = lg(max(1.0, bound))
-    f[15] = 1.0 if bounded else 0.0
+    f[15] = 1.0 if det_rows else 0.0
     f[16] = 0
     return f
 

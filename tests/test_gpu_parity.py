@@ -129,6 +129,40 @@ def test_grocery_star_small(eng):
           min_segment=16)
 
 
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("shape", ["grocery", "retail"])
+def test_bf16_split_contraction(eng, shape, precision):
+    # float tiles of the contraction on the bf16 matrix cores, integer cells
+    # exact.  BF16x6 (three parts, six products) meets the FP32 tolerance.
+    # BF16x3 (two parts, three products) leaves out terms of about 2^-17 of
+    # each product: 1e-5 relative where the sum does not cancel, and 2^-16 of
+    # the sum of the terms' magnitudes everywhere
+    if shape == "grocery":
+        p = W.grocery_star(seed=3, n_sales=200_003, n_stores=9, n_items=300, n_dates=80, n_oil=60, n_hol=30)
+    else:
+        p = W.retail_snowflake(seed=4, n_inv=120_001, n_locn=40, n_dates=12, n_ksn=300, n_weather_dates=14)
+    print(f"[case] {shape} {precision}", flush=True)
+    plan, prep, res = run_engine(eng, p, precision=precision, policy="fact", row_piece_max=5_000, min_segment=16)
+    ref = oracle.evaluate(p)
+    if precision == "bf16x6":
+        worst = compare_all(res, ref, F32_TOL, f"{shape}_{precision}")
+    else:
+        worst = compare_all(res, ref, 2.0 ** -16, f"{shape}_{precision}", floor=1.0)
+        rel = [float(np.max(np.abs(g["sum"] - r["sum"]) / np.maximum(np.abs(r["sum"]), 1e-300)))
+               for g, r in zip(res, ref) if r["sum"].size and np.all(r["sum"] != 0)]
+        print(f"[{precision}] {shape}: worst error / sum|terms| {worst:.3e}; worst plain relative "
+              f"{max(rel):.3e}", flush=True)
+    print(f"[{precision}] {shape}: worst scaled error {worst:.3e}", flush=True)
+
+
+def test_bf16x3_needs_matrix_cores(eng):
+    p = W.tiny_star(seed=0, n_fact=1_000)
+    with pytest.raises(eng.LmfaoError):
+        eng.Plan(p, precision="bf16x3", contraction="valu")
+    with pytest.raises(eng.LmfaoError):
+        eng.Plan(p, precision="bf16x6", contraction="valu")
+
+
 def test_repeat_runs_identical_counts(eng):
     p = W.tiny_star(seed=2, n_fact=40_000)
     plan = eng.Plan(p, policy="fact", row_piece_max=-1, min_segment=1)
