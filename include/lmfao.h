@@ -197,10 +197,12 @@ typedef struct {
  * capacity.  LEARNED without an estimator blob behaves as BOUND. */
 enum { LMFAO_SIZING_BOUND = 0, LMFAO_SIZING_LEARNED = 1 };
 
-/* Estimator blob: {version = 1, d = LMFAO_EST_FEATURES, h, margin},
+/* Estimator blob: {version = 2, d = LMFAO_EST_FEATURES, h, margin},
  * then d feature means, d feature standard deviations, then the
  * lmfao_mlp_size(d, h) network parameters (layout of lmfao_mlp_train).  The
- * network maps standardized features (x - mean) / std to log2(1 + groups).
+ * network maps standardized features (x - mean) / std to the shortfall of
+ * log2(1 + groups) below feature 14 (log2 of the BOUND group count), so the
+ * estimate is y = x[14] - network((x - mean) / std).
  * Features of an output with key attributes K, in order (log2 means
  * log2(1 + value); per-key slots follow K's order, zero past |K| or past 3):
  *   0 log2 rows of the query's root relation   1 log2 total rows of all relations
@@ -209,8 +211,14 @@ enum { LMFAO_SIZING_BOUND = 0, LMFAO_SIZING_LEARNED = 1 };
  *   10..12 tree distance from the root to the nearest relation holding the key
  *   13 log2 product of the distinct counts     14 log2 of the BOUND group count
  *   15 1 if some relation's tuple determines every key attribute, else 0
- *   16 number of conditions of the batch-wide filter */
-#define LMFAO_EST_FEATURES 17
+ *   16 number of conditions of the batch-wide filter
+ *   17..19 log2 rows of each key's holder (the relation nearest the root
+ *          holding it)
+ *   20..22 log2 distinct values, in the holder's neighbour toward the root, of
+ *          the first attribute the two share (the holder's rows if it is the
+ *          root)
+ *   23..25 log2 distinct values of that attribute in the holder (same) */
+#define LMFAO_EST_FEATURES 26
 
 typedef struct lmfao_plan_s* lmfao_plan_t;
 typedef struct lmfao_prepared_s* lmfao_prepared_t;

@@ -296,7 +296,7 @@ class Prepared:
     def features(self, q: int):
         """Estimator features of query q (``lmfao_prepared_features``), or None
         for a query without group-by attributes."""
-        f = (C.c_float * 17)()
+        f = (C.c_float * 26)()
         st = self.lib.lmfao_prepared_features(self.handle, int(q), f)
         if st != 0:
             return None

@@ -1380,7 +1380,7 @@ Plan* build_plan(const lmfao_schema* schema, const lmfao_join_tree* tree, const 
     if (P->opts.estimator && P->opts.estimator_len > 0) {
       const float* e = P->opts.estimator;
       const int64_t len = P->opts.estimator_len;
-      if (len < 4 || e[0] != 1.f || e[1] != (float)LMFAO_EST_FEATURES || !(e[2] >= 1.f && e[2] <= 4096.f))
+      if (len < 4 || e[0] != 2.f || e[1] != (float)LMFAO_EST_FEATURES || !(e[2] >= 1.f && e[2] <= 4096.f))
         throw PlanError{LMFAO_EINVAL, "estimator blob: bad header"};
       const int64_t d = LMFAO_EST_FEATURES, h = (int64_t)e[2];
       const int64_t n = d * h + h + h * h + h + h + 1;

@@ -116,6 +116,7 @@ struct lmfao_prepared_s {
   lmfao::DHashOut* hash_dev = nullptr;                // device copy of the hash descriptors
   int hash_regrowths = 0;                             // runs repeated after a hash overflow
   std::map<int, int64_t> distinct;                    // distinct values per integer attribute
+  std::map<std::pair<int, int>, int64_t> distinct_rel; // ... per (attribute, relation)
   int32_t* hash_ovf = nullptr;                        // per table overflow flag
   std::vector<std::vector<const void*>> ecols;       // caller's columns, then derived bucket codes
   std::vector<const void* const*> ecol_ptrs;
@@ -1196,21 +1197,17 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
   }
 }
 
-// Distinct values of an integer attribute, counted on the GPU in the
-// smallest relation that holds it (every value of D is among them).
-static int64_t distinct_of(Prep& S, int a, hipStream_t st) {
-  auto it = S.distinct.find(a);
-  if (it != S.distinct.end()) return it->second;
+// Distinct values of integer attribute a in relation r, counted on the GPU
+// (a bitmap over the domain); the domain when a has none declared.
+static int64_t distinct_in(Prep& S, int a, int r, hipStream_t st) {
+  auto it = S.distinct_rel.find({a, r});
+  if (it != S.distinct_rel.end()) return it->second;
   Plan& P = *S.P;
   const AttrDef& A = P.attrs[a];
-  int best = -1, bc = -1;
-  for (size_t r = 0; r < P.rels.size(); ++r) {
-    auto c = P.rels[r].col.find(a);
-    if (c == P.rels[r].col.end() || P.rels[r].dtypes[c->second] != LMFAO_I32) continue;
-    if (best < 0 || P.rels[r].n_rows < P.rels[best].n_rows) best = (int)r, bc = c->second;
-  }
+  auto c = P.rels[r].col.find(a);
   int64_t d = A.domain > 0 ? A.domain : INT64_MAX;
-  if (best >= 0 && A.domain > 0) {
+  if (c != P.rels[r].col.end() && P.rels[r].dtypes[c->second] == LMFAO_I32 && A.domain > 0) {
+    const int best = r, bc = c->second;
     const int64_t words = (A.domain + 31) / 32;
     void *bits = nullptr, *cnt = nullptr;
     HIP_OK(hipMalloc(&bits, (size_t)words * 4));
@@ -1228,6 +1225,23 @@ static int64_t distinct_of(Prep& S, int a, hipStream_t st) {
     if (e != hipSuccess) throw PlanError{LMFAO_EHIP, std::string("distinct count: ") + hipGetErrorString(e)};
     d = (int64_t)h;
   }
+  S.distinct_rel[{a, r}] = d;
+  return d;
+}
+
+// Distinct values of an integer attribute in the smallest relation that
+// holds it (every value of D is among them).
+static int64_t distinct_of(Prep& S, int a, hipStream_t st) {
+  auto it = S.distinct.find(a);
+  if (it != S.distinct.end()) return it->second;
+  Plan& P = *S.P;
+  int best = -1;
+  for (size_t r = 0; r < P.rels.size(); ++r) {
+    auto c = P.rels[r].col.find(a);
+    if (c == P.rels[r].col.end() || P.rels[r].dtypes[c->second] != LMFAO_I32) continue;
+    if (best < 0 || P.rels[r].n_rows < P.rels[best].n_rows) best = (int)r;
+  }
+  const int64_t d = best >= 0 ? distinct_in(S, a, best, st) : (P.attrs[a].domain > 0 ? P.attrs[a].domain : INT64_MAX);
   S.distinct[a] = d;
   return d;
 }
@@ -1302,12 +1316,30 @@ static void query_features(Prep& S, const QueryDef& Q, float* f, hipStream_t st)
     const double dc = (double)distinct_of(S, a, st);
     pd *= dc;
     if (k >= 3) continue;
-    int near = 1 << 20;
+    int near = 1 << 20, h = -1;
     for (size_t r = 0; r < P.rels.size(); ++r)
-      if (P.rels[r].col.count(a) && dist[r] >= 0) near = std::min(near, dist[r]);
+      if (P.rels[r].col.count(a) && dist[r] >= 0 && dist[r] < near) near = dist[r], h = (int)r;
     f[4 + k] = lg(dc);
     f[7 + k] = lg((double)P.attrs[a].domain);
     f[10 + k] = (float)(near == (1 << 20) ? 0 : near);
+    if (h < 0) continue;
+    // the key's holder (nearest the root) and how much of it the join toward
+    // the root reaches: distinct values of the first join attribute on the
+    // root side and in the holder
+    const double hrows = (double)P.rels[h].n_rows;
+    f[17 + k] = lg(hrows);
+    f[20 + k] = f[17 + k];
+    f[23 + k] = f[17 + k];
+    if (h == Q.root) continue;
+    int par = -1;
+    for (int v : P.adj[h])
+      if (dist[v] == dist[h] - 1) par = v;
+    for (int j : P.rels[h].attrs) {
+      if (!P.rels[par].col.count(j)) continue;
+      f[20 + k] = lg((double)distinct_in(S, j, par, st));
+      f[23 + k] = lg((double)distinct_in(S, j, h, st));
+      break;
+    }
   }
   f[13] = lg(pd);
   f[14] = lg(query_bound(S, Q, st));
@@ -1315,7 +1347,8 @@ static void query_features(Prep& S, const QueryDef& Q, float* f, hipStream_t st)
   f[16] = (float)P.filter.size();
 }
 
-// log2(1 + groups) the estimator predicts from the features (FP32, host)
+// log2(1 + groups) the estimator predicts from the features (FP32, host):
+// the bound feature less the network's shortfall
 static double estimate_log2_groups(const std::vector<float>& blob, const float* x) {
   const int d = LMFAO_EST_FEATURES, h = (int)blob[2];
   const float* mean = blob.data() + 4;
@@ -1340,7 +1373,7 @@ static double estimate_log2_groups(const std::vector<float>& blob, const float* 
   }
   float y = b3[0];
   for (int j = 0; j < h; ++j) y += h2[j] * w3[j];
-  return (double)y;
+  return (double)x[14] - (double)y;
 }
 
 // largest initial hash table (2^26 slots, 1.5 GiB with one value); larger
@@ -1412,9 +1445,16 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
   HIP_OK(hipMemcpyAsync(&flag, S.err_flag, 4, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   if (flag & 2) throw PlanError{LMFAO_EINVAL, "an integer column holds a value outside its declared domain"};
-  // column statistics: distinct counts of every group-by attribute
-  for (const QueryDef& Q : P.queries)
+  // column statistics: distinct counts of every group-by attribute and of
+  // the join attributes the estimator features read (while the caller's
+  // columns are at hand)
+  for (const QueryDef& Q : P.queries) {
     for (int a : Q.groupby) distinct_of(S, a, st);
+    if (!Q.groupby.empty()) {
+      float f[LMFAO_EST_FEATURES];
+      query_features(S, Q, f, st);
+    }
+  }
   // output buffers: every view and query result lives in one arena that a
   // single fill zeroes at the start of each run
   S.vout.resize(P.views.size());
@@ -1457,7 +1497,7 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
         float f[LMFAO_EST_FEATURES];
         query_features(S, Q, f, st);
         const double y = estimate_log2_groups(P.estimator, f) + (double)P.estimator[3];
-        H.est = std::exp2(std::min(y, 62.0)) - 1.0;
+        H.est = std::max(0.0, std::exp2(std::min(y, 62.0)) - 1.0);
         want = (int64_t)std::min<double>((double)top, std::max(1024.0, 2.0 * H.est));
       }
       H.cap = 1;

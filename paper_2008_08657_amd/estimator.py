@@ -11,8 +11,9 @@ run repeated, so results never depend on the prediction.
   (``workloads.estimator_workload``): features of every query with group-by
   attributes and the exact number of groups the run produced;
 * training: the library's GPU kernels (``lmfao_mlp_train``), Adam on the mean
-  squared error of the log2 target (the square of the log q-error), with the
-  best validation snapshot kept;
+  squared error of the network's output against the shortfall of
+  log2(1 + groups) below the bound feature (so the error is the log2
+  q-error), with the best validation snapshot kept;
 * margin: the 95th percentile of the validation under-estimate, added to the
   prediction so that few tables start too small;
 * weights file: JSON with the feature names, network size, standardisation,
@@ -33,15 +34,19 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "estimator_weights.json")
-VERSION = 1
+VERSION = 2     # the network predicts the shortfall below the bound feature
 FEATURES = [
     "log2_root_rows", "log2_total_rows", "n_relations", "n_keys",
     "log2_distinct_0", "log2_distinct_1", "log2_distinct_2",
     "log2_domain_0", "log2_domain_1", "log2_domain_2",
     "distance_0", "distance_1", "distance_2",
     "log2_distinct_product", "log2_bound", "key_determined", "n_filter_conditions",
+    "log2_holder_rows_0", "log2_holder_rows_1", "log2_holder_rows_2",
+    "log2_join_distinct_parent_0", "log2_join_distinct_parent_1", "log2_join_distinct_parent_2",
+    "log2_join_distinct_holder_0", "log2_join_distinct_holder_1", "log2_join_distinct_holder_2",
 ]
 D = len(FEATURES)
+BOUND = FEATURES.index("log2_bound")
 
 
 def pack(mean, std, params, h: int, margin: float) -> np.ndarray:
@@ -81,10 +86,11 @@ def _predict_host(blob: np.ndarray, X: np.ndarray) -> np.ndarray:
     b2 = p[o:o + h]; o += h
     w3 = p[o:o + h]; o += h
     b3 = p[o]
-    z = (np.asarray(X, np.float32) - mean) / np.where(std > 0, std, 1).astype(np.float32)
+    X = np.asarray(X, np.float32)
+    z = (X - mean) / np.where(std > 0, std, 1).astype(np.float32)
     a = np.maximum(z @ W1 + b1, 0)
     a = np.maximum(a @ W2 + b2, 0)
-    return a @ w3 + b3
+    return X[:, BOUND] - (a @ w3 + b3)
 
 
 def corpus(problems, device="cuda:0", log=None, total=None):
@@ -128,8 +134,11 @@ def corpus(problems, device="cuda:0", log=None, total=None):
             f = prep.features(q)
             if f is None:
                 continue
+            n_groups = len(res[q]["keys"])
+            if n_groups == 0:
+                continue   # empty join: no table to size
             X.append(f)
-            t.append(np.log2(1.0 + len(res[q]["keys"])))
+            t.append(np.log2(1.0 + n_groups))
             tag.append(p["name"])
         del prep, plan
         if log and (k + 1) % 20 == 0:
@@ -164,8 +173,10 @@ def train(X, t, h: int = 64, rounds: int = 40, steps_per_round: int = 200, batch
     std = X[tr].std(axis=0)
     std[std == 0] = 1
     Z = ((X - mean) / std).astype(np.float32)
+    # target: how far below the bound the group count lies (never negative)
+    short = np.maximum(X[:, BOUND] - t, 0).astype(np.float32)
     Xtr = torch.from_numpy(np.ascontiguousarray(Z[tr])).to(device)
-    ttr = torch.from_numpy(np.ascontiguousarray(t[tr])).to(device)
+    ttr = torch.from_numpy(np.ascontiguousarray(short[tr])).to(device)
     Xva = torch.from_numpy(np.ascontiguousarray(Z[val])).to(device)
     params = torch.from_numpy(_he_init(h, seed + 1)).to(device)
     ntr = int(tr.sum())
@@ -174,12 +185,12 @@ def train(X, t, h: int = 64, rounds: int = 40, steps_per_round: int = 200, batch
     for r in range(rounds):
         order = torch.from_numpy(g.integers(0, ntr, steps_per_round * bs).astype(np.int32)).to(device)
         losses = binding.mlp_train(params, Xtr, ttr, order, bs, h, lr=lr)
-        yv = binding.mlp_predict(params, Xva, h).cpu().numpy()
+        yv = X[val, BOUND] - binding.mlp_predict(params, Xva, h).cpu().numpy()
         err = float(np.mean((yv - t[val]) ** 2))
         trace.append((r, float(np.mean(losses[-20:])), err))
         if err < best_err:
             best_err, best = err, params.clone()
-    yv = binding.mlp_predict(best, Xva, h).cpu().numpy()
+    yv = X[val, BOUND] - binding.mlp_predict(best, Xva, h).cpu().numpy()
     under = t[val] - yv
     margin = float(max(0.0, np.percentile(under, 95)))
     blob = pack(mean, std, best.cpu().numpy(), h, margin)
@@ -201,6 +212,7 @@ def main(argv=None):
     ap.add_argument("--max-rows", type=int, default=1_000_000)
     ap.add_argument("--hidden", type=int, default=64)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--corpus-out", default=None, help="also save the corpus (npz)")
     a = ap.parse_args(argv)
     import workloads as W
     log = lambda m: print(m, flush=True)  # noqa: E731
@@ -208,6 +220,8 @@ def main(argv=None):
     probs = (W.estimator_workload(a.seed * 100_000 + s, a.max_rows) for s in range(a.workloads))
     X, t, tag = corpus(probs, log=log, total=a.workloads)
     log(f"corpus: {len(X)} outputs in {time.time() - t0:.1f} s")
+    if a.corpus_out:
+        np.savez(a.corpus_out, X=X, t=t, tag=np.asarray(tag))
     blob, rep = train(X, t, h=a.hidden, groups=tag, seed=a.seed)
     # held out: Rk-means chains (a generator the corpus never draws from)
     held = [W.rkmeans_chain(seed=s, n1=200_000, n2=20_000, n3=2_000, n_x=8, n_y=6, n_z=6, max_dom=1_000_000)

@@ -30,7 +30,7 @@ def test_host_network_matches_oracle():
     y = est._predict_host(blob, X)
     p = mlp.unflatten(params.astype(np.float64), est.D, 8)
     yo, _ = mlp.forward(p, (X.astype(np.float64) - mean) / std)
-    np.testing.assert_allclose(y, yo, rtol=1e-4, atol=1e-4)
+    np.testing.assert_allclose(y, X[:, est.BOUND] - yo, rtol=1e-4, atol=1e-4)
 
 
 def test_weights_file_round_trip(tmp_path):

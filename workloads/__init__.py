@@ -459,7 +459,7 @@ def cart_node(seed: int = 0, n_inv: int = 84_000_000, n_thr: int = 20, n_node_co
 
 
 def rkmeans_chain(seed: int = 0, n1: int = 50_000_000, n2: int = 5_000_000, n3: int = 200_000,
-                  n_x: int = 40, n_y: int = 30, n_z: int = 30, max_dom: int = 1_000_000):
+                  n_x: int = 40, n_y: int = 30, n_z: int = 30, max_dom: int = 1_000_000, zipf: float = 0.0):
     """Step 1 of Rk-means (section 3, Rk-means) on a chain join R1(a, b, x*) -
     R2(b, c, y*) - R3(c, z*) with foreign keys b and c (every R1 row joins
     exactly once).  Attribute j takes values k ~ U[0, d_j) with d_j =
@@ -468,7 +468,8 @@ def rkmeans_chain(seed: int = 0, n1: int = 50_000_000, n2: int = 5_000_000, n3: 
     n_x + n_y + n_z attributes, plus SUM(1) GROUP BY X_i, X_j for 10 pairs
     (4 within R1, 2 within R2, 1 within R3, 2 across R1 x R2, 1 across
     R1 x R3) picked by seed from domain-sorted attributes so that their group
-    counts spread from small to large."""
+    counts spread from small to large.  ``zipf`` > 0 draws every attribute
+    from Zipf(zipf) over its domain instead of uniformly."""
     r1, r2, r3, rd = _spawn(seed, 4)
     top = np.log10(max_dom)
     names = ([f"x{j}" for j in range(1, n_x + 1)] + [f"y{j}" for j in range(1, n_y + 1)]
@@ -480,7 +481,8 @@ def rkmeans_chain(seed: int = 0, n1: int = 50_000_000, n2: int = 5_000_000, n3: 
     for rel, rng, pre, cnt, n in ((R1, r1, "x", n_x, n1), (R2, r2, "y", n_y, n2), (R3, r3, "z", n_z, n3)):
         for j in range(1, cnt + 1):
             a = f"{pre}{j}"
-            rel[a] = rng.integers(0, dom[a], n, dtype=np.int32)
+            rel[a] = (zipf_keys(rng, n, dom[a], zipf) if zipf > 0
+                      else rng.integers(0, dom[a], n, dtype=np.int32))
     schema = [
         _rel("R1", n1, [_attr("a", "i32"), _attr("b", "i32", n2)]
              + [_attr(f"x{j}", "i32", dom[f"x{j}"]) for j in range(1, n_x + 1)]),
@@ -512,7 +514,8 @@ def estimator_workload(seed: int, max_rows: int = 1_000_000):
     10^U(4, log10 max_rows) rows, every other relation up to as many as its
     parent.  An edge is a foreign key into the child (probability 0.7: the
     child's key attribute is 0..n-1, the parent's reference uniform or Zipf) or
-    a many-to-many join on an attribute with domain 10^U(1, 4).  Every relation
+    a many-to-many join on an attribute with domain 10^U(1, 4), the parent
+    referring to values the child holds.  Every relation
     has 1-3 integer attributes with domains 10^U(1, 6), uniform or Zipf(s in
     [0.8, 1.5]).  Batch: SUM(1) grouped by each such attribute and by up to 6
     random pairs of them that one relation reaches through foreign keys."""
@@ -543,11 +546,13 @@ def estimator_workload(seed: int, max_rows: int = 1_000_000):
             attrs[p].append(_attr(k, "i32", rows[c]))
             data[p][k] = values(rows[p], rows[c])
         else:
+            # many-to-many: the parent refers to values the child holds
             dk = int(10 ** g.uniform(1, 4))
             attrs[c].append(_attr(k, "i32", dk))
             data[c][k] = values(rows[c], dk)
+            held = np.unique(data[c][k])
             attrs[p].append(_attr(k, "i32", dk))
-            data[p][k] = values(rows[p], dk)
+            data[p][k] = held[values(rows[p], len(held))]
     feats, owned = [], [[] for _ in range(n_rel)]
     for r in range(n_rel):
         for j in range(int(g.integers(1, 4))):
