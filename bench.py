@@ -152,11 +152,15 @@ def main():
     kd = steps[kern[0]]
     kern_ms = kern[1]
     alg_bytes = kd["alg_read_bytes"] + kd["alg_write_bytes"]
-    if kd["kind"] == "gemm":
-        # FP64 matrix-core contraction: priced against the FP64 MFMA peak
+    t_s = kern_ms * 1e-3
+    mfma_peak = 2500.0 if precision.startswith("bf16") else 78.6   # the contraction's MFMA type
+    if kd["kind"] in ("gemm", "contract") and kd["alg_flop"] / t_s / 1e12 / mfma_peak > alg_bytes / t_s / 8e12:
+        # matrix-core contraction: priced against the MFMA peak of its type
+        # (FP64, or bf16 for the split forms, counting useful flops only)
+        peak = mfma_peak
         achieved = kd["alg_flop"] / (kern_ms * 1e-3) / 1e12
-        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": 78.6, "unit": "TFLOP/s",
-                    "frac": round(achieved / 78.6, 4), "traffic": None,
+        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4), "traffic": None,
                     "kernel": kern[0], "kernel_ms": round(kern_ms, 4), "alg_flop": kd["alg_flop"]}
     else:
         achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
@@ -164,6 +168,27 @@ def main():
                     "frac": round(achieved / 8000.0, 4), "traffic": None,
                     "kernel": kern[0], "kernel_ms": round(kern_ms, 4),
                     "alg_bytes": int(alg_bytes)}
+
+    # HBM traffic of the dominant kernel from committed counter runs, valid
+    # only while its generated source is the one that was profiled
+    group = kern[0].rsplit(":", 1)[0]
+    src = next((x.split("\n", 1)[1] for x in prep.kernel_sources() if x.split("\n", 1)[0] == group), None)
+    digest = None
+    if src is not None:
+        from paper_2008_08657_amd.profiling import source_digest
+        digest = source_digest(src)
+    roofline["kernel_source_digest"] = digest
+    prof_dir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+    if digest and os.path.isdir(prof_dir):
+        for fn in sorted(os.listdir(prof_dir)):
+            if not (fn.startswith("traffic_") and fn.endswith(".json")):
+                continue
+            with open(os.path.join(prof_dir, fn)) as f:
+                rec = json.load(f)
+            if rec.get("workload") == args.config and rec.get("step") == kern[0] and \
+                    rec.get("source_digest") == digest:
+                roofline["traffic"] = int(rec["bytes"])
+                roofline["traffic_source"] = fn
 
     # sanity on the GPU results: COUNT equals |D| (closed form)
     check = {}

@@ -11,6 +11,8 @@
 // caches the function by source text for the life of the process.  The
 // kernel computes exactly what the generic lean scan computes.
 #include <hip/hip_runtime.h>
+
+#include <cctype>
 #include <hip/hiprtc.h>
 
 #include <cstdio>
@@ -48,7 +50,11 @@ std::string mu(int m) { return "mu" + std::to_string(m); }
 
 }  // namespace
 
-bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::string& why) {
+bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, GenKernel& out, std::string& why) {
+  // kernel name: lmfao_scan_ plus the tag's letters and digits (profiles
+  // tell the groups apart by it)
+  std::string kname = "lmfao_scan_";
+  for (char ch : tag) kname += std::isalnum((unsigned char)ch) ? ch : '_';
   const DFast& F = d.F;
   if (!d.fast) {
     why = "not a lean scan";
@@ -121,7 +127,7 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::stri
     e << "__device__ __forceinline__ float wsumc(float s) { return wsum(s); }\n";
   }
   e << "extern \"C\" __global__ __launch_bounds__(" << kGenWaves * 64
-    << ") void lmfao_gen_scan(const unsigned long long* __restrict__ A) {\n";
+    << ") void " << kname << "(const unsigned long long* __restrict__ A) {\n";
   e << "  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];\n";
   e << "  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;\n";
   // arguments
@@ -364,7 +370,7 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, GenKernel& out, std::stri
   auto it = cache.find(src);
   if (it == cache.end()) {
     hipFunction_t fn = nullptr;
-    if (!compile_kernel(src, "lmfao_gen_scan", fn, why)) return false;
+    if (!compile_kernel(src, kname.c_str(), fn, why)) return false;
     it = cache.emplace(src, fn).first;
   }
   out.fn = it->second;

@@ -21,7 +21,8 @@ struct GenKernel {
 // Generates and compiles the scan of a lean scan descriptor.  Returns false
 // with a reason when the descriptor is outside what the generator handles or
 // compilation fails; the caller then launches the generic lean kernel.
-bool gen_scan_kernel(const DScan& d, int n_atoms, bool f64, GenKernel& out, std::string& why);
+bool gen_scan_kernel(const DScan& d, int n_atoms, bool f64, const std::string& tag, GenKernel& out,
+                     std::string& why);
 
 // hipRTC compile of `src` for gfx950 and load of the function `name`.
 bool compile_kernel(const std::string& src, const char* name, hipFunction_t& fn, std::string& why);

@@ -34,6 +34,9 @@ constexpr int kMaxTables = 8;      // direct group-by tables written by a scan
 constexpr int kMaxTableComps = 8;
 constexpr int kOneHotMax = 64;     // largest code domain expanded one-hot
 constexpr int kHistMax = 1024;     // largest code domain kept per piece
+constexpr int kScanWaves = 8;      // wavefronts per scan block (each holds its own histograms)
+constexpr int kLdsBytes = 160 * 1024;            // LDS of one compute unit
+constexpr int64_t kLdsTableMax = 12288;          // int32 count entries privatized in LDS
 constexpr int kTriangle = (kMaxAtoms + 1) * (kMaxAtoms + 2) / 2;  // incl. (1,1)
 constexpr int64_t kDenseRowsMax = (int64_t)1 << 24;  // larger key spaces go to hash tables
 
@@ -241,6 +244,7 @@ struct GroupDef {
   std::vector<int> unique_views;  // views built directly (unique on their key)
   std::set<int> deps;             // groups this one depends on
   bool has_program = false;
+  bool force_rows = false;        // evaluated row by row (an output has no scan form)
   GroupProgram prog;
 };
 

@@ -543,8 +543,10 @@ void launch_validate(const int32_t* col, int64_t n, int64_t dom, int32_t* err_fl
 // against the domain at prepare time.
 __global__ void k_mark_values(const int32_t* __restrict__ col, int64_t n, uint32_t* __restrict__ bits) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t v = (uint32_t)col[i];
-    atomicOr(bits + (v >> 5), 1u << (v & 31));
+    const uint32_t v = (uint32_t)col[i], m = 1u << (v & 31);
+    // most values repeat: test the bit before paying for the atomic (a
+    // stale read only costs a redundant atomic)
+    if (!(bits[v >> 5] & m)) atomicOr(bits + (v >> 5), m);
   }
 }
 __global__ void k_popcount(const uint32_t* __restrict__ bits, int64_t words, unsigned long long* __restrict__ out) {
@@ -624,7 +626,7 @@ void launch_segment_starts(const uint64_t* keys, int64_t n, uint64_t div, unsign
 // ---------------------------------------------------------------------------
 // node scan
 // ---------------------------------------------------------------------------
-constexpr int kScanWaves = 8;   // wavefronts per block
+// kScanWaves (wavefronts per scan block) is shared with the planner
 
 __device__ __forceinline__ int tri_index(int i, int j, int n) {
   // extended atoms 0..n (0 = constant 1), i <= j; row-major upper triangle

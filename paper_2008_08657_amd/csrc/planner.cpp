@@ -889,7 +889,7 @@ void ProgBuilder::build() {
       for (int a : P.views[o.id].key) cells *= (double)P.attrs[a].domain;
     hashed |= cells > (double)kDenseRowsMax;
   }
-  if (R.n_rows <= kRowPieceMax || hashed) {
+  if (R.n_rows <= kRowPieceMax || hashed || G.force_rows) {
     g.row_pieces = true;
     g.cut = L + 1;
   } else {
@@ -1222,10 +1222,117 @@ void ProgBuilder::build() {
   g.gemm_cells = cells;
 }
 
-static void build_programs(Plan& P) {
+// cells of an output's dense key space
+static double out_cells(const Plan& P, const OutRef& o) {
+  const std::vector<int>& gb = o.kind == 0 ? P.queries[o.id].groupby : P.views[o.id].carried;
+  double cells = 1;
+  for (int a : gb) cells *= (double)P.attrs[a].domain;
+  if (o.kind == 1)
+    for (int a : P.views[o.id].key) cells *= (double)P.attrs[a].domain;
+  return cells;
+}
+
+// what the kernels of one group can hold
+static bool program_fits(const GroupProgram& g) {
+  int tables = 0;
+  for (const ProgOutput& po : g.outs) tables += po.mode == 2;
+  // a scan block holds every histogram once per wavefront (FP64 bins at most),
+  // the per-wave factor staging and the LDS-privatized tables
+  const int64_t wave = (int64_t)g.hist_i_bins * 4 + (int64_t)g.hist_f_bins * 8 + 16 + (kMaxAtoms + 5) * 64 * 8;
+  const bool lds_ok = (int64_t)kScanWaves * wave + kLdsTableMax * 4 <= kLdsBytes;
+  return g.in_masks.size() <= (size_t)kMaxMasks && g.psi_i.size() <= (size_t)kMaxMasks &&
+         g.in_codes.size() <= (size_t)kMaxCodes && g.hists.size() <= (size_t)kMaxHists &&
+         g.views.size() <= (size_t)kMaxViews && (g.row_pieces || (tables <= kMaxTables && lds_ok));
+}
+
+// Moves outputs [from, end) of group gi into a new group at the same node and
+// level (no dependency between the two) and renumbers the outputs' groups.
+static void split_group(Plan& P, int gi, size_t from) {
+  GroupDef H;
+  H.node = P.groups[gi].node;
+  H.level = P.groups[gi].level;
+  H.force_rows = P.groups[gi].force_rows;
+  H.outs.assign(P.groups[gi].outs.begin() + from, P.groups[gi].outs.end());
+  P.groups[gi].outs.resize(from);
+  const int hi = (int)P.groups.size();
+  for (auto& o : H.outs) {
+    if (o.kind == 1) P.views[o.id].group = hi;
+    else P.queries[o.id].group = hi;
+  }
+  P.groups.push_back(H);
   for (auto& G : P.groups) {
-    ProgBuilder b(P, G);
-    b.build();
+    G.deps.clear();
+    for (auto& o : G.outs) {
+      if (o.kind == 1)
+        for (int d : P.views[o.id].deps) G.deps.insert(P.views[d].group);
+      else
+        for (auto& kv : P.queries[o.id].in_view) G.deps.insert(P.views[kv.second].group);
+    }
+  }
+}
+
+// Builds every group's program.  Outputs kept in hash tables are evaluated row
+// by row, so they leave their group for one of their own; a group whose
+// program exceeds what one scan kernel holds (columns, codes, masks,
+// histograms, views) is halved until each part fits.
+static void build_programs(Plan& P) {
+  for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    auto& outs = P.groups[gi].outs;
+    std::stable_partition(outs.begin(), outs.end(),
+                          [&](const OutRef& o) { return out_cells(P, o) <= (double)kDenseRowsMax; });
+    size_t n_dense = 0;
+    while (n_dense < outs.size() && out_cells(P, outs[n_dense]) <= (double)kDenseRowsMax) ++n_dense;
+    if (n_dense > 0 && n_dense < outs.size()) split_group(P, (int)gi, n_dense);
+  }
+  for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    for (;;) {
+      GroupDef& G = P.groups[gi];
+      G.has_program = false;
+      G.prog = GroupProgram{};
+      G.unique_views.clear();
+      std::string why;
+      try {
+        ProgBuilder b(P, G);
+        b.build();
+        if (!G.has_program || program_fits(G.prog)) break;
+        why = "a group exceeds the limits of one scan kernel";
+      } catch (const PlanError& e) {
+        if (e.status != LMFAO_EUNSUPPORTED) throw;
+        if (e.msg.find("mixes large inner group-by keys") != std::string::npos && !G.force_rows) {
+          // outputs with no scan form go to a group evaluated row by row
+          auto& outs = P.groups[gi].outs;
+          std::vector<char> alone_ok(outs.size(), 1);
+          for (size_t k = 0; k < outs.size(); ++k) {
+            GroupDef T;
+            T.node = P.groups[gi].node;
+            T.level = P.groups[gi].level;
+            T.outs = {outs[k]};
+            try {
+              ProgBuilder tb(P, T);
+              tb.build();
+            } catch (const PlanError& e2) {
+              if (e2.status != LMFAO_EUNSUPPORTED || e2.msg.find("mixes large inner") == std::string::npos) throw;
+              alone_ok[k] = 0;
+            }
+          }
+          std::vector<OutRef> keep, rows;
+          for (size_t k = 0; k < outs.size(); ++k) (alone_ok[k] ? keep : rows).push_back(outs[k]);
+          if (keep.empty()) {
+            P.groups[gi].force_rows = true;
+          } else {
+            outs = keep;
+            outs.insert(outs.end(), rows.begin(), rows.end());
+            split_group(P, (int)gi, keep.size());
+            P.groups.back().force_rows = true;
+          }
+          continue;
+        }
+        if (e.msg.rfind("too many", 0) != 0) throw;
+        why = e.msg;
+      }
+      if (P.groups[gi].outs.size() < 2) fail(LMFAO_EUNSUPPORTED, why);
+      split_group(P, (int)gi, P.groups[gi].outs.size() / 2);
+    }
   }
 }
 

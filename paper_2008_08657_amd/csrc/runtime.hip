@@ -36,7 +36,6 @@ static constexpr int64_t kPieceMax = 8192;    // rows of one piece at most
 static constexpr int64_t kPieceMaxF64 = 64;   // FP64 plans: short (uncompensated) histogram chains
 static constexpr int64_t kItemRows = 4096;    // rows one wavefront takes per work item, at most
 static constexpr int64_t kTargetItems = 16384; // work items wanted per scan: ~4 per resident wavefront
-static constexpr int64_t kLdsTableMax = 12288;   // int32 count entries privatized in LDS
 
 struct OutBuf {
   int64_t* cnt = nullptr;
@@ -935,7 +934,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     if (fast && S.P->opts.codegen == 0) {
       GenKernel gk;
       std::string why;
-      if (gen_scan_kernel(d, NA, f64, gk, why)) {
+      if (gen_scan_kernel(d, NA, f64, gname, gk, why)) {
         s.gen_fn = gk.fn;
         s.gen_args = upload_vec(S, gk.args, st);
         s.gen_block = gk.block;

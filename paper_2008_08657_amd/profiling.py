@@ -1,0 +1,105 @@
+"""Summaries of rocprofv3 output for the benchmark's kernels.
+
+``summarize``: a Markdown table of the kernel-trace statistics
+(``*_kernel_stats.csv``) with the command that produced them.
+
+``traffic``: HBM bytes per launch of one kernel from two counter runs
+(``FETCH_SIZE`` and ``WRITE_SIZE``, KiB per dispatch), each scaled by what the
+same counter reads for a plain device copy of known size.  The record names
+the kernel and a digest of its generated source; ``bench.py`` reports the
+bytes only while the kernel it measures has that same source.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import sys
+
+
+def source_digest(text: str) -> str:
+    return hashlib.sha1(text.encode()).hexdigest()[:16]
+
+
+def _counter_rows(path, counter):
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] == counter:
+                yield row["Kernel_Name"], float(row["Counter_Value"])
+
+
+def mean_counter(path, counter, kernel):
+    vals = [v for k, v in _counter_rows(path, counter) if k == kernel]
+    if not vals:
+        raise SystemExit(f"{path}: no {counter} rows for kernel {kernel}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def copy_counter(path, counter):
+    """The counter of the largest copy dispatch (the 1 GiB calibration copy)."""
+    vals = [v for k, v in _counter_rows(path, counter) if "copyBuffer" in k]
+    if not vals:
+        raise SystemExit(f"{path}: no copy dispatch")
+    return max(vals)
+
+
+def traffic(a):
+    f_kib, nf = mean_counter(a.fetch, "FETCH_SIZE", a.kernel)
+    w_kib, nw = mean_counter(a.write, "WRITE_SIZE", a.kernel)
+    cf = copy_counter(a.copy_fetch, "FETCH_SIZE")
+    cw = copy_counter(a.copy_write, "WRITE_SIZE")
+    f_scale = a.copy_bytes / (cf * 1024.0)
+    w_scale = a.copy_bytes / (cw * 1024.0)
+    rec = {"workload": a.workload, "kernel": a.kernel, "step": a.step, "source_digest": a.source_digest,
+           "fetch_kib": f_kib, "write_kib": w_kib, "dispatches": [nf, nw],
+           "copy_bytes": a.copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "bytes_read": f_kib * 1024.0 * f_scale, "bytes_written": w_kib * 1024.0 * w_scale,
+           "commands": a.command}
+    rec["bytes"] = rec["bytes_read"] + rec["bytes_written"]
+    with open(a.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def summarize(a):
+    rows = []
+    with open(a.trace, newline="") as f:
+        for r in csv.DictReader(f):
+            rows.append(r)
+    lines = [f"# {a.title}", "", "Command:", "", "```", *a.command, "```", "",
+             "| kernel | calls | total ms | average us | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:a.top]:
+        name = r["Name"] if len(r["Name"]) < 90 else r["Name"][:87] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if a.note:
+        lines += ["", *a.note]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "out", "workload", "step"):
+        t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--source-digest", required=True)
+    t.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    t.add_argument("--command", action="append", default=[])
+    s = sub.add_parser("summarize")
+    s.add_argument("--trace", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", required=True)
+    s.add_argument("--top", type=int, default=25)
+    s.add_argument("--command", action="append", default=[])
+    s.add_argument("--note", action="append", default=[])
+    a = ap.parse_args(argv)
+    traffic(a) if a.cmd == "traffic" else summarize(a)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -232,6 +232,19 @@ def test_forms_agree(eng, form):
           min_segment=16)
 
 
+def test_rkmeans_chain_wide(eng):
+    # 64 attributes over three relations, all scanned (row pieces only below
+    # 5,000 rows): groups split to fit the scan kernels, cross pairs with a
+    # large outer key evaluated row by row, hashed pairs in groups of their own
+    p = W.rkmeans_chain(seed=3, n1=150_000, n2=80_000, n3=70_000, n_x=24, n_y=20, n_z=20, max_dom=30_000)
+    print("[case] rkmeans wide", flush=True)
+    plan = eng.Plan(p, precision="f32", policy="fact", row_piece_max=5_000, min_segment=16)
+    assert len(plan.describe()["groups"]) > 3
+    prep = eng.Prepared(plan, eng.device_columns(p))
+    prep.run(sync=True)
+    compare_all(prep.results(), oracle.evaluate(p), F32_TOL, "rkmeans_wide")
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 @pytest.mark.parametrize("hash_slots", [0, 1024])
 def test_rkmeans_chain(eng, seed, hash_slots):

@@ -220,3 +220,25 @@ def test_per_view_form_has_one_output_per_group():
     assert all(len(g["outputs"]) == 1 for g in solo["groups"])
     n_out = len(solo["views"]) + len(solo["queries"])
     assert len(solo["groups"]) == n_out == 9
+
+
+def test_wide_chain_groups_are_split_to_fit_the_kernels():
+    # Rk-means step 1 at full size: 40 + 30 + 30 attributes grouped one by one
+    # and in pairs; the planner halves groups whose scan would exceed one
+    # kernel's columns or histograms, moves hashed outputs and outputs with no
+    # scan form (an inner and a large outer key) to groups evaluated row by row
+    p = W.rkmeans_chain(seed=0, n1=2000, n2=200, n3=20)
+    for r, n in zip(p["schema"], (50_000_000, 5_000_000, 200_000)):
+        r["n_rows"] = n
+    d = E.Plan(p, precision="f32", policy="fact").describe()
+    outs = [o for g in d["groups"] for o in g["outputs"]]
+    queries = sorted(o["id"] for o in outs if o["kind"] == "query")
+    assert queries == list(range(len(p["batch"])))
+    by_rel = {}
+    for g in d["groups"]:
+        by_rel.setdefault(g["node"], []).append(g)
+    assert len(by_rel["R1"]) > 2
+    assert any((g.get("program") or {}).get("row_pieces") for g in by_rel["R1"])
+    for g in d["groups"]:
+        prog = g.get("program") or {}
+        assert len(prog.get("scan_cols", [])) <= 16
