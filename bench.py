@@ -54,7 +54,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="retail", choices=["retail", "tiny", "grocery", "cart", "chain"])
-    ap.add_argument("--precision", default=None, choices=["f64", "f32", "bf16x3", "bf16x6"],
+    ap.add_argument("--precision", default=None, choices=["f64", "f32", "bf16x3", "bf16x2"],
                     help="arithmetic (default: the configuration's own)")
     ap.add_argument("--sizing", default=None, choices=["bound", "learned"],
                     help="hash-table sizing (default: learned for chain, bound otherwise)")

@@ -131,15 +131,16 @@ typedef struct {
 
 /* F64 and F32: arithmetic of the scans, views and contraction.  BF16X3:
  * scans and views in FP32; in the matrix-core contraction each tile without
- * integer cells splits its FP32 operands x into hi = bf16(x) and
- * lo = bf16(x - hi) and sums hi*hi' + hi*lo' + lo*hi' on the bf16 matrix
- * cores (v_mfma_f32_16x16x16_bf16), in FP32 within a chunk of 16 pieces and
- * FP64 across chunks; tiles with integer cells stay exact in FP64.  Each
- * product is then within about 2^-16 of exact, so a float result is within
- * 2^-16 of the sum of its terms' magnitudes (relative 1e-5 unless the sum
- * cancels).  BF16X6: three parts (hi, mid, lo) and six products, FP32
- * accuracy.  Both require LMFAO_CONTRACT_MFMA. */
-enum { LMFAO_PREC_F64 = 0, LMFAO_PREC_F32 = 1, LMFAO_PREC_BF16X3 = 2, LMFAO_PREC_BF16X6 = 3 };
+ * integer cells splits its FP32 operands x into three bf16 parts,
+ * hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid) (24 bits in all),
+ * and sums the six products hi*hi' + hi*mid' + mid*hi' + hi*lo' + mid*mid' +
+ * lo*hi' on the bf16 matrix cores (v_mfma_f32_16x16x16_bf16), in FP32 within
+ * a chunk of 16 pieces and FP64 across chunks; the terms left out are about
+ * 2^-24 of each product, FP32 accuracy.  Tiles with integer cells stay exact
+ * in FP64.  BF16X2: two parts (hi, lo) and three products; each product is
+ * then within about 2^-16 of exact, so a float result is within 2^-16 of the
+ * sum of its terms' magnitudes.  Both require LMFAO_CONTRACT_MFMA. */
+enum { LMFAO_PREC_F64 = 0, LMFAO_PREC_F32 = 1, LMFAO_PREC_BF16X3 = 2, LMFAO_PREC_BF16X2 = 3 };
 enum { LMFAO_FORM_FUSED = 0, LMFAO_FORM_PER_VIEW = 1 };
 /* Root heuristics.  GROUPBY: the relation holding every group-by attribute,
  * the largest such relation (reproduces the roots of the worked example);

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblmfao.so")
 
 I32, F32, F64 = 0, 1, 2
-PREC_F64, PREC_F32 = 0, 1
+PREC_F64, PREC_F32, PREC_BF16X3, PREC_BF16X2 = 0, 1, 2, 3
 FORM_FUSED, FORM_PER_VIEW = 0, 1
 ROOT_GROUPBY, ROOT_FACT = 0, 1
 OPS = {"<=": 0, "<": 1, ">": 2, ">=": 3, "==": 4, "!=": 5}
@@ -201,9 +201,10 @@ class Plan:
         schema, tree, batch = marshal_problem(problem, keep)
         opts = lmfao_options()
         self.lib.lmfao_default_options(C.byref(opts))
-        if precision not in ("f64", "f32", "bf16x3", "bf16x6"):
-            raise ValueError(f"precision must be 'f64', 'f32', 'bf16x3' or 'bf16x6', not {precision!r}")
-        opts.precision = {"f64": PREC_F64, "f32": PREC_F32, "bf16x3": 2, "bf16x6": 3}[precision]
+        if precision not in ("f64", "f32", "bf16x3", "bf16x2"):
+            raise ValueError(f"precision must be 'f64', 'f32', 'bf16x3' or 'bf16x2', not {precision!r}")
+        opts.precision = {"f64": PREC_F64, "f32": PREC_F32, "bf16x3": PREC_BF16X3,
+                          "bf16x2": PREC_BF16X2}[precision]
         opts.form = FORM_FUSED if form == "fused" else FORM_PER_VIEW
         pol = policy if policy is not None else problem.get("policy", "groupby")
         opts.root_policy = ROOT_FACT if pol == "fact" else ROOT_GROUPBY

@@ -1595,9 +1595,10 @@ int contract_fused_lds_bytes(const DContract& C, int tn) {
 }
 int contract_fused_chunk() { return kFKC; }
 
-// BF16x3 split of a value: hi = bf16(x) and lo = bf16(x - hi), both rounded
-// to nearest even from FP32; hi*hi' + hi*lo' + lo*hi' leaves out lo*lo' and
-// the residues below lo, about 2^-16 of the product at most.
+// BF16 split of a value into NS parts, each the bf16 (nearest even) of what
+// the parts before it leave of the FP32 value.  NS = 2: hi*hi' + hi*lo' +
+// lo*hi' leaves out lo*lo' and the residues below lo, about 2^-16 of the
+// product at most.
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);
@@ -1648,7 +1649,7 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
   const int64_t kb = (int64_t)blockIdx.x * G->k_per_block;
   const int64_t ke = std::min<int64_t>(G->n, kb + G->k_per_block);
   const bool do_scatter = blockIdx.y == 0;
-  // BF16x3 tiles hold no integer cell (integer features and columns come
+  // split (BF16) tiles hold no integer cell (integer features and columns come
   // first); the others stay on the exact FP64 path
   const bool split = NS > 0 && (f0 >= C->n_feat_int || g0 >= C->n_col_int);
   uint16_t* Asp = (uint16_t*)As;                           // NS planes of [kGemmMT][kBKS]

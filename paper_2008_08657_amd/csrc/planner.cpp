@@ -1496,7 +1496,7 @@ Plan* build_plan(const lmfao_schema* schema, const lmfao_join_tree* tree, const 
     }
     P->opts.estimator = nullptr;
     P->opts.estimator_len = 0;
-    if (P->opts.precision < LMFAO_PREC_F64 || P->opts.precision > LMFAO_PREC_BF16X6)
+    if (P->opts.precision < LMFAO_PREC_F64 || P->opts.precision > LMFAO_PREC_BF16X2)
       throw PlanError{LMFAO_EINVAL, "unknown precision"};
     if (P->opts.precision >= LMFAO_PREC_BF16X3 && P->opts.contraction != LMFAO_CONTRACT_MFMA)
       throw PlanError{LMFAO_EINVAL, "BF16 split precisions run the contraction on the matrix cores"};

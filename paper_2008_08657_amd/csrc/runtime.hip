@@ -1636,8 +1636,8 @@ static void enqueue_run(Prep& S, hipStream_t st) {
         break;
       case 8:
         launch_contract_fused((const DContract*)s.dev, (const DGemm*)s.dev2, S.f64,
-                              S.P->opts.precision == LMFAO_PREC_BF16X3   ? 2
-                              : S.P->opts.precision == LMFAO_PREC_BF16X6 ? 3
+                              S.P->opts.precision == LMFAO_PREC_BF16X3   ? 3
+                              : S.P->opts.precision == LMFAO_PREC_BF16X2 ? 2
                                                                          : 0,
                               s.na, s.grid, s.grid_y, s.lds, st);
         break;
