@@ -10,7 +10,10 @@ FP64 merges and results.  Synthetic data, seed 0.
 
 One step = one ``lmfao_run``: every view and every query of the plan, on the
 GPU, inputs already resident in HBM (prepare -- sorting and trie pieces -- is
-done once before the timed region and reported separately).
+done once before the timed region and reported separately).  The timed steps
+replay the run as a HIP graph captured during the warm-up (``--no-graph``
+launches directly); the per-kernel durations behind ``roofline`` come from as
+many further runs launched directly with HIP events around each launch.
 
 metric: join-tuple-aggregates/s = |D| * A / t_step, with |D| = 84M join tuples
 (every fact row joins exactly once) and A = 1,269 SUM expressions.
@@ -58,6 +61,7 @@ def main():
                     help="arithmetic (default: the configuration's own)")
     ap.add_argument("--sizing", default=None, choices=["bound", "learned"],
                     help="hash-table sizing (default: learned for chain, bound otherwise)")
+    ap.add_argument("--no-graph", action="store_true", help="launch every run directly (no HIP graph replay)")
     ap.add_argument("--plain-steps", type=int, default=0,
                     help="also time this many steps of the plain per-view form on the same input")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the fact table (testing only)")
@@ -120,7 +124,8 @@ def main():
     n_aggs = sum(len(q["aggs"]) for q in problem["batch"])
     t_gen = time.perf_counter() - t_gen
 
-    plan = E.Plan(problem, precision=precision, policy=problem["policy"], form=args.form, sizing=sizing)
+    plan = E.Plan(problem, precision=precision, policy=problem["policy"], form=args.form, sizing=sizing,
+                  graph=not args.no_graph)
     cols = E.device_columns(problem)
     torch.cuda.synchronize()
     t_prep = time.perf_counter()
@@ -134,17 +139,29 @@ def main():
     prep.run(sync=True)   # checks the kernels' error flags once
     torch.cuda.synchronize()
 
-    prep.set_timing(True)
+    # timed region: K runs replayed from the captured HIP graph (the warm-up
+    # captured it), bracketed by device synchronisation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         prep.run(sync=False)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    prep.set_timing(False)
-    timing = prep.timing()          # mean ms per timed launch over the timed steps
-    desc = prep.describe()
     ms_per_step = 1e3 * t / args.steps
+    graph = prep.describe()["graph"]
+
+    # per-launch durations: K more runs launched directly with HIP events
+    # around every timed launch, on the run's stream
+    prep.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prep.run(sync=False)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    prep.set_timing(False)
+    timing = prep.timing()          # mean ms per timed launch over those runs
+    desc = prep.describe()
 
     # dominant kernel: the timed launch with the largest mean duration
     steps = {s["name"]: s for s in desc["steps"]}
@@ -207,7 +224,8 @@ def main():
         del prep
         torch.cuda.empty_cache()
         cols = E.device_columns(problem)
-        pplan = E.Plan(problem, precision=precision, policy=problem["policy"], form="per_view", sizing=sizing)
+        pplan = E.Plan(problem, precision=precision, policy=problem["policy"], form="per_view", sizing=sizing,
+                       codegen=False)
         pprep = E.Prepared(pplan, cols)
         del cols
         torch.cuda.empty_cache()
@@ -245,6 +263,7 @@ def main():
                    "prepare_s": round(t_prep, 2), "generate_s": round(t_gen, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "graph": {"captured": bool(graph["captured"]), "ms_per_step_direct": round(1e3 * t_eager / args.steps, 4)},
         "kernels_ms": {k: round(v, 4) for k, v in timing},
         "plain": plain,
         "hash_sizing": sizing_info,

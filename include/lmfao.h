@@ -185,6 +185,13 @@ typedef struct {
   const float* estimator;/* HOST estimator blob (layout below), copied by
                             lmfao_plan; NULL = none                          */
   int64_t estimator_len; /* floats in `estimator`                            */
+  int32_t graph;         /* 1: the first lmfao_run without sync or timing is
+                            captured into a HIP graph (on a stream of the
+                            library's own) and later ones replay it on the
+                            caller's stream; a run with sync, or with timing
+                            on, launches directly, and a hash-table regrowth
+                            drops the graph.  Falls back to direct launches
+                            if capture fails.                               */
 } lmfao_options;
 
 /* Initial capacity of a hash table.  BOUND: twice the most groups the output

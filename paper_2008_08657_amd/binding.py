@@ -73,7 +73,8 @@ class lmfao_options(C.Structure):
                 ("n_order", C.POINTER(C.c_int32)), ("order", C.POINTER(C.POINTER(C.c_char_p))),
                 ("min_segment", C.c_int32), ("row_piece_max", C.c_int64),
                 ("contraction", C.c_int32), ("codegen", C.c_int32), ("hash_slots", C.c_int64),
-                ("sizing", C.c_int32), ("estimator", C.POINTER(C.c_float)), ("estimator_len", C.c_int64)]
+                ("sizing", C.c_int32), ("estimator", C.POINTER(C.c_float)), ("estimator_len", C.c_int64),
+                ("graph", C.c_int32)]
 
 
 class LmfaoError(RuntimeError):
@@ -194,7 +195,7 @@ class Plan:
 
     def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
                  min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0,
-                 sizing="bound", estimator=None):
+                 sizing="bound", estimator=None, graph=False):
         self.lib = load_library()
         self.problem = problem
         keep = _Keep()
@@ -215,6 +216,7 @@ class Plan:
         opts.contraction = 0 if contraction == "mfma" else 1
         opts.codegen = 0 if codegen else 1
         opts.hash_slots = int(hash_slots)
+        opts.graph = 1 if graph else 0
         if sizing not in ("bound", "learned"):
             raise ValueError(f"sizing must be 'bound' or 'learned', not {sizing!r}")
         opts.sizing = 0 if sizing == "bound" else 1

@@ -1852,6 +1852,90 @@ void launch_contract_fused(const DContract* c, const DGemm* g, bool f64, int bf1
   else launch_contract_fused_t<float, 0>(c, g, tn, gx, gy, lds, s);
 }
 
+// Row-by-row evaluation of a group whose outputs are all scattered (hash
+// tables, or keys with no scan form): one thread per row looks up the outer
+// views, forms the multiplicities, factors and codes, and adds every scatter
+// cell of the row into its output.  No staging, no barriers: the cost is the
+// row's loads and the table updates.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_rows(const DContract* __restrict__ C) {
+  const int NA = C->n_atoms, NC = C->n_codes, NM = C->n_masks, NV = C->n_views, n_sc = C->n_scatter;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < C->n_pieces;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    int64_t vrow[kMaxViews], vcnt[kMaxViews];
+    for (int v = 0; v < NV; ++v) {
+      const DView& V = C->views[v];
+      int64_t vr = 0;
+      for (int k = 0; k < V.nkey; ++k) vr += ld_int(C->pcols[V.key_src[k]], p) * V.key_stride[k];
+      vrow[v] = vr;
+      vcnt[v] = V.cnt[vr];
+    }
+    int64_t mu[kMaxMasks * 4];
+    for (int m = 0; m < NM; ++m) {
+      const uint32_t bits = C->masks[m];
+      int64_t x = 1;
+      for (int v = 0; v < NV; ++v)
+        if (bits & (1u << v)) x *= vcnt[v];
+      mu[m] = x;
+    }
+    double atom[kMaxOuterAtoms];
+    for (int a = 0; a < NA; ++a) {
+      const DAtom& At = C->atoms[a];
+      T x;
+      if (At.kind == SRC_COL) x = ld_val<T>(C->pcols[At.src], p);
+      else x = vcnt[At.src] ? view_val<T>(C->views[At.src], vrow[At.src], At.slot) : (T)0;
+      atom[a] = (double)x;
+    }
+    int32_t code[kMaxOuterCodes];
+    for (int c = 0; c < NC; ++c) {
+      const DAtom& Cd = C->codes[c];
+      int32_t x;
+      if (Cd.kind == SRC_COL) x = (int32_t)ld_int(C->pcols[Cd.src], p);
+      else {
+        const DView& V = C->views[Cd.src];
+        x = vcnt[Cd.src] ? V.codes[vrow[Cd.src] * V.n_codes + Cd.slot] : -1;
+      }
+      code[c] = x;
+    }
+    for (int sc = 0; sc < n_sc; ++sc) {
+      const int o = C->sc_out[sc];
+      int64_t row = 0;
+      bool ok = true;
+      for (int k = 0; k < 3; ++k) {
+        const int cidx = C->so_code[o * 3 + k];
+        if (cidx < 0) continue;
+        const int32_t cval = code[cidx];
+        if (cval < 0) ok = false;
+        row += (int64_t)cval * C->so_stride[o * 3 + k];
+      }
+      if (!ok) continue;
+      const int f = C->sc_f[sc], g = C->sc_g[sc];
+      const int comp = C->sc_comp[sc];
+      const DColB& B = C->cols[g];
+      if (comp < 0) {
+        int64_t v = feat_int(C->feats[f], mu, code);
+        int64_t cnt = C->w ? C->w[p] : 1;
+        if (B.kind == B_CNTF) {
+          const DFeat& F = B.feat;
+          if (F.c1 >= 0 && code[F.c1] != F.v1) cnt = 0;
+          if (F.c2 >= 0 && code[F.c2] != F.v2) cnt = 0;
+        }
+        v *= cnt;
+        if (v) scatter_count(C, o, row, v);
+      } else {
+        const double a = feat_d(C->feats[f], mu, code, atom, f < C->n_feat_int);
+        const double b = col_d<T>(C, B, p, code, atom);
+        const double v = a * b;
+        if (v != 0.0) scatter_value(C, o, row, comp, v);
+      }
+    }
+  }
+}
+void launch_scatter_rows(const DContract* c, bool f64, int grid, hipStream_t s) {
+  if (f64) hipLaunchKernelGGL(k_scatter_rows<double>, dim3(grid), dim3(256), 0, s, c);
+  else hipLaunchKernelGGL(k_scatter_rows<float>, dim3(grid), dim3(256), 0, s, c);
+}
+
 // Block-major partial merge: block x takes 16 consecutive cells (one 128-byte
 // line per partial row) and 16 lanes' worth of partial blocks per cell; each
 // thread sums its blocks in order (compensated), then the 16 partial sums of a

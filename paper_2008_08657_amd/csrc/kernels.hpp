@@ -124,6 +124,8 @@ int contract_fused_chunk();
 // bf16_parts 2 or 3: float-only tiles of the FP32 form on the bf16 matrix
 // cores (operands split into 2 or 3 bf16 parts, 3 or 6 products, FP32 within
 // a chunk of pieces, FP64 across); 0: FP64 matrix cores
+// row pieces whose outputs are all scattered: one thread per row
+void launch_scatter_rows(const DContract* c, bool f64, int grid, hipStream_t s);
 void launch_contract_fused(const DContract* c, const DGemm* g, bool f64, int bf16_parts, int tn, int gx, int gy,
                            int lds, hipStream_t s);
 void launch_merge_bm(const DCell* cells, int64_t n_cells, const double* part, int n_blocks, int ng, int64_t ncell,

@@ -1232,10 +1232,36 @@ static double out_cells(const Plan& P, const OutRef& o) {
   return cells;
 }
 
+// factors a scan holds: the inner atoms, plus one copy of an atom for every
+// further mask under which a float entry needs the same triangle slot (the
+// runtime builds the scan descriptor the same way)
+static int scan_atoms(const GroupProgram& g) {
+  int n = (int)g.in_atoms.size();
+  std::map<std::pair<int, int>, uint32_t> taken;
+  for (const PsiEntryF& e : g.psi_f) {
+    int ai = e.ai, aj = e.aj;
+    auto it = taken.find({ai, aj});
+    if (it != taken.end() && it->second != e.imask) {
+      const int dup = n++;
+      if (aj >= 0) aj = dup; else ai = dup;
+      if (ai > aj) std::swap(ai, aj);
+    }
+    taken[{ai, aj}] = e.imask;
+  }
+  return n;
+}
+
 // what the kernels of one group can hold
 static bool program_fits(const GroupProgram& g) {
-  int tables = 0;
-  for (const ProgOutput& po : g.outs) tables += po.mode == 2;
+  int tables = 0, inner_views = 0;
+  bool table_ok = true;
+  for (const ProgOutput& po : g.outs) {
+    tables += po.mode == 2;
+    if (po.mode == 2)
+      table_ok = table_ok && po.key_codes.size() <= 3 && po.tcomps.size() <= (size_t)kMaxTableComps;
+  }
+  for (int o : g.view_outer) inner_views += o == 0;
+  if (!g.row_pieces && (scan_atoms(g) > kMaxAtoms || inner_views > kMaxInnerViews || !table_ok)) return false;
   // a scan block holds every histogram once per wavefront (FP64 bins at most),
   // the per-wave factor staging and the LDS-privatized tables
   const int64_t wave = (int64_t)g.hist_i_bins * 4 + (int64_t)g.hist_f_bins * 8 + 16 + (kMaxAtoms + 5) * 64 * 8;

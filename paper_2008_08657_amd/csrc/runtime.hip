@@ -83,7 +83,8 @@ struct Step {
   int gen_block = 0;
   void* dev2 = nullptr;             // second descriptor (fused contraction: the product's)
   int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract (VALU), 5 merge, 6 image build,
-              // 7 (unused), 8 MFMA contraction, 9 block-major merge, 10 filter, 11 finalize
+              // 7 (unused), 8 MFMA contraction, 9 block-major merge, 10 filter, 11 finalize,
+              // 12 row-by-row scatter
   int fast = 0;
   void* dev = nullptr;
   int64_t n = 0;
@@ -130,7 +131,12 @@ struct lmfao_prepared_s {
   int timed_runs = 0;               // runs recorded since the last lmfao_run_timing
   std::vector<float> step_ms;
   hipStream_t stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;                // captured run (graph option)
+  hipStream_t capture_stream = nullptr;
+  bool graph_failed = false;
   ~lmfao_prepared_s() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
     for (auto& e : ev) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     for (auto& H : hashes)
@@ -386,6 +392,22 @@ static void build_contract_mfma(Prep& S, const GroupProgram& g, const std::strin
   c.part_f = nullptr;
   c.part_i = nullptr;
   c.pieces_per_block = 0;
+  if (c.row_pieces && g.gemm_cells.empty()) {
+    // every output is scattered: the row-by-row kernel, no matrix product
+    Step sr;
+    sr.name = gname + ":scatter";
+    sr.kind = 12;
+    sr.dev = upload(S, c, st);
+    sr.grid = (int)std::max<int64_t>(1, std::min<int64_t>((n_pieces + 255) / 256, 16384));
+    sr.pieces = n_pieces;
+    sr.rows = n_pieces;
+    for (int i = 0; i < c.n_pcols; ++i) sr.alg_read += (double)n_pieces * (c.pcols[i].dtype == LMFAO_F64 ? 8 : 4);
+    for (int v = 0; v < c.n_views; ++v)
+      sr.alg_read += (double)std::min<int64_t>(c.views[v].n_keys, n_pieces) *
+                     (8 + c.views[v].n_vals * (c.views[v].vals_f64 ? 8 : 4) + c.views[v].n_codes * 4);
+    S.steps.push_back(sr);
+    return;
+  }
   const int tn = gemm_tile_cols(std::max(1, NG));
   const int gy = gemm_macro_tiles(std::max(1, NF), std::max(1, NG));
   const int64_t kc = contract_fused_chunk();
@@ -1590,7 +1612,7 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
 
 // timed steps: scans and contractions (the kernels that move the data); the
 // whole run is timed as well.  Slot 0 of a run = whole run.
-static bool timed_step(const Step& s) { return s.kind == 2 || s.kind == 4 || s.kind == 8; }
+static bool timed_step(const Step& s) { return s.kind == 2 || s.kind == 4 || s.kind == 8 || s.kind == 12; }
 static int timed_slots(const Prep& S) {
   int n = 1;
   for (auto& s : S.steps) n += timed_step(s);
@@ -1633,6 +1655,9 @@ static void enqueue_run(Prep& S, hipStream_t st) {
       case 4: launch_contract((const DContract*)s.dev, S.f64, s.grid, s.grid_y, s.lds, st); break;
       case 5:
         launch_merge_cells((const DCell*)s.dev, s.n, s.part_f, s.part_i, s.n_blocks, s.NF, s.NG, s.NFI, s.NGI, st);
+        break;
+      case 12:
+        launch_scatter_rows((const DContract*)s.dev, S.f64, s.grid, st);
         break;
       case 8:
         launch_contract_fused((const DContract*)s.dev, (const DGemm*)s.dev2, S.f64,
@@ -1791,12 +1816,55 @@ static bool grow_hashes(Prep& S, hipStream_t st) {
   return grown;
 }
 
+// Replays the run as a HIP graph, capturing it first (on the library's own
+// stream: the caller's may be the legacy default stream, which cannot be
+// captured).  Returns false when capture is not possible; the caller then
+// launches directly.
+static bool run_graph(Prep& S, hipStream_t st) {
+  if (S.graph_failed) return false;
+  if (!S.graph_exec) {
+    if (!S.capture_stream && hipStreamCreateWithFlags(&S.capture_stream, hipStreamNonBlocking) != hipSuccess) {
+      S.graph_failed = true;
+      return false;
+    }
+    if (hipStreamBeginCapture(S.capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      S.graph_failed = true;
+      (void)hipGetLastError();
+      return false;
+    }
+    bool ok = true;
+    try {
+      enqueue_run(S, S.capture_stream);
+    } catch (const HipError&) {
+      ok = false;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(S.capture_stream, &g);
+    if (ok && e == hipSuccess && g) ok = hipGraphInstantiate(&S.graph_exec, g, nullptr, nullptr, 0) == hipSuccess;
+    else ok = false;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+      S.graph_exec = nullptr;
+      S.graph_failed = true;
+      (void)hipGetLastError();
+      return false;
+    }
+  }
+  HIP_OK(hipGraphLaunch(S.graph_exec, st));
+  return true;
+}
+
+static void drop_graph(Prep& S) {
+  if (S.graph_exec) (void)hipGraphExecDestroy(S.graph_exec);
+  S.graph_exec = nullptr;
+}
+
 lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, int32_t sync) {
   g_last_error.clear();
   if (!plan || !prep || prep->P != plan->P) return set_err(LMFAO_EINVAL, "plan and prepared handle do not match");
   hipStream_t st = (hipStream_t)stream;
   try {
-    enqueue_run(*prep, st);
+    if (!(prep->P->opts.graph && !sync && !prep->timing && run_graph(*prep, st))) enqueue_run(*prep, st);
     if (sync) {
       HIP_OK(hipStreamSynchronize(st));
       int32_t flag = 0;
@@ -1805,6 +1873,7 @@ lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, i
       while (flag & 8) {
         if (!grow_hashes(*prep, st))
           return set_err(LMFAO_EOVERFLOW, "a hash table at its largest size still overflowed");
+        drop_graph(*prep);   // the captured launches point at the old tables
         prep->hash_regrowths++;
         enqueue_run(*prep, st);
         HIP_OK(hipStreamSynchronize(st));
@@ -2163,8 +2232,9 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     if (!first) j += ",";
     first = false;
     static const char* kinds[] = {"fill",  "view_build", "scan",     "table_reduce", "contract", "merge",
-                                  "image", "stage",      "contract", "merge",        "filter",   "finalize"};
-    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 12, "one name per step kind");
+                                  "image", "stage",      "contract", "merge",        "filter",   "finalize",
+                                  "scatter"};
+    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 13, "one name per step kind");
     char tmp[512];
     snprintf(tmp, sizeof(tmp),
              "{\"name\":\"%s\",\"kind\":\"%s\",\"rows\":%lld,\"pieces\":%lld,\"alg_read_bytes\":%.0f,"
@@ -2201,7 +2271,9 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
              (long long)H.cap, (long long)H.bound, H.est);
     j += tmp;
   }
-  j += "],\"hash_regrowths\":" + std::to_string(prep->hash_regrowths) + "}";
+  j += "],\"hash_regrowths\":" + std::to_string(prep->hash_regrowths);
+  j += ",\"graph\":{\"captured\":" + std::to_string(prep->graph_exec ? 1 : 0) +
+       ",\"failed\":" + std::to_string(prep->graph_failed ? 1 : 0) + "}}";
   if (need) *need = j.size() + 1;
   if (buf && cap) {
     size_t n = std::min(cap - 1, j.size());

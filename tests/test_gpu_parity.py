@@ -163,6 +163,35 @@ def test_bf16x3_needs_matrix_cores(eng):
         eng.Plan(p, precision="bf16x2", contraction="valu")
 
 
+@pytest.mark.parametrize("shape", ["retail", "chain"])
+def test_graph_replay(eng, shape):
+    # the run captured into a HIP graph and replayed several times, with eager
+    # runs and other device work between the replays; every replay is checked
+    import torch
+    if shape == "retail":
+        p = W.retail_snowflake(seed=5, n_inv=60_001, n_locn=30, n_dates=10, n_ksn=200, n_weather_dates=12)
+        kw = dict(row_piece_max=5_000, min_segment=16)
+    else:
+        p = W.rkmeans_chain(seed=6, n1=40_000, n2=4_000, n3=400, n_x=6, n_y=5, n_z=5, max_dom=1_000_000)
+        kw = {}
+    print(f"[case] graph replay {shape}", flush=True)
+    plan = eng.Plan(p, precision="f32", policy="fact", graph=True, **kw)
+    prep = eng.Prepared(plan, eng.device_columns(p))
+    ref = oracle.evaluate(p)
+    prep.run(sync=True)
+    compare_all(prep.results(), ref, F32_TOL, f"{shape} eager")
+    for i in range(3):
+        prep.run(sync=False)
+        torch.cuda.synchronize()
+        compare_all(prep.results(), ref, F32_TOL, f"{shape} replay {i}")
+        x = torch.arange(4096, device="cuda", dtype=torch.float32)
+        assert float((x * 2).sum().item()) == 4095 * 4096.0
+        prep.run(sync=True)
+        compare_all(prep.results(), ref, F32_TOL, f"{shape} eager {i}")
+    d = prep.describe()
+    assert d["graph"]["failed"] == 0 and d["graph"]["captured"] == 1
+
+
 def test_repeat_runs_identical_counts(eng):
     p = W.tiny_star(seed=2, n_fact=40_000)
     plan = eng.Plan(p, policy="fact", row_piece_max=-1, min_segment=1)
