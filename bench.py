@@ -62,6 +62,7 @@ def main():
     ap.add_argument("--sizing", default=None, choices=["bound", "learned"],
                     help="hash-table sizing (default: learned for chain, bound otherwise)")
     ap.add_argument("--no-graph", action="store_true", help="launch every run directly (no HIP graph replay)")
+    ap.add_argument("--one-hot-max", type=int, default=0, help="outputs keyed by outer codes only: largest key space expanded one-hot (0 = per group)")
     ap.add_argument("--plain-steps", type=int, default=0,
                     help="also time this many steps of the plain per-view form on the same input")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the fact table (testing only)")
@@ -125,7 +126,7 @@ def main():
     t_gen = time.perf_counter() - t_gen
 
     plan = E.Plan(problem, precision=precision, policy=problem["policy"], form=args.form, sizing=sizing,
-                  graph=not args.no_graph)
+                  graph=not args.no_graph, one_hot_max=args.one_hot_max)
     cols = E.device_columns(problem)
     torch.cuda.synchronize()
     t_prep = time.perf_counter()

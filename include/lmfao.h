@@ -192,6 +192,12 @@ typedef struct {
                             on, launches directly, and a hash-table regrowth
                             drops the graph.  Falls back to direct launches
                             if capture fails.                               */
+  int32_t one_hot_max;   /* outputs keyed only by outer codes: the largest key
+                            space expanded one-hot into the matrix-core
+                            contraction; larger ones are scattered per piece.
+                            0 = 64, or 16 in a group whose one-hot features
+                            would exceed 256.  Outputs that also have inner
+                            keys expand outer key spaces up to 64          */
 } lmfao_options;
 
 /* Initial capacity of a hash table.  BOUND: twice the most groups the output

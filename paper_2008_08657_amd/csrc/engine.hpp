@@ -33,6 +33,9 @@ constexpr int kMaxHists = 64;      // per-piece histograms in a scan
 constexpr int kMaxTables = 8;      // direct group-by tables written by a scan
 constexpr int kMaxTableComps = 8;
 constexpr int kOneHotMax = 64;     // largest code domain expanded one-hot
+constexpr int kOneHotPure = 16;    // ... for outputs keyed by outer codes only, once a
+                                   // group's one-hot features exceed the budget below
+constexpr int kOneHotFeatureBudget = 256;
 constexpr int kHistMax = 1024;     // largest code domain kept per piece
 constexpr int kScanWaves = 8;      // wavefronts per scan block (each holds its own histograms)
 constexpr int kLdsBytes = 160 * 1024;            // LDS of one compute unit
@@ -245,6 +248,7 @@ struct GroupDef {
   std::set<int> deps;             // groups this one depends on
   bool has_program = false;
   bool force_rows = false;        // evaluated row by row (an output has no scan form)
+  int one_hot_pure = 0;           // one-hot limit of outer-only outputs (0 = kOneHotMax)
   GroupProgram prog;
 };
 

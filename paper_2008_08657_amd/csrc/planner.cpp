@@ -1053,10 +1053,16 @@ void ProgBuilder::build() {
     int64_t outer_prod = 1;
     for (int i : outer_codes) outer_prod *= dom[i];
     bool outer_small = outer_prod <= kOneHotMax;
+    // an output keyed only by outer codes can take either form: one-hot
+    // features of the matrix product (cheap for small domains) or a scatter
+    // of each piece's cells (cheap once the one-hot features outnumber them)
+    const int64_t pure_one_hot = P.opts.one_hot_max > 0 ? P.opts.one_hot_max
+                                 : G.one_hot_pure > 0  ? G.one_hot_pure
+                                                       : kOneHotMax;
     bool counts_only = monos.empty();
     bool pure_inner = outer_codes.empty() && !any_outer_atom;
     if (inner_codes.empty()) {
-      po.mode = outer_small ? 0 : 1;
+      po.mode = outer_prod <= pure_one_hot ? 0 : 1;
     } else if (pure_inner && (counts_only || inner_codes.size() > 1 || dom[inner_codes[0]] > kHistMax)) {
       po.mode = 2;   // direct table: no outer factor to multiply later
     } else if (inner_codes.size() == 1 && dom[inner_codes[0]] <= kHistMax && outer_small) {
@@ -1278,6 +1284,7 @@ static void split_group(Plan& P, int gi, size_t from) {
   H.node = P.groups[gi].node;
   H.level = P.groups[gi].level;
   H.force_rows = P.groups[gi].force_rows;
+  H.one_hot_pure = P.groups[gi].one_hot_pure;
   H.outs.assign(P.groups[gi].outs.begin() + from, P.groups[gi].outs.end());
   P.groups[gi].outs.resize(from);
   const int hi = (int)P.groups.size();
@@ -1320,6 +1327,13 @@ static void build_programs(Plan& P) {
       try {
         ProgBuilder b(P, G);
         b.build();
+        // many one-hot features (each a row of the matrix product) cost more
+        // than scattering the outer-only outputs' cells per piece
+        if (G.has_program && P.opts.one_hot_max == 0 && G.one_hot_pure == 0 &&
+            G.prog.feats.size() > (size_t)kOneHotFeatureBudget) {
+          G.one_hot_pure = kOneHotPure;
+          continue;
+        }
         if (!G.has_program || program_fits(G.prog)) break;
         why = "a group exceeds the limits of one scan kernel";
       } catch (const PlanError& e) {
