@@ -62,7 +62,8 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   }
   const char* T = f64 ? "double" : "float";
   const int s = f64 ? 2 : 1;                       // dwords per factor slot in an image
-  const int code_off = NA * s, cnt_off = code_off + 4;
+  const int NCS = d.n_codes > 4 ? d.n_codes : 4;   // code slots of an image record and code registers
+  const int code_off = NA * s, cnt_off = code_off + NCS;
   const int W = ((cnt_off + 1) + 3) & ~3;
   const int tsz = f64 ? 8 : 4;
   std::vector<uint64_t> args;
@@ -142,7 +143,7 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
       fcol_arg[a] = arg((uint64_t)F.fcol[a]);
       e << "  const T* __restrict__ fc" << a << " = (const T*)A[" << fcol_arg[a] << "];\n";
     }
-  for (int c = 0; c < 4; ++c)
+  for (int c = 0; c < NCS; ++c)
     if (F.ccol[c]) e << "  const int* __restrict__ cc" << c << " = (const int*)A[" << arg((uint64_t)F.ccol[c]) << "];\n";
   for (int v = 0; v < 2; ++v) {
     if (!F.img[v]) continue;
@@ -172,10 +173,16 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   // LDS: count tables (block), then a histogram area per wavefront.  Each
   // histogram is kept in kRep copies, lane & (kRep-1) choosing the copy, so
   // that lanes adding to the same bin mostly meet in different copies; the
-  // copies are summed when the piece closes.
-  constexpr int kRep = 4;
+  // copies are summed when the piece closes.  Four copies while the block
+  // fits in 64 KB, fewer for large histograms.
   const int hib = d.hist_i_bins, hfb = d.hist_f_bins;
   const int tab_bytes = (d.lds_tab_i * 4 + 15) & ~15;
+  auto lds_for = [&](int rep) {
+    const int hb = ((rep * hib * 4 + 7) & ~7) + rep * hfb * tsz;
+    return tab_bytes + kGenWaves * ((hb + 15) & ~15);
+  };
+  int kRep = 4;
+  while (kRep > 1 && lds_for(kRep) > 65536) kRep /= 2;
   const int hist_i_bytes = (kRep * hib * 4 + 7) & ~7;
   const int hist_bytes = hist_i_bytes + kRep * hfb * tsz;
   const int wave_stride = (hist_bytes + 15) & ~15;
@@ -196,7 +203,7 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   auto emit_load = [&](const char* pre, const char* row) {
     for (int a = 0; a < NA; ++a)
       if (F.fcol[a]) e << "      " << pre << "f" << a << " = fc" << a << "[" << row << "];\n";
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < NCS; ++c)
       if (F.ccol[c]) e << "      " << pre << "c" << c << " = cc" << c << "[" << row << "];\n";
     for (int v = 0; v < 2; ++v) {
       if (!F.img[v]) continue;
@@ -209,7 +216,7 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   auto emit_decl = [&](const char* pre) {
     for (int a = 0; a < NA; ++a)
       if (F.fcol[a]) e << "      T " << pre << "f" << a << ";\n";
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < NCS; ++c)
       if (F.ccol[c]) e << "      int " << pre << "c" << c << ";\n";
     for (int v = 0; v < 2; ++v)
       if (F.img[v]) e << "      int " << pre << "k" << v << ";\n";
@@ -260,7 +267,7 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   // current row values = prefetched ones
   for (int a = 0; a < NA; ++a)
     if (F.fcol[a]) e << "        const T cf" << a << " = nf" << a << ";\n";
-  for (int c = 0; c < 4; ++c)
+  for (int c = 0; c < NCS; ++c)
     if (F.ccol[c]) e << "        const int cc_" << c << " = nc" << c << ";\n";
   for (int v = 0; v < 2; ++v)
     if (F.img[v]) e << "        const int ck" << v << " = nk" << v << ";\n";
@@ -271,7 +278,8 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   // factor values: a0 = 1, column part + image parts
   e << "        const T a0 = (T)1;\n";
   for (int a = 0; a < NA; ++a) e << "        T a" << a + 1 << " = " << (F.fcol[a] ? "cf" + std::to_string(a) : "(T)0") << ";\n";
-  for (int c = 0; c < 4; ++c) e << "        int c" << c << " = " << (F.ccol[c] ? "cc_" + std::to_string(c) : "0") << ";\n";
+  for (int c = 0; c < NCS; ++c)
+    e << "        int c" << c << " = " << (F.ccol[c] ? "cc_" + std::to_string(c) : "0") << ";\n";
   e << "        const int wv = valid ? " << (d.w ? "cw" : "1") << " : 0;\n";
   for (int m = 0; m < 4; ++m) e << "        int " << mu(m) << " = wv;\n";
   for (int v = 0; v < 2; ++v) {
@@ -289,7 +297,7 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
       else
         e << "          a" << a + 1 << " += __uint_as_float(" << dw(a) << ");\n";
     }
-    for (int c = 0; c < 4; ++c) e << "          c" << c << " += (int)" << dw(code_off + c) << ";\n";
+    for (int c = 0; c < NCS; ++c) e << "          c" << c << " += (int)" << dw(code_off + c) << ";\n";
     e << "          const int vc = valid ? (int)" << dw(cnt_off) << " : 0;\n";
     for (int m = 0; m < n_masks; ++m)
       if (d.masks[m] & (1u << v)) e << "          " << mu(m) << " *= vc;\n";
@@ -309,7 +317,7 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   // histograms
   for (int h = 0; h < F.n_hist; ++h) {
     const uint32_t w = F.hword[h];
-    const int code = (int)(w & 3u), m = (int)((w >> 2) & 3u), off = (int)(w >> 13);
+    const int code = F.hcode[h], m = (int)((w >> 2) & 3u), off = (int)(w >> 13);
     if ((w >> 4) & 1u) {
       const int ai = (int)((w >> 5) & 15u), aj = (int)((w >> 9) & 15u);
       e << "        if (" << mu(m) << ") atomicAdd(&hist_f[rep_f + " << off << " + c" << code << "], (T)" << mu(m)

@@ -377,24 +377,26 @@ struct DImageBuild {
 
 constexpr int kFastHists = 32;
 constexpr int kFastTables = 4;
+constexpr int kGenTables = 8;     // direct tables of a generated scan
 
 // hoisted form of a lean scan (all loop-invariant, read once per kernel)
 struct DFast {
   const void* fcol[kMaxAtoms];     // factor columns in the compute type (null: factor from an image)
-  const int32_t* ccol[4];          // code columns (null: code from an image)
+  const int32_t* ccol[kMaxCodes];  // code columns (null: code from an image)
   const void* img[2];              // inner view images (null: no view)
   const int32_t* kcol[2][2];       // key columns of each image (second: null for one-attribute keys)
   int32_t kmul[2][2];              // dense key = sum of key column * kmul
   int32_t n_hist;
   uint32_t hword[kFastHists];      // code(2) | mask(2) | float(1) | ai+1(4) | aj+1(4) | offset(16)
+  int8_t hcode[kFastHists];        // full code index (the generated scans allow 16 codes)
   int32_t n_tab;
-  int32_t tab_ncode[kFastTables];
-  int32_t tab_code[kFastTables][3];
-  int32_t tab_stride[kFastTables][3];
-  int32_t tab_mask[kFastTables];   // count weight mask
-  int32_t tab_lds[kFastTables];    // 1: LDS offset valid, else global counts
-  int32_t tab_off[kFastTables];
-  int64_t* tab_cnt[kFastTables];
+  int32_t tab_ncode[kGenTables];
+  int32_t tab_code[kGenTables][3];
+  int32_t tab_stride[kGenTables][3];
+  int32_t tab_mask[kGenTables];    // count weight mask
+  int32_t tab_lds[kGenTables];     // 1: LDS offset valid, else global counts
+  int32_t tab_off[kGenTables];
+  int64_t* tab_cnt[kGenTables];
 };
 
 struct DScan {

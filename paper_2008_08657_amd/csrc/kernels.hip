@@ -949,9 +949,11 @@ struct ImgShape {
   static constexpr int width = ((cnt_off + 1) + 3) & ~3;
 };
 
-int image_width_dw(int na, bool f64) {
+// image record: factor slots, code slots (4, or one per code past 4), count
+int image_code_slots(int n_codes) { return n_codes > 4 ? n_codes : 4; }
+int image_width_dw(int na, bool f64, int n_codes) {
   int code_off = na * (f64 ? 2 : 1);
-  return ((code_off + 5) + 3) & ~3;
+  return ((code_off + image_code_slots(n_codes) + 1) + 3) & ~3;
 }
 int image_code_off(int na, bool f64) { return na * (f64 ? 2 : 1); }
 
@@ -2047,6 +2049,18 @@ __global__ void k_table_reduce(const DTableReduce* __restrict__ R) {
     for (int k = 0; k < R->n_copy; ++k) atomic_add_f64(&R->copy_vals[i * R->copy_nv + R->copy_comp[k]], (double)s);
   }
 }
+__global__ void k_count_copy(const DCountCopy* __restrict__ C) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < C->n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = C->cnt[i];
+    if (c == 0) continue;
+    for (int k = 0; k < C->n_copy; ++k) C->vals[i * C->nv + C->comp[k]] += (double)c;
+  }
+}
+void launch_count_copy(const DCountCopy* d, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_count_copy, dim3((int)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s, d);
+}
+
 void launch_table_reduce(const DTableReduce* d, int64_t n, int n_blocks, hipStream_t s) {
   if (n <= 0) return;
   const int gy = std::max(1, (n_blocks + kReduceSlice - 1) / kReduceSlice);

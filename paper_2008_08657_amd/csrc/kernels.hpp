@@ -57,6 +57,15 @@ struct DKeyCols {
   int32_t* err_flag;
 };
 
+// SUM(1) components of a table kept in global memory, copied from its counts
+struct DCountCopy {
+  const int64_t* cnt;
+  double* vals;
+  int64_t n;
+  int32_t nv, n_copy;
+  int32_t comp[kMaxTableComps];
+};
+
 struct DTableReduce {
   int64_t n;            // elements of this count table
   int32_t n_blocks;
@@ -106,7 +115,8 @@ void launch_distinct(const int32_t* col, int64_t n, int64_t dom, uint32_t* bits,
 int scan_lds_bytes(const DScan& S, bool f64);
 int scan_fast_lds_bytes(const DScan& S, bool f64);
 void launch_scan_fast(const DScan* d, int na, bool f64, int grid, int lds, hipStream_t s);
-int image_width_dw(int na, bool f64);
+int image_code_slots(int n_codes);
+int image_width_dw(int na, bool f64, int n_codes);
 int image_code_off(int na, bool f64);
 void launch_build_image(const DImageBuild* d, int64_t n_keys, bool f64, hipStream_t s);
 void launch_scan(const DScan* d, int na, bool f64, int grid, int lds, hipStream_t s);
@@ -134,5 +144,6 @@ void launch_merge_bm(const DCell* cells, int64_t n_cells, const double* part, in
 void launch_merge_cells(const DCell* cells, int64_t n_cells, const double* part_f, const int64_t* part_i,
                         int n_blocks, int NF, int NG, int NFI, int NGI, hipStream_t s);
 void launch_table_reduce(const DTableReduce* d, int64_t n, int n_blocks, hipStream_t s);
+void launch_count_copy(const DCountCopy* d, int64_t n, hipStream_t s);
 
 }  // namespace lmfao

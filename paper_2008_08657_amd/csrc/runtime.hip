@@ -84,7 +84,7 @@ struct Step {
   void* dev2 = nullptr;             // second descriptor (fused contraction: the product's)
   int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract (VALU), 5 merge, 6 image build,
               // 7 (unused), 8 MFMA contraction, 9 block-major merge, 10 filter, 11 finalize,
-              // 12 row-by-row scatter
+              // 12 row-by-row scatter, 13 count copy
   int fast = 0;
   void* dev = nullptr;
   int64_t n = 0;
@@ -767,6 +767,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     bool tab_omask_set = false;
     std::vector<std::pair<int, int>> lds_tables;   // (output index, lds offset)
     std::map<int, std::vector<int>> table_copies;    // output index -> SUM(1) components copied from the count
+    std::vector<DCountCopy> count_copies;             // the same for tables kept in global memory
     for (size_t oi = 0; oi < g.outs.size(); ++oi) {
       const ProgOutput& po = g.outs[oi];
       if (po.mode != 2) continue;
@@ -790,7 +791,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
       std::vector<int> copies;
       T.n_tcomps = 0;
       for (const TableComp& tc : po.tcomps) {
-        if (in_lds && tc.comp >= 0 && tc.ai < 0 && tc.aj < 0 && tc.imask == count_mask && O.f64) {
+        if (tc.comp >= 0 && tc.ai < 0 && tc.aj < 0 && tc.imask == count_mask && O.f64) {
           copies.push_back(tc.comp);
           continue;
         }
@@ -810,6 +811,16 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
         T.lds_off = lds_used;
         lds_tables.push_back({(int)oi, lds_used});
         lds_used += (int)po.n_rows;
+      } else if (!copies.empty()) {
+        // a global table's SUM(1) components: copied from its counts after the scan
+        DCountCopy cc{};
+        cc.cnt = O.cnt;
+        cc.vals = (double*)O.vals;
+        cc.n = po.n_rows;
+        cc.nv = O.n_vals;
+        cc.n_copy = (int)copies.size();
+        for (size_t k = 0; k < copies.size(); ++k) cc.comp[k] = copies[k];
+        count_copies.push_back(cc);
       }
       if (po.omask) {
         if (tab_omask_set && tab_omask != po.omask)
@@ -863,32 +874,40 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     grid = std::max(grid, 1);
     d.part_i = (int32_t*)dalloc(S, (size_t)grid * std::max(1, lds_used) * 4);
     d.err_flag = S.err_flag;
-    // lean kernel: inner views through per-key images (single-attribute keys),
-    // at most 2 inner views, 4 codes, 16 histograms, 2 count-only direct tables
-    bool fast = n_in <= 2 && d.n_codes <= 4 && d.n_masks <= 4 && d.n_pi <= 4 && R.n_rows < ((int64_t)1 << 31) &&
-                d.n_hists <= kFastHists && d.n_tables <= kFastTables && d.pf_uniform;
+    // lean scans: inner views through per-key images (keys of at most two
+    // attributes), at most 2 inner views, one multiplicity mask for all float
+    // entries, count-only direct tables.  The built-in lean kernel takes 4
+    // codes and 4 tables; a generated one takes 16 codes and 8 tables.
+    bool lean = n_in <= 2 && d.n_codes <= kMaxCodes && d.n_masks <= 4 && d.n_pi <= 4 &&
+                R.n_rows < ((int64_t)1 << 31) && d.n_hists <= kFastHists && d.n_tables <= kGenTables &&
+                d.pf_uniform;
     d.n_atoms = NA;
     for (int v = 0; v < n_in; ++v)
-      fast = fast && d.views[v].n_keys < ((int64_t)1 << 31) && d.views[v].nkey <= 2;
-    for (int i = 0; i < d.n_hists; ++i) fast = fast && d.hists[i].offset + d.hists[i].dom < (1 << 19);
+      lean = lean && d.views[v].n_keys < ((int64_t)1 << 31) && d.views[v].nkey <= 2;
+    for (int i = 0; i < d.n_hists; ++i) lean = lean && d.hists[i].offset + d.hists[i].dom < (1 << 19);
     for (int t = 0; t < d.n_tables; ++t) {
-      fast = fast && d.tables[t].n_tcomps == 1 && d.tables[t].tcomp[0] < 0 && d.tables[t].ncode <= 3 &&
+      lean = lean && d.tables[t].n_tcomps == 1 && d.tables[t].tcomp[0] < 0 && d.tables[t].ncode <= 3 &&
              d.tables[t].n_rows < ((int64_t)1 << 31);
     }
+    const bool builtin = lean && d.n_codes <= 4 && d.n_tables <= kFastTables;
+    const bool fast = builtin || (lean && S.P->opts.codegen == 0);
     d.fast = fast ? 1 : 0;
     if (fast) {
       DFast& F = d.F;
       for (int a = 0; a < NA; ++a)
         F.fcol[a] = atoms[a].kind == SRC_COL ? typed_sorted_column(S, r, scols[atoms[a].src], st) : nullptr;
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < kMaxCodes; ++c)
         F.ccol[c] = (c < d.n_codes && g.in_codes[c].kind == SRC_COL)
                         ? (const int32_t*)N.sorted_col[scols[g.in_codes[c].src]] : (const int32_t*)nullptr;
       F.n_hist = d.n_hists;
       for (int i = 0; i < d.n_hists; ++i) {
         const DHist& H = d.hists[i];
+        F.hcode[i] = (int8_t)H.code;
         const DWeight& Wt = weights[H.wi];
         // factor slots: 0 is the constant 1, so an absent factor multiplies by 1
-        uint32_t w = (uint32_t)H.code | ((uint32_t)Wt.mask_idx << 2) | ((uint32_t)(H.is_float ? 1 : 0) << 4);
+        // the packed code field holds the built-in kernel's 4 codes; the full
+        // index (generated kernels take 16 codes) is in hcode
+        uint32_t w = ((uint32_t)H.code & 3u) | ((uint32_t)Wt.mask_idx << 2) | ((uint32_t)(H.is_float ? 1 : 0) << 4);
         if (H.is_float) w |= ((uint32_t)(Wt.ai + 1) << 5) | ((uint32_t)(Wt.aj + 1) << 9);
         w |= (uint32_t)H.offset << 13;
         F.hword[i] = w;
@@ -906,8 +925,9 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
         F.tab_off[t] = TB.lds_off;
         F.tab_cnt[t] = TB.cnt;
       }
-      const int W = image_width_dw(NA, f64);
+      const int W = image_width_dw(NA, f64, d.n_codes);
       const int code_off = image_code_off(NA, f64);
+      const int code_slots = image_code_slots(d.n_codes);
       for (size_t k = 0; k < g.views.size(); ++k) {
         int v = scan_view[k];
         if (v < 0) continue;
@@ -917,7 +937,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
         ib.n_keys = V.n_keys;
         ib.width_dw = W;
         ib.code_off = code_off;
-        ib.cnt_off = code_off + 4;
+        ib.cnt_off = code_off + code_slots;
         ib.t_f64 = f64 ? 1 : 0;
         ib.n_atoms = NA;
         for (int a = 0; a < NA; ++a)
@@ -929,7 +949,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
         d.imgs[v].img = ib.img;
         d.imgs[v].width_dw = W;
         d.imgs[v].code_off = code_off;
-        d.imgs[v].cnt_off = code_off + 4;
+        d.imgs[v].cnt_off = code_off + code_slots;
         d.imgs[v].key_col = V.nkey == 1 ? V.key_src[0] : -1;
         F.img[v] = ib.img;
         for (int k = 0; k < 2; ++k) {
@@ -946,12 +966,12 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
         S.steps.push_back(b);
       }
     }
-    int lds = fast ? scan_fast_lds_bytes(d, f64) : scan_lds_bytes(d, f64);
+    int lds = builtin ? scan_fast_lds_bytes(d, f64) : scan_lds_bytes(d, f64);
     if (lds > 160 * 1024) throw PlanError{LMFAO_EUNSUPPORTED, "scan needs more LDS than a CU has"};
     Step s;
     s.name = gname + ":scan";
     s.kind = 2;
-    s.fast = fast ? 1 : 0;
+    s.fast = builtin ? 1 : 0;
     s.dev = upload(S, d, st);
     if (fast && S.P->opts.codegen == 0) {
       GenKernel gk;
@@ -1004,6 +1024,14 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
       t.dev = upload(S, tr, st);
       t.n = po.n_rows;
       t.n_blocks = grid;
+      S.steps.push_back(t);
+    }
+    for (const DCountCopy& cc : count_copies) {
+      Step t;
+      t.name = gname + ":count_copy";
+      t.kind = 13;
+      t.dev = upload(S, cc, st);
+      t.n = cc.n;
       S.steps.push_back(t);
     }
   }
@@ -1659,6 +1687,7 @@ static void enqueue_run(Prep& S, hipStream_t st) {
       case 12:
         launch_scatter_rows((const DContract*)s.dev, S.f64, s.grid, st);
         break;
+      case 13: launch_count_copy((const DCountCopy*)s.dev, s.n, st); break;
       case 8:
         launch_contract_fused((const DContract*)s.dev, (const DGemm*)s.dev2, S.f64,
                               S.P->opts.precision == LMFAO_PREC_BF16X3   ? 3
@@ -2233,8 +2262,8 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     first = false;
     static const char* kinds[] = {"fill",  "view_build", "scan",     "table_reduce", "contract", "merge",
                                   "image", "stage",      "contract", "merge",        "filter",   "finalize",
-                                  "scatter"};
-    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 13, "one name per step kind");
+                                  "scatter", "count_copy"};
+    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 14, "one name per step kind");
     char tmp[512];
     snprintf(tmp, sizeof(tmp),
              "{\"name\":\"%s\",\"kind\":\"%s\",\"rows\":%lld,\"pieces\":%lld,\"alg_read_bytes\":%.0f,"
