@@ -192,6 +192,31 @@ def test_graph_replay(eng, shape):
     assert d["graph"]["failed"] == 0 and d["graph"]["captured"] == 1
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_direct_tables_with_values(eng, precision):
+    # per-key sums grouped by a key too large for a per-piece histogram
+    # (item, 3,000 values) are direct tables with value components (SUM(1),
+    # SUM(units), SUM(units^2), SUM(units*g1)) written by the scan
+    p = W.tiny_star(seed=7, n_fact=120_001, n_stores=40, n_items=3_000)
+    p["batch"] = [{"groupby": ["item"], "where": [], "root": None,
+                   "aggs": [[], [("units", 1)], [("units", 2)], [("units", 1), ("g1", 1)]]},
+                  {"groupby": ["store"], "where": [], "root": None, "aggs": [[], [("units", 1)]]},
+                  {"groupby": ["cat"], "where": [], "root": None, "aggs": [[("units", 1)], [("f1", 1)]]}]
+    if precision == "f32":
+        for r in p["schema"]:
+            for a in r["attrs"]:
+                if a["dtype"] == "f64":
+                    a["dtype"] = "f32"
+                    p["data"][r["name"]][a["name"]] = p["data"][r["name"]][a["name"]].astype(np.float32)
+    # store outer, item inner: the item group-by is a table written by the scan
+    plan, prep, res = run_engine(eng, p, precision=precision, policy="fact", row_piece_max=-1, min_segment=16,
+                                 order={"S": ["store", "item"]})
+    d = prep.describe()
+    scans = [(s["name"], s["lean"]) for s in d["steps"] if s["kind"] == "scan"]
+    print(f"[case] tables with values {precision}: scans {scans}", flush=True)
+    compare_all(res, oracle.evaluate(p), F64_TOL if precision == "f64" else F32_TOL, f"tables_{precision}")
+
+
 def test_repeat_runs_identical_counts(eng):
     p = W.tiny_star(seed=2, n_fact=40_000)
     plan = eng.Plan(p, policy="fact", row_piece_max=-1, min_segment=1)
