@@ -62,6 +62,7 @@ def main():
     ap.add_argument("--sizing", default=None, choices=["bound", "learned"],
                     help="hash-table sizing (default: learned for chain, bound otherwise)")
     ap.add_argument("--no-graph", action="store_true", help="launch every run directly (no HIP graph replay)")
+    ap.add_argument("--scan-blocks", type=int, default=0, help="most workgroups of a scan launch (0 = 2048 generated, 512 built-in)")
     ap.add_argument("--one-hot-max", type=int, default=0, help="outputs keyed by outer codes only: largest key space expanded one-hot (0 = per group)")
     ap.add_argument("--plain-steps", type=int, default=0,
                     help="also time this many steps of the plain per-view form on the same input")
@@ -126,7 +127,7 @@ def main():
     t_gen = time.perf_counter() - t_gen
 
     plan = E.Plan(problem, precision=precision, policy=problem["policy"], form=args.form, sizing=sizing,
-                  graph=not args.no_graph, one_hot_max=args.one_hot_max)
+                  graph=not args.no_graph, one_hot_max=args.one_hot_max, scan_blocks=args.scan_blocks)
     cols = E.device_columns(problem)
     torch.cuda.synchronize()
     t_prep = time.perf_counter()
@@ -193,8 +194,10 @@ def main():
     src = next((x.split("\n", 1)[1] for x in prep.kernel_sources() if x.split("\n", 1)[0] == group), None)
     digest = None
     if src is not None:
+        # the kernel's source and its launch grid: counters taken at another
+        # grid do not describe this launch
         from paper_2008_08657_amd.profiling import source_digest
-        digest = source_digest(src)
+        digest = source_digest(src + f"\n// grid {kd['grid']}")
     roofline["kernel_source_digest"] = digest
     prof_dir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
     if digest and os.path.isdir(prof_dir):

@@ -198,6 +198,10 @@ typedef struct {
                             0 = 64, or 16 in a group whose one-hot features
                             would exceed 256.  Outputs that also have inner
                             keys expand outer key spaces up to 64          */
+  int32_t scan_blocks;   /* most workgroups of one scan launch (0 = 2048 for
+                            generated scans, 512 for the built-in ones);
+                            each has 8 wavefronts and takes whole work
+                            items                                          */
 } lmfao_options;
 
 /* Initial capacity of a hash table.  BOUND: twice the most groups the output

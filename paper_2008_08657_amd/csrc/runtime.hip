@@ -869,10 +869,6 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     psi_i = (int32_t*)dalloc(S, (size_t)std::max<int64_t>(1, N.n_pieces) * std::max(1, psi_i_stride) * 4);
     d.psi_f = psi_f;
     d.psi_i = psi_i;
-    int waves = scan_waves_per_block();
-    int grid = (int)std::min<int64_t>((N.n_items + waves - 1) / waves, 512);
-    grid = std::max(grid, 1);
-    d.part_i = (int32_t*)dalloc(S, (size_t)grid * std::max(1, lds_used) * 4);
     d.err_flag = S.err_flag;
     // lean scans: inner views through per-key images (keys of at most two
     // attributes), at most 2 inner views, one multiplicity mask for all float
@@ -892,6 +888,14 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     const bool builtin = lean && d.n_codes <= 4 && d.n_tables <= kFastTables;
     const bool fast = builtin || (lean && S.P->opts.codegen == 0);
     d.fast = fast ? 1 : 0;
+    // generated scans gain from more resident wavefronts; the built-in ones
+    // (descriptor-driven, more registers) do best with fewer
+    const int waves = scan_waves_per_block();
+    const bool expect_gen = lean && S.P->opts.codegen == 0;
+    const int max_blocks = S.P->opts.scan_blocks > 0 ? S.P->opts.scan_blocks : (expect_gen ? 2048 : 512);
+    int grid = (int)std::min<int64_t>((N.n_items + waves - 1) / waves, max_blocks);
+    grid = std::max(grid, 1);
+    d.part_i = (int32_t*)dalloc(S, (size_t)grid * std::max(1, lds_used) * 4);
     if (fast) {
       DFast& F = d.F;
       for (int a = 0; a < NA; ++a)
@@ -990,7 +994,8 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     s.grid = grid;
     s.lds = lds;
     // bytes the scan must move: each scanned column once, the piece offsets,
-    // each inner view's rows once, the per-piece partial sums, table partials
+    // each inner view's rows once, the per-piece partial sums (the per-block
+    // table partials depend on the launch, not on the work, and are left out)
     s.rows = R.n_rows;
     s.pieces = N.n_pieces;
     for (int i = 0; i < d.n_cols; ++i) s.alg_read += (double)R.n_rows * (d.cols[i].dtype == LMFAO_F64 ? 8 : 4);
@@ -1000,7 +1005,6 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
                          : (double)d.views[v].n_keys * (8 + d.views[v].n_vals * (d.views[v].vals_f64 ? 8 : 4) +
                                                         d.views[v].n_codes * 4);
     s.alg_write += (double)N.n_pieces * (psi_f_stride * (f64 ? 8 : 4) + psi_i_stride * 4);
-    s.alg_write += (double)grid * lds_used * 4;
     s.alg_flop = (double)R.n_rows * 2 * (double)std::max(1, d.pf_n);
     S.steps.push_back(s);
     for (auto& lt : lds_tables) {

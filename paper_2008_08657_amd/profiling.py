@@ -6,8 +6,12 @@
 ``traffic``: HBM bytes per launch of one kernel from two counter runs
 (``FETCH_SIZE`` and ``WRITE_SIZE``, KiB per dispatch), each scaled by what the
 same counter reads for a plain device copy of known size.  The record names
-the kernel and a digest of its generated source; ``bench.py`` reports the
-bytes only while the kernel it measures has that same source.
+the kernel and a digest of its generated source and launch grid;
+``bench.py`` reports the bytes only while the kernel it measures has that
+same source and grid.
+
+``counters``: per-dispatch means of SQ counters of one kernel (instruction
+mix, waves, waits) as a Markdown table.
 """
 from __future__ import annotations
 
@@ -63,6 +67,25 @@ def traffic(a):
     print(json.dumps(rec))
 
 
+def counters(a):
+    sums, n = {}, {}
+    with open(a.csv, newline="") as f:
+        for row in csv.DictReader(f):
+            if row["Kernel_Name"] != a.kernel:
+                continue
+            k = row["Counter_Name"]
+            sums[k] = sums.get(k, 0.0) + float(row["Counter_Value"])
+            n[k] = n.get(k, 0) + 1
+    lines = [f"# {a.title}", "", "Command:", "", "```", *a.command, "```", "",
+             "| counter | mean per dispatch |", "|---|---:|"]
+    for k in sorted(sums):
+        lines.append(f"| {k} | {sums[k] / n[k]:.0f} |")
+    if a.note:
+        lines += ["", *a.note]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def summarize(a):
     rows = []
     with open(a.trace, newline="") as f:
@@ -96,8 +119,15 @@ def main(argv=None):
     s.add_argument("--top", type=int, default=25)
     s.add_argument("--command", action="append", default=[])
     s.add_argument("--note", action="append", default=[])
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", required=True)
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", action="append", default=[])
+    c.add_argument("--note", action="append", default=[])
     a = ap.parse_args(argv)
-    traffic(a) if a.cmd == "traffic" else summarize(a)
+    {"traffic": traffic, "summarize": summarize, "counters": counters}[a.cmd](a)
     return 0
 
 
