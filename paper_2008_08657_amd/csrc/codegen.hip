@@ -29,6 +29,7 @@ namespace lmfao {
 namespace {
 
 constexpr int kGenWaves = 8;   // wavefronts per workgroup
+constexpr int kMaxRep = 4;     // most copies of each per-piece histogram
 
 struct Emit {
   std::ostringstream o;
@@ -173,15 +174,15 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   // LDS: count tables (block), then a histogram area per wavefront.  Each
   // histogram is kept in kRep copies, lane & (kRep-1) choosing the copy, so
   // that lanes adding to the same bin mostly meet in different copies; the
-  // copies are summed when the piece closes.  Four copies while the block
-  // fits in 64 KB, fewer for large histograms.
+  // copies are summed when the piece closes.  Up to kMaxRep copies while the
+  // block fits in 64 KB, fewer for large histograms.
   const int hib = d.hist_i_bins, hfb = d.hist_f_bins;
   const int tab_bytes = (d.lds_tab_i * 4 + 15) & ~15;
   auto lds_for = [&](int rep) {
     const int hb = ((rep * hib * 4 + 7) & ~7) + rep * hfb * tsz;
     return tab_bytes + kGenWaves * ((hb + 15) & ~15);
   };
-  int kRep = 4;
+  int kRep = kMaxRep;
   while (kRep > 1 && lds_for(kRep) > 65536) kRep /= 2;
   const int hist_i_bytes = (kRep * hib * 4 + 7) & ~7;
   const int hist_bytes = hist_i_bytes + kRep * hfb * tsz;

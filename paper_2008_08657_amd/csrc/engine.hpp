@@ -192,6 +192,7 @@ struct ProgOutput {
   std::vector<TableComp> tcomps;      // table mode
   bool dst_is_view = false;           // writes vals as view table (f32/f64 by view)
   bool hashed = false;                // scatter mode into a hash table (key space > kDenseRowsMax)
+  std::vector<int> count_copies;      // scatter mode: SUM(1) components, equal to the count
 };
 
 struct PsiEntryF {

@@ -1083,6 +1083,17 @@ void ProgBuilder::build() {
       std::vector<int> oat, iat;
       for (auto& p : s.parts) (p.outer ? oat : iat).push_back(p.atom);
       if (oat.size() > 2 || iat.size() > 2) fail(LMFAO_EUNSUPPORTED, "component of degree > 2");
+      if (po.mode == 1 && o.kind == 0 && ci >= 0 && oat.empty() && iat.empty()) {
+        // a SUM(1) component of a query (FP64 results) under the count's
+        // masks scatters the same cells as the count: it is copied from the
+        // count instead
+        uint32_t om0, im0;
+        masks_for(Split{}, om0, im0);
+        if (om == om0 && im == im0) {
+          po.count_copies.push_back(ci);
+          continue;
+        }
+      }
       if (po.mode == 2) {   // table: inner codes only, inner atoms only
         TableComp tc;
         tc.comp = ci;

@@ -59,6 +59,7 @@ struct HashBuf {
   double* vals = nullptr;
   int n_vals = 0;
   int fill_step = -1;              // index of its zeroing steps (keys, cnt, vals)
+  std::vector<int> count_copies;   // value columns equal to the count (SUM(1))
 };
 
 struct NodeData {
@@ -1605,7 +1606,36 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
   std::iota(gorder.begin(), gorder.end(), 0);
   std::stable_sort(gorder.begin(), gorder.end(),
                    [&](int a, int b) { return P.groups[a].level < P.groups[b].level; });
-  for (int gi : gorder) build_group(S, gi, cols, st);
+  for (int gi : gorder) {
+    build_group(S, gi, cols, st);
+    // SUM(1) components of scattered outputs: copied from the counts once the
+    // group's steps are done (hash tables: when the results are read)
+    const GroupDef& G = P.groups[gi];
+    if (!G.has_program) continue;
+    for (const ProgOutput& po : G.prog.outs) {
+      if (po.count_copies.empty()) continue;
+      const OutBuf& O = po.ref.kind == 0 ? S.qout[po.ref.id] : S.vout[po.ref.id];
+      if (O.hash >= 0) {
+        S.hashes[O.hash].count_copies = po.count_copies;
+        continue;
+      }
+      if (!O.f64) throw PlanError{LMFAO_EINVAL, "internal: count copy into an FP32 output"};
+      DCountCopy cc{};
+      cc.cnt = O.cnt;
+      cc.vals = (double*)O.vals;
+      cc.n = O.n_rows;
+      cc.nv = O.n_vals;
+      cc.n_copy = (int)po.count_copies.size();
+      if (cc.n_copy > kMaxTableComps) throw PlanError{LMFAO_EUNSUPPORTED, "too many SUM(1) components"};
+      for (int k = 0; k < cc.n_copy; ++k) cc.comp[k] = po.count_copies[k];
+      Step t;
+      t.name = "g" + std::to_string(gi) + ":" + P.rels[G.node].name + ":count_copy";
+      t.kind = 13;
+      t.dev = upload(S, cc, st);
+      t.n = cc.n;
+      S.steps.push_back(t);
+    }
+  }
   // range queries: sums over the bucket ranges their conditions select
   std::vector<DFinalize> fin;
   for (size_t u = 0; u < P.user.size(); ++u) {
@@ -1953,6 +1983,7 @@ static lmfao_status gather_hash(const lmfao_prepared_s* prep, const OutBuf& B, G
     g.rows.push_back((int64_t)keys[i] - 1);
     g.cnt.push_back(cnt[i]);
     for (int k = 0; k < H.n_vals; ++k) g.vals.push_back(vals[(size_t)i * H.n_vals + k]);
+    for (int k : H.count_copies) g.vals[g.vals.size() - H.n_vals + k] += (double)cnt[i];
   }
   return LMFAO_OK;
 }
