@@ -107,6 +107,19 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
        "  const int before = __shfl(P, start > 0 ? start - 1 : 0, 64);\n"
        "  const bool tail = lane == 63 || ((H >> (lane + 1)) & 1ull);\n"
        "  return tail ? P - (start > 0 ? before : 0) : 0;\n}\n";
+  // the same for FP64 values: a scan segmented at the run starts, so the last
+  // lane of a run holds the run's sum (no difference of prefix sums)
+  e << "__device__ __forceinline__ double run_total_d(int bin, double x, int lane) {\n"
+       "  const int prev = __builtin_amdgcn_update_dpp(-1, bin, 0x138, 0xf, 0xf, false);\n"
+       "  const unsigned long long H = __ballot(lane == 0 || prev != bin);\n"
+       "  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);\n"
+       "  const int start = 63 - __clzll(H & upto);\n"
+       "  double P = x;\n"
+       "  for (int o = 1; o < 64; o <<= 1) {\n"
+       "    const double y = __shfl_up(P, o, 64);\n"
+       "    if (lane - o >= start) P += y;\n  }\n"
+       "  const bool tail = lane == 63 || ((H >> (lane + 1)) & 1ull);\n"
+       "  return tail ? P : 0.0;\n}\n";
   if (f64) {
     e << "__device__ __forceinline__ T wsum(T x) {\n"
          "  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);\n  return x;\n}\n";
@@ -162,6 +175,9 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
         << arg((uint64_t)d.outer_views[v].cnt) << "];\n";
   }
   bool any_global_tab = false;
+  for (int t = 0; t < F.n_tab; ++t)
+    if (F.tab_nvc[t] > 0)
+      e << "  double* __restrict__ tv" << t << " = (double*)A[" << arg((uint64_t)F.tab_vals[t]) << "];\n";
   for (int t = 0; t < F.n_tab; ++t)
     if (!F.tab_lds[t]) {
       any_global_tab = true;
@@ -332,12 +348,24 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   for (int t = 0; t < F.n_tab; ++t) {
     e << "        {\n          const int row = 0";
     for (int k = 0; k < F.tab_ncode[t]; ++k) e << " + c" << F.tab_code[t][k] << " * " << F.tab_stride[t][k];
-    e << ";\n          const int m = run_total(row, " << (has_mu_out ? "mu_out * " : "") << mu(F.tab_mask[t])
-      << ", lane);\n";
-    if (F.tab_lds[t])
-      e << "          if (m) atomicAdd(&tab_i[" << F.tab_off[t] << " + row], m);\n";
-    else
-      e << "          if (m) atomicAdd(&tab" << t << "[row], (unsigned long long)(long long)m);\n";
+    e << ";\n";
+    if (F.tab_has_cnt[t]) {
+      e << "          const int m = run_total(row, " << (has_mu_out ? "mu_out * " : "") << mu(F.tab_mask[t])
+        << ", lane);\n";
+      if (F.tab_lds[t])
+        e << "          if (m) atomicAdd(&tab_i[" << F.tab_off[t] << " + row], m);\n";
+      else
+        e << "          if (m) atomicAdd(&tab" << t << "[row], (unsigned long long)(long long)m);\n";
+    }
+    // value components: multiplicity times their factors, summed over each
+    // run of equal rows in FP64, one atomic per run
+    for (int k = 0; k < F.tab_nvc[t]; ++k) {
+      const int w = F.tab_vw[t][k];
+      e << "          { const double vs = run_total_d(row, (double)((T)(" << (has_mu_out ? "mu_out * " : "")
+        << mu((w >> 8) & 3) << ") * a" << (w & 15) << " * a" << ((w >> 4) & 15) << "), lane);\n"
+        << "            if (vs != 0.0) atomicAdd(&tv" << t << "[(long long)row * " << F.tab_nv[t] << " + "
+        << F.tab_vcomp[t][k] << "], vs); }\n";
+    }
     e << "        }\n";
   }
   e << "      }\n";

@@ -398,6 +398,13 @@ struct DFast {
   int32_t tab_lds[kGenTables];     // 1: LDS offset valid, else global counts
   int32_t tab_off[kGenTables];
   int64_t* tab_cnt[kGenTables];
+  // generated scans: value components of a table, added to FP64 outputs
+  int32_t tab_has_cnt[kGenTables];
+  int32_t tab_nvc[kGenTables];
+  int32_t tab_vcomp[kGenTables][kMaxTableComps];
+  int32_t tab_vw[kGenTables][kMaxTableComps];   // (ai + 1) | (aj + 1) << 4 | mask << 8
+  double* tab_vals[kGenTables];
+  int32_t tab_nv[kGenTables];
 };
 
 struct DScan {

@@ -882,11 +882,21 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     for (int v = 0; v < n_in; ++v)
       lean = lean && d.views[v].n_keys < ((int64_t)1 << 31) && d.views[v].nkey <= 2;
     for (int i = 0; i < d.n_hists; ++i) lean = lean && d.hists[i].offset + d.hists[i].dom < (1 << 19);
+    // tables: keys of at most 3 codes, at most one count component; value
+    // components (generated scans only) go to FP64 outputs
+    bool counts_only = true;
     for (int t = 0; t < d.n_tables; ++t) {
-      lean = lean && d.tables[t].n_tcomps == 1 && d.tables[t].tcomp[0] < 0 && d.tables[t].ncode <= 3 &&
-             d.tables[t].n_rows < ((int64_t)1 << 31);
+      const DTable& TB = d.tables[t];
+      int n_cnt = 0;
+      bool vals = false;
+      for (int k = 0; k < TB.n_tcomps; ++k) {
+        if (TB.tcomp[k] < 0) ++n_cnt;
+        else vals = true;
+      }
+      lean = lean && TB.ncode <= 3 && TB.n_rows < ((int64_t)1 << 31) && n_cnt <= 1 && (!vals || TB.vals_f64);
+      counts_only = counts_only && TB.n_tcomps == 1 && TB.tcomp[0] < 0;
     }
-    const bool builtin = lean && d.n_codes <= 4 && d.n_tables <= kFastTables;
+    const bool builtin = lean && counts_only && d.n_codes <= 4 && d.n_tables <= kFastTables;
     const bool fast = builtin || (lean && S.P->opts.codegen == 0);
     d.fast = fast ? 1 : 0;
     // generated scans gain from more resident wavefronts; the built-in ones
@@ -925,7 +935,22 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
           F.tab_code[t][k] = TB.code[k];
           F.tab_stride[t][k] = (int32_t)TB.stride[k];
         }
-        F.tab_mask[t] = weights[TB.twi[0]].mask_idx;
+        F.tab_mask[t] = 0;
+        F.tab_has_cnt[t] = 0;
+        F.tab_nvc[t] = 0;
+        for (int k = 0; k < TB.n_tcomps; ++k) {
+          const DWeight& Wk = weights[TB.twi[k]];
+          if (TB.tcomp[k] < 0) {
+            F.tab_has_cnt[t] = 1;
+            F.tab_mask[t] = Wk.mask_idx;
+          } else {
+            F.tab_vcomp[t][F.tab_nvc[t]] = TB.tcomp[k];
+            F.tab_vw[t][F.tab_nvc[t]] = (Wk.ai + 1) | ((Wk.aj + 1) << 4) | (Wk.mask_idx << 8);
+            F.tab_nvc[t]++;
+          }
+        }
+        F.tab_vals[t] = (double*)TB.vals;
+        F.tab_nv[t] = TB.n_vals;
         F.tab_lds[t] = TB.lds;
         F.tab_off[t] = TB.lds_off;
         F.tab_cnt[t] = TB.cnt;

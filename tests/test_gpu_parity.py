@@ -196,7 +196,8 @@ def test_graph_replay(eng, shape):
 def test_direct_tables_with_values(eng, precision):
     # per-key sums grouped by a key too large for a per-piece histogram
     # (item, 3,000 values) are direct tables with value components (SUM(1),
-    # SUM(units), SUM(units^2), SUM(units*g1)) written by the scan
+    # SUM(units), SUM(units^2), SUM(units*g1)) written by the generated scan,
+    # values summed in FP64 over runs of equal keys
     p = W.tiny_star(seed=7, n_fact=120_001, n_stores=40, n_items=3_000)
     p["batch"] = [{"groupby": ["item"], "where": [], "root": None,
                    "aggs": [[], [("units", 1)], [("units", 2)], [("units", 1), ("g1", 1)]]},
@@ -214,6 +215,7 @@ def test_direct_tables_with_values(eng, precision):
     d = prep.describe()
     scans = [(s["name"], s["lean"]) for s in d["steps"] if s["kind"] == "scan"]
     print(f"[case] tables with values {precision}: scans {scans}", flush=True)
+    assert any(lean == 2 for _, lean in scans), "the scan with value tables was not generated"
     compare_all(res, oracle.evaluate(p), F64_TOL if precision == "f64" else F32_TOL, f"tables_{precision}")
 
 
