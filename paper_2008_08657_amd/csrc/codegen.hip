@@ -191,7 +191,8 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   // histogram is kept in kRep copies, lane & (kRep-1) choosing the copy, so
   // that lanes adding to the same bin mostly meet in different copies; the
   // copies are summed when the piece closes.  Up to kMaxRep copies while the
-  // block fits in 64 KB, fewer for large histograms.
+  // block fits in 64 KB, fewer for large histograms; large direct tables in
+  // LDS take the block up to the whole LDS of a CU.
   const int hib = d.hist_i_bins, hfb = d.hist_f_bins;
   const int tab_bytes = (d.lds_tab_i * 4 + 15) & ~15;
   auto lds_for = [&](int rep) {
@@ -204,8 +205,8 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   const int hist_bytes = hist_i_bytes + kRep * hfb * tsz;
   const int wave_stride = (hist_bytes + 15) & ~15;
   const int lds = tab_bytes + kGenWaves * wave_stride;
-  if (lds > 65536) {
-    why = "generated scan would need more than 64 KB of LDS";
+  if (lds > 160 * 1024) {
+    why = "generated scan would need more LDS than a CU has";
     return false;
   }
   e << "  int* tab_i = (int*)smem;\n";
