@@ -30,6 +30,7 @@ namespace {
 
 constexpr int kGenWaves = 8;   // wavefronts per workgroup
 constexpr int kMaxRep = 4;     // most copies of each per-piece histogram
+constexpr int kRegHist = 16;   // histograms up to this many bins are kept in registers
 
 struct Emit {
   std::ostringstream o;
@@ -275,6 +276,15 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   }
   e << "      __builtin_amdgcn_wave_barrier();\n";
   for (size_t k = 0; k < terms.size(); ++k) e << "      T acc" << k << " = (T)0;\n";
+  // small histograms: a private counter per lane and bin, summed over the
+  // wavefront when the piece closes (no LDS atomics on skewed codes)
+  auto reg_hist = [&](int h) { return d.hists[h].dom <= kRegHist; };
+  for (int h = 0; h < F.n_hist; ++h) {
+    if (!reg_hist(h)) continue;
+    const bool fl = (F.hword[h] >> 4) & 1u;
+    for (int b = 0; b < d.hists[h].dom; ++b)
+      e << "      " << (fl ? "T" : "int") << " rh" << h << "_" << b << " = " << (fl ? "(T)0" : "0") << ";\n";
+  }
   for (int k = 0; k < d.n_pi; ++k) e << "      int cnt" << k << " = 0;\n";
   emit_decl("n");
   e << "      {\n        const int r = rb + lane < re ? rb + lane : rb;\n";
@@ -336,6 +346,21 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   for (int h = 0; h < F.n_hist; ++h) {
     const uint32_t w = F.hword[h];
     const int code = F.hcode[h], m = (int)((w >> 2) & 3u), off = (int)(w >> 13);
+    if (reg_hist(h)) {
+      if ((w >> 4) & 1u) {
+        const int ai = (int)((w >> 5) & 15u), aj = (int)((w >> 9) & 15u);
+        e << "        { const T hv = (T)" << mu(m) << " * a" << ai << " * a" << aj << ";";
+        for (int b = 0; b < d.hists[h].dom; ++b)
+          e << " rh" << h << "_" << b << " += c" << code << " == " << b << " ? hv : (T)0;";
+        e << " }\n";
+      } else {
+        e << "        { const int hv = " << mu(m) << ";";
+        for (int b = 0; b < d.hists[h].dom; ++b)
+          e << " rh" << h << "_" << b << " += c" << code << " == " << b << " ? hv : 0;";
+        e << " }\n";
+      }
+      continue;
+    }
     if ((w >> 4) & 1u) {
       const int ai = (int)((w >> 5) & 15u), aj = (int)((w >> 9) & 15u);
       e << "        if (" << mu(m) << ") atomicAdd(&hist_f[rep_f + " << off << " + c" << code << "], (T)" << mu(m)
@@ -379,6 +404,16 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   }
   for (int k = 0; k < d.n_pi; ++k)
     e << "      { const int sm = wsumi(cnt" << k << "); if (lane == 0) irow[" << k << "] = sm; }\n";
+  // register histograms into the first LDS copy (their LDS bins are zero)
+  for (int h = 0; h < F.n_hist; ++h) {
+    if (!reg_hist(h)) continue;
+    const uint32_t w = F.hword[h];
+    const bool fl = (w >> 4) & 1u;
+    const int off = (int)(w >> 13);
+    for (int b = 0; b < d.hists[h].dom; ++b)
+      e << "      { const " << (fl ? "T" : "int") << " sm = " << (fl ? "wsumc" : "wsumi") << "(rh" << h << "_" << b
+        << "); if (lane == 0) " << (fl ? "hist_f" : "hist_i") << "[" << off + b << "] = sm; }\n";
+  }
   e << "      __builtin_amdgcn_wave_barrier();\n      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");\n";
   if (hib > 0) {
     e << "      for (int i = lane; i < " << hib << "; i += 64) irow[" << d.n_pi << " + i] = hist_i[i]";

@@ -301,6 +301,19 @@ def test_rkmeans_chain_wide(eng):
     compare_all(prep.results(), oracle.evaluate(p), F32_TOL, "rkmeans_wide")
 
 
+def test_rkmeans_chain_large_domains(eng):
+    # count tables over domains up to 10^6 written by the scans (global
+    # tables; the R1 groups are scanned, not evaluated row by row)
+    p = W.rkmeans_chain(seed=8, n1=150_000, n2=80_000, n3=70_000, n_x=6, n_y=5, n_z=5, max_dom=1_000_000)
+    print("[case] rkmeans large domains", flush=True)
+    plan = eng.Plan(p, precision="f32", policy="fact", row_piece_max=5_000, min_segment=16)
+    prep = eng.Prepared(plan, eng.device_columns(p))
+    prep.run(sync=True)
+    kinds = {s["kind"] for s in prep.describe()["steps"]}
+    assert "scan" in kinds
+    compare_all(prep.results(), oracle.evaluate(p), F32_TOL, "rkmeans_large_domains")
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 @pytest.mark.parametrize("hash_slots", [0, 1024])
 def test_rkmeans_chain(eng, seed, hash_slots):
