@@ -278,7 +278,7 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   for (size_t k = 0; k < terms.size(); ++k) e << "      T acc" << k << " = (T)0;\n";
   // small histograms: a private counter per lane and bin, summed over the
   // wavefront when the piece closes (no LDS atomics on skewed codes)
-  auto reg_hist = [&](int h) { return d.hists[h].dom <= kRegHist; };
+  auto reg_hist = [&](int h) { return d.hists[h].dom <= std::min(kRegHist, (int)F.reg_hist_bins); };
   for (int h = 0; h < F.n_hist; ++h) {
     if (!reg_hist(h)) continue;
     const bool fl = (F.hword[h] >> 4) & 1u;

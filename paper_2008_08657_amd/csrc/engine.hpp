@@ -405,6 +405,7 @@ struct DFast {
   int32_t tab_vw[kGenTables][kMaxTableComps];   // (ai + 1) | (aj + 1) << 4 | mask << 8
   double* tab_vals[kGenTables];
   int32_t tab_nv[kGenTables];
+  int32_t reg_hist_bins;           // generated scans: histograms this small live in registers
 };
 
 struct DScan {

@@ -915,6 +915,9 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
         F.ccol[c] = (c < d.n_codes && g.in_codes[c].kind == SRC_COL)
                         ? (const int32_t*)N.sorted_col[scols[g.in_codes[c].src]] : (const int32_t*)nullptr;
       F.n_hist = d.n_hists;
+      // per-lane register histograms pay off when a piece spans at least one
+      // 64-row chunk (their wavefront sums are taken once per piece)
+      F.reg_hist_bins = R.n_rows >= 64 * std::max<int64_t>(1, N.n_pieces) ? 16 : 0;
       for (int i = 0; i < d.n_hists; ++i) {
         const DHist& H = d.hists[i];
         F.hcode[i] = (int8_t)H.code;
