@@ -63,6 +63,8 @@ def main():
                     help="hash-table sizing (default: learned for chain, bound otherwise)")
     ap.add_argument("--no-graph", action="store_true", help="launch every run directly (no HIP graph replay)")
     ap.add_argument("--scan-blocks", type=int, default=0, help="most workgroups of a scan launch (0 = 2048 generated, 512 built-in)")
+    ap.add_argument("--contract-splits", type=int, default=0,
+                    help="piece ranges per output tile column of a contraction (0 = 1024)")
     ap.add_argument("--one-hot-max", type=int, default=0, help="outputs keyed by outer codes only: largest key space expanded one-hot (0 = per group)")
     ap.add_argument("--plain-steps", type=int, default=0,
                     help="also time this many steps of the plain per-view form on the same input")
@@ -98,36 +100,18 @@ def main():
 
     E.load_library()
     t_gen = time.perf_counter()
-    if args.config == "retail":
-        n_inv = int(84_000_000 * args.scale)
-        problem = W.retail_snowflake(seed=0, n_inv=n_inv)
-        precision, workload = "f32", "retail-shaped snowflake (Inv 84M x 5 relations), covariance + 6 one-hot categoricals"
-    elif args.config == "grocery":
-        n_sales = int(120_000_000 * args.scale)
-        problem = W.grocery_star(seed=0, n_sales=n_sales)
-        precision, workload = "bf16x3", "grocery-shaped star (Sales 120M x 6 relations), covariance + 10 categoricals"
-    elif args.config == "cart":
-        n_inv = int(84_000_000 * args.scale)
-        problem = W.cart_node(seed=0, n_inv=n_inv)
-        precision, workload = "f32", ("CART node on the retail snowflake (Inv 84M): 840 thresholds + 7 "
-                                      "categorical group-bys x {SUM(1), SUM(y), SUM(y^2)} under a 3-condition path")
-    elif args.config == "chain":
-        n1 = int(50_000_000 * args.scale)
-        problem = W.rkmeans_chain(seed=0, n1=n1, n2=max(1000, n1 // 10), n3=max(100, n1 // 250))
-        precision, workload = "f32", ("Rk-means step 1 on a 3-relation chain (R1 50M, R2 5M, R3 200k; 100 "
-                                      "attributes, domains 10..1e6): SUM(1) by each attribute and 10 pairs")
-    else:
-        problem = W.tiny_star(seed=0)
-        precision, workload = "f64", "tiny star (S 100k x 3 relations), covariance grouped by cat"
-    precision = args.precision or precision
-    sizing = args.sizing or ("learned" if args.config == "chain" else "bound")
+    bw = W.bench_workload(args.config, args.scale)
+    problem, workload = bw["problem"], bw["workload"]
+    precision = args.precision or bw["precision"]
+    sizing = args.sizing or bw["sizing"]
     fact = max(problem["schema"], key=lambda r: r["n_rows"])
     n_join = fact["n_rows"]   # every fact row joins exactly once (complete foreign keys)
     n_aggs = sum(len(q["aggs"]) for q in problem["batch"])
     t_gen = time.perf_counter() - t_gen
 
     plan = E.Plan(problem, precision=precision, policy=problem["policy"], form=args.form, sizing=sizing,
-                  graph=not args.no_graph, one_hot_max=args.one_hot_max, scan_blocks=args.scan_blocks)
+                  graph=not args.no_graph, one_hot_max=args.one_hot_max, scan_blocks=args.scan_blocks,
+                  contract_splits=args.contract_splits)
     cols = E.device_columns(problem)
     torch.cuda.synchronize()
     t_prep = time.perf_counter()
@@ -269,6 +253,8 @@ def main():
         "cpu_baseline": cpu,
         "graph": {"captured": bool(graph["captured"]), "ms_per_step_direct": round(1e3 * t_eager / args.steps, 4)},
         "kernels_ms": {k: round(v, 4) for k, v in timing},
+        "kernels_launch": {k: [steps[k]["grid"], steps[k]["grid_y"], steps[k]["lds"]]
+                           for k, _ in timing if k in steps},
         "plain": plain,
         "hash_sizing": sizing_info,
         "check": check,

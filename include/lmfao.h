@@ -202,6 +202,9 @@ typedef struct {
                             generated scans, 512 for the built-in ones);
                             each has 8 wavefronts and takes whole work
                             items                                          */
+  int32_t contract_splits; /* ranges the pieces of a matrix-core contraction
+                            are cut into, per column of output tiles (0 =
+                            1024, fewer past 4096 workgroups)              */
 } lmfao_options;
 
 /* Initial capacity of a hash table.  BOUND: twice the most groups the output

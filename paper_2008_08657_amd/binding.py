@@ -74,7 +74,8 @@ class lmfao_options(C.Structure):
                 ("min_segment", C.c_int32), ("row_piece_max", C.c_int64),
                 ("contraction", C.c_int32), ("codegen", C.c_int32), ("hash_slots", C.c_int64),
                 ("sizing", C.c_int32), ("estimator", C.POINTER(C.c_float)), ("estimator_len", C.c_int64),
-                ("graph", C.c_int32), ("one_hot_max", C.c_int32), ("scan_blocks", C.c_int32)]
+                ("graph", C.c_int32), ("one_hot_max", C.c_int32), ("scan_blocks", C.c_int32),
+                ("contract_splits", C.c_int32)]
 
 
 class LmfaoError(RuntimeError):
@@ -195,7 +196,8 @@ class Plan:
 
     def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
                  min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0,
-                 sizing="bound", estimator=None, graph=False, one_hot_max=0, scan_blocks=0):
+                 sizing="bound", estimator=None, graph=False, one_hot_max=0, scan_blocks=0,
+                 contract_splits=0):
         self.lib = load_library()
         self.problem = problem
         keep = _Keep()
@@ -219,6 +221,7 @@ class Plan:
         opts.graph = 1 if graph else 0
         opts.one_hot_max = int(one_hot_max)
         opts.scan_blocks = int(scan_blocks)
+        opts.contract_splits = int(contract_splits)
         if sizing not in ("bound", "learned"):
             raise ValueError(f"sizing must be 'bound' or 'learned', not {sizing!r}")
         opts.sizing = 0 if sizing == "bound" else 1

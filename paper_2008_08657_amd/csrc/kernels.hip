@@ -2,7 +2,11 @@
 //
 //  k_fill            zero-fill of views and results
 //  k_view_build      views whose subtree has one join tuple per key: one
-//                    pass over the relation, dense key-indexed tables
+//                    pass over the relation, dense key-indexed tables (a
+//                    thread per output element; k_view_build_rows, a thread
+//                    per row, on large relations)
+//  k_build_image     per key of a view, the record a scan gathers (factors,
+//                    codes, multiplicity), written a dword per lane
 //  k_radix_*         stable LSD radix sort of packed trie keys (prepare)
 //  k_segment_starts  trie-level segment boundaries of a sorted relation
 //  k_scan<T,NA>      the node scan: one wavefront per run of pieces of the
@@ -352,8 +356,107 @@ void launch_ridge_bgd(const double* sigma, int dim, int label, double lam, doubl
 // ---------------------------------------------------------------------------
 // view build for single-valued subtrees
 // ---------------------------------------------------------------------------
+// One thread per output element: a row of the view is a multiplicity, n_vals
+// values and n_codes codes, and a workgroup takes about 256 such elements of
+// consecutive relation rows, so that rows which land in order (a relation
+// stored in key order) give coalesced stores and a view of a few thousand
+// rows still spreads over many workgroups.  Where each element comes from is
+// resolved once per workgroup into LDS.  The thread of a row's multiplicity
+// also checks that the key is unique.
+constexpr int kVBCols = 1 + 64 + kMaxOuterCodes;
+enum VBSrc : int8_t { VB_I32 = 0, VB_F32 = 1, VB_F64 = 2, VB_VIEW_F32 = 3, VB_VIEW_F64 = 4, VB_VIEW_CODE = 5 };
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_view_build(const DViewBuild* __restrict__ B) {
+  __shared__ const void* s_ptr[kVBCols];
+  __shared__ int32_t s_slot[kVBCols], s_stride[kVBCols];
+  __shared__ int8_t s_src[kVBCols], s_view[kVBCols];
+  const int64_t n = B->n_rows;
+  const int nvals = B->n_vals, ncodes = B->n_codes;
+  const int width = 1 + nvals + ncodes;
+  for (int c = threadIdx.x; c < width; c += 256) {
+    const void* p = nullptr;
+    int8_t src = VB_I32, view = -1;
+    int32_t slot = 0, stride = 0;
+    if (c >= 1 && c <= nvals) {
+      const int sl = c - 1;
+      if (B->val_kind[sl] == SRC_COL) {
+        const DCol& C = B->cols[B->val_src[sl]];
+        p = C.ptr;
+        src = C.dtype == LMFAO_F64 ? VB_F64 : C.dtype == LMFAO_F32 ? VB_F32 : VB_I32;
+      } else {
+        view = (int8_t)B->val_src[sl];
+        const DView& V = B->views[view];
+        p = V.vals;
+        src = V.vals_f64 ? VB_VIEW_F64 : VB_VIEW_F32;
+        slot = B->val_slot[sl];
+        stride = V.n_vals;
+      }
+    } else if (c > nvals) {
+      const int sl = c - 1 - nvals;
+      if (B->code_kind[sl] == SRC_COL) {
+        p = B->cols[B->code_src[sl]].ptr;
+      } else {
+        view = (int8_t)B->code_src[sl];
+        const DView& V = B->views[view];
+        p = V.codes;
+        src = VB_VIEW_CODE;
+        slot = B->code_slot[sl];
+        stride = V.n_codes;
+      }
+    }
+    s_ptr[c] = p;
+    s_src[c] = src;
+    s_view[c] = view;
+    s_slot[c] = slot;
+    s_stride[c] = stride;
+  }
+  __syncthreads();
+  const int rpt = width >= 256 ? 1 : 256 / width;   // relation rows per tile
+  const int64_t n_tiles = (n + rpt - 1) / rpt;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t r0 = t * rpt;
+    const int m = (int)(n - r0 < rpt ? n - r0 : rpt);
+    for (int j = threadIdx.x; j < m * width; j += 256) {
+      const int i = j / width, col = j - i * width;
+      const int64_t r = r0 + i;
+      int64_t row = 0;
+      for (int k = 0; k < B->nkey; ++k) row += ld_int(B->cols[B->key_col[k]], r) * B->key_stride[k];
+      const int my_view = s_view[col];
+      int64_t mu = 1, my_vr = 0;
+      for (int v = 0; v < B->n_views; ++v) {
+        const DView& V = B->views[v];
+        int64_t vr = 0;
+        for (int k = 0; k < V.nkey; ++k) vr += ld_int(B->cols[V.key_src[k]], r) * V.key_stride[k];
+        mu *= V.cnt[vr];
+        if (v == my_view) my_vr = vr;
+      }
+      if (B->w) mu *= B->w[r];
+      if (mu == 0) continue;
+      const void* p = s_ptr[col];
+      const int src = s_src[col];
+      const int64_t at = my_view >= 0 ? my_vr * s_stride[col] + s_slot[col] : r;
+      if (col == 0) {
+        unsigned long long old = atomicAdd((unsigned long long*)&B->out_cnt[row], (unsigned long long)mu);
+        if (old != 0 || mu != 1) atomicOr(B->err_flag, 1);   // key not unique
+      } else if (col <= nvals) {
+        T x;
+        if (src == VB_F64 || src == VB_VIEW_F64) x = (T)((const double*)p)[at];
+        else if (src == VB_F32 || src == VB_VIEW_F32) x = (T)((const float*)p)[at];
+        else x = (T)((const int32_t*)p)[at];
+        ((T*)B->out_vals)[row * nvals + (col - 1)] = x;
+      } else {
+        B->out_codes[row * ncodes + (col - 1 - nvals)] = ((const int32_t*)p)[at];
+      }
+    }
+  }
+}
+
+// One thread per relation row, for large relations: every element of a row
+// is written by the row's thread, with the value and code loops uniform over
+// the workgroup (descriptor reads stay scalar).
+template <typename T>
+__global__ __launch_bounds__(256) void k_view_build_rows(const DViewBuild* __restrict__ B) {
   const int64_t n = B->n_rows;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
@@ -373,30 +476,42 @@ __global__ __launch_bounds__(256) void k_view_build(const DViewBuild* __restrict
     unsigned long long old = atomicAdd((unsigned long long*)&B->out_cnt[row], (unsigned long long)mu);
     if (old != 0 || mu != 1) atomicOr(B->err_flag, 1);   // key not unique
     T* ov = (T*)B->out_vals;
-    for (int s = 0; s < B->n_vals; ++s) {
+    for (int sl = 0; sl < B->n_vals; ++sl) {
       T x;
-      if (B->val_kind[s] == SRC_COL) x = ld_val<T>(B->cols[B->val_src[s]], r);
-      else {
-        int v = B->val_src[s];
-        x = view_val<T>(B->views[v], vrow[v], B->val_slot[s]);
+      if (B->val_kind[sl] == SRC_COL) {
+        x = ld_val<T>(B->cols[B->val_src[sl]], r);
+      } else {
+        const int v = B->val_src[sl];
+        x = view_val<T>(B->views[v], vrow[v], B->val_slot[sl]);
       }
-      ov[row * B->n_vals + s] = x;
+      ov[row * B->n_vals + sl] = x;
     }
-    for (int s = 0; s < B->n_codes; ++s) {
+    for (int sl = 0; sl < B->n_codes; ++sl) {
       int32_t c;
-      if (B->code_kind[s] == SRC_COL) c = (int32_t)ld_int(B->cols[B->code_src[s]], r);
-      else {
-        int v = B->code_src[s];
-        c = B->views[v].codes[vrow[v] * B->views[v].n_codes + B->code_slot[s]];
+      if (B->code_kind[sl] == SRC_COL) {
+        c = (int32_t)ld_int(B->cols[B->code_src[sl]], r);
+      } else {
+        const int v = B->code_src[sl];
+        c = B->views[v].codes[vrow[v] * B->views[v].n_codes + B->code_slot[sl]];
       }
-      B->out_codes[row * B->n_codes + s] = c;
+      B->out_codes[row * B->n_codes + sl] = c;
     }
   }
 }
 
 void launch_view_build(const DViewBuild* d, int64_t n_rows, bool f64, hipStream_t s) {
   if (n_rows <= 0) return;
-  int grid = (int)std::min<int64_t>((n_rows + 255) / 256, 8192);
+  if (n_rows >= kViewBuildRowsMin) {
+    // large relations: a thread per row (measured faster there than a thread
+    // per element, whose keys are re-read once per element)
+    const int grid = (int)std::min<int64_t>((n_rows + 255) / 256, 8192);
+    if (f64) hipLaunchKernelGGL(k_view_build_rows<double>, dim3(grid), dim3(256), 0, s, d);
+    else hipLaunchKernelGGL(k_view_build_rows<float>, dim3(grid), dim3(256), 0, s, d);
+    return;
+  }
+  // a tile holds 256 / (1 + n_vals + n_codes) rows, at least one: one
+  // workgroup per row covers every tile, the surplus exits at once
+  const int grid = (int)std::min<int64_t>(n_rows, 8192);
   if (f64) hipLaunchKernelGGL(k_view_build<double>, dim3(grid), dim3(256), 0, s, d);
   else hipLaunchKernelGGL(k_view_build<float>, dim3(grid), dim3(256), 0, s, d);
 }
@@ -957,39 +1072,48 @@ int image_width_dw(int na, bool f64, int n_codes) {
 }
 int image_code_off(int na, bool f64) { return na * (f64 ? 2 : 1); }
 
+// Each workgroup fills the images of 64 consecutive keys, a contiguous run of
+// 64 * width dwords, one dword per lane per store.
 template <typename T>
-__global__ void k_build_image(const DImageBuild* __restrict__ B) {
+__global__ __launch_bounds__(256) void k_build_image(const DImageBuild* __restrict__ B) {
   const DView& V = B->view;
   const int W = B->width_dw;
   constexpr int s = sizeof(T) / 4;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < B->n_keys;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t* row = (uint32_t*)B->img + k * W;
-    const int64_t cnt = V.cnt[k];
-    for (int i = 0; i < W; ++i) row[i] = 0u;
-    for (int a = 0; a < B->n_atoms; ++a) {
-      int slot = B->atom_slot[a];
-      if (slot < 0 || cnt == 0) continue;
-      T x = view_val<T>(V, k, slot);
-      if (s == 1) {
-        row[a] = __float_as_uint((float)x);
-      } else {
-        double d = (double)x;
-        uint64_t u = (uint64_t)__double_as_longlong(d);
-        row[2 * a] = (uint32_t)u;
-        row[2 * a + 1] = (uint32_t)(u >> 32);
+  const int64_t n_tiles = (B->n_keys + 63) / 64;
+  uint32_t* img = (uint32_t*)B->img;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t k0 = t * 64;
+    const int m = (int)(B->n_keys - k0 < 64 ? B->n_keys - k0 : 64);
+    for (int j = threadIdx.x; j < m * W; j += 256) {
+      const int i = j / W, col = j - i * W;
+      const int64_t k = k0 + i;
+      const int64_t cnt = V.cnt[k];
+      uint32_t out = 0u;
+      if (col == B->cnt_off) {
+        out = (uint32_t)cnt;
+      } else if (cnt != 0 && col < B->code_off) {
+        const int a = col / s;
+        const int slot = a < B->n_atoms ? B->atom_slot[a] : -1;
+        if (slot >= 0) {
+          const T x = view_val<T>(V, k, slot);
+          if (s == 1) {
+            out = __float_as_uint((float)x);
+          } else {
+            const uint64_t u = (uint64_t)__double_as_longlong((double)x);
+            out = (col & 1) ? (uint32_t)(u >> 32) : (uint32_t)u;
+          }
+        }
+      } else if (cnt != 0 && col - B->code_off < B->n_codes) {
+        const int slot = B->code_slot[col - B->code_off];
+        if (slot >= 0) out = (uint32_t)V.codes[k * V.n_codes + slot];
       }
+      img[k0 * W + j] = out;
     }
-    for (int c = 0; c < B->n_codes; ++c) {
-      int slot = B->code_slot[c];
-      if (slot >= 0 && cnt != 0) row[B->code_off + c] = (uint32_t)V.codes[k * V.n_codes + slot];
-    }
-    row[B->cnt_off] = (uint32_t)cnt;
   }
 }
 void launch_build_image(const DImageBuild* d, int64_t n_keys, bool f64, hipStream_t s) {
   if (n_keys <= 0) return;
-  int grid = (int)std::min<int64_t>((n_keys + 255) / 256, 8192);
+  int grid = (int)std::min<int64_t>((n_keys + 63) / 64, 8192);
   if (f64) hipLaunchKernelGGL(k_build_image<double>, dim3(grid), dim3(256), 0, s, d);
   else hipLaunchKernelGGL(k_build_image<float>, dim3(grid), dim3(256), 0, s, d);
 }

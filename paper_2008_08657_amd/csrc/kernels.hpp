@@ -96,6 +96,9 @@ void launch_sigma_assemble(const DSigmaEntry* e, int64_t n, double* sigma, int d
 void launch_ridge_bgd(const double* sigma, int dim, int label, double lam, double eta, int max_iter, double tol,
                       double* theta, double* out, hipStream_t s);
 constexpr int kRidgeMaxDim = 2048;
+// relations of at least this many rows build their view a thread per row,
+// smaller ones a thread per output element
+constexpr int64_t kViewBuildRowsMin = 65536;
 void launch_view_build(const DViewBuild* d, int64_t n_rows, bool f64, hipStream_t s);
 void launch_make_keys(const DKeyCols* d, uint64_t* keys, uint32_t* idx, int64_t n, hipStream_t s);
 void launch_sort(uint64_t* keys, uint32_t* idx, uint64_t* keys_tmp, uint32_t* idx_tmp, int64_t n, int bits,

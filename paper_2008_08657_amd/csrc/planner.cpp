@@ -1551,6 +1551,8 @@ Plan* build_plan(const lmfao_schema* schema, const lmfao_join_tree* tree, const 
       throw PlanError{LMFAO_EINVAL, "unknown precision"};
     if (P->opts.precision >= LMFAO_PREC_BF16X3 && P->opts.contraction != LMFAO_CONTRACT_MFMA)
       throw PlanError{LMFAO_EINVAL, "BF16 split precisions run the contraction on the matrix cores"};
+    if (P->opts.scan_blocks < 0 || P->opts.contract_splits < 0 || P->opts.contract_splits > (1 << 20))
+      throw PlanError{LMFAO_EINVAL, "scan_blocks and contract_splits must be 0 (automatic) or positive"};
     intake(*P, schema, tree, batch);
     compute_uniqueness(*P);
     generate_views(*P);

@@ -412,7 +412,13 @@ static void build_contract_mfma(Prep& S, const GroupProgram& g, const std::strin
   const int tn = gemm_tile_cols(std::max(1, NG));
   const int gy = gemm_macro_tiles(std::max(1, NF), std::max(1, NG));
   const int64_t kc = contract_fused_chunk();
-  const int64_t want = std::max(1, 512 / gy);   // K splits: ~2 blocks per CU in all
+  // Pieces are cut into about 1024 ranges per column of output tiles (fewer
+  // when the grid would pass 4096 workgroups): with two to three resident
+  // workgroups per CU the three dependent loads of each 16-piece chunk stay
+  // hidden, and the FP64 partials to merge stay small.
+  const int64_t want = S.P->opts.contract_splits > 0
+                           ? (int64_t)S.P->opts.contract_splits
+                           : std::max<int64_t>(1, std::min<int64_t>(1024, 4096 / gy));
   int64_t kpb = (n_pieces + want - 1) / want;
   kpb = std::max<int64_t>(kc, (kpb + kc - 1) / kc * kc);
   const int gx = (int)std::max<int64_t>(1, (n_pieces + kpb - 1) / kpb);
@@ -903,7 +909,12 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     // (descriptor-driven, more registers) do best with fewer
     const int waves = scan_waves_per_block();
     const bool expect_gen = lean && S.P->opts.codegen == 0;
-    const int max_blocks = S.P->opts.scan_blocks > 0 ? S.P->opts.scan_blocks : (expect_gen ? 2048 : 512);
+    // and every workgroup keeps at least 2048 rows, so that on a small
+    // relation the per-workgroup partial tables stay cheap to merge
+    const int max_blocks =
+        S.P->opts.scan_blocks > 0
+            ? S.P->opts.scan_blocks
+            : (int)std::min<int64_t>(expect_gen ? 2048 : 512, std::max<int64_t>(256, (R.n_rows + 2047) / 2048));
     int grid = (int)std::min<int64_t>((N.n_items + waves - 1) / waves, max_blocks);
     grid = std::max(grid, 1);
     d.part_i = (int32_t*)dalloc(S, (size_t)grid * std::max(1, lds_used) * 4);

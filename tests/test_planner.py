@@ -242,3 +242,10 @@ def test_wide_chain_groups_are_split_to_fit_the_kernels():
     for g in d["groups"]:
         prog = g.get("program") or {}
         assert len(prog.get("scan_cols", [])) <= 16
+
+
+@pytest.mark.parametrize("kw", [{"scan_blocks": -1}, {"contract_splits": -4}])
+def test_negative_launch_options_are_rejected(kw):
+    with pytest.raises(E.LmfaoError) as ei:
+        E.Plan(W.tiny_star(n_fact=100), policy="fact", **kw)
+    assert str(ei.value).startswith("EINVAL")

@@ -587,3 +587,37 @@ def estimator_workload(seed: int, max_rows: int = 1_000_000):
     return {"name": f"estimator_{shape}_{seed}", "schema": schema,
             "tree": [(parent[c], c) for c in range(1, n_rel)], "batch": batch,
             "data": {names[r]: data[r] for r in range(n_rel)}, "policy": "fact", "precision": "f32"}
+
+
+def bench_workload(config: str, scale: float = 1.0) -> dict:
+    """The measured workloads at their full sizes (``scale`` shrinks the fact
+    relation): the relations, the batch, the arithmetic precision they run in,
+    the hash-table sizing and a one-line description.  The benchmark and the
+    full-size parity tests both build their inputs here, so both see the same
+    data and the same launch configuration."""
+    if config == "retail":
+        problem = retail_snowflake(seed=0, n_inv=int(84_000_000 * scale))
+        precision, sizing = "f32", "bound"
+        workload = "retail-shaped snowflake (Inv 84M x 5 relations), covariance + 6 one-hot categoricals"
+    elif config == "grocery":
+        problem = grocery_star(seed=0, n_sales=int(120_000_000 * scale))
+        precision, sizing = "bf16x3", "bound"
+        workload = "grocery-shaped star (Sales 120M x 6 relations), covariance + 10 categoricals"
+    elif config == "cart":
+        problem = cart_node(seed=0, n_inv=int(84_000_000 * scale))
+        precision, sizing = "f32", "bound"
+        workload = ("CART node on the retail snowflake (Inv 84M): 840 thresholds + 7 "
+                    "categorical group-bys x {SUM(1), SUM(y), SUM(y^2)} under a 3-condition path")
+    elif config == "chain":
+        n1 = int(50_000_000 * scale)
+        problem = rkmeans_chain(seed=0, n1=n1, n2=max(1000, n1 // 10), n3=max(100, n1 // 250))
+        precision, sizing = "f32", "learned"
+        workload = ("Rk-means step 1 on a 3-relation chain (R1 50M, R2 5M, R3 200k; 100 "
+                    "attributes, domains 10..1e6): SUM(1) by each attribute and 10 pairs")
+    elif config == "tiny":
+        problem = tiny_star(seed=0)
+        precision, sizing = "f64", "bound"
+        workload = "tiny star (S 100k x 3 relations), covariance grouped by cat"
+    else:
+        raise ValueError(f"unknown workload {config!r}")
+    return {"problem": problem, "precision": precision, "sizing": sizing, "workload": workload}
