@@ -346,3 +346,18 @@ def test_view_build_large_and_small_relations(eng, n_weather_dates):
     p = W.retail_snowflake(seed=9, n_inv=150_001, n_locn=260, n_dates=min(12, n_weather_dates),
                            n_ksn=300, n_weather_dates=n_weather_dates)
     check(eng, p, F32_TOL, f"view build, Weather {260 * n_weather_dates} rows", precision="f32", policy="fact")
+
+
+def test_register_histograms_with_multiplicities(eng):
+    # a few items carry two tags: inside the scan some rows weigh cat's
+    # register histogram with a multiplicity of 2.  Register histograms need
+    # pieces of 64 rows or more on average: FP32, and more than 16384 * 64
+    # rows so that the work items grow past one chunk.
+    p = W.tagged_star(seed=4, n_fact=2_500_000)
+    ref = oracle.evaluate(p)
+    for order in ({"S": ["store", "item"]}, None):
+        print(f"[case] tagged star, order {order}", flush=True)
+        _, prep, res = run_engine(eng, p, precision="f32", policy="fact", order=order)
+        compare_all(res, ref, F32_TOL, f"tagged star {order}")
+        if order is not None:
+            assert any(" rh0_0 = 0;" in src for src in prep.kernel_sources())

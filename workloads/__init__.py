@@ -621,3 +621,37 @@ def bench_workload(config: str, scale: float = 1.0) -> dict:
     else:
         raise ValueError(f"unknown workload {config!r}")
     return {"problem": problem, "precision": precision, "sizing": sizing, "workload": workload}
+
+
+def tagged_star(seed: int = 0, n_fact: int = 200_000, n_stores: int = 40, n_items: int = 3_000,
+                dup_frac: float = 0.03, n_cat: int = 12):
+    """Star S(store, item, units) with Stores(store, f1, f2), Items(item, g1,
+    cat in [0, n_cat)) and Tags(item, tagw): every item has one tag and a
+    fraction ``dup_frac`` of the items a second one, so the join multiplies a
+    few fact rows by two.  Batch: COUNT, SUM(units), SUM(units*g1), SUM(f1),
+    each ungrouped and grouped by cat, plus SUM(1) grouped by (store, cat)."""
+    r_s, r_st, r_it, r_tg = _spawn(seed, 4)
+    extra = np.sort(r_tg.choice(n_items, max(1, int(dup_frac * n_items)), replace=False)).astype(np.int32)
+    tag_items = np.concatenate([np.arange(n_items, dtype=np.int32), extra])
+    data = {
+        "S": {"store": zipf_keys(r_s, n_fact, n_stores, 1.0), "item": zipf_keys(r_s, n_fact, n_items, 1.1),
+              "units": r_s.lognormal(0.0, 1.0, n_fact)},
+        "Stores": {"store": np.arange(n_stores, dtype=np.int32),
+                   "f1": r_st.standard_normal(n_stores), "f2": r_st.standard_normal(n_stores)},
+        "Items": {"item": np.arange(n_items, dtype=np.int32), "g1": r_it.standard_normal(n_items),
+                  "cat": r_it.integers(0, n_cat, n_items).astype(np.int32)},
+        "Tags": {"item": tag_items, "tagw": r_tg.standard_normal(len(tag_items))},
+    }
+    schema = [
+        _rel("S", n_fact, [_attr("store", "i32", n_stores), _attr("item", "i32", n_items), _attr("units", "f64")]),
+        _rel("Stores", n_stores, [_attr("store", "i32", n_stores, True), _attr("f1", "f64"), _attr("f2", "f64")]),
+        _rel("Items", n_items, [_attr("item", "i32", n_items, True), _attr("g1", "f64"),
+                                _attr("cat", "i32", n_cat)]),
+        _rel("Tags", len(tag_items), [_attr("item", "i32", n_items), _attr("tagw", "f64")]),
+    ]
+    aggs = [[], [("units", 1)], [("units", 1), ("g1", 1)], [("f1", 1)]]
+    batch = [{"groupby": [], "where": [], "aggs": aggs, "root": None},
+             {"groupby": ["cat"], "where": [], "aggs": aggs, "root": None},
+             {"groupby": ["store", "cat"], "where": [], "aggs": [[]], "root": None}]
+    return {"name": "tagged_star", "schema": schema, "tree": [(0, 1), (0, 2), (0, 3)],
+            "batch": batch, "data": data, "policy": "fact", "precision": "f64"}
