@@ -17,6 +17,7 @@
 
 #include <cstdio>
 #include <map>
+#include <algorithm>
 #include <mutex>
 #include <sstream>
 #include <string>
@@ -415,63 +416,93 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
       (fl ? fv[(size_t)d.pf_n + off + b] : iv[(size_t)d.n_pi + off + b]) =
           "rh" + std::to_string(h) + "_" + std::to_string(b);
   }
-  // Many values: one transposed butterfly over all of them.  At the step
+  // Many values: a transposed butterfly over each block of 64.  At the step
   // with lane mask m every lane pairs values (2i, 2i+1), keeps the one its
   // lane bit selects, sends the other to lane ^ m and adds what it receives;
   // after six steps lane L holds the wavefront total of value
   // bitreverse6(L).  About 4 operations per value in all, against 13 for a
   // separate reduction per value.  FP64 plans keep the compensated
   // reduction per value.
-  auto butterfly = [&](const std::vector<std::string>& vals, const char* ty, const std::string& nm,
-                       const std::string& dst_lo, int n_lo, const std::string& dst_hi) {
-    int present = 0;
-    uint64_t mask = 0;
-    for (size_t v = 0; v < vals.size(); ++v)
-      if (!vals[v].empty()) {
-        ++present;
-        mask |= 1ull << v;
+  // A block whose present values are too sparse for the butterfly to pay
+  // (about 4 operations per pair it combines, against 13 per separate
+  // reduction) reduces them one by one.
+  auto close_values = [&](const std::vector<std::string>& vals, const char* ty, const std::string& nm,
+                          const std::string& dst_lo, int n_lo, const std::string& dst_hi, bool tree_ok,
+                          const char* sumfn) {
+    auto one_by_one = [&](size_t lo, size_t hi) {
+      for (size_t v = lo; v < hi; ++v) {
+        if (vals[v].empty()) continue;
+        e << "      { const " << ty << " sm = " << sumfn << "(" << vals[v] << "); if (lane == 0) ";
+        if ((int)v < n_lo) e << dst_lo << "[" << v << "] = sm; }\n";
+        else e << dst_hi << "[" << v - n_lo << "] = sm; }\n";
       }
-    if (present < kTreeMin || vals.size() > 64) return false;
-    e << "      {\n";
-    std::vector<std::string> cur;
-    for (size_t v = 0; v < vals.size(); ++v) cur.push_back(vals[v].empty() ? std::string("(") + ty + ")0" : vals[v]);
-    for (int st = 0; st < 6; ++st) {
-      const int m = 32 >> st;
-      const std::string bit = nm + "b" + std::to_string(st);
-      e << "        const bool " << bit << " = (lane & " << m << ") != 0;\n";
-      std::vector<std::string> nxt;
-      for (size_t i = 0; 2 * i < cur.size(); ++i) {
-        const std::string x = cur[2 * i], y = 2 * i + 1 < cur.size() ? cur[2 * i + 1] : std::string("(") + ty + ")0";
-        const std::string out = nm + std::to_string(st) + "_" + std::to_string(i);
-        e << "        const " << ty << " " << out << " = (" << bit << " ? " << y << " : " << x << ") + __shfl_xor("
-          << bit << " ? " << x << " : " << y << ", " << m << ", 64);\n";
-        nxt.push_back(out);
+    };
+    std::vector<size_t> tree_blocks;
+    for (size_t base = 0; base < vals.size(); base += 64) {
+      size_t nb = 0;
+      int present = 0;
+      for (size_t v = 0; v < 64 && base + v < vals.size(); ++v)
+        if (!vals[base + v].empty()) {
+          nb = v + 1;
+          ++present;
+        }
+      int pairs = 0;   // pairs combined over the six steps
+      for (size_t n = nb, st = 0; st < 6; ++st) {
+        n = (n + 1) / 2;
+        pairs += (int)n;
       }
-      cur = nxt;
+      if (tree_ok && present >= kTreeMin && 13 * present >= 4 * pairs) tree_blocks.push_back(base);
     }
-    e << "        const int v = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);\n"
-      << "        if ((" << mask << "ull >> v) & 1ull) {\n"
-      << "          if (v < " << n_lo << ") " << dst_lo << "[v] = " << cur[0] << ";\n"
-      << "          else " << dst_hi << "[v - " << n_lo << "] = " << cur[0] << ";\n"
-      << "        }\n      }\n";
-    return true;
+    if (!tree_blocks.empty()) {
+      e << "      {\n        const int bv = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);\n";
+      for (int st = 0; st < 6; ++st)
+        e << "        const bool " << nm << "b" << st << " = (lane & " << (32 >> st) << ") != 0;\n";
+      for (size_t base : tree_blocks) {
+        const size_t nb = std::min<size_t>(64, vals.size() - base);
+        uint64_t mask = 0;
+        std::vector<std::string> cur;
+        size_t last = 0;
+        for (size_t v = 0; v < nb; ++v)
+          if (!vals[base + v].empty()) last = v + 1;
+        for (size_t v = 0; v < last; ++v) {
+          if (!vals[base + v].empty()) mask |= 1ull << v;
+          cur.push_back(vals[base + v].empty() ? std::string("(") + ty + ")0" : vals[base + v]);
+        }
+        const std::string pre = nm + std::to_string(base / 64) + "_";
+        for (int st = 0; st < 6; ++st) {
+          const int m = 32 >> st;
+          const std::string bit = nm + "b" + std::to_string(st);
+          std::vector<std::string> nxt;
+          for (size_t i = 0; 2 * i < cur.size(); ++i) {
+            const std::string x = cur[2 * i],
+                              y = 2 * i + 1 < cur.size() ? cur[2 * i + 1] : std::string("(") + ty + ")0";
+            const std::string out = pre + std::to_string(st) + "_" + std::to_string(i);
+            e << "        const " << ty << " " << out << " = (" << bit << " ? " << y << " : " << x
+              << ") + __shfl_xor(" << bit << " ? " << x << " : " << y << ", " << m << ", 64);\n";
+            nxt.push_back(out);
+          }
+          cur = nxt;
+        }
+        e << "        if ((" << mask << "ull >> bv) & 1ull) {\n"
+          << "          const int v = " << base << " + bv;\n"
+          << "          if (v < " << n_lo << ") " << dst_lo << "[v] = " << cur[0] << ";\n"
+          << "          else " << dst_hi << "[v - " << n_lo << "] = " << cur[0] << ";\n"
+          << "        }\n";
+      }
+      e << "      }\n";
+    }
+    for (size_t base = 0; base < vals.size(); base += 64) {
+      if (std::find(tree_blocks.begin(), tree_blocks.end(), base) != tree_blocks.end()) continue;
+      one_by_one(base, std::min<size_t>(vals.size(), base + 64));
+    }
   };
-  if (f64 || !butterfly(fv, "T", "bf", "prow", d.pf_n, "hist_f")) {
-    for (size_t v = 0; v < fv.size(); ++v) {
-      if (fv[v].empty()) continue;
-      e << "      { const T sm = wsumc(" << fv[v] << "); if (lane == 0) ";
-      if ((int)v < d.pf_n) e << "prow[" << v << "] = sm; }\n";
-      else e << "hist_f[" << v - d.pf_n << "] = sm; }\n";
-    }
-  }
-  if (!butterfly(iv, "int", "bi", "irow", d.n_pi, "hist_i")) {
-    for (size_t v = 0; v < iv.size(); ++v) {
-      if (iv[v].empty()) continue;
-      e << "      { const int sm = wsumi(" << iv[v] << "); if (lane == 0) ";
-      if ((int)v < d.n_pi) e << "irow[" << v << "] = sm; }\n";
-      else e << "hist_i[" << v - d.n_pi << "] = sm; }\n";
-    }
-  }
+  // The butterfly's exchanges go through the LDS crossbar: a scan that also
+  // keeps histograms in LDS (atomics per row) measured slower with it, so
+  // there every value keeps its own reduction.
+  bool lds_hists = false;
+  for (int h = 0; h < F.n_hist; ++h) lds_hists = lds_hists || !reg_hist(h);
+  close_values(fv, "T", "bf", "prow", d.pf_n, "hist_f", !f64 && !lds_hists, "wsumc");
+  close_values(iv, "int", "bi", "irow", d.n_pi, "hist_i", !lds_hists, "wsumi");
   e << "      __builtin_amdgcn_wave_barrier();\n      __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\");\n";
   if (hib > 0) {
     e << "      for (int i = lane; i < " << hib << "; i += 64) irow[" << d.n_pi << " + i] = hist_i[i]";
