@@ -361,3 +361,50 @@ def test_register_histograms_with_multiplicities(eng):
         compare_all(res, ref, F32_TOL, f"tagged star {order}")
         if order is not None:
             assert any(" rh0_0 = 0;" in src for src in prep.kernel_sources())
+
+
+def _tiny_star_variant(n_fact, seed=11):
+    return W.tiny_star(seed=seed, n_fact=n_fact, n_stores=7, n_items=90)
+
+
+@pytest.mark.parametrize("n_fact", [1, 63, 64, 65, 4097])
+def test_ragged_sizes(eng, n_fact):
+    # one row, one row short of a 64-row chunk, exactly one chunk, one row
+    # past it, one row past a 4,096-row work item
+    p = _tiny_star_variant(n_fact)
+    check(eng, p, F64_TOL, f"ragged {n_fact}", policy="fact")
+    check(eng, p, F64_TOL, f"ragged {n_fact} scan", policy="fact", row_piece_max=-1, min_segment=1)
+
+
+def test_empty_join(eng):
+    # Items holds one item that no fact row uses: the join is empty, and every
+    # query has no group (the ungrouped ones no row either)
+    p = _tiny_star_variant(3_000)
+    p["data"]["Items"] = {"item": np.array([89], np.int32), "g1": np.array([0.5]), "g2": np.array([-1.0]),
+                          "g3": np.array([2.0]), "cat": np.array([3], np.int32)}
+    p["schema"][2]["n_rows"] = 1
+    p["data"]["S"]["item"] = np.minimum(p["data"]["S"]["item"], 88).astype(np.int32)
+    ref = oracle.evaluate(p)
+    assert all(r["keys"].shape[0] == 0 for r in ref)
+    check(eng, p, F64_TOL, "empty join", policy="fact")
+    check(eng, p, F64_TOL, "empty join scan", policy="fact", row_piece_max=-1, min_segment=1)
+
+
+def test_filter_selects_nothing(eng):
+    p = _tiny_star_variant(5_000)
+    p["batch"] = [dict(q, where=[("units", "<", -1.0)]) for q in p["batch"][:6]] + p["batch"][:2]
+    ref = oracle.evaluate(p)
+    assert all(r["keys"].shape[0] == 0 for r in ref[:6])
+    check(eng, p, F64_TOL, "filter selects nothing", policy="fact")
+
+
+def test_dangling_keys(eng):
+    # half of the items are missing from Items: their fact rows drop out
+    p = _tiny_star_variant(20_000)
+    keep = p["data"]["Items"]["item"] % 2 == 0
+    p["data"]["Items"] = {k: v[keep] for k, v in p["data"]["Items"].items()}
+    p["schema"][2]["n_rows"] = int(keep.sum())
+    ref = oracle.evaluate(p)
+    assert 0 < int(ref[0]["count"][0]) < 20_000
+    check(eng, p, F64_TOL, "dangling keys", policy="fact")
+    check(eng, p, F64_TOL, "dangling keys scan", policy="fact", row_piece_max=-1, min_segment=1)
