@@ -58,3 +58,38 @@ def test_describe_buffer_convention():
     small = ctypes.create_string_buffer(8)
     assert pl.lib.lmfao_plan_describe(pl.handle, small, 8, ctypes.byref(need)) == 0
     assert len(small.value) == 7 and need.value > 8
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # every struct the binding mirrors has the size and field offsets the C
+    # compiler gives the header's declaration
+    import shutil
+    import subprocess
+    from paper_2008_08657_amd import binding as B
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = ["lmfao_attr", "lmfao_relation", "lmfao_schema", "lmfao_edge", "lmfao_join_tree", "lmfao_factor",
+             "lmfao_aggregate", "lmfao_condition", "lmfao_query", "lmfao_batch", "lmfao_options"]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lmfao.h"', "int main(void) {"]
+    for n in names:
+        lines.append(f'  printf("{n} size %zu\\n", sizeof({n}));')
+        for fname, _ in getattr(B, n)._fields_:
+            lines.append(f'  printf("{n} {fname} %zu\\n", offsetof({n}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c_side = {}
+    for ln in out:
+        if ln:
+            parts = ln.split()
+            c_side[(parts[0], parts[1])] = int(parts[2])
+    for n in names:
+        st = getattr(B, n)
+        assert c_side[(n, "size")] == ctypes.sizeof(st), n
+        for fname, _ in st._fields_:
+            assert c_side[(n, fname)] == getattr(st, fname).offset, f"{n}.{fname}"
