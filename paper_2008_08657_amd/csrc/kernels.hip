@@ -475,26 +475,38 @@ __global__ __launch_bounds__(256) void k_view_build_rows(const DViewBuild* __res
     if (mu == 0) continue;
     unsigned long long old = atomicAdd((unsigned long long*)&B->out_cnt[row], (unsigned long long)mu);
     if (old != 0 || mu != 1) atomicOr(B->err_flag, 1);   // key not unique
+    auto val = [&](int sl) -> T {
+      if (B->val_kind[sl] == SRC_COL) return ld_val<T>(B->cols[B->val_src[sl]], r);
+      const int v = B->val_src[sl];
+      return view_val<T>(B->views[v], vrow[v], B->val_slot[sl]);
+    };
+    auto code = [&](int sl) -> int32_t {
+      if (B->code_kind[sl] == SRC_COL) return (int32_t)ld_int(B->cols[B->code_src[sl]], r);
+      const int v = B->code_src[sl];
+      return B->views[v].codes[vrow[v] * B->views[v].n_codes + B->code_slot[sl]];
+    };
+    // 16-byte stores where the row stride allows (view buffers are 256-byte
+    // aligned): a quarter of the store instructions of one per element
     T* ov = (T*)B->out_vals;
-    for (int sl = 0; sl < B->n_vals; ++sl) {
-      T x;
-      if (B->val_kind[sl] == SRC_COL) {
-        x = ld_val<T>(B->cols[B->val_src[sl]], r);
+    const int nv = B->n_vals, nc = B->n_codes;
+    if constexpr (sizeof(T) == 4) {
+      if ((nv & 3) == 0) {
+        for (int sl = 0; sl < nv; sl += 4)
+          *(float4*)(ov + row * nv + sl) = make_float4(val(sl), val(sl + 1), val(sl + 2), val(sl + 3));
       } else {
-        const int v = B->val_src[sl];
-        x = view_val<T>(B->views[v], vrow[v], B->val_slot[sl]);
+        for (int sl = 0; sl < nv; ++sl) ov[row * nv + sl] = val(sl);
       }
-      ov[row * B->n_vals + sl] = x;
+    } else {
+      if ((nv & 1) == 0) {
+        for (int sl = 0; sl < nv; sl += 2) *(double2*)(ov + row * nv + sl) = make_double2(val(sl), val(sl + 1));
+      } else {
+        for (int sl = 0; sl < nv; ++sl) ov[row * nv + sl] = val(sl);
+      }
     }
-    for (int sl = 0; sl < B->n_codes; ++sl) {
-      int32_t c;
-      if (B->code_kind[sl] == SRC_COL) {
-        c = (int32_t)ld_int(B->cols[B->code_src[sl]], r);
-      } else {
-        const int v = B->code_src[sl];
-        c = B->views[v].codes[vrow[v] * B->views[v].n_codes + B->code_slot[sl]];
-      }
-      B->out_codes[row * B->n_codes + sl] = c;
+    if ((nc & 1) == 0) {
+      for (int sl = 0; sl < nc; sl += 2) *(int2*)(B->out_codes + row * nc + sl) = make_int2(code(sl), code(sl + 1));
+    } else {
+      for (int sl = 0; sl < nc; ++sl) B->out_codes[row * nc + sl] = code(sl);
     }
   }
 }
@@ -1072,42 +1084,48 @@ int image_width_dw(int na, bool f64, int n_codes) {
 }
 int image_code_off(int na, bool f64) { return na * (f64 ? 2 : 1); }
 
+// One dword of key k's image record: a factor (or half of an FP64 one), a
+// code, or the multiplicity; zero elsewhere and for keys without tuples
+template <typename T>
+__device__ __forceinline__ uint32_t image_dword(const DImageBuild* __restrict__ B, const DView& V, int64_t k,
+                                                int64_t cnt, int col) {
+  constexpr int s = sizeof(T) / 4;
+  if (col == B->cnt_off) return (uint32_t)cnt;
+  if (cnt == 0) return 0u;
+  if (col < B->code_off) {
+    const int a = col / s;
+    const int slot = a < B->n_atoms ? B->atom_slot[a] : -1;
+    if (slot < 0) return 0u;
+    const T x = view_val<T>(V, k, slot);
+    if (s == 1) return __float_as_uint((float)x);
+    const uint64_t u = (uint64_t)__double_as_longlong((double)x);
+    return (col & 1) ? (uint32_t)(u >> 32) : (uint32_t)u;
+  }
+  if (col - B->code_off < B->n_codes) {
+    const int slot = B->code_slot[col - B->code_off];
+    if (slot >= 0) return (uint32_t)V.codes[k * V.n_codes + slot];
+  }
+  return 0u;
+}
+
 // Each workgroup fills the images of 64 consecutive keys, a contiguous run of
-// 64 * width dwords, one dword per lane per store.
+// 64 * width dwords, four dwords per lane per store (widths are multiples of
+// 4 and the image buffer is allocated on its own, so every store is aligned).
 template <typename T>
 __global__ __launch_bounds__(256) void k_build_image(const DImageBuild* __restrict__ B) {
   const DView& V = B->view;
-  const int W = B->width_dw;
-  constexpr int s = sizeof(T) / 4;
+  const int W4 = B->width_dw >> 2;
   const int64_t n_tiles = (B->n_keys + 63) / 64;
-  uint32_t* img = (uint32_t*)B->img;
+  uint4* img = (uint4*)B->img;
   for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const int64_t k0 = t * 64;
     const int m = (int)(B->n_keys - k0 < 64 ? B->n_keys - k0 : 64);
-    for (int j = threadIdx.x; j < m * W; j += 256) {
-      const int i = j / W, col = j - i * W;
+    for (int j = threadIdx.x; j < m * W4; j += 256) {
+      const int i = j / W4, c0 = (j - i * W4) * 4;
       const int64_t k = k0 + i;
       const int64_t cnt = V.cnt[k];
-      uint32_t out = 0u;
-      if (col == B->cnt_off) {
-        out = (uint32_t)cnt;
-      } else if (cnt != 0 && col < B->code_off) {
-        const int a = col / s;
-        const int slot = a < B->n_atoms ? B->atom_slot[a] : -1;
-        if (slot >= 0) {
-          const T x = view_val<T>(V, k, slot);
-          if (s == 1) {
-            out = __float_as_uint((float)x);
-          } else {
-            const uint64_t u = (uint64_t)__double_as_longlong((double)x);
-            out = (col & 1) ? (uint32_t)(u >> 32) : (uint32_t)u;
-          }
-        }
-      } else if (cnt != 0 && col - B->code_off < B->n_codes) {
-        const int slot = B->code_slot[col - B->code_off];
-        if (slot >= 0) out = (uint32_t)V.codes[k * V.n_codes + slot];
-      }
-      img[k0 * W + j] = out;
+      img[k0 * W4 + j] = make_uint4(image_dword<T>(B, V, k, cnt, c0), image_dword<T>(B, V, k, cnt, c0 + 1),
+                                    image_dword<T>(B, V, k, cnt, c0 + 2), image_dword<T>(B, V, k, cnt, c0 + 3));
     }
   }
 }

@@ -339,13 +339,15 @@ def test_rkmeans_chain(eng, seed, hash_slots):
         np.testing.assert_array_equal(x["count"], y["count"])
 
 
-@pytest.mark.parametrize("n_weather_dates", [300, 7])
-def test_view_build_large_and_small_relations(eng, n_weather_dates):
+@pytest.mark.parametrize("n_weather_dates, precision", [(300, "f32"), (300, "f64"), (7, "f32")])
+def test_view_build_large_and_small_relations(eng, n_weather_dates, precision):
     # Weather over 260 x n_weather_dates (locn, date) keys: 78,000 rows take
-    # the thread-per-row view build, 1,820 the thread-per-element one
+    # the thread-per-row view build (16-byte stores of 8 values and 2 codes),
+    # 1,820 the thread-per-element one
     p = W.retail_snowflake(seed=9, n_inv=150_001, n_locn=260, n_dates=min(12, n_weather_dates),
                            n_ksn=300, n_weather_dates=n_weather_dates)
-    check(eng, p, F32_TOL, f"view build, Weather {260 * n_weather_dates} rows", precision="f32", policy="fact")
+    check(eng, p, F32_TOL if precision == "f32" else F64_TOL,
+          f"view build, Weather {260 * n_weather_dates} rows, {precision}", precision=precision, policy="fact")
 
 
 def test_register_histograms_with_multiplicities(eng):
