@@ -38,7 +38,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["materialize_join", "evaluate", "evaluate_query", "evaluate_single",
-           "OPS"]
+           "evaluate_view", "subtree", "OPS"]
 
 OPS = {
     "<=": np.less_equal, "<": np.less, ">": np.greater, ">=": np.greater_equal,
@@ -204,3 +204,72 @@ def evaluate_single(problem: dict, qi: int, ai: int) -> dict:
     q["aggs"] = [q["aggs"][ai]]
     sub = dict(problem, batch=[q])
     return evaluate(sub)[0]
+
+
+def subtree(problem: dict, from_rel: str, to_rel: str) -> list:
+    """Relations on the ``from_rel`` side of the join-tree edge (from_rel,
+    to_rel): those reached from ``from_rel`` without crossing that edge."""
+    names = [r["name"] for r in problem["schema"]]
+    a, b = names.index(from_rel), names.index(to_rel)
+    adj = {i: set() for i in range(len(names))}
+    for u, v in problem["tree"]:
+        adj[u].add(v)
+        adj[v].add(u)
+    if b not in adj[a]:
+        raise ValueError(f"{from_rel} and {to_rel} are not adjacent in the join tree")
+    seen, stack = [a], [a]
+    while stack:
+        u = stack.pop()
+        for v in sorted(adj[u]):
+            if v not in seen and not (u == a and v == b):
+                seen.append(v)
+                stack.append(v)
+    return [names[i] for i in seen]
+
+
+def evaluate_view(problem: dict, from_rel: str, to_rel: str, key, aggs, carried=(), where=()) -> dict:
+    """A view along the join-tree edge from ``from_rel`` to ``to_rel``
+    (section 2, view generation layer: the view computes, over the join of
+    the relations below the edge, the partial aggregates the queries above it
+    need, grouped by the edge's join attributes).
+
+    Plain definition: D_S = the natural join of the relations in the subtree
+    of ``from_rel`` (bag semantics, as ``materialize_join``); the result is
+    ``evaluate_query`` of ``SELECT key, SUM(aggs) FROM D_S WHERE where GROUP
+    BY key``.  ``carried`` attributes must be functions of the key within D_S
+    (a view that carries a group-by attribute up the tree); their value per
+    group is returned in ``codes`` (groups x |carried|, int64), and a key
+    whose tuples disagree on one raises ``ValueError``."""
+    names = subtree(problem, from_rel, to_rel)
+    order = {n: i for i, n in enumerate(names)}
+    idx = {r["name"]: i for i, r in enumerate(problem["schema"])}
+    sub = {
+        "schema": [problem["schema"][idx[n]] for n in names],
+        "data": {n: problem["data"][n] for n in names},
+        "tree": [(order[problem["schema"][u]["name"]], order[problem["schema"][v]["name"]])
+                 for u, v in problem["tree"]
+                 if problem["schema"][u]["name"] in order and problem["schema"][v]["name"] in order],
+    }
+    needed = set(key) | set(carried) | {w[0] for w in where}
+    for f in aggs:
+        needed |= {a for a, _ in f}
+    D = materialize_join(sub, needed)
+    res = evaluate_query(D, {"groupby": list(key), "where": list(where), "aggs": list(aggs)})
+    n = len(next(iter(D.values()))) if D else 0
+    sel = _mask(D, list(where), n)
+    codes = np.zeros((res["keys"].shape[0], len(carried)), dtype=np.int64)
+    if carried and len(res["keys"]):
+        kc = np.stack([D[k][sel].astype(np.int64) for k in key], axis=1)
+        _, inv = np.unique(kc, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        for j, c in enumerate(carried):
+            v = D[c][sel].astype(np.int64)
+            lo = np.full(len(res["keys"]), np.iinfo(np.int64).max)
+            hi = np.full(len(res["keys"]), np.iinfo(np.int64).min)
+            np.minimum.at(lo, inv, v)
+            np.maximum.at(hi, inv, v)
+            if np.any(lo != hi):
+                raise ValueError(f"carried attribute {c} is not a function of the key {list(key)}")
+            codes[:, j] = lo
+    res["codes"] = codes
+    return res

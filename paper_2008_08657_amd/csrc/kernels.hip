@@ -2203,6 +2203,45 @@ void launch_count_copy(const DCountCopy* d, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_count_copy, dim3((int)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s, d);
 }
 
+// largest count of each listed view (grid-stride, one atomicMax per block)
+__global__ void k_mult_max(const DMultCheck* __restrict__ D) {
+  __shared__ unsigned long long red[4];
+  for (int v = 0; v < D->n; ++v) {
+    unsigned long long m = 0;
+    const int64_t* c = D->cnt[v];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < D->n_keys[v];
+         i += (int64_t)gridDim.x * blockDim.x)
+      m = max(m, (unsigned long long)max<int64_t>(c[i], 0));
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, red[w]);
+      if (m) atomicMax(&D->maxv[v], m);
+    }
+    __syncthreads();
+  }
+}
+
+// rows x product of the largest multiplicities against 2^31 - 1; resets maxv
+__global__ void k_mult_verdict(const DMultCheck* __restrict__ D) {
+  if (threadIdx.x != 0) return;
+  double prod = D->rows;
+  for (int v = 0; v < D->n; ++v) {
+    const unsigned long long m = D->maxv[v];
+    prod *= (double)(m ? m : 1ull);
+    D->maxv[v] = 0;
+  }
+  if (prod > 2147483647.0) atomicOr(D->err_flag, 16);
+}
+
+void launch_mult_check(const DMultCheck* d, const DMultCheck& h, hipStream_t s) {
+  int64_t most = 1;
+  for (int v = 0; v < h.n; ++v) most = std::max(most, h.n_keys[v]);
+  hipLaunchKernelGGL(k_mult_max, dim3((int)std::min<int64_t>((most + 255) / 256, 1024)), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_mult_verdict, dim3(1), dim3(64), 0, s, d);
+}
+
 void launch_table_reduce(const DTableReduce* d, int64_t n, int n_blocks, hipStream_t s) {
   if (n <= 0) return;
   const int gy = std::max(1, (n_blocks + kReduceSlice - 1) / kReduceSlice);

@@ -80,6 +80,22 @@ struct DTableReduce {
   int32_t copy_comp[kMaxTableComps];
 };
 
+// Range check of the 32-bit multiplicities a scan sums: the largest count of
+// each multi-valued view the scan looks up, times the most rows one workgroup
+// of the scan sums into one 32-bit counter, must stay below 2^31 (else error
+// bit 16).  `maxv` holds one zero-initialised slot per view; the check resets
+// it, so every run starts from zero without a memset.
+struct DMultCheck {
+  int32_t n;
+  int32_t pad;
+  const int64_t* cnt[kMaxViews];
+  int64_t n_keys[kMaxViews];
+  double rows;
+  unsigned long long* maxv;
+  int32_t* err_flag;
+};
+void launch_mult_check(const DMultCheck* d, const DMultCheck& h, hipStream_t s);
+
 void launch_fill(void* p, int64_t bytes, hipStream_t s);
 void launch_filter(const DFilter* d, int64_t n_rows, hipStream_t s);
 void launch_bucketize(const void* src, int dtype, int64_t n, const double* thr, int n_thr, int kind, int32_t* out,

@@ -20,6 +20,7 @@
 //     Figure 3 pushed past the inner loops).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <iterator>
 #include <tuple>
 #include <cstring>
@@ -1433,7 +1434,13 @@ static std::string describe(const Plan& P) {
     if (i) o << ",";
     o << "{\"name\":\"" << json_escape(P.attrs[D.attr].name) << "\",\"source\":\""
       << json_escape(P.attrs[D.src].name) << "\",\"relation\":\"" << json_escape(P.rels[D.rel].name)
-      << "\",\"kind\":" << D.kind << ",\"thresholds\":" << D.thr.size() << "}";
+      << "\",\"kind\":" << D.kind << ",\"thresholds\":" << D.thr.size() << ",\"threshold_values\":[";
+    for (size_t t = 0; t < D.thr.size(); ++t) {
+      char num[64];
+      std::snprintf(num, sizeof num, "%.17g", D.thr[t]);
+      o << (t ? "," : "") << num;
+    }
+    o << "]}";
   }
   o << "],\"user_queries\":[";
   for (size_t i = 0; i < P.user.size(); ++i) {
@@ -1463,6 +1470,31 @@ static std::string describe(const Plan& P) {
       if (!first) o << ",";
       first = false;
       o << d;
+    }
+    // physical layout: the value columns and code columns lmfao_view_copy
+    // returns per dense key (last key attribute fastest), and the conditions
+    // pushed into the view
+    o << "],\"n_keys\":" << V.n_keys << ",\"stored_values\":[";
+    first = true;
+    if (V.unique) {
+      for (int a : V.val_attrs) {
+        if (!first) o << ",";
+        first = false;
+        o << "\"" << json_escape(P.attrs[a].name) << "\"";
+      }
+    } else {
+      for (auto& m : V.val_monos) {
+        if (!first) o << ",";
+        first = false;
+        o << "\"" << json_escape(mono_str(P, m)) << "\"";
+      }
+    }
+    o << "],\"stored_codes\":" << attrs_json(V.code_attrs) << ",\"conditions\":[";
+    for (size_t c = 0; c < V.conds.size(); ++c) {
+      if (c) o << ",";
+      char num[64];
+      std::snprintf(num, sizeof num, "%.17g", V.conds[c].c);
+      o << "[\"" << json_escape(P.attrs[V.conds[c].attr].name) << "\"," << V.conds[c].op << "," << num << "]";
     }
     o << "]}";
   }

@@ -71,6 +71,7 @@ struct NodeData {
   int32_t* piece_key = nullptr;
   int32_t* item_piece = nullptr;
   int n_items = 0;
+  int64_t max_item_rows = 0;       // rows of the longest work item
   int cut = 0;
   uint32_t* perm = nullptr;        // sort permutation, kept until prepare ends
   std::vector<void*> typed_col;    // sorted copies in the compute type (factor columns of lean scans)
@@ -85,7 +86,7 @@ struct Step {
   void* dev2 = nullptr;             // second descriptor (fused contraction: the product's)
   int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract (VALU), 5 merge, 6 image build,
               // 7 (unused), 8 MFMA contraction, 9 block-major merge, 10 filter, 11 finalize,
-              // 12 row-by-row scatter, 13 count copy
+              // 12 row-by-row scatter, 13 count copy, 14 multiplicity range check
   int fast = 0;
   void* dev = nullptr;
   int64_t n = 0;
@@ -96,6 +97,7 @@ struct Step {
   const double* part_f = nullptr;
   const int64_t* part_i = nullptr;
   int n_blocks = 0, NF = 0, NG = 0, NFI = 0, NGI = 0;
+  DMultCheck mult{};                // kind 14: host copy of the descriptor
   // accounting (host-computed): bytes the step must move, arithmetic it must do
   double alg_read = 0, alg_write = 0, alg_flop = 0;
   int64_t rows = 0, pieces = 0;
@@ -350,6 +352,9 @@ static void prepare_node(Prep& S, int r, int cut, const std::vector<int>& need_c
     }
     if (items.back() != (int32_t)N.n_pieces) items.push_back((int32_t)N.n_pieces);
     N.n_items = (int)items.size() - 1;
+    N.max_item_rows = 0;
+    for (int i = 0; i < N.n_items; ++i)
+      N.max_item_rows = std::max<int64_t>(N.max_item_rows, pb[items[i + 1]] - pb[items[i]]);
     N.piece_begin = upload_vec(S, pb, st);
     std::vector<int32_t> flat;
     for (int l = 0; l < cut; ++l) flat.insert(flat.end(), pk[l].begin(), pk[l].end());
@@ -1012,6 +1017,31 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
     }
     int lds = builtin ? scan_fast_lds_bytes(d, f64) : scan_lds_bytes(d, f64);
     if (lds > 160 * 1024) throw PlanError{LMFAO_EUNSUPPORTED, "scan needs more LDS than a CU has"};
+    {
+      // multiplicities of multi-valued views reach the scan's 32-bit counters
+      // (per-piece counts, LDS tables summed per workgroup, image records):
+      // check their range on the device before the scan
+      DMultCheck mc{};
+      for (int vid : g.views)
+        if (!P.views[vid].unique && mc.n < kMaxViews) {
+          mc.cnt[mc.n] = S.vout[vid].cnt;
+          mc.n_keys[mc.n] = S.vout[vid].n_rows;
+          mc.n++;
+        }
+      if (mc.n) {
+        const int64_t per_block = (N.n_items + (int64_t)grid * waves - 1) / ((int64_t)grid * waves);
+        mc.rows = (double)std::min<int64_t>(R.n_rows, per_block * waves * std::max<int64_t>(N.max_item_rows, 1));
+        mc.maxv = (unsigned long long*)dalloc(S, kMaxViews * 8);
+        HIP_OK(hipMemsetAsync(mc.maxv, 0, kMaxViews * 8, st));
+        mc.err_flag = S.err_flag;
+        Step m;
+        m.name = gname + ":mult_check";
+        m.kind = 14;
+        m.dev = upload(S, mc, st);
+        m.mult = mc;
+        S.steps.push_back(m);
+      }
+    }
     Step s;
     s.name = gname + ":scan";
     s.kind = 2;
@@ -1473,20 +1503,28 @@ static double estimate_log2_groups(const std::vector<float>& blob, const float* 
 // ones are reached by regrowth when the groups are really there
 constexpr int64_t kHashInitSlots = (int64_t)1 << 26;
 
-// (re)allocates the slots of a hash table; old slots are released
-static void alloc_hash(Prep& S, HashBuf& H) {
+// (re)allocates the slots of a hash table for H.cap slots.  The new arrays
+// are allocated first; the old ones are released only once all three exist,
+// so a failed allocation leaves the table as it was (H.cap restored) and
+// throws PlanError{LMFAO_ENOMEM}.
+static void alloc_hash(Prep& S, HashBuf& H, int64_t old_cap = 0) {
+  void* fresh[3] = {nullptr, nullptr, nullptr};
+  const size_t bytes[3] = {(size_t)H.cap * 8, (size_t)H.cap * 8, (size_t)H.cap * 8 * std::max(1, H.n_vals)};
+  for (int i = 0; i < 3; ++i) {
+    hipError_t e = hipMalloc(&fresh[i], std::max<size_t>(bytes[i], 8));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      for (int j = 0; j < i; ++j) (void)hipFree(fresh[j]);
+      const int64_t want = H.cap;
+      if (old_cap) H.cap = old_cap;
+      throw PlanError{LMFAO_ENOMEM, "hash table of " + std::to_string(want) + " slots: " + hipGetErrorString(e)};
+    }
+  }
   for (void* p : {(void*)H.keys, (void*)H.cnt, (void*)H.vals})
     if (p) (void)hipFree(p);
-  auto get = [&](size_t bytes) {
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 8));
-    if (e != hipSuccess) throw PlanError{LMFAO_ENOMEM, "hash table of " + std::to_string(H.cap) + " slots: " +
-                                                        hipGetErrorString(e)};
-    return p;
-  };
-  H.keys = (unsigned long long*)get(H.cap * 8);
-  H.cnt = (int64_t*)get(H.cap * 8);
-  H.vals = (double*)get(H.cap * 8 * std::max(1, H.n_vals));
+  H.keys = (unsigned long long*)fresh[0];
+  H.cnt = (int64_t*)fresh[1];
+  H.vals = (double*)fresh[2];
 }
 
 static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_t st) {
@@ -1761,6 +1799,7 @@ static void enqueue_run(Prep& S, hipStream_t st) {
         launch_scatter_rows((const DContract*)s.dev, S.f64, s.grid, st);
         break;
       case 13: launch_count_copy((const DCountCopy*)s.dev, s.n, st); break;
+      case 14: launch_mult_check((const DMultCheck*)s.dev, s.mult, st); break;
       case 8:
         launch_contract_fused((const DContract*)s.dev, (const DGemm*)s.dev2, S.f64,
                               S.P->opts.precision == LMFAO_PREC_BF16X3   ? 3
@@ -1903,8 +1942,9 @@ static bool grow_hashes(Prep& S, hipStream_t st) {
     int64_t top = 1;
     while (top < 2 * H.bound) top <<= 1;
     if (H.cap >= std::max<int64_t>(top, 1024)) return false;
+    const int64_t old_cap = H.cap;
     H.cap = std::min(H.cap * 4, std::max<int64_t>(top, 1024));
-    alloc_hash(S, H);
+    alloc_hash(S, H, old_cap);
     S.steps[H.fill_step].dev = H.keys;
     S.steps[H.fill_step].bytes = H.cap * 8;
     S.steps[H.fill_step + 1].dev = H.cnt;
@@ -1961,6 +2001,18 @@ static void drop_graph(Prep& S) {
   S.graph_exec = nullptr;
 }
 
+static lmfao_status flag_status(int32_t flag) {
+  if (flag & 1) return set_err(LMFAO_EINVAL, "a relation has duplicate values of its declared primary key");
+  if (flag & 2) return set_err(LMFAO_EINVAL, "an integer column holds a value outside its declared domain");
+  if (flag & 4)
+    return set_err(LMFAO_EOVERFLOW, "an integer aggregate reached 2^53 in the FP64 matrix-core contraction "
+                                    "(use the VALU contraction)");
+  if (flag & 16)
+    return set_err(LMFAO_EOVERFLOW, "a join multiplicity times the rows a scan block sums exceeds the range of "
+                                    "the scan's 32-bit counters");
+  return LMFAO_OK;
+}
+
 lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, int32_t sync) {
   g_last_error.clear();
   if (!plan || !prep || prep->P != plan->P) return set_err(LMFAO_EINVAL, "plan and prepared handle do not match");
@@ -1981,16 +2033,33 @@ lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, i
         HIP_OK(hipStreamSynchronize(st));
         HIP_OK(hipMemcpy(&flag, prep->err_flag, 4, hipMemcpyDeviceToHost));
       }
-      if (flag & 1) return set_err(LMFAO_EINVAL, "a relation has duplicate values of its declared primary key");
-      if (flag & 2) return set_err(LMFAO_EINVAL, "an integer column holds a value outside its declared domain");
-      if (flag & 4)
-        return set_err(LMFAO_EOVERFLOW, "an integer aggregate reached 2^53 in the FP64 matrix-core contraction "
-                                        "(use the VALU contraction)");
+      lmfao_status fs = flag_status(flag);
+      if (fs) return fs;
     }
+  } catch (const PlanError& e) {
+    // a hash table that could not be regrown: the status names the cause
+    return set_err(e.status == LMFAO_ENOMEM ? LMFAO_EOVERFLOW : e.status, e.msg);
   } catch (const HipError& e) {
     return set_err(LMFAO_EHIP, e.msg);
   }
   return LMFAO_OK;
+}
+
+// The error bits the kernels of a run set, read after the run completed:
+// 1 duplicate primary key, 2 a value outside its declared domain, 4 an
+// integer cell reached 2^53 in the FP64 matrix-core contraction, 8 a hash
+// table overflowed (regrown by a run with sync), 16 a join multiplicity that
+// the scan's 32-bit counters cannot hold.
+static lmfao_status read_flags(const lmfao_prepared_s* prep) {
+  int32_t flag = 0;
+  try {
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(&flag, prep->err_flag, 4, hipMemcpyDeviceToHost));
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  if (flag & 8) return set_err(LMFAO_EOVERFLOW, "a hash table overflowed in the last run (run with sync)");
+  return flag_status(flag);
 }
 
 // dense image of a hashed output: rows with their counts and values, in row order
@@ -2003,11 +2072,8 @@ static lmfao_status gather_hash(const lmfao_prepared_s* prep, const OutBuf& B, G
   std::vector<unsigned long long> keys(H.cap);
   std::vector<int64_t> cnt(H.cap);
   std::vector<double> vals((size_t)H.cap * std::max(1, H.n_vals));
+  if (lmfao_status fs = read_flags(prep)) return fs;
   try {
-    int32_t flag = 0;
-    HIP_OK(hipDeviceSynchronize());
-    HIP_OK(hipMemcpy(&flag, prep->err_flag, 4, hipMemcpyDeviceToHost));
-    if (flag & 8) return set_err(LMFAO_EOVERFLOW, "a hash table overflowed in the last run (run with sync)");
     HIP_OK(hipMemcpy(keys.data(), H.keys, H.cap * 8, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(cnt.data(), H.cnt, H.cap * 8, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(vals.data(), H.vals, vals.size() * 8, hipMemcpyDeviceToHost));
@@ -2052,9 +2118,9 @@ lmfao_status lmfao_result_shape(lmfao_prepared_t prep, int32_t q, int64_t* n_gro
     if (st) return st;
     g = (int64_t)gh.rows.size();
   } else {
+    if (lmfao_status fs = read_flags(prep)) return fs;
     std::vector<int64_t> cnt(B.n_rows);
     try {
-      HIP_OK(hipDeviceSynchronize());
       HIP_OK(hipMemcpy(cnt.data(), B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
     } catch (const HipError& e) {
       return set_err(LMFAO_EHIP, e.msg);
@@ -2094,10 +2160,10 @@ lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, 
     for (size_t i = 0; i < gh.rows.size(); ++i) emit((int64_t)i, gh.rows[i], gh.cnt[i], gh.vals.data() + i * B.n_vals);
     return LMFAO_OK;
   }
+  if (lmfao_status fs = read_flags(prep)) return fs;
   std::vector<int64_t> cnt(B.n_rows);
   std::vector<double> vals((size_t)B.n_rows * B.n_vals);
   try {
-    HIP_OK(hipDeviceSynchronize());
     HIP_OK(hipMemcpy(cnt.data(), B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
     if (!vals.empty()) HIP_OK(hipMemcpy(vals.data(), B.vals, vals.size() * 8, hipMemcpyDeviceToHost));
   } catch (const HipError& e) {
@@ -2238,8 +2304,8 @@ lmfao_status lmfao_view_shape(lmfao_prepared_t prep, int32_t v, int64_t* n_keys,
 lmfao_status lmfao_view_copy(lmfao_prepared_t prep, int32_t v, int64_t* counts, double* values, int32_t* codes) {
   if (!prep || v < 0 || v >= (int)prep->vout.size()) return set_err(LMFAO_EINVAL, "bad view index");
   const OutBuf& B = prep->vout[v];
+  if (lmfao_status fs = read_flags(prep)) return fs;
   try {
-    HIP_OK(hipDeviceSynchronize());
     if (counts) HIP_OK(hipMemcpy(counts, B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
     if (values && B.n_vals) {
       size_t n = (size_t)B.n_rows * B.n_vals;
@@ -2336,8 +2402,8 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     first = false;
     static const char* kinds[] = {"fill",  "view_build", "scan",     "table_reduce", "contract", "merge",
                                   "image", "stage",      "contract", "merge",        "filter",   "finalize",
-                                  "scatter", "count_copy"};
-    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 14, "one name per step kind");
+                                  "scatter", "count_copy", "mult_check"};
+    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 15, "one name per step kind");
     char tmp[512];
     snprintf(tmp, sizeof(tmp),
              "{\"name\":\"%s\",\"kind\":\"%s\",\"rows\":%lld,\"pieces\":%lld,\"alg_read_bytes\":%.0f,"

@@ -59,6 +59,62 @@ def test_adam_first_step_is_sign_times_lr():
         np.testing.assert_allclose((before[k] - p[k])[nz], 0.01 * np.sign(g[k][nz]), rtol=1e-12)
 
 
+def _unit_params(val):
+    return {k: np.full(sh, val, dtype=np.float64) for k, sh in
+            (("W1", (1, 1)), ("b1", (1,)), ("W2", (1, 1)), ("b2", (1,)), ("w3", (1,)), ("b3", (1,)))}
+
+
+def test_adam_steps_two_and_three_hand_computed():
+    # gradients +g, -g, +g on every parameter (beta1 = 0.9, beta2 = 0.999,
+    # eps = 0).  By hand:
+    #   t=1: m = 0.1 g,               v = 0.001 g^2,
+    #        m/(1-0.9)   = g,          v/(1-0.999)   = g^2     -> step  lr
+    #   t=2: m = 0.09 g - 0.1 g = -0.01 g,   v = 0.000999 g^2 + 0.001 g^2 = 0.001999 g^2
+    #        m/(1-0.81)  = -g/19,      v/(1-0.998001) = g^2    -> step -lr/19
+    #   t=3: m = -0.009 g + 0.1 g = 0.091 g, v = 0.001997001 g^2 + 0.001 g^2 = 0.002997001 g^2
+    #        m/(1-0.729) = 91 g/271,   v/(1-0.997002999) = g^2 -> step 91 lr/271
+    # (steps are in the direction of sign(g) and are subtracted).
+    lr, g0 = 0.01, 0.37
+    p = _unit_params(1.0)
+    st = {}
+    want = 1.0
+    for t, (sgn, step) in enumerate(((1, 1.0), (-1, -1.0 / 19.0), (1, 91.0 / 271.0)), start=1):
+        g = _unit_params(sgn * g0)
+        mlp.adam_step(p, g, st, lr=lr, eps=0.0)
+        want -= lr * step
+        for k in mlp.ORDER:
+            np.testing.assert_allclose(p[k], want, rtol=0, atol=1e-15, err_msg=f"t={t} {k}")
+    assert st["t"] == 3
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    # with a constant gradient the bias-corrected moments equal g and g^2 at
+    # every t, so each step is exactly lr * sign(g); a bias correction with a
+    # wrong t, or moments not carried over, breaks this from t = 2 on
+    p = _unit_params(0.0)
+    st = {}
+    for t in range(1, 6):
+        mlp.adam_step(p, _unit_params(-2.5), st, lr=0.125, eps=0.0)
+        for k in mlp.ORDER:
+            np.testing.assert_allclose(p[k], 0.125 * t, rtol=1e-13)
+
+
+def test_planted_adam_without_moment_carry_is_caught(monkeypatch):
+    real = mlp.adam_step
+
+    def forgetful(p, g, state, **kw):   # moments reset every step
+        for k in list(state):
+            if k != "t":
+                del state[k]
+        return real(p, g, state, **kw)
+
+    p = _unit_params(1.0)
+    st = {}
+    for sgn in (1, -1):
+        forgetful(p, _unit_params(sgn * 0.37), st, lr=0.01, eps=0.0)
+    assert not np.allclose(p["W1"], 1.0 - 0.01 + 0.01 / 19.0, rtol=0, atol=1e-15)
+
+
 def test_training_fits_a_smooth_target():
     rng = np.random.default_rng(5)
     X = rng.uniform(-1, 1, (256, 3))

@@ -12,13 +12,20 @@ operand swap) fails at least one of them:
   (numpy matmul), a group-by on a key equals ``numpy.bincount``, a foreign-key
   two-relation join equals fancy indexing;
 * invariants: group marginals add up to the ungrouped aggregate, SUM(a*b)
-  equals SUM(b*a).
+  equals SUM(b*a); a view's counts times the opposite view's counts, summed
+  over the edge key, give |D| (a join tree factorises COUNT at every edge).
+
+Conditions in the brute force are evaluated with Python's own scalar
+comparison operators (``operator.le`` and so on), never with the oracle's
+``OPS`` table, and a float32 column compares against the constant rounded to
+float32 (the oracle's stated reading).
 
 The planted-mistake tests at the end patch the oracle on the CPU and check that
 the pins notice.
 """
 import itertools
 import math
+import operator
 
 import numpy as np
 import pytest
@@ -27,12 +34,28 @@ import oracle
 import workloads as W
 
 
-def brute_force(problem, qi):
-    """Reference by enumeration: sum over all tuple combinations that agree on
-    every shared attribute name."""
-    rels = problem["schema"]
+PY_OPS = {"<=": operator.le, "<": operator.lt, ">": operator.gt, ">=": operator.ge,
+          "==": operator.eq, "!=": operator.ne}
+
+
+def _py_const(problem, attr, c):
+    """The constant as the brute force compares it: rounded to float32 for a
+    float32 column, else a Python float / int."""
+    for r in problem["schema"]:
+        for a in r["attrs"]:
+            if a["name"] == attr and a["dtype"] == "f32":
+                return float(np.float32(c))
+    return c
+
+
+def brute_force(problem, qi=None, rels=None, query=None):
+    """Reference by enumeration: sum over all tuple combinations (of the
+    relations named in ``rels``, default all) that agree on every shared
+    attribute name."""
+    rels = [r for r in problem["schema"] if rels is None or r["name"] in rels]
     data = problem["data"]
-    q = problem["batch"][qi]
+    q = problem["batch"][qi] if query is None else query
+    where = [(a, PY_OPS[op], _py_const(problem, a, c)) for a, op, c in q.get("where", [])]
     groups = {}
     ranges = [range(r["n_rows"]) for r in rels]
     for combo in itertools.product(*ranges):
@@ -50,7 +73,7 @@ def brute_force(problem, qi):
                 break
         if not ok:
             continue
-        if not all(oracle.OPS[op](tup[a], c) for a, op, c in q.get("where", [])):
+        if not all(cmp(tup[a], c) for a, cmp, c in where):
             continue
         g = tuple(tup[a] for a in q.get("groupby", []))
         slot = groups.setdefault(g, [0, [[] for _ in q["aggs"]]])
@@ -89,6 +112,46 @@ def test_brute_force_random_foreign_keys(seed):
 def test_brute_force_with_predicates():
     p = W.random_acyclic(7, n_rel=3, max_rows=6, max_dom=3)
     p["batch"] = [dict(q, where=[("x0", "<=", 0.1), ("c1", "!=", 1)]) for q in p["batch"]]
+    assert_matches_brute(p)
+
+
+def _operator_problem(seed):
+    """A random join whose batch exercises all six comparison operators, on a
+    float and an integer attribute, with constants equal to values the data
+    holds (so that < and <=, > and >= select different tuples)."""
+    p = W.random_acyclic(seed, n_rel=3, max_rows=6, max_dom=3)
+    x0 = p["data"]["R0"]["x0"]
+    c1 = p["data"]["R1"]["c1"]
+    tx = float(np.sort(x0)[len(x0) // 2])
+    tc = int(c1[0])
+    batch = []
+    for op in ("<=", "<", ">", ">=", "==", "!="):
+        for q in p["batch"][:2]:
+            batch.append(dict(q, where=[("x0", op, tx)]))
+            batch.append(dict(q, where=[("c1", op, tc)]))
+    p["batch"] = batch
+    return p
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_brute_force_all_comparison_operators(seed):
+    assert_matches_brute(_operator_problem(seed))
+
+
+def test_float32_condition_compares_in_float32():
+    # a constant between two float32 neighbours: in float32 it rounds onto the
+    # data value, in float64 it lies above it
+    v = np.float32(0.1)
+    c = float(v) + 1e-12
+    schema = [{"name": "R", "n_rows": 3, "attrs": [
+        {"name": "x", "dtype": "f32", "domain": 0, "key": False}]}]
+    data = {"R": {"x": np.array([v, np.float32(0.5), np.float32(-1)], dtype=np.float32)}}
+    batch = [{"groupby": [], "where": [("x", "<", c)], "aggs": [[]], "root": None},
+             {"groupby": [], "where": [("x", "==", c)], "aggs": [[]], "root": None}]
+    p = {"schema": schema, "tree": [], "batch": batch, "data": data}
+    res = oracle.evaluate(p)
+    assert res[0]["count"].tolist() == [1]      # only -1 < 0.1f
+    assert res[1]["count"].tolist() == [1]      # 0.1f == round_f32(c)
     assert_matches_brute(p)
 
 
@@ -236,3 +299,92 @@ def test_planted_wrong_group_key_is_caught(monkeypatch):
     cat = it["cat"][p["data"]["S"]["item"]]
     cnt = np.bincount(cat, minlength=20)
     assert r1["count"].tolist() != cnt[np.nonzero(cnt)[0]].tolist()
+
+
+def test_planted_operator_swap_is_caught(monkeypatch):
+    # < evaluated as <= : every pin that goes through the oracle's own OPS
+    # table would still pass; the brute force's scalar operators do not
+    monkeypatch.setitem(oracle.OPS, "<", np.less_equal)
+    assert any(_brute_mismatch(_operator_problem(seed)) for seed in range(4))
+
+
+def test_planted_ge_as_gt_is_caught(monkeypatch):
+    monkeypatch.setitem(oracle.OPS, ">=", np.greater)
+    assert any(_brute_mismatch(_operator_problem(seed)) for seed in range(4))
+
+
+# ---------------------------------------------------------------------------
+# views: the join of the subtree below an edge, grouped by the edge key
+# ---------------------------------------------------------------------------
+
+def _edge_views(problem, u, v, aggs, where=()):
+    nu, nv = problem["schema"][u]["name"], problem["schema"][v]["name"]
+    key = sorted({a["name"] for a in problem["schema"][u]["attrs"]}
+                 & {a["name"] for a in problem["schema"][v]["attrs"]})
+    return nu, nv, key
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_view_matches_brute_force_over_the_subtree(seed):
+    p = W.random_acyclic(200 + seed, n_rel=4, max_rows=5, max_dom=3)
+    for u, v in p["tree"]:
+        for a, b in ((u, v), (v, u)):
+            na, nb, key = _edge_views(p, a, b, [])
+            sub = oracle.subtree(p, na, nb)
+            feats = [f"x{int(r[1:])}" for r in sub]
+            aggs = [[], [(feats[0], 1)], [(feats[-1], 2)], [(feats[0], 1), (feats[-1], 1)]]
+            r = oracle.evaluate_view(p, na, nb, key, aggs)
+            keys, counts, sums = brute_force(p, rels=sub, query={"groupby": key, "aggs": aggs})
+            assert [tuple(int(x) for x in k) for k in r["keys"]] == keys
+            assert r["count"].tolist() == counts
+            if keys:
+                np.testing.assert_allclose(r["sum"], np.array(sums), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_views_factorise_count_at_every_edge(seed):
+    # for an edge (u, v) of a join tree with join attributes K,
+    # |D| = sum over k of |D_u(k)| * |D_v(k)|: every tuple of D is one tuple of
+    # the u side and one of the v side that agree on K
+    p = W.random_acyclic(300 + seed, n_rel=4, max_rows=6, max_dom=3)
+    total = oracle.evaluate(dict(p, batch=[{"groupby": [], "where": [], "aggs": [[]], "root": None}]))[0]
+    n_d = int(total["count"].sum())
+    for u, v in p["tree"]:
+        nu, nv, key = _edge_views(p, u, v, [])
+        a = oracle.evaluate_view(p, nu, nv, key, [[]])
+        b = oracle.evaluate_view(p, nv, nu, key, [[]])
+        ca = {tuple(k): c for k, c in zip(a["keys"].tolist(), a["count"].tolist())}
+        cb = {tuple(k): c for k, c in zip(b["keys"].tolist(), b["count"].tolist())}
+        assert sum(ca[k] * cb.get(k, 0) for k in ca) == n_d
+
+
+def test_view_carried_attribute_and_condition():
+    # a foreign-key dimension: the view of Items toward S carries cat, which
+    # is a function of the key item
+    p = W.tiny_star(seed=2, n_fact=500, n_stores=5, n_items=30)
+    r = oracle.evaluate_view(p, "Items", "S", ["item"], [[("g1", 1)]], carried=["cat"],
+                             where=[("g2", ">", 0.0)])
+    it = p["data"]["Items"]
+    keep = it["g2"] > 0
+    assert r["keys"][:, 0].tolist() == np.nonzero(keep)[0].tolist()
+    assert r["codes"][:, 0].tolist() == it["cat"][keep].tolist()
+    np.testing.assert_array_equal(r["sum"][:, 0], it["g1"][keep])
+    assert r["count"].tolist() == [1] * int(keep.sum())
+
+
+def test_planted_wrong_subtree_side_is_caught(monkeypatch):
+    real = oracle.subtree
+
+    def flipped(problem, a, b):   # the other side of the edge
+        return real(problem, b, a)
+
+    monkeypatch.setattr(oracle, "subtree", flipped)
+    p = W.random_acyclic(201, n_rel=4, max_rows=5, max_dom=3)
+    caught = False
+    for u, v in p["tree"]:
+        na, nb, key = _edge_views(p, u, v, [])
+        r = oracle.evaluate_view(p, na, nb, key, [[]])
+        keys, counts, _ = brute_force(p, rels=real(p, na, nb), query={"groupby": key, "aggs": [[]]})
+        if [tuple(int(x) for x in k) for k in r["keys"]] != keys or r["count"].tolist() != counts:
+            caught = True
+    assert caught
