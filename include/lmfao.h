@@ -26,8 +26,13 @@
  *   - at most 2 group-by attributes per query, each an integer attribute with
  *     a domain hint (values in [0, domain));
  *   - every join attribute is an integer attribute with a domain hint;
- *   - conditions (WHERE) are accepted by the planner but not yet executed on
- *     the GPU (LMFAO_EUNSUPPORTED from lmfao_plan when present).
+ *   - conditions (WHERE) are conjunctions of `attr op constant`: the
+ *     conditions every query of the batch shares (a tree node's path
+ *     condition) filter the relations' rows at the start of every run, and
+ *     each query may add one more condition on a single attribute (a split
+ *     candidate), which is planned as a group-by on a bucket code of that
+ *     attribute and summed over the buckets it selects; a query with two or
+ *     more conditions of its own returns LMFAO_EUNSUPPORTED.
  *
  * Conventions for every entry point:
  *   - all pointers to schema, tree, batch and option structs are host

@@ -301,6 +301,9 @@ struct PlanError {
 Plan* build_plan(const lmfao_schema* schema, const lmfao_join_tree* tree,
                  const lmfao_batch* batch, const lmfao_options* opts);
 
+// sets the thread-local text lmfao_last_error() returns
+void record_error(const std::string& msg);
+
 std::vector<int> join_attrs(const Plan& P, int a, int b);
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,8 @@ namespace lmfao {
 
 static thread_local std::string g_last_error;
 
+void record_error(const std::string& msg) { g_last_error = msg; }
+
 struct HipError {
   std::string msg;
 };

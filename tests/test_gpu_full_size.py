@@ -1,86 +1,99 @@
-"""Parity at the benchmark's full size, in the launch configuration it times.
+"""Parity at the benchmark's full sizes, in the launch configuration it times.
 
-The retail-shaped snowflake (Inv 84M rows, 1,269 queries, FP32) runs exactly
-as the benchmark runs it: the same generator call, the same plan options, the
-warm-up run that captures the HIP graph, then graph replays.  The oracle cannot
-evaluate the whole batch at this size in reasonable time, so a seeded sample
-of outputs is compared instead: query 0 (COUNT and SUM(1) of the whole join),
-two further aggregates without group-by and one grouped query, each reduced
-to one aggregate, whole (every group), from one materialisation of the join
-over the columns they need.  Keys and counts must be identical, sums within
-the FP32 bound of the other parity tests.
+Each measured workload (``workloads.bench_workload``: the retail-shaped
+snowflake, the grocery-shaped star in BF16x3, the CART node batch and the
+Rk-means step-1 chain) runs exactly as ``bench.py`` runs it: the same
+generator call, the same plan options (``workloads.bench_plan_options``), a
+warm-up run that captures the HIP graph, then a graph replay.  EVERY output is
+compared with the expected results that ``tests/golden/make_full_size.py``
+wrote from the streaming tier-B oracle (the plain definition, enumerating the
+natural join on all host cores):
+
+* keys and counts identical, float sums within 1e-5 of
+  max(|oracle|, 1e-3 * sum |terms|);
+* outputs with too many groups to store (the chain's large integer
+  group-bys) by their group count, total count and a SHA-256 over the keys
+  and counts, which the GPU result must reproduce bit for bit.
+
+The golden files record the digest of the generated columns: a mismatch
+means the generator changed and the files must be written again.
 """
+import hashlib
+import json
+import os
 import time
 
 import numpy as np
 import pytest
 
-import oracle
 import workloads as W
 
 from parity import compare
 
 pytestmark = pytest.mark.gpu
 
-F32_TOL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-5
 
 
-def sampled_batch(batch, seed):
-    rng = np.random.default_rng(seed)
-    plain = [i for i, q in enumerate(batch) if i and not q["groupby"]]
-    grouped = [i for i, q in enumerate(batch) if q["groupby"]]
-    picks = [0] + sorted(rng.choice(plain, 2, replace=False).tolist()) + [int(rng.choice(grouped))]
-    out = []
-    for qi in picks:
-        ai = 0 if qi == 0 else int(rng.integers(len(batch[qi]["aggs"])))
-        out.append((qi, ai))
-    return out
+def load_golden(config):
+    z = np.load(os.path.join(GOLDEN, f"full_{config}.npz"), allow_pickle=False)
+    meta = json.loads(bytes(z["meta"]).decode())
+    return z, meta
 
 
-def test_retail_full_size_sampled():
+def result_digest(keys, count):
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(keys, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(count, dtype="<i8").tobytes())
+    return h.hexdigest()
+
+
+def check_against_golden(prep, problem, config):
+    z, meta = load_golden(config)
+    worst, digests = 0.0, 0
+    for qi, m in enumerate(meta["queries"]):
+        r = prep.result(qi)
+        where = f"{config} full size, query {qi}"
+        assert r["keys"].shape[0] == m["groups"], f"{where}: {r['keys'].shape[0]} groups, expected {m['groups']}"
+        assert int(r["count"].sum()) == m["total_count"], where
+        if m["stored"]:
+            ref = {"keys": z[f"q{qi}_keys"], "count": z[f"q{qi}_count"], "sum": z[f"q{qi}_sum"],
+                   "abs": z[f"q{qi}_abs"]}
+            worst = max(worst, compare(r, ref, TOL, where))
+        else:
+            assert result_digest(r["keys"], r["count"]) == m["sha256"], f"{where}: keys or counts differ"
+            aggs = problem["batch"][qi]["aggs"]
+            for k, f in enumerate(aggs):
+                if not f:   # SUM(1) equals the count exactly
+                    np.testing.assert_array_equal(r["sum"][:, k], r["count"].astype(np.float64), err_msg=where)
+            digests += 1
+    return worst, digests, len(meta["queries"])
+
+
+@pytest.mark.parametrize("config", ["retail", "grocery", "cart", "chain"])
+def test_full_size_every_output(config):
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_2008_08657_amd as E
     E.load_library()
     t0 = time.perf_counter()
-    bw = W.bench_workload("retail")
+    bw = W.bench_workload(config)
     problem = bw["problem"]
-    print(f"[full] retail generated in {time.perf_counter() - t0:.1f} s", flush=True)
-
-    plan = E.Plan(problem, precision=bw["precision"], policy=problem["policy"], form="fused",
-                  sizing=bw["sizing"], graph=True)
+    _, meta = load_golden(config)
+    assert W.problem_digest(problem) == meta["problem_digest"], \
+        f"the {config} generator changed: run tests/golden/make_full_size.py {config}"
+    print(f"[full] {config} generated in {time.perf_counter() - t0:.1f} s", flush=True)
+    plan = E.Plan(problem, **W.bench_plan_options(bw))
     cols = E.device_columns(problem)
     prep = E.Prepared(plan, cols)
     del cols
+    torch.cuda.empty_cache()
     prep.run(sync=False)          # warm-up: captures the graph
-    prep.run(sync=True)           # replay, error flags checked
-    assert prep.describe()["graph"]["captured"]
-    picks = sampled_batch(problem["batch"], seed=2008)
-    gpu = {}
-    for qi, ai in picks:
-        r = prep.result(qi)
-        gpu[qi] = {"keys": r["keys"], "count": r["count"], "sum": r["sum"][:, ai:ai + 1]}
+    prep.run(sync=True)           # a replay (or a run after a regrowth), error flags checked
+    t0 = time.perf_counter()
+    worst, digests, n = check_against_golden(prep, problem, config)
+    print(f"[full] {config}: {n} queries, {n - digests} compared cell by cell (worst scaled error {worst:.2e}), "
+          f"{digests} by digest; read back in {time.perf_counter() - t0:.1f} s", flush=True)
     del prep, plan
     torch.cuda.empty_cache()
-    print(f"[full] GPU run done; sampled (query, aggregate): {picks}", flush=True)
-
-    sub = []
-    needed = set()
-    for qi, ai in picks:
-        q = dict(problem["batch"][qi])
-        q["aggs"] = [q["aggs"][ai]]
-        sub.append(q)
-        needed |= set(q["groupby"]) | {w[0] for w in q["where"]} | {a for a, _ in q["aggs"][0]}
-    t0 = time.perf_counter()
-    D = oracle.materialize_join(problem, needed)
-    print(f"[full] oracle join materialised in {time.perf_counter() - t0:.1f} s", flush=True)
-
-    n_join = problem["schema"][0]["n_rows"]
-    for (qi, ai), q in zip(picks, sub):
-        t0 = time.perf_counter()
-        r = oracle.evaluate_query(D, q)
-        if qi == 0:
-            assert int(r["count"][0]) == n_join      # complete foreign keys: |D| = |Inv|
-        worst = compare(gpu[qi], r, F32_TOL, f"retail full size, query {qi} aggregate {ai}")
-        print(f"[full] query {qi} aggregate {ai}: {r['keys'].shape[0]} groups, worst scaled error {worst:.2e} "
-              f"(oracle {time.perf_counter() - t0:.1f} s)", flush=True)

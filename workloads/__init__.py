@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "zipf_keys", "tiny_star", "retail_snowflake", "grocery_star", "cart_node", "quantile_thresholds",
     "rkmeans_chain", "favorita_example", "random_acyclic", "covariance_batch",
-    "problem_digest", "fact_prefix", "estimator_workload",
+    "problem_digest", "fact_prefix", "estimator_workload", "bench_workload", "bench_plan_options",
 ]
 
 
@@ -621,6 +621,15 @@ def bench_workload(config: str, scale: float = 1.0) -> dict:
     else:
         raise ValueError(f"unknown workload {config!r}")
     return {"problem": problem, "precision": precision, "sizing": sizing, "workload": workload}
+
+
+def bench_plan_options(bw: dict, form: str = "fused", graph: bool = True) -> dict:
+    """Plan options of a measured workload (``bench_workload``) as the
+    benchmark runs it; the full-size parity tests use the same, so that they
+    check the launch configuration that is timed."""
+    p = bw["problem"]
+    return {"precision": bw["precision"], "policy": p["policy"], "form": form, "sizing": bw["sizing"],
+            "graph": graph}
 
 
 def tagged_star(seed: int = 0, n_fact: int = 200_000, n_stores: int = 40, n_items: int = 3_000,
