@@ -390,6 +390,21 @@ lmfao_status lmfao_mlp_grad(int32_t d, int32_t h, const float* params, const flo
                             float* grad, float* loss, void* stream);
 lmfao_status lmfao_mlp_predict(int32_t d, int32_t h, const float* params, const float* X, int32_t n, float* y,
                                void* stream);
+
+/* lmfao_mlp_grad_noalloc: lmfao_mlp_grad for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments, same kernels and the same gradient;
+ * the loss is summed in FP64 on the device.  It calls no hipMalloc, hipFree or
+ * allocating library routine: its scratch (the batch's activations and
+ * errors) is one fixed array of 8 MiB per GPU, held by the library for the
+ * life of the process, so the batch must satisfy 6*n*h + 3*n + 64 <= 2^21
+ * (e.g. n <= 5,400 rows at h = 64); larger batches return LMFAO_EINVAL with
+ * the limit in lmfao_last_error() before any work is enqueued.  Every call on
+ * one GPU shares that array, so calls that overlap on one GPU (from several
+ * host threads, or on streams that run concurrently) race; each call
+ * synchronises `stream` before returning. */
+lmfao_status lmfao_mlp_grad_noalloc(int32_t d, int32_t h, const float* params, const float* X, const float* t,
+                                    int32_t n, float* grad, float* loss, void* stream);
 lmfao_status lmfao_mlp_train(int32_t d, int32_t h, float* params, const float* X, const float* t, int32_t n,
                              const int32_t* order, int32_t n_steps, int32_t batch, float lr, float* loss_trace,
                              void* stream);

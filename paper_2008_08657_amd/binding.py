@@ -426,6 +426,20 @@ def mlp_grad(params, X, t, h: int, stream=None):
     return grad, float(loss.value)
 
 
+def mlp_grad_noalloc(params, X, t, h: int, stream=None):
+    """``lmfao_mlp_grad_noalloc``: the gradient and loss with the library's
+    fixed device scratch instead of allocations.  Returns (grad, loss)."""
+    import torch
+    lib = load_library()
+    n, d = int(X.shape[0]), int(X.shape[1])
+    grad = torch.empty_like(params)
+    loss = C.c_float()
+    _check(lib, lib.lmfao_mlp_grad_noalloc(d, int(h), _f32_dev(params, "params"), _f32_dev(X, "X"),
+                                           _f32_dev(t, "t"), n, _f32_dev(grad, "grad"), C.byref(loss),
+                                           _stream_arg(stream)))
+    return grad, float(loss.value)
+
+
 def mlp_predict(params, X, h: int, stream=None):
     """Network outputs for the rows of X (``lmfao_mlp_predict``)."""
     import torch

@@ -11,9 +11,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
+#include "engine.hpp"
 #include "lmfao.h"
 
 namespace lmfao {
@@ -132,6 +134,20 @@ __global__ void k_sqerr(const float* __restrict__ y, const float* __restrict__ t
 
 inline int blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + 255) / 256); }
 
+// sum of r[0..n) in FP64 by one workgroup, written to *out
+__global__ void k_sum(const float* __restrict__ r, int n, double* __restrict__ out) {
+  __shared__ double part[256];
+  double a = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a += (double)r[i];
+  part[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = part[0];
+}
+
 struct Work {
   float *z1 = nullptr, *h1 = nullptr, *z2 = nullptr, *h2 = nullptr, *y = nullptr, *dy = nullptr, *dh2 = nullptr,
         *dh1 = nullptr, *sq = nullptr;
@@ -182,6 +198,36 @@ float mean_sq(const float* y, const float* t, const int32_t* rows, int n, Work& 
   return (float)(acc / n);
 }
 
+// Device scratch of lmfao_mlp_grad_noalloc: the batch's activations and
+// back-propagated errors (6 n h floats), the outputs, their errors and squared
+// errors (3 n floats) and the FP64 loss, in one file-scope array of fixed
+// size that each GPU holds for the life of the process.
+constexpr int64_t kMlpScratchFloats = (int64_t)2 << 20;   // 8 MiB
+constexpr int64_t kMlpScratchTail = 64;                   // loss accumulator (floats)
+__device__ __align__(256) float scratch[kMlpScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// the scratch array's device address on the current GPU, looked up once per
+// device (the array's host-side name is not a device address)
+hipError_t scratch_address(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (float*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 }  // namespace lmfao
 
@@ -206,6 +252,54 @@ lmfao_status lmfao_mlp_grad(int32_t d, int32_t h, const float* params, const flo
   const float l = mean_sq(w.y, t, nullptr, n, w, s);
   if (loss) *loss = l;
   return std::isnan(l) ? LMFAO_EHIP : LMFAO_OK;
+}
+
+lmfao_status lmfao_mlp_grad_noalloc(int32_t d, int32_t h, const float* params, const float* X, const float* t,
+                                    int32_t n, float* grad, float* loss, void* stream) {
+  if (d <= 0 || h <= 0 || n <= 0 || !params || !X || !t || !grad) {
+    record_error("lmfao_mlp_grad_noalloc: non-positive size or null pointer");
+    return LMFAO_EINVAL;
+  }
+  const int64_t need = 6 * (int64_t)n * h + 3 * (int64_t)n + kMlpScratchTail;
+  if (need > kMlpScratchFloats) {
+    record_error("lmfao_mlp_grad_noalloc: a batch of " + std::to_string(n) + " rows with " + std::to_string(h) +
+                 " hidden units needs " + std::to_string(need * 4) + " bytes of scratch; the fixed scratch holds " +
+                 std::to_string(kMlpScratchFloats * 4) + " (6*n*h + 3*n + 64 floats at most)");
+    return LMFAO_EINVAL;
+  }
+  float* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) {
+    record_error(std::string("lmfao_mlp_grad_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+    return LMFAO_EHIP;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Net N(d, h);
+  Work w;   // points into the scratch array; owns nothing
+  const int64_t nh = (int64_t)n * h;
+  float* q = base;
+  for (float** p : {&w.z1, &w.h1, &w.z2, &w.h2, &w.dh2, &w.dh1}) {
+    *p = q;
+    q += nh;
+  }
+  for (float** p : {&w.y, &w.dy, &w.sq}) {
+    *p = q;
+    q += n;
+  }
+  double* acc = (double*)(base + kMlpScratchFloats - kMlpScratchTail);
+  pass(N, params, X, t, nullptr, n, w, grad, s);
+  hipLaunchKernelGGL(k_sqerr, dim3(blocks(n)), dim3(256), 0, s, w.y, t, (const int32_t*)nullptr, n, w.sq);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, w.sq, n, acc);
+  double sum = 0;
+  e = hipMemcpyAsync(&sum, acc, sizeof sum, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    record_error(std::string("lmfao_mlp_grad_noalloc: ") + hipGetErrorString(e));
+    return LMFAO_EHIP;
+  }
+  if (loss) *loss = (float)(sum / n);
+  return LMFAO_OK;
 }
 
 lmfao_status lmfao_mlp_predict(int32_t d, int32_t h, const float* params, const float* X, int32_t n, float* y,
