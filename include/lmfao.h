@@ -207,6 +207,14 @@ typedef struct {
                             generated scans, 512 for the built-in ones);
                             each has 8 wavefronts and takes whole work
                             items                                          */
+  int32_t partition;     /* 0: SUM(1) queries whose dense group-by table is
+                            larger than a scan keeps in LDS (and at most 2^24
+                            cells), grouped by columns of their root or codes
+                            of single-valued views into it, are counted by
+                            radix partition: their rows' cells are grouped
+                            by 2^15-cell slice and each slice is counted in
+                            LDS; 1: such tables are counted by the scans
+                            with global atomics                             */
   int32_t contract_splits; /* ranges the pieces of a matrix-core contraction
                             are cut into, per column of output tiles (0 =
                             1024, fewer past 4096 workgroups)              */
@@ -220,8 +228,11 @@ typedef struct {
  * estimator predicts, 2^(y + margin) - 1, at half occupancy, never above the
  * BOUND capacity and never below 1024 slots.  Both round up to a power of
  * two and start at most at 2^26 slots; regrowth goes up to the BOUND
- * capacity.  LEARNED without an estimator blob behaves as BOUND. */
-enum { LMFAO_SIZING_BOUND = 0, LMFAO_SIZING_LEARNED = 1 };
+ * capacity.  LEARNED without an estimator blob behaves as BOUND.  EXACT:
+ * lmfao_prepare runs the whole batch once with BOUND tables, counts every
+ * table's groups on the device and reallocates it at twice that count (the
+ * exact-count pass; it belongs to lmfao_prepare, not to lmfao_run). */
+enum { LMFAO_SIZING_BOUND = 0, LMFAO_SIZING_LEARNED = 1, LMFAO_SIZING_EXACT = 2 };
 
 /* Estimator blob: {version = 2, d = LMFAO_EST_FEATURES, h, margin},
  * then d feature means, d feature standard deviations, then the

@@ -75,7 +75,7 @@ class lmfao_options(C.Structure):
                 ("contraction", C.c_int32), ("codegen", C.c_int32), ("hash_slots", C.c_int64),
                 ("sizing", C.c_int32), ("estimator", C.POINTER(C.c_float)), ("estimator_len", C.c_int64),
                 ("graph", C.c_int32), ("one_hot_max", C.c_int32), ("scan_blocks", C.c_int32),
-                ("contract_splits", C.c_int32)]
+                ("partition", C.c_int32), ("contract_splits", C.c_int32)]
 
 
 class LmfaoError(RuntimeError):
@@ -197,7 +197,7 @@ class Plan:
     def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
                  min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0,
                  sizing="bound", estimator=None, graph=False, one_hot_max=0, scan_blocks=0,
-                 contract_splits=0):
+                 contract_splits=0, partition=True):
         self.lib = load_library()
         self.problem = problem
         keep = _Keep()
@@ -222,9 +222,10 @@ class Plan:
         opts.one_hot_max = int(one_hot_max)
         opts.scan_blocks = int(scan_blocks)
         opts.contract_splits = int(contract_splits)
-        if sizing not in ("bound", "learned"):
-            raise ValueError(f"sizing must be 'bound' or 'learned', not {sizing!r}")
-        opts.sizing = 0 if sizing == "bound" else 1
+        opts.partition = 0 if partition else 1
+        if sizing not in ("bound", "learned", "exact"):
+            raise ValueError(f"sizing must be 'bound', 'learned' or 'exact', not {sizing!r}")
+        opts.sizing = {"bound": 0, "learned": 1, "exact": 2}[sizing]
         if sizing == "learned" and estimator is None:
             from . import estimator as _est
             estimator = _est.load()

@@ -249,6 +249,8 @@ struct GroupDef {
   std::set<int> deps;             // groups this one depends on
   bool has_program = false;
   bool force_rows = false;        // evaluated row by row (an output has no scan form)
+  bool partitioned = false;       // SUM(1) queries with large dense tables, counted by
+                                  // radix partition (no program)
   int one_hot_pure = 0;           // one-hot limit of outer-only outputs (0 = kOneHotMax)
   GroupProgram prog;
 };

@@ -2203,6 +2203,299 @@ void launch_count_copy(const DCountCopy* d, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_count_copy, dim3((int)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s, d);
 }
 
+__global__ void k_count_keys(const unsigned long long* __restrict__ keys, int64_t n, unsigned long long* out) {
+  unsigned long long c = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += keys[i] != 0;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+void launch_count_keys(const unsigned long long* keys, int64_t n, unsigned long long* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_count_keys, dim3((int)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s, keys, n,
+                     out);
+}
+
+// ---------------------------------------------------------------------------
+// radix-partitioned counting of large dense tables
+// ---------------------------------------------------------------------------
+constexpr int kPartThreads = 256;
+constexpr int64_t kPartTile = (int64_t)1 << 20;   // partitioned entries (or rows) one counting workgroup takes
+constexpr int kPartWaveSlices = 8;                 // up to this many slices: wavefront-aggregated LDS atomics
+
+struct PartRow {
+  int64_t v0, v1, v2, v3;   // the row's key in each view (named fields: kept in registers)
+  uint32_t vok;             // bit v: the row has a partner tuple in view v (count 1)
+  int32_t w;
+};
+
+__device__ __forceinline__ int64_t part_view_key(const DPartCount& D, int v, int64_t row) {
+  int64_t k = (int64_t)D.vkey[v][0][row] * D.vstride[v][0];
+  if (D.vnkey[v] > 1) k += (int64_t)D.vkey[v][1][row] * D.vstride[v][1];
+  return k;
+}
+
+__device__ __forceinline__ void part_row(const DPartCount& D, int64_t row, PartRow& R) {
+  R.w = D.w ? D.w[row] : 1;
+  R.vok = 0;
+  R.v0 = R.v1 = R.v2 = R.v3 = 0;
+  const int nv = D.n_views;
+  if (nv > 0) R.v0 = part_view_key(D, 0, row);
+  if (nv > 1) R.v1 = part_view_key(D, 1, row);
+  if (nv > 2) R.v2 = part_view_key(D, 2, row);
+  if (nv > 3) R.v3 = part_view_key(D, 3, row);
+  if (nv > 0 && R.v0 >= 0 && R.v0 < D.vnkeys[0] && D.vcnt[0][R.v0] > 0) R.vok |= 1u;
+  if (nv > 1 && R.v1 >= 0 && R.v1 < D.vnkeys[1] && D.vcnt[1][R.v1] > 0) R.vok |= 2u;
+  if (nv > 2 && R.v2 >= 0 && R.v2 < D.vnkeys[2] && D.vcnt[2][R.v2] > 0) R.vok |= 4u;
+  if (nv > 3 && R.v3 >= 0 && R.v3 < D.vnkeys[3] && D.vcnt[3][R.v3] > 0) R.vok |= 8u;
+}
+
+__device__ __forceinline__ int64_t part_vrow(const PartRow& R, int v) {
+  return v == 0 ? R.v0 : v == 1 ? R.v1 : v == 2 ? R.v2 : R.v3;
+}
+
+// dense cell of output o for the row; -1: the row does not count (weight 0);
+// -2: a key outside its declared domain
+__device__ __forceinline__ int64_t part_cell(const DPartCount& D, int o, int64_t row, const PartRow& R) {
+  if (!R.w || (D.vmask[o] & ~R.vok)) return -1;
+  int64_t cell = 0;
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k < D.nkey[o]) {
+      const int src = D.ksrc[o][k];
+      const int32_t c =
+          src < 0 ? D.kcol[o][k][row] : D.vcodes[src][part_vrow(R, src) * D.vncodes[src] + D.kslot[o][k]];
+      bad |= c < 0 || c >= D.kdom[o][k];
+      cell += (int64_t)c * D.kstride[o][k];
+    }
+  }
+  return bad ? -2 : cell;
+}
+
+// the cells of every output of the launch set for one row (-1 when the row
+// does not count or is outside the block's range); all loads are issued
+// before any counter is touched
+__device__ __forceinline__ void part_cells(const DPartCount& D, int64_t row, bool in, int32_t* slice, uint32_t* low,
+                                           bool multi_only) {
+  PartRow R;
+  part_row(D, in ? row : 0, R);
+#pragma unroll
+  for (int o = 0; o < kPartOuts; ++o) {
+    slice[o] = -1;
+    low[o] = 0;
+    if (o < D.n_out && in && (!multi_only || D.n_buckets[o] > 1)) {
+      const int64_t cell = part_cell(D, o, row, R);
+      if (cell == -2) atomicOr(D.err_flag, 2);
+      if (cell >= 0) {
+        slice[o] = (int32_t)(cell >> kPartShift);
+        low[o] = (uint32_t)(cell & ((1 << kPartShift) - 1));
+      }
+    }
+  }
+}
+
+// adds one per lane with b >= 0 to bins[b], one LDS atomic per distinct b in
+// the wavefront (wave-uniform control flow required)
+__device__ inline void wave_count(uint32_t* bins, int b) {
+  unsigned long long pending = __ballot(b >= 0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int bl = __shfl(b, leader, 64);
+    const unsigned long long same = __ballot(b == bl) & pending;
+    if ((int)__lane_id() == leader) atomicAdd(&bins[bl], (uint32_t)__popcll(same));
+    pending &= ~same;
+  }
+}
+
+// reserves a slot in cur[b] per lane with b >= 0: the position, or -1
+__device__ inline int64_t wave_reserve(uint32_t* cur, int b) {
+  int64_t pos = -1;
+  const int lane = (int)__lane_id();
+  unsigned long long pending = __ballot(b >= 0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int bl = __shfl(b, leader, 64);
+    const unsigned long long same = __ballot(b == bl) & pending;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&cur[bl], (uint32_t)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if ((same >> lane) & 1ull) pos = (int64_t)base + __popcll(same & ((1ull << lane) - 1ull));
+    pending &= ~same;
+  }
+  return pos;
+}
+
+// pass 1: per workgroup row range, the number of counted rows per slice
+__global__ void __launch_bounds__(kPartThreads) k_part_slices(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  __shared__ uint32_t bins[kPartOuts * kPartMaxBuckets];
+  for (int i = threadIdx.x; i < D.n_out * kPartMaxBuckets; i += blockDim.x) bins[i] = 0;
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * D.rows_per_block;
+  const int64_t r1 = min(D.n_rows, r0 + D.rows_per_block);
+  for (int64_t base = r0; base < r1; base += blockDim.x) {
+    const int64_t row = base + threadIdx.x;
+    int32_t slice[kPartOuts];
+    uint32_t low[kPartOuts];
+    part_cells(D, row, row < r1, slice, low, true);
+#pragma unroll
+    for (int o = 0; o < kPartOuts; ++o) {
+      if (o >= D.n_out || D.n_buckets[o] <= 1) continue;
+      // few slices: one LDS atomic per distinct slice in the wavefront (lanes
+      // would otherwise queue on one address); many: one per lane
+      if (D.n_buckets[o] <= kPartWaveSlices) wave_count(&bins[o * kPartMaxBuckets], slice[o]);
+      else if (slice[o] >= 0) atomicAdd(&bins[o * kPartMaxBuckets + slice[o]], 1u);
+    }
+  }
+  __syncthreads();
+  for (int o = 0; o < D.n_out; ++o)
+    for (int b = threadIdx.x; b < D.n_buckets[o]; b += blockDim.x)
+      D.bcount[((int64_t)o * kPartMaxBuckets + b) * D.n_blocks + blockIdx.x] = bins[o * kPartMaxBuckets + b];
+}
+
+// pass 2: exclusive offsets over (slice, workgroup), one workgroup per output
+__global__ void __launch_bounds__(1024) k_part_offsets(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  const int o = blockIdx.x;
+  if (o >= D.n_out || D.n_buckets[o] <= 1) return;
+  __shared__ uint32_t tmp[1024];
+  const int64_t n = (int64_t)D.n_buckets[o] * D.n_blocks;
+  uint32_t* a = D.bcount + (int64_t)o * kPartMaxBuckets * D.n_blocks;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t v = i < n ? a[i] : 0u;
+    tmp[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const uint32_t x = (int)threadIdx.x >= d ? tmp[threadIdx.x - d] : 0u;
+      __syncthreads();
+      tmp[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (i < n) a[i] = carry + tmp[threadIdx.x] - v;
+    carry += tmp[1023];
+    __syncthreads();
+  }
+  uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
+  for (int b = threadIdx.x; b <= D.n_buckets[o]; b += blockDim.x)
+    bs[b] = b < D.n_buckets[o] ? a[(int64_t)b * D.n_blocks] : carry;
+}
+
+// pass 3: the low 15 bits of every counted row's cell, grouped by slice
+__global__ void __launch_bounds__(kPartThreads) k_part_scatter(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  __shared__ uint32_t cur[kPartOuts * kPartMaxBuckets];
+  for (int o = 0; o < D.n_out; ++o)
+    for (int b = threadIdx.x; b < D.n_buckets[o]; b += blockDim.x)
+      cur[o * kPartMaxBuckets + b] = D.bcount[((int64_t)o * kPartMaxBuckets + b) * D.n_blocks + blockIdx.x];
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * D.rows_per_block;
+  const int64_t r1 = min(D.n_rows, r0 + D.rows_per_block);
+  for (int64_t base = r0; base < r1; base += blockDim.x) {
+    const int64_t row = base + threadIdx.x;
+    int32_t slice[kPartOuts];
+    uint32_t low[kPartOuts];
+    part_cells(D, row, row < r1, slice, low, true);
+#pragma unroll
+    for (int o = 0; o < kPartOuts; ++o) {
+      if (o >= D.n_out || D.n_buckets[o] <= 1) continue;
+      int64_t pos = -1;
+      if (D.n_buckets[o] <= kPartWaveSlices) pos = wave_reserve(&cur[o * kPartMaxBuckets], slice[o]);
+      else if (slice[o] >= 0) pos = atomicAdd(&cur[o * kPartMaxBuckets + slice[o]], 1u);
+      if (pos >= 0 && pos < D.n_rows) D.part[(int64_t)o * D.n_rows + pos] = (uint16_t)low[o];
+    }
+  }
+}
+
+// pass 4: every slice counted in LDS (2^15 counters), nonzero counters added
+// to the output table; outputs of a single slice are counted from the rows
+constexpr int kPartHistThreads = 1024;
+__global__ void __launch_bounds__(kPartHistThreads) k_part_hist(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  extern __shared__ uint32_t bins[];
+  const int o = blockIdx.y;
+  const int64_t t0 = (int64_t)blockIdx.x * kPartTile;
+  constexpr int kSlice = 1 << kPartShift;
+  if (D.n_buckets[o] > 1) {
+    const uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
+    const int nb = D.n_buckets[o];
+    const int64_t total = bs[nb];
+    if (t0 >= total) return;
+    const int64_t t1 = min(total, t0 + kPartTile);
+    int b = 0;
+    while (b < nb && (int64_t)bs[b + 1] <= t0) ++b;
+    const uint16_t* part = D.part + (int64_t)o * D.n_rows;
+    for (; b < nb && (int64_t)bs[b] < t1; ++b) {
+      const int64_t s0 = max(t0, (int64_t)bs[b]), s1 = min(t1, (int64_t)bs[b + 1]);
+      if (s0 >= s1) continue;
+      for (int i = threadIdx.x; i < kSlice; i += blockDim.x) bins[i] = 0;
+      __syncthreads();
+      // four entries per thread per round: the loads are in flight together
+      for (int64_t i = s0 + threadIdx.x; i < s1; i += 4 * (int64_t)blockDim.x) {
+        uint32_t e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t k = i + (int64_t)u * blockDim.x;
+          e[u] = k < s1 ? (uint32_t)part[k] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (e[u] != 0xffffffffu) atomicAdd(&bins[e[u]], 1u);
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < kSlice; i += blockDim.x) {
+        const uint32_t v = bins[i];
+        const int64_t cell = ((int64_t)b << kPartShift) + i;
+        if (v && cell < D.n_cells[o]) atomicAdd((unsigned long long*)&D.out_cnt[o][cell], (unsigned long long)v);
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  if (t0 >= D.n_rows) return;
+  const int64_t t1 = min(D.n_rows, t0 + kPartTile);
+  for (int i = threadIdx.x; i < kSlice; i += blockDim.x) bins[i] = 0;
+  __syncthreads();
+  for (int64_t row = t0 + threadIdx.x; row < t1; row += 2 * (int64_t)blockDim.x) {
+    int64_t cell[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t rr = row + (int64_t)u * blockDim.x;
+      cell[u] = -1;
+      if (rr < t1) {
+        PartRow R;
+        part_row(D, rr, R);
+        cell[u] = part_cell(D, o, rr, R);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (cell[u] == -2) atomicOr(D.err_flag, 2);
+      else if (cell[u] >= 0) atomicAdd(&bins[cell[u]], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSlice; i += blockDim.x) {
+    const uint32_t v = bins[i];
+    if (v && i < D.n_cells[o]) atomicAdd((unsigned long long*)&D.out_cnt[o][i], (unsigned long long)v);
+  }
+}
+
+void launch_part_count(const DPartCount* d, const DPartCount& h, hipStream_t s) {
+  if (h.n_rows <= 0 || h.n_out <= 0) return;
+  bool multi = false;
+  for (int o = 0; o < h.n_out; ++o) multi |= h.n_buckets[o] > 1;
+  if (multi) {
+    hipLaunchKernelGGL(k_part_slices, dim3(h.n_blocks), dim3(kPartThreads), 0, s, d);
+    hipLaunchKernelGGL(k_part_offsets, dim3(h.n_out), dim3(1024), 0, s, d);
+    hipLaunchKernelGGL(k_part_scatter, dim3(h.n_blocks), dim3(kPartThreads), 0, s, d);
+  }
+  const int tiles = (int)((h.n_rows + kPartTile - 1) / kPartTile);
+  hipLaunchKernelGGL(k_part_hist, dim3(tiles, h.n_out), dim3(kPartHistThreads), (1 << kPartShift) * 4, s, d);
+}
+
 // largest count of each listed view (grid-stride, one atomicMax per block)
 __global__ void k_mult_max(const DMultCheck* __restrict__ D) {
   __shared__ unsigned long long red[4];

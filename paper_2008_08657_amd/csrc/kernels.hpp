@@ -96,7 +96,53 @@ struct DMultCheck {
 };
 void launch_mult_check(const DMultCheck* d, const DMultCheck& h, hipStream_t s);
 
+// Radix-partitioned counting of large dense group-by tables of SUM(1)
+// queries (key spaces above what a scan keeps in LDS): per row a dense cell
+// index from up to 3 codes (columns of the relation or codes carried by
+// unique views), weighted by the filter and the views' 0/1 counts.  Tables of
+// more than one 2^15-cell slice are partitioned by slice (count, offsets,
+// scatter of the low 15 bits) and every slice is then counted in LDS; tables
+// of one slice are counted in LDS straight from the columns.
+constexpr int kPartOuts = 16;
+constexpr int kPartViews = 4;
+constexpr int kPartShift = 15;
+constexpr int kPartMaxBuckets = 512;
+struct DPartCount {
+  int64_t n_rows;
+  int64_t rows_per_block;
+  int32_t n_blocks;
+  int32_t n_out;
+  const int32_t* w;                        // filter weight per row (null: all 1)
+  int32_t n_views;
+  int32_t pad;
+  const int64_t* vcnt[kPartViews];         // view counts (0/1: unique views)
+  const int32_t* vcodes[kPartViews];       // carried codes [n_keys x vncodes]
+  int32_t vncodes[kPartViews];
+  int32_t vnkey[kPartViews];
+  const int32_t* vkey[kPartViews][2];      // key columns of the relation
+  int64_t vstride[kPartViews][2];
+  int64_t vnkeys[kPartViews];
+  uint32_t vmask[kPartOuts];               // views whose counts weight the output
+  int32_t nkey[kPartOuts];
+  int32_t ksrc[kPartOuts][3];              // -1: column, else view index
+  const int32_t* kcol[kPartOuts][3];
+  int32_t kslot[kPartOuts][3];
+  int64_t kstride[kPartOuts][3];
+  int64_t kdom[kPartOuts][3];
+  int64_t n_cells[kPartOuts];
+  int32_t n_buckets[kPartOuts];
+  int64_t* out_cnt[kPartOuts];
+  uint32_t* bcount;                        // [out][bucket][block] counts, then exclusive offsets
+  uint32_t* bstart;                        // [out][kPartMaxBuckets + 1] bucket starts in part
+  uint16_t* part;                          // [out][n_rows] low 15 bits of the cell
+  int32_t* err_flag;
+};
+// the three partition launches (count, offsets, scatter) and the LDS count
+void launch_part_count(const DPartCount* d, const DPartCount& h, hipStream_t s);
+
 void launch_fill(void* p, int64_t bytes, hipStream_t s);
+// number of nonzero keys (occupied slots) of a hash table, added to *out
+void launch_count_keys(const unsigned long long* keys, int64_t n, unsigned long long* out, hipStream_t s);
 void launch_filter(const DFilter* d, int64_t n_rows, hipStream_t s);
 void launch_bucketize(const void* src, int dtype, int64_t n, const double* thr, int n_thr, int kind, int32_t* out,
                       hipStream_t s);

@@ -1316,6 +1316,57 @@ static void split_group(Plan& P, int gi, size_t from) {
   }
 }
 
+// A query whose every aggregate is SUM(1), rooted at `node`, grouped by at
+// most 3 attributes into a dense table larger than a scan keeps in LDS, whose
+// group-by attributes are columns of the node or carried by the single-valued
+// views into it: its table is counted by radix partition (a slice of the key
+// space at a time, in LDS) instead of by global atomics from the scan.
+static bool partition_eligible(const Plan& P, int qid, int node) {
+  const QueryDef& Q = P.queries[qid];
+  if (Q.root != node || Q.groupby.empty() || Q.groupby.size() > 3) return false;
+  for (const Mono& m : Q.aggs)
+    if (!m.empty()) return false;
+  double cells = 1;
+  for (int a : Q.groupby) {
+    if (P.attrs[a].domain <= 0) return false;
+    cells *= (double)P.attrs[a].domain;
+  }
+  if (cells <= (double)kLdsTableMax || cells > (double)kDenseRowsMax) return false;
+  if (Q.in_view.size() > 4) return false;
+  for (auto& kv : Q.in_view)
+    if (!P.views[kv.second].unique || P.views[kv.second].key.size() > 2) return false;
+  for (int a : Q.groupby) {
+    if (P.rels[node].has(a)) continue;
+    bool carried = false;
+    for (auto& kv : Q.in_view)
+      for (int c : P.views[kv.second].carried) carried |= c == a;
+    if (!carried) return false;
+  }
+  return true;
+}
+
+// Moves the partition-eligible queries of every group into a group of their
+// own at the same node and level (no program; the runtime counts them).
+static void extract_partitioned(Plan& P) {
+  const size_t n = P.groups.size();
+  for (size_t gi = 0; gi < n; ++gi) {
+    GroupDef& G = P.groups[gi];
+    if (G.force_rows || G.partitioned) continue;
+    std::vector<OutRef> keep, part;
+    for (const OutRef& o : G.outs)
+      (o.kind == 0 && partition_eligible(P, o.id, G.node) ? part : keep).push_back(o);
+    if (part.empty()) continue;
+    if (keep.empty()) {
+      G.partitioned = true;
+      continue;
+    }
+    G.outs = keep;
+    G.outs.insert(G.outs.end(), part.begin(), part.end());
+    split_group(P, (int)gi, keep.size());
+    P.groups.back().partitioned = true;
+  }
+}
+
 // Builds every group's program.  Outputs kept in hash tables are evaluated row
 // by row, so they leave their group for one of their own; a group whose
 // program exceeds what one scan kernel holds (columns, codes, masks,
@@ -1329,7 +1380,12 @@ static void build_programs(Plan& P) {
     while (n_dense < outs.size() && out_cells(P, outs[n_dense]) <= (double)kDenseRowsMax) ++n_dense;
     if (n_dense > 0 && n_dense < outs.size()) split_group(P, (int)gi, n_dense);
   }
+  if (P.opts.partition == 0) extract_partitioned(P);
   for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    if (P.groups[gi].partitioned) {
+      P.groups[gi].has_program = false;
+      continue;
+    }
     for (;;) {
       GroupDef& G = P.groups[gi];
       G.has_program = false;
@@ -1516,6 +1572,7 @@ static std::string describe(const Plan& P) {
       o << d;
     }
     o << "]";
+    if (G.partitioned) o << ",\"partitioned\":true";
     if (G.has_program) {
       const GroupProgram& g = G.prog;
       o << ",\"program\":{\"cut\":" << g.cut << ",\"row_pieces\":" << (g.row_pieces ? "true" : "false")

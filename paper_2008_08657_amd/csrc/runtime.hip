@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -88,7 +89,8 @@ struct Step {
   void* dev2 = nullptr;             // second descriptor (fused contraction: the product's)
   int kind;   // 0 fill, 1 view build, 2 scan, 3 table reduce, 4 contract (VALU), 5 merge, 6 image build,
               // 7 (unused), 8 MFMA contraction, 9 block-major merge, 10 filter, 11 finalize,
-              // 12 row-by-row scatter, 13 count copy, 14 multiplicity range check
+              // 12 row-by-row scatter, 13 count copy, 14 multiplicity range check,
+              // 15 radix-partitioned count
   int fast = 0;
   void* dev = nullptr;
   int64_t n = 0;
@@ -100,6 +102,12 @@ struct Step {
   const int64_t* part_i = nullptr;
   int n_blocks = 0, NF = 0, NG = 0, NFI = 0, NGI = 0;
   DMultCheck mult{};                // kind 14: host copy of the descriptor
+  DPartCount part{};                // kind 15: host copy of the descriptor
+  // the relation pass this launch belongs to: the relation's columns its
+  // outputs reference (bucket codes counted as their source column), whether
+  // read from HBM or folded by prepare into piece keys
+  int relation = -1;
+  std::vector<int> pass_cols;
   // accounting (host-computed): bytes the step must move, arithmetic it must do
   double alg_read = 0, alg_write = 0, alg_flop = 0;
   int64_t rows = 0, pieces = 0;
@@ -551,9 +559,166 @@ static const int32_t* filter_weights(Prep& S, int r, bool sorted, const void* co
   return f.out;
 }
 
+// the input column a (possibly derived bucket-code) column of relation r stands for
+static int source_column(const Plan& P, int r, int c) {
+  const RelDef& R = P.rels[r];
+  if (c < R.n_input_attrs) return c;
+  for (const DerivedAttr& D : P.derived)
+    if (D.rel == r && D.attr == R.attrs[c]) return R.col.at(D.src);
+  return c;
+}
+
+// A group of SUM(1) queries with large dense tables (planner: partitioned):
+// their cells are counted by radix partition, up to kPartOuts queries per
+// launch set, over the relation in its sorted order when a scan of the same
+// node sorts it (the views' keys then come in order), else in input order.
+static void build_partition(Prep& S, int gi, const void* const* const* cols, hipStream_t st) {
+  Plan& P = *S.P;
+  GroupDef& G = P.groups[gi];
+  const int r = G.node;
+  const RelDef& R = P.rels[r];
+  NodeData& N = S.nodes[r];
+  const std::string gname = "g" + std::to_string(gi) + ":" + R.name;
+  int cut = -1;
+  for (const GroupDef& H : P.groups)
+    if (H.node == r && H.has_program && !H.prog.row_pieces) {
+      cut = H.prog.cut;
+      break;
+    }
+  const bool sorted = cut >= 0;
+  for (size_t base = 0; base < G.outs.size(); base += kPartOuts) {
+    const size_t end = std::min(G.outs.size(), base + (size_t)kPartOuts);
+    // relation columns and views the launch set reads
+    std::vector<int> views, need;
+    for (size_t k = base; k < end; ++k) {
+      const QueryDef& Q = P.queries[G.outs[k].id];
+      for (auto& kv : Q.in_view)
+        if (std::find(views.begin(), views.end(), kv.second) == views.end()) views.push_back(kv.second);
+      for (int a : Q.groupby)
+        if (R.has(a)) need.push_back(R.col.at(a));
+    }
+    if ((int)views.size() > kPartViews) throw PlanError{LMFAO_EUNSUPPORTED, "partitioned count with more than 4 views"};
+    for (int vid : views)
+      for (int a : P.views[vid].key) need.push_back(R.col.at(a));
+    std::sort(need.begin(), need.end());
+    need.erase(std::unique(need.begin(), need.end()), need.end());
+    if (sorted) prepare_node(S, r, cut, need, cols, st);
+    auto col = [&](int c) -> const int32_t* {
+      if (R.dtypes[c] != LMFAO_I32) throw PlanError{LMFAO_EINVAL, "internal: partitioned key column not int32"};
+      return sorted ? (const int32_t*)N.sorted_col[c] : (const int32_t*)raw_column(S, r, c, cols, st);
+    };
+    DPartCount d{};
+    d.n_rows = R.n_rows;
+    d.w = filter_weights(S, r, sorted, cols, st);
+    d.n_views = (int)views.size();
+    for (int v = 0; v < d.n_views; ++v) {
+      const ViewDef& V = P.views[views[v]];
+      const DView dv = dview_of(S, views[v]);
+      d.vcnt[v] = dv.cnt;
+      d.vcodes[v] = dv.codes;
+      d.vncodes[v] = dv.n_codes;
+      d.vnkey[v] = (int)V.key.size();
+      d.vnkeys[v] = V.n_keys;
+      for (int q = 0; q < d.vnkey[v]; ++q) {
+        d.vkey[v][q] = col(R.col.at(V.key[q]));
+        d.vstride[v][q] = dv.key_stride[q];
+      }
+    }
+    d.n_out = (int)(end - base);
+    bool multi = false;
+    std::vector<DCountCopy> copies;
+    double rows_bytes = 0;
+    for (int o = 0; o < d.n_out; ++o) {
+      const int qid = G.outs[base + o].id;
+      const QueryDef& Q = P.queries[qid];
+      const OutBuf& B = S.qout[qid];
+      d.out_cnt[o] = B.cnt;
+      d.n_cells[o] = B.n_rows;
+      d.n_buckets[o] = (int)((B.n_rows + (1 << kPartShift) - 1) >> kPartShift);
+      if (d.n_buckets[o] > kPartMaxBuckets) throw PlanError{LMFAO_EINVAL, "internal: partitioned table too large"};
+      multi |= d.n_buckets[o] > 1;
+      for (auto& kv : Q.in_view) {
+        const int v = (int)(std::find(views.begin(), views.end(), kv.second) - views.begin());
+        d.vmask[o] |= 1u << v;
+      }
+      const std::vector<int64_t> st_ = strides_of(P, Q.groupby);
+      d.nkey[o] = (int)Q.groupby.size();
+      for (int k = 0; k < d.nkey[o]; ++k) {
+        const int a = Q.groupby[k];
+        d.kstride[o][k] = st_[k];
+        d.kdom[o][k] = P.attrs[a].domain;
+        if (R.has(a)) {
+          d.ksrc[o][k] = -1;
+          d.kcol[o][k] = col(R.col.at(a));
+          d.kslot[o][k] = 0;
+          rows_bytes += 4;
+        } else {
+          d.ksrc[o][k] = -1;
+          for (int v = 0; v < d.n_views; ++v)
+            if (((d.vmask[o] >> v) & 1u) && P.views[views[v]].slot_of_code(a) >= 0) {
+              d.ksrc[o][k] = v;
+              d.kslot[o][k] = P.views[views[v]].slot_of_code(a);
+              break;
+            }
+          if (d.ksrc[o][k] < 0) throw PlanError{LMFAO_EINVAL, "internal: partitioned key attribute not found"};
+        }
+      }
+      if (B.n_vals > 0) {
+        DCountCopy cc{};
+        cc.cnt = B.cnt;
+        cc.vals = (double*)B.vals;
+        cc.n = B.n_rows;
+        cc.nv = B.n_vals;
+        cc.n_copy = B.n_vals;
+        if (cc.n_copy > kMaxTableComps) throw PlanError{LMFAO_EUNSUPPORTED, "too many SUM(1) components"};
+        for (int k = 0; k < cc.n_copy; ++k) cc.comp[k] = k;
+        copies.push_back(cc);
+      }
+    }
+    const int64_t n = R.n_rows;
+    d.rows_per_block = std::max<int64_t>(65536, ((n + 1023) / 1024 + 255) / 256 * 256);
+    d.n_blocks = (int)std::max<int64_t>(1, (n + d.rows_per_block - 1) / d.rows_per_block);
+    d.bcount = (uint32_t*)dalloc(S, (size_t)d.n_out * kPartMaxBuckets * d.n_blocks * 4);
+    d.bstart = (uint32_t*)dalloc(S, (size_t)d.n_out * (kPartMaxBuckets + 1) * 4);
+    d.part = multi ? (uint16_t*)dalloc(S, (size_t)d.n_out * std::max<int64_t>(n, 1) * 2) : nullptr;
+    d.err_flag = S.err_flag;
+    Step s;
+    s.name = gname + ":partition";
+    s.kind = 15;
+    s.dev = upload(S, d, st);
+    s.part = d;
+    s.rows = n;
+    s.grid = d.n_blocks;
+    // bytes the method needs: every key column and view key read once; the
+    // counts written once per cell (the partition round trip is the kernel's)
+    std::set<int> rc(need.begin(), need.end());
+    for (int c : rc) s.alg_read += (double)n * 4;
+    for (int o = 0; o < d.n_out; ++o) s.alg_write += (double)d.n_cells[o] * 8;
+    s.relation = r;
+    s.pass_cols.clear();
+    for (int c : rc) s.pass_cols.push_back(source_column(P, r, c));
+    std::sort(s.pass_cols.begin(), s.pass_cols.end());
+    s.pass_cols.erase(std::unique(s.pass_cols.begin(), s.pass_cols.end()), s.pass_cols.end());
+    (void)rows_bytes;
+    S.steps.push_back(s);
+    for (const DCountCopy& cc : copies) {
+      Step t;
+      t.name = gname + ":count_copy";
+      t.kind = 13;
+      t.dev = upload(S, cc, st);
+      t.n = cc.n;
+      S.steps.push_back(t);
+    }
+  }
+}
+
 static void build_group(Prep& S, int gi, const void* const* const* cols, hipStream_t st) {
   Plan& P = *S.P;
   GroupDef& G = P.groups[gi];
+  if (G.partitioned) {
+    build_partition(S, gi, cols, st);
+    return;
+  }
   const int r = G.node;
   const RelDef& R = P.rels[r];
   NodeData& N = S.nodes[r];
@@ -1078,6 +1243,13 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
                                                         d.views[v].n_codes * 4);
     s.alg_write += (double)N.n_pieces * (psi_f_stride * (f64 ? 8 : 4) + psi_i_stride * 4);
     s.alg_flop = (double)R.n_rows * 2 * (double)std::max(1, d.pf_n);
+    {
+      std::set<int> rc;
+      for (int c : scols) rc.insert(source_column(P, r, c));
+      for (int l = 0; l < g.cut && l < (int)g.order.size(); ++l) rc.insert(source_column(P, r, R.col.at(g.order[l])));
+      s.relation = r;
+      s.pass_cols.assign(rc.begin(), rc.end());
+    }
     S.steps.push_back(s);
     for (auto& lt : lds_tables) {
       const ProgOutput& po = g.outs[lt.first];
@@ -1259,7 +1431,18 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
   c.so_cnt = upload_vec(S, so_cnt, st);
   c.so_vals = upload_vec(S, so_vals, st);
   if (S.P->opts.contraction == LMFAO_CONTRACT_MFMA) {
+    const size_t first = S.steps.size();
     build_contract_mfma(S, g, gname, c, n_pieces, psi_f_stride, psi_i_stride, f64, st);
+    if (g.row_pieces) {
+      // a row-by-row pass reads the relation's columns itself
+      std::set<int> rc;
+      for (int c2 : pk) rc.insert(source_column(P, r, c2));
+      for (size_t i = first; i < S.steps.size(); ++i)
+        if (S.steps[i].kind == 12 || S.steps[i].kind == 8) {
+          S.steps[i].relation = r;
+          S.steps[i].pass_cols.assign(rc.begin(), rc.end());
+        }
+    }
     return;
   }
   c.part_f = (double*)dalloc(S, (size_t)grid_x * std::max(1, c.n_feat * c.n_col) * 8);
@@ -1626,6 +1809,8 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
       int64_t want = top;
       if (P.opts.hash_slots > 0) {
         want = P.opts.hash_slots;
+      } else if (P.opts.sizing == LMFAO_SIZING_EXACT) {
+        want = top;   // the exact-count run at the end of prepare resizes it
       } else if (P.opts.sizing == LMFAO_SIZING_LEARNED && !P.estimator.empty()) {
         float f[LMFAO_EST_FEATURES];
         query_features(S, Q, f, st);
@@ -1753,7 +1938,9 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
 
 // timed steps: scans and contractions (the kernels that move the data); the
 // whole run is timed as well.  Slot 0 of a run = whole run.
-static bool timed_step(const Step& s) { return s.kind == 2 || s.kind == 4 || s.kind == 8 || s.kind == 12; }
+static bool timed_step(const Step& s) {
+  return s.kind == 2 || s.kind == 4 || s.kind == 8 || s.kind == 12 || s.kind == 15;
+}
 static int timed_slots(const Prep& S) {
   int n = 1;
   for (auto& s : S.steps) n += timed_step(s);
@@ -1802,6 +1989,7 @@ static void enqueue_run(Prep& S, hipStream_t st) {
         break;
       case 13: launch_count_copy((const DCountCopy*)s.dev, s.n, st); break;
       case 14: launch_mult_check((const DMultCheck*)s.dev, s.mult, st); break;
+      case 15: launch_part_count((const DPartCount*)s.dev, s.part, st); break;
       case 8:
         launch_contract_fused((const DContract*)s.dev, (const DGemm*)s.dev2, S.f64,
                               S.P->opts.precision == LMFAO_PREC_BF16X3   ? 3
@@ -1909,6 +2097,8 @@ lmfao_status lmfao_plan_workspace_bytes(lmfao_plan_t plan, size_t* bytes) {
   return LMFAO_OK;
 }
 
+static void exact_sizes(Prep& S, hipStream_t st);
+
 lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns, void* stream,
                            lmfao_prepared_t* out) {
   g_last_error.clear();
@@ -1922,6 +2112,8 @@ lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns,
     if (!columns[r]) return set_err(LMFAO_EINVAL, "null column list of relation " + plan->P->rels[r].name);
   try {
     prepare_all(*S, columns, (hipStream_t)stream);
+    if (plan->P->opts.sizing == LMFAO_SIZING_EXACT && plan->P->opts.hash_slots <= 0)
+      exact_sizes(*S, (hipStream_t)stream);
   } catch (const PlanError& e) {
     return set_err(e.status, e.msg);
   } catch (const HipError& e) {
@@ -1934,6 +2126,29 @@ lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns,
 // Grows every hash table whose inserts overflowed (x4, up to twice its bound)
 // and refreshes the descriptors the kernels read.  Returns false when a
 // table is already at its largest size.
+// Reallocates hash table i at `cap` slots and points the run's fill steps and
+// the table's device descriptor at the new arrays.
+static void resize_hash(Prep& S, size_t i, int64_t cap) {
+  HashBuf& H = S.hashes[i];
+  const int64_t old_cap = H.cap;
+  H.cap = cap;
+  alloc_hash(S, H, old_cap);
+  S.steps[H.fill_step].dev = H.keys;
+  S.steps[H.fill_step].bytes = H.cap * 8;
+  S.steps[H.fill_step + 1].dev = H.cnt;
+  S.steps[H.fill_step + 1].bytes = H.cap * 8;
+  S.steps[H.fill_step + 2].dev = H.vals;
+  S.steps[H.fill_step + 2].bytes = H.cap * 8 * std::max(1, H.n_vals);
+  DHashOut d{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0};
+  HIP_OK(hipMemcpy(S.hash_dev + i, &d, sizeof d, hipMemcpyHostToDevice));
+}
+
+static int64_t bound_capacity(const HashBuf& H) {
+  int64_t top = 1;
+  while (top < 2 * H.bound) top <<= 1;
+  return std::max<int64_t>(top, 1024);
+}
+
 static bool grow_hashes(Prep& S, hipStream_t st) {
   std::vector<int32_t> ovf(S.hashes.size(), 0);
   HIP_OK(hipMemcpy(ovf.data(), S.hash_ovf, ovf.size() * 4, hipMemcpyDeviceToHost));
@@ -1941,23 +2156,43 @@ static bool grow_hashes(Prep& S, hipStream_t st) {
   for (size_t i = 0; i < S.hashes.size(); ++i) {
     if (!ovf[i]) continue;
     HashBuf& H = S.hashes[i];
-    int64_t top = 1;
-    while (top < 2 * H.bound) top <<= 1;
-    if (H.cap >= std::max<int64_t>(top, 1024)) return false;
-    const int64_t old_cap = H.cap;
-    H.cap = std::min(H.cap * 4, std::max<int64_t>(top, 1024));
-    alloc_hash(S, H, old_cap);
-    S.steps[H.fill_step].dev = H.keys;
-    S.steps[H.fill_step].bytes = H.cap * 8;
-    S.steps[H.fill_step + 1].dev = H.cnt;
-    S.steps[H.fill_step + 1].bytes = H.cap * 8;
-    S.steps[H.fill_step + 2].dev = H.vals;
-    S.steps[H.fill_step + 2].bytes = H.cap * 8 * std::max(1, H.n_vals);
-    DHashOut d{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0};
-    HIP_OK(hipMemcpy(S.hash_dev + i, &d, sizeof d, hipMemcpyHostToDevice));
+    const int64_t top = bound_capacity(H);
+    if (H.cap >= top) return false;
+    resize_hash(S, i, std::min(H.cap * 4, top));
     grown = true;
   }
   return grown;
+}
+
+// EXACT sizing: one whole run (its tables start at the BOUND capacity), then
+// every table is counted on the device and reallocated at twice its exact
+// group count; the run is part of lmfao_prepare, not of the timed lmfao_run.
+static void exact_sizes(Prep& S, hipStream_t st) {
+  if (S.hashes.empty()) return;
+  enqueue_run(S, st);
+  HIP_OK(hipStreamSynchronize(st));
+  int32_t flag = 0;
+  HIP_OK(hipMemcpy(&flag, S.err_flag, 4, hipMemcpyDeviceToHost));
+  while (flag & 8) {
+    if (!grow_hashes(S, st)) throw PlanError{LMFAO_EOVERFLOW, "a hash table at its largest size still overflowed"};
+    S.hash_regrowths++;
+    enqueue_run(S, st);
+    HIP_OK(hipStreamSynchronize(st));
+    HIP_OK(hipMemcpy(&flag, S.err_flag, 4, hipMemcpyDeviceToHost));
+  }
+  unsigned long long* cnt = (unsigned long long*)dalloc(S, S.hashes.size() * 8);
+  HIP_OK(hipMemsetAsync(cnt, 0, S.hashes.size() * 8, st));
+  for (size_t i = 0; i < S.hashes.size(); ++i) launch_count_keys(S.hashes[i].keys, S.hashes[i].cap, cnt + i, st);
+  std::vector<unsigned long long> groups(S.hashes.size());
+  HIP_OK(hipMemcpyAsync(groups.data(), cnt, groups.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  for (size_t i = 0; i < S.hashes.size(); ++i) {
+    HashBuf& H = S.hashes[i];
+    H.est = (double)groups[i];
+    int64_t cap = 1024;
+    while (cap < 2 * (int64_t)groups[i]) cap <<= 1;
+    if (cap != H.cap) resize_hash(S, i, cap);
+  }
 }
 
 // Replays the run as a HIP graph, capturing it first (on the library's own
@@ -2404,15 +2639,30 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
     first = false;
     static const char* kinds[] = {"fill",  "view_build", "scan",     "table_reduce", "contract", "merge",
                                   "image", "stage",      "contract", "merge",        "filter",   "finalize",
-                                  "scatter", "count_copy", "mult_check"};
-    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 15, "one name per step kind");
+                                  "scatter", "count_copy", "mult_check", "partition"};
+    static_assert(sizeof(kinds) / sizeof(kinds[0]) == 16, "one name per step kind");
     char tmp[512];
     snprintf(tmp, sizeof(tmp),
              "{\"name\":\"%s\",\"kind\":\"%s\",\"rows\":%lld,\"pieces\":%lld,\"alg_read_bytes\":%.0f,"
-             "\"alg_write_bytes\":%.0f,\"alg_flop\":%.0f,\"grid\":%d,\"grid_y\":%d,\"lds\":%d,\"lean\":%d}",
+             "\"alg_write_bytes\":%.0f,\"alg_flop\":%.0f,\"grid\":%d,\"grid_y\":%d,\"lds\":%d,\"lean\":%d",
              s.name.c_str(), kinds[s.kind], (long long)s.rows, (long long)s.pieces, s.alg_read, s.alg_write,
              s.alg_flop, s.grid, s.grid_y, s.lds, s.gen_fn ? 2 : s.fast);
     j += tmp;
+    if (s.relation >= 0) {
+      const RelDef& R = prep->P->rels[s.relation];
+      double pass = 0;
+      std::string pc, pw;
+      for (size_t k = 0; k < s.pass_cols.size(); ++k) {
+        const int w = R.dtypes[s.pass_cols[k]] == LMFAO_F64 ? 8 : 4;
+        pass += (double)R.n_rows * w;
+        pc += (k ? "," : "") + std::to_string(s.pass_cols[k]);
+        pw += (k ? "," : "") + std::to_string(w);
+      }
+      j += ",\"relation\":\"" + R.name + "\",\"relation_rows\":" + std::to_string(R.n_rows) +
+           ",\"pass_read_bytes\":" + std::to_string((long long)pass) + ",\"pass_cols\":[" + pc +
+           "],\"pass_col_bytes\":[" + pw + "]";
+    }
+    j += "}";
   }
   int64_t fill_bytes = 0;
   for (auto& s : prep->steps)
