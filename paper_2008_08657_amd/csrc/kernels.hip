@@ -2250,6 +2250,22 @@ __device__ __forceinline__ void part_row(const DPartCount& D, int64_t row, PartR
   if (nv > 3 && R.v3 >= 0 && R.v3 < D.vnkeys[3] && D.vcnt[3][R.v3] > 0) R.vok |= 8u;
 }
 
+// the same from the byte the slice pass stored (view keys recomputed only
+// when some output reads a view's code)
+__device__ __forceinline__ void part_row_w8(const DPartCount& D, int64_t row, PartRow& R) {
+  const uint32_t x = D.w8[row];
+  R.w = (int32_t)(x & 1u);
+  R.vok = x >> 1;
+  R.v0 = R.v1 = R.v2 = R.v3 = 0;
+  if (D.vkeys_needed) {
+    const int nv = D.n_views;
+    if (nv > 0) R.v0 = part_view_key(D, 0, row);
+    if (nv > 1) R.v1 = part_view_key(D, 1, row);
+    if (nv > 2) R.v2 = part_view_key(D, 2, row);
+    if (nv > 3) R.v3 = part_view_key(D, 3, row);
+  }
+}
+
 __device__ __forceinline__ int64_t part_vrow(const PartRow& R, int v) {
   return v == 0 ? R.v0 : v == 1 ? R.v1 : v == 2 ? R.v2 : R.v3;
 }
@@ -2273,23 +2289,39 @@ __device__ __forceinline__ int64_t part_cell(const DPartCount& D, int o, int64_t
   return bad ? -2 : cell;
 }
 
-// the cells of every output of the launch set for one row (-1 when the row
-// does not count or is outside the block's range); all loads are issued
-// before any counter is touched
-__device__ __forceinline__ void part_cells(const DPartCount& D, int64_t row, bool in, int32_t* slice, uint32_t* low,
-                                           bool multi_only) {
+// bits of a cell for the hashed outputs' grouping (a 64-bit finalising mix)
+__device__ __forceinline__ uint64_t part_mix(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
+// the cells of every output of the launch set for one row, and their slice
+// (-1 when the row does not count or is outside the block's range): dense
+// outputs slice by the cell's high bits, hashed ones by 9 bits of its mix;
+// all loads are issued before any counter is touched
+__device__ __forceinline__ void part_cells(const DPartCount& D, int64_t row, bool in, int32_t* slice, int64_t* cellv,
+                                           bool multi_only, bool first) {
   PartRow R;
-  part_row(D, in ? row : 0, R);
+  if (first) {
+    part_row(D, in ? row : 0, R);
+    if (in && D.w8) D.w8[row] = (uint8_t)((R.w ? 1u : 0u) | (R.vok << 1));
+  } else {
+    part_row_w8(D, in ? row : 0, R);
+  }
 #pragma unroll
   for (int o = 0; o < kPartOuts; ++o) {
     slice[o] = -1;
-    low[o] = 0;
+    cellv[o] = 0;
     if (o < D.n_out && in && (!multi_only || D.n_buckets[o] > 1)) {
       const int64_t cell = part_cell(D, o, row, R);
       if (cell == -2) atomicOr(D.err_flag, 2);
       if (cell >= 0) {
-        slice[o] = (int32_t)(cell >> kPartShift);
-        low[o] = (uint32_t)(cell & ((1 << kPartShift) - 1));
+        slice[o] = D.hashed[o] ? (int32_t)(part_mix((uint64_t)cell) >> 55) : (int32_t)(cell >> kPartShift);
+        cellv[o] = cell;
       }
     }
   }
@@ -2337,8 +2369,8 @@ __global__ void __launch_bounds__(kPartThreads) k_part_slices(const DPartCount* 
   for (int64_t base = r0; base < r1; base += blockDim.x) {
     const int64_t row = base + threadIdx.x;
     int32_t slice[kPartOuts];
-    uint32_t low[kPartOuts];
-    part_cells(D, row, row < r1, slice, low, true);
+    int64_t cellv[kPartOuts];
+    part_cells(D, row, row < r1, slice, cellv, true, true);
 #pragma unroll
     for (int o = 0; o < kPartOuts; ++o) {
       if (o >= D.n_out || D.n_buckets[o] <= 1) continue;
@@ -2354,18 +2386,18 @@ __global__ void __launch_bounds__(kPartThreads) k_part_slices(const DPartCount* 
       D.bcount[((int64_t)o * kPartMaxBuckets + b) * D.n_blocks + blockIdx.x] = bins[o * kPartMaxBuckets + b];
 }
 
-// pass 2: exclusive offsets over (slice, workgroup), one workgroup per output
+// pass 2a: per (output, slice), exclusive offsets of the workgroups' rows
+// within the slice and the slice total
 __global__ void __launch_bounds__(1024) k_part_offsets(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
-  const int o = blockIdx.x;
-  if (o >= D.n_out || D.n_buckets[o] <= 1) return;
+  const int o = blockIdx.y, b = blockIdx.x;
+  if (o >= D.n_out || b >= D.n_buckets[o] || D.n_buckets[o] <= 1) return;
   __shared__ uint32_t tmp[1024];
-  const int64_t n = (int64_t)D.n_buckets[o] * D.n_blocks;
-  uint32_t* a = D.bcount + (int64_t)o * kPartMaxBuckets * D.n_blocks;
+  uint32_t* a = D.bcount + ((int64_t)o * kPartMaxBuckets + b) * D.n_blocks;
   uint32_t carry = 0;
-  for (int64_t base = 0; base < n; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const uint32_t v = i < n ? a[i] : 0u;
+  for (int base = 0; base < D.n_blocks; base += 1024) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < D.n_blocks ? a[i] : 0u;
     tmp[threadIdx.x] = v;
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
@@ -2374,13 +2406,32 @@ __global__ void __launch_bounds__(1024) k_part_offsets(const DPartCount* __restr
       tmp[threadIdx.x] += x;
       __syncthreads();
     }
-    if (i < n) a[i] = carry + tmp[threadIdx.x] - v;
+    if (i < D.n_blocks) a[i] = carry + tmp[threadIdx.x] - v;
     carry += tmp[1023];
     __syncthreads();
   }
+  if (threadIdx.x == 0) D.btotal[(int64_t)o * kPartMaxBuckets + b] = carry;
+}
+
+// pass 2b: slice starts (exclusive scan of the slice totals), per output
+__global__ void __launch_bounds__(kPartMaxBuckets) k_part_bases(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  const int o = blockIdx.x;
+  if (o >= D.n_out || D.n_buckets[o] <= 1) return;
+  __shared__ uint32_t tmp[kPartMaxBuckets];
+  const int nb = D.n_buckets[o];
+  const uint32_t v = (int)threadIdx.x < nb ? D.btotal[(int64_t)o * kPartMaxBuckets + threadIdx.x] : 0u;
+  tmp[threadIdx.x] = v;
+  __syncthreads();
+  for (int d = 1; d < kPartMaxBuckets; d <<= 1) {
+    const uint32_t x = (int)threadIdx.x >= d ? tmp[threadIdx.x - d] : 0u;
+    __syncthreads();
+    tmp[threadIdx.x] += x;
+    __syncthreads();
+  }
   uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
-  for (int b = threadIdx.x; b <= D.n_buckets[o]; b += blockDim.x)
-    bs[b] = b < D.n_buckets[o] ? a[(int64_t)b * D.n_blocks] : carry;
+  if ((int)threadIdx.x < nb) bs[threadIdx.x] = tmp[threadIdx.x] - v;
+  if (threadIdx.x == 0) bs[nb] = tmp[kPartMaxBuckets - 1];
 }
 
 // pass 3: the low 15 bits of every counted row's cell, grouped by slice
@@ -2389,72 +2440,91 @@ __global__ void __launch_bounds__(kPartThreads) k_part_scatter(const DPartCount*
   __shared__ uint32_t cur[kPartOuts * kPartMaxBuckets];
   for (int o = 0; o < D.n_out; ++o)
     for (int b = threadIdx.x; b < D.n_buckets[o]; b += blockDim.x)
-      cur[o * kPartMaxBuckets + b] = D.bcount[((int64_t)o * kPartMaxBuckets + b) * D.n_blocks + blockIdx.x];
+      cur[o * kPartMaxBuckets + b] = D.bstart[(int64_t)o * (kPartMaxBuckets + 1) + b] +
+                                     D.bcount[((int64_t)o * kPartMaxBuckets + b) * D.n_blocks + blockIdx.x];
   __syncthreads();
   const int64_t r0 = (int64_t)blockIdx.x * D.rows_per_block;
   const int64_t r1 = min(D.n_rows, r0 + D.rows_per_block);
   for (int64_t base = r0; base < r1; base += blockDim.x) {
     const int64_t row = base + threadIdx.x;
     int32_t slice[kPartOuts];
-    uint32_t low[kPartOuts];
-    part_cells(D, row, row < r1, slice, low, true);
+    int64_t cellv[kPartOuts];
+    part_cells(D, row, row < r1, slice, cellv, true, false);
 #pragma unroll
     for (int o = 0; o < kPartOuts; ++o) {
       if (o >= D.n_out || D.n_buckets[o] <= 1) continue;
       int64_t pos = -1;
       if (D.n_buckets[o] <= kPartWaveSlices) pos = wave_reserve(&cur[o * kPartMaxBuckets], slice[o]);
       else if (slice[o] >= 0) pos = atomicAdd(&cur[o * kPartMaxBuckets + slice[o]], 1u);
-      if (pos >= 0 && pos < D.n_rows) D.part[(int64_t)o * D.n_rows + pos] = (uint16_t)low[o];
+      if (pos < 0 || pos >= D.n_rows) continue;
+      if (D.hashed[o]) D.part64[(int64_t)o * D.n_rows + pos] = (uint64_t)cellv[o];
+      else D.part[(int64_t)o * D.n_rows + pos] = (uint16_t)(cellv[o] & ((1 << kPartShift) - 1));
     }
   }
 }
 
-// pass 4: every slice counted in LDS (2^15 counters), nonzero counters added
-// to the output table; outputs of a single slice are counted from the rows
+// pass 4, dense outputs of several slices: tiles of kPartTile partitioned
+// entries (balanced whatever the slice sizes), each slice piece of a tile
+// counted in LDS (2^15 counters) and its nonzero counters added to the
+// output's table
 constexpr int kPartHistThreads = 1024;
 __global__ void __launch_bounds__(kPartHistThreads) k_part_hist(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
   extern __shared__ uint32_t bins[];
   const int o = blockIdx.y;
-  const int64_t t0 = (int64_t)blockIdx.x * kPartTile;
+  if (D.hashed[o] || D.n_buckets[o] <= 1) return;
   constexpr int kSlice = 1 << kPartShift;
-  if (D.n_buckets[o] > 1) {
-    const uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
-    const int nb = D.n_buckets[o];
-    const int64_t total = bs[nb];
-    if (t0 >= total) return;
-    const int64_t t1 = min(total, t0 + kPartTile);
-    int b = 0;
-    while (b < nb && (int64_t)bs[b + 1] <= t0) ++b;
-    const uint16_t* part = D.part + (int64_t)o * D.n_rows;
-    for (; b < nb && (int64_t)bs[b] < t1; ++b) {
-      const int64_t s0 = max(t0, (int64_t)bs[b]), s1 = min(t1, (int64_t)bs[b + 1]);
-      if (s0 >= s1) continue;
-      for (int i = threadIdx.x; i < kSlice; i += blockDim.x) bins[i] = 0;
-      __syncthreads();
-      // four entries per thread per round: the loads are in flight together
-      for (int64_t i = s0 + threadIdx.x; i < s1; i += 4 * (int64_t)blockDim.x) {
-        uint32_t e[4];
+  const uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
+  const int nb = D.n_buckets[o];
+  const int64_t total = bs[nb];
+  const int64_t t0 = (int64_t)blockIdx.x * kPartTile;
+  if (t0 >= total) return;
+  const int64_t t1 = min(total, t0 + kPartTile);
+  int b = 0;
+  while (b < nb && (int64_t)bs[b + 1] <= t0) ++b;
+  const uint16_t* part = D.part + (int64_t)o * D.n_rows;
+  for (; b < nb && (int64_t)bs[b] < t1; ++b) {
+    const int64_t s0 = max(t0, (int64_t)bs[b]), s1 = min(t1, (int64_t)bs[b + 1]);
+    if (s0 >= s1) continue;
+    for (int i = threadIdx.x; i < kSlice; i += blockDim.x) bins[i] = 0;
+    __syncthreads();
+    // four entries per thread per round: the loads are in flight together
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += 4 * (int64_t)blockDim.x) {
+      uint32_t e[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t k = i + (int64_t)u * blockDim.x;
-          e[u] = k < s1 ? (uint32_t)part[k] : 0xffffffffu;
-        }
+      for (int u = 0; u < 4; ++u) {
+        const int64_t k = i + (int64_t)u * blockDim.x;
+        e[u] = k < s1 ? (uint32_t)part[k] : 0xffffffffu;
+      }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (e[u] != 0xffffffffu) atomicAdd(&bins[e[u]], 1u);
-      }
-      __syncthreads();
-      for (int i = threadIdx.x; i < kSlice; i += blockDim.x) {
-        const uint32_t v = bins[i];
-        const int64_t cell = ((int64_t)b << kPartShift) + i;
-        if (v && cell < D.n_cells[o]) atomicAdd((unsigned long long*)&D.out_cnt[o][cell], (unsigned long long)v);
-      }
-      __syncthreads();
+      for (int u = 0; u < 4; ++u)
+        if (e[u] != 0xffffffffu) atomicAdd(&bins[e[u]], 1u);
     }
-    return;
+    __syncthreads();
+    // a tile that holds the whole slice owns its cells: plain stores
+    const bool whole = s0 == (int64_t)bs[b] && s1 == (int64_t)bs[b + 1];
+    int64_t* out = D.out_cnt[o] + ((int64_t)b << kPartShift);
+    const int64_t n = min((int64_t)kSlice, D.n_cells[o] - ((int64_t)b << kPartShift));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint32_t v = bins[i];
+      if (!v) continue;
+      if (whole) out[i] = (int64_t)v;
+      else atomicAdd((unsigned long long*)&out[i], (unsigned long long)v);
+    }
+    __syncthreads();
   }
+}
+
+// pass 4, dense outputs of one slice: tiles of rows counted in LDS straight
+// from the columns, nonzero counters added to the output's table
+__global__ void __launch_bounds__(kPartHistThreads) k_part_hist1(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  extern __shared__ uint32_t bins[];
+  const int o = blockIdx.y;
+  if (D.hashed[o] || D.n_buckets[o] > 1) return;
+  const int64_t t0 = (int64_t)blockIdx.x * kPartTile;
   if (t0 >= D.n_rows) return;
+  constexpr int kSlice = 1 << kPartShift;
   const int64_t t1 = min(D.n_rows, t0 + kPartTile);
   for (int i = threadIdx.x; i < kSlice; i += blockDim.x) bins[i] = 0;
   __syncthreads();
@@ -2466,7 +2536,7 @@ __global__ void __launch_bounds__(kPartHistThreads) k_part_hist(const DPartCount
       cell[u] = -1;
       if (rr < t1) {
         PartRow R;
-        part_row(D, rr, R);
+        part_row_w8(D, rr, R);
         cell[u] = part_cell(D, o, rr, R);
       }
     }
@@ -2483,17 +2553,144 @@ __global__ void __launch_bounds__(kPartHistThreads) k_part_hist(const DPartCount
   }
 }
 
+// pass 4 of hashed outputs, one workgroup per group of cells: the group is
+// ordered by sub-group (a counting sort on the next hash bits, into part64b;
+// sub-groups of about 3072 cells), then every sub-group is counted in an LDS
+// hash table (8192 slots) and its (cell, count) pairs are written to the
+// group's own region of the output's table (cap / 512 slots, positions from
+// an LDS counter: no global atomics).  A full LDS table or a full region sets
+// the table's overflow flag (the run is repeated with a larger table).
+constexpr int kPartHashSlots = 8192;
+constexpr int kPartSubCells = 3072;
+constexpr int kPartMaxSub = 1024;
+constexpr int kPartHashLds = kPartHashSlots * 12 + (2 * kPartMaxSub + 2) * 4;
+__global__ void __launch_bounds__(1024) k_part_hash(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  const int o = blockIdx.y;
+  if (!D.hashed[o]) return;
+  extern __shared__ unsigned long long lkeys[];
+  uint32_t* lcnt = (uint32_t*)(lkeys + kPartHashSlots);
+  uint32_t* suboff = lcnt + kPartHashSlots;     // [S + 1]
+  uint32_t* cursor = suboff + kPartMaxSub + 1;  // [S]; cursor[kPartMaxSub] = entries written
+  const DHashOut& H = D.htab[D.hidx[o]];
+  const int64_t cap = H.mask + 1;
+  const int b = blockIdx.x;
+  const int64_t region = cap / kPartHashBuckets;
+  const int64_t region0 = (int64_t)b * region;
+  const uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
+  const int64_t s0 = bs[b], s1 = bs[b + 1];
+  if (s0 >= s1) return;
+  int S = 1, sbits = 0;
+  while (S < kPartMaxSub && (int64_t)S * kPartSubCells < s1 - s0) {
+    S <<= 1;
+    ++sbits;
+  }
+  const uint64_t* part = D.part64 + (int64_t)o * D.n_rows;
+  uint64_t* sorted = D.part64b + (int64_t)o * D.n_rows;
+  const int lane = (int)__lane_id();
+  constexpr unsigned long long kEmpty = ~0ull;
+  auto sub_of = [&](uint64_t cell) {
+    return sbits ? (int)((part_mix(cell) >> (55 - sbits)) & (uint64_t)(S - 1)) : 0;
+  };
+  // counting sort of the group by sub-group
+  for (int i = threadIdx.x; i <= S; i += blockDim.x) suboff[i] = 0;
+  if (threadIdx.x == 0) cursor[kPartMaxSub] = 0;
+  __syncthreads();
+  if (S > 1) {
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) atomicAdd(&suboff[sub_of(part[i]) + 1], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int i = 1; i <= S; ++i) suboff[i] += suboff[i - 1];
+    __syncthreads();
+    for (int i = threadIdx.x; i < S; i += blockDim.x) cursor[i] = suboff[i];
+    __syncthreads();
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+      const uint64_t cell = part[i];
+      const uint32_t pos = atomicAdd(&cursor[sub_of(cell)], 1u);
+      sorted[s0 + pos] = cell;
+    }
+  } else {
+    if (threadIdx.x == 0) suboff[1] = (uint32_t)(s1 - s0);
+  }
+  __syncthreads();
+  const uint64_t* src = S > 1 ? sorted : part;
+  for (int sub = 0; sub < S; ++sub) {
+    const int64_t r0 = s0 + suboff[sub], r1 = s0 + suboff[sub + 1];
+    if (r0 >= r1) continue;
+    for (int i = threadIdx.x; i < kPartHashSlots; i += blockDim.x) {
+      lkeys[i] = kEmpty;
+      lcnt[i] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+      const uint64_t cell = src[i];
+      uint32_t slot = (uint32_t)part_mix(cell) & (kPartHashSlots - 1);
+      bool done = false;
+      for (int probe = 0; probe < kPartHashSlots && !done; ++probe) {
+        const unsigned long long prev = atomicCAS(&lkeys[slot], kEmpty, (unsigned long long)cell);
+        if (prev == kEmpty || prev == cell) {
+          atomicAdd(&lcnt[slot], 1u);
+          done = true;
+        }
+        slot = (slot + 1) & (kPartHashSlots - 1);
+      }
+      if (!done) {
+        atomicOr(H.ovf, 1);
+        atomicOr(D.err_flag, 8);
+      }
+    }
+    __syncthreads();
+    for (int base = 0; base < kPartHashSlots; base += blockDim.x) {
+      const int slot = base + threadIdx.x;
+      const unsigned long long key = lkeys[slot];
+      const bool occ = key != kEmpty;
+      const unsigned long long m = __ballot(occ);
+      uint32_t p0 = 0;
+      if (lane == 0 && m) p0 = atomicAdd(&cursor[kPartMaxSub], (uint32_t)__popcll(m));
+      p0 = __shfl(p0, 0, 64);
+      if (occ) {
+        const int64_t pos = (int64_t)p0 + __popcll(m & ((1ull << lane) - 1ull));
+        if (pos < region) {
+          H.keys[region0 + pos] = key + 1ull;
+          H.cnt[region0 + pos] = (int64_t)lcnt[slot];
+        } else {
+          atomicOr(H.ovf, 1);
+          atomicOr(D.err_flag, 8);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 void launch_part_count(const DPartCount* d, const DPartCount& h, hipStream_t s) {
   if (h.n_rows <= 0 || h.n_out <= 0) return;
-  bool multi = false;
-  for (int o = 0; o < h.n_out; ++o) multi |= h.n_buckets[o] > 1;
+  bool multi = false, hashed = false;
+  for (int o = 0; o < h.n_out; ++o) {
+    multi |= h.n_buckets[o] > 1;
+    hashed |= h.hashed[o] != 0;
+  }
+  bool single = false, dense_multi = false;
+  int nb_max = 1;
+  for (int o = 0; o < h.n_out; ++o) {
+    single |= !h.hashed[o] && h.n_buckets[o] <= 1;
+    dense_multi |= !h.hashed[o] && h.n_buckets[o] > 1;
+    nb_max = std::max(nb_max, h.n_buckets[o]);
+  }
+  // the slice pass also stores every row's weight byte for the later passes
+  hipLaunchKernelGGL(k_part_slices, dim3(h.n_blocks), dim3(kPartThreads), 0, s, d);
   if (multi) {
-    hipLaunchKernelGGL(k_part_slices, dim3(h.n_blocks), dim3(kPartThreads), 0, s, d);
-    hipLaunchKernelGGL(k_part_offsets, dim3(h.n_out), dim3(1024), 0, s, d);
+    hipLaunchKernelGGL(k_part_offsets, dim3(nb_max, h.n_out), dim3(1024), 0, s, d);
+    hipLaunchKernelGGL(k_part_bases, dim3(h.n_out), dim3(kPartMaxBuckets), 0, s, d);
     hipLaunchKernelGGL(k_part_scatter, dim3(h.n_blocks), dim3(kPartThreads), 0, s, d);
   }
   const int tiles = (int)((h.n_rows + kPartTile - 1) / kPartTile);
-  hipLaunchKernelGGL(k_part_hist, dim3(tiles, h.n_out), dim3(kPartHistThreads), (1 << kPartShift) * 4, s, d);
+  if (dense_multi)
+    hipLaunchKernelGGL(k_part_hist, dim3(tiles, h.n_out), dim3(kPartHistThreads), (1 << kPartShift) * 4, s, d);
+  if (single)
+    hipLaunchKernelGGL(k_part_hist1, dim3(tiles, h.n_out), dim3(kPartHistThreads), (1 << kPartShift) * 4, s, d);
+  if (hashed)
+    hipLaunchKernelGGL(k_part_hash, dim3(kPartHashBuckets, h.n_out), dim3(1024), kPartHashLds, s, d);
 }
 
 // largest count of each listed view (grid-stride, one atomicMax per block)

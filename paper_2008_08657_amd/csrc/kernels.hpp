@@ -107,6 +107,7 @@ constexpr int kPartOuts = 16;
 constexpr int kPartViews = 4;
 constexpr int kPartShift = 15;
 constexpr int kPartMaxBuckets = 512;
+constexpr int kPartMaxBlocks = 4096;       // workgroups of the slice count and scatter passes
 struct DPartCount {
   int64_t n_rows;
   int64_t rows_per_block;
@@ -132,11 +133,24 @@ struct DPartCount {
   int64_t n_cells[kPartOuts];
   int32_t n_buckets[kPartOuts];
   int64_t* out_cnt[kPartOuts];
-  uint32_t* bcount;                        // [out][bucket][block] counts, then exclusive offsets
+  uint32_t* bcount;                        // [out][bucket][block] counts, then offsets within the bucket
+  uint32_t* btotal;                        // [out][bucket] rows per bucket
   uint32_t* bstart;                        // [out][kPartMaxBuckets + 1] bucket starts in part
   uint16_t* part;                          // [out][n_rows] low 15 bits of the cell
+  // outputs kept in hash tables: rows are grouped by 9 bits of a hash of the
+  // cell, every (group, sub-group) counted in an LDS hash table and its
+  // (cell, count) pairs written to the group's region of the output's table
+  int32_t hashed[kPartOuts];
+  int32_t hidx[kPartOuts];                 // index of the output's table in htab
+  const DHashOut* htab;
+  uint8_t* w8;                             // [n_rows] per row: bit 0 filter weight, bits 1.. the views'
+                                           // 0/1 counts (written by the slice pass, read by the others)
+  int32_t vkeys_needed;                    // some output's key is a code carried by a view
+  uint64_t* part64;                        // [out][n_rows] cells of hashed outputs
+  uint64_t* part64b;                       // the same cells, ordered by sub-group within each group
   int32_t* err_flag;
 };
+constexpr int kPartHashBuckets = 512;
 // the three partition launches (count, offsets, scatter) and the LDS count
 void launch_part_count(const DPartCount* d, const DPartCount& h, hipStream_t s);
 

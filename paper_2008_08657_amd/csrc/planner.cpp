@@ -1317,10 +1317,11 @@ static void split_group(Plan& P, int gi, size_t from) {
 }
 
 // A query whose every aggregate is SUM(1), rooted at `node`, grouped by at
-// most 3 attributes into a dense table larger than a scan keeps in LDS, whose
-// group-by attributes are columns of the node or carried by the single-valued
-// views into it: its table is counted by radix partition (a slice of the key
-// space at a time, in LDS) instead of by global atomics from the scan.
+// most 3 attributes into a table larger than a scan keeps in LDS (dense, or a
+// hash table past 2^24 cells), whose group-by attributes are columns of the
+// node or carried by the single-valued views into it: its table is counted by
+// radix partition (a slice of the key space, or of a hash of the key, at a
+// time, in LDS) instead of by global atomics from a scan or a row pass.
 static bool partition_eligible(const Plan& P, int qid, int node) {
   const QueryDef& Q = P.queries[qid];
   if (Q.root != node || Q.groupby.empty() || Q.groupby.size() > 3) return false;
@@ -1331,7 +1332,9 @@ static bool partition_eligible(const Plan& P, int qid, int node) {
     if (P.attrs[a].domain <= 0) return false;
     cells *= (double)P.attrs[a].domain;
   }
-  if (cells <= (double)kLdsTableMax || cells > (double)kDenseRowsMax) return false;
+  // dense tables past what a scan keeps in LDS, and hash tables (key spaces
+  // past 2^24 cells) of cells below 2^62
+  if (cells <= (double)kLdsTableMax || cells >= 4.6e18) return false;
   if (Q.in_view.size() > 4) return false;
   for (auto& kv : Q.in_view)
     if (!P.views[kv.second].unique || P.views[kv.second].key.size() > 2) return false;

@@ -625,7 +625,7 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       }
     }
     d.n_out = (int)(end - base);
-    bool multi = false;
+    bool any_hashed = false, any_dense_multi = false;
     std::vector<DCountCopy> copies;
     double rows_bytes = 0;
     for (int o = 0; o < d.n_out; ++o) {
@@ -634,9 +634,20 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       const OutBuf& B = S.qout[qid];
       d.out_cnt[o] = B.cnt;
       d.n_cells[o] = B.n_rows;
-      d.n_buckets[o] = (int)((B.n_rows + (1 << kPartShift) - 1) >> kPartShift);
-      if (d.n_buckets[o] > kPartMaxBuckets) throw PlanError{LMFAO_EINVAL, "internal: partitioned table too large"};
-      multi |= d.n_buckets[o] > 1;
+      if (B.hash >= 0) {
+        d.hashed[o] = 1;
+        d.hidx[o] = B.hash;
+        d.n_buckets[o] = kPartHashBuckets;
+        any_hashed = true;
+        // SUM(1) components equal the count: added when the table is read
+        HashBuf& H = S.hashes[B.hash];
+        H.count_copies.clear();
+        for (int k = 0; k < B.n_vals; ++k) H.count_copies.push_back(k);
+      } else {
+        d.n_buckets[o] = (int)((B.n_rows + (1 << kPartShift) - 1) >> kPartShift);
+        if (d.n_buckets[o] > kPartMaxBuckets) throw PlanError{LMFAO_EINVAL, "internal: partitioned table too large"};
+        any_dense_multi |= d.n_buckets[o] > 1;
+      }
       for (auto& kv : Q.in_view) {
         const int v = (int)(std::find(views.begin(), views.end(), kv.second) - views.begin());
         d.vmask[o] |= 1u << v;
@@ -663,7 +674,7 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
           if (d.ksrc[o][k] < 0) throw PlanError{LMFAO_EINVAL, "internal: partitioned key attribute not found"};
         }
       }
-      if (B.n_vals > 0) {
+      if (B.n_vals > 0 && B.hash < 0) {
         DCountCopy cc{};
         cc.cnt = B.cnt;
         cc.vals = (double*)B.vals;
@@ -676,14 +687,21 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       }
     }
     const int64_t n = R.n_rows;
-    d.rows_per_block = std::max<int64_t>(65536, ((n + 1023) / 1024 + 255) / 256 * 256);
+    d.rows_per_block = std::max<int64_t>(16384, ((n + kPartMaxBlocks - 1) / kPartMaxBlocks + 255) / 256 * 256);
     d.n_blocks = (int)std::max<int64_t>(1, (n + d.rows_per_block - 1) / d.rows_per_block);
     d.bcount = (uint32_t*)dalloc(S, (size_t)d.n_out * kPartMaxBuckets * d.n_blocks * 4);
     d.bstart = (uint32_t*)dalloc(S, (size_t)d.n_out * (kPartMaxBuckets + 1) * 4);
-    d.part = multi ? (uint16_t*)dalloc(S, (size_t)d.n_out * std::max<int64_t>(n, 1) * 2) : nullptr;
+    d.btotal = (uint32_t*)dalloc(S, (size_t)d.n_out * kPartMaxBuckets * 4);
+    d.part = any_dense_multi ? (uint16_t*)dalloc(S, (size_t)d.n_out * std::max<int64_t>(n, 1) * 2) : nullptr;
+    d.w8 = (uint8_t*)dalloc(S, (size_t)std::max<int64_t>(n, 1));
+    for (int o = 0; o < d.n_out; ++o)
+      for (int k = 0; k < d.nkey[o]; ++k) d.vkeys_needed |= d.ksrc[o][k] >= 0 ? 1 : 0;
+    d.part64 = any_hashed ? (uint64_t*)dalloc(S, (size_t)d.n_out * std::max<int64_t>(n, 1) * 8) : nullptr;
+    d.part64b = any_hashed ? (uint64_t*)dalloc(S, (size_t)d.n_out * std::max<int64_t>(n, 1) * 8) : nullptr;
+    d.htab = S.hash_dev;
     d.err_flag = S.err_flag;
     Step s;
-    s.name = gname + ":partition";
+    s.name = gname + ":partition" + (base ? std::to_string(base / kPartOuts) : std::string());
     s.kind = 15;
     s.dev = upload(S, d, st);
     s.part = d;
@@ -693,7 +711,9 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
     // counts written once per cell (the partition round trip is the kernel's)
     std::set<int> rc(need.begin(), need.end());
     for (int c : rc) s.alg_read += (double)n * 4;
-    for (int o = 0; o < d.n_out; ++o) s.alg_write += (double)d.n_cells[o] * 8;
+    for (int o = 0; o < d.n_out; ++o)
+      s.alg_write += d.hashed[o] ? (double)std::min<int64_t>(S.hashes[d.hidx[o]].bound, n) * 16
+                                 : (double)d.n_cells[o] * 8;
     s.relation = r;
     s.pass_cols.clear();
     for (int c : rc) s.pass_cols.push_back(source_column(P, r, c));

@@ -238,10 +238,25 @@ def test_wide_chain_groups_are_split_to_fit_the_kernels():
     for g in d["groups"]:
         by_rel.setdefault(g["node"], []).append(g)
     assert len(by_rel["R1"]) > 2
-    assert any((g.get("program") or {}).get("row_pieces") for g in by_rel["R1"])
+    # SUM(1) group-bys whose table a scan cannot keep in LDS (dense past 12k
+    # cells, or hashed) are counted by radix partition, in groups of their own
+    part = [o["id"] for g in by_rel["R1"] if g.get("partitioned") for o in g["outputs"]]
+    doms = p["domains"]
+    for qi in part:
+        cells = 1
+        for a in p["batch"][qi]["groupby"]:
+            cells *= doms[a]
+        assert cells > 12288
+    assert any(len(p["batch"][qi]["groupby"]) == 2 and
+               doms[p["batch"][qi]["groupby"][0]] * doms[p["batch"][qi]["groupby"][1]] > 1 << 24 for qi in part)
     for g in d["groups"]:
         prog = g.get("program") or {}
         assert len(prog.get("scan_cols", [])) <= 16
+    # without partitioning, hashed outputs are evaluated row by row
+    d = E.Plan(p, precision="f32", policy="fact", partition=False).describe()
+    r1 = [g for g in d["groups"] if g["node"] == "R1"]
+    assert not any(g.get("partitioned") for g in d["groups"])
+    assert any((g.get("program") or {}).get("row_pieces") for g in r1)
 
 
 @pytest.mark.parametrize("kw", [{"scan_blocks": -1}, {"contract_splits": -4}])
