@@ -52,6 +52,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 HBM_PEAK_GBS = 8000.0
+T0 = time.perf_counter()
+
+
+def _log(msg):
+    """A progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench {time.perf_counter() - T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def _cpu_model():
@@ -75,9 +81,11 @@ def _cpu_baseline(problem, target_s=15.0):
     n_aggs = sum(len(q["aggs"]) for q in problem["batch"])
     st = {}
     cal = max(1000, n_fact // 100)
+    _log(f"cpu baseline: calibration on {cal} {fact['name']} rows")
     tierb.evaluate(problem, root=fact["name"], root_rows=cal, stats=st)
     rows = int(min(n_fact, max(cal, cal * target_s / max(st["seconds"], 1e-3))))
     st = {}
+    _log(f"cpu baseline: {rows} {fact['name']} rows")
     tierb.evaluate(problem, root=fact["name"], root_rows=rows, stats=st)
     return {"value": rows * n_aggs / st["seconds"], "unit": "join-tuple*aggregates/s", "cores": st["threads"],
             "kind": "oracle", "seconds": round(st["seconds"], 3),
@@ -216,6 +224,7 @@ def measure(E, W, config, args, full=True):
     plain form and (with hash tables) the sizing comparison."""
     import torch
     t_gen = time.perf_counter()
+    _log(f"{config}: generating")
     bw = W.bench_workload(config, args.scale)
     problem = bw["problem"]
     if args.precision and full:
@@ -231,12 +240,14 @@ def measure(E, W, config, args, full=True):
     plan = E.Plan(problem, **opts)
     cols = E.device_columns(problem)
     torch.cuda.synchronize()
+    _log(f"{config}: prepare")
     t_prep = time.perf_counter()
     prep = E.Prepared(plan, cols)
     t_prep = time.perf_counter() - t_prep
     del cols
     torch.cuda.empty_cache()
 
+    _log(f"{config}: warm-up and timed steps")
     for _ in range(args.warmup):
         prep.run(sync=False)
     prep.run(sync=True)   # checks the kernels' error flags (and regrows a hash table that overflowed)
@@ -274,6 +285,7 @@ def measure(E, W, config, args, full=True):
     }
     if not args.no_check and args.scale == 1.0:
         t0 = time.perf_counter()
+        _log(f"{config}: comparing with the golden results")
         rec["accuracy"] = _accuracy(prep, config, problem)
         if rec["accuracy"] is not None:
             rec["accuracy"]["seconds"] = round(time.perf_counter() - t0, 1)
@@ -284,6 +296,7 @@ def measure(E, W, config, args, full=True):
     if has_hash and args.sizing_steps > 0:
         rec["hash_sizing"] = _sizing(E, W, bw, args)
     if args.plain_steps > 0:
+        _log(f"{config}: plain per-view form")
         cols = E.device_columns(problem)
         pplan = E.Plan(problem, **dict(W.bench_plan_options(bw, form="per_view", graph=False), codegen=False))
         pprep = E.Prepared(pplan, cols)
@@ -308,6 +321,7 @@ def _sizing(E, W, bw, args):
     problem = bw["problem"]
     out, digests = {}, {}
     for sizing in ("learned", "bound", "exact"):
+        _log(f"sizing comparison: {sizing}")
         cols = E.device_columns(problem)
         plan = E.Plan(problem, **dict(W.bench_plan_options(dict(bw, sizing=sizing), graph=not args.no_graph)))
         t0 = time.perf_counter()
