@@ -40,6 +40,7 @@ constexpr int kHistMax = 1024;     // largest code domain kept per piece
 constexpr int kScanWaves = 8;      // wavefronts per scan block (each holds its own histograms)
 constexpr int kLdsBytes = 160 * 1024;            // LDS of one compute unit
 constexpr int64_t kLdsTableMax = 12288;          // int32 count entries privatized in LDS
+constexpr int64_t kPartMinCells = 1;             // smallest SUM(1) table moved from a scan to the partition count
 constexpr int kTriangle = (kMaxAtoms + 1) * (kMaxAtoms + 2) / 2;  // incl. (1,1)
 constexpr int64_t kDenseRowsMax = (int64_t)1 << 24;  // larger key spaces go to hash tables
 

@@ -2217,11 +2217,29 @@ void launch_count_keys(const unsigned long long* keys, int64_t n, unsigned long 
 }
 
 // ---------------------------------------------------------------------------
-// radix-partitioned counting of large dense tables
+// radix-partitioned counting of large group-by tables of SUM(1)
 // ---------------------------------------------------------------------------
-constexpr int kPartThreads = 256;
-constexpr int64_t kPartTile = (int64_t)1 << 20;   // partitioned entries (or rows) one counting workgroup takes
-constexpr int kPartWaveSlices = 8;                 // up to this many slices: wavefront-aggregated LDS atomics
+// Every launch set runs, in order:
+//   k_part_w8          per row one byte: filter weight and the views' 0/1 counts
+//   k_part_direct      tables of one slice (at most 2^15 cells): a chunk of rows
+//                      per workgroup counted in LDS straight from the key columns
+//   k_part_tile        tables of several slices and hashed tables: a tile of
+//                      rows per workgroup, its entries (low 15 bits of the cell,
+//                      or the whole cell) ordered by slice in LDS and written
+//                      back contiguously, with the tile's slice offsets
+//   k_part_bases       entries per slice summed over tiles, slice starts
+//   k_part_slice_count one workgroup per (slice, chunk of tiles): the slice's
+//                      segments of every tile counted in LDS
+//   k_part_reduce      per-chunk partial tables summed into the output
+//   k_part_hash        hashed tables: one workgroup per group of cells
+// No pass scatters single entries to global memory and no pass adds to a
+// global counter per row, so the counting runs at the rate of the key-column
+// reads and the contiguous entry round trip.
+constexpr int kPartSlice = 1 << kPartShift;        // cells one LDS table holds
+constexpr int kPartTileThreads = 1024;
+constexpr int kPartCountThreads = 1024;
+constexpr int kPartDirectUnroll = 8;               // rows per thread in flight in the direct count (int32 cells)
+constexpr int kPartSegUnroll = 8;                  // entries per lane in flight in the segment count
 
 struct PartRow {
   int64_t v0, v1, v2, v3;   // the row's key in each view (named fields: kept in registers)
@@ -2250,8 +2268,8 @@ __device__ __forceinline__ void part_row(const DPartCount& D, int64_t row, PartR
   if (nv > 3 && R.v3 >= 0 && R.v3 < D.vnkeys[3] && D.vcnt[3][R.v3] > 0) R.vok |= 8u;
 }
 
-// the same from the byte the slice pass stored (view keys recomputed only
-// when some output reads a view's code)
+// the same from the byte k_part_w8 stored (view keys recomputed only when
+// some output reads a view's code)
 __device__ __forceinline__ void part_row_w8(const DPartCount& D, int64_t row, PartRow& R) {
   const uint32_t x = D.w8[row];
   R.w = (int32_t)(x & 1u);
@@ -2289,6 +2307,95 @@ __device__ __forceinline__ int64_t part_cell(const DPartCount& D, int o, int64_t
   return bad ? -2 : cell;
 }
 
+// the cell of output o for a row in range, -1 otherwise; a key outside its
+// domain gives -1 and sets *bad (no side effect here, so that the callers'
+// loads of several rows stay in flight together)
+__device__ __forceinline__ int64_t part_row_cell(const DPartCount& D, int o, int64_t row, bool in, bool* bad) {
+  if (!in) return -1;
+  PartRow R;
+  part_row_w8(D, row, R);
+  const int64_t cell = part_cell(D, o, row, R);
+  *bad |= cell == -2;
+  return cell < 0 ? -1 : cell;
+}
+
+// The cells of output o for U rows first + u * stride (rows at or past r_end
+// give -1), with every load of the batch issued before any is used: row
+// indices are clamped into range so that no load sits behind a branch.
+// Outputs whose keys are all columns of the relation take this straight
+// path; keys carried by views go through part_row_w8 and part_cell, a row
+// at a time.  C is int32_t for dense tables (at most 2^24 cells) and
+// int64_t for hashed ones.
+template <int U, typename C>
+__device__ __forceinline__ void part_load_cells(const DPartCount& D, int o, int32_t first, int32_t stride,
+                                                int32_t r_end, C (&cell)[U], bool& bad) {
+  const int32_t last = r_end - 1;
+  if (!D.keys_cols[o]) {
+#pragma unroll 1
+    for (int u = 0; u < U; ++u) {
+      const int32_t r = first + u * stride;
+      const C v = (C)part_row_cell(D, o, r < r_end ? r : last, r < r_end, &bad);
+#pragma unroll
+      for (int j = 0; j < U; ++j)   // keeps cell[] in registers (no dynamic index)
+        if (j == u) cell[j] = v;
+    }
+    return;
+  }
+  uint32_t wb[U];
+  int32_t k0[U], k1[U], k2[U];
+  {
+    const uint8_t* w8 = D.w8;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t r = first + u * stride;
+      wb[u] = w8[r < r_end ? r : last];
+    }
+  }
+  const int nk = D.nkey[o];
+  {
+    const int32_t* c = D.kcol[o][0];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t r = first + u * stride;
+      k0[u] = c[r < r_end ? r : last];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) k1[u] = k2[u] = 0;
+  if (nk > 1) {
+    const int32_t* c = D.kcol[o][1];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t r = first + u * stride;
+      k1[u] = c[r < r_end ? r : last];
+    }
+  }
+  if (nk > 2) {
+    const int32_t* c = D.kcol[o][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t r = first + u * stride;
+      k2[u] = c[r < r_end ? r : last];
+    }
+  }
+  const uint32_t vm = D.vmask[o];
+  const int64_t d0 = D.kdom[o][0], d1 = nk > 1 ? D.kdom[o][1] : 1, d2 = nk > 2 ? D.kdom[o][2] : 1;
+  const int64_t s0 = D.kstride[o][0], s1 = nk > 1 ? D.kstride[o][1] : 0, s2 = nk > 2 ? D.kstride[o][2] : 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const bool in = first + u * stride < r_end;
+    const bool counts = in && (wb[u] & 1u) && !(vm & ~(wb[u] >> 1));
+    const bool out = k0[u] < 0 || k0[u] >= d0 || k1[u] < 0 || k1[u] >= d1 || k2[u] < 0 || k2[u] >= d2;
+    bad |= counts && out;
+    if (sizeof(C) == 4)
+      cell[u] = counts && !out ? (C)((uint32_t)k0[u] * (uint32_t)s0 + (uint32_t)k1[u] * (uint32_t)s1 +
+                                     (uint32_t)k2[u] * (uint32_t)s2)
+                               : (C)-1;
+    else
+      cell[u] = counts && !out ? (C)((int64_t)k0[u] * s0 + (int64_t)k1[u] * s1 + (int64_t)k2[u] * s2) : (C)-1;
+  }
+}
+
 // bits of a cell for the hashed outputs' grouping (a 64-bit finalising mix)
 __device__ __forceinline__ uint64_t part_mix(uint64_t x) {
   x ^= x >> 30;
@@ -2299,125 +2406,145 @@ __device__ __forceinline__ uint64_t part_mix(uint64_t x) {
   return x;
 }
 
-// the cells of every output of the launch set for one row, and their slice
-// (-1 when the row does not count or is outside the block's range): dense
-// outputs slice by the cell's high bits, hashed ones by 9 bits of its mix;
-// all loads are issued before any counter is touched
-__device__ __forceinline__ void part_cells(const DPartCount& D, int64_t row, bool in, int32_t* slice, int64_t* cellv,
-                                           bool multi_only, bool first) {
-  PartRow R;
-  if (first) {
-    part_row(D, in ? row : 0, R);
-    if (in && D.w8) D.w8[row] = (uint8_t)((R.w ? 1u : 0u) | (R.vok << 1));
+// pass 0: the per-row byte (bit 0 filter weight, bits 1.. the views' 0/1
+// counts) for every later pass, and zero slice totals
+__global__ void __launch_bounds__(256) k_part_w8(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < D.n_out * kPartMaxBuckets; i += blockDim.x) D.btotal[i] = 0;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < D.n_rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    PartRow R;
+    part_row(D, row, R);
+    D.w8[row] = (uint8_t)((R.w ? 1u : 0u) | (R.vok << 1));
+  }
+}
+
+// flush of an LDS table of one slice: the output's cells [base, base + n)
+// (one chunk: plain stores, the cells are the workgroup's own), else the
+// chunk's partial table
+__device__ __forceinline__ void part_flush(const DPartCount& D, int o, int c, int64_t base, const uint32_t* bins) {
+  const int64_t n = min((int64_t)kPartSlice, D.n_cells[o] - base);
+  if (D.chunks[o] <= 1) {
+    int64_t* out = D.out_cnt[o] + base;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = (int64_t)bins[i];
   } else {
-    part_row_w8(D, in ? row : 0, R);
-  }
-#pragma unroll
-  for (int o = 0; o < kPartOuts; ++o) {
-    slice[o] = -1;
-    cellv[o] = 0;
-    if (o < D.n_out && in && (!multi_only || D.n_buckets[o] > 1)) {
-      const int64_t cell = part_cell(D, o, row, R);
-      if (cell == -2) atomicOr(D.err_flag, 2);
-      if (cell >= 0) {
-        slice[o] = D.hashed[o] ? (int32_t)(part_mix((uint64_t)cell) >> 55) : (int32_t)(cell >> kPartShift);
-        cellv[o] = cell;
-      }
-    }
+    uint32_t* out = D.partial + D.partial_base[o] + (int64_t)c * D.n_cells[o] + base;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = bins[i];
   }
 }
 
-// adds one per lane with b >= 0 to bins[b], one LDS atomic per distinct b in
-// the wavefront (wave-uniform control flow required)
-__device__ inline void wave_count(uint32_t* bins, int b) {
-  unsigned long long pending = __ballot(b >= 0);
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const int bl = __shfl(b, leader, 64);
-    const unsigned long long same = __ballot(b == bl) & pending;
-    if ((int)__lane_id() == leader) atomicAdd(&bins[bl], (uint32_t)__popcll(same));
-    pending &= ~same;
-  }
-}
-
-// reserves a slot in cur[b] per lane with b >= 0: the position, or -1
-__device__ inline int64_t wave_reserve(uint32_t* cur, int b) {
-  int64_t pos = -1;
-  const int lane = (int)__lane_id();
-  unsigned long long pending = __ballot(b >= 0);
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const int bl = __shfl(b, leader, 64);
-    const unsigned long long same = __ballot(b == bl) & pending;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&cur[bl], (uint32_t)__popcll(same));
-    base = __shfl(base, leader, 64);
-    if ((same >> lane) & 1ull) pos = (int64_t)base + __popcll(same & ((1ull << lane) - 1ull));
-    pending &= ~same;
-  }
-  return pos;
-}
-
-// pass 1: per workgroup row range, the number of counted rows per slice
-__global__ void __launch_bounds__(kPartThreads) k_part_slices(const DPartCount* __restrict__ Dp) {
+// pass 1a, tables of one slice: workgroup (chunk, output) counts the chunk's
+// rows in LDS; every thread keeps kPartDirectUnroll rows' loads in flight
+__global__ void __launch_bounds__(kPartCountThreads) k_part_direct(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
-  __shared__ uint32_t bins[kPartOuts * kPartMaxBuckets];
-  for (int i = threadIdx.x; i < D.n_out * kPartMaxBuckets; i += blockDim.x) bins[i] = 0;
+  const int o = blockIdx.y, c = blockIdx.x;
+  if (o >= D.n_out || D.hashed[o] || D.n_buckets[o] != 1 || c >= D.chunks[o]) return;
+  extern __shared__ uint32_t bins[];
+  for (int i = threadIdx.x; i < kPartSlice; i += blockDim.x) bins[i] = 0;
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * D.rows_per_block;
-  const int64_t r1 = min(D.n_rows, r0 + D.rows_per_block);
-  for (int64_t base = r0; base < r1; base += blockDim.x) {
-    const int64_t row = base + threadIdx.x;
-    int32_t slice[kPartOuts];
-    int64_t cellv[kPartOuts];
-    part_cells(D, row, row < r1, slice, cellv, true, true);
+  const int64_t per = (D.n_rows + D.chunks[o] - 1) / D.chunks[o];
+  const int64_t r0 = (int64_t)c * per, r1 = min(D.n_rows, r0 + per);
+  const int64_t step = (int64_t)kPartDirectUnroll * blockDim.x;
+  bool bad = false;
+  for (int64_t base = r0; base < r1; base += step) {
+    int32_t cell[kPartDirectUnroll];
+    part_load_cells<kPartDirectUnroll>(D, o, (int32_t)base + (int32_t)threadIdx.x, (int32_t)blockDim.x, (int32_t)r1,
+                                       cell, bad);
 #pragma unroll
-    for (int o = 0; o < kPartOuts; ++o) {
-      if (o >= D.n_out || D.n_buckets[o] <= 1) continue;
-      // few slices: one LDS atomic per distinct slice in the wavefront (lanes
-      // would otherwise queue on one address); many: one per lane
-      if (D.n_buckets[o] <= kPartWaveSlices) wave_count(&bins[o * kPartMaxBuckets], slice[o]);
-      else if (slice[o] >= 0) atomicAdd(&bins[o * kPartMaxBuckets + slice[o]], 1u);
+    for (int u = 0; u < kPartDirectUnroll; ++u)
+      if (cell[u] >= 0) atomicAdd(&bins[cell[u]], 1u);
+  }
+  if (bad) atomicOr(D.err_flag, 2);
+  __syncthreads();
+  part_flush(D, o, c, 0, bins);
+}
+
+// pass 1b: workgroup (tile, output) orders its tile's entries by slice (a
+// counting sort in LDS: rank within the slice by an LDS atomic, slice starts
+// by a scan) and writes them to the tile's region of the output's entry
+// array, contiguously, with the tile's S + 1 slice offsets.  Dense tables
+// store the low 15 bits of the cell (the slice is implied by the position),
+// hashed tables the whole cell, grouped by 9 bits of its mix.
+template <typename E, int TILE>
+__global__ void __launch_bounds__(kPartTileThreads) k_part_tile(const DPartCount* __restrict__ Dp) {
+  constexpr bool kHashed = sizeof(E) == 8;
+  constexpr int PER = TILE / kPartTileThreads;
+  const DPartCount& D = *Dp;
+  const int o = blockIdx.y, tile = blockIdx.x;
+  if (o >= D.n_out || (D.hashed[o] != 0) != kHashed || (!kHashed && D.n_buckets[o] <= 1) ||
+      tile >= D.n_tiles[o])
+    return;
+  __shared__ uint32_t off[kPartMaxBuckets + 1];
+  __shared__ E stage[TILE];
+  const int S = D.n_buckets[o];
+  for (int i = threadIdx.x; i <= S; i += blockDim.x) off[i] = 0;
+  __syncthreads();
+  const int64_t r0 = (int64_t)tile * TILE;
+  typedef typename std::conditional<kHashed, int64_t, int32_t>::type C;
+  C cell[PER];
+  bool bad = false;
+  part_load_cells<PER>(D, o, (int32_t)r0 + (int32_t)threadIdx.x, kPartTileThreads, (int32_t)D.n_rows, cell, bad);
+  if (bad) atomicOr(D.err_flag, 2);
+  uint32_t sr[PER];   // slice << 16 | rank within the slice; ~0: no entry
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    sr[u] = ~0u;
+    if (cell[u] >= 0) {
+      const uint32_t s = kHashed ? (uint32_t)(part_mix((uint64_t)cell[u]) >> 55) : (uint32_t)(cell[u] >> kPartShift);
+      sr[u] = (s << 16) | atomicAdd(&off[s + 1], 1u);
     }
   }
   __syncthreads();
-  for (int o = 0; o < D.n_out; ++o)
-    for (int b = threadIdx.x; b < D.n_buckets[o]; b += blockDim.x)
-      D.bcount[((int64_t)o * kPartMaxBuckets + b) * D.n_blocks + blockIdx.x] = bins[o * kPartMaxBuckets + b];
-}
-
-// pass 2a: per (output, slice), exclusive offsets of the workgroups' rows
-// within the slice and the slice total
-__global__ void __launch_bounds__(1024) k_part_offsets(const DPartCount* __restrict__ Dp) {
-  const DPartCount& D = *Dp;
-  const int o = blockIdx.y, b = blockIdx.x;
-  if (o >= D.n_out || b >= D.n_buckets[o] || D.n_buckets[o] <= 1) return;
-  __shared__ uint32_t tmp[1024];
-  uint32_t* a = D.bcount + ((int64_t)o * kPartMaxBuckets + b) * D.n_blocks;
-  uint32_t carry = 0;
-  for (int base = 0; base < D.n_blocks; base += 1024) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = i < D.n_blocks ? a[i] : 0u;
-    tmp[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-      const uint32_t x = (int)threadIdx.x >= d ? tmp[threadIdx.x - d] : 0u;
-      __syncthreads();
-      tmp[threadIdx.x] += x;
-      __syncthreads();
+  // inclusive scan of off[1..S] by the first wavefront: off[s] = start of slice s
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    constexpr int kPer = (kPartMaxBuckets + 63) / 64;
+    uint32_t v[kPer], run = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int s = 1 + lane * kPer + i;
+      v[i] = s <= S ? off[s] : 0u;
+      run += v[i];
     }
-    if (i < D.n_blocks) a[i] = carry + tmp[threadIdx.x] - v;
-    carry += tmp[1023];
-    __syncthreads();
+    uint32_t incl = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t x = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += x;
+    }
+    uint32_t acc = incl - run;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int s = 1 + lane * kPer + i;
+      acc += v[i];
+      if (s <= S) off[s] = acc;
+    }
   }
-  if (threadIdx.x == 0) D.btotal[(int64_t)o * kPartMaxBuckets + b] = carry;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u)
+    if (sr[u] != ~0u) {
+      const uint32_t pos = off[sr[u] >> 16] + (sr[u] & 0xffffu);
+      stage[pos] = kHashed ? (E)(uint64_t)cell[u] : (E)((uint64_t)cell[u] & (kPartSlice - 1));
+    }
+  __syncthreads();
+  const int n = (int)off[S];
+  E* dst = (kHashed ? (E*)(D.part64 + (int64_t)D.slot[o] * D.n_rows) : (E*)(D.part + (int64_t)D.slot[o] * D.n_rows)) + r0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = stage[i];
+  // slice-major: the offsets of one slice over consecutive tiles are adjacent
+  uint32_t* to = D.toff + D.toff_base[o] + tile;
+  const int64_t nt = D.n_tiles[o];
+  for (int i = threadIdx.x; i <= S; i += blockDim.x) to[(int64_t)i * nt] = off[i];
+  for (int i = threadIdx.x; i < S; i += blockDim.x)
+    if (off[i + 1] > off[i]) atomicAdd(&D.btotal[o * kPartMaxBuckets + i], off[i + 1] - off[i]);
 }
 
-// pass 2b: slice starts (exclusive scan of the slice totals), per output
+// slice starts per output (exclusive scan of the slice totals)
 __global__ void __launch_bounds__(kPartMaxBuckets) k_part_bases(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
   const int o = blockIdx.x;
-  if (o >= D.n_out || D.n_buckets[o] <= 1) return;
+  if (o >= D.n_out || !D.hashed[o]) return;
   __shared__ uint32_t tmp[kPartMaxBuckets];
   const int nb = D.n_buckets[o];
   const uint32_t v = (int)threadIdx.x < nb ? D.btotal[(int64_t)o * kPartMaxBuckets + threadIdx.x] : 0u;
@@ -2434,144 +2561,143 @@ __global__ void __launch_bounds__(kPartMaxBuckets) k_part_bases(const DPartCount
   if (threadIdx.x == 0) bs[nb] = tmp[kPartMaxBuckets - 1];
 }
 
-// pass 3: the low 15 bits of every counted row's cell, grouped by slice
-__global__ void __launch_bounds__(kPartThreads) k_part_scatter(const DPartCount* __restrict__ Dp) {
-  const DPartCount& D = *Dp;
-  __shared__ uint32_t cur[kPartOuts * kPartMaxBuckets];
-  for (int o = 0; o < D.n_out; ++o)
-    for (int b = threadIdx.x; b < D.n_buckets[o]; b += blockDim.x)
-      cur[o * kPartMaxBuckets + b] = D.bstart[(int64_t)o * (kPartMaxBuckets + 1) + b] +
-                                     D.bcount[((int64_t)o * kPartMaxBuckets + b) * D.n_blocks + blockIdx.x];
-  __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * D.rows_per_block;
-  const int64_t r1 = min(D.n_rows, r0 + D.rows_per_block);
-  for (int64_t base = r0; base < r1; base += blockDim.x) {
-    const int64_t row = base + threadIdx.x;
-    int32_t slice[kPartOuts];
-    int64_t cellv[kPartOuts];
-    part_cells(D, row, row < r1, slice, cellv, true, false);
-#pragma unroll
-    for (int o = 0; o < kPartOuts; ++o) {
-      if (o >= D.n_out || D.n_buckets[o] <= 1) continue;
-      int64_t pos = -1;
-      if (D.n_buckets[o] <= kPartWaveSlices) pos = wave_reserve(&cur[o * kPartMaxBuckets], slice[o]);
-      else if (slice[o] >= 0) pos = atomicAdd(&cur[o * kPartMaxBuckets + slice[o]], 1u);
-      if (pos < 0 || pos >= D.n_rows) continue;
-      if (D.hashed[o]) D.part64[(int64_t)o * D.n_rows + pos] = (uint64_t)cellv[o];
-      else D.part[(int64_t)o * D.n_rows + pos] = (uint16_t)(cellv[o] & ((1 << kPartShift) - 1));
+// Visits every entry of slice s in tiles [t0, t1) of output o.  The
+// workgroup takes one tile per thread at a time, flattens the tiles'
+// segments of slice s (a block scan of their lengths) and gives each thread
+// kPartSegUnroll consecutive entries per round (the loads in flight
+// together), so every wavefront has work however the entries spread over
+// the tiles.  visit(entry) is called per entry.  sh_start and sh_excl hold
+// blockDim entries, sh_w 16 + 1.
+template <typename E, typename F>
+__device__ __forceinline__ void part_segments(const DPartCount& D, int o, int s, int t0, int t1, const E* src,
+                                              int64_t* sh_start, uint32_t* sh_excl, uint32_t* sh_w, F&& visit) {
+  const int lane = (int)__lane_id();
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int B = blockDim.x;
+  const int tile_rows = D.tile_rows[o];
+  const int64_t nt = D.n_tiles[o];
+  const uint32_t* to = D.toff + D.toff_base[o];
+  for (int tb = t0; tb < t1; tb += B) {
+    const int t = tb + threadIdx.x;
+    uint32_t lo = 0, hi = 0;
+    if (t < t1) {
+      lo = to[(int64_t)s * nt + t];
+      hi = to[(int64_t)(s + 1) * nt + t];
     }
-  }
-}
-
-// pass 4, dense outputs of several slices: tiles of kPartTile partitioned
-// entries (balanced whatever the slice sizes), each slice piece of a tile
-// counted in LDS (2^15 counters) and its nonzero counters added to the
-// output's table
-constexpr int kPartHistThreads = 1024;
-__global__ void __launch_bounds__(kPartHistThreads) k_part_hist(const DPartCount* __restrict__ Dp) {
-  const DPartCount& D = *Dp;
-  extern __shared__ uint32_t bins[];
-  const int o = blockIdx.y;
-  if (D.hashed[o] || D.n_buckets[o] <= 1) return;
-  constexpr int kSlice = 1 << kPartShift;
-  const uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
-  const int nb = D.n_buckets[o];
-  const int64_t total = bs[nb];
-  const int64_t t0 = (int64_t)blockIdx.x * kPartTile;
-  if (t0 >= total) return;
-  const int64_t t1 = min(total, t0 + kPartTile);
-  int b = 0;
-  while (b < nb && (int64_t)bs[b + 1] <= t0) ++b;
-  const uint16_t* part = D.part + (int64_t)o * D.n_rows;
-  for (; b < nb && (int64_t)bs[b] < t1; ++b) {
-    const int64_t s0 = max(t0, (int64_t)bs[b]), s1 = min(t1, (int64_t)bs[b + 1]);
-    if (s0 >= s1) continue;
-    for (int i = threadIdx.x; i < kSlice; i += blockDim.x) bins[i] = 0;
-    __syncthreads();
-    // four entries per thread per round: the loads are in flight together
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += 4 * (int64_t)blockDim.x) {
-      uint32_t e[4];
+    const uint32_t len = hi - lo;
+    uint32_t incl = len;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t k = i + (int64_t)u * blockDim.x;
-        e[u] = k < s1 ? (uint32_t)part[k] : 0xffffffffu;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t x = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += x;
+    }
+    if (lane == 63) sh_w[wid] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < nw; ++w) {
+      const uint32_t x = sh_w[w];
+      before += w < wid ? x : 0u;
+      total += x;
+    }
+    sh_excl[threadIdx.x] = before + incl - len;
+    sh_start[threadIdx.x] = (int64_t)t * tile_rows + lo;
+    __syncthreads();
+    for (uint32_t k0 = (uint32_t)threadIdx.x * kPartSegUnroll; k0 < total; k0 += (uint32_t)B * kPartSegUnroll) {
+      // the last tile whose segment starts at or before k0
+      int lo_i = 0, hi_i = B - 1;
+      while (lo_i < hi_i) {
+        const int mid = (lo_i + hi_i + 1) >> 1;
+        if (sh_excl[mid] <= k0) lo_i = mid;
+        else hi_i = mid - 1;
       }
+      int cur = lo_i;
+      int64_t idx[kPartSegUnroll];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (e[u] != 0xffffffffu) atomicAdd(&bins[e[u]], 1u);
-    }
-    __syncthreads();
-    // a tile that holds the whole slice owns its cells: plain stores
-    const bool whole = s0 == (int64_t)bs[b] && s1 == (int64_t)bs[b + 1];
-    int64_t* out = D.out_cnt[o] + ((int64_t)b << kPartShift);
-    const int64_t n = min((int64_t)kSlice, D.n_cells[o] - ((int64_t)b << kPartShift));
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const uint32_t v = bins[i];
-      if (!v) continue;
-      if (whole) out[i] = (int64_t)v;
-      else atomicAdd((unsigned long long*)&out[i], (unsigned long long)v);
-    }
-    __syncthreads();
-  }
-}
-
-// pass 4, dense outputs of one slice: tiles of rows counted in LDS straight
-// from the columns, nonzero counters added to the output's table
-__global__ void __launch_bounds__(kPartHistThreads) k_part_hist1(const DPartCount* __restrict__ Dp) {
-  const DPartCount& D = *Dp;
-  extern __shared__ uint32_t bins[];
-  const int o = blockIdx.y;
-  if (D.hashed[o] || D.n_buckets[o] > 1) return;
-  const int64_t t0 = (int64_t)blockIdx.x * kPartTile;
-  if (t0 >= D.n_rows) return;
-  constexpr int kSlice = 1 << kPartShift;
-  const int64_t t1 = min(D.n_rows, t0 + kPartTile);
-  for (int i = threadIdx.x; i < kSlice; i += blockDim.x) bins[i] = 0;
-  __syncthreads();
-  for (int64_t row = t0 + threadIdx.x; row < t1; row += 2 * (int64_t)blockDim.x) {
-    int64_t cell[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int64_t rr = row + (int64_t)u * blockDim.x;
-      cell[u] = -1;
-      if (rr < t1) {
-        PartRow R;
-        part_row_w8(D, rr, R);
-        cell[u] = part_cell(D, o, rr, R);
+      for (int u = 0; u < kPartSegUnroll; ++u) {
+        const uint32_t k = k0 + (uint32_t)u;
+        idx[u] = -1;
+        if (k < total) {
+          while (cur + 1 < B && sh_excl[cur + 1] <= k) ++cur;
+          idx[u] = sh_start[cur] + (k - sh_excl[cur]);
+        }
       }
-    }
+      // the loads, unconditional (an index past the range reads entry 0)
+      E e[kPartSegUnroll];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      if (cell[u] == -2) atomicOr(D.err_flag, 2);
-      else if (cell[u] >= 0) atomicAdd(&bins[cell[u]], 1u);
+      for (int u = 0; u < kPartSegUnroll; ++u) e[u] = src[idx[u] >= 0 ? idx[u] : 0];
+#pragma unroll
+      for (int u = 0; u < kPartSegUnroll; ++u)
+        if (idx[u] >= 0) visit(e[u]);
     }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kSlice; i += blockDim.x) {
-    const uint32_t v = bins[i];
-    if (v && i < D.n_cells[o]) atomicAdd((unsigned long long*)&D.out_cnt[o][i], (unsigned long long)v);
+    __syncthreads();
   }
 }
 
-// pass 4 of hashed outputs, one workgroup per group of cells: the group is
-// ordered by sub-group (a counting sort on the next hash bits, into part64b;
-// sub-groups of about 3072 cells), then every sub-group is counted in an LDS
-// hash table (8192 slots) and its (cell, count) pairs are written to the
+// pass 2, dense tables of several slices: workgroup (slice x chunk, output)
+// counts the slice's segments of the chunk's tiles in LDS
+__global__ void __launch_bounds__(kPartCountThreads) k_part_slice_count(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  const int o = blockIdx.y;
+  if (o >= D.n_out || D.hashed[o] || D.n_buckets[o] <= 1) return;
+  const int C = D.chunks[o];
+  const int x = blockIdx.x;
+  if (x >= D.n_buckets[o] * C) return;
+  const int s = x / C, c = x % C;
+  extern __shared__ uint32_t bins[];
+  __shared__ int64_t sh_start[kPartCountThreads];
+  __shared__ uint32_t sh_excl[kPartCountThreads];
+  __shared__ uint32_t sh_w[kPartCountThreads / 64];
+  for (int i = threadIdx.x; i < kPartSlice; i += blockDim.x) bins[i] = 0;
+  __syncthreads();
+  const int nt = D.n_tiles[o];
+  const int t0 = (int)((int64_t)c * nt / C), t1 = (int)((int64_t)(c + 1) * nt / C);
+  part_segments<uint16_t>(D, o, s, t0, t1, D.part + (int64_t)D.slot[o] * D.n_rows, sh_start, sh_excl, sh_w,
+                          [&](uint16_t v) { atomicAdd(&bins[v], 1u); });
+  __syncthreads();
+  part_flush(D, o, c, (int64_t)s << kPartShift, bins);
+}
+
+// per-chunk partial tables summed into the outputs (grid-stride per output)
+__global__ void k_part_reduce(const DPartCount* __restrict__ Dp) {
+  const DPartCount& D = *Dp;
+  const int o = blockIdx.y;
+  if (o >= D.n_out || D.hashed[o] || D.chunks[o] <= 1) return;
+  const int C = D.chunks[o];
+  const int64_t n = D.n_cells[o];
+  const uint32_t* p = D.partial + D.partial_base[o];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t s = 0;
+    for (int c = 0; c < C; ++c) s += p[(int64_t)c * n + i];
+    D.out_cnt[o][i] = (int64_t)s;
+  }
+}
+
+// pass 2 of hashed outputs, one workgroup per group of cells: the group's
+// segments are gathered from every tile and ordered by sub-group (a counting
+// sort on the next hash bits, into the group's region of part64b;
+// sub-groups of about 192 cells), then every wavefront counts whole
+// sub-groups in an LDS hash table of its own (512 slots; no workgroup
+// barrier between sub-groups) and writes their (cell, count) pairs to the
 // group's own region of the output's table (cap / 512 slots, positions from
-// an LDS counter: no global atomics).  A full LDS table or a full region sets
-// the table's overflow flag (the run is repeated with a larger table).
-constexpr int kPartHashSlots = 8192;
-constexpr int kPartSubCells = 3072;
+// an LDS counter: no global atomics); the region's other slots are cleared,
+// so the table needs no fill.  A full LDS table or a full region sets the
+// table's overflow flag (the run is repeated with a larger table).
+constexpr int kPartWaveSlots = 512;
+constexpr int kPartHashWaves = 16;
+constexpr int kPartSubCells = 192;
 constexpr int kPartMaxSub = 1024;
-constexpr int kPartHashLds = kPartHashSlots * 12 + (2 * kPartMaxSub + 2) * 4;
-__global__ void __launch_bounds__(1024) k_part_hash(const DPartCount* __restrict__ Dp) {
+constexpr int kPartHashLds = kPartWaveSlots * kPartHashWaves * 12 + (2 * kPartMaxSub + 2) * 4;
+__global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
   const int o = blockIdx.y;
-  if (!D.hashed[o]) return;
+  if (o >= D.n_out || !D.hashed[o]) return;
   extern __shared__ unsigned long long lkeys[];
-  uint32_t* lcnt = (uint32_t*)(lkeys + kPartHashSlots);
-  uint32_t* suboff = lcnt + kPartHashSlots;     // [S + 1]
-  uint32_t* cursor = suboff + kPartMaxSub + 1;  // [S]; cursor[kPartMaxSub] = entries written
+  __shared__ int64_t sh_start[kPartHashWaves * 64];
+  __shared__ uint32_t sh_excl[kPartHashWaves * 64];
+  __shared__ uint32_t sh_w[kPartHashWaves];
+  uint32_t* lcnt = (uint32_t*)(lkeys + kPartWaveSlots * kPartHashWaves);
+  uint32_t* suboff = lcnt + kPartWaveSlots * kPartHashWaves;   // [S + 1]
+  uint32_t* cursor = suboff + kPartMaxSub + 1;                 // [S]; cursor[kPartMaxSub] = entries written
   const DHashOut& H = D.htab[D.hidx[o]];
   const int64_t cap = H.mask + 1;
   const int b = blockIdx.x;
@@ -2579,118 +2705,145 @@ __global__ void __launch_bounds__(1024) k_part_hash(const DPartCount* __restrict
   const int64_t region0 = (int64_t)b * region;
   const uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
   const int64_t s0 = bs[b], s1 = bs[b + 1];
-  if (s0 >= s1) return;
+  const int lane = (int)__lane_id(), wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) cursor[kPartMaxSub] = 0;
   int S = 1, sbits = 0;
   while (S < kPartMaxSub && (int64_t)S * kPartSubCells < s1 - s0) {
     S <<= 1;
     ++sbits;
   }
-  const uint64_t* part = D.part64 + (int64_t)o * D.n_rows;
-  uint64_t* sorted = D.part64b + (int64_t)o * D.n_rows;
-  const int lane = (int)__lane_id();
+  const uint64_t* part = D.part64 + (int64_t)D.slot[o] * D.n_rows;
+  uint64_t* sorted = D.part64b + (int64_t)D.slot[o] * D.n_rows;
   constexpr unsigned long long kEmpty = ~0ull;
   auto sub_of = [&](uint64_t cell) {
     return sbits ? (int)((part_mix(cell) >> (55 - sbits)) & (uint64_t)(S - 1)) : 0;
   };
-  // counting sort of the group by sub-group
-  for (int i = threadIdx.x; i <= S; i += blockDim.x) suboff[i] = 0;
-  if (threadIdx.x == 0) cursor[kPartMaxSub] = 0;
-  __syncthreads();
-  if (S > 1) {
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) atomicAdd(&suboff[sub_of(part[i]) + 1], 1u);
+  if (s0 < s1) {
+    // counting sort of the group by sub-group, gathered from the tiles
+    for (int i = threadIdx.x; i <= S; i += blockDim.x) suboff[i] = 0;
+    __syncthreads();
+    const int nt = D.n_tiles[o];
+    part_segments<uint64_t>(D, o, b, 0, nt, part, sh_start, sh_excl, sh_w,
+                            [&](uint64_t cell) { atomicAdd(&suboff[sub_of(cell) + 1], 1u); });
     __syncthreads();
     if (threadIdx.x == 0)
       for (int i = 1; i <= S; ++i) suboff[i] += suboff[i - 1];
     __syncthreads();
     for (int i = threadIdx.x; i < S; i += blockDim.x) cursor[i] = suboff[i];
     __syncthreads();
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-      const uint64_t cell = part[i];
+    part_segments<uint64_t>(D, o, b, 0, nt, part, sh_start, sh_excl, sh_w, [&](uint64_t cell) {
       const uint32_t pos = atomicAdd(&cursor[sub_of(cell)], 1u);
       sorted[s0 + pos] = cell;
+    });
+    __threadfence_block();
+    __syncthreads();
+    unsigned long long* wkeys = lkeys + wid * kPartWaveSlots;
+    uint32_t* wcnt = lcnt + wid * kPartWaveSlots;
+    bool full = false;
+    for (int sub = wid; sub < S; sub += kPartHashWaves) {
+      const int64_t r0 = s0 + suboff[sub], r1 = s0 + suboff[sub + 1];
+      if (r0 >= r1) continue;
+      for (int i = lane; i < kPartWaveSlots; i += 64) {
+        wkeys[i] = kEmpty;
+        wcnt[i] = 0;
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int64_t i0 = r0 + lane; i0 < r1; i0 += 4 * 64) {
+        uint64_t cv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t i = i0 + (int64_t)u * 64;
+          cv[u] = sorted[i < r1 ? i : r0];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (i0 + (int64_t)u * 64 >= r1) continue;
+          const uint64_t cell = cv[u];
+          uint32_t slot = (uint32_t)part_mix(cell) & (kPartWaveSlots - 1);
+          bool done = false;
+          for (int probe = 0; probe < kPartWaveSlots && !done; ++probe) {
+            const unsigned long long prev = atomicCAS(&wkeys[slot], kEmpty, (unsigned long long)cell);
+            if (prev == kEmpty || prev == cell) {
+              atomicAdd(&wcnt[slot], 1u);
+              done = true;
+            }
+            slot = (slot + 1) & (kPartWaveSlots - 1);
+          }
+          full |= !done;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int base = 0; base < kPartWaveSlots; base += 64) {
+        const int slot = base + lane;
+        const unsigned long long key = wkeys[slot];
+        const bool occ = key != kEmpty;
+        const unsigned long long m = __ballot(occ);
+        uint32_t p0 = 0;
+        if (lane == 0 && m) p0 = atomicAdd(&cursor[kPartMaxSub], (uint32_t)__popcll(m));
+        p0 = __shfl(p0, 0, 64);
+        if (occ) {
+          const int64_t pos = (int64_t)p0 + __popcll(m & ((1ull << lane) - 1ull));
+          if (pos < region) {
+            H.keys[region0 + pos] = key + 1ull;
+            H.cnt[region0 + pos] = (int64_t)wcnt[slot];
+          } else {
+            full = true;
+          }
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-  } else {
-    if (threadIdx.x == 0) suboff[1] = (uint32_t)(s1 - s0);
+    if (full) {
+      atomicOr(H.ovf, 1);
+      atomicOr(D.err_flag, 8);
+    }
   }
   __syncthreads();
-  const uint64_t* src = S > 1 ? sorted : part;
-  for (int sub = 0; sub < S; ++sub) {
-    const int64_t r0 = s0 + suboff[sub], r1 = s0 + suboff[sub + 1];
-    if (r0 >= r1) continue;
-    for (int i = threadIdx.x; i < kPartHashSlots; i += blockDim.x) {
-      lkeys[i] = kEmpty;
-      lcnt[i] = 0;
-    }
-    __syncthreads();
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-      const uint64_t cell = src[i];
-      uint32_t slot = (uint32_t)part_mix(cell) & (kPartHashSlots - 1);
-      bool done = false;
-      for (int probe = 0; probe < kPartHashSlots && !done; ++probe) {
-        const unsigned long long prev = atomicCAS(&lkeys[slot], kEmpty, (unsigned long long)cell);
-        if (prev == kEmpty || prev == cell) {
-          atomicAdd(&lcnt[slot], 1u);
-          done = true;
-        }
-        slot = (slot + 1) & (kPartHashSlots - 1);
-      }
-      if (!done) {
-        atomicOr(H.ovf, 1);
-        atomicOr(D.err_flag, 8);
-      }
-    }
-    __syncthreads();
-    for (int base = 0; base < kPartHashSlots; base += blockDim.x) {
-      const int slot = base + threadIdx.x;
-      const unsigned long long key = lkeys[slot];
-      const bool occ = key != kEmpty;
-      const unsigned long long m = __ballot(occ);
-      uint32_t p0 = 0;
-      if (lane == 0 && m) p0 = atomicAdd(&cursor[kPartMaxSub], (uint32_t)__popcll(m));
-      p0 = __shfl(p0, 0, 64);
-      if (occ) {
-        const int64_t pos = (int64_t)p0 + __popcll(m & ((1ull << lane) - 1ull));
-        if (pos < region) {
-          H.keys[region0 + pos] = key + 1ull;
-          H.cnt[region0 + pos] = (int64_t)lcnt[slot];
-        } else {
-          atomicOr(H.ovf, 1);
-          atomicOr(D.err_flag, 8);
-        }
-      }
-    }
-    __syncthreads();
-  }
+  // the region's remaining slots hold no group
+  const int64_t used = min((int64_t)cursor[kPartMaxSub], region);
+  for (int64_t i = used + threadIdx.x; i < region; i += blockDim.x) H.keys[region0 + i] = 0ull;
 }
+
+constexpr int kPartTileDense = 16384;
+constexpr int kPartTileHash = 8192;
+int part_tile_rows(bool hashed) { return hashed ? kPartTileHash : kPartTileDense; }
 
 void launch_part_count(const DPartCount* d, const DPartCount& h, hipStream_t s) {
   if (h.n_rows <= 0 || h.n_out <= 0) return;
-  bool multi = false, hashed = false;
+  bool single = false, dense_multi = false, hashed = false, reduce = false;
+  int tiles_dense = 0, tiles_hash = 0, slice_chunks = 0, direct_chunks = 0;
   for (int o = 0; o < h.n_out; ++o) {
-    multi |= h.n_buckets[o] > 1;
-    hashed |= h.hashed[o] != 0;
+    if (h.hashed[o]) {
+      hashed = true;
+      tiles_hash = std::max(tiles_hash, h.n_tiles[o]);
+    } else if (h.n_buckets[o] <= 1) {
+      single = true;
+      direct_chunks = std::max(direct_chunks, h.chunks[o]);
+      reduce |= h.chunks[o] > 1;
+    } else {
+      dense_multi = true;
+      tiles_dense = std::max(tiles_dense, h.n_tiles[o]);
+      slice_chunks = std::max(slice_chunks, h.n_buckets[o] * h.chunks[o]);
+      reduce |= h.chunks[o] > 1;
+    }
   }
-  bool single = false, dense_multi = false;
-  int nb_max = 1;
-  for (int o = 0; o < h.n_out; ++o) {
-    single |= !h.hashed[o] && h.n_buckets[o] <= 1;
-    dense_multi |= !h.hashed[o] && h.n_buckets[o] > 1;
-    nb_max = std::max(nb_max, h.n_buckets[o]);
-  }
-  // the slice pass also stores every row's weight byte for the later passes
-  hipLaunchKernelGGL(k_part_slices, dim3(h.n_blocks), dim3(kPartThreads), 0, s, d);
-  if (multi) {
-    hipLaunchKernelGGL(k_part_offsets, dim3(nb_max, h.n_out), dim3(1024), 0, s, d);
-    hipLaunchKernelGGL(k_part_bases, dim3(h.n_out), dim3(kPartMaxBuckets), 0, s, d);
-    hipLaunchKernelGGL(k_part_scatter, dim3(h.n_blocks), dim3(kPartThreads), 0, s, d);
-  }
-  const int tiles = (int)((h.n_rows + kPartTile - 1) / kPartTile);
-  if (dense_multi)
-    hipLaunchKernelGGL(k_part_hist, dim3(tiles, h.n_out), dim3(kPartHistThreads), (1 << kPartShift) * 4, s, d);
+  const int g8 = (int)std::min<int64_t>((h.n_rows + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_part_w8, dim3(g8), dim3(256), 0, s, d);
   if (single)
-    hipLaunchKernelGGL(k_part_hist1, dim3(tiles, h.n_out), dim3(kPartHistThreads), (1 << kPartShift) * 4, s, d);
-  if (hashed)
-    hipLaunchKernelGGL(k_part_hash, dim3(kPartHashBuckets, h.n_out), dim3(1024), kPartHashLds, s, d);
+    hipLaunchKernelGGL(k_part_direct, dim3(direct_chunks, h.n_out), dim3(kPartCountThreads), kPartSlice * 4, s, d);
+  if (dense_multi) {
+    hipLaunchKernelGGL((k_part_tile<uint16_t, kPartTileDense>), dim3(tiles_dense, h.n_out), dim3(kPartTileThreads),
+                       0, s, d);
+    hipLaunchKernelGGL(k_part_slice_count, dim3(slice_chunks, h.n_out), dim3(kPartCountThreads), kPartSlice * 4, s,
+                       d);
+  }
+  if (reduce) hipLaunchKernelGGL(k_part_reduce, dim3(256, h.n_out), dim3(256), 0, s, d);
+  if (hashed) {
+    hipLaunchKernelGGL((k_part_tile<uint64_t, kPartTileHash>), dim3(tiles_hash, h.n_out), dim3(kPartTileThreads), 0,
+                       s, d);
+    hipLaunchKernelGGL(k_part_bases, dim3(h.n_out), dim3(kPartMaxBuckets), 0, s, d);
+    hipLaunchKernelGGL(k_part_hash, dim3(kPartHashBuckets, h.n_out), dim3(kPartHashWaves * 64), kPartHashLds, s, d);
+  }
 }
 
 // largest count of each listed view (grid-stride, one atomicMax per block)

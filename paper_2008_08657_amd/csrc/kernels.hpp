@@ -96,23 +96,23 @@ struct DMultCheck {
 };
 void launch_mult_check(const DMultCheck* d, const DMultCheck& h, hipStream_t s);
 
-// Radix-partitioned counting of large dense group-by tables of SUM(1)
-// queries (key spaces above what a scan keeps in LDS): per row a dense cell
-// index from up to 3 codes (columns of the relation or codes carried by
-// unique views), weighted by the filter and the views' 0/1 counts.  Tables of
-// more than one 2^15-cell slice are partitioned by slice (count, offsets,
-// scatter of the low 15 bits) and every slice is then counted in LDS; tables
-// of one slice are counted in LDS straight from the columns.
+// Radix-partitioned counting of large group-by tables of SUM(1) queries (key
+// spaces above what a scan keeps in LDS): per row a dense cell index from up
+// to 3 codes (columns of the relation or codes carried by unique views),
+// weighted by the filter and the views' 0/1 counts.  Tables of one 2^15-cell
+// slice are counted in LDS straight from the columns; larger ones are ordered
+// by slice within tiles of rows (low 15 bits kept) and every slice is then
+// counted in LDS from its tile segments; hash tables (key spaces past 2^24
+// cells) are ordered by 9 bits of a hash of the cell and every group of cells
+// counted in LDS hash tables.
 constexpr int kPartOuts = 16;
 constexpr int kPartViews = 4;
 constexpr int kPartShift = 15;
 constexpr int kPartMaxBuckets = 512;
-constexpr int kPartMaxBlocks = 4096;       // workgroups of the slice count and scatter passes
 struct DPartCount {
   int64_t n_rows;
-  int64_t rows_per_block;
-  int32_t n_blocks;
   int32_t n_out;
+  int32_t pad0;
   const int32_t* w;                        // filter weight per row (null: all 1)
   int32_t n_views;
   int32_t pad;
@@ -131,27 +131,35 @@ struct DPartCount {
   int64_t kstride[kPartOuts][3];
   int64_t kdom[kPartOuts][3];
   int64_t n_cells[kPartOuts];
-  int32_t n_buckets[kPartOuts];
+  int32_t n_buckets[kPartOuts];            // slices (dense), or hash groups (hashed)
   int64_t* out_cnt[kPartOuts];
-  uint32_t* bcount;                        // [out][bucket][block] counts, then offsets within the bucket
-  uint32_t* btotal;                        // [out][bucket] rows per bucket
-  uint32_t* bstart;                        // [out][kPartMaxBuckets + 1] bucket starts in part
-  uint16_t* part;                          // [out][n_rows] low 15 bits of the cell
-  // outputs kept in hash tables: rows are grouped by 9 bits of a hash of the
-  // cell, every (group, sub-group) counted in an LDS hash table and its
-  // (cell, count) pairs written to the group's region of the output's table
   int32_t hashed[kPartOuts];
   int32_t hidx[kPartOuts];                 // index of the output's table in htab
+  int32_t slot[kPartOuts];                 // index among the launch set's outputs of its kind (entry arrays)
+  int32_t tile_rows[kPartOuts];            // rows per tile of the tile pass
+  int32_t n_tiles[kPartOuts];
+  int32_t chunks[kPartOuts];               // counting workgroups per slice (1: stores straight to the output)
+  int64_t toff_base[kPartOuts];            // the output's [slice + 1][tile] offsets within toff
+  int64_t partial_base[kPartOuts];         // the output's [chunk][cell] partial counts within partial
+  uint32_t* toff;
+  uint32_t* partial;
+  uint32_t* btotal;                        // [out][kPartMaxBuckets] entries per group (hashed outputs)
+  uint32_t* bstart;                        // [out][kPartMaxBuckets + 1] group starts in part64b
+  uint16_t* part;                          // [dense slot][n_rows] low 15 bits of cells, tile-ordered by slice
+  uint64_t* part64;                        // [hashed slot][n_rows] cells, tile-ordered by group
+  uint64_t* part64b;                       // [hashed slot][n_rows] the cells ordered by group and sub-group
   const DHashOut* htab;
   uint8_t* w8;                             // [n_rows] per row: bit 0 filter weight, bits 1.. the views'
-                                           // 0/1 counts (written by the slice pass, read by the others)
+                                           // 0/1 counts (written by the first pass, read by the others)
   int32_t vkeys_needed;                    // some output's key is a code carried by a view
-  uint64_t* part64;                        // [out][n_rows] cells of hashed outputs
-  uint64_t* part64b;                       // the same cells, ordered by sub-group within each group
+  int32_t keys_cols[kPartOuts];            // every key of the output is a column of the relation
+  int32_t pad2;
   int32_t* err_flag;
 };
 constexpr int kPartHashBuckets = 512;
-// the three partition launches (count, offsets, scatter) and the LDS count
+// rows per tile of the tile pass (dense and hashed outputs)
+int part_tile_rows(bool hashed);
+// the launch set's passes (row bytes, direct and slice counts, hashed groups)
 void launch_part_count(const DPartCount* d, const DPartCount& h, hipStream_t s);
 
 void launch_fill(void* p, int64_t bytes, hipStream_t s);

@@ -1322,19 +1322,23 @@ static void split_group(Plan& P, int gi, size_t from) {
 // node or carried by the single-valued views into it: its table is counted by
 // radix partition (a slice of the key space, or of a hash of the key, at a
 // time, in LDS) instead of by global atomics from a scan or a row pass.
-static bool partition_eligible(const Plan& P, int qid, int node) {
+static double query_cells(const Plan& P, int qid) {
+  double cells = 1;
+  for (int a : P.queries[qid].groupby) cells *= (double)std::max<int64_t>(P.attrs[a].domain, 0);
+  return cells;
+}
+
+static bool partition_eligible(const Plan& P, int qid, int node, double min_cells = (double)kLdsTableMax) {
   const QueryDef& Q = P.queries[qid];
   if (Q.root != node || Q.groupby.empty() || Q.groupby.size() > 3) return false;
   for (const Mono& m : Q.aggs)
     if (!m.empty()) return false;
-  double cells = 1;
-  for (int a : Q.groupby) {
+  for (int a : Q.groupby)
     if (P.attrs[a].domain <= 0) return false;
-    cells *= (double)P.attrs[a].domain;
-  }
+  const double cells = query_cells(P, qid);
   // dense tables past what a scan keeps in LDS, and hash tables (key spaces
   // past 2^24 cells) of cells below 2^62
-  if (cells <= (double)kLdsTableMax || cells >= 4.6e18) return false;
+  if (cells <= min_cells || cells >= 4.6e18) return false;
   if (Q.in_view.size() > 4) return false;
   for (auto& kv : Q.in_view)
     if (!P.views[kv.second].unique || P.views[kv.second].key.size() > 2) return false;
@@ -1344,6 +1348,58 @@ static bool partition_eligible(const Plan& P, int qid, int node) {
     for (auto& kv : Q.in_view)
       for (int c : P.views[kv.second].carried) carried |= c == a;
     if (!carried) return false;
+  }
+  return true;
+}
+
+// A scan keeps its group-by tables in LDS, in output order, while they fit
+// in kLdsTableMax cells, and adds to the others with a global atomic per row.
+// The partition-eligible ones among those
+// that would not fit move to a partitioned group of the same node and level
+// (counted in LDS a slice at a time).  Returns whether any moved.
+static bool move_lds_overflow(Plan& P, int gi) {
+  GroupDef& G = P.groups[gi];
+  int64_t used = 0;
+  std::vector<OutRef> moved;
+  for (const ProgOutput& po : G.prog.outs) {
+    if (po.mode != 2) continue;
+    if (used + po.n_rows <= kLdsTableMax) {
+      used += po.n_rows;
+      continue;
+    }
+    if (po.ref.kind == 0 && partition_eligible(P, po.ref.id, G.node, (double)kPartMinCells)) moved.push_back(po.ref);
+  }
+  if (moved.empty()) return false;
+  int target = -1;
+  for (size_t h = 0; h < P.groups.size(); ++h)
+    if ((int)h != gi && P.groups[h].partitioned && P.groups[h].node == G.node && P.groups[h].level == G.level)
+      target = (int)h;
+  std::vector<OutRef> keep;
+  for (const OutRef& o : G.outs)
+    if (std::find_if(moved.begin(), moved.end(), [&](const OutRef& m) { return m.kind == o.kind && m.id == o.id; }) ==
+        moved.end())
+      keep.push_back(o);
+  if (target < 0) {
+    G.outs = keep;
+    G.outs.insert(G.outs.end(), moved.begin(), moved.end());
+    split_group(P, gi, keep.size());
+    P.groups.back().partitioned = true;
+    P.groups.back().has_program = false;
+  } else {
+    P.groups[gi].outs = keep;
+    for (const OutRef& m : moved) {
+      P.groups[target].outs.push_back(m);
+      P.queries[m.id].group = target;
+    }
+    for (auto& H : P.groups) {
+      H.deps.clear();
+      for (auto& o : H.outs) {
+        if (o.kind == 1)
+          for (int d : P.views[o.id].deps) H.deps.insert(P.views[d].group);
+        else
+          for (auto& kv : P.queries[o.id].in_view) H.deps.insert(P.views[kv.second].group);
+      }
+    }
   }
   return true;
 }
@@ -1405,6 +1461,7 @@ static void build_programs(Plan& P) {
           G.one_hot_pure = kOneHotPure;
           continue;
         }
+        if (G.has_program && program_fits(G.prog) && P.opts.partition == 0 && move_lds_overflow(P, (int)gi)) continue;
         if (!G.has_program || program_fits(G.prog)) break;
         why = "a group exceeds the limits of one scan kernel";
       } catch (const PlanError& e) {

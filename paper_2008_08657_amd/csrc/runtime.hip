@@ -61,7 +61,8 @@ struct HashBuf {
   int64_t* cnt = nullptr;
   double* vals = nullptr;
   int n_vals = 0;
-  int fill_step = -1;              // index of its zeroing steps (keys, cnt, vals)
+  int fill_step = -1;              // index of its zeroing steps (keys, cnt, vals); -1: none
+  bool counts_only = false;        // written whole by the partition count; every value is the count
   std::vector<int> count_copies;   // value columns equal to the count (SUM(1))
 };
 
@@ -625,7 +626,6 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       }
     }
     d.n_out = (int)(end - base);
-    bool any_hashed = false, any_dense_multi = false;
     std::vector<DCountCopy> copies;
     double rows_bytes = 0;
     for (int o = 0; o < d.n_out; ++o) {
@@ -638,7 +638,6 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
         d.hashed[o] = 1;
         d.hidx[o] = B.hash;
         d.n_buckets[o] = kPartHashBuckets;
-        any_hashed = true;
         // SUM(1) components equal the count: added when the table is read
         HashBuf& H = S.hashes[B.hash];
         H.count_copies.clear();
@@ -646,7 +645,6 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       } else {
         d.n_buckets[o] = (int)((B.n_rows + (1 << kPartShift) - 1) >> kPartShift);
         if (d.n_buckets[o] > kPartMaxBuckets) throw PlanError{LMFAO_EINVAL, "internal: partitioned table too large"};
-        any_dense_multi |= d.n_buckets[o] > 1;
       }
       for (auto& kv : Q.in_view) {
         const int v = (int)(std::find(views.begin(), views.end(), kv.second) - views.begin());
@@ -687,17 +685,48 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       }
     }
     const int64_t n = R.n_rows;
-    d.rows_per_block = std::max<int64_t>(16384, ((n + kPartMaxBlocks - 1) / kPartMaxBlocks + 255) / 256 * 256);
-    d.n_blocks = (int)std::max<int64_t>(1, (n + d.rows_per_block - 1) / d.rows_per_block);
-    d.bcount = (uint32_t*)dalloc(S, (size_t)d.n_out * kPartMaxBuckets * d.n_blocks * 4);
+    if (n > (int64_t)INT32_MAX - (1 << 16))
+      throw PlanError{LMFAO_EUNSUPPORTED, "partitioned count of a relation of 2^31 rows or more"};
+    // entry arrays per kind, tile offsets and per-chunk partial tables
+    int n_dense_slots = 0, n_hash_slots = 0;
+    int64_t toff_total = 0, partial_total = 0;
+    for (int o = 0; o < d.n_out; ++o) {
+      d.slot[o] = -1;
+      d.chunks[o] = 1;
+      if (d.hashed[o] || d.n_buckets[o] > 1) {
+        d.slot[o] = d.hashed[o] ? n_hash_slots++ : n_dense_slots++;
+        d.tile_rows[o] = part_tile_rows(d.hashed[o] != 0);
+        d.n_tiles[o] = (int)((n + d.tile_rows[o] - 1) / d.tile_rows[o]);
+        d.toff_base[o] = toff_total;
+        toff_total += (int64_t)d.n_tiles[o] * (d.n_buckets[o] + 1);
+        // about 64 counting workgroups per dense output, each at least 16 tiles
+        if (!d.hashed[o])
+          d.chunks[o] = (int)std::max<int64_t>(
+              1, std::min<int64_t>((64 + d.n_buckets[o] - 1) / d.n_buckets[o], d.n_tiles[o] / 16));
+      } else {
+        // one slice: chunks of at least 64k rows, at most 64
+        d.chunks[o] = (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 65536));
+      }
+      if (d.chunks[o] > 1) {
+        d.partial_base[o] = partial_total;
+        partial_total += (int64_t)d.chunks[o] * d.n_cells[o];
+      }
+    }
+    d.toff = toff_total ? (uint32_t*)dalloc(S, (size_t)toff_total * 4) : nullptr;
+    d.partial = partial_total ? (uint32_t*)dalloc(S, (size_t)partial_total * 4) : nullptr;
     d.bstart = (uint32_t*)dalloc(S, (size_t)d.n_out * (kPartMaxBuckets + 1) * 4);
     d.btotal = (uint32_t*)dalloc(S, (size_t)d.n_out * kPartMaxBuckets * 4);
-    d.part = any_dense_multi ? (uint16_t*)dalloc(S, (size_t)d.n_out * std::max<int64_t>(n, 1) * 2) : nullptr;
+    d.part = n_dense_slots ? (uint16_t*)dalloc(S, (size_t)n_dense_slots * std::max<int64_t>(n, 1) * 2) : nullptr;
     d.w8 = (uint8_t*)dalloc(S, (size_t)std::max<int64_t>(n, 1));
-    for (int o = 0; o < d.n_out; ++o)
-      for (int k = 0; k < d.nkey[o]; ++k) d.vkeys_needed |= d.ksrc[o][k] >= 0 ? 1 : 0;
-    d.part64 = any_hashed ? (uint64_t*)dalloc(S, (size_t)d.n_out * std::max<int64_t>(n, 1) * 8) : nullptr;
-    d.part64b = any_hashed ? (uint64_t*)dalloc(S, (size_t)d.n_out * std::max<int64_t>(n, 1) * 8) : nullptr;
+    for (int o = 0; o < d.n_out; ++o) {
+      d.keys_cols[o] = 1;
+      for (int k = 0; k < d.nkey[o]; ++k) {
+        d.vkeys_needed |= d.ksrc[o][k] >= 0 ? 1 : 0;
+        d.keys_cols[o] &= d.ksrc[o][k] < 0 ? 1 : 0;
+      }
+    }
+    d.part64 = n_hash_slots ? (uint64_t*)dalloc(S, (size_t)n_hash_slots * std::max<int64_t>(n, 1) * 8) : nullptr;
+    d.part64b = n_hash_slots ? (uint64_t*)dalloc(S, (size_t)n_hash_slots * std::max<int64_t>(n, 1) * 8) : nullptr;
     d.htab = S.hash_dev;
     d.err_flag = S.err_flag;
     Step s;
@@ -706,7 +735,7 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
     s.dev = upload(S, d, st);
     s.part = d;
     s.rows = n;
-    s.grid = d.n_blocks;
+    s.grid = (int)((n + part_tile_rows(false) - 1) / part_tile_rows(false));
     // bytes the method needs: every key column and view key read once; the
     // counts written once per cell (the partition round trip is the kernel's)
     std::set<int> rc(need.begin(), need.end());
@@ -1876,11 +1905,17 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
     std::vector<DHashOut> hd(S.hashes.size());
     for (size_t i = 0; i < S.hashes.size(); ++i) {
       HashBuf& H = S.hashes[i];
+      // tables counted by radix partition are written whole by their last
+      // pass (every slot, groups or empty), and their values are the counts
+      const QueryDef& QH = P.queries[H.query];
+      H.counts_only = QH.group >= 0 && P.groups[QH.group].partitioned;
       alloc_hash(S, H);
-      H.fill_step = (int)S.steps.size();
-      add_fill(S, H.keys, H.cap * 8, "hash keys");
-      add_fill(S, H.cnt, H.cap * 8, "hash counts");
-      add_fill(S, H.vals, H.cap * 8 * std::max(1, H.n_vals), "hash values");
+      if (!H.counts_only) {
+        H.fill_step = (int)S.steps.size();
+        add_fill(S, H.keys, H.cap * 8, "hash keys");
+        add_fill(S, H.cnt, H.cap * 8, "hash counts");
+        add_fill(S, H.vals, H.cap * 8 * std::max(1, H.n_vals), "hash values");
+      }
       hd[i] = DHashOut{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0};
     }
     S.hash_dev = upload_vec(S, hd, st);
@@ -2153,12 +2188,14 @@ static void resize_hash(Prep& S, size_t i, int64_t cap) {
   const int64_t old_cap = H.cap;
   H.cap = cap;
   alloc_hash(S, H, old_cap);
-  S.steps[H.fill_step].dev = H.keys;
-  S.steps[H.fill_step].bytes = H.cap * 8;
-  S.steps[H.fill_step + 1].dev = H.cnt;
-  S.steps[H.fill_step + 1].bytes = H.cap * 8;
-  S.steps[H.fill_step + 2].dev = H.vals;
-  S.steps[H.fill_step + 2].bytes = H.cap * 8 * std::max(1, H.n_vals);
+  if (H.fill_step >= 0) {
+    S.steps[H.fill_step].dev = H.keys;
+    S.steps[H.fill_step].bytes = H.cap * 8;
+    S.steps[H.fill_step + 1].dev = H.cnt;
+    S.steps[H.fill_step + 1].bytes = H.cap * 8;
+    S.steps[H.fill_step + 2].dev = H.vals;
+    S.steps[H.fill_step + 2].bytes = H.cap * 8 * std::max(1, H.n_vals);
+  }
   DHashOut d{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0};
   HIP_OK(hipMemcpy(S.hash_dev + i, &d, sizeof d, hipMemcpyHostToDevice));
 }
@@ -2333,7 +2370,8 @@ static lmfao_status gather_hash(const lmfao_prepared_s* prep, const OutBuf& B, G
   try {
     HIP_OK(hipMemcpy(keys.data(), H.keys, H.cap * 8, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(cnt.data(), H.cnt, H.cap * 8, hipMemcpyDeviceToHost));
-    HIP_OK(hipMemcpy(vals.data(), H.vals, vals.size() * 8, hipMemcpyDeviceToHost));
+    // a counts-only table's values are its counts (added below)
+    if (!H.counts_only) HIP_OK(hipMemcpy(vals.data(), H.vals, vals.size() * 8, hipMemcpyDeviceToHost));
   } catch (const HipError& e) {
     return set_err(LMFAO_EHIP, e.msg);
   }

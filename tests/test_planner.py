@@ -10,6 +10,7 @@ item level, V_{H->S} at the date level and V_{T->S} at the store level.
 """
 import json
 
+import numpy as np
 import pytest
 
 import workloads as W
@@ -239,14 +240,20 @@ def test_wide_chain_groups_are_split_to_fit_the_kernels():
         by_rel.setdefault(g["node"], []).append(g)
     assert len(by_rel["R1"]) > 2
     # SUM(1) group-bys whose table a scan cannot keep in LDS (dense past 12k
-    # cells, or hashed) are counted by radix partition, in groups of their own
+    # cells, hashed, or past what the scan's other tables leave of its LDS
+    # budget) are counted by radix partition, in groups of their own
     part = [o["id"] for g in by_rel["R1"] if g.get("partitioned") for o in g["outputs"]]
     doms = p["domains"]
+    cells_of = {}
+    for qi, q in enumerate(p["batch"]):
+        cells_of[qi] = int(np.prod([doms[a] for a in q["groupby"]])) if q["groupby"] else 0
+    eligible_large = {qi for qi, q in enumerate(p["batch"])
+                      if cells_of[qi] > 12288 and all(not f for f in q["aggs"]) and
+                      all(a.startswith("x") or a == "b" for a in q["groupby"])}
+    assert eligible_large <= set(part)
     for qi in part:
-        cells = 1
-        for a in p["batch"][qi]["groupby"]:
-            cells *= doms[a]
-        assert cells > 12288
+        assert all(not f for f in p["batch"][qi]["aggs"])
+        assert cells_of[qi] > 12288 or len(p["batch"][qi]["groupby"]) == 1
     assert any(len(p["batch"][qi]["groupby"]) == 2 and
                doms[p["batch"][qi]["groupby"][0]] * doms[p["batch"][qi]["groupby"][1]] > 1 << 24 for qi in part)
     for g in d["groups"]:
