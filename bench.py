@@ -201,12 +201,13 @@ def _largest_pass(desc, timing):
 
 def _traffic(prep, kern, kd, config):
     """HBM bytes of the dominant launch from committed counter runs, valid only
-    while its generated source and grid are the ones that were profiled."""
+    while its source (the generated kernel, or the library's kernel file for
+    built-in kernels) and grid are the ones that were profiled."""
+    from paper_2008_08657_amd.profiling import source_digest, builtin_source
     group = kern[0].rsplit(":", 1)[0]
     src = next((x.split("\n", 1)[1] for x in prep.kernel_sources() if x.split("\n", 1)[0] == group), None)
-    if src is None:
-        return None, None
-    from paper_2008_08657_amd.profiling import source_digest
+    if src is None or kd.get("lean", 0) != 2:
+        src = builtin_source() + f"\n// step {kern[0]}"
     digest = source_digest(src + f"\n// grid {kd['grid']}")
     prof_dir = os.path.join(ROOT, "profiles")
     for fn in sorted(os.listdir(prof_dir)) if os.path.isdir(prof_dir) else []:

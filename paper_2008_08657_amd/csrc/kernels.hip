@@ -2808,41 +2808,57 @@ constexpr int kPartTileDense = 16384;
 constexpr int kPartTileHash = 8192;
 int part_tile_rows(bool hashed) { return hashed ? kPartTileHash : kPartTileDense; }
 
-void launch_part_count(const DPartCount* d, const DPartCount& h, hipStream_t s) {
+void launch_part_count(const DPartCount* d, const DPartCount& h, int phase, hipStream_t s) {
   if (h.n_rows <= 0 || h.n_out <= 0) return;
-  bool single = false, dense_multi = false, hashed = false, reduce = false;
   int tiles_dense = 0, tiles_hash = 0, slice_chunks = 0, direct_chunks = 0;
   for (int o = 0; o < h.n_out; ++o) {
     if (h.hashed[o]) {
-      hashed = true;
       tiles_hash = std::max(tiles_hash, h.n_tiles[o]);
     } else if (h.n_buckets[o] <= 1) {
-      single = true;
       direct_chunks = std::max(direct_chunks, h.chunks[o]);
-      reduce |= h.chunks[o] > 1;
     } else {
-      dense_multi = true;
       tiles_dense = std::max(tiles_dense, h.n_tiles[o]);
       slice_chunks = std::max(slice_chunks, h.n_buckets[o] * h.chunks[o]);
-      reduce |= h.chunks[o] > 1;
     }
   }
-  const int g8 = (int)std::min<int64_t>((h.n_rows + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_part_w8, dim3(g8), dim3(256), 0, s, d);
-  if (single)
-    hipLaunchKernelGGL(k_part_direct, dim3(direct_chunks, h.n_out), dim3(kPartCountThreads), kPartSlice * 4, s, d);
-  if (dense_multi) {
-    hipLaunchKernelGGL((k_part_tile<uint16_t, kPartTileDense>), dim3(tiles_dense, h.n_out), dim3(kPartTileThreads),
-                       0, s, d);
-    hipLaunchKernelGGL(k_part_slice_count, dim3(slice_chunks, h.n_out), dim3(kPartCountThreads), kPartSlice * 4, s,
-                       d);
-  }
-  if (reduce) hipLaunchKernelGGL(k_part_reduce, dim3(256, h.n_out), dim3(256), 0, s, d);
-  if (hashed) {
-    hipLaunchKernelGGL((k_part_tile<uint64_t, kPartTileHash>), dim3(tiles_hash, h.n_out), dim3(kPartTileThreads), 0,
-                       s, d);
-    hipLaunchKernelGGL(k_part_bases, dim3(h.n_out), dim3(kPartMaxBuckets), 0, s, d);
-    hipLaunchKernelGGL(k_part_hash, dim3(kPartHashBuckets, h.n_out), dim3(kPartHashWaves * 64), kPartHashLds, s, d);
+  switch (phase) {
+    case kPartPhaseRows: {
+      const int g8 = (int)std::min<int64_t>((h.n_rows + 255) / 256, 8192);
+      hipLaunchKernelGGL(k_part_w8, dim3(g8), dim3(256), 0, s, d);
+      break;
+    }
+    case kPartPhaseDirect:
+      if (direct_chunks)
+        hipLaunchKernelGGL(k_part_direct, dim3(direct_chunks, h.n_out), dim3(kPartCountThreads), kPartSlice * 4, s,
+                           d);
+      break;
+    case kPartPhaseTile:
+      if (tiles_dense)
+        hipLaunchKernelGGL((k_part_tile<uint16_t, kPartTileDense>), dim3(tiles_dense, h.n_out),
+                           dim3(kPartTileThreads), 0, s, d);
+      break;
+    case kPartPhaseSlices:
+      if (slice_chunks)
+        hipLaunchKernelGGL(k_part_slice_count, dim3(slice_chunks, h.n_out), dim3(kPartCountThreads),
+                           kPartSlice * 4, s, d);
+      break;
+    case kPartPhaseReduce:
+      hipLaunchKernelGGL(k_part_reduce, dim3(256, h.n_out), dim3(256), 0, s, d);
+      break;
+    case kPartPhaseTileHash:
+      if (tiles_hash) {
+        hipLaunchKernelGGL((k_part_tile<uint64_t, kPartTileHash>), dim3(tiles_hash, h.n_out), dim3(kPartTileThreads),
+                           0, s, d);
+        hipLaunchKernelGGL(k_part_bases, dim3(h.n_out), dim3(kPartMaxBuckets), 0, s, d);
+      }
+      break;
+    case kPartPhaseHash:
+      if (tiles_hash)
+        hipLaunchKernelGGL(k_part_hash, dim3(kPartHashBuckets, h.n_out), dim3(kPartHashWaves * 64), kPartHashLds, s,
+                           d);
+      break;
+    default:
+      break;
   }
 }
 

@@ -159,8 +159,18 @@ struct DPartCount {
 constexpr int kPartHashBuckets = 512;
 // rows per tile of the tile pass (dense and hashed outputs)
 int part_tile_rows(bool hashed);
-// the launch set's passes (row bytes, direct and slice counts, hashed groups)
-void launch_part_count(const DPartCount* d, const DPartCount& h, hipStream_t s);
+// one pass of the launch set: row bytes, direct counts, slice-ordered tiles,
+// slice counts, partial-table sums, hash-ordered tiles, hashed groups
+enum {
+  kPartPhaseRows = 0,
+  kPartPhaseDirect = 1,
+  kPartPhaseTile = 2,
+  kPartPhaseSlices = 3,
+  kPartPhaseReduce = 4,
+  kPartPhaseTileHash = 5,
+  kPartPhaseHash = 6
+};
+void launch_part_count(const DPartCount* d, const DPartCount& h, int phase, hipStream_t s);
 
 void launch_fill(void* p, int64_t bytes, hipStream_t s);
 // number of nonzero keys (occupied slots) of a hash table, added to *out

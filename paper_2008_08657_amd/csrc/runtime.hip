@@ -729,27 +729,76 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
     d.part64b = n_hash_slots ? (uint64_t*)dalloc(S, (size_t)n_hash_slots * std::max<int64_t>(n, 1) * 8) : nullptr;
     d.htab = S.hash_dev;
     d.err_flag = S.err_flag;
-    Step s;
-    s.name = gname + ":partition" + (base ? std::to_string(base / kPartOuts) : std::string());
-    s.kind = 15;
-    s.dev = upload(S, d, st);
-    s.part = d;
-    s.rows = n;
-    s.grid = (int)((n + part_tile_rows(false) - 1) / part_tile_rows(false));
-    // bytes the method needs: every key column and view key read once; the
-    // counts written once per cell (the partition round trip is the kernel's)
+    // one step per pass of the launch set (each a kernel of its own, timed
+    // and profiled alone): bytes are what the pass must read and write once
+    const void* ddev = upload(S, d, st);
     std::set<int> rc(need.begin(), need.end());
-    for (int c : rc) s.alg_read += (double)n * 4;
-    for (int o = 0; o < d.n_out; ++o)
-      s.alg_write += d.hashed[o] ? (double)std::min<int64_t>(S.hashes[d.hidx[o]].bound, n) * 16
-                                 : (double)d.n_cells[o] * 8;
-    s.relation = r;
-    s.pass_cols.clear();
-    for (int c : rc) s.pass_cols.push_back(source_column(P, r, c));
-    std::sort(s.pass_cols.begin(), s.pass_cols.end());
-    s.pass_cols.erase(std::unique(s.pass_cols.begin(), s.pass_cols.end()), s.pass_cols.end());
+    std::vector<int> pcols;
+    for (int c : rc) pcols.push_back(source_column(P, r, c));
+    std::sort(pcols.begin(), pcols.end());
+    pcols.erase(std::unique(pcols.begin(), pcols.end()), pcols.end());
+    const std::string suffix = base ? std::to_string(base / kPartOuts) : std::string();
+    bool any_single = false, any_multi = false, any_hashed = false, any_chunks = false;
+    double key_single = 0, key_multi = 0, key_hashed = 0, cells_single = 0, cells_multi = 0, groups_hashed = 0;
+    double part_single = 0, part_multi = 0, outs_multi = 0, outs_hashed = 0, offs = 0, tiles_multi = 0;
+    for (int o = 0; o < d.n_out; ++o) {
+      const double keys = (double)n * 4 * d.nkey[o];
+      if (d.hashed[o]) {
+        any_hashed = true;
+        key_hashed += keys;
+        outs_hashed += 1;
+        groups_hashed += (double)std::min<int64_t>(S.hashes[d.hidx[o]].bound, n);
+        offs += (double)d.n_tiles[o] * (d.n_buckets[o] + 1) * 4;
+      } else if (d.n_buckets[o] <= 1) {
+        any_single = true;
+        key_single += keys;
+        cells_single += (double)d.n_cells[o];
+        part_single += d.chunks[o] > 1 ? (double)d.chunks[o] * d.n_cells[o] : 0.0;
+      } else {
+        any_multi = true;
+        key_multi += keys;
+        cells_multi += (double)d.n_cells[o];
+        outs_multi += 1;
+        tiles_multi = std::max(tiles_multi, (double)d.n_tiles[o]);
+        part_multi += d.chunks[o] > 1 ? (double)d.chunks[o] * d.n_cells[o] : 0.0;
+      }
+      any_chunks |= d.chunks[o] > 1;
+    }
+    auto add_phase = [&](int phase, const char* what, double rd, double wr) {
+      Step s;
+      s.name = gname + ":" + what + suffix;
+      s.kind = 15;
+      s.na = phase;
+      s.dev = (void*)ddev;
+      s.part = d;
+      s.rows = n;
+      s.grid = (int)((n + part_tile_rows(false) - 1) / part_tile_rows(false));
+      s.alg_read = rd;
+      s.alg_write = wr;
+      s.relation = r;
+      s.pass_cols = pcols;
+      S.steps.push_back(s);
+    };
+    double vkeys = 0;
+    for (int v = 0; v < d.n_views; ++v) vkeys += (double)n * 4 * d.vnkey[v];
+    add_phase(kPartPhaseRows, "part_rows", vkeys + (d.w ? (double)n * 4 : 0.0), (double)n);
+    if (any_single)
+      add_phase(kPartPhaseDirect, "part_direct", key_single + (double)n,
+                part_single > 0 ? part_single * 4 : cells_single * 8);
+    if (any_multi) {
+      add_phase(kPartPhaseTile, "part_tile", key_multi + (double)n * outs_multi,
+                (double)n * 2 * outs_multi + tiles_multi * outs_multi * 4);
+      add_phase(kPartPhaseSlices, "part_slices", (double)n * 2 * outs_multi,
+                part_multi > 0 ? part_multi * 4 : cells_multi * 8);
+    }
+    if (any_chunks) add_phase(kPartPhaseReduce, "part_reduce", (part_single + part_multi) * 4,
+                              (cells_single + cells_multi) * 8);
+    if (any_hashed) {
+      add_phase(kPartPhaseTileHash, "part_tile_hash", key_hashed + (double)n * outs_hashed,
+                (double)n * 8 * outs_hashed + offs);
+      add_phase(kPartPhaseHash, "part_hash", (double)n * 8 * outs_hashed + offs, groups_hashed * 16);
+    }
     (void)rows_bytes;
-    S.steps.push_back(s);
     for (const DCountCopy& cc : copies) {
       Step t;
       t.name = gname + ":count_copy";
@@ -2044,7 +2093,7 @@ static void enqueue_run(Prep& S, hipStream_t st) {
         break;
       case 13: launch_count_copy((const DCountCopy*)s.dev, s.n, st); break;
       case 14: launch_mult_check((const DMultCheck*)s.dev, s.mult, st); break;
-      case 15: launch_part_count((const DPartCount*)s.dev, s.part, st); break;
+      case 15: launch_part_count((const DPartCount*)s.dev, s.part, s.na, st); break;
       case 8:
         launch_contract_fused((const DContract*)s.dev, (const DGemm*)s.dev2, S.f64,
                               S.P->opts.precision == LMFAO_PREC_BF16X3   ? 3

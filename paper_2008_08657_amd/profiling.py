@@ -26,6 +26,20 @@ def source_digest(text: str) -> str:
     return hashlib.sha1(text.encode()).hexdigest()[:16]
 
 
+def builtin_source() -> str:
+    """The text of the library's built-in kernels (a traffic record of a
+    built-in kernel is valid while this text is unchanged)."""
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "csrc", "kernels.hip")) as f:
+        return f.read()
+
+
+def step_digest(source: str, step: str, grid: int) -> str:
+    """Digest of a built-in kernel's step as bench.py computes it."""
+    return source_digest(source + f"\n// step {step}" + f"\n// grid {grid}")
+
+
 def _counter_rows(path, counter):
     with open(path, newline="") as f:
         for row in csv.DictReader(f):
