@@ -218,6 +218,15 @@ typedef struct {
   int32_t contract_splits; /* ranges the pieces of a matrix-core contraction
                             are cut into, per column of output tiles (0 =
                             1024, fewer past 4096 workgroups)              */
+  uint32_t row_weights;  /* bit r set: relation r (schema index below 32)
+                            takes a 0/1 weight per row, written by the
+                            caller into the buffer lmfao_row_weights returns
+                            (all 1 after lmfao_prepare); every run counts a
+                            tuple of D only if each of its rows in these
+                            relations has weight 1 -- a condition common to
+                            the whole batch whose constants change between
+                            runs without a new plan (a CART node's path,
+                            section 3, decision trees)                     */
 } lmfao_options;
 
 /* Initial capacity of a hash table.  BOUND: twice the most groups the output
@@ -339,6 +348,105 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
  * group's name; the count is "generated_scans" in lmfao_prepared_describe.
  * Same buffer convention as lmfao_plan_describe; LMFAO_EINVAL for a bad i. */
 lmfao_status lmfao_prepared_kernel_source(lmfao_prepared_t prep, int32_t i, char* buf, size_t cap, size_t* need);
+
+/* Row weights of relation `rel` (lmfao_options.row_weights): *weights
+ * receives the DEVICE address of its n_rows int32 weights, in the caller's
+ * row order, owned by `prep` (valid until lmfao_prepared_free).  Writes
+ * between runs take effect at the next lmfao_run, graph replays included;
+ * a weight other than 0 or 1 counts as 1.  LMFAO_EINVAL if the relation
+ * was not given row weights. */
+lmfao_status lmfao_row_weights(lmfao_prepared_t prep, int32_t rel, int32_t** weights);
+
+/* A conjunction of conditions evaluated per row on the GPU:
+ * out[r] = 1 if for every k, column_k[r] op_k constant_k, else 0 (out[r] = 1
+ * for every row when n_conds == 0).  Columns and `out` are DEVICE arrays of
+ * n_rows values; a constant is compared in its column's type (an F32
+ * column's constant is rounded to float first), as lmfao_plan does.  At most
+ * 8 conditions; enqueued on `stream`, not synchronised.  LMFAO_EINVAL for a
+ * bad op, dtype, count or NULL pointer. */
+typedef struct {
+  const void* column;   /* DEVICE column */
+  int32_t dtype;        /* LMFAO_I32 / LMFAO_F32 / LMFAO_F64 */
+  int32_t op;           /* LMFAO_LE ... LMFAO_NE */
+  double constant;
+} lmfao_column_condition;
+lmfao_status lmfao_eval_conditions(int64_t n_rows, int32_t n_conds, const lmfao_column_condition* conds,
+                                   int32_t* out, void* stream);
+
+/* CART split selection and tree growth (paper, section 3, "Decision Trees").
+ * A node is the bag of tuples of D that satisfy its path condition.  A
+ * candidate is a condition on one attribute -- LMFAO_CART_LE: attr <= value,
+ * LMFAO_CART_EQ: attr == value -- whose left branch T holds the node's
+ * tuples where it is true, the right branch the rest (attr > value,
+ * attr != value).  Its cost is VAR(T) + VAR(node \ T), with
+ * VAR(B) = SUM(y^2) - SUM(y)^2 / |B| (0 for an empty branch), FP64.  It is
+ * valid when both branches hold at least min_leaf tuples; among valid
+ * candidates the least cost wins, and candidates whose cost lies within
+ * tie_eps * max(|VAR(node)|, 1) of the least are tied: the first one in the
+ * candidate list wins (list candidates by attribute, then value).
+ * The statistics come from the batch's own results: `query` of a candidate
+ * is a query of the caller's batch whose aggregates 0, 1, 2 are SUM(1),
+ * SUM(y), SUM(y*y) over the tuples where the candidate holds (LE: a query
+ * with the condition and no group-by, `group` 0; EQ: a query grouped by the
+ * attribute alone, `group` its code), and `total_query` is such a query with
+ * no condition and no group-by. */
+enum { LMFAO_CART_LE = 0, LMFAO_CART_EQ = 1 };
+typedef struct {
+  const char* attr;
+  int32_t kind;     /* LMFAO_CART_LE or LMFAO_CART_EQ */
+  double value;
+  int32_t query;
+  int64_t group;
+} lmfao_cart_candidate;
+typedef struct {
+  int32_t n_candidates;
+  const lmfao_cart_candidate* candidates;   /* HOST array, in tie-break order */
+  int32_t total_query;
+  int32_t max_depth;   /* lmfao_cart_grow: nodes at this depth are leaves (at most 8) */
+  int64_t min_leaf;
+  double tie_eps;
+} lmfao_cart_spec;
+typedef struct {
+  int32_t best;     /* chosen candidate, -1 if none is valid */
+  int32_t pad;
+  int64_t n, n_left, n_right;
+  double sum_y, sum_y2, sum_y_left, sum_y2_left;
+  double cost;      /* VAR(left) + VAR(right) of the chosen split (VAR(node) if none) */
+} lmfao_cart_split;
+typedef struct {
+  int32_t parent, depth;
+  int32_t split;        /* candidate index, -1 for a leaf */
+  int32_t left, right;  /* children (left: the candidate holds), -1 for a leaf */
+  int32_t pad;
+  int64_t n;            /* tuples of D in the node */
+  double sum_y, sum_y2;
+  double cost;          /* the split's cost, or VAR(node) for a leaf */
+} lmfao_cart_node;
+
+/* The best split of the node the last lmfao_run of `prep` evaluated, chosen
+ * on the GPU from the device results (one workgroup); `out` is HOST, `costs`
+ * a DEVICE array of n_candidates doubles receiving every candidate's cost
+ * (+inf if invalid), or NULL.  Synchronises `stream`.  LMFAO_EINVAL for a
+ * query index, group row or aggregate layout that does not match the
+ * description above (aggregates 0, 1, 2 must be SUM(1), SUM(y), SUM(y*y) of
+ * one y). */
+lmfao_status lmfao_cart_best_split(lmfao_prepared_t prep, const lmfao_cart_spec* spec, lmfao_cart_split* out,
+                                   double* costs, void* stream);
+
+/* Grows the tree breadth first from the whole of D: for every node above
+ * max_depth it writes the node's path condition into the row weights of the
+ * relations holding the path's attributes (evaluated on the GPU over
+ * `columns`, the caller's DEVICE columns as given to lmfao_prepare, which
+ * must still be valid), runs the batch (a graph replay when the plan was
+ * captured) and selects the split on the GPU; nodes at max_depth take their
+ * statistics from their parent's split.  Node 0 is the root, children follow
+ * in breadth-first order, left before right.  Every attribute a candidate
+ * names must be held by a relation with row weights.  `nodes` is a HOST
+ * array of `cap` entries (2^(max_depth+1) - 1 suffice); *n_nodes receives the
+ * count.  Errors of the runs (kernel flags) are returned. */
+lmfao_status lmfao_cart_grow(lmfao_plan_t plan, lmfao_prepared_t prep, const void* const* const* columns,
+                             const lmfao_cart_spec* spec, lmfao_cart_node* nodes, int32_t cap, int32_t* n_nodes,
+                             void* stream);
 
 /* Ridge linear regression over the batch's results (paper, section 3,
  * "Linear Regression"): x = (1, continuous..., one-hot blocks of the

@@ -75,7 +75,34 @@ class lmfao_options(C.Structure):
                 ("contraction", C.c_int32), ("codegen", C.c_int32), ("hash_slots", C.c_int64),
                 ("sizing", C.c_int32), ("estimator", C.POINTER(C.c_float)), ("estimator_len", C.c_int64),
                 ("graph", C.c_int32), ("one_hot_max", C.c_int32), ("scan_blocks", C.c_int32),
-                ("partition", C.c_int32), ("contract_splits", C.c_int32)]
+                ("partition", C.c_int32), ("contract_splits", C.c_int32), ("row_weights", C.c_uint32)]
+
+
+class lmfao_column_condition(C.Structure):
+    _fields_ = [("column", C.c_void_p), ("dtype", C.c_int32), ("op", C.c_int32), ("constant", C.c_double)]
+
+
+class lmfao_cart_candidate(C.Structure):
+    _fields_ = [("attr", C.c_char_p), ("kind", C.c_int32), ("value", C.c_double), ("query", C.c_int32),
+                ("group", C.c_int64)]
+
+
+class lmfao_cart_spec(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("candidates", C.POINTER(lmfao_cart_candidate)),
+                ("total_query", C.c_int32), ("max_depth", C.c_int32), ("min_leaf", C.c_int64),
+                ("tie_eps", C.c_double)]
+
+
+class lmfao_cart_split(C.Structure):
+    _fields_ = [("best", C.c_int32), ("pad", C.c_int32), ("n", C.c_int64), ("n_left", C.c_int64),
+                ("n_right", C.c_int64), ("sum_y", C.c_double), ("sum_y2", C.c_double),
+                ("sum_y_left", C.c_double), ("sum_y2_left", C.c_double), ("cost", C.c_double)]
+
+
+class lmfao_cart_node(C.Structure):
+    _fields_ = [("parent", C.c_int32), ("depth", C.c_int32), ("split", C.c_int32), ("left", C.c_int32),
+                ("right", C.c_int32), ("pad", C.c_int32), ("n", C.c_int64), ("sum_y", C.c_double),
+                ("sum_y2", C.c_double), ("cost", C.c_double)]
 
 
 class LmfaoError(RuntimeError):
@@ -135,6 +162,15 @@ def load_library(path: str = LIB_PATH):
     lib.lmfao_prepared_free.restype = None
     lib.lmfao_last_error.argtypes = []
     lib.lmfao_last_error.restype = C.c_char_p
+    lib.lmfao_row_weights.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+    lib.lmfao_row_weights.restype = C.c_int32
+    lib.lmfao_eval_conditions.argtypes = [C.c_int64, C.c_int32, C.POINTER(lmfao_column_condition), vp, vp]
+    lib.lmfao_eval_conditions.restype = C.c_int32
+    lib.lmfao_cart_best_split.argtypes = [vp, C.POINTER(lmfao_cart_spec), C.POINTER(lmfao_cart_split), vp, vp]
+    lib.lmfao_cart_best_split.restype = C.c_int32
+    lib.lmfao_cart_grow.argtypes = [vp, vp, C.POINTER(C.POINTER(vp)), C.POINTER(lmfao_cart_spec),
+                                    C.POINTER(lmfao_cart_node), C.c_int32, C.POINTER(C.c_int32), vp]
+    lib.lmfao_cart_grow.restype = C.c_int32
     _lib = lib
     return lib
 
@@ -197,7 +233,7 @@ class Plan:
     def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
                  min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0,
                  sizing="bound", estimator=None, graph=False, one_hot_max=0, scan_blocks=0,
-                 contract_splits=0, partition=True):
+                 contract_splits=0, partition=True, row_weights=()):
         self.lib = load_library()
         self.problem = problem
         keep = _Keep()
@@ -223,6 +259,8 @@ class Plan:
         opts.scan_blocks = int(scan_blocks)
         opts.contract_splits = int(contract_splits)
         opts.partition = 0 if partition else 1
+        rel_names = [r["name"] for r in problem["schema"]]
+        opts.row_weights = sum(1 << rel_names.index(r) for r in row_weights)
         if sizing not in ("bound", "learned", "exact"):
             raise ValueError(f"sizing must be 'bound', 'learned' or 'exact', not {sizing!r}")
         opts.sizing = {"bound": 0, "learned": 1, "exact": 2}[sizing]
@@ -357,6 +395,44 @@ class Prepared:
             _check(self.lib, self.lib.lmfao_prepared_kernel_source(self.handle, i, buf, need.value, C.byref(need)))
             out.append(buf.value.decode())
         return out
+
+    def _cart_spec(self, keep, spec):
+        cands = [lmfao_cart_candidate(keep.s(c["attr"]), {"<=": 0, "==": 1}[c["op"]], float(c["value"]),
+                                      int(c["query"]), int(c.get("group", 0))) for c in spec["candidates"]]
+        arr = keep.arr(lmfao_cart_candidate, cands)
+        sp = lmfao_cart_spec(len(cands), arr, int(spec["total_query"]), int(spec.get("max_depth", 0)),
+                             int(spec.get("min_leaf", 1)), float(spec.get("tie_eps", 1e-9)))
+        keep.refs.append(sp)
+        return sp
+
+    def cart_best_split(self, spec, costs=None) -> dict:
+        """The node's best split from the last run's results, chosen on the
+        GPU (``lmfao_cart_best_split``); ``costs`` an optional float64 device
+        tensor receiving every candidate's cost."""
+        keep = _Keep()
+        sp = self._cart_spec(keep, spec)
+        out = lmfao_cart_split()
+        cp = C.c_void_p(costs.data_ptr()) if costs is not None else None
+        _check(self.lib, self.lib.lmfao_cart_best_split(self.handle, C.byref(sp), C.byref(out), cp, self.stream))
+        return {f: getattr(out, f) for f, _ in lmfao_cart_split._fields_ if f != "pad"}
+
+    def cart_grow(self, spec, columns) -> list:
+        """Grows the regression tree on the GPU (``lmfao_cart_grow``);
+        ``columns`` are the device tensors given to the constructor (they
+        must still be alive).  Returns the nodes as dicts."""
+        keep = _Keep()
+        per_rel = []
+        for r in self.plan.problem["schema"]:
+            ptrs = [C.c_void_p(int(columns[r["name"]][a["name"]].data_ptr())) for a in r["attrs"]]
+            per_rel.append(C.cast(keep.arr(C.c_void_p, ptrs), C.POINTER(C.c_void_p)))
+        cols = keep.arr(C.POINTER(C.c_void_p), per_rel)
+        sp = self._cart_spec(keep, spec)
+        cap = (1 << (int(spec.get("max_depth", 0)) + 1)) - 1
+        nodes = (lmfao_cart_node * cap)()
+        n = C.c_int32()
+        _check(self.lib, self.lib.lmfao_cart_grow(self.plan.handle, self.handle, cols, C.byref(sp), nodes, cap,
+                                                  C.byref(n), self.stream))
+        return [{f: getattr(nodes[i], f) for f, _ in lmfao_cart_node._fields_ if f != "pad"} for i in range(n.value)]
 
     def ridge_sigma(self, continuous, categorical=()):
         """Sigma = sum over D of x x^T assembled on the device from the last

@@ -187,18 +187,102 @@ __device__ __forceinline__ bool cond_holds(double x, int op, double c) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_filter(const DFilter* __restrict__ F) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < F->n_rows;
+__device__ __forceinline__ void filter_rows(const DFilter& F) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < F.n_rows;
        r += (int64_t)gridDim.x * blockDim.x) {
     int w = 1;
-    for (int k = 0; k < F->n_conds; ++k) w &= cond_holds(ld_cmp(F->cols[k], r), F->op[k], F->c[k]) ? 1 : 0;
-    F->out[r] = w;
+    if (F.ext) w = F.ext[F.perm ? (int64_t)F.perm[r] : r] != 0 ? 1 : 0;
+    for (int k = 0; k < F.n_conds; ++k) w &= cond_holds(ld_cmp(F.cols[k], r), F.op[k], F.c[k]) ? 1 : 0;
+    F.out[r] = w;
   }
 }
+__global__ __launch_bounds__(256) void k_filter(const DFilter* __restrict__ F) { filter_rows(*F); }
+__global__ __launch_bounds__(256) void k_filter_value(const DFilter F) { filter_rows(F); }
 void launch_filter(const DFilter* d, int64_t n_rows, hipStream_t s) {
   if (n_rows <= 0) return;
   const int grid = (int)std::min<int64_t>((n_rows + 255) / 256, 8192);
   hipLaunchKernelGGL(k_filter, dim3(grid), dim3(256), 0, s, d);
+}
+void launch_filter_value(const DFilter& f, hipStream_t s) {
+  if (f.n_rows <= 0) return;
+  const int grid = (int)std::min<int64_t>((f.n_rows + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_filter_value, dim3(grid), dim3(256), 0, s, f);
+}
+
+// ---------------------------------------------------------------------------
+// CART split selection (section 3, decision trees)
+// ---------------------------------------------------------------------------
+// One workgroup.  Cost of candidate i = VAR(left) + VAR(right) with
+// VAR(B) = SUM(y^2) - SUM(y)^2 / |B| (0 for an empty branch), in FP64; a
+// candidate is valid when both branches hold at least min_leaf tuples.  The
+// least valid cost is found first; the chosen candidate is the first one
+// (lowest index) within tie_eps * max(|VAR(node)|, 1) of it.
+__device__ __forceinline__ double cart_var(int64_t n, double sy, double sy2) {
+  return n > 0 ? sy2 - sy * sy / (double)n : 0.0;
+}
+
+__global__ void __launch_bounds__(1024) k_cart_split(const int64_t* const* __restrict__ cand_cnt,
+                                                     const double* const* __restrict__ cand_vals, int n_cand,
+                                                     const int64_t* __restrict__ tot_cnt,
+                                                     const double* __restrict__ tot_vals, int64_t min_leaf,
+                                                     double tie_eps, double* __restrict__ costs,
+                                                     DCartBest* __restrict__ best) {
+  __shared__ double red_d[16];
+  __shared__ int red_i[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t n = *tot_cnt;
+  const double sy = tot_vals[1], sy2 = tot_vals[2];
+  double least = INFINITY;
+  for (int i = threadIdx.x; i < n_cand; i += blockDim.x) {
+    const int64_t nl = *cand_cnt[i];
+    const double syl = cand_vals[i][1], sy2l = cand_vals[i][2];
+    const int64_t nr = n - nl;
+    const bool ok = nl >= min_leaf && nr >= min_leaf;
+    const double c = cart_var(nl, syl, sy2l) + cart_var(nr, sy - syl, sy2 - sy2l);
+    costs[i] = ok ? c : INFINITY;
+    if (ok) least = fmin(least, c);
+  }
+  for (int o = 32; o > 0; o >>= 1) least = fmin(least, __shfl_xor(least, o, 64));
+  if (lane == 0) red_d[wid] = least;
+  __syncthreads();
+  least = INFINITY;
+  for (int w = 0; w < nw; ++w) least = fmin(least, red_d[w]);
+  const double tol = tie_eps * fmax(fabs(cart_var(n, sy, sy2)), 1.0);
+  int first = INT_MAX;
+  if (least < INFINITY)
+    for (int i = threadIdx.x; i < n_cand; i += blockDim.x)
+      if (costs[i] <= least + tol) {
+        first = min(first, i);
+        break;   // later indices of this thread are larger
+      }
+  for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
+  if (lane == 0) red_i[wid] = first;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < nw; ++w) first = min(first, red_i[w]);
+    DCartBest b{};
+    b.best = first == INT_MAX ? -1 : first;
+    b.n = n;
+    b.sy = sy;
+    b.sy2 = sy2;
+    if (b.best >= 0) {
+      b.n_left = *cand_cnt[first];
+      b.n_right = n - b.n_left;
+      b.sy_left = cand_vals[first][1];
+      b.sy2_left = cand_vals[first][2];
+      b.cost = costs[first];
+    } else {
+      b.cost = cart_var(n, sy, sy2);
+    }
+    *best = b;
+  }
+}
+
+void launch_cart_split(const int64_t* const* cand_cnt, const double* const* cand_vals, int n_cand,
+                       const int64_t* tot_cnt, const double* tot_vals, int64_t min_leaf, double tie_eps,
+                       double* costs, DCartBest* best, hipStream_t s) {
+  hipLaunchKernelGGL(k_cart_split, dim3(1), dim3(1024), 0, s, cand_cnt, cand_vals, n_cand, tot_cnt, tot_vals,
+                     min_leaf, tie_eps, costs, best);
 }
 
 // bucket = number of thresholds below the value (kind 0) or at most the value

@@ -35,8 +35,25 @@ struct DFilter {
   DCol cols[kMaxFilterConds];
   int32_t op[kMaxFilterConds];
   double c[kMaxFilterConds];   // constant, already in the column's comparison type
+  const int32_t* ext;          // caller's 0/1 row weights in input row order (null: none)
+  const uint32_t* perm;        // row r of this order is input row perm[r] (null: input order)
   int32_t* out;
 };
+
+// best split of a CART node batch (section 3, decision trees): per candidate
+// the left branch's count and sums of y and y^2 are read from the results of
+// the last run, the right branch is the node minus the left
+struct DCartBest {
+  int32_t best;                // candidate index, -1: none valid
+  int32_t pad;
+  int64_t n, n_left, n_right;  // node and branch tuple counts
+  double sy, sy2;              // node sums of y and y^2
+  double sy_left, sy2_left;    // the chosen left branch's
+  double cost;                 // VAR(left) + VAR(right) of the chosen split
+};
+void launch_cart_split(const int64_t* const* cand_cnt, const double* const* cand_vals, int n_cand,
+                       const int64_t* tot_cnt, const double* tot_vals, int64_t min_leaf, double tie_eps,
+                       double* costs, DCartBest* best, hipStream_t s);
 
 // one range query of the caller's batch: sums of a planned query's buckets
 struct DFinalize {
@@ -176,6 +193,8 @@ void launch_fill(void* p, int64_t bytes, hipStream_t s);
 // number of nonzero keys (occupied slots) of a hash table, added to *out
 void launch_count_keys(const unsigned long long* keys, int64_t n, unsigned long long* out, hipStream_t s);
 void launch_filter(const DFilter* d, int64_t n_rows, hipStream_t s);
+// the same with the descriptor passed by value (no device copy)
+void launch_filter_value(const DFilter& f, hipStream_t s);
 void launch_bucketize(const void* src, int dtype, int64_t n, const double* thr, int n_thr, int kind, int32_t* out,
                       hipStream_t s);
 void launch_finalize(const DFinalize* d, int n, hipStream_t s);

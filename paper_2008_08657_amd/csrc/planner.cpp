@@ -1703,6 +1703,8 @@ Plan* build_plan(const lmfao_schema* schema, const lmfao_join_tree* tree, const 
     if (P->opts.scan_blocks < 0 || P->opts.contract_splits < 0 || P->opts.contract_splits > (1 << 20))
       throw PlanError{LMFAO_EINVAL, "scan_blocks and contract_splits must be 0 (automatic) or positive"};
     intake(*P, schema, tree, batch);
+    if (P->rels.size() < 32 && (P->opts.row_weights >> P->rels.size()) != 0)
+      throw PlanError{LMFAO_EINVAL, "row_weights names a relation the schema does not have"};
     compute_uniqueness(*P);
     generate_views(*P);
     view_layouts(*P);

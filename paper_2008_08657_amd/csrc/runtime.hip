@@ -135,6 +135,10 @@ struct lmfao_prepared_s {
   std::vector<std::vector<const void*>> ecols;       // caller's columns, then derived bucket codes
   std::vector<const void* const*> ecol_ptrs;
   std::vector<int32_t*> w_raw, w_sorted;             // filter weights per relation (lazily built)
+  std::vector<int32_t*> row_w;                       // caller-written row weights (options.row_weights)
+  std::vector<uint32_t*> row_perm;                   // sort permutation kept for sorted weights
+  void* cart_dev = nullptr;                          // CART split: candidate pointers, best, costs
+  size_t cart_bytes = 0;
   std::vector<char> w_raw_done, w_sorted_done;
   std::vector<lmfao::NodeData> nodes;
   std::vector<void*> allocs;
@@ -521,6 +525,21 @@ static const int32_t* filter_weights(Prep& S, int r, bool sorted, const void* co
   const RelDef& R = P.rels[r];
   DFilter f{};
   f.n_rows = R.n_rows;
+  const bool ext = r < (int)S.row_w.size() && S.row_w[r];
+  if (ext) {
+    f.ext = S.row_w[r];
+    if (sorted) {
+      // the run reads the caller's weights through the sort permutation
+      NodeData& N = S.nodes[r];
+      if (!S.row_perm[r]) {
+        if (!N.perm) throw PlanError{LMFAO_EINVAL, "internal: row weights without permutation"};
+        S.row_perm[r] = (uint32_t*)dalloc(S, (size_t)std::max<int64_t>(R.n_rows, 1) * 4);
+        if (R.n_rows > 0)
+          HIP_OK(hipMemcpyAsync(S.row_perm[r], N.perm, (size_t)R.n_rows * 4, hipMemcpyDeviceToDevice, st));
+      }
+      f.perm = S.row_perm[r];
+    }
+  }
   for (const Cond& c : P.filter) {
     if (!R.has(c.attr)) continue;
     if (f.n_conds >= kMaxFilterConds) throw PlanError{LMFAO_EUNSUPPORTED, "too many conditions on " + R.name};
@@ -544,7 +563,7 @@ static const int32_t* filter_weights(Prep& S, int r, bool sorted, const void* co
     f.c[f.n_conds] = c.c;
     f.n_conds++;
   }
-  if (f.n_conds == 0) return nullptr;
+  if (f.n_conds == 0 && !ext) return nullptr;
   f.out = (int32_t*)dalloc(S, (size_t)std::max<int64_t>(R.n_rows, 1) * 4);
   Step s;
   s.name = "filter:" + R.name + (sorted ? ":sorted" : ":raw");
@@ -554,6 +573,7 @@ static const int32_t* filter_weights(Prep& S, int r, bool sorted, const void* co
   s.rows = R.n_rows;
   s.alg_read = 0;
   for (int k = 0; k < f.n_conds; ++k) s.alg_read += (double)R.n_rows * dtype_bytes(f.cols[k].dtype);
+  if (ext) s.alg_read += (double)R.n_rows * (sorted ? 8 : 4);
   s.alg_write = (double)R.n_rows * 4;
   S.steps.push_back(s);
   cache[r] = f.out;
@@ -1819,6 +1839,17 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
   S.w_sorted_done.assign(P.rels.size(), 0);
   S.err_flag = (int32_t*)dalloc(S, 8);
   HIP_OK(hipMemsetAsync(S.err_flag, 0, 8, st));
+  // caller-written row weights, all 1 until written
+  S.row_w.assign(P.rels.size(), nullptr);
+  S.row_perm.assign(P.rels.size(), nullptr);
+  for (size_t r = 0; r < P.rels.size() && r < 32; ++r) {
+    if (!((P.opts.row_weights >> r) & 1u)) continue;
+    S.row_w[r] = (int32_t*)dalloc(S, (size_t)std::max<int64_t>(P.rels[r].n_rows, 1) * 4);
+    DFilter ones{};
+    ones.n_rows = P.rels[r].n_rows;
+    ones.out = S.row_w[r];
+    launch_filter_value(ones, st);
+  }
   // the caller's columns, then the derived bucket codes of condition thresholds
   S.ecols.assign(P.rels.size(), {});
   S.ecol_ptrs.assign(P.rels.size(), nullptr);
@@ -2524,6 +2555,222 @@ lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, 
 // ---------------------------------------------------------------------------
 // ridge regression over the batch's results (section 3, linear regression)
 // ---------------------------------------------------------------------------
+lmfao_status lmfao_row_weights(lmfao_prepared_t prep, int32_t rel, int32_t** weights) {
+  g_last_error.clear();
+  if (!prep || !weights) return set_err(LMFAO_EINVAL, "null argument");
+  if (rel < 0 || rel >= (int)prep->row_w.size() || !prep->row_w[rel])
+    return set_err(LMFAO_EINVAL, "relation without row weights (lmfao_options.row_weights)");
+  *weights = prep->row_w[rel];
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_eval_conditions(int64_t n_rows, int32_t n_conds, const lmfao_column_condition* conds,
+                                   int32_t* out, void* stream) {
+  g_last_error.clear();
+  if (n_rows < 0 || n_conds < 0 || (n_conds && !conds) || (n_rows && !out)) return set_err(LMFAO_EINVAL, "bad argument");
+  if (n_conds > kMaxFilterConds) return set_err(LMFAO_EINVAL, "more than 8 conditions");
+  DFilter f{};
+  f.n_rows = n_rows;
+  f.n_conds = n_conds;
+  f.out = out;
+  for (int k = 0; k < n_conds; ++k) {
+    const lmfao_column_condition& c = conds[k];
+    if (!c.column && n_rows) return set_err(LMFAO_EINVAL, "null column");
+    if (c.dtype != LMFAO_I32 && c.dtype != LMFAO_F32 && c.dtype != LMFAO_F64) return set_err(LMFAO_EINVAL, "bad dtype");
+    if (c.op < LMFAO_LE || c.op > LMFAO_NE) return set_err(LMFAO_EINVAL, "bad op");
+    f.cols[k] = DCol{c.column, c.dtype, 0};
+    f.op[k] = c.op;
+    f.c[k] = c.dtype == LMFAO_F32 ? (double)(float)c.constant : c.constant;
+  }
+  try {
+    launch_filter_value(f, (hipStream_t)stream);
+    HIP_OK(hipGetLastError());
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
+}  // extern "C"
+
+namespace lmfao {
+
+// device pointers of every candidate's count and (SUM(1), SUM(y), SUM(y^2))
+// values and of the node totals, checked against the batch: each query's
+// aggregates 0, 1, 2 must be SUM(1), SUM(y), SUM(y*y) of one y
+static lmfao_status cart_inputs(lmfao_prepared_s* prep, const lmfao_cart_spec* spec,
+                                std::vector<const void*>& ptrs) {
+  const Plan& P = *prep->P;
+  if (!spec || spec->n_candidates < 0 || (spec->n_candidates && !spec->candidates))
+    return set_err(LMFAO_EINVAL, "bad CART specification");
+  int y = -1;
+  auto agg_ok = [&](int q) {
+    if (q < 0 || q >= (int)P.user.size()) return false;
+    const QueryDef& Q = P.queries[P.user[q].internal];
+    if (Q.aggs.size() < 3 || !Q.aggs[0].empty() || Q.aggs[1].size() != 1 || Q.aggs[2].size() != 2) return false;
+    const int a = Q.aggs[1][0];
+    if (Q.aggs[2][0] != a || Q.aggs[2][1] != a) return false;
+    if (y < 0) y = a;
+    return y == a;
+  };
+  const int n = spec->n_candidates;
+  ptrs.assign((size_t)2 * n + 2, nullptr);
+  for (int i = 0; i < n; ++i) {
+    const lmfao_cart_candidate& c = spec->candidates[i];
+    if (!agg_ok(c.query)) return set_err(LMFAO_EINVAL, "candidate query without SUM(1), SUM(y), SUM(y*y)");
+    if (c.kind != LMFAO_CART_LE && c.kind != LMFAO_CART_EQ) return set_err(LMFAO_EINVAL, "bad candidate kind");
+    int nk = 0;
+    const OutBuf& B = user_out(prep, c.query, &nk);
+    if (B.hash >= 0) return set_err(LMFAO_EINVAL, "candidate query kept in a hash table");
+    if ((c.kind == LMFAO_CART_LE && (nk != 0 || c.group != 0)) || (c.kind == LMFAO_CART_EQ && nk != 1) ||
+        c.group < 0 || c.group >= B.n_rows)
+      return set_err(LMFAO_EINVAL, "candidate group row does not match its query");
+    ptrs[i] = B.cnt + c.group;
+    ptrs[n + i] = (const double*)B.vals + c.group * B.n_vals;
+  }
+  int nk = 0;
+  if (!agg_ok(spec->total_query)) return set_err(LMFAO_EINVAL, "total query without SUM(1), SUM(y), SUM(y*y)");
+  const OutBuf& T = user_out(prep, spec->total_query, &nk);
+  if (nk != 0 || T.hash >= 0) return set_err(LMFAO_EINVAL, "total query has group-by attributes");
+  ptrs[2 * n] = T.cnt;
+  ptrs[2 * n + 1] = T.vals;
+  return LMFAO_OK;
+}
+
+// uploads the pointers and runs the split kernel; *best on the host
+static lmfao_status cart_split(lmfao_prepared_s* prep, const lmfao_cart_spec* spec,
+                               const std::vector<const void*>& ptrs, double* costs, lmfao_cart_split* out,
+                               hipStream_t st) {
+  const int n = spec->n_candidates;
+  const size_t need = ptrs.size() * 8 + sizeof(DCartBest) + (size_t)std::max(n, 1) * 8 + 256;
+  try {
+    if (prep->cart_bytes < need) {
+      prep->cart_dev = dalloc(*prep, need);
+      prep->cart_bytes = need;
+    }
+    char* base = (char*)prep->cart_dev;
+    const void** dptr = (const void**)base;
+    DCartBest* dbest = (DCartBest*)(base + ((ptrs.size() * 8 + 255) & ~(size_t)255));
+    double* dcost = costs ? costs : (double*)((char*)dbest + 256);
+    HIP_OK(hipMemcpyAsync(dptr, ptrs.data(), ptrs.size() * 8, hipMemcpyHostToDevice, st));
+    launch_cart_split((const int64_t* const*)dptr, (const double* const*)(dptr + n), n,
+                      (const int64_t*)ptrs[2 * n], (const double*)ptrs[2 * n + 1], spec->min_leaf, spec->tie_eps,
+                      dcost, dbest, st);
+    HIP_OK(hipGetLastError());
+    DCartBest b{};
+    HIP_OK(hipMemcpyAsync(&b, dbest, sizeof b, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    *out = lmfao_cart_split{b.best, 0, b.n, b.n_left, b.n_right, b.sy, b.sy2, b.sy_left, b.sy2_left, b.cost};
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
+}  // namespace lmfao
+
+extern "C" {
+
+lmfao_status lmfao_cart_best_split(lmfao_prepared_t prep, const lmfao_cart_spec* spec, lmfao_cart_split* out,
+                                   double* costs, void* stream) {
+  g_last_error.clear();
+  if (!prep || !out) return set_err(LMFAO_EINVAL, "null argument");
+  std::vector<const void*> ptrs;
+  if (lmfao_status e = cart_inputs(prep, spec, ptrs)) return e;
+  if (lmfao_status e = read_flags(prep)) return e;
+  return cart_split(prep, spec, ptrs, costs, out, (hipStream_t)stream);
+}
+
+lmfao_status lmfao_cart_grow(lmfao_plan_t plan, lmfao_prepared_t prep, const void* const* const* columns,
+                             const lmfao_cart_spec* spec, lmfao_cart_node* nodes, int32_t cap, int32_t* n_nodes,
+                             void* stream) {
+  g_last_error.clear();
+  if (!plan || !prep || prep->P != plan->P || !columns || !nodes || !n_nodes || cap < 1)
+    return set_err(LMFAO_EINVAL, "null argument");
+  std::vector<const void*> ptrs;
+  if (lmfao_status e = cart_inputs(prep, spec, ptrs)) return e;
+  if (spec->max_depth < 0 || spec->max_depth > kMaxFilterConds)
+    return set_err(LMFAO_EINVAL, "max_depth must be between 0 and 8");
+  const Plan& P = *prep->P;
+  hipStream_t st = (hipStream_t)stream;
+  // the relation (with row weights) and column holding each candidate's attribute
+  const int nc = spec->n_candidates;
+  std::vector<int> crel(nc), ccol(nc);
+  for (int i = 0; i < nc; ++i) {
+    const char* nm = spec->candidates[i].attr;
+    auto it = nm ? P.attr_id.find(nm) : P.attr_id.end();
+    if (it == P.attr_id.end()) return set_err(LMFAO_EINVAL, "unknown candidate attribute");
+    crel[i] = -1;
+    for (size_t r = 0; r < P.rels.size() && crel[i] < 0; ++r)
+      if (prep->row_w[r] && P.rels[r].has(it->second) && P.rels[r].col.at(it->second) < P.rels[r].n_input_attrs) {
+        crel[i] = (int)r;
+        ccol[i] = P.rels[r].col.at(it->second);
+      }
+    if (crel[i] < 0) return set_err(LMFAO_EINVAL, "a candidate attribute is held by no relation with row weights");
+  }
+  struct Pending {
+    int parent, depth;
+    std::vector<std::pair<int, bool>> path;
+    int64_t n;             // statistics from the parent's split (leaves at max_depth)
+    double sy, sy2;
+  };
+  auto var_of = [](int64_t n, double sy, double sy2) { return n > 0 ? sy2 - sy * sy / (double)n : 0.0; };
+  std::vector<Pending> queue{{-1, 0, {}, 0, 0.0, 0.0}};
+  int count = 0;
+  for (size_t qi = 0; qi < queue.size(); ++qi) {
+    if (count >= cap) return set_err(LMFAO_EINVAL, "node array too small");
+    const Pending nd = queue[qi];
+    lmfao_cart_node& out = nodes[count];
+    out = lmfao_cart_node{nd.parent, nd.depth, -1, -1, -1, 0, nd.n, nd.sy, nd.sy2, var_of(nd.n, nd.sy, nd.sy2)};
+    const int self = count++;
+    if (nd.depth >= spec->max_depth) continue;   // a leaf, statistics from its parent's split
+    // the path condition, pushed into the row weights of the relations holding its attributes
+    try {
+      for (size_t r = 0; r < P.rels.size(); ++r) {
+        if (!prep->row_w[r]) continue;
+        DFilter f{};
+        f.n_rows = P.rels[r].n_rows;
+        f.out = prep->row_w[r];
+        for (const auto& pc : nd.path) {
+          const int i = pc.first;
+          if (crel[i] != (int)r) continue;
+          const lmfao_cart_candidate& c = spec->candidates[i];
+          const int dt = P.rels[r].dtypes[ccol[i]];
+          f.cols[f.n_conds] = DCol{columns[r][ccol[i]], dt, 0};
+          f.op[f.n_conds] = c.kind == LMFAO_CART_LE ? (pc.second ? LMFAO_LE : LMFAO_GT)
+                                                    : (pc.second ? LMFAO_EQ : LMFAO_NE);
+          f.c[f.n_conds] = dt == LMFAO_F32 ? (double)(float)c.value : c.value;
+          f.n_conds++;
+        }
+        launch_filter_value(f, st);
+      }
+      HIP_OK(hipGetLastError());
+    } catch (const HipError& e) {
+      return set_err(LMFAO_EHIP, e.msg);
+    }
+    if (lmfao_status e = lmfao_run(plan, prep, stream, 0)) return e;
+    if (lmfao_status e = read_flags(prep)) return e;
+    lmfao_cart_split sp{};
+    if (lmfao_status e = cart_split(prep, spec, ptrs, nullptr, &sp, st)) return e;
+    out.n = sp.n;
+    out.sum_y = sp.sum_y;
+    out.sum_y2 = sp.sum_y2;
+    out.cost = sp.cost;
+    if (sp.best < 0) continue;
+    out.split = sp.best;
+    // children in breadth-first order: left (the candidate holds), then right
+    Pending L{self, nd.depth + 1, nd.path, sp.n_left, sp.sum_y_left, sp.sum_y2_left};
+    Pending R{self, nd.depth + 1, nd.path, sp.n_right, sp.sum_y - sp.sum_y_left, sp.sum_y2 - sp.sum_y2_left};
+    L.path.push_back({sp.best, true});
+    R.path.push_back({sp.best, false});
+    out.left = (int32_t)queue.size();
+    out.right = (int32_t)queue.size() + 1;
+    queue.push_back(L);
+    queue.push_back(R);
+  }
+  *n_nodes = count;
+  return LMFAO_OK;
+}
 lmfao_status lmfao_ridge_sigma(lmfao_prepared_t prep, int32_t n_cont, const char* const* cont, int32_t n_cat,
                                const char* const* cat, double* sigma, int32_t* dim_out, void* stream) {
   g_last_error.clear();

@@ -458,6 +458,45 @@ def cart_node(seed: int = 0, n_inv: int = 84_000_000, n_thr: int = 20, n_node_co
 
 
 
+def cart_tree(seed: int = 0, n_inv: int = 200_000, n_thr: int = 8, cont=None, cats=None, label: str = "units",
+              **retail_kw):
+    """The node batch of regression-tree growth by CART on the retail-shaped
+    snowflake (section 3, decision trees), the same for every node: per
+    continuous candidate attribute and distinct threshold (``n_thr`` quantile
+    thresholds of its base column) a query with the condition x <= t and the
+    aggregates SUM(1), SUM(y), SUM(y^2) of y = ``label``; per categorical
+    attribute one query grouped by it with the same aggregates (a candidate
+    x == v per code v); and the node totals.  A node's path condition is
+    applied through per-row weights of the relations holding the candidate
+    attributes (``row_weights``).  ``cart`` lists the candidates in
+    tie-break order (attributes as listed, then values) with the query and
+    group row holding each one's statistics."""
+    p = retail_snowflake(seed=seed, n_inv=n_inv, **retail_kw)
+    owner = {}
+    for r in p["schema"]:
+        for a in r["attrs"]:
+            owner.setdefault(a["name"], r["name"])
+    dom = {a["name"]: a["domain"] for r in p["schema"] for a in r["attrs"]}
+    cont = list(cont) if cont is not None else ["i1", "i2", "s1", "s2", "d1", "w1", "w2"]
+    cats = list(cats) if cats is not None else ["icat1", "scat1", "wcat1"]
+    stats = [[], [(label, 1)], [(label, 2)]]
+    batch, cands = [], []
+    for x in cont:
+        for t in sorted(set(quantile_thresholds(p["data"][owner[x]][x], n_thr))):
+            cands.append({"attr": x, "op": "<=", "value": t, "query": len(batch), "group": 0})
+            batch.append({"groupby": [], "where": [(x, "<=", t)], "aggs": stats, "root": None})
+    for c in cats:
+        q = len(batch)
+        batch.append({"groupby": [c], "where": [], "aggs": stats, "root": None})
+        for v in range(int(dom[c])):
+            cands.append({"attr": c, "op": "==", "value": v, "query": q, "group": v})
+    total = len(batch)
+    batch.append({"groupby": [], "where": [], "aggs": stats, "root": None})
+    p.update(name="cart_tree", batch=batch, label=label, cart={"candidates": cands, "total_query": total},
+             row_weights=sorted({owner[x] for x in cont + cats}))
+    return p
+
+
 def rkmeans_chain(seed: int = 0, n1: int = 50_000_000, n2: int = 5_000_000, n3: int = 200_000,
                   n_x: int = 40, n_y: int = 30, n_z: int = 30, max_dom: int = 1_000_000, zipf: float = 0.0):
     """Step 1 of Rk-means (section 3, Rk-means) on a chain join R1(a, b, x*) -
