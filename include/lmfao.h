@@ -298,6 +298,22 @@ lmfao_status lmfao_plan_workspace_bytes(lmfao_plan_t plan, size_t* bytes);
 lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns,
                            void* stream, lmfao_prepared_t* out);
 
+/* lmfao_prepare with every device buffer of the prepared plan -- sorted
+ * columns, pieces, views, results, hash tables, sort scratch, and later the
+ * compacted results of lmfao_result_device and regrown hash tables -- carved
+ * from the caller's `workspace` (a DEVICE allocation of `workspace_bytes`
+ * bytes, aligned to 256 bytes, e.g. a torch tensor; the library allocates no
+ * device memory for this handle).  Nothing is handed back before
+ * lmfao_prepared_free, so scratch counts in full.  A workspace that is too
+ * small gives LMFAO_ENOMEM (message: the bytes carved so far).
+ * lmfao_prepared_workspace_bytes of a handle prepared from the same plan and
+ * inputs gives the bytes needed: what lmfao_prepare carved, plus with
+ * with_results != 0 what lmfao_result_device carves for every query.  The
+ * workspace must stay allocated until lmfao_prepared_free. */
+lmfao_status lmfao_prepare_in(lmfao_plan_t plan, const void* const* const* columns, void* workspace,
+                              size_t workspace_bytes, void* stream, lmfao_prepared_t* out);
+lmfao_status lmfao_prepared_workspace_bytes(lmfao_prepared_t prep, int32_t with_results, size_t* bytes);
+
 /* Evaluates the whole batch: every view and query of the plan, level by
  * level, on `stream`.  Enqueue only: returns once the work is queued unless
  * `sync` is nonzero (then it synchronizes and checks key-uniqueness and
@@ -305,15 +321,34 @@ lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns,
  * are overwritten by the next lmfao_run on the same handle. */
 lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, int32_t sync);
 
+/* Result of query q of the caller's batch after a completed run, compacted
+ * on the GPU (section 2: the output of the batch): the present groups
+ * (count > 0) in lexicographic key order -- dense tables by a scan over their
+ * cells, hash tables by a scan over their slots and a radix sort by key.
+ * DEVICE arrays owned by `prep`: keys n_groups x n_keys int64 (row-major),
+ * counts n_groups int64, values n_groups x n_aggs double.  They stay valid
+ * until the next lmfao_run on `prep` (the next call after that compacts
+ * again) or lmfao_prepared_free.  Reads the run's error flags first (any
+ * kernel error is returned); synchronises `stream`. */
+typedef struct {
+  int64_t n_groups;
+  int32_t n_keys, n_aggs;
+  const int64_t* keys;
+  const int64_t* counts;
+  const double* values;
+} lmfao_output;
+lmfao_status lmfao_result_device(lmfao_prepared_t prep, int32_t q, lmfao_output* out, void* stream);
+
 /* Result of query q after a completed run: number of present groups (groups
  * with at least one join tuple; lexicographic key order), number of group-by
  * attributes and aggregates. */
 lmfao_status lmfao_result_shape(lmfao_prepared_t prep, int32_t q, int64_t* n_groups,
                                 int32_t* n_keys, int32_t* n_aggs);
 
-/* Copies query q's result to HOST buffers: keys (n_groups x n_keys int64, may
- * be NULL), counts (n_groups int64, may be NULL), values (n_groups x n_aggs
- * double, may be NULL).  Synchronizes the device. */
+/* Copies query q's result (compacted on the GPU as lmfao_result_device) to
+ * HOST buffers: keys (n_groups x n_keys int64, may be NULL), counts
+ * (n_groups int64, may be NULL), values (n_groups x n_aggs double, may be
+ * NULL).  Synchronizes the device. */
 lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys,
                                int64_t* counts, double* values);
 

@@ -78,6 +78,11 @@ class lmfao_options(C.Structure):
                 ("partition", C.c_int32), ("contract_splits", C.c_int32), ("row_weights", C.c_uint32)]
 
 
+class lmfao_output(C.Structure):
+    _fields_ = [("n_groups", C.c_int64), ("n_keys", C.c_int32), ("n_aggs", C.c_int32), ("keys", C.c_void_p),
+                ("counts", C.c_void_p), ("values", C.c_void_p)]
+
+
 class lmfao_column_condition(C.Structure):
     _fields_ = [("column", C.c_void_p), ("dtype", C.c_int32), ("op", C.c_int32), ("constant", C.c_double)]
 
@@ -162,6 +167,12 @@ def load_library(path: str = LIB_PATH):
     lib.lmfao_prepared_free.restype = None
     lib.lmfao_last_error.argtypes = []
     lib.lmfao_last_error.restype = C.c_char_p
+    lib.lmfao_prepare_in.argtypes = [vp, C.POINTER(C.POINTER(vp)), vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.lmfao_prepare_in.restype = C.c_int32
+    lib.lmfao_prepared_workspace_bytes.argtypes = [vp, C.c_int32, C.POINTER(C.c_size_t)]
+    lib.lmfao_prepared_workspace_bytes.restype = C.c_int32
+    lib.lmfao_result_device.argtypes = [vp, C.c_int32, C.POINTER(lmfao_output), vp]
+    lib.lmfao_result_device.restype = C.c_int32
     lib.lmfao_row_weights.argtypes = [vp, C.c_int32, C.POINTER(vp)]
     lib.lmfao_row_weights.restype = C.c_int32
     lib.lmfao_eval_conditions.argtypes = [C.c_int64, C.c_int32, C.POINTER(lmfao_column_condition), vp, vp]
@@ -178,6 +189,14 @@ def load_library(path: str = LIB_PATH):
 def _check(lib, st):
     if st != 0:
         raise LmfaoError(st, lib.lmfao_last_error().decode(errors="replace"))
+
+
+class _DeviceArray:
+    """A device array the library owns, described to torch without a copy."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(int(x) for x in shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 2, "strides": None}
 
 
 class _Keep:
@@ -312,7 +331,7 @@ class Prepared:
     contiguous, int32 / float32 / float64 as declared).  The plan must outlive
     this object."""
 
-    def __init__(self, plan: Plan, columns: dict, stream=None):
+    def __init__(self, plan: Plan, columns: dict, stream=None, workspace=None):
         self.plan = plan
         self.lib = plan.lib
         keep = _Keep()
@@ -323,8 +342,41 @@ class Prepared:
         cols = keep.arr(C.POINTER(C.c_void_p), per_rel)
         self.stream = C.c_void_p(stream) if stream else C.c_void_p()
         h = C.c_void_p()
-        _check(self.lib, self.lib.lmfao_prepare(plan.handle, cols, self.stream, C.byref(h)))
+        if workspace is None:
+            _check(self.lib, self.lib.lmfao_prepare(plan.handle, cols, self.stream, C.byref(h)))
+        else:
+            # a caller (torch) allocation holds every device buffer of the handle
+            self.workspace = workspace
+            _check(self.lib, self.lib.lmfao_prepare_in(plan.handle, cols, C.c_void_p(workspace.data_ptr()),
+                                                       workspace.numel() * workspace.element_size(),
+                                                       self.stream, C.byref(h)))
         self.handle = h
+
+    def workspace_bytes(self, with_results=True) -> int:
+        """Bytes a workspace must hold for this plan and these inputs
+        (``lmfao_prepared_workspace_bytes``)."""
+        b = C.c_size_t()
+        _check(self.lib, self.lib.lmfao_prepared_workspace_bytes(self.handle, 1 if with_results else 0,
+                                                                 C.byref(b)))
+        return int(b.value)
+
+    def result_device(self, q: int) -> dict:
+        """Query q's result compacted on the GPU (``lmfao_result_device``):
+        torch tensors over the library's device arrays (no copy), valid until
+        the next run."""
+        import torch
+        o = lmfao_output()
+        _check(self.lib, self.lib.lmfao_result_device(self.handle, int(q), C.byref(o), self.stream))
+        n = int(o.n_groups)
+
+        def view(ptr, shape, typestr, dtype):
+            if n == 0 or not ptr:
+                return torch.empty(shape, dtype=dtype, device="cuda")
+            return torch.as_tensor(_DeviceArray(ptr, shape, typestr), device="cuda")
+
+        return {"keys": view(o.keys, (n, o.n_keys), "<i8", torch.int64),
+                "count": view(o.counts, (n,), "<i8", torch.int64),
+                "sum": view(o.values, (n, o.n_aggs), "<f8", torch.float64)}
 
     def run(self, sync=True, stream=None):
         s = C.c_void_p(stream) if stream is not None else self.stream

@@ -646,27 +646,88 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of hist[0..m) in one block of 1024 threads (chunked)
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, int64_t m) {
-  __shared__ uint32_t part[1024];
-  int64_t chunk = (m + 1023) / 1024;
-  int64_t b = threadIdx.x * chunk, e = std::min<int64_t>(m, b + chunk);
-  uint32_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += a[i];
-  part[threadIdx.x] = s;
+// ---------------------------------------------------------------------------
+// exclusive scan of a uint32 array over many workgroups: per tile of
+// kScanTile values its sum, a scan of the tile sums in one workgroup, then
+// every tile rescanned from its offset (in place); the total is written
+// after the tile sums (bsum[n_tiles])
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t x = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += x;
+  }
+  if (lane == 63) wsum[wid] = incl;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int w = 0; w < nw; ++w) {
+    const uint32_t x = wsum[w];
+    before += w < wid ? x : 0u;
+    all += x;
   }
-  uint32_t run = part[threadIdx.x] - s;
-  for (int64_t i = b; i < e; ++i) {
-    uint32_t v = a[i];
-    a[i] = run;
-    run += v;
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const uint32_t* __restrict__ a, int64_t m,
+                                                           uint32_t* __restrict__ bsum) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  uint32_t s = 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) s += base + u < m ? a[base + u] : 0u;
+  uint32_t total;
+  (void)block_scan_excl(s, &total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(uint32_t* __restrict__ bsum, int64_t nb) {
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t v = b < nb ? bsum[b] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_scan_excl(v, &total);
+    if (b < nb) bsum[b] = carry + ex;
+    carry += total;
   }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_rescan(uint32_t* __restrict__ a, int64_t m,
+                                                             const uint32_t* __restrict__ bsum) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  uint32_t v[kScanPer], s = 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    v[u] = base + u < m ? a[base + u] : 0u;
+    s += v[u];
+  }
+  uint32_t total;
+  uint32_t run = bsum[blockIdx.x] + block_scan_excl(s, &total);
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u)
+    if (base + u < m) {
+      a[base + u] = run;
+      run += v[u];
+    }
+}
+
+int64_t scan_tiles(int64_t m) { return (m + kScanTile - 1) / kScanTile; }
+
+void launch_scan_excl(uint32_t* a, int64_t m, uint32_t* bsum, hipStream_t s) {
+  const int64_t nb = scan_tiles(m);
+  if (nb > 0) hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, m, bsum);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, bsum, nb);
+  if (nb > 0) hipLaunchKernelGGL(k_tile_rescan, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, m, bsum);
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* __restrict__ kin,
@@ -726,7 +787,7 @@ void launch_sort(uint64_t* keys, uint32_t* idx, uint64_t* keys_tmp, uint32_t* id
   for (int p = 0; p < passes; ++p) {
     int shift = p * 8;
     hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, s, ka, n, shift, hist, nblocks);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * nblocks);
+    launch_scan_excl(hist, (int64_t)256 * nblocks, hist + (int64_t)256 * nblocks, s);
     hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, ka, va, kb, vb, n, shift,
                        hist, nblocks);
     std::swap(ka, kb);
@@ -736,6 +797,59 @@ void launch_sort(uint64_t* keys, uint32_t* idx, uint64_t* keys_tmp, uint32_t* id
 }
 
 int sort_tile() { return kSortTile; }
+
+// ---------------------------------------------------------------------------
+// result compaction (present groups, lexicographic order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool compact_present(const DCompact& D, int64_t i) {
+  return (!D.hkeys || D.hkeys[i] != 0ull) && D.cnt[i] > 0;
+}
+
+__device__ __forceinline__ void compact_emit_one(const DCompact& D, int64_t p, int64_t row, int64_t slot) {
+  for (int k = 0; k < D.n_keys; ++k) D.keys_out[p * D.n_keys + k] = (row / D.stride[k]) % D.dom[k];
+  const int64_t c = D.cnt[slot];
+  D.cnt_out[p] = c;
+  for (int j = 0; j < D.n_vals; ++j)
+    D.vals_out[p * D.n_vals + j] =
+        (D.vals ? D.vals[slot * D.n_vals + j] : 0.0) + (((D.copy_mask >> j) & 1ull) ? (double)c : 0.0);
+}
+
+__global__ void k_compact_flags(const DCompact D) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < D.n_src; i += (int64_t)gridDim.x * blockDim.x)
+    D.pos[i] = compact_present(D, i) ? 1u : 0u;
+}
+
+__global__ void k_compact_place(const DCompact D) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < D.n_src;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (!compact_present(D, i)) continue;
+    const int64_t p = D.pos[i];
+    if (D.hkeys) {
+      D.rows[p] = D.hkeys[i] - 1ull;
+      D.slot[p] = (uint32_t)i;
+    } else {
+      compact_emit_one(D, p, i, i);
+    }
+  }
+}
+
+__global__ void k_compact_emit(const DCompact D, int64_t n) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+    compact_emit_one(D, p, (int64_t)D.rows[p], (int64_t)D.slot[p]);
+}
+
+void launch_compact(const DCompact& d, hipStream_t s) {
+  const int grid = (int)std::min<int64_t>(std::max<int64_t>((d.n_src + 255) / 256, 1), 8192);
+  hipLaunchKernelGGL(k_compact_flags, dim3(grid), dim3(256), 0, s, d);
+  launch_scan_excl(d.pos, d.n_src, d.pos + d.n_src, s);
+  hipLaunchKernelGGL(k_compact_place, dim3(grid), dim3(256), 0, s, d);
+}
+
+void launch_compact_emit(const DCompact& d, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_compact_emit, dim3(grid), dim3(256), 0, s, d, n);
+}
 
 __global__ void k_validate(const int32_t* __restrict__ col, int64_t n, int64_t dom, int32_t* err) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {

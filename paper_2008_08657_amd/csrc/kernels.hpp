@@ -217,6 +217,35 @@ void launch_make_keys(const DKeyCols* d, uint64_t* keys, uint32_t* idx, int64_t 
 void launch_sort(uint64_t* keys, uint32_t* idx, uint64_t* keys_tmp, uint32_t* idx_tmp, int64_t n, int bits,
                  uint32_t* hist, hipStream_t s, bool* swapped);
 int sort_tile();
+// A query's result compacted on the device into its present groups (count
+// > 0), keys decomposed per attribute, in lexicographic key order: dense
+// tables in row order (the row is the mixed-radix key, first attribute most
+// significant), hash tables gathered and then sorted by row.
+struct DCompact {
+  const int64_t* cnt;                  // [n_src] dense rows or hash slots
+  const double* vals;                  // [n_src x n_vals], null: no stored values
+  const unsigned long long* hkeys;     // hash tables: row + 1 per slot, 0 = empty; null: dense
+  int64_t n_src;
+  int32_t n_vals, n_keys;
+  uint64_t copy_mask;                  // value components equal to the count, added from it
+  int64_t stride[4], dom[4];           // key decomposition of a row
+  uint32_t* pos;                       // [n_src + scan tiles + 1]: present flags, then positions
+  uint64_t* rows;                      // hash tables: rows of the present groups
+  uint32_t* slot;                      // ... and their slots
+  int64_t* keys_out;                   // [groups x n_keys]
+  int64_t* cnt_out;                    // [groups]
+  double* vals_out;                    // [groups x n_vals]
+};
+// flags, scan and (dense) emission; *groups receives the group count (pos
+// must hold scan_tiles(n_src) + 1 more values)
+void launch_compact(const DCompact& d, hipStream_t s);
+// hash tables after launch_compact: emission of the n sorted groups
+void launch_compact_emit(const DCompact& d, int64_t n, hipStream_t s);
+
+// exclusive scan of a[0..m) in place over many workgroups; bsum holds
+// scan_tiles(m) + 1 values and receives the tile offsets, then the total
+int64_t scan_tiles(int64_t m);
+void launch_scan_excl(uint32_t* a, int64_t m, uint32_t* bsum, hipStream_t s);
 void launch_gather(const void* src, const uint32_t* perm, void* dst, int64_t n, int elem_bytes, hipStream_t s);
 void launch_gather_convert(const void* src, int src_dtype, const uint32_t* perm, void* dst, int64_t n, bool to_f64,
                            hipStream_t s);

@@ -114,6 +114,16 @@ struct Step {
   int64_t rows = 0, pieces = 0;
 };
 
+// a caller query's result compacted on the device (lmfao_result_device)
+struct Compacted {
+  int64_t epoch = -1;          // the run it was compacted after (-1: never)
+  int64_t n_groups = 0;
+  int64_t cap = 0;             // groups the buffers hold
+  int64_t* keys = nullptr;     // [cap x n_keys]
+  int64_t* cnt = nullptr;      // [cap]
+  double* vals = nullptr;      // [cap x n_vals]
+};
+
 }  // namespace lmfao
 
 struct lmfao_plan_s {
@@ -139,6 +149,17 @@ struct lmfao_prepared_s {
   std::vector<uint32_t*> row_perm;                   // sort permutation kept for sorted weights
   void* cart_dev = nullptr;                          // CART split: candidate pointers, best, costs
   size_t cart_bytes = 0;
+  char* ws = nullptr;                                // caller's workspace (lmfao_prepare_in), or null
+  size_t ws_cap = 0;
+  size_t ws_used = 0;                                // bytes carved (workspace or hipMalloc)
+  size_t ws_prepared = 0;                            // ... when lmfao_prepare returned
+  int64_t run_epoch = 0;                             // runs enqueued
+  std::vector<lmfao::Compacted> compact;             // device results per caller query
+  uint32_t* cpos = nullptr;                          // compaction scratch: flags and positions
+  int64_t cpos_n = 0;
+  uint64_t *crows = nullptr, *crows2 = nullptr;      // ... hashed groups' rows and slots, sort buffers
+  uint32_t *cslot = nullptr, *cslot2 = nullptr, *chist = nullptr;
+  int64_t crows_n = 0;
   std::vector<char> w_raw_done, w_sorted_done;
   std::vector<lmfao::NodeData> nodes;
   std::vector<void*> allocs;
@@ -157,9 +178,10 @@ struct lmfao_prepared_s {
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     for (auto& e : ev) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
-    for (auto& H : hashes)
-      for (void* p : {(void*)H.keys, (void*)H.cnt, (void*)H.vals})
-        if (p) (void)hipFree(p);
+    if (!ws)
+      for (auto& H : hashes)
+        for (void* p : {(void*)H.keys, (void*)H.cnt, (void*)H.vals})
+          if (p) (void)hipFree(p);
   }
 };
 
@@ -167,12 +189,37 @@ namespace lmfao {
 
 using Prep = lmfao_prepared_s;
 
-static void* dalloc(Prep& S, size_t bytes) {
-  void* p = nullptr;
+// Device memory of a prepared plan.  With a caller's workspace
+// (lmfao_prepare_in) every buffer is carved from it, 256-byte aligned, and
+// nothing is returned before the handle is freed; otherwise hipMalloc.  Both
+// count the bytes carved, which is what a workspace for the same plan and
+// inputs must hold (lmfao_prepared_workspace_bytes).
+static void* dmem(Prep& S, size_t bytes) {
   if (bytes == 0) bytes = 8;
+  const size_t carved = (bytes + 255) & ~(size_t)255;
+  if (S.ws) {
+    if (S.ws_used + carved > S.ws_cap)
+      throw PlanError{LMFAO_ENOMEM, "workspace of " + std::to_string(S.ws_cap) + " bytes is too small (" +
+                                        std::to_string(S.ws_used + carved) + " bytes needed so far)"};
+    void* p = S.ws + S.ws_used;
+    S.ws_used += carved;
+    return p;
+  }
+  void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) throw HipError{"hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e)};
-  S.allocs.push_back(p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw PlanError{LMFAO_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e)};
+  }
+  S.ws_used += carved;
+  return p;
+}
+static void dfree(Prep& S, void* p) {
+  if (!S.ws && p) (void)hipFree(p);
+}
+static void* dalloc(Prep& S, size_t bytes) {
+  void* p = dmem(S, bytes);
+  if (!S.ws) S.allocs.push_back(p);
   return p;
 }
 
@@ -271,12 +318,14 @@ static void prepare_node(Prep& S, int r, int cut, const std::vector<int>& need_c
     DKeyCols* dkc = upload(S, kc, st);
     uint64_t *keys, *keys2;
     uint32_t *idx, *idx2, *hist;
-    HIP_OK(hipMalloc(&keys, std::max<int64_t>(n, 1) * 8));
-    HIP_OK(hipMalloc(&keys2, std::max<int64_t>(n, 1) * 8));
-    HIP_OK(hipMalloc(&idx, std::max<int64_t>(n, 1) * 4));
-    HIP_OK(hipMalloc(&idx2, std::max<int64_t>(n, 1) * 4));
+    keys = (uint64_t*)dmem(S, std::max<int64_t>(n, 1) * 8);
+    keys2 = (uint64_t*)dmem(S, std::max<int64_t>(n, 1) * 8);
+    idx = (uint32_t*)dmem(S, std::max<int64_t>(n, 1) * 4);
+    idx2 = (uint32_t*)dmem(S, std::max<int64_t>(n, 1) * 4);
     int nblocks = (int)((n + sort_tile() - 1) / sort_tile());
-    HIP_OK(hipMalloc(&hist, (size_t)256 * std::max(nblocks, 1) * 4));
+    // digit counts per block, then the scan's tile sums and total
+    const int64_t hist_n = (int64_t)256 * std::max(nblocks, 1);
+    hist = (uint32_t*)dmem(S, (size_t)(hist_n + scan_tiles(hist_n) + 1) * 4);
     if (n > 0) {
       launch_make_keys(dkc, keys, idx, n, st);
       bool swapped = false;
@@ -297,9 +346,9 @@ static void prepare_node(Prep& S, int r, int cut, const std::vector<int>& need_c
       unsigned long long* dcount;
       int64_t* dpos;
       uint64_t* dkey;
-      HIP_OK(hipMalloc(&dcount, 8));
-      HIP_OK(hipMalloc(&dpos, cap * 8));
-      HIP_OK(hipMalloc(&dkey, cap * 8));
+      dcount = (unsigned long long*)dmem(S, 8);
+      dpos = (int64_t*)dmem(S, cap * 8);
+      dkey = (uint64_t*)dmem(S, cap * 8);
       HIP_OK(hipMemsetAsync(dcount, 0, 8, st));
       if (n > 0) launch_segment_starts(keys, n, div, dcount, dpos, dkey, cap, st);
       unsigned long long cnt = 0;
@@ -312,21 +361,21 @@ static void prepare_node(Prep& S, int r, int cut, const std::vector<int>& need_c
           HIP_OK(hipMemcpy(hpos.data(), dpos, cnt * 8, hipMemcpyDeviceToHost));
           HIP_OK(hipMemcpy(hkey.data(), dkey, cnt * 8, hipMemcpyDeviceToHost));
         }
-        (void)hipFree(dcount);
-        (void)hipFree(dpos);
-        (void)hipFree(dkey);
+        dfree(S, dcount);
+        dfree(S, dpos);
+        dfree(S, dkey);
         break;
       }
       cap = (int64_t)cnt;
-      (void)hipFree(dcount);
-      (void)hipFree(dpos);
-      (void)hipFree(dkey);
+      dfree(S, dcount);
+      dfree(S, dpos);
+      dfree(S, dkey);
     }
     HIP_OK(hipStreamSynchronize(st));
-    (void)hipFree(keys);
-    (void)hipFree(keys2);
-    (void)hipFree(idx2);
-    (void)hipFree(hist);
+    dfree(S, keys);
+    dfree(S, keys2);
+    dfree(S, idx2);
+    dfree(S, hist);
     N.perm = idx;
     // pieces: segments in row order, split so that the scan has about
     // kTargetItems work items of whole 64-row chunks (small relations get
@@ -1635,19 +1684,15 @@ static int64_t distinct_in(Prep& S, int a, int r, hipStream_t st) {
   if (c != P.rels[r].col.end() && P.rels[r].dtypes[c->second] == LMFAO_I32 && A.domain > 0) {
     const int best = r, bc = c->second;
     const int64_t words = (A.domain + 31) / 32;
-    void *bits = nullptr, *cnt = nullptr;
-    HIP_OK(hipMalloc(&bits, (size_t)words * 4));
-    if (hipMalloc(&cnt, 8) != hipSuccess) {
-      (void)hipFree(bits);
-      throw PlanError{LMFAO_ENOMEM, "distinct-count counter"};
-    }
+    void* bits = dmem(S, (size_t)words * 4);
+    void* cnt = dmem(S, 8);
     launch_distinct((const int32_t*)S.ecols[best][bc], P.rels[best].n_rows, A.domain, (uint32_t*)bits,
                     (unsigned long long*)cnt, st);
     unsigned long long h = 0;
     hipError_t e = hipMemcpyAsync(&h, cnt, 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(bits);
-    (void)hipFree(cnt);
+    dfree(S, bits);
+    dfree(S, cnt);
     if (e != hipSuccess) throw PlanError{LMFAO_EHIP, std::string("distinct count: ") + hipGetErrorString(e)};
     d = (int64_t)h;
   }
@@ -1812,19 +1857,21 @@ constexpr int64_t kHashInitSlots = (int64_t)1 << 26;
 // throws PlanError{LMFAO_ENOMEM}.
 static void alloc_hash(Prep& S, HashBuf& H, int64_t old_cap = 0) {
   void* fresh[3] = {nullptr, nullptr, nullptr};
-  const size_t bytes[3] = {(size_t)H.cap * 8, (size_t)H.cap * 8, (size_t)H.cap * 8 * std::max(1, H.n_vals)};
+  // a counts-only table's values are never read (they are its counts)
+  const size_t bytes[3] = {(size_t)H.cap * 8, (size_t)H.cap * 8,
+                           H.counts_only ? (size_t)8 : (size_t)H.cap * 8 * std::max(1, H.n_vals)};
   for (int i = 0; i < 3; ++i) {
-    hipError_t e = hipMalloc(&fresh[i], std::max<size_t>(bytes[i], 8));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      for (int j = 0; j < i; ++j) (void)hipFree(fresh[j]);
+    try {
+      fresh[i] = dmem(S, std::max<size_t>(bytes[i], 8));
+    } catch (const PlanError& e) {
+      for (int j = 0; j < i; ++j) dfree(S, fresh[j]);
       const int64_t want = H.cap;
       if (old_cap) H.cap = old_cap;
-      throw PlanError{LMFAO_ENOMEM, "hash table of " + std::to_string(want) + " slots: " + hipGetErrorString(e)};
+      throw PlanError{LMFAO_ENOMEM, "hash table of " + std::to_string(want) + " slots: " + e.msg};
     }
   }
   for (void* p : {(void*)H.keys, (void*)H.cnt, (void*)H.vals})
-    if (p) (void)hipFree(p);
+    if (p) dfree(S, p);
   H.keys = (unsigned long long*)fresh[0];
   H.cnt = (int64_t*)fresh[1];
   H.vals = (double*)fresh[2];
@@ -2066,7 +2113,7 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
   HIP_OK(hipStreamSynchronize(st));
   for (auto& N : S.nodes)
     if (N.perm) {
-      (void)hipFree(N.perm);
+      dfree(S, N.perm);
       N.perm = nullptr;
     }
 }
@@ -2234,8 +2281,10 @@ lmfao_status lmfao_plan_workspace_bytes(lmfao_plan_t plan, size_t* bytes) {
 
 static void exact_sizes(Prep& S, hipStream_t st);
 
-lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns, void* stream,
-                           lmfao_prepared_t* out) {
+static const OutBuf& user_out(const lmfao_prepared_s* prep, int q, int* n_keys);
+
+static lmfao_status prepare_impl(lmfao_plan_t plan, const void* const* const* columns, void* workspace,
+                                 size_t ws_bytes, void* stream, lmfao_prepared_t* out) {
   g_last_error.clear();
   if (!plan || !columns || !out) return set_err(LMFAO_EINVAL, "null argument");
   *out = nullptr;
@@ -2243,6 +2292,8 @@ lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns,
   S->P = plan->P;
   S->f64 = plan->P->opts.precision == LMFAO_PREC_F64;
   S->stream = (hipStream_t)stream;
+  S->ws = (char*)workspace;
+  S->ws_cap = workspace ? ws_bytes : 0;
   for (size_t r = 0; r < plan->P->rels.size(); ++r)
     if (!columns[r]) return set_err(LMFAO_EINVAL, "null column list of relation " + plan->P->rels[r].name);
   try {
@@ -2254,7 +2305,50 @@ lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns,
   } catch (const HipError& e) {
     return set_err(LMFAO_EHIP, e.msg);
   }
+  S->ws_prepared = S->ws_used;
   *out = S.release();
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_prepare(lmfao_plan_t plan, const void* const* const* columns, void* stream,
+                           lmfao_prepared_t* out) {
+  return prepare_impl(plan, columns, nullptr, 0, stream, out);
+}
+
+lmfao_status lmfao_prepare_in(lmfao_plan_t plan, const void* const* const* columns, void* workspace,
+                              size_t workspace_bytes, void* stream, lmfao_prepared_t* out) {
+  if (!workspace || (uintptr_t)workspace % 256 != 0)
+    return set_err(LMFAO_EINVAL, "the workspace must be a device address aligned to 256 bytes");
+  return prepare_impl(plan, columns, workspace, workspace_bytes, stream, out);
+}
+
+lmfao_status lmfao_prepared_workspace_bytes(lmfao_prepared_t prep, int32_t with_results, size_t* bytes) {
+  g_last_error.clear();
+  if (!prep || !bytes) return set_err(LMFAO_EINVAL, "null argument");
+  size_t b = prep->ws_prepared;
+  if (with_results) {
+    // what lmfao_result_device carves for every query: its compacted arrays,
+    // the shared scan scratch and the shared hash-sort scratch
+    auto carve = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const Plan& P = *prep->P;
+    int64_t pos_max = 0, rows_max = 0;
+    for (size_t q = 0; q < P.user.size(); ++q) {
+      int nk = 0;
+      const OutBuf& B = user_out(prep, (int)q, &nk);
+      const int64_t n = B.hash >= 0 ? prep->hashes[B.hash].cap : B.n_rows;
+      b += carve((size_t)std::max<int64_t>(n * nk, 1) * 8) + carve((size_t)n * 8) +
+           carve((size_t)std::max<int64_t>(n * B.n_vals, 1) * 8);
+      pos_max = std::max(pos_max, n + scan_tiles(n) + 1);
+      if (B.hash >= 0) rows_max = std::max(rows_max, n);
+    }
+    b += carve((size_t)pos_max * 4);
+    if (rows_max) {
+      const int64_t hist_n = (int64_t)256 * ((rows_max + sort_tile() - 1) / sort_tile() + 1);
+      b += 2 * carve((size_t)rows_max * 8) + 2 * carve((size_t)rows_max * 4) +
+           carve((size_t)(hist_n + scan_tiles(hist_n) + 1) * 4);
+    }
+  }
+  *bytes = b;
   return LMFAO_OK;
 }
 
@@ -2391,6 +2485,7 @@ lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, i
   g_last_error.clear();
   if (!plan || !prep || prep->P != plan->P) return set_err(LMFAO_EINVAL, "plan and prepared handle do not match");
   hipStream_t st = (hipStream_t)stream;
+  prep->run_epoch++;
   try {
     if (!(prep->P->opts.graph && !sync && !prep->timing && run_graph(*prep, st))) enqueue_run(*prep, st);
     if (sync) {
@@ -2436,38 +2531,6 @@ static lmfao_status read_flags(const lmfao_prepared_s* prep) {
   return flag_status(flag);
 }
 
-// dense image of a hashed output: rows with their counts and values, in row order
-struct Gathered {
-  std::vector<int64_t> rows, cnt;
-  std::vector<double> vals;
-};
-static lmfao_status gather_hash(const lmfao_prepared_s* prep, const OutBuf& B, Gathered& g) {
-  const HashBuf& H = prep->hashes[B.hash];
-  std::vector<unsigned long long> keys(H.cap);
-  std::vector<int64_t> cnt(H.cap);
-  std::vector<double> vals((size_t)H.cap * std::max(1, H.n_vals));
-  if (lmfao_status fs = read_flags(prep)) return fs;
-  try {
-    HIP_OK(hipMemcpy(keys.data(), H.keys, H.cap * 8, hipMemcpyDeviceToHost));
-    HIP_OK(hipMemcpy(cnt.data(), H.cnt, H.cap * 8, hipMemcpyDeviceToHost));
-    // a counts-only table's values are its counts (added below)
-    if (!H.counts_only) HIP_OK(hipMemcpy(vals.data(), H.vals, vals.size() * 8, hipMemcpyDeviceToHost));
-  } catch (const HipError& e) {
-    return set_err(LMFAO_EHIP, e.msg);
-  }
-  std::vector<int64_t> order;
-  for (int64_t i = 0; i < H.cap; ++i)
-    if (keys[i] && cnt[i] > 0) order.push_back(i);
-  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return keys[a] < keys[b]; });
-  for (int64_t i : order) {
-    g.rows.push_back((int64_t)keys[i] - 1);
-    g.cnt.push_back(cnt[i]);
-    for (int k = 0; k < H.n_vals; ++k) g.vals.push_back(vals[(size_t)i * H.n_vals + k]);
-    for (int k : H.count_copies) g.vals[g.vals.size() - H.n_vals + k] += (double)cnt[i];
-  }
-  return LMFAO_OK;
-}
-
 // the output buffer and group-by attributes of query q of the caller's batch
 static const OutBuf& user_out(const lmfao_prepared_s* prep, int q, int* n_keys) {
   const Plan& P = *prep->P;
@@ -2481,73 +2544,152 @@ static const OutBuf& user_out(const lmfao_prepared_s* prep, int q, int* n_keys) 
   return prep->qout[U.internal];
 }
 
-lmfao_status lmfao_result_shape(lmfao_prepared_t prep, int32_t q, int64_t* n_groups, int32_t* n_keys,
-                                int32_t* n_aggs) {
-  if (!prep || q < 0 || q >= (int)prep->P->user.size()) return set_err(LMFAO_EINVAL, "bad query index");
+}  // extern "C"
+
+namespace lmfao {
+
+// Compacts caller query q's result of the last run on the device (once per
+// run): present groups, keys per attribute, lexicographic order.  Hash tables
+// are gathered by a scan over their slots and sorted by row (the LSD radix
+// sort of prepare); dense tables keep row order.  Synchronises `st` (the
+// group count sizes the hash sort).
+static lmfao_status compact_result(lmfao_prepared_s* prep, int q, hipStream_t st) {
+  const Plan& P = *prep->P;
+  if (prep->compact.size() != P.user.size()) prep->compact.assign(P.user.size(), Compacted{});
+  Compacted& C = prep->compact[q];
+  if (C.epoch == prep->run_epoch && prep->run_epoch > 0) return LMFAO_OK;
+  if (lmfao_status fs = read_flags(prep)) return fs;
+  const QueryDef& Q = P.queries[P.user[q].internal];
   int nk = 0;
   const OutBuf& B = user_out(prep, q, &nk);
-  int64_t g = 0;
-  if (B.hash >= 0) {
-    Gathered gh;
-    lmfao_status st = gather_hash(prep, B, gh);
-    if (st) return st;
-    g = (int64_t)gh.rows.size();
-  } else {
-    if (lmfao_status fs = read_flags(prep)) return fs;
-    std::vector<int64_t> cnt(B.n_rows);
-    try {
-      HIP_OK(hipMemcpy(cnt.data(), B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
-    } catch (const HipError& e) {
-      return set_err(LMFAO_EHIP, e.msg);
+  if (nk > 4) return set_err(LMFAO_EUNSUPPORTED, "more than 4 group-by attributes");
+  try {
+    Prep& S = *prep;
+    DCompact d{};
+    d.n_vals = B.n_vals;
+    d.n_keys = nk;
+    std::vector<int64_t> dom(nk);
+    for (int i = 0; i < nk; ++i) dom[i] = P.attrs[Q.groupby[i]].domain;
+    int64_t m = 1;
+    for (int i = nk - 1; i >= 0; --i) {
+      d.stride[i] = m;
+      d.dom[i] = dom[i];
+      m = m * std::max<int64_t>(dom[i], 1);
     }
-    for (int64_t c : cnt) g += c > 0;
+    const HashBuf* H = B.hash >= 0 ? &S.hashes[B.hash] : nullptr;
+    d.cnt = H ? H->cnt : B.cnt;
+    d.vals = H ? (H->counts_only ? nullptr : H->vals) : (B.n_vals ? (const double*)B.vals : nullptr);
+    d.hkeys = H ? H->keys : nullptr;
+    d.n_src = H ? H->cap : B.n_rows;
+    if (H)
+      for (int k : H->count_copies) d.copy_mask |= 1ull << k;
+    // scratch shared by all queries, sized once for the largest (a regrown
+    // hash table may need more later)
+    int64_t pos_max = 0, rows_max = 0;
+    for (size_t u = 0; u < P.user.size(); ++u) {
+      int uk = 0;
+      const OutBuf& UB = user_out(prep, (int)u, &uk);
+      const int64_t un = UB.hash >= 0 ? S.hashes[UB.hash].cap : UB.n_rows;
+      pos_max = std::max(pos_max, un + scan_tiles(un) + 1);
+      if (UB.hash >= 0) rows_max = std::max(rows_max, un);
+    }
+    if (S.cpos_n < pos_max) {
+      S.cpos = (uint32_t*)dalloc(S, (size_t)pos_max * 4);
+      S.cpos_n = pos_max;
+    }
+    d.pos = S.cpos;
+    const int64_t bound = d.n_src;   // groups at most
+    if (H && S.crows_n < rows_max) {
+      S.crows = (uint64_t*)dalloc(S, (size_t)rows_max * 8);
+      S.crows2 = (uint64_t*)dalloc(S, (size_t)rows_max * 8);
+      S.cslot = (uint32_t*)dalloc(S, (size_t)rows_max * 4);
+      S.cslot2 = (uint32_t*)dalloc(S, (size_t)rows_max * 4);
+      const int64_t hist_n = (int64_t)256 * ((rows_max + sort_tile() - 1) / sort_tile() + 1);
+      S.chist = (uint32_t*)dalloc(S, (size_t)(hist_n + scan_tiles(hist_n) + 1) * 4);
+      S.crows_n = rows_max;
+    }
+    d.rows = S.crows;
+    d.slot = S.cslot;
+    // the compacted arrays hold every group a dense table could have, or
+    // every slot of the hash table (its size changes only by regrowth)
+    if (C.cap < bound) {
+      C.keys = (int64_t*)dalloc(S, (size_t)std::max<int64_t>(bound * nk, 1) * 8);
+      C.cnt = (int64_t*)dalloc(S, (size_t)bound * 8);
+      C.vals = (double*)dalloc(S, (size_t)std::max<int64_t>(bound * B.n_vals, 1) * 8);
+      C.cap = bound;
+    }
+    d.keys_out = C.keys;
+    d.cnt_out = C.cnt;
+    d.vals_out = C.vals;
+    launch_compact(d, st);
+    HIP_OK(hipGetLastError());
+    uint32_t n = 0;
+    HIP_OK(hipMemcpyAsync(&n, d.pos + d.n_src + scan_tiles(d.n_src), 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (H && n > 0) {
+      int bits = 1;
+      while (bits < 63 && ((B.n_rows - 1) >> bits) != 0) ++bits;
+      bool swapped = false;
+      launch_sort(d.rows, d.slot, S.crows2, S.cslot2, n, bits, S.chist, st, &swapped);
+      if (swapped) {
+        d.rows = S.crows2;
+        d.slot = S.cslot2;
+      }
+      launch_compact_emit(d, n, st);
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipStreamSynchronize(st));
+    }
+    C.n_groups = n;
+    C.epoch = prep->run_epoch;
+  } catch (const PlanError& e) {
+    return set_err(e.status, e.msg);
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
   }
-  if (n_groups) *n_groups = g;
-  if (n_keys) *n_keys = nk;
-  if (n_aggs) *n_aggs = B.n_vals;
+  return LMFAO_OK;
+}
+
+}  // namespace lmfao
+
+extern "C" {
+
+lmfao_status lmfao_result_device(lmfao_prepared_t prep, int32_t q, lmfao_output* out, void* stream) {
+  g_last_error.clear();
+  if (!prep || !out || q < 0 || q >= (int)prep->P->user.size()) return set_err(LMFAO_EINVAL, "bad query index");
+  if (lmfao_status e = compact_result(prep, q, (hipStream_t)stream)) return e;
+  const Compacted& C = prep->compact[q];
+  int nk = 0;
+  const OutBuf& B = user_out(prep, q, &nk);
+  out->n_groups = C.n_groups;
+  out->n_keys = nk;
+  out->n_aggs = B.n_vals;
+  out->keys = C.keys;
+  out->counts = C.cnt;
+  out->values = C.vals;
+  return LMFAO_OK;
+}
+
+lmfao_status lmfao_result_shape(lmfao_prepared_t prep, int32_t q, int64_t* n_groups, int32_t* n_keys,
+                                int32_t* n_aggs) {
+  lmfao_output o{};
+  if (lmfao_status e = lmfao_result_device(prep, q, &o, nullptr)) return e;
+  if (n_groups) *n_groups = o.n_groups;
+  if (n_keys) *n_keys = o.n_keys;
+  if (n_aggs) *n_aggs = o.n_aggs;
   return LMFAO_OK;
 }
 
 lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, int64_t* counts, double* values) {
-  if (!prep || q < 0 || q >= (int)prep->P->user.size()) return set_err(LMFAO_EINVAL, "bad query index");
-  const Plan& P = *prep->P;
-  const QueryDef& Q = P.queries[P.user[q].internal];
-  int nk = 0;
-  const OutBuf& B = user_out(prep, q, &nk);
-  std::vector<int64_t> dom(nk);
-  for (int i = 0; i < nk; ++i) dom[i] = P.attrs[Q.groupby[i]].domain;
-  auto emit = [&](int64_t g, int64_t row, int64_t c, const double* v) {
-    if (keys) {
-      int64_t x = row;
-      for (int i = nk - 1; i >= 0; --i) {
-        keys[g * nk + i] = x % dom[i];
-        x /= dom[i];
-      }
-    }
-    if (counts) counts[g] = c;
-    if (values)
-      for (int k = 0; k < B.n_vals; ++k) values[g * B.n_vals + k] = v[k];
-  };
-  if (B.hash >= 0) {
-    Gathered gh;
-    lmfao_status st = gather_hash(prep, B, gh);
-    if (st) return st;
-    for (size_t i = 0; i < gh.rows.size(); ++i) emit((int64_t)i, gh.rows[i], gh.cnt[i], gh.vals.data() + i * B.n_vals);
-    return LMFAO_OK;
-  }
-  if (lmfao_status fs = read_flags(prep)) return fs;
-  std::vector<int64_t> cnt(B.n_rows);
-  std::vector<double> vals((size_t)B.n_rows * B.n_vals);
+  lmfao_output o{};
+  if (lmfao_status e = lmfao_result_device(prep, q, &o, nullptr)) return e;
   try {
-    HIP_OK(hipMemcpy(cnt.data(), B.cnt, B.n_rows * 8, hipMemcpyDeviceToHost));
-    if (!vals.empty()) HIP_OK(hipMemcpy(vals.data(), B.vals, vals.size() * 8, hipMemcpyDeviceToHost));
+    if (keys && o.n_groups * o.n_keys)
+      HIP_OK(hipMemcpy(keys, o.keys, (size_t)o.n_groups * o.n_keys * 8, hipMemcpyDeviceToHost));
+    if (counts && o.n_groups) HIP_OK(hipMemcpy(counts, o.counts, (size_t)o.n_groups * 8, hipMemcpyDeviceToHost));
+    if (values && o.n_groups * o.n_aggs)
+      HIP_OK(hipMemcpy(values, o.values, (size_t)o.n_groups * o.n_aggs * 8, hipMemcpyDeviceToHost));
   } catch (const HipError& e) {
     return set_err(LMFAO_EHIP, e.msg);
-  }
-  int64_t g = 0;
-  for (int64_t row = 0; row < B.n_rows; ++row) {
-    if (cnt[row] <= 0) continue;
-    emit(g++, row, cnt[row], vals.data() + (size_t)row * B.n_vals);
   }
   return LMFAO_OK;
 }

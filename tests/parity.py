@@ -7,9 +7,9 @@ Integers (group keys, counts) must be identical.  A float cell passes when
 where ``sum |terms|`` is the oracle's sum of absolute product terms for that
 cell.  The floor makes the test meaningful for cells whose exact value is a
 near-cancelling sum of N(0,1) terms (plain relative error is ill-conditioned
-there).  A form whose products carry a fixed relative error (the BF16x3
-contraction, about 2^-16) is held to ``floor=1``: its error bound is relative
-to the sum of the terms' magnitudes.
+there).  A form whose products carry a fixed relative error (the BF16x2
+contraction, about 2^-16 per product) is held to ``floor=1``: its error bound
+is relative to the sum of the terms' magnitudes.
 """
 import numpy as np
 
