@@ -237,9 +237,21 @@ def measure(E, W, config, args, full=True):
     n_aggs = sum(len(q["aggs"]) for q in problem["batch"])
     t_gen = time.perf_counter() - t_gen
     opts = W.bench_plan_options(bw, graph=not args.no_graph)
-    opts.update(scan_blocks=args.scan_blocks, contract_splits=args.contract_splits, one_hot_max=args.one_hot_max)
-    plan = E.Plan(problem, **opts)
     cols = E.device_columns(problem)
+    tuning = None
+    if args.scan_blocks or args.contract_splits or args.one_hot_max or args.no_tune:
+        opts.update(scan_blocks=args.scan_blocks, contract_splits=args.contract_splits,
+                    one_hot_max=args.one_hot_max)
+    else:
+        # launch shapes from the autotuner (its JSON cache; a miss is tuned now)
+        _log(f"{config}: launch shapes (autotuner, cache {os.path.relpath(args.tune_cache, ROOT)})")
+        t0 = time.perf_counter()
+        tuned = E.tune(problem, cols, cache_path=args.tune_cache, runs=5, **opts)
+        opts = tuned["options"]
+        tuning = {"scan_blocks": opts["scan_blocks"], "contract_splits": opts["contract_splits"],
+                  "one_hot_max": opts["one_hot_max"], "tuned_ms": round(tuned["tuned_ms"], 4),
+                  "base_ms": round(tuned["base_ms"], 4), "seconds": round(time.perf_counter() - t0, 1)}
+    plan = E.Plan(problem, **opts)
     torch.cuda.synchronize()
     _log(f"{config}: prepare")
     t_prep = time.perf_counter()
@@ -282,7 +294,9 @@ def measure(E, W, config, args, full=True):
         "kernels_ms": {k: round(v, 4) for k, v in timing},
         "hash_tables": {"tables": len(desc.get("hash_tables", [])),
                         "slots": sum(h["slots"] for h in desc.get("hash_tables", [])),
-                        "regrowths": desc.get("hash_regrowths", 0)},
+                        "regrowths": desc.get("hash_regrowths", 0),
+                        "picked_by_estimator": desc.get("picked_hash", 0)},
+        "tuning": tuning,
     }
     if not args.no_check and args.scale == 1.0:
         t0 = time.perf_counter()
@@ -368,6 +382,8 @@ def main():
                     help="steps of the plain per-view form timed on the same input (0 = skip)")
     ap.add_argument("--sizing-steps", type=int, default=5,
                     help="steps timed per hash-table sizing in the sizing comparison (0 = skip)")
+    ap.add_argument("--no-tune", action="store_true", help="the library's default launch shapes (no autotuner)")
+    ap.add_argument("--tune-cache", default=None, help="JSON cache of the autotuner (default: the package's)")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the fact table (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the comparison with the golden results")
@@ -396,6 +412,8 @@ def main():
         return
 
     E.load_library()
+    if args.tune_cache is None:
+        args.tune_cache = E.TUNED_SHAPES
     head = measure(E, W, args.config, args, full=True)
     subs = {}
     for c in [x for x in args.sub.split(",") if x and x != args.config]:

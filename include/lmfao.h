@@ -314,6 +314,23 @@ lmfao_status lmfao_prepare_in(lmfao_plan_t plan, const void* const* const* colum
                               size_t workspace_bytes, void* stream, lmfao_prepared_t* out);
 lmfao_status lmfao_prepared_workspace_bytes(lmfao_prepared_t prep, int32_t with_results, size_t* bytes);
 
+/* Autotuner of the physical plan's launch shapes.  Tunes, for the batch
+ * over these relations on this device, the options that shape launches --
+ * scan_blocks (workgroups per scan launch), contract_splits (ranges per
+ * column of contraction tiles) and one_hot_max (one-hot or scattered outer
+ * codes) -- by coordinate descent from `opts`: each variant is planned,
+ * prepared and timed over `runs` runs (HIP events on `stream`, graph replay
+ * when opts->graph), and the fastest kept.  Results are cached in the JSON
+ * file `cache_path` (created or updated; NULL: no cache) under a 64-bit
+ * FNV-1a hash of the plan description with the base options, the relation
+ * sizes and the device architecture: a cached entry is returned without any
+ * timing.  On return `opts` holds the tuned values and *best_ms and
+ * *base_ms (HOST, may be NULL) the step time of the tuned and the base
+ * options (from the cache when cached).  `columns` as for lmfao_prepare. */
+lmfao_status lmfao_tune(const lmfao_schema* schema, const lmfao_join_tree* tree, const lmfao_batch* batch,
+                        lmfao_options* opts, const void* const* const* columns, const char* cache_path,
+                        int32_t runs, double* best_ms, double* base_ms, void* stream);
+
 /* Evaluates the whole batch: every view and query of the plan, level by
  * level, on `stream`.  Enqueue only: returns once the work is queued unless
  * `sync` is nonzero (then it synchronizes and checks key-uniqueness and

@@ -167,6 +167,10 @@ def load_library(path: str = LIB_PATH):
     lib.lmfao_prepared_free.restype = None
     lib.lmfao_last_error.argtypes = []
     lib.lmfao_last_error.restype = C.c_char_p
+    lib.lmfao_tune.argtypes = [C.POINTER(lmfao_schema), C.POINTER(lmfao_join_tree), C.POINTER(lmfao_batch),
+                               C.POINTER(lmfao_options), C.POINTER(C.POINTER(vp)), C.c_char_p, C.c_int32,
+                               C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
+    lib.lmfao_tune.restype = C.c_int32
     lib.lmfao_prepare_in.argtypes = [vp, C.POINTER(C.POINTER(vp)), vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.lmfao_prepare_in.restype = C.c_int32
     lib.lmfao_prepared_workspace_bytes.argtypes = [vp, C.c_int32, C.POINTER(C.c_size_t)]
@@ -246,59 +250,95 @@ def marshal_problem(problem, keep: _Keep):
     return schema, tree, batch
 
 
+def build_options(problem, keep, precision="f64", policy=None, form="fused", order=None,
+                  min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0,
+                  sizing="bound", estimator=None, graph=False, one_hot_max=0, scan_blocks=0,
+                  contract_splits=0, partition=True, row_weights=()):
+    """Keyword options -> ``lmfao_options`` (buffers it points to kept in ``keep``)."""
+    lib = load_library()
+    opts = lmfao_options()
+    lib.lmfao_default_options(C.byref(opts))
+    if precision not in ("f64", "f32", "bf16x3", "bf16x2"):
+        raise ValueError(f"precision must be 'f64', 'f32', 'bf16x3' or 'bf16x2', not {precision!r}")
+    opts.precision = {"f64": PREC_F64, "f32": PREC_F32, "bf16x3": PREC_BF16X3,
+                      "bf16x2": PREC_BF16X2}[precision]
+    opts.form = FORM_FUSED if form == "fused" else FORM_PER_VIEW
+    pol = policy if policy is not None else problem.get("policy", "groupby")
+    opts.root_policy = ROOT_FACT if pol == "fact" else ROOT_GROUPBY
+    opts.min_segment = int(min_segment)
+    opts.row_piece_max = int(row_piece_max)
+    if contraction not in ("mfma", "valu"):
+        raise ValueError(f"contraction must be 'mfma' or 'valu', not {contraction!r}")
+    opts.contraction = 0 if contraction == "mfma" else 1
+    opts.codegen = 0 if codegen else 1
+    opts.hash_slots = int(hash_slots)
+    opts.graph = 1 if graph else 0
+    opts.one_hot_max = int(one_hot_max)
+    opts.scan_blocks = int(scan_blocks)
+    opts.contract_splits = int(contract_splits)
+    opts.partition = 0 if partition else 1
+    rel_names = [r["name"] for r in problem["schema"]]
+    opts.row_weights = sum(1 << rel_names.index(r) for r in row_weights)
+    if sizing not in ("bound", "learned", "exact"):
+        raise ValueError(f"sizing must be 'bound', 'learned' or 'exact', not {sizing!r}")
+    opts.sizing = {"bound": 0, "learned": 1, "exact": 2}[sizing]
+    if sizing == "learned" and estimator is None:
+        from . import estimator as _est
+        estimator = _est.load()
+    if estimator is not None:
+        import numpy as np
+        blob = np.ascontiguousarray(estimator, dtype=np.float32)
+        keep.refs.append(blob)
+        opts.estimator = blob.ctypes.data_as(C.POINTER(C.c_float))
+        opts.estimator_len = int(blob.size)
+    if order:
+        names = [r["name"] for r in problem["schema"]]
+        n_order = [len(order.get(n, [])) for n in names]
+        lists = [keep.arr(C.c_char_p, [keep.s(a) for a in order.get(n, [])]) for n in names]
+        opts.n_order = keep.arr(C.c_int32, n_order)
+        ptrs = keep.arr(C.POINTER(C.c_char_p), [C.cast(l, C.POINTER(C.c_char_p)) for l in lists])
+        opts.order = C.cast(ptrs, C.POINTER(C.POINTER(C.c_char_p)))
+    keep.refs.append(opts)
+    return opts
+
+
+def _column_table(problem, columns, keep):
+    per_rel = []
+    for r in problem["schema"]:
+        ptrs = [C.c_void_p(int(columns[r["name"]][a["name"]].data_ptr())) for a in r["attrs"]]
+        per_rel.append(C.cast(keep.arr(C.c_void_p, ptrs), C.POINTER(C.c_void_p)))
+    return keep.arr(C.POINTER(C.c_void_p), per_rel)
+
+
+def tune(problem, columns, cache_path=None, runs=5, stream=None, **plan_kw) -> dict:
+    """Launch shapes tuned for this batch, relations and device
+    (``lmfao_tune``): the plan keyword options with scan_blocks,
+    contract_splits and one_hot_max replaced, plus the step times of the
+    tuned and base options ("tuned_ms", "base_ms")."""
+    lib = load_library()
+    keep = _Keep()
+    schema, tree, batch = marshal_problem(problem, keep)
+    opts = build_options(problem, keep, **plan_kw)
+    cols = _column_table(problem, columns, keep)
+    best, base = C.c_double(), C.c_double()
+    path = keep.s(cache_path) if cache_path else None
+    _check(lib, lib.lmfao_tune(C.byref(schema), C.byref(tree), C.byref(batch), C.byref(opts), cols, path,
+                               int(runs), C.byref(best), C.byref(base), C.c_void_p(stream) if stream else None))
+    out = dict(plan_kw, scan_blocks=opts.scan_blocks, contract_splits=opts.contract_splits,
+               one_hot_max=opts.one_hot_max)
+    return {"options": out, "tuned_ms": best.value, "base_ms": base.value}
+
+
 class Plan:
     """A plan handle (``lmfao_plan``)."""
 
-    def __init__(self, problem, precision="f64", policy=None, form="fused", order=None,
-                 min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0,
-                 sizing="bound", estimator=None, graph=False, one_hot_max=0, scan_blocks=0,
-                 contract_splits=0, partition=True, row_weights=()):
+    def __init__(self, problem, **kw):
         self.lib = load_library()
         self.problem = problem
         keep = _Keep()
         schema, tree, batch = marshal_problem(problem, keep)
-        opts = lmfao_options()
-        self.lib.lmfao_default_options(C.byref(opts))
-        if precision not in ("f64", "f32", "bf16x3", "bf16x2"):
-            raise ValueError(f"precision must be 'f64', 'f32', 'bf16x3' or 'bf16x2', not {precision!r}")
-        opts.precision = {"f64": PREC_F64, "f32": PREC_F32, "bf16x3": PREC_BF16X3,
-                          "bf16x2": PREC_BF16X2}[precision]
-        opts.form = FORM_FUSED if form == "fused" else FORM_PER_VIEW
-        pol = policy if policy is not None else problem.get("policy", "groupby")
-        opts.root_policy = ROOT_FACT if pol == "fact" else ROOT_GROUPBY
-        opts.min_segment = int(min_segment)
-        opts.row_piece_max = int(row_piece_max)
-        if contraction not in ("mfma", "valu"):
-            raise ValueError(f"contraction must be 'mfma' or 'valu', not {contraction!r}")
-        opts.contraction = 0 if contraction == "mfma" else 1
-        opts.codegen = 0 if codegen else 1
-        opts.hash_slots = int(hash_slots)
-        opts.graph = 1 if graph else 0
-        opts.one_hot_max = int(one_hot_max)
-        opts.scan_blocks = int(scan_blocks)
-        opts.contract_splits = int(contract_splits)
-        opts.partition = 0 if partition else 1
-        rel_names = [r["name"] for r in problem["schema"]]
-        opts.row_weights = sum(1 << rel_names.index(r) for r in row_weights)
-        if sizing not in ("bound", "learned", "exact"):
-            raise ValueError(f"sizing must be 'bound', 'learned' or 'exact', not {sizing!r}")
-        opts.sizing = {"bound": 0, "learned": 1, "exact": 2}[sizing]
-        if sizing == "learned" and estimator is None:
-            from . import estimator as _est
-            estimator = _est.load()
-        if estimator is not None:
-            import numpy as np
-            blob = np.ascontiguousarray(estimator, dtype=np.float32)
-            keep.refs.append(blob)
-            opts.estimator = blob.ctypes.data_as(C.POINTER(C.c_float))
-            opts.estimator_len = int(blob.size)
-        if order:
-            names = [r["name"] for r in problem["schema"]]
-            n_order = [len(order.get(n, [])) for n in names]
-            lists = [keep.arr(C.c_char_p, [keep.s(a) for a in order.get(n, [])]) for n in names]
-            opts.n_order = keep.arr(C.c_int32, n_order)
-            ptrs = keep.arr(C.POINTER(C.c_char_p), [C.cast(l, C.POINTER(C.c_char_p)) for l in lists])
-            opts.order = C.cast(ptrs, C.POINTER(C.POINTER(C.c_char_p)))
+        opts = build_options(problem, keep, **kw)
+        precision = kw.get("precision", "f64")
         h = C.c_void_p()
         _check(self.lib, self.lib.lmfao_plan(C.byref(schema), C.byref(tree), C.byref(batch),
                                              C.byref(opts), C.byref(h)))
@@ -335,11 +375,7 @@ class Prepared:
         self.plan = plan
         self.lib = plan.lib
         keep = _Keep()
-        per_rel = []
-        for r in plan.problem["schema"]:
-            ptrs = [C.c_void_p(int(columns[r["name"]][a["name"]].data_ptr())) for a in r["attrs"]]
-            per_rel.append(C.cast(keep.arr(C.c_void_p, ptrs), C.POINTER(C.c_void_p)))
-        cols = keep.arr(C.POINTER(C.c_void_p), per_rel)
+        cols = _column_table(plan.problem, columns, keep)
         self.stream = C.c_void_p(stream) if stream else C.c_void_p()
         h = C.c_void_p()
         if workspace is None:
@@ -473,11 +509,7 @@ class Prepared:
         ``columns`` are the device tensors given to the constructor (they
         must still be alive).  Returns the nodes as dicts."""
         keep = _Keep()
-        per_rel = []
-        for r in self.plan.problem["schema"]:
-            ptrs = [C.c_void_p(int(columns[r["name"]][a["name"]].data_ptr())) for a in r["attrs"]]
-            per_rel.append(C.cast(keep.arr(C.c_void_p, ptrs), C.POINTER(C.c_void_p)))
-        cols = keep.arr(C.POINTER(C.c_void_p), per_rel)
+        cols = _column_table(self.plan.problem, columns, keep)
         sp = self._cart_spec(keep, spec)
         cap = (1 << (int(spec.get("max_depth", 0)) + 1)) - 1
         nodes = (lmfao_cart_node * cap)()

@@ -43,6 +43,8 @@ constexpr int64_t kLdsTableMax = 12288;          // int32 count entries privatiz
 constexpr int64_t kPartMinCells = 1;             // smallest SUM(1) table moved from a scan to the partition count
 constexpr int kTriangle = (kMaxAtoms + 1) * (kMaxAtoms + 2) / 2;  // incl. (1,1)
 constexpr int64_t kDenseRowsMax = (int64_t)1 << 24;  // larger key spaces go to hash tables
+constexpr int64_t kPickMinCells = (int64_t)1 << 15;  // smaller tables stay dense (one LDS slice)
+constexpr double kDenseDensityMin = 8.0;             // learned sizing hashes tables predicted sparser than 1/8
 
 // ---------------------------------------------------------------------------
 // logical plan

@@ -154,6 +154,7 @@ struct lmfao_prepared_s {
   size_t ws_used = 0;                                // bytes carved (workspace or hipMalloc)
   size_t ws_prepared = 0;                            // ... when lmfao_prepare returned
   int64_t run_epoch = 0;                             // runs enqueued
+  int picked_hash = 0;                               // dense key spaces the estimator sent to hash tables
   std::vector<lmfao::Compacted> compact;             // device results per caller query
   uint32_t* cpos = nullptr;                          // compaction scratch: flags and positions
   int64_t cpos_n = 0;
@@ -1973,7 +1974,32 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
     }
     B.f64 = true;
     B.n_vals = (int)Q.aggs.size();
-    if (dense > (double)kDenseRowsMax) {
+    const bool learned = P.opts.sizing == LMFAO_SIZING_LEARNED && !P.estimator.empty();
+    double est = -1.0;
+    auto estimate = [&]() {
+      if (est < 0) {
+        float f[LMFAO_EST_FEATURES];
+        query_features(S, Q, f, st);
+        const double y = estimate_log2_groups(P.estimator, f) + (double)P.estimator[3];
+        est = std::max(0.0, std::exp2(std::min(y, 62.0)) - 1.0);
+      }
+      return est;
+    };
+    bool hashed = dense > (double)kDenseRowsMax;
+    // Learned sizing also picks dense or hash for the tables the partition
+    // count keeps (it counts either kind per output): a table past one LDS
+    // slice whose predicted group count is below 1/kDenseDensityMin of its
+    // key range is hashed (the regrowth fallback keeps results exact
+    // whatever the prediction).  Tables with range queries stay dense.
+    if (!hashed && learned && dense > (double)kPickMinCells && Q.group >= 0 && P.groups[Q.group].partitioned) {
+      bool ranged = false;
+      for (const UserQuery& U : P.user) ranged |= U.internal == (int)q && U.range;
+      if (!ranged && estimate() * kDenseDensityMin < dense) {
+        hashed = true;
+        S.picked_hash++;
+      }
+    }
+    if (hashed) {
       // hash table: at most one group per tuple of the root relation
       HashBuf H;
       H.query = (int)q;
@@ -1987,11 +2013,8 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
         want = P.opts.hash_slots;
       } else if (P.opts.sizing == LMFAO_SIZING_EXACT) {
         want = top;   // the exact-count run at the end of prepare resizes it
-      } else if (P.opts.sizing == LMFAO_SIZING_LEARNED && !P.estimator.empty()) {
-        float f[LMFAO_EST_FEATURES];
-        query_features(S, Q, f, st);
-        const double y = estimate_log2_groups(P.estimator, f) + (double)P.estimator[3];
-        H.est = std::max(0.0, std::exp2(std::min(y, 62.0)) - 1.0);
+      } else if (learned) {
+        H.est = estimate();
         want = (int64_t)std::min<double>((double)top, std::max(1024.0, 2.0 * H.est));
       }
       H.cap = 1;
@@ -2697,6 +2720,165 @@ lmfao_status lmfao_result_copy(lmfao_prepared_t prep, int32_t q, int64_t* keys, 
 // ---------------------------------------------------------------------------
 // ridge regression over the batch's results (section 3, linear regression)
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// autotuner of launch shapes (JSON cache keyed by plan hash)
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace lmfao {
+
+static uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull) {
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+struct TuneEntry {
+  int scan_blocks = 0, contract_splits = 0, one_hot_max = 0;
+  double ms = 0, base_ms = 0;
+};
+
+// the cache: {"entries": {"<key>": {"scan_blocks": n, ...}, ...}}, one entry
+// per line as this writer emits it
+static std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
+  std::map<std::string, TuneEntry> m;
+  if (!path) return m;
+  FILE* f = fopen(path, "r");
+  if (!f) return m;
+  char line[1024];
+  while (fgets(line, sizeof line, f)) {
+    char key[64];
+    TuneEntry e;
+    if (sscanf(line, " \"%63[0-9a-f]\": {\"scan_blocks\": %d, \"contract_splits\": %d, \"one_hot_max\": %d, "
+                     "\"ms\": %lf, \"base_ms\": %lf",
+               key, &e.scan_blocks, &e.contract_splits, &e.one_hot_max, &e.ms, &e.base_ms) == 6)
+      m[key] = e;
+  }
+  fclose(f);
+  return m;
+}
+
+static void write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) throw PlanError{LMFAO_EINVAL, std::string("cannot write ") + path};
+  fprintf(f, "{\"entries\": {\n");
+  size_t i = 0;
+  for (auto& kv : m) {
+    const TuneEntry& e = kv.second;
+    fprintf(f, "  \"%s\": {\"scan_blocks\": %d, \"contract_splits\": %d, \"one_hot_max\": %d, \"ms\": %.6f, "
+               "\"base_ms\": %.6f}%s\n",
+            kv.first.c_str(), e.scan_blocks, e.contract_splits, e.one_hot_max, e.ms, e.base_ms,
+            ++i < m.size() ? "," : "");
+  }
+  fprintf(f, "}}\n");
+  fclose(f);
+  if (rename(tmp.c_str(), path) != 0) throw PlanError{LMFAO_EINVAL, std::string("cannot replace ") + path};
+}
+
+}  // namespace lmfao
+
+extern "C" {
+
+lmfao_status lmfao_tune(const lmfao_schema* schema, const lmfao_join_tree* tree, const lmfao_batch* batch,
+                        lmfao_options* opts, const void* const* const* columns, const char* cache_path,
+                        int32_t runs, double* best_ms, double* base_ms, void* stream) {
+  g_last_error.clear();
+  if (!schema || !tree || !batch || !opts || !columns) return set_err(LMFAO_EINVAL, "null argument");
+  if (runs <= 0) runs = 5;
+  hipStream_t st = (hipStream_t)stream;
+  // the key: the plan with the base options, the relation sizes, the device
+  lmfao_plan_t base = nullptr;
+  if (lmfao_status e = lmfao_plan(schema, tree, batch, opts, &base)) return e;
+  std::string ident = base->P->json;
+  lmfao_plan_free(base);
+  for (int r = 0; r < schema->n_relations; ++r) ident += "|" + std::to_string(schema->relations[r].n_rows);
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) ident += prop.gcnArchName;
+  char key[32];
+  snprintf(key, sizeof key, "%016llx", (unsigned long long)fnv1a(ident));
+  try {
+    std::map<std::string, TuneEntry> cache = read_tune_cache(cache_path);
+    auto hit = cache.find(key);
+    if (hit != cache.end()) {
+      opts->scan_blocks = hit->second.scan_blocks;
+      opts->contract_splits = hit->second.contract_splits;
+      opts->one_hot_max = hit->second.one_hot_max;
+      if (best_ms) *best_ms = hit->second.ms;
+      if (base_ms) *base_ms = hit->second.base_ms;
+      return LMFAO_OK;
+    }
+    // one variant: plan, prepare, a checked run, then `runs` timed runs
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    auto measure = [&](const lmfao_options& o, double* ms) -> lmfao_status {
+      lmfao_plan_t pl = nullptr;
+      lmfao_prepared_t pr = nullptr;
+      lmfao_status e = lmfao_plan(schema, tree, batch, &o, &pl);
+      if (!e) e = lmfao_prepare(pl, columns, stream, &pr);
+      if (!e) e = lmfao_run(pl, pr, stream, 1);
+      if (!e) e = lmfao_run(pl, pr, stream, 0);   // captures the graph when asked
+      if (!e) {
+        (void)hipEventRecord(e0, st);
+        for (int i = 0; i < runs && !e; ++i) e = lmfao_run(pl, pr, stream, 0);
+        (void)hipEventRecord(e1, st);
+        float t = 0;
+        if (!e && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+          *ms = (double)t / runs;
+        else if (!e)
+          e = set_err(LMFAO_EHIP, "timing events failed");
+      }
+      if (pr) lmfao_prepared_free(pr);
+      if (pl) lmfao_plan_free(pl);
+      return e;
+    };
+    lmfao_options best = *opts;
+    double best_t = 0;
+    lmfao_status e = measure(best, &best_t);
+    const double base_t = best_t;
+    // coordinate descent over the three shapes (0 = the library's default)
+    static const int kScan[] = {0, 512, 1024, 4096};
+    static const int kSplit[] = {0, 256, 512, 2048, 4096};
+    static const int kOneHot[] = {0, 16, 64};
+    for (int param = 0; param < 3 && !e; ++param) {
+      const int* vals = param == 0 ? kScan : param == 1 ? kSplit : kOneHot;
+      const int nv = param == 0 ? 4 : param == 1 ? 5 : 3;
+      const int cur = param == 0 ? best.scan_blocks : param == 1 ? best.contract_splits : best.one_hot_max;
+      for (int i = 0; i < nv && !e; ++i) {
+        if (vals[i] == cur) continue;
+        lmfao_options o = best;
+        (param == 0 ? o.scan_blocks : param == 1 ? o.contract_splits : o.one_hot_max) = vals[i];
+        double t = 0;
+        e = measure(o, &t);
+        if (!e && t < best_t) {
+          best = o;
+          best_t = t;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e) return e;
+    opts->scan_blocks = best.scan_blocks;
+    opts->contract_splits = best.contract_splits;
+    opts->one_hot_max = best.one_hot_max;
+    if (best_ms) *best_ms = best_t;
+    if (base_ms) *base_ms = base_t;
+    cache[key] = TuneEntry{best.scan_blocks, best.contract_splits, best.one_hot_max, best_t, base_t};
+    write_tune_cache(cache_path, cache);
+  } catch (const PlanError& e) {
+    return set_err(e.status, e.msg);
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
 lmfao_status lmfao_row_weights(lmfao_prepared_t prep, int32_t rel, int32_t** weights) {
   g_last_error.clear();
   if (!prep || !weights) return set_err(LMFAO_EINVAL, "null argument");
@@ -3163,7 +3345,8 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
   int64_t fill_bytes = 0;
   for (auto& s : prep->steps)
     if (s.kind == 0) fill_bytes += s.bytes;
-  j += "],\"fill_bytes\":" + std::to_string(fill_bytes) + ",\"codegen_failures\":[";
+  j += "],\"fill_bytes\":" + std::to_string(fill_bytes) + ",\"picked_hash\":" + std::to_string(prep->picked_hash) +
+       ",\"codegen_failures\":[";
   for (size_t i = 0; i < prep->gen_failures.size(); ++i) {
     if (i) j += ",";
     std::string m;

@@ -153,10 +153,41 @@ def test_learned_sizing_gain_on_held_out_chain(seed, zipf):
     ref, dref = _run(p)
     got, dgot = _run(p, sizing="learned")
     _same(ref, got)
+    # tables hashed under both sizings (key spaces past 2^24 cells): no more
+    # slots; tables the estimator moved from dense to hash (predicted density
+    # below 1/8): really sparse (fewer groups than half their cells)
+    both = {t["query"] for t in dref["hash_tables"]}
     s_bound = sum(t["slots"] for t in dref["hash_tables"])
-    s_learned = sum(t["slots"] for t in dgot["hash_tables"])
+    s_learned = sum(t["slots"] for t in dgot["hash_tables"] if t["query"] in both)
     groups = {t["query"]: len(ref[t["query"]]["keys"]) for t in dref["hash_tables"]}
     print(f"[gain] slots bound {s_bound} learned {s_learned} regrowths {dgot['hash_regrowths']} "
-          f"groups {sorted(groups.values())} est {[round(t['est_groups']) for t in dgot['hash_tables']]}",
-          flush=True)
+          f"groups {sorted(groups.values())} est {[round(t['est_groups']) for t in dgot['hash_tables']]} "
+          f"picked {dgot['picked_hash']}", flush=True)
     assert s_learned <= s_bound
+    plan_q = {t["query"] for t in dgot["hash_tables"]} - both
+    desc = lm.Plan(p, precision="f32", policy="fact").describe()
+    for qi in plan_q:
+        user = [u for u, x in enumerate(desc["user_queries"]) if x["planned"] == qi]
+        cells = int(np.prod([p["domains"][a] for a in p["batch"][user[0]]["groupby"]]))
+        assert 2 * len(ref[user[0]]["keys"]) < cells, qi
+
+
+def test_estimator_picks_hash_tables_for_sparse_dense_key_spaces():
+    # a small chain: pair tables of a few million cells hold a few thousand
+    # groups; under learned sizing the estimator sends them to hash tables,
+    # bound sizing keeps them dense, and both equal the oracle
+    import oracle
+    from parity import compare
+    p = W.rkmeans_chain(seed=5, n1=60_000, n2=6_000, n3=400, n_x=6, n_y=4, n_z=3)
+    ref = oracle.evaluate(p)
+    picked = {}
+    for sizing in ("learned", "bound"):
+        plan = lm.Plan(p, precision="f32", policy="fact", sizing=sizing)
+        prep = lm.Prepared(plan, lm.device_columns(p))
+        prep.run(sync=True)
+        d = prep.describe()
+        picked[sizing] = d["picked_hash"]
+        for q in range(len(p["batch"])):
+            compare(prep.result(q), ref[q], 1e-5, f"{sizing} query {q}")
+    assert picked["bound"] == 0
+    assert picked["learned"] >= 1

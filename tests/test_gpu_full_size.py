@@ -3,8 +3,9 @@
 Each measured workload (``workloads.bench_workload``: the retail-shaped
 snowflake, the grocery-shaped star in BF16x3, the CART node batch and the
 Rk-means step-1 chain) runs exactly as ``bench.py`` runs it: the same
-generator call, the same plan options (``workloads.bench_plan_options``), a
-warm-up run that captures the HIP graph, then a graph replay.  EVERY output is
+generator call, the same plan options (``workloads.bench_plan_options``) with
+the autotuner's launch shapes, a warm-up run that captures the HIP graph,
+then a graph replay.  EVERY output is
 compared with the expected results that ``tests/golden/make_full_size.py``
 wrote from the streaming tier-B oracle (the plain definition, enumerating the
 natural join on all host cores):
@@ -84,8 +85,10 @@ def test_full_size_every_output(config):
     assert W.problem_digest(problem) == meta["problem_digest"], \
         f"the {config} generator changed: run tests/golden/make_full_size.py {config}"
     print(f"[full] {config} generated in {time.perf_counter() - t0:.1f} s", flush=True)
-    plan = E.Plan(problem, **W.bench_plan_options(bw))
     cols = E.device_columns(problem)
+    # the launch shapes bench.py times: the autotuner's (from its cache)
+    opts = E.tune(problem, cols, cache_path=E.TUNED_SHAPES, runs=5, **W.bench_plan_options(bw))["options"]
+    plan = E.Plan(problem, **opts)
     prep = E.Prepared(plan, cols)
     del cols
     torch.cuda.empty_cache()
