@@ -94,6 +94,13 @@ def test_full_size_every_output(config):
     torch.cuda.empty_cache()
     prep.run(sync=False)          # warm-up: captures the graph
     prep.run(sync=True)           # a replay (or a run after a regrowth), error flags checked
+    # the timed path: the largest relation's scans run the kernels generated
+    # for their groups (hipRTC), not the built-in fallback
+    d = prep.describe()
+    assert not d["codegen_failures"], d["codegen_failures"]
+    scans = [s for s in d["steps"] if s["kind"] == "scan"]
+    top = max(s["rows"] for s in scans)
+    assert all(s["lean"] == 2 for s in scans if s["rows"] == top), [s["name"] for s in scans]
     t0 = time.perf_counter()
     worst, digests, n = check_against_golden(prep, problem, config)
     print(f"[full] {config}: {n} queries, {n - digests} compared cell by cell (worst scaled error {worst:.2e}), "
