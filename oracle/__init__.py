@@ -38,7 +38,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["materialize_join", "evaluate", "evaluate_query", "evaluate_single",
-           "evaluate_view", "subtree", "OPS"]
+           "evaluate_view", "subtree", "with_functions", "OPS"]
 
 OPS = {
     "<=": np.less_equal, "<": np.less, ">": np.greater, ">=": np.greater_equal,
@@ -181,6 +181,25 @@ def evaluate_query(D: dict, query: dict) -> dict:
     return {"keys": keys, "count": count, "sum": sums, "abs": abss}
 
 
+def with_functions(problem: dict, D: dict, names) -> dict:
+    """User-defined factors (section 2: aggregates such as SUM(g(item) *
+    h(date)) with functions g, h of one attribute): problem["functions"][name]
+    = {"attr": a, "values": v} tabulates the function at every value of the
+    integer attribute a; the column ``name`` of D is v[t[a]] per tuple t."""
+    funcs = problem.get("functions", {})
+    for name in names:
+        if name in funcs and name not in D:
+            f = funcs[name]
+            D[name] = np.asarray(f["values"], dtype=np.float64)[np.asarray(D[f["attr"]], dtype=np.int64)]
+    return D
+
+
+def _needed(problem: dict, names) -> set:
+    """Attribute columns the names stand for (a function needs its argument)."""
+    funcs = problem.get("functions", {})
+    return {funcs[a]["attr"] if a in funcs else a for a in names}
+
+
 def evaluate(problem: dict, queries=None) -> list:
     """Every query of the batch (or the listed query indices) over the
     materialised join of ``problem``."""
@@ -193,7 +212,8 @@ def evaluate(problem: dict, queries=None) -> list:
         needed |= {w[0] for w in q.get("where", [])}
         for f in q["aggs"]:
             needed |= {a for a, _ in f}
-    D = materialize_join(problem, needed)
+    D = materialize_join(problem, _needed(problem, needed))
+    with_functions(problem, D, needed)
     return [evaluate_query(D, batch[i]) for i in idx]
 
 

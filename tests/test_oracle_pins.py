@@ -78,10 +78,13 @@ def brute_force(problem, qi=None, rels=None, query=None):
         g = tuple(tup[a] for a in q.get("groupby", []))
         slot = groups.setdefault(g, [0, [[] for _ in q["aggs"]]])
         slot[0] += 1
+        funcs = problem.get("functions", {})
         for k, factors in enumerate(q["aggs"]):
             t = 1.0
             for a, p in factors:
-                t *= tup[a] ** p
+                # a user-defined factor: its table at the tuple's argument value
+                v = float(funcs[a]["values"][tup[funcs[a]["attr"]]]) if a in funcs else tup[a]
+                t *= v ** p
             slot[1][k].append(t)
     keys = sorted(groups)
     return keys, [groups[k][0] for k in keys], [[math.fsum(v) for v in groups[k][1]] for k in keys]
@@ -388,3 +391,19 @@ def test_planted_wrong_subtree_side_is_caught(monkeypatch):
         if [tuple(int(x) for x in k) for k in r["keys"]] != keys or r["count"].tolist() != counts:
             caught = True
     assert caught
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_user_defined_factors(seed):
+    # SUM(g(x) * h(y)) and SUM(g(x)^2) grouped and ungrouped, with g, h
+    # tables over integer attributes (section 2, the example query Q2)
+    p = W.random_acyclic(seed)
+    ints = [(a["name"], a["domain"]) for r in p["schema"] for a in r["attrs"] if a["dtype"] == "i32" and a.get("domain")]
+    rng = np.random.default_rng(seed)
+    (xa, xd), (ya, yd) = ints[0], ints[-1]
+    p["functions"] = {"g": {"attr": xa, "values": rng.normal(size=xd)},
+                      "h": {"attr": ya, "values": rng.normal(size=yd)}}
+    gb = [ya] if ya != xa else []
+    p["batch"] = [{"groupby": [], "where": [], "aggs": [[("g", 1), ("h", 1)], [("g", 2)], []]},
+                  {"groupby": gb, "where": [], "aggs": [[("g", 1)], [("h", 1), ("g", 1)]]}]
+    assert_matches_brute(p)
