@@ -129,9 +129,24 @@ typedef struct {
   int32_t root;        /* relation index, or -1 for the root heuristic */
 } lmfao_query;
 
+/* A user-defined factor (section 2: aggregates such as SUM(g(item) *
+ * h(date))): a function of one integer attribute with a domain, given by
+ * its value at every attribute value 0 .. domain-1 (HOST array of
+ * n_values = domain doubles, copied by lmfao_plan).  Factors name it in
+ * `attr` like an attribute (power 1 or 2); at prepare time its values are
+ * gathered into an FP64 column of one relation holding the attribute. */
+typedef struct {
+  const char* name;
+  const char* attr;
+  int64_t n_values;
+  const double* values;
+} lmfao_function;
+
 typedef struct {
   int32_t n_queries;
   const lmfao_query* queries;
+  int32_t n_functions;
+  const lmfao_function* functions;
 } lmfao_batch;
 
 /* F64 and F32: arithmetic of the scans, views and contraction.  BF16X3:
@@ -152,7 +167,18 @@ enum { LMFAO_FORM_FUSED = 0, LMFAO_FORM_PER_VIEW = 1 };
  * FACT: the largest relation from which every group-by attribute is reached
  * through primary-key joins (carried as a code by single-valued views), and
  * queries over the attributes of a single relation are rooted there. */
-enum { LMFAO_ROOT_GROUPBY = 0, LMFAO_ROOT_FACT = 1 };
+enum { LMFAO_ROOT_GROUPBY = 0, LMFAO_ROOT_FACT = 1, LMFAO_ROOT_COST = 2 };
+/* COST: a cost model and a search.  A root assignment costs the bytes the
+ * fused plan moves: one pass over every relation that computes a view or a
+ * query (16 bytes a row) plus every distinct view's dense key space (8 bytes
+ * a cell; views are shared across queries as view generation merges them).
+ * Starting from the FACT roots, the queries with the same group-by
+ * attributes and conditions move together, class by class, to the root of
+ * least cost with the other classes fixed, until a round moves nothing.
+ * Root overrides in the batch are kept.  If the plan of the chosen roots
+ * falls outside the supported class, the FACT roots are used instead
+ * ("root_fallback" in the description).  lmfao_plan_describe reports the
+ * final assignment's cost ("root_cost_bytes") under every policy. */
 /* Kernel for the segment-level contraction sum over pieces of (outer
  * features) x (inner partial sums).  MFMA: the features and columns of each
  * piece are staged in FP64 and multiplied on the matrix cores

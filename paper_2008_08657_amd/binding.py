@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblmfao.so")
 I32, F32, F64 = 0, 1, 2
 PREC_F64, PREC_F32, PREC_BF16X3, PREC_BF16X2 = 0, 1, 2, 3
 FORM_FUSED, FORM_PER_VIEW = 0, 1
-ROOT_GROUPBY, ROOT_FACT = 0, 1
+ROOT_GROUPBY, ROOT_FACT, ROOT_COST = 0, 1, 2
 OPS = {"<=": 0, "<": 1, ">": 2, ">=": 3, "==": 4, "!=": 5}
 _DTYPES = {"i32": I32, "f32": F32, "f64": F64}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED", 5: "EOVERFLOW"}
@@ -64,8 +64,14 @@ class lmfao_query(C.Structure):
                 ("root", C.c_int32)]
 
 
+class lmfao_function(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("attr", C.c_char_p), ("n_values", C.c_int64),
+                ("values", C.POINTER(C.c_double))]
+
+
 class lmfao_batch(C.Structure):
-    _fields_ = [("n_queries", C.c_int32), ("queries", C.POINTER(lmfao_query))]
+    _fields_ = [("n_queries", C.c_int32), ("queries", C.POINTER(lmfao_query)),
+                ("n_functions", C.c_int32), ("functions", C.POINTER(lmfao_function))]
 
 
 class lmfao_options(C.Structure):
@@ -245,7 +251,11 @@ def marshal_problem(problem, keep: _Keep):
         root_i = -1 if root is None else (names.index(root) if isinstance(root, str) else int(root))
         queries.append(lmfao_query(len(q.get("groupby", [])), gb, len(q.get("where", [])), conds,
                                    len(aggs), keep.arr(lmfao_aggregate, aggs), root_i))
-    batch = lmfao_batch(len(queries), keep.arr(lmfao_query, queries))
+    funcs = []
+    for name, f in problem.get("functions", {}).items():
+        vals = [float(x) for x in f["values"]]
+        funcs.append(lmfao_function(keep.s(name), keep.s(f["attr"]), len(vals), keep.arr(C.c_double, vals)))
+    batch = lmfao_batch(len(queries), keep.arr(lmfao_query, queries), len(funcs), keep.arr(lmfao_function, funcs))
     keep.refs += [schema, tree, batch]
     return schema, tree, batch
 
@@ -264,7 +274,9 @@ def build_options(problem, keep, precision="f64", policy=None, form="fused", ord
                       "bf16x2": PREC_BF16X2}[precision]
     opts.form = FORM_FUSED if form == "fused" else FORM_PER_VIEW
     pol = policy if policy is not None else problem.get("policy", "groupby")
-    opts.root_policy = ROOT_FACT if pol == "fact" else ROOT_GROUPBY
+    if pol not in ("fact", "groupby", "cost"):
+        raise ValueError(f"policy must be 'fact', 'groupby' or 'cost', not {pol!r}")
+    opts.root_policy = {"fact": ROOT_FACT, "groupby": ROOT_GROUPBY, "cost": ROOT_COST}[pol]
     opts.min_segment = int(min_segment)
     opts.row_piece_max = int(row_piece_max)
     if contraction not in ("mfma", "valu"):

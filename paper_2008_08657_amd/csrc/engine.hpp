@@ -263,8 +263,8 @@ struct GroupDef {
 // the value (kind 1: t <= x, for x < t and x >= t).  Thresholds are rounded to
 // the attribute's comparison type (FP32 columns compare in FP32) and sorted.
 struct DerivedAttr {
-  int attr = -1, src = -1, rel = -1, kind = 0;
-  std::vector<double> thr;
+  int attr = -1, src = -1, rel = -1, kind = 0;   // kind 0, 1: bucket codes (<= / < thresholds); 2: function
+  std::vector<double> thr;                        // thresholds, or the function's values per source value
 };
 
 // A query of the caller's batch: either one planned query, or the sum over a
@@ -296,6 +296,8 @@ struct Plan {
   std::string unsupported_reason;
   std::vector<std::vector<char>> uniq;   // uniq[n][p]: V_{n->p} unique (adjacency)
   std::string json;
+  double root_cost = 0;            // root cost model of the final root assignment (bytes)
+  std::string root_fallback;       // ROOT_COST fell back to the FACT roots: why
 };
 
 // builds the logical and physical plan; throws PlanError on invalid input

@@ -285,6 +285,25 @@ void launch_cart_split(const int64_t* const* cand_cnt, const double* const* cand
                      min_leaf, tie_eps, costs, best);
 }
 
+// a function of an integer attribute, tabulated: out[r] = tab[src[r]]; an
+// argument outside the table flags error 2 and gives 0
+__global__ __launch_bounds__(256) void k_gather_table(const int32_t* __restrict__ src, int64_t n,
+                                                     const double* __restrict__ tab, int64_t nt,
+                                                     double* __restrict__ out, int32_t* err) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = src[r];
+    const bool ok = v >= 0 && (int64_t)v < nt;
+    if (!ok) atomicOr(err, 2);
+    out[r] = ok ? tab[v] : 0.0;
+  }
+}
+void launch_gather_table(const int32_t* src, int64_t n, const double* tab, int64_t nt, double* out, int32_t* err,
+                         hipStream_t s) {
+  if (n <= 0) return;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_gather_table, dim3(grid), dim3(256), 0, s, src, n, tab, nt, out, err);
+}
+
 // bucket = number of thresholds below the value (kind 0) or at most the value
 // (kind 1); thresholds sorted ascending, in the column's comparison type
 __global__ __launch_bounds__(256) void k_bucketize(DCol src, int64_t n, const double* __restrict__ thr, int n_thr,

@@ -198,6 +198,9 @@ void launch_filter_value(const DFilter& f, hipStream_t s);
 void launch_bucketize(const void* src, int dtype, int64_t n, const double* thr, int n_thr, int kind, int32_t* out,
                       hipStream_t s);
 void launch_finalize(const DFinalize* d, int n, hipStream_t s);
+// out[r] = tab[src[r]] (a tabulated function of an integer column)
+void launch_gather_table(const int32_t* src, int64_t n, const double* tab, int64_t nt, double* out, int32_t* err,
+                         hipStream_t s);
 
 // covariance-matrix assembly entry: Sigma[a][b] = Sigma[b][a] = *src
 struct DSigmaEntry {

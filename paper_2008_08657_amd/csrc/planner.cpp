@@ -156,6 +156,34 @@ static void intake(Plan& P, const lmfao_schema* schema, const lmfao_join_tree* t
     if (P.attrs[a].dtype != LMFAO_I32 || P.attrs[a].domain <= 0)
       fail(LMFAO_EUNSUPPORTED, "join attribute " + P.attrs[a].name + " needs an integer domain");
   }
+  // user-defined factors: an FP64 column of the smallest relation holding
+  // the argument, gathered from the function's table at prepare time
+  if (batch && batch->n_functions < 0) fail(LMFAO_EINVAL, "negative function count");
+  for (int fi = 0; batch && fi < batch->n_functions; ++fi) {
+    const lmfao_function& F = batch->functions[fi];
+    if (!F.name || !*F.name || !F.attr) fail(LMFAO_EINVAL, "unnamed function or argument");
+    if (P.attr_id.count(F.name)) fail(LMFAO_EINVAL, std::string("function name ") + F.name + " is taken");
+    auto it = P.attr_id.find(F.attr);
+    if (it == P.attr_id.end()) fail(LMFAO_EINVAL, std::string("unknown function argument ") + F.attr);
+    const AttrDef& A = P.attrs[it->second];
+    if (A.dtype != LMFAO_I32 || A.domain <= 0 || F.n_values != A.domain || !F.values)
+      fail(LMFAO_EINVAL, std::string("function ") + F.name + ": needs one value per value of an integer attribute");
+    DerivedAttr D;
+    D.src = it->second;
+    D.kind = 2;
+    D.thr.assign(F.values, F.values + F.n_values);
+    for (size_t r = 0; r < P.rels.size(); ++r)
+      if (P.rels[r].has(D.src) && (D.rel < 0 || P.rels[r].n_rows < P.rels[D.rel].n_rows)) D.rel = (int)r;
+    D.attr = (int)P.attrs.size();
+    P.attr_id[F.name] = D.attr;
+    P.attrs.push_back(AttrDef{F.name, LMFAO_F64, 0});
+    RelDef& R = P.rels[D.rel];
+    R.col[D.attr] = (int)R.attrs.size();
+    R.attrs.push_back(D.attr);
+    R.dtypes.push_back(LMFAO_F64);
+    R.is_key.push_back(0);
+    P.derived.push_back(D);
+  }
   // batch
   if (!batch || batch->n_queries <= 0) fail(LMFAO_EINVAL, "empty batch");
   for (int qi = 0; qi < batch->n_queries; ++qi) {
@@ -466,9 +494,113 @@ struct ViewKey {
   }
 };
 
+// The view a query rooted at `root` needs along the edge from node u to its
+// parent p (its identity as view generation merges views: direction,
+// carried group-by attributes unless the view is single-valued, conditions).
+static ViewKey view_key_of(const Plan& P, const QueryDef& q, const std::vector<int>& owner, int u, int p,
+                           const std::set<int>& subset, std::vector<int>* carried_out = nullptr) {
+  auto owned = [&](int a) { return subset.count(owner[a]) != 0; };
+  ViewKey k{u, p, {}, {}};
+  std::vector<int> carried;
+  for (int g : q.groupby)
+    if (owned(g)) carried.push_back(g);
+  std::sort(carried.begin(), carried.end());
+  if (!P.uniq[u][p]) k.carried = carried;
+  for (auto& c : q.conds)
+    if (owned(c.attr)) k.conds.push_back(c);
+  if (carried_out) *carried_out = carried;
+  return k;
+}
+
+// Root cost model: the bytes a root assignment makes the fused plan move --
+// one pass over every node that computes a view or a query (rows x 16 B) and,
+// per distinct view (views are merged across queries as view generation
+// merges them), its dense key space written once (cells x 8 B).
+static double root_assignment_cost(const Plan& P, const std::vector<int>& roots) {
+  const int n = (int)P.rels.size();
+  std::set<ViewKey> views;
+  std::vector<char> active(n, 0);
+  double out = 0;
+  for (size_t qi = 0; qi < P.queries.size(); ++qi) {
+    const QueryDef& q = P.queries[qi];
+    const int root = roots[qi];
+    active[root] = 1;
+    std::vector<int> parent;
+    std::vector<int> owner = owners_from(P, root, parent);
+    for (int u = 0; u < n; ++u) {
+      if (u == root) continue;
+      std::vector<int> sub;
+      subtree(P, u, parent[u], sub);
+      std::set<int> subset(sub.begin(), sub.end());
+      std::vector<int> carried;
+      ViewKey k = view_key_of(P, q, owner, u, parent[u], subset, &carried);
+      if (!views.insert(k).second) continue;
+      active[u] = 1;
+      double cells = 1;
+      for (int a : join_attrs(P, u, parent[u])) cells *= (double)std::max<int64_t>(P.attrs[a].domain, 1);
+      for (int g : carried) cells *= (double)std::max<int64_t>(P.attrs[g].domain, 1);
+      out += std::min(cells, 1e15) * 8.0;
+    }
+  }
+  double scans = 0;
+  for (int u = 0; u < n; ++u)
+    if (active[u]) scans += (double)P.rels[u].n_rows * 16.0;
+  return scans + out;
+}
+
+// ROOT_COST policy: queries without an override start at the FACT roots;
+// queries with the same group-by attributes and conditions (the parts that
+// decide their views) move together, class by class (largest first), to the
+// root of least plan cost with the others fixed, until a round changes
+// nothing (at most 4 rounds).
+static void assign_roots_by_cost(Plan& P) {
+  const int n = (int)P.rels.size();
+  std::vector<int> roots(P.queries.size());
+  std::map<std::pair<std::vector<int>, std::vector<Cond>>, std::vector<int>> classes;
+  for (size_t qi = 0; qi < P.queries.size(); ++qi) {
+    const QueryDef& q = P.queries[qi];
+    roots[qi] = q.root >= 0 ? q.root : root_fact(P, q);
+    if (roots[qi] < 0) {
+      int best = 0;
+      for (int r = 1; r < n; ++r)
+        if (P.rels[r].n_rows > P.rels[best].n_rows) best = r;
+      roots[qi] = best;
+    }
+    if (q.root >= 0) continue;   // the caller's override stays
+    std::vector<int> gb = q.groupby;
+    std::sort(gb.begin(), gb.end());
+    classes[{gb, q.conds}].push_back((int)qi);
+  }
+  std::vector<const std::vector<int>*> order;
+  for (auto& kv : classes) order.push_back(&kv.second);
+  std::stable_sort(order.begin(), order.end(), [](auto* a, auto* b) { return a->size() > b->size(); });
+  double cost = root_assignment_cost(P, roots);
+  for (int round = 0; round < 4; ++round) {
+    bool moved = false;
+    for (const std::vector<int>* cls : order) {
+      const int cur = roots[(*cls)[0]];
+      int best = cur;
+      for (int r = 0; r < n; ++r) {
+        if (r == cur) continue;
+        for (int qi : *cls) roots[qi] = r;
+        const double c = root_assignment_cost(P, roots);
+        if (c < cost * (1.0 - 1e-12)) {
+          cost = c;
+          best = r;
+        }
+      }
+      for (int qi : *cls) roots[qi] = best;
+      moved |= best != cur;
+    }
+    if (!moved) break;
+  }
+  for (size_t qi = 0; qi < P.queries.size(); ++qi) P.queries[qi].root = roots[qi];
+}
+
 static void generate_views(Plan& P) {
   int n = (int)P.rels.size();
   std::map<ViewKey, int> index;
+  if (P.opts.root_policy == LMFAO_ROOT_COST) assign_roots_by_cost(P);
   for (size_t qi = 0; qi < P.queries.size(); ++qi) {
     QueryDef& q = P.queries[qi];
     if (q.root < 0) {
@@ -501,16 +633,10 @@ static void generate_views(Plan& P) {
       subtree(P, u, p, sub);
       std::set<int> subset(sub.begin(), sub.end());
       auto owned = [&](int a) { return subset.count(owner[a]) != 0; };
-      ViewKey k{u, p, {}, {}};
-      std::vector<int> carried;
-      for (int g : q.groupby)
-        if (owned(g)) carried.push_back(g);
-      std::sort(carried.begin(), carried.end());
       // a single-valued view determines its carried attributes from its key,
       // so views that differ only in them are one view storing all of them
-      if (!P.uniq[u][p]) k.carried = carried;
-      for (auto& c : q.conds)
-        if (owned(c.attr)) k.conds.push_back(c);
+      std::vector<int> carried;
+      ViewKey k = view_key_of(P, q, owner, u, p, subset, &carried);
       int id;
       auto it = index.find(k);
       if (it == index.end()) {
@@ -543,6 +669,11 @@ static void generate_views(Plan& P) {
       vid[u] = id;
     }
     for (int c : P.adj[q.root]) q.in_view[c] = vid[c];
+  }
+  {
+    std::vector<int> roots;
+    for (auto& q : P.queries) roots.push_back(q.root);
+    P.root_cost = root_assignment_cost(P, roots);
   }
   // levels (dependencies form a DAG by construction)
   std::function<int(int)> lvl = [&](int v) -> int {
@@ -1544,14 +1675,22 @@ static std::string describe(const Plan& P) {
     o << "[\"" << json_escape(P.attrs[P.filter[i].attr].name) << "\",\"" << ops[P.filter[i].op] << "\","
       << P.filter[i].c << "]";
   }
-  o << "],\"derived\":[";
+  {
+    char num[64];
+    std::snprintf(num, sizeof num, "%.6g", P.root_cost);
+    o << "],\"root_cost_bytes\":" << num;
+    if (!P.root_fallback.empty())
+      o << ",\"root_fallback\":\"" << json_escape(P.root_fallback) << "\"";
+  }
+  o << ",\"derived\":[";
   for (size_t i = 0; i < P.derived.size(); ++i) {
     const DerivedAttr& D = P.derived[i];
     if (i) o << ",";
     o << "{\"name\":\"" << json_escape(P.attrs[D.attr].name) << "\",\"source\":\""
       << json_escape(P.attrs[D.src].name) << "\",\"relation\":\"" << json_escape(P.rels[D.rel].name)
-      << "\",\"kind\":" << D.kind << ",\"thresholds\":" << D.thr.size() << ",\"threshold_values\":[";
-    for (size_t t = 0; t < D.thr.size(); ++t) {
+      << "\",\"kind\":" << D.kind << ",\"thresholds\":" << (D.kind == 2 ? 0 : D.thr.size())
+      << ",\"threshold_values\":[";
+    for (size_t t = 0; D.kind != 2 && t < D.thr.size(); ++t) {
       char num[64];
       std::snprintf(num, sizeof num, "%.17g", D.thr[t]);
       o << (t ? "," : "") << num;
@@ -1678,8 +1817,30 @@ static std::string describe(const Plan& P) {
   return o.str();
 }
 
+static Plan* build_plan_once(const lmfao_schema* schema, const lmfao_join_tree* tree, const lmfao_batch* batch,
+                             const lmfao_options* opts);
+
+// With the ROOT_COST policy, a root assignment whose plan falls outside what
+// the kernels support (EUNSUPPORTED) is replaced by the FACT roots.
 Plan* build_plan(const lmfao_schema* schema, const lmfao_join_tree* tree, const lmfao_batch* batch,
                  const lmfao_options* opts) {
+  if (!opts || opts->root_policy != LMFAO_ROOT_COST) return build_plan_once(schema, tree, batch, opts);
+  try {
+    return build_plan_once(schema, tree, batch, opts);
+  } catch (const PlanError& e) {
+    if (e.status != LMFAO_EUNSUPPORTED) throw;
+    lmfao_options o = *opts;
+    o.root_policy = LMFAO_ROOT_FACT;
+    Plan* P = build_plan_once(schema, tree, batch, &o);
+    P->opts.root_policy = LMFAO_ROOT_COST;
+    P->root_fallback = e.msg;
+    P->json = describe(*P);
+    return P;
+  }
+}
+
+static Plan* build_plan_once(const lmfao_schema* schema, const lmfao_join_tree* tree, const lmfao_batch* batch,
+                             const lmfao_options* opts) {
   Plan* P = new Plan();
   try {
     if (opts) P->opts = *opts;

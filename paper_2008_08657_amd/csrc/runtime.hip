@@ -1911,8 +1911,16 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
     const int sc = R.col.at(D.src), dc = R.col.at(D.attr);
     if (R.n_rows > 0 && !S.ecols[D.rel][sc])
       throw PlanError{LMFAO_EINVAL, "null column " + P.attrs[D.src].name + " of " + R.name};
-    int32_t* out = (int32_t*)dalloc(S, (size_t)std::max<int64_t>(R.n_rows, 1) * 4);
     const double* thr = upload_vec(S, D.thr, st);
+    if (D.kind == 2) {
+      // a user-defined factor: its table at every row's argument value
+      double* out = (double*)dalloc(S, (size_t)std::max<int64_t>(R.n_rows, 1) * 8);
+      launch_gather_table((const int32_t*)S.ecols[D.rel][sc], R.n_rows, thr, (int64_t)D.thr.size(), out,
+                          S.err_flag, st);
+      S.ecols[D.rel][dc] = out;
+      continue;
+    }
+    int32_t* out = (int32_t*)dalloc(S, (size_t)std::max<int64_t>(R.n_rows, 1) * 4);
     launch_bucketize(S.ecols[D.rel][sc], R.dtypes[sc], R.n_rows, thr, (int)D.thr.size(), D.kind, out, st);
     S.ecols[D.rel][dc] = out;
   }

@@ -410,3 +410,18 @@ def test_dangling_keys(eng):
     assert 0 < int(ref[0]["count"][0]) < 20_000
     check(eng, p, F64_TOL, "dangling keys", policy="fact")
     check(eng, p, F64_TOL, "dangling keys scan", policy="fact", row_piece_max=-1, min_segment=1)
+
+
+@pytest.mark.parametrize("which", ["tiny", "grocery", "random8", "random9"])
+def test_root_cost_policy_matches_oracle(which):
+    # roots chosen by the cost model give the oracle's results
+    import paper_2008_08657_amd as E
+    p = {"tiny": lambda: W.tiny_star(seed=2, n_fact=50_000),
+         "grocery": lambda: W.grocery_star(seed=1, n_sales=150_000),
+         "random8": lambda: W.random_acyclic(8), "random9": lambda: W.random_acyclic(9)}[which]()
+    prec, tol = ("f64", 1e-12) if which != "grocery" else ("f32", 1e-5)
+    plan = E.Plan(p, precision=prec, policy="cost")
+    prep = E.Prepared(plan, E.device_columns(p))
+    prep.run(sync=True)
+    ref = oracle.evaluate(p)
+    compare_all([prep.result(q) for q in range(len(p["batch"]))], ref, tol, which)

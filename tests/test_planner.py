@@ -271,3 +271,27 @@ def test_negative_launch_options_are_rejected(kw):
     with pytest.raises(E.LmfaoError) as ei:
         E.Plan(W.tiny_star(n_fact=100), policy="fact", **kw)
     assert str(ei.value).startswith("EINVAL")
+
+
+@pytest.mark.parametrize("which", ["tiny", "grocery", "chain", "random8", "random9"])
+def test_root_cost_policy_never_costs_more_than_its_start(which):
+    # the search starts at the FACT roots and accepts only moves that lower
+    # the modelled bytes; a plan outside the supported class falls back to
+    # FACT (equal cost)
+    p = {"tiny": lambda: W.tiny_star(seed=0, n_fact=100_000),
+         "grocery": lambda: W.grocery_star(seed=0, n_sales=500_000),
+         "chain": lambda: W.rkmeans_chain(seed=0, n1=200_000, n2=20_000, n3=1_000),
+         "random8": lambda: W.random_acyclic(8), "random9": lambda: W.random_acyclic(9)}[which]()
+    fact = E.Plan(p, precision="f32", policy="fact").describe()
+    cost = E.Plan(p, precision="f32", policy="cost").describe()
+    assert cost["root_cost_bytes"] <= fact["root_cost_bytes"] * (1 + 1e-12)
+    assert len(cost["queries"]) == len(fact["queries"])
+
+
+def test_root_cost_policy_shares_the_fact_scan_on_the_tiny_star():
+    # every query of the tiny star can read the fact relation S once; the
+    # dimension roots of FACT cost a pass over each dimension and more views
+    p = W.tiny_star(seed=0, n_fact=100_000)
+    d = E.Plan(p, precision="f64", policy="cost").describe()
+    assert {q["root"] for q in d["queries"]} == {"S"}
+    assert len(d["views"]) == 2

@@ -458,6 +458,27 @@ def cart_node(seed: int = 0, n_inv: int = 84_000_000, n_thr: int = 20, n_node_co
 
 
 
+def udf_grocery(seed: int = 0, n_sales: int = 200_000, **kw):
+    """The grocery-shaped star with user-defined factors (section 2, the
+    example's second query: SUM(g(item) * h(date))): g tabulated over the
+    item domain and h over the date domain (values ~ N(0, 1)).  Batch: that
+    query, SUM(g(item)) grouped by store, SUM(h(date)^2) grouped by family,
+    SUM(g(item) * unit_sales), SUM(g(item)^2) and COUNT."""
+    p = grocery_star(seed=seed, n_sales=n_sales, **kw)
+    dom = {a["name"]: a["domain"] for r in p["schema"] for a in r["attrs"]}
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 7])))
+    p["functions"] = {"g": {"attr": "item", "values": rng.standard_normal(int(dom["item"]))},
+                      "h": {"attr": "date", "values": rng.standard_normal(int(dom["date"]))}}
+    p["batch"] = [
+        {"groupby": [], "where": [], "aggs": [[("g", 1), ("h", 1)]], "root": None},
+        {"groupby": ["store"], "where": [], "aggs": [[("g", 1)]], "root": None},
+        {"groupby": ["family"], "where": [], "aggs": [[("h", 2)]], "root": None},
+        {"groupby": [], "where": [], "aggs": [[("g", 1), ("unit_sales", 1)], [("g", 2)], []], "root": None},
+    ]
+    p["name"] = "udf_grocery"
+    return p
+
+
 def cart_tree(seed: int = 0, n_inv: int = 200_000, n_thr: int = 8, cont=None, cats=None, label: str = "units",
               **retail_kw):
     """The node batch of regression-tree growth by CART on the retail-shaped
