@@ -526,6 +526,53 @@ lmfao_status lmfao_cart_grow(lmfao_plan_t plan, lmfao_prepared_t prep, const voi
                              const lmfao_cart_spec* spec, lmfao_cart_node* nodes, int32_t cap, int32_t* n_nodes,
                              void* stream);
 
+/* Rk-means (paper, section 3, "Rk-means").  Step 1 is a batch of
+ * SUM(1) GROUP BY X_j queries (lmfao_run); their device results
+ * (lmfao_result_device: ascending codes and counts) are step 2's input.
+ *
+ * lmfao_kmeans_1d, step 2: weighted k-means on every projection.  Set s is
+ * the ascending integer values values[offsets[s] .. offsets[s+1]) with
+ * integer weights (DEVICE int64 arrays; offsets is HOST, n_sets + 1
+ * entries).  Lloyd's algorithm in FP64, one workgroup per set: centroid i
+ * (0 <= i < k) starts at the first value whose cumulative weight reaches
+ * (2i + 1) / (2k) of the set's total; then every value is assigned to its
+ * nearest centroid (the lowest index on a tie) and every centroid moved to
+ * the weighted mean of its values (a centroid with none stays), until an
+ * assignment step changes nothing or after max_iter update steps.  With
+ * integer values and weights every sum is exact below 2^53, so the result
+ * does not depend on the order of the additions.  Writes centroids (DEVICE,
+ * n_sets x k doubles), the cluster of every value (DEVICE int32, aligned
+ * with `values`) and, if not NULL, the update steps per set (HOST).
+ * 1 <= k <= 64.  Synchronises `stream`.
+ *
+ * lmfao_grid_coreset, step 3: SELECT C_1, ..., C_n, SUM(1) FROM D JOIN
+ * A_1(X_1, C_1) ... JOIN A_n(X_n, C_n) GROUP BY C_1, ..., C_n, where dims[j]
+ * gives A_j as the ascending codes of X_j and their clusters (DEVICE
+ * arrays, n_codes each; values of X_j not listed map to cluster 0).  The
+ * join must be one whose tuples a root row determines: every other relation
+ * is reached from the root through one integer key attribute (FK chains and
+ * stars; LMFAO_EUNSUPPORTED otherwise).  On the GPU: each root row's cluster
+ * ids are packed (a power of two of bits each, at most 512 bits in all) and
+ * counted by a 64-bit fingerprint in a hash table; a second pass compares
+ * every row's packed ids with its group's representative, and a fingerprint
+ * shared by two different id vectors gives LMFAO_EUNSUPPORTED instead of a
+ * merged group.  `out` receives the groups in no particular order: keys
+ * n_groups x n int64 cluster ids, counts their weights, no values (DEVICE
+ * arrays owned by `prep`).  `columns` as for lmfao_prepare (still valid).
+ * Synchronises `stream`. */
+lmfao_status lmfao_kmeans_1d(int32_t n_sets, const int64_t* offsets, const int64_t* values, const int64_t* weights,
+                             int32_t k, int32_t max_iter, double* centroids, int32_t* assignment, int32_t* steps,
+                             void* stream);
+typedef struct {
+  const char* attr;
+  const int64_t* codes;     /* DEVICE, ascending */
+  const int32_t* cluster;   /* DEVICE, the cluster (0 .. k-1) of each code */
+  int64_t n_codes;
+} lmfao_grid_dim;
+lmfao_status lmfao_grid_coreset(lmfao_plan_t plan, lmfao_prepared_t prep, const void* const* const* columns,
+                                int32_t n_dims, const lmfao_grid_dim* dims, int32_t k, lmfao_output* out,
+                                void* stream);
+
 /* Ridge linear regression over the batch's results (paper, section 3,
  * "Linear Regression"): x = (1, continuous..., one-hot blocks of the
  * categoricals over their whole domains); Sigma = sum over D of x x^T.

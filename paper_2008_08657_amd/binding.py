@@ -89,6 +89,10 @@ class lmfao_output(C.Structure):
                 ("counts", C.c_void_p), ("values", C.c_void_p)]
 
 
+class lmfao_grid_dim(C.Structure):
+    _fields_ = [("attr", C.c_char_p), ("codes", C.c_void_p), ("cluster", C.c_void_p), ("n_codes", C.c_int64)]
+
+
 class lmfao_column_condition(C.Structure):
     _fields_ = [("column", C.c_void_p), ("dtype", C.c_int32), ("op", C.c_int32), ("constant", C.c_double)]
 
@@ -183,6 +187,12 @@ def load_library(path: str = LIB_PATH):
     lib.lmfao_prepared_workspace_bytes.restype = C.c_int32
     lib.lmfao_result_device.argtypes = [vp, C.c_int32, C.POINTER(lmfao_output), vp]
     lib.lmfao_result_device.restype = C.c_int32
+    lib.lmfao_kmeans_1d.argtypes = [C.c_int32, C.POINTER(C.c_int64), vp, vp, C.c_int32, C.c_int32, vp, vp,
+                                    C.POINTER(C.c_int32), vp]
+    lib.lmfao_kmeans_1d.restype = C.c_int32
+    lib.lmfao_grid_coreset.argtypes = [vp, vp, C.POINTER(C.POINTER(vp)), C.c_int32, C.POINTER(lmfao_grid_dim),
+                                       C.c_int32, C.POINTER(lmfao_output), vp]
+    lib.lmfao_grid_coreset.restype = C.c_int32
     lib.lmfao_row_weights.argtypes = [vp, C.c_int32, C.POINTER(vp)]
     lib.lmfao_row_weights.restype = C.c_int32
     lib.lmfao_eval_conditions.argtypes = [C.c_int64, C.c_int32, C.POINTER(lmfao_column_condition), vp, vp]
@@ -530,6 +540,25 @@ class Prepared:
                                                   C.byref(n), self.stream))
         return [{f: getattr(nodes[i], f) for f, _ in lmfao_cart_node._fields_ if f != "pad"} for i in range(n.value)]
 
+    def grid_coreset(self, columns, dims, k: int) -> dict:
+        """Rk-means step 3 (``lmfao_grid_coreset``): ``dims`` lists (attr,
+        codes, cluster) with int64 and int32 device tensors; returns the grid
+        points' cluster ids and weights as device tensors (no copy)."""
+        import torch
+        keep = _Keep()
+        cols = _column_table(self.plan.problem, columns, keep)
+        ds = keep.arr(lmfao_grid_dim, [lmfao_grid_dim(keep.s(a), C.c_void_p(c.data_ptr()), C.c_void_p(cl.data_ptr()),
+                                                      int(c.numel())) for a, c, cl in dims])
+        o = lmfao_output()
+        _check(self.lib, self.lib.lmfao_grid_coreset(self.plan.handle, self.handle, cols, len(dims), ds, int(k),
+                                                     C.byref(o), self.stream))
+        n = int(o.n_groups)
+        if n == 0:
+            return {"keys": torch.empty((0, len(dims)), dtype=torch.int64, device="cuda"),
+                    "count": torch.empty(0, dtype=torch.int64, device="cuda")}
+        return {"keys": torch.as_tensor(_DeviceArray(o.keys, (n, len(dims)), "<i8"), device="cuda"),
+                "count": torch.as_tensor(_DeviceArray(o.counts, (n,), "<i8"), device="cuda")}
+
     def ridge_sigma(self, continuous, categorical=()):
         """Sigma = sum over D of x x^T assembled on the device from the last
         run's results (``lmfao_ridge_sigma``); a (dim, dim) FP64 torch tensor."""
@@ -565,6 +594,30 @@ def ridge_bgd(sigma, label: int, lam: float, eta: float = 0.0, max_iter: int = 2
                                     C.c_double(eta), int(max_iter), C.c_double(tol),
                                     C.c_void_p(theta.data_ptr()), stats, C.c_void_p(stream) if stream else None))
     return theta, int(stats[0]), float(stats[1]), float(stats[2])
+
+
+def kmeans_1d(sets, k: int, max_iter: int = 100, stream=None):
+    """Rk-means step 2 (``lmfao_kmeans_1d``): ``sets`` lists (values,
+    weights) pairs of int64 device tensors (ascending values).  Returns
+    (centroids n_sets x k float64 tensor, per-set cluster tensors, update
+    steps per set)."""
+    import torch
+    lib = load_library()
+    sizes = [int(v.numel()) for v, _ in sets]
+    offsets = [0]
+    for m in sizes:
+        offsets.append(offsets[-1] + m)
+    values = torch.cat([v.reshape(-1) for v, _ in sets]) if sets else torch.empty(0, dtype=torch.int64, device="cuda")
+    weights = torch.cat([w.reshape(-1) for _, w in sets]) if sets else torch.empty(0, dtype=torch.int64, device="cuda")
+    cent = torch.empty((len(sets), k), dtype=torch.float64, device="cuda")
+    assign = torch.empty(max(1, offsets[-1]), dtype=torch.int32, device="cuda")
+    steps = (C.c_int32 * max(1, len(sets)))()
+    off = (C.c_int64 * len(offsets))(*offsets)
+    _check(lib, lib.lmfao_kmeans_1d(len(sets), off, C.c_void_p(values.data_ptr()), C.c_void_p(weights.data_ptr()),
+                                    int(k), int(max_iter), C.c_void_p(cent.data_ptr()),
+                                    C.c_void_p(assign.data_ptr()), steps, _stream_arg(stream)))
+    parts = [assign[offsets[i]:offsets[i + 1]] for i in range(len(sets))]
+    return cent, parts, [steps[i] for i in range(len(sets))]
 
 
 def _stream_arg(stream):

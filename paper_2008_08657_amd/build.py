@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblmfao.so")
 
-SOURCES = ["planner.cpp", "runtime.hip", "kernels.hip", "codegen.hip", "mlp.hip"]
+SOURCES = ["planner.cpp", "runtime.hip", "kernels.hip", "codegen.hip", "mlp.hip", "rkmeans.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

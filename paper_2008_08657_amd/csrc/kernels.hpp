@@ -245,6 +245,46 @@ void launch_compact(const DCompact& d, hipStream_t s);
 // hash tables after launch_compact: emission of the n sorted groups
 void launch_compact_emit(const DCompact& d, int64_t n, hipStream_t s);
 
+// Rk-means step 2: weighted 1-D k-means (Lloyd) per set of ascending
+// integer values with integer weights, one workgroup per set
+constexpr int kKmMaxClusters = 64;
+void launch_kmeans_1d(const int64_t* off, int n_sets, const int64_t* values, const int64_t* weights, int k,
+                      int max_iter, double* centroids, int32_t* assignment, int32_t* steps, hipStream_t s);
+
+// Rk-means step 3: the grid coreset over a join whose tuples a root row
+// determines (relations in breadth-first order from the root, each reached
+// from its parent through one key attribute)
+constexpr int kGridMaxWords = 8;     // 512 bits of packed cluster ids
+constexpr int kGridMaxRels = 8;
+constexpr int kGridMaxDims = 256;
+struct DGrid {
+  int64_t n_rows;                          // rows of the root relation
+  int32_t n_rels, n_dims, bits, n_words;
+  int32_t parent[kGridMaxRels];            // breadth-first parent of relation i
+  const int32_t* pkey[kGridMaxRels];       // the parent's column of the key reaching relation i
+  const int32_t* index[kGridMaxRels];      // key value -> row of relation i (-1: none)
+  int64_t index_n[kGridMaxRels];
+  const int32_t* col[kGridMaxDims];        // dimension d's column in relation rel[d]
+  int32_t rel[kGridMaxDims];
+  const int32_t* cluster[kGridMaxDims];    // cluster id of every value of dimension d
+  int64_t dom[kGridMaxDims];
+  unsigned long long* keys;                // fingerprint per slot (0: empty)
+  unsigned long long* cnt;
+  int32_t* rep;                            // a root row of the slot's group
+  int64_t mask;
+  int32_t* flag;                           // 1 fingerprint clash, 2 table full, 4 value outside a domain, 8 key twice
+};
+void launch_grid_index(const int32_t* key, int64_t n, int32_t* index, int64_t index_n, int32_t* flag,
+                       hipStream_t s);
+void launch_grid_count(const DGrid* d, int64_t n_rows, hipStream_t s);
+// present flags and positions of the slots (pos: slots + scan tiles + 1
+// values; the group count lands after the tile sums), then the groups
+void launch_grid_positions(const DGrid* d, int64_t slots, uint32_t* pos, hipStream_t s);
+void launch_grid_emit(const DGrid* d, int64_t slots, const uint32_t* pos, int64_t* keys_out, int64_t* cnt_out,
+                      hipStream_t s);
+void launch_code_table(const int64_t* codes, const int32_t* cluster, int64_t n, int32_t* table, int64_t dom,
+                       int32_t* flag, hipStream_t s);
+
 // exclusive scan of a[0..m) in place over many workgroups; bsum holds
 // scan_tiles(m) + 1 values and receives the tile offsets, then the total
 int64_t scan_tiles(int64_t m);

@@ -2887,6 +2887,193 @@ lmfao_status lmfao_tune(const lmfao_schema* schema, const lmfao_join_tree* tree,
   return LMFAO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Rk-means steps 2 and 3 (section 3, Rk-means)
+// ---------------------------------------------------------------------------
+lmfao_status lmfao_kmeans_1d(int32_t n_sets, const int64_t* offsets, const int64_t* values, const int64_t* weights,
+                             int32_t k, int32_t max_iter, double* centroids, int32_t* assignment, int32_t* steps,
+                             void* stream) {
+  g_last_error.clear();
+  if (n_sets < 0 || (n_sets && (!offsets || !centroids))) return set_err(LMFAO_EINVAL, "null argument");
+  if (k < 1 || k > kKmMaxClusters || max_iter < 0) return set_err(LMFAO_EINVAL, "k must be in [1, 64]");
+  for (int i = 0; i < n_sets; ++i)
+    if (offsets[i] < 0 || offsets[i + 1] < offsets[i]) return set_err(LMFAO_EINVAL, "offsets must not decrease");
+  if (n_sets && offsets[n_sets] > 0 && (!values || !weights || !assignment))
+    return set_err(LMFAO_EINVAL, "null values, weights or assignment");
+  if (n_sets == 0) return LMFAO_OK;
+  hipStream_t st = (hipStream_t)stream;
+  void* doff = nullptr;
+  void* dsteps = nullptr;
+  try {
+    HIP_OK(hipMalloc(&doff, (size_t)(n_sets + 1) * 8));
+    HIP_OK(hipMalloc(&dsteps, (size_t)n_sets * 4));
+    HIP_OK(hipMemcpyAsync(doff, offsets, (size_t)(n_sets + 1) * 8, hipMemcpyHostToDevice, st));
+    launch_kmeans_1d((const int64_t*)doff, n_sets, values, weights, k, max_iter, centroids, assignment,
+                     (int32_t*)dsteps, st);
+    HIP_OK(hipGetLastError());
+    std::vector<int32_t> hs(n_sets);
+    HIP_OK(hipMemcpyAsync(hs.data(), dsteps, (size_t)n_sets * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (steps) std::copy(hs.begin(), hs.end(), steps);
+  } catch (const HipError& e) {
+    (void)hipFree(doff);
+    (void)hipFree(dsteps);
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  (void)hipFree(doff);
+  (void)hipFree(dsteps);
+  return LMFAO_OK;
+}
+
+}  // extern "C"
+
+// breadth-first parents of the join tree from `root` (-1 for the root)
+static std::vector<int> bfs_parents(const lmfao::Plan& P, int root) {
+  std::vector<int> parent(P.rels.size(), -1), order{root};
+  std::vector<char> seen(P.rels.size(), 0);
+  seen[root] = 1;
+  for (size_t i = 0; i < order.size(); ++i)
+    for (int v : P.adj[order[i]])
+      if (!seen[v]) {
+        seen[v] = 1;
+        parent[v] = order[i];
+        order.push_back(v);
+      }
+  return parent;
+}
+
+extern "C" {
+
+lmfao_status lmfao_grid_coreset(lmfao_plan_t plan, lmfao_prepared_t prep, const void* const* const* columns,
+                                int32_t n_dims, const lmfao_grid_dim* dims, int32_t k, lmfao_output* out,
+                                void* stream) {
+  g_last_error.clear();
+  if (!plan || !prep || prep->P != plan->P || !columns || !out || n_dims < 1 || !dims)
+    return set_err(LMFAO_EINVAL, "null argument");
+  if (k < 1 || k > 256) return set_err(LMFAO_EINVAL, "k must be in [1, 256]");
+  const Plan& P = *prep->P;
+  const int n = (int)P.rels.size();
+  hipStream_t st = (hipStream_t)stream;
+  // the root: every other relation reached through one key attribute (the
+  // view toward the root is single-valued); the largest such relation
+  int root = -1;
+  for (int r = 0; r < n; ++r) {
+    const std::vector<int> parent = bfs_parents(P, r);
+    bool ok = true;
+    for (int u = 0; u < n && ok; ++u)
+      if (u != r) ok = P.uniq[u][parent[u]] && join_attrs(P, u, parent[u]).size() == 1;
+    if (ok && (root < 0 || P.rels[r].n_rows > P.rels[root].n_rows)) root = r;
+  }
+  if (root < 0) return set_err(LMFAO_EUNSUPPORTED, "the grid coreset needs a join whose tuples a root row determines");
+  if (n > kGridMaxRels) return set_err(LMFAO_EUNSUPPORTED, "more than 8 relations");
+  int bits = 1;
+  while ((1 << bits) < k) bits <<= 1;
+  if (k == 1) bits = 1;
+  const int words = (n_dims * bits + 63) / 64;
+  if (n_dims > kGridMaxDims || words > kGridMaxWords)
+    return set_err(LMFAO_EUNSUPPORTED, "more than 512 bits of packed cluster ids");
+  try {
+    Prep& S = *prep;
+    const std::vector<int> parent = bfs_parents(P, root);
+    std::vector<int> order{root};
+    for (size_t i = 0; i < order.size(); ++i)
+      for (int v : P.adj[order[i]])
+        if (v != parent[order[i]]) order.push_back(v);
+    std::vector<int> pos_of(n, -1);
+    for (int i = 0; i < n; ++i) pos_of[order[i]] = i;
+    int32_t* flag = (int32_t*)dalloc(S, 8);
+    HIP_OK(hipMemsetAsync(flag, 0, 8, st));
+    DGrid g{};
+    g.n_rows = P.rels[root].n_rows;
+    g.n_rels = n;
+    g.n_dims = n_dims;
+    g.bits = bits;
+    g.n_words = words;
+    g.flag = flag;
+    for (int i = 1; i < n; ++i) {
+      const int u = order[i], p = parent[u];
+      const int a = join_attrs(P, u, p)[0];
+      g.parent[i] = pos_of[p];
+      g.pkey[i] = (const int32_t*)columns[p][P.rels[p].col.at(a)];
+      g.index_n[i] = P.attrs[a].domain;
+      int32_t* idx = (int32_t*)dalloc(S, (size_t)std::max<int64_t>(g.index_n[i], 1) * 4);
+      HIP_OK(hipMemsetAsync(idx, 0xff, (size_t)std::max<int64_t>(g.index_n[i], 1) * 4, st));
+      launch_grid_index((const int32_t*)columns[u][P.rels[u].col.at(a)], P.rels[u].n_rows, idx, g.index_n[i], flag,
+                        st);
+      g.index[i] = idx;
+    }
+    for (int d = 0; d < n_dims; ++d) {
+      auto it = dims[d].attr ? P.attr_id.find(dims[d].attr) : P.attr_id.end();
+      if (it == P.attr_id.end()) return set_err(LMFAO_EINVAL, "unknown grid attribute");
+      const int a = it->second;
+      if (P.attrs[a].dtype != LMFAO_I32 || P.attrs[a].domain <= 0 || dims[d].n_codes < 0 ||
+          (dims[d].n_codes && (!dims[d].codes || !dims[d].cluster)))
+        return set_err(LMFAO_EINVAL, "grid attributes are integer attributes with a domain and a code list");
+      int rel = -1;
+      for (int i = 0; i < n && rel < 0; ++i)
+        if (P.rels[order[i]].has(a) && P.rels[order[i]].col.at(a) < P.rels[order[i]].n_input_attrs) rel = i;
+      if (rel < 0) return set_err(LMFAO_EINVAL, "grid attribute held by no relation");
+      g.rel[d] = rel;
+      g.col[d] = (const int32_t*)columns[order[rel]][P.rels[order[rel]].col.at(a)];
+      g.dom[d] = P.attrs[a].domain;
+      int32_t* table = (int32_t*)dalloc(S, (size_t)g.dom[d] * 4);
+      HIP_OK(hipMemsetAsync(table, 0, (size_t)g.dom[d] * 4, st));
+      launch_code_table(dims[d].codes, dims[d].cluster, dims[d].n_codes, table, g.dom[d], flag, st);
+      g.cluster[d] = table;
+    }
+    // at most one group per root row and k^n id vectors; half occupancy
+    double bound = (double)std::max<int64_t>(g.n_rows, 1);
+    bound = std::min(bound, std::pow((double)k, (double)n_dims));
+    int64_t cap = 1024;
+    while ((double)cap < 2.0 * bound) cap <<= 1;
+    for (int attempt = 0;; ++attempt) {
+      g.mask = cap - 1;
+      g.keys = (unsigned long long*)dalloc(S, (size_t)cap * 8);
+      g.cnt = (unsigned long long*)dalloc(S, (size_t)cap * 8);
+      g.rep = (int32_t*)dalloc(S, (size_t)cap * 4);
+      HIP_OK(hipMemsetAsync(g.keys, 0, (size_t)cap * 8, st));
+      HIP_OK(hipMemsetAsync(g.cnt, 0, (size_t)cap * 8, st));
+      DGrid* dg = upload(S, g, st);
+      launch_grid_count(dg, g.n_rows, st);
+      HIP_OK(hipGetLastError());
+      int32_t f = 0;
+      HIP_OK(hipMemcpyAsync(&f, flag, 4, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      if (f & 8) return set_err(LMFAO_EINVAL, "a key value held by two rows of a relation");
+      if (f & 4) return set_err(LMFAO_EINVAL, "a value outside its domain, or a cluster id past k");
+      if (f & 2) {
+        if (attempt >= 2) return set_err(LMFAO_EOVERFLOW, "grid coreset table full");
+        cap <<= 2;
+        HIP_OK(hipMemsetAsync(flag, 0, 4, st));
+        continue;
+      }
+      if (f & 1) return set_err(LMFAO_EUNSUPPORTED, "two grid points share a 64-bit fingerprint");
+      uint32_t* posv = (uint32_t*)dalloc(S, (size_t)(cap + scan_tiles(cap) + 1) * 4);
+      launch_grid_positions(dg, cap, posv, st);
+      uint32_t ng = 0;
+      HIP_OK(hipMemcpyAsync(&ng, posv + cap + scan_tiles(cap), 4, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      int64_t* kout = (int64_t*)dalloc(S, (size_t)std::max<int64_t>((int64_t)ng * n_dims, 1) * 8);
+      int64_t* cout_ = (int64_t*)dalloc(S, (size_t)std::max<uint32_t>(ng, 1) * 8);
+      launch_grid_emit(dg, cap, posv, kout, cout_, st);
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipStreamSynchronize(st));
+      out->n_groups = ng;
+      out->n_keys = n_dims;
+      out->n_aggs = 0;
+      out->keys = kout;
+      out->counts = cout_;
+      out->values = nullptr;
+      break;
+    }
+  } catch (const PlanError& e) {
+    return set_err(e.status, e.msg);
+  } catch (const HipError& e) {
+    return set_err(LMFAO_EHIP, e.msg);
+  }
+  return LMFAO_OK;
+}
+
 lmfao_status lmfao_row_weights(lmfao_prepared_t prep, int32_t rel, int32_t** weights) {
   g_last_error.clear();
   if (!prep || !weights) return set_err(LMFAO_EINVAL, "null argument");

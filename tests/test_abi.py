@@ -71,7 +71,7 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("no C compiler")
     names = ["lmfao_attr", "lmfao_relation", "lmfao_schema", "lmfao_edge", "lmfao_join_tree", "lmfao_factor",
              "lmfao_aggregate", "lmfao_condition", "lmfao_query", "lmfao_function", "lmfao_batch", "lmfao_options",
-             "lmfao_output", "lmfao_column_condition", "lmfao_cart_candidate", "lmfao_cart_spec", "lmfao_cart_split",
+             "lmfao_output", "lmfao_grid_dim", "lmfao_column_condition", "lmfao_cart_candidate", "lmfao_cart_spec", "lmfao_cart_split",
              "lmfao_cart_node"]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lmfao.h"', "int main(void) {"]
     for n in names:
