@@ -273,9 +273,11 @@ def marshal_problem(problem, keep: _Keep):
 def build_options(problem, keep, precision="f64", policy=None, form="fused", order=None,
                   min_segment=0, row_piece_max=0, contraction="mfma", codegen=True, hash_slots=0,
                   sizing="bound", estimator=None, graph=False, one_hot_max=0, scan_blocks=0,
-                  contract_splits=0, partition=True, row_weights=()):
-    """Keyword options -> ``lmfao_options`` (buffers it points to kept in ``keep``)."""
-    lib = load_library()
+                  contract_splits=0, partition=True, row_weights=(), lib=None):
+    """Keyword options -> ``lmfao_options`` (buffers it points to kept in
+    ``keep``); ``lib`` is the library whose ``lmfao_default_options`` fills
+    the defaults (this package's by default)."""
+    lib = lib if lib is not None else load_library()
     opts = lmfao_options()
     lib.lmfao_default_options(C.byref(opts))
     if precision not in ("f64", "f32", "bf16x3", "bf16x2"):

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblmfao.so")
 
-SOURCES = ["planner.cpp", "runtime.hip", "kernels.hip", "codegen.hip", "mlp.hip", "rkmeans.hip"]
+SOURCES = ["planner.cpp", "plan_abi.cpp", "runtime.hip", "kernels.hip", "codegen.hip", "mlp.hip", "rkmeans.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -29,7 +29,8 @@ def _flags(src):
         flags += ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
                   "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
     else:
-        flags += ["-x", "c++"]
+        # host-only C++ (the planner and the plan ABI): warnings are errors
+        flags += ["-x", "c++", "-Werror"]
     return flags
 
 

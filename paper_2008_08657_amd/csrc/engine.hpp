@@ -308,8 +308,9 @@ struct PlanError {
 Plan* build_plan(const lmfao_schema* schema, const lmfao_join_tree* tree,
                  const lmfao_batch* batch, const lmfao_options* opts);
 
-// sets the thread-local text lmfao_last_error() returns
+// sets (clears) the thread-local text lmfao_last_error() returns
 void record_error(const std::string& msg);
+void clear_error();
 
 std::vector<int> join_attrs(const Plan& P, int a, int b);
 
@@ -485,6 +486,8 @@ struct DHashOut {
   int64_t mask;                    // capacity - 1 (power of two)
   int32_t* ovf;                    // set when an insert found no slot
   int32_t n_vals, pad;
+  uint32_t* used;                  // tables written by the partition count: the groups each region
+                                   // received at the last run (its slots past them are zero); else null
 };
 
 struct DContract {
@@ -551,3 +554,8 @@ struct DCell {
 };
 
 }  // namespace lmfao
+
+// the opaque handle behind lmfao_plan_t
+struct lmfao_plan_s {
+  lmfao::Plan* P = nullptr;
+};

@@ -2896,9 +2896,12 @@ __global__ void k_part_reduce(const DPartCount* __restrict__ Dp) {
 // sub-groups in an LDS hash table of its own (512 slots; no workgroup
 // barrier between sub-groups) and writes their (cell, count) pairs to the
 // group's own region of the output's table (cap / 512 slots, positions from
-// an LDS counter: no global atomics); the region's other slots are cleared,
-// so the table needs no fill.  A full LDS table or a full region sets the
-// table's overflow flag (the run is repeated with a larger table).
+// an LDS counter: no global atomics).  The region's slots past its groups
+// stay zero: the table is cleared once when allocated, and each run clears
+// only the slots the previous run filled past this run's groups (the group
+// count per region is kept beside the table; it also sizes a regrowth).  A
+// full LDS table or a full region sets the table's overflow flag (the run is
+// repeated with a larger table).
 constexpr int kPartWaveSlots = 512;
 constexpr int kPartHashWaves = 16;
 constexpr int kPartSubCells = 192;
@@ -2923,7 +2926,11 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
   const uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
   const int64_t s0 = bs[b], s1 = bs[b + 1];
   const int lane = (int)__lane_id(), wid = threadIdx.x >> 6;
-  if (threadIdx.x == 0) cursor[kPartMaxSub] = 0;
+  __shared__ uint32_t sh_prev;   // groups the last run left in this region (only thread 0 touches the record)
+  if (threadIdx.x == 0) {
+    cursor[kPartMaxSub] = 0;
+    sh_prev = H.used ? H.used[b] : 0xffffffffu;
+  }
   int S = 1, sbits = 0;
   while (S < kPartMaxSub && (int64_t)S * kPartSubCells < s1 - s0) {
     S <<= 1;
@@ -3016,9 +3023,14 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
     }
   }
   __syncthreads();
-  // the region's remaining slots hold no group
-  const int64_t used = min((int64_t)cursor[kPartMaxSub], region);
-  for (int64_t i = used + threadIdx.x; i < region; i += blockDim.x) H.keys[region0 + i] = 0ull;
+  // the region's slots past this run's groups hold none: the table was
+  // cleared when it was allocated, so only the slots the last run filled
+  // beyond them are cleared (every slot, for a table without the record)
+  const int64_t total = (int64_t)cursor[kPartMaxSub];
+  const int64_t used = min(total, region);
+  const int64_t prev = min((int64_t)sh_prev, region);
+  for (int64_t i = used + threadIdx.x; i < prev; i += blockDim.x) H.keys[region0 + i] = 0ull;
+  if (H.used && threadIdx.x == 0) H.used[b] = (uint32_t)total;
 }
 
 constexpr int kPartTileDense = 16384;

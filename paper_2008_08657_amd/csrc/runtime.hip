@@ -21,10 +21,6 @@
 
 namespace lmfao {
 
-static thread_local std::string g_last_error;
-
-void record_error(const std::string& msg) { g_last_error = msg; }
-
 struct HipError {
   std::string msg;
 };
@@ -62,7 +58,8 @@ struct HashBuf {
   double* vals = nullptr;
   int n_vals = 0;
   int fill_step = -1;              // index of its zeroing steps (keys, cnt, vals); -1: none
-  bool counts_only = false;        // written whole by the partition count; every value is the count
+  bool counts_only = false;        // written by the partition count; every value is the count
+  uint32_t* used = nullptr;        // counts-only tables: groups per region at the last run
   std::vector<int> count_copies;   // value columns equal to the count (SUM(1))
 };
 
@@ -126,9 +123,6 @@ struct Compacted {
 
 }  // namespace lmfao
 
-struct lmfao_plan_s {
-  lmfao::Plan* P = nullptr;
-};
 
 struct lmfao_prepared_s {
   lmfao::Plan* P = nullptr;
@@ -1855,8 +1849,10 @@ constexpr int64_t kHashInitSlots = (int64_t)1 << 26;
 // (re)allocates the slots of a hash table for H.cap slots.  The new arrays
 // are allocated first; the old ones are released only once all three exist,
 // so a failed allocation leaves the table as it was (H.cap restored) and
-// throws PlanError{LMFAO_ENOMEM}.
-static void alloc_hash(Prep& S, HashBuf& H, int64_t old_cap = 0) {
+// throws PlanError{LMFAO_ENOMEM}.  A counts-only table is cleared here, on
+// the stream, once: the partition count then keeps every slot past each
+// region's groups at zero by clearing only what the previous run left there.
+static void alloc_hash(Prep& S, HashBuf& H, hipStream_t st, int64_t old_cap = 0) {
   void* fresh[3] = {nullptr, nullptr, nullptr};
   // a counts-only table's values are never read (they are its counts)
   const size_t bytes[3] = {(size_t)H.cap * 8, (size_t)H.cap * 8,
@@ -1876,6 +1872,12 @@ static void alloc_hash(Prep& S, HashBuf& H, int64_t old_cap = 0) {
   H.keys = (unsigned long long*)fresh[0];
   H.cnt = (int64_t*)fresh[1];
   H.vals = (double*)fresh[2];
+  if (H.counts_only) {
+    if (!H.used) H.used = (uint32_t*)dalloc(S, kPartHashBuckets * 4);
+    launch_fill(H.keys, H.cap * 8, st);
+    launch_fill(H.used, kPartHashBuckets * 4, st);
+    HIP_OK(hipGetLastError());
+  }
 }
 
 static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_t st) {
@@ -2067,14 +2069,14 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
       // pass (every slot, groups or empty), and their values are the counts
       const QueryDef& QH = P.queries[H.query];
       H.counts_only = QH.group >= 0 && P.groups[QH.group].partitioned;
-      alloc_hash(S, H);
+      alloc_hash(S, H, st);
       if (!H.counts_only) {
         H.fill_step = (int)S.steps.size();
         add_fill(S, H.keys, H.cap * 8, "hash keys");
         add_fill(S, H.cnt, H.cap * 8, "hash counts");
         add_fill(S, H.vals, H.cap * 8 * std::max(1, H.n_vals), "hash values");
       }
-      hd[i] = DHashOut{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0};
+      hd[i] = DHashOut{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0, H.used};
     }
     S.hash_dev = upload_vec(S, hd, st);
   }
@@ -2236,57 +2238,11 @@ static void enqueue_run(Prep& S, hipStream_t st) {
 using namespace lmfao;
 
 static lmfao_status set_err(lmfao_status st, const std::string& m) {
-  g_last_error = m;
+  record_error(m);
   return st;
 }
 
 extern "C" {
-
-void lmfao_default_options(lmfao_options* o) {
-  if (!o) return;
-  std::memset(o, 0, sizeof(*o));
-  o->precision = LMFAO_PREC_F64;
-  o->form = LMFAO_FORM_FUSED;
-  o->root_policy = LMFAO_ROOT_GROUPBY;
-  o->n_order = nullptr;
-  o->order = nullptr;
-  o->min_segment = 0;
-}
-
-lmfao_status lmfao_plan(const lmfao_schema* schema, const lmfao_join_tree* tree, const lmfao_batch* batch,
-                        const lmfao_options* opts, lmfao_plan_t* out) {
-  g_last_error.clear();
-  if (!out) return set_err(LMFAO_EINVAL, "null output handle");
-  *out = nullptr;
-  try {
-    Plan* P = build_plan(schema, tree, batch, opts);
-    if (!P->supported) {
-      std::string why = P->unsupported_reason;
-      delete P;
-      return set_err(LMFAO_EUNSUPPORTED, why);
-    }
-    lmfao_plan_s* h = new lmfao_plan_s;
-    h->P = P;
-    *out = h;
-    return LMFAO_OK;
-  } catch (const PlanError& e) {
-    return set_err(e.status, e.msg);
-  } catch (const std::exception& e) {
-    return set_err(LMFAO_EINVAL, e.what());
-  }
-}
-
-lmfao_status lmfao_plan_describe(lmfao_plan_t plan, char* buf, size_t cap, size_t* need) {
-  if (!plan) return set_err(LMFAO_EINVAL, "null plan");
-  const std::string& j = plan->P->json;
-  if (need) *need = j.size() + 1;
-  if (buf && cap) {
-    size_t n = std::min(cap - 1, j.size());
-    std::memcpy(buf, j.data(), n);
-    buf[n] = 0;
-  }
-  return LMFAO_OK;
-}
 
 lmfao_status lmfao_plan_workspace_bytes(lmfao_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return set_err(LMFAO_EINVAL, "null argument");
@@ -2316,7 +2272,7 @@ static const OutBuf& user_out(const lmfao_prepared_s* prep, int q, int* n_keys);
 
 static lmfao_status prepare_impl(lmfao_plan_t plan, const void* const* const* columns, void* workspace,
                                  size_t ws_bytes, void* stream, lmfao_prepared_t* out) {
-  g_last_error.clear();
+  clear_error();
   if (!plan || !columns || !out) return set_err(LMFAO_EINVAL, "null argument");
   *out = nullptr;
   std::unique_ptr<lmfao_prepared_s> S(new lmfao_prepared_s);
@@ -2354,7 +2310,7 @@ lmfao_status lmfao_prepare_in(lmfao_plan_t plan, const void* const* const* colum
 }
 
 lmfao_status lmfao_prepared_workspace_bytes(lmfao_prepared_t prep, int32_t with_results, size_t* bytes) {
-  g_last_error.clear();
+  clear_error();
   if (!prep || !bytes) return set_err(LMFAO_EINVAL, "null argument");
   size_t b = prep->ws_prepared;
   if (with_results) {
@@ -2388,11 +2344,11 @@ lmfao_status lmfao_prepared_workspace_bytes(lmfao_prepared_t prep, int32_t with_
 // table is already at its largest size.
 // Reallocates hash table i at `cap` slots and points the run's fill steps and
 // the table's device descriptor at the new arrays.
-static void resize_hash(Prep& S, size_t i, int64_t cap) {
+static void resize_hash(Prep& S, size_t i, int64_t cap, hipStream_t st) {
   HashBuf& H = S.hashes[i];
   const int64_t old_cap = H.cap;
   H.cap = cap;
-  alloc_hash(S, H, old_cap);
+  alloc_hash(S, H, st, old_cap);
   if (H.fill_step >= 0) {
     S.steps[H.fill_step].dev = H.keys;
     S.steps[H.fill_step].bytes = H.cap * 8;
@@ -2401,8 +2357,9 @@ static void resize_hash(Prep& S, size_t i, int64_t cap) {
     S.steps[H.fill_step + 2].dev = H.vals;
     S.steps[H.fill_step + 2].bytes = H.cap * 8 * std::max(1, H.n_vals);
   }
-  DHashOut d{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0};
-  HIP_OK(hipMemcpy(S.hash_dev + i, &d, sizeof d, hipMemcpyHostToDevice));
+  DHashOut d{H.keys, H.cnt, H.vals, H.cap - 1, S.hash_ovf + i, H.n_vals, 0, H.used};
+  HIP_OK(hipMemcpyAsync(S.hash_dev + i, &d, sizeof d, hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
 }
 
 static int64_t bound_capacity(const HashBuf& H) {
@@ -2418,9 +2375,24 @@ static bool grow_hashes(Prep& S, hipStream_t st) {
   for (size_t i = 0; i < S.hashes.size(); ++i) {
     if (!ovf[i]) continue;
     HashBuf& H = S.hashes[i];
+    if (H.used) {
+      // a table of the partition count knows how many groups each of its
+      // regions received (also past a full region): the smallest power-of-two
+      // region that holds the largest one
+      std::vector<uint32_t> u(kPartHashBuckets);
+      HIP_OK(hipMemcpy(u.data(), H.used, u.size() * 4, hipMemcpyDeviceToHost));
+      const int64_t need = *std::max_element(u.begin(), u.end());
+      int64_t region = 1;
+      while (region < need) region <<= 1;
+      // no larger region needed: the overflow was not a full region
+      if (region * kPartHashBuckets <= H.cap) return false;
+      resize_hash(S, i, region * kPartHashBuckets, st);
+      grown = true;
+      continue;
+    }
     const int64_t top = bound_capacity(H);
     if (H.cap >= top) return false;
-    resize_hash(S, i, std::min(H.cap * 4, top));
+    resize_hash(S, i, std::min(H.cap * 4, top), st);
     grown = true;
   }
   return grown;
@@ -2453,7 +2425,7 @@ static void exact_sizes(Prep& S, hipStream_t st) {
     H.est = (double)groups[i];
     int64_t cap = 1024;
     while (cap < 2 * (int64_t)groups[i]) cap <<= 1;
-    if (cap != H.cap) resize_hash(S, i, cap);
+    if (cap != H.cap) resize_hash(S, i, cap, st);
   }
 }
 
@@ -2513,7 +2485,7 @@ static lmfao_status flag_status(int32_t flag) {
 }
 
 lmfao_status lmfao_run(lmfao_plan_t plan, lmfao_prepared_t prep, void* stream, int32_t sync) {
-  g_last_error.clear();
+  clear_error();
   if (!plan || !prep || prep->P != plan->P) return set_err(LMFAO_EINVAL, "plan and prepared handle do not match");
   hipStream_t st = (hipStream_t)stream;
   prep->run_epoch++;
@@ -2685,7 +2657,7 @@ static lmfao_status compact_result(lmfao_prepared_s* prep, int q, hipStream_t st
 extern "C" {
 
 lmfao_status lmfao_result_device(lmfao_prepared_t prep, int32_t q, lmfao_output* out, void* stream) {
-  g_last_error.clear();
+  clear_error();
   if (!prep || !out || q < 0 || q >= (int)prep->P->user.size()) return set_err(LMFAO_EINVAL, "bad query index");
   if (lmfao_status e = compact_result(prep, q, (hipStream_t)stream)) return e;
   const Compacted& C = prep->compact[q];
@@ -2794,7 +2766,7 @@ extern "C" {
 lmfao_status lmfao_tune(const lmfao_schema* schema, const lmfao_join_tree* tree, const lmfao_batch* batch,
                         lmfao_options* opts, const void* const* const* columns, const char* cache_path,
                         int32_t runs, double* best_ms, double* base_ms, void* stream) {
-  g_last_error.clear();
+  clear_error();
   if (!schema || !tree || !batch || !opts || !columns) return set_err(LMFAO_EINVAL, "null argument");
   if (runs <= 0) runs = 5;
   hipStream_t st = (hipStream_t)stream;
@@ -2893,7 +2865,7 @@ lmfao_status lmfao_tune(const lmfao_schema* schema, const lmfao_join_tree* tree,
 lmfao_status lmfao_kmeans_1d(int32_t n_sets, const int64_t* offsets, const int64_t* values, const int64_t* weights,
                              int32_t k, int32_t max_iter, double* centroids, int32_t* assignment, int32_t* steps,
                              void* stream) {
-  g_last_error.clear();
+  clear_error();
   if (n_sets < 0 || (n_sets && (!offsets || !centroids))) return set_err(LMFAO_EINVAL, "null argument");
   if (k < 1 || k > kKmMaxClusters || max_iter < 0) return set_err(LMFAO_EINVAL, "k must be in [1, 64]");
   for (int i = 0; i < n_sets; ++i)
@@ -2947,7 +2919,7 @@ extern "C" {
 lmfao_status lmfao_grid_coreset(lmfao_plan_t plan, lmfao_prepared_t prep, const void* const* const* columns,
                                 int32_t n_dims, const lmfao_grid_dim* dims, int32_t k, lmfao_output* out,
                                 void* stream) {
-  g_last_error.clear();
+  clear_error();
   if (!plan || !prep || prep->P != plan->P || !columns || !out || n_dims < 1 || !dims)
     return set_err(LMFAO_EINVAL, "null argument");
   if (k < 1 || k > 256) return set_err(LMFAO_EINVAL, "k must be in [1, 256]");
@@ -3075,7 +3047,7 @@ lmfao_status lmfao_grid_coreset(lmfao_plan_t plan, lmfao_prepared_t prep, const 
 }
 
 lmfao_status lmfao_row_weights(lmfao_prepared_t prep, int32_t rel, int32_t** weights) {
-  g_last_error.clear();
+  clear_error();
   if (!prep || !weights) return set_err(LMFAO_EINVAL, "null argument");
   if (rel < 0 || rel >= (int)prep->row_w.size() || !prep->row_w[rel])
     return set_err(LMFAO_EINVAL, "relation without row weights (lmfao_options.row_weights)");
@@ -3085,7 +3057,7 @@ lmfao_status lmfao_row_weights(lmfao_prepared_t prep, int32_t rel, int32_t** wei
 
 lmfao_status lmfao_eval_conditions(int64_t n_rows, int32_t n_conds, const lmfao_column_condition* conds,
                                    int32_t* out, void* stream) {
-  g_last_error.clear();
+  clear_error();
   if (n_rows < 0 || n_conds < 0 || (n_conds && !conds) || (n_rows && !out)) return set_err(LMFAO_EINVAL, "bad argument");
   if (n_conds > kMaxFilterConds) return set_err(LMFAO_EINVAL, "more than 8 conditions");
   DFilter f{};
@@ -3192,7 +3164,7 @@ extern "C" {
 
 lmfao_status lmfao_cart_best_split(lmfao_prepared_t prep, const lmfao_cart_spec* spec, lmfao_cart_split* out,
                                    double* costs, void* stream) {
-  g_last_error.clear();
+  clear_error();
   if (!prep || !out) return set_err(LMFAO_EINVAL, "null argument");
   std::vector<const void*> ptrs;
   if (lmfao_status e = cart_inputs(prep, spec, ptrs)) return e;
@@ -3203,7 +3175,7 @@ lmfao_status lmfao_cart_best_split(lmfao_prepared_t prep, const lmfao_cart_spec*
 lmfao_status lmfao_cart_grow(lmfao_plan_t plan, lmfao_prepared_t prep, const void* const* const* columns,
                              const lmfao_cart_spec* spec, lmfao_cart_node* nodes, int32_t cap, int32_t* n_nodes,
                              void* stream) {
-  g_last_error.clear();
+  clear_error();
   if (!plan || !prep || prep->P != plan->P || !columns || !nodes || !n_nodes || cap < 1)
     return set_err(LMFAO_EINVAL, "null argument");
   std::vector<const void*> ptrs;
@@ -3292,7 +3264,7 @@ lmfao_status lmfao_cart_grow(lmfao_plan_t plan, lmfao_prepared_t prep, const voi
 }
 lmfao_status lmfao_ridge_sigma(lmfao_prepared_t prep, int32_t n_cont, const char* const* cont, int32_t n_cat,
                                const char* const* cat, double* sigma, int32_t* dim_out, void* stream) {
-  g_last_error.clear();
+  clear_error();
   if (!prep || n_cont < 0 || n_cat < 0 || (n_cont && !cont) || (n_cat && !cat))
     return set_err(LMFAO_EINVAL, "null argument");
   const Plan& P = *prep->P;
@@ -3382,7 +3354,7 @@ lmfao_status lmfao_ridge_sigma(lmfao_prepared_t prep, int32_t n_cont, const char
 
 lmfao_status lmfao_ridge_bgd(const double* sigma, int32_t dim, int32_t label, double lambda, double eta,
                              int32_t max_iter, double tol, double* theta, double* stats, void* stream) {
-  g_last_error.clear();
+  clear_error();
   if (!sigma || !theta || !stats) return set_err(LMFAO_EINVAL, "null argument");
   if (dim < 2 || dim > kRidgeMaxDim || label < 0 || label >= dim || max_iter < 0 || !(lambda >= 0))
     return set_err(LMFAO_EINVAL, "bad dimension, label, iteration count or lambda");
@@ -3578,14 +3550,7 @@ lmfao_status lmfao_prepared_describe(lmfao_prepared_t prep, char* buf, size_t ca
   return LMFAO_OK;
 }
 
-void lmfao_plan_free(lmfao_plan_t plan) {
-  if (!plan) return;
-  delete plan->P;
-  delete plan;
-}
-
 void lmfao_prepared_free(lmfao_prepared_t prep) { delete prep; }
 
-const char* lmfao_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

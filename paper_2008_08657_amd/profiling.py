@@ -1,7 +1,11 @@
 """Summaries of rocprofv3 output for the benchmark's kernels.
 
 ``summarize``: a Markdown table of the kernel-trace statistics
-(``*_kernel_stats.csv``) with the command that produced them.
+(``*_kernel_stats.csv``) with the command that produced them; with
+``--dispatches`` and ``--last N``, also the mean duration of the last N
+launches of each named kernel (the launches of ``bench.py``'s timed region,
+after the prepare, warm-up and checked runs), read from the per-dispatch
+trace (``*_kernel_trace.csv``).
 
 ``traffic``: HBM bytes per launch of one kernel from two counter runs
 (``FETCH_SIZE`` and ``WRITE_SIZE``, KiB per dispatch), each scaled by what the
@@ -47,8 +51,8 @@ def _counter_rows(path, counter):
                 yield row["Kernel_Name"], float(row["Counter_Value"])
 
 
-def mean_counter(path, counter, kernel):
-    vals = [v for k, v in _counter_rows(path, counter) if k == kernel]
+def mean_counter(path, counter, kernel, skip=0):
+    vals = [v for k, v in _counter_rows(path, counter) if k == kernel][skip:]
     if not vals:
         raise SystemExit(f"{path}: no {counter} rows for kernel {kernel}")
     return sum(vals) / len(vals), len(vals)
@@ -63,14 +67,14 @@ def copy_counter(path, counter):
 
 
 def traffic(a):
-    f_kib, nf = mean_counter(a.fetch, "FETCH_SIZE", a.kernel)
-    w_kib, nw = mean_counter(a.write, "WRITE_SIZE", a.kernel)
+    f_kib, nf = mean_counter(a.fetch, "FETCH_SIZE", a.kernel, a.skip)
+    w_kib, nw = mean_counter(a.write, "WRITE_SIZE", a.kernel, a.skip)
     cf = copy_counter(a.copy_fetch, "FETCH_SIZE")
     cw = copy_counter(a.copy_write, "WRITE_SIZE")
     f_scale = a.copy_bytes / (cf * 1024.0)
     w_scale = a.copy_bytes / (cw * 1024.0)
     rec = {"workload": a.workload, "kernel": a.kernel, "step": a.step, "source_digest": a.source_digest,
-           "fetch_kib": f_kib, "write_kib": w_kib, "dispatches": [nf, nw],
+           "fetch_kib": f_kib, "write_kib": w_kib, "dispatches": [nf, nw], "skipped_first": a.skip,
            "copy_bytes": a.copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": f_scale, "write_scale": w_scale,
            "bytes_read": f_kib * 1024.0 * f_scale, "bytes_written": w_kib * 1024.0 * w_scale,
@@ -111,10 +115,29 @@ def summarize(a):
         name = r["Name"] if len(r["Name"]) < 90 else r["Name"][:87] + "..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if a.dispatches and a.last > 0 and a.kernel:
+        lines += ["", f"Last {a.last} launches of each kernel below (the timed steps), from the per-dispatch trace:",
+                  "", "| kernel | launches | average us | min us | max us |", "|---|---:|---:|---:|---:|"]
+        for k in a.kernel:
+            d = last_launches(a.dispatches, k, a.last)
+            if d:
+                lines.append(f"| `{k}` | {len(d)} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} |")
     if a.note:
         lines += ["", *a.note]
     with open(a.out, "w") as f:
         f.write("\n".join(lines) + "\n")
+
+
+def last_launches(path, kernel, n):
+    """Durations (us) of the last n launches of the kernel whose name starts
+    with ``kernel``, in dispatch order."""
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Kernel_Name"].startswith(kernel):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    rows.sort()
+    return [(e - s) / 1e3 for s, e in rows[-n:]]
 
 
 def main(argv=None):
@@ -125,12 +148,18 @@ def main(argv=None):
         t.add_argument("--" + k.replace("_", "-"), required=True)
     t.add_argument("--source-digest", required=True)
     t.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    # dispatches left out at the start (a first run into a table that is
+    # regrown afterwards has a different size from the timed runs')
+    t.add_argument("--skip", type=int, default=0)
     t.add_argument("--command", action="append", default=[])
     s = sub.add_parser("summarize")
     s.add_argument("--trace", required=True)
     s.add_argument("--out", required=True)
     s.add_argument("--title", required=True)
     s.add_argument("--top", type=int, default=25)
+    s.add_argument("--dispatches", default=None)
+    s.add_argument("--last", type=int, default=0)
+    s.add_argument("--kernel", action="append", default=[])
     s.add_argument("--command", action="append", default=[])
     s.add_argument("--note", action="append", default=[])
     c = sub.add_parser("counters")
