@@ -2613,6 +2613,39 @@ __device__ __forceinline__ void part_load_cells(const DPartCount& D, int o, int3
   }
 }
 
+// The weights of the same rows for a weighted output: the product of the
+// counts of the output's multiplicity views per row (0 where the cell is
+// -1), loads issued together; a product of 2^32 or more sets `big` (the
+// partition count's LDS tables hold 32-bit counts).
+template <int U, typename C>
+__device__ __forceinline__ void part_load_weights(const DPartCount& D, int o, int32_t first, int32_t stride,
+                                                  int32_t r_end, const C (&cell)[U], uint32_t (&wt)[U], bool& big) {
+  const int32_t last = r_end - 1;
+  uint64_t p[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) p[u] = 1;
+  const uint32_t m = D.vmask[o] & D.vmult;
+#pragma unroll
+  for (int v = 0; v < kPartViews; ++v) {
+    if (!((m >> v) & 1u)) continue;
+    const uint32_t* wv = D.wv[v];
+    uint32_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t r = first + u * stride;
+      x[u] = wv[r < r_end ? r : last];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t q = p[u] * x[u];   // both factors below 2^32: no 64-bit overflow
+      big |= cell[u] >= 0 && q > 0xffffffffull;
+      p[u] = q > 0xffffffffull ? 0xffffffffull : q;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) wt[u] = cell[u] >= 0 ? (uint32_t)p[u] : 0u;
+}
+
 // bits of a cell for the hashed outputs' grouping (a 64-bit finalising mix)
 __device__ __forceinline__ uint64_t part_mix(uint64_t x) {
   x ^= x >> 30;
@@ -2624,7 +2657,8 @@ __device__ __forceinline__ uint64_t part_mix(uint64_t x) {
 }
 
 // pass 0: the per-row byte (bit 0 filter weight, bits 1.. the views' 0/1
-// counts) for every later pass, and zero slice totals
+// counts) for every later pass, the counts of multiplicity views, and zero
+// slice totals
 __global__ void __launch_bounds__(256) k_part_w8(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
   if (blockIdx.x == 0)
@@ -2634,6 +2668,15 @@ __global__ void __launch_bounds__(256) k_part_w8(const DPartCount* __restrict__ 
     PartRow R;
     part_row(D, row, R);
     D.w8[row] = (uint8_t)((R.w ? 1u : 0u) | (R.vok << 1));
+    // the counts of the views with several tuples per key (weights of the
+    // weighted outputs; a key outside the view counts 0)
+    for (int v = 0; v < D.n_views; ++v) {
+      if (!((D.vmult >> v) & 1u)) continue;
+      const int64_t k = part_vrow(R, v);
+      const int64_t c = k >= 0 && k < D.vnkeys[v] ? D.vcnt[v][k] : 0;
+      if (c > (int64_t)0xffffffff) atomicOr(D.err_flag, 16);
+      D.wv[v][row] = c <= 0 ? 0u : c > (int64_t)0xffffffff ? 0xffffffffu : (uint32_t)c;
+    }
   }
 }
 
@@ -2653,27 +2696,41 @@ __device__ __forceinline__ void part_flush(const DPartCount& D, int o, int c, in
 
 // pass 1a, tables of one slice: workgroup (chunk, output) counts the chunk's
 // rows in LDS; every thread keeps kPartDirectUnroll rows' loads in flight
+// (W: the weighted outputs, each row adding its weight)
+template <bool W>
 __global__ void __launch_bounds__(kPartCountThreads) k_part_direct(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
   const int o = blockIdx.y, c = blockIdx.x;
-  if (o >= D.n_out || D.hashed[o] || D.n_buckets[o] != 1 || c >= D.chunks[o]) return;
+  if (o >= D.n_out || D.hashed[o] || D.n_buckets[o] != 1 || c >= D.chunks[o] || (D.weighted[o] != 0) != W) return;
   extern __shared__ uint32_t bins[];
+  __shared__ unsigned long long wsum;
   for (int i = threadIdx.x; i < kPartSlice; i += blockDim.x) bins[i] = 0;
+  if (threadIdx.x == 0) wsum = 0;
   __syncthreads();
   const int64_t per = (D.n_rows + D.chunks[o] - 1) / D.chunks[o];
   const int64_t r0 = (int64_t)c * per, r1 = min(D.n_rows, r0 + per);
   const int64_t step = (int64_t)kPartDirectUnroll * blockDim.x;
-  bool bad = false;
+  bool bad = false, big = false;
+  uint64_t mine = 0;
   for (int64_t base = r0; base < r1; base += step) {
     int32_t cell[kPartDirectUnroll];
-    part_load_cells<kPartDirectUnroll>(D, o, (int32_t)base + (int32_t)threadIdx.x, (int32_t)blockDim.x, (int32_t)r1,
-                                       cell, bad);
+    const int32_t first = (int32_t)base + (int32_t)threadIdx.x;
+    part_load_cells<kPartDirectUnroll>(D, o, first, (int32_t)blockDim.x, (int32_t)r1, cell, bad);
+    uint32_t wt[kPartDirectUnroll];
+    if (W) part_load_weights<kPartDirectUnroll>(D, o, first, (int32_t)blockDim.x, (int32_t)r1, cell, wt, big);
 #pragma unroll
     for (int u = 0; u < kPartDirectUnroll; ++u)
-      if (cell[u] >= 0) atomicAdd(&bins[cell[u]], 1u);
+      if (cell[u] >= 0) {
+        atomicAdd(&bins[cell[u]], W ? wt[u] : 1u);
+        if (W) mine += wt[u];
+      }
   }
   if (bad) atomicOr(D.err_flag, 2);
+  if (W && mine) atomicAdd(&wsum, (unsigned long long)mine);
   __syncthreads();
+  // a 32-bit LDS count may have wrapped: reported, not returned wrong
+  if (W && threadIdx.x == 0 && wsum > 0xffffffffull) atomicOr(D.err_flag, 16);
+  if (W && big) atomicOr(D.err_flag, 16);
   part_flush(D, o, c, 0, bins);
 }
 
@@ -2683,17 +2740,18 @@ __global__ void __launch_bounds__(kPartCountThreads) k_part_direct(const DPartCo
 // array, contiguously, with the tile's S + 1 slice offsets.  Dense tables
 // store the low 15 bits of the cell (the slice is implied by the position),
 // hashed tables the whole cell, grouped by 9 bits of its mix.
-template <typename E, int TILE>
+template <typename E, int TILE, bool W>
 __global__ void __launch_bounds__(kPartTileThreads) k_part_tile(const DPartCount* __restrict__ Dp) {
   constexpr bool kHashed = sizeof(E) == 8;
   constexpr int PER = TILE / kPartTileThreads;
   const DPartCount& D = *Dp;
   const int o = blockIdx.y, tile = blockIdx.x;
   if (o >= D.n_out || (D.hashed[o] != 0) != kHashed || (!kHashed && D.n_buckets[o] <= 1) ||
-      tile >= D.n_tiles[o])
+      tile >= D.n_tiles[o] || (D.weighted[o] != 0) != W)
     return;
   __shared__ uint32_t off[kPartMaxBuckets + 1];
   __shared__ E stage[TILE];
+  __shared__ uint32_t wstage[W ? TILE : 1];   // weighted outputs: the entries' weights
   const int S = D.n_buckets[o];
   for (int i = threadIdx.x; i <= S; i += blockDim.x) off[i] = 0;
   __syncthreads();
@@ -2703,6 +2761,13 @@ __global__ void __launch_bounds__(kPartTileThreads) k_part_tile(const DPartCount
   bool bad = false;
   part_load_cells<PER>(D, o, (int32_t)r0 + (int32_t)threadIdx.x, kPartTileThreads, (int32_t)D.n_rows, cell, bad);
   if (bad) atomicOr(D.err_flag, 2);
+  uint32_t wt[PER];
+  if (W) {
+    bool big = false;
+    part_load_weights<PER>(D, o, (int32_t)r0 + (int32_t)threadIdx.x, kPartTileThreads, (int32_t)D.n_rows, cell, wt,
+                           big);
+    if (big) atomicOr(D.err_flag, 16);
+  }
   uint32_t sr[PER];   // slice << 16 | rank within the slice; ~0: no entry
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -2744,11 +2809,16 @@ __global__ void __launch_bounds__(kPartTileThreads) k_part_tile(const DPartCount
     if (sr[u] != ~0u) {
       const uint32_t pos = off[sr[u] >> 16] + (sr[u] & 0xffffu);
       stage[pos] = kHashed ? (E)(uint64_t)cell[u] : (E)((uint64_t)cell[u] & (kPartSlice - 1));
+      if (W) wstage[pos] = wt[u];
     }
   __syncthreads();
   const int n = (int)off[S];
   E* dst = (kHashed ? (E*)(D.part64 + (int64_t)D.slot[o] * D.n_rows) : (E*)(D.part + (int64_t)D.slot[o] * D.n_rows)) + r0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = stage[i];
+  if (W) {
+    uint32_t* wd = D.partw + (int64_t)D.wslot[o] * D.n_rows + r0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) wd[i] = wstage[i];
+  }
   // slice-major: the offsets of one slice over consecutive tiles are adjacent
   uint32_t* to = D.toff + D.toff_base[o] + tile;
   const int64_t nt = D.n_tiles[o];
@@ -2783,11 +2853,13 @@ __global__ void __launch_bounds__(kPartMaxBuckets) k_part_bases(const DPartCount
 // segments of slice s (a block scan of their lengths) and gives each thread
 // kPartSegUnroll consecutive entries per round (the loads in flight
 // together), so every wavefront has work however the entries spread over
-// the tiles.  visit(entry) is called per entry.  sh_start and sh_excl hold
-// blockDim entries, sh_w 16 + 1.
-template <typename E, typename F>
+// the tiles.  visit(entry, weight) is called per entry: the entry's weight
+// from `wsrc` (same positions as `src`) when W, else 1.  sh_start and
+// sh_excl hold blockDim entries, sh_w 16 + 1.
+template <typename E, bool W, typename F>
 __device__ __forceinline__ void part_segments(const DPartCount& D, int o, int s, int t0, int t1, const E* src,
-                                              int64_t* sh_start, uint32_t* sh_excl, uint32_t* sh_w, F&& visit) {
+                                              const uint32_t* wsrc, int64_t* sh_start, uint32_t* sh_excl,
+                                              uint32_t* sh_w, F&& visit) {
   const int lane = (int)__lane_id();
   const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int B = blockDim.x;
@@ -2840,11 +2912,15 @@ __device__ __forceinline__ void part_segments(const DPartCount& D, int o, int s,
       }
       // the loads, unconditional (an index past the range reads entry 0)
       E e[kPartSegUnroll];
+      uint32_t w[kPartSegUnroll];
 #pragma unroll
-      for (int u = 0; u < kPartSegUnroll; ++u) e[u] = src[idx[u] >= 0 ? idx[u] : 0];
+      for (int u = 0; u < kPartSegUnroll; ++u) {
+        e[u] = src[idx[u] >= 0 ? idx[u] : 0];
+        w[u] = W ? wsrc[idx[u] >= 0 ? idx[u] : 0] : 1u;
+      }
 #pragma unroll
       for (int u = 0; u < kPartSegUnroll; ++u)
-        if (idx[u] >= 0) visit(e[u]);
+        if (idx[u] >= 0) visit(e[u], w[u]);
     }
     __syncthreads();
   }
@@ -2852,10 +2928,11 @@ __device__ __forceinline__ void part_segments(const DPartCount& D, int o, int s,
 
 // pass 2, dense tables of several slices: workgroup (slice x chunk, output)
 // counts the slice's segments of the chunk's tiles in LDS
+template <bool W>
 __global__ void __launch_bounds__(kPartCountThreads) k_part_slice_count(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
   const int o = blockIdx.y;
-  if (o >= D.n_out || D.hashed[o] || D.n_buckets[o] <= 1) return;
+  if (o >= D.n_out || D.hashed[o] || D.n_buckets[o] <= 1 || (D.weighted[o] != 0) != W) return;
   const int C = D.chunks[o];
   const int x = blockIdx.x;
   if (x >= D.n_buckets[o] * C) return;
@@ -2868,9 +2945,19 @@ __global__ void __launch_bounds__(kPartCountThreads) k_part_slice_count(const DP
   __syncthreads();
   const int nt = D.n_tiles[o];
   const int t0 = (int)((int64_t)c * nt / C), t1 = (int)((int64_t)(c + 1) * nt / C);
-  part_segments<uint16_t>(D, o, s, t0, t1, D.part + (int64_t)D.slot[o] * D.n_rows, sh_start, sh_excl, sh_w,
-                          [&](uint16_t v) { atomicAdd(&bins[v], 1u); });
+  __shared__ unsigned long long wsum;
+  if (threadIdx.x == 0) wsum = 0;
+  uint64_t mine = 0;
+  part_segments<uint16_t, W>(D, o, s, t0, t1, D.part + (int64_t)D.slot[o] * D.n_rows,
+                             W ? D.partw + (int64_t)D.wslot[o] * D.n_rows : nullptr, sh_start, sh_excl, sh_w,
+                             [&](uint16_t v, uint32_t w) {
+                               atomicAdd(&bins[v], w);
+                               if (W) mine += w;
+                             });
+  if (W && mine) atomicAdd(&wsum, (unsigned long long)mine);
   __syncthreads();
+  // a 32-bit LDS count may have wrapped: reported, not returned wrong
+  if (W && threadIdx.x == 0 && wsum > 0xffffffffull) atomicOr(D.err_flag, 16);
   part_flush(D, o, c, (int64_t)s << kPartShift, bins);
 }
 
@@ -2947,15 +3034,15 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
     for (int i = threadIdx.x; i <= S; i += blockDim.x) suboff[i] = 0;
     __syncthreads();
     const int nt = D.n_tiles[o];
-    part_segments<uint64_t>(D, o, b, 0, nt, part, sh_start, sh_excl, sh_w,
-                            [&](uint64_t cell) { atomicAdd(&suboff[sub_of(cell) + 1], 1u); });
+    part_segments<uint64_t, false>(D, o, b, 0, nt, part, nullptr, sh_start, sh_excl, sh_w,
+                                   [&](uint64_t cell, uint32_t) { atomicAdd(&suboff[sub_of(cell) + 1], 1u); });
     __syncthreads();
     if (threadIdx.x == 0)
       for (int i = 1; i <= S; ++i) suboff[i] += suboff[i - 1];
     __syncthreads();
     for (int i = threadIdx.x; i < S; i += blockDim.x) cursor[i] = suboff[i];
     __syncthreads();
-    part_segments<uint64_t>(D, o, b, 0, nt, part, sh_start, sh_excl, sh_w, [&](uint64_t cell) {
+    part_segments<uint64_t, false>(D, o, b, 0, nt, part, nullptr, sh_start, sh_excl, sh_w, [&](uint64_t cell, uint32_t) {
       const uint32_t pos = atomicAdd(&cursor[sub_of(cell)], 1u);
       sorted[s0 + pos] = cell;
     });
@@ -3039,15 +3126,17 @@ int part_tile_rows(bool hashed) { return hashed ? kPartTileHash : kPartTileDense
 
 void launch_part_count(const DPartCount* d, const DPartCount& h, int phase, hipStream_t s) {
   if (h.n_rows <= 0 || h.n_out <= 0) return;
-  int tiles_dense = 0, tiles_hash = 0, slice_chunks = 0, direct_chunks = 0;
+  // grids per kind; [1]: the weighted outputs' kernels
+  int tiles_dense[2] = {0, 0}, slice_chunks[2] = {0, 0}, direct_chunks[2] = {0, 0}, tiles_hash = 0;
   for (int o = 0; o < h.n_out; ++o) {
+    const int w = h.weighted[o] ? 1 : 0;
     if (h.hashed[o]) {
       tiles_hash = std::max(tiles_hash, h.n_tiles[o]);
     } else if (h.n_buckets[o] <= 1) {
-      direct_chunks = std::max(direct_chunks, h.chunks[o]);
+      direct_chunks[w] = std::max(direct_chunks[w], h.chunks[o]);
     } else {
-      tiles_dense = std::max(tiles_dense, h.n_tiles[o]);
-      slice_chunks = std::max(slice_chunks, h.n_buckets[o] * h.chunks[o]);
+      tiles_dense[w] = std::max(tiles_dense[w], h.n_tiles[o]);
+      slice_chunks[w] = std::max(slice_chunks[w], h.n_buckets[o] * h.chunks[o]);
     }
   }
   switch (phase) {
@@ -3057,18 +3146,27 @@ void launch_part_count(const DPartCount* d, const DPartCount& h, int phase, hipS
       break;
     }
     case kPartPhaseDirect:
-      if (direct_chunks)
-        hipLaunchKernelGGL(k_part_direct, dim3(direct_chunks, h.n_out), dim3(kPartCountThreads), kPartSlice * 4, s,
-                           d);
+      if (direct_chunks[0])
+        hipLaunchKernelGGL(k_part_direct<false>, dim3(direct_chunks[0], h.n_out), dim3(kPartCountThreads),
+                           kPartSlice * 4, s, d);
+      if (direct_chunks[1])
+        hipLaunchKernelGGL(k_part_direct<true>, dim3(direct_chunks[1], h.n_out), dim3(kPartCountThreads),
+                           kPartSlice * 4, s, d);
       break;
     case kPartPhaseTile:
-      if (tiles_dense)
-        hipLaunchKernelGGL((k_part_tile<uint16_t, kPartTileDense>), dim3(tiles_dense, h.n_out),
+      if (tiles_dense[0])
+        hipLaunchKernelGGL((k_part_tile<uint16_t, kPartTileDense, false>), dim3(tiles_dense[0], h.n_out),
+                           dim3(kPartTileThreads), 0, s, d);
+      if (tiles_dense[1])
+        hipLaunchKernelGGL((k_part_tile<uint16_t, kPartTileDense, true>), dim3(tiles_dense[1], h.n_out),
                            dim3(kPartTileThreads), 0, s, d);
       break;
     case kPartPhaseSlices:
-      if (slice_chunks)
-        hipLaunchKernelGGL(k_part_slice_count, dim3(slice_chunks, h.n_out), dim3(kPartCountThreads),
+      if (slice_chunks[0])
+        hipLaunchKernelGGL(k_part_slice_count<false>, dim3(slice_chunks[0], h.n_out), dim3(kPartCountThreads),
+                           kPartSlice * 4, s, d);
+      if (slice_chunks[1])
+        hipLaunchKernelGGL(k_part_slice_count<true>, dim3(slice_chunks[1], h.n_out), dim3(kPartCountThreads),
                            kPartSlice * 4, s, d);
       break;
     case kPartPhaseReduce:
@@ -3076,8 +3174,8 @@ void launch_part_count(const DPartCount* d, const DPartCount& h, int phase, hipS
       break;
     case kPartPhaseTileHash:
       if (tiles_hash) {
-        hipLaunchKernelGGL((k_part_tile<uint64_t, kPartTileHash>), dim3(tiles_hash, h.n_out), dim3(kPartTileThreads),
-                           0, s, d);
+        hipLaunchKernelGGL((k_part_tile<uint64_t, kPartTileHash, false>), dim3(tiles_hash, h.n_out),
+                           dim3(kPartTileThreads), 0, s, d);
         hipLaunchKernelGGL(k_part_bases, dim3(h.n_out), dim3(kPartMaxBuckets), 0, s, d);
       }
       break;

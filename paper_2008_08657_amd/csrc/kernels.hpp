@@ -170,7 +170,13 @@ struct DPartCount {
                                            // 0/1 counts (written by the first pass, read by the others)
   int32_t vkeys_needed;                    // some output's key is a code carried by a view
   int32_t keys_cols[kPartOuts];            // every key of the output is a column of the relation
-  int32_t pad2;
+  uint32_t vmult;                          // bit v: view v holds several tuples per key (its count
+                                           // is a multiplicity, not 0/1)
+  uint32_t* wv[kPartViews];                // [n_rows] per such view: the row's count (first pass)
+  int32_t weighted[kPartOuts];             // the output counts each row with the product of the
+                                           // counts of its multiplicity views (dense tables only)
+  int32_t wslot[kPartOuts];                // weighted outputs of several slices: index in partw
+  uint32_t* partw;                         // [weighted slot][n_rows] the entries' weights, tile-ordered
   int32_t* err_flag;
 };
 constexpr int kPartHashBuckets = 512;

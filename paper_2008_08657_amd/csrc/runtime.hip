@@ -679,6 +679,8 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
     for (int v = 0; v < d.n_views; ++v) {
       const ViewDef& V = P.views[views[v]];
       const DView dv = dview_of(S, views[v]);
+      // a view of several subtree tuples per key: its count weights the row
+      if (!V.unique) d.vmult |= 1u << v;
       d.vcnt[v] = dv.cnt;
       d.vcodes[v] = dv.codes;
       d.vncodes[v] = dv.n_codes;
@@ -714,6 +716,8 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
         const int v = (int)(std::find(views.begin(), views.end(), kv.second) - views.begin());
         d.vmask[o] |= 1u << v;
       }
+      d.weighted[o] = (d.vmask[o] & d.vmult) ? 1 : 0;
+      if (d.weighted[o] && d.hashed[o]) throw PlanError{LMFAO_EINVAL, "internal: weighted partitioned count hashed"};
       const std::vector<int64_t> st_ = strides_of(P, Q.groupby);
       d.nkey[o] = (int)Q.groupby.size();
       for (int k = 0; k < d.nkey[o]; ++k) {
@@ -752,13 +756,15 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
     if (n > (int64_t)INT32_MAX - (1 << 16))
       throw PlanError{LMFAO_EUNSUPPORTED, "partitioned count of a relation of 2^31 rows or more"};
     // entry arrays per kind, tile offsets and per-chunk partial tables
-    int n_dense_slots = 0, n_hash_slots = 0;
+    int n_dense_slots = 0, n_hash_slots = 0, n_weight_slots = 0;
     int64_t toff_total = 0, partial_total = 0;
     for (int o = 0; o < d.n_out; ++o) {
       d.slot[o] = -1;
+      d.wslot[o] = -1;
       d.chunks[o] = 1;
       if (d.hashed[o] || d.n_buckets[o] > 1) {
         d.slot[o] = d.hashed[o] ? n_hash_slots++ : n_dense_slots++;
+        if (d.weighted[o]) d.wslot[o] = n_weight_slots++;
         d.tile_rows[o] = part_tile_rows(d.hashed[o] != 0);
         d.n_tiles[o] = (int)((n + d.tile_rows[o] - 1) / d.tile_rows[o]);
         d.toff_base[o] = toff_total;
@@ -782,6 +788,9 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
     d.btotal = (uint32_t*)dalloc(S, (size_t)d.n_out * kPartMaxBuckets * 4);
     d.part = n_dense_slots ? (uint16_t*)dalloc(S, (size_t)n_dense_slots * std::max<int64_t>(n, 1) * 2) : nullptr;
     d.w8 = (uint8_t*)dalloc(S, (size_t)std::max<int64_t>(n, 1));
+    d.partw = n_weight_slots ? (uint32_t*)dalloc(S, (size_t)n_weight_slots * std::max<int64_t>(n, 1) * 4) : nullptr;
+    for (int v = 0; v < d.n_views; ++v)
+      if ((d.vmult >> v) & 1u) d.wv[v] = (uint32_t*)dalloc(S, (size_t)std::max<int64_t>(n, 1) * 4);
     for (int o = 0; o < d.n_out; ++o) {
       d.keys_cols[o] = 1;
       for (int k = 0; k < d.nkey[o]; ++k) {
@@ -843,16 +852,23 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       s.pass_cols = pcols;
       S.steps.push_back(s);
     };
-    double vkeys = 0;
-    for (int v = 0; v < d.n_views; ++v) vkeys += (double)n * 4 * d.vnkey[v];
-    add_phase(kPartPhaseRows, "part_rows", vkeys + (d.w ? (double)n * 4 : 0.0), (double)n);
+    double vkeys = 0, nvm = 0, w_single = 0, w_multi = 0;
+    for (int v = 0; v < d.n_views; ++v) {
+      vkeys += (double)n * 4 * d.vnkey[v];
+      nvm += (d.vmult >> v) & 1u;
+    }
+    for (int o = 0; o < d.n_out; ++o)
+      if (d.weighted[o]) (d.n_buckets[o] <= 1 ? w_single : w_multi) += 1;
+    // weighted outputs: the rows' view counts (4 bytes per view) and, past
+    // one slice, each entry's weight written and read back
+    add_phase(kPartPhaseRows, "part_rows", vkeys + (d.w ? (double)n * 4 : 0.0), (double)n * (1 + 4 * nvm));
     if (any_single)
-      add_phase(kPartPhaseDirect, "part_direct", key_single + (double)n,
+      add_phase(kPartPhaseDirect, "part_direct", key_single + (double)n + (double)n * 4 * nvm * w_single,
                 part_single > 0 ? part_single * 4 : cells_single * 8);
     if (any_multi) {
-      add_phase(kPartPhaseTile, "part_tile", key_multi + (double)n * outs_multi,
-                (double)n * 2 * outs_multi + tiles_multi * outs_multi * 4);
-      add_phase(kPartPhaseSlices, "part_slices", (double)n * 2 * outs_multi,
+      add_phase(kPartPhaseTile, "part_tile", key_multi + (double)n * outs_multi + (double)n * 4 * nvm * w_multi,
+                (double)n * 2 * outs_multi + (double)n * 4 * w_multi + tiles_multi * outs_multi * 4);
+      add_phase(kPartPhaseSlices, "part_slices", (double)n * 2 * outs_multi + (double)n * 4 * w_multi,
                 part_multi > 0 ? part_multi * 4 : cells_multi * 8);
     }
     if (any_chunks) add_phase(kPartPhaseReduce, "part_reduce", (part_single + part_multi) * 4,
@@ -2000,8 +2016,12 @@ static void prepare_all(Prep& S, const void* const* const* user_cols, hipStream_
     // count keeps (it counts either kind per output): a table past one LDS
     // slice whose predicted group count is below 1/kDenseDensityMin of its
     // key range is hashed (the regrowth fallback keeps results exact
-    // whatever the prediction).  Tables with range queries stay dense.
-    if (!hashed && learned && dense > (double)kPickMinCells && Q.group >= 0 && P.groups[Q.group].partitioned) {
+    // whatever the prediction).  Tables with range queries stay dense, and so
+    // do tables counted with view multiplicities.
+    bool weighted = false;   // counted with view multiplicities: the partition count keeps it dense
+    for (auto& kv : Q.in_view) weighted |= !P.views[kv.second].unique;
+    if (!hashed && learned && !weighted && dense > (double)kPickMinCells && Q.group >= 0 &&
+        P.groups[Q.group].partitioned) {
       bool ranged = false;
       for (const UserQuery& U : P.user) ranged |= U.internal == (int)q && U.range;
       if (!ranged && estimate() * kDenseDensityMin < dense) {
