@@ -302,8 +302,8 @@ def test_rkmeans_chain_wide(eng):
 
 
 def test_rkmeans_chain_large_domains(eng):
-    # count tables over domains up to 10^6 written by the scans (global
-    # tables; the R1 groups are scanned, not evaluated row by row)
+    # count tables over domains up to 10^6 (counted by radix partition; the
+    # R1 groups are scanned, not evaluated row by row)
     p = W.rkmeans_chain(seed=8, n1=150_000, n2=80_000, n3=70_000, n_x=6, n_y=5, n_z=5, max_dom=1_000_000)
     print("[case] rkmeans large domains", flush=True)
     plan = eng.Plan(p, precision="f32", policy="fact", row_piece_max=5_000, min_segment=16)
@@ -312,6 +312,24 @@ def test_rkmeans_chain_large_domains(eng):
     kinds = {s["kind"] for s in prep.describe()["steps"]}
     assert "scan" in kinds
     compare_all(prep.results(), oracle.evaluate(p), F32_TOL, "rkmeans_large_domains")
+
+
+@pytest.mark.parametrize("seed, max_dom", [(11, 20_000), (12, 1_000_000)])
+def test_weighted_partition_count(eng, seed, max_dom):
+    # SUM(1) group-bys rooted at R2 and R3 count each row with the count of
+    # R1 tuples per key b carried by the view into it (about 65 per key):
+    # the partition count multiplies rows by those counts, in tables of one
+    # slice (domains up to 20,000) or of several (up to 10^6)
+    p = W.rkmeans_chain(seed=seed, n1=400_000, n2=6_000, n3=500, n_x=4, n_y=6, n_z=6, max_dom=max_dom)
+    print(f"[case] weighted partition seed {seed} max_dom {max_dom}", flush=True)
+    plan = eng.Plan(p, precision="f32", policy="fact")
+    prep = eng.Prepared(plan, eng.device_columns(p))
+    prep.run(sync=True)
+    names = [s["name"] for s in prep.describe()["steps"]]
+    assert any(":R2:part_" in n for n in names) and any(":R3:part_" in n for n in names), names
+    if max_dom > 1 << 15:
+        assert any(":R2:part_slices" in n for n in names), names
+    compare_all(prep.results(), oracle.evaluate(p), F32_TOL, f"weighted_partition_{seed}")
 
 
 @pytest.mark.parametrize("seed", [1, 2])
