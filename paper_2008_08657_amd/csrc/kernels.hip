@@ -2739,7 +2739,8 @@ __global__ void __launch_bounds__(kPartCountThreads) k_part_direct(const DPartCo
 // by a scan) and writes them to the tile's region of the output's entry
 // array, contiguously, with the tile's S + 1 slice offsets.  Dense tables
 // store the low 15 bits of the cell (the slice is implied by the position),
-// hashed tables the whole cell, grouped by 9 bits of its mix.
+// hashed tables the whole cell, grouped by the top kPartHashBits bits of
+// its mix.
 template <typename E, int TILE, bool W>
 __global__ void __launch_bounds__(kPartTileThreads) k_part_tile(const DPartCount* __restrict__ Dp) {
   constexpr bool kHashed = sizeof(E) == 8;
@@ -2773,7 +2774,7 @@ __global__ void __launch_bounds__(kPartTileThreads) k_part_tile(const DPartCount
   for (int u = 0; u < PER; ++u) {
     sr[u] = ~0u;
     if (cell[u] >= 0) {
-      const uint32_t s = kHashed ? (uint32_t)(part_mix((uint64_t)cell[u]) >> 55) : (uint32_t)(cell[u] >> kPartShift);
+      const uint32_t s = kHashed ? (uint32_t)(part_mix((uint64_t)cell[u]) >> (64 - kPartHashBits)) : (uint32_t)(cell[u] >> kPartShift);
       sr[u] = (s << 16) | atomicAdd(&off[s + 1], 1u);
     }
   }
@@ -2979,10 +2980,10 @@ __global__ void k_part_reduce(const DPartCount* __restrict__ Dp) {
 // pass 2 of hashed outputs, one workgroup per group of cells: the group's
 // segments are gathered from every tile and ordered by sub-group (a counting
 // sort on the next hash bits, into the group's region of part64b;
-// sub-groups of about 192 cells), then every wavefront counts whole
-// sub-groups in an LDS hash table of its own (512 slots; no workgroup
+// sub-groups of at most kPartSubCells entries), then every wavefront counts whole
+// sub-groups in an LDS hash table of its own (kPartWaveSlots slots; no workgroup
 // barrier between sub-groups) and writes their (cell, count) pairs to the
-// group's own region of the output's table (cap / 512 slots, positions from
+// group's own region of the output's table (cap / kPartHashBuckets slots, positions from
 // an LDS counter: no global atomics).  The region's slots past its groups
 // stay zero: the table is cleared once when allocated, and each run clears
 // only the slots the previous run filled past this run's groups (the group
@@ -2991,8 +2992,8 @@ __global__ void k_part_reduce(const DPartCount* __restrict__ Dp) {
 // repeated with a larger table).
 constexpr int kPartWaveSlots = 512;
 constexpr int kPartHashWaves = 16;
-constexpr int kPartSubCells = 192;
-constexpr int kPartMaxSub = 1024;
+constexpr int kPartSubCells = 256;
+constexpr int kPartMaxSub = 4096;
 constexpr int kPartHashLds = kPartWaveSlots * kPartHashWaves * 12 + (2 * kPartMaxSub + 2) * 4;
 __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
@@ -3027,7 +3028,7 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
   uint64_t* sorted = D.part64b + (int64_t)D.slot[o] * D.n_rows;
   constexpr unsigned long long kEmpty = ~0ull;
   auto sub_of = [&](uint64_t cell) {
-    return sbits ? (int)((part_mix(cell) >> (55 - sbits)) & (uint64_t)(S - 1)) : 0;
+    return sbits ? (int)((part_mix(cell) >> (64 - kPartHashBits - sbits)) & (uint64_t)(S - 1)) : 0;
   };
   if (s0 < s1) {
     // counting sort of the group by sub-group, gathered from the tiles
@@ -3121,7 +3122,7 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
 }
 
 constexpr int kPartTileDense = 16384;
-constexpr int kPartTileHash = 8192;
+constexpr int kPartTileHash = 16384;
 int part_tile_rows(bool hashed) { return hashed ? kPartTileHash : kPartTileDense; }
 
 void launch_part_count(const DPartCount* d, const DPartCount& h, int phase, hipStream_t s) {

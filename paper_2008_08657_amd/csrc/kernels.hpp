@@ -179,7 +179,8 @@ struct DPartCount {
   uint32_t* partw;                         // [weighted slot][n_rows] the entries' weights, tile-ordered
   int32_t* err_flag;
 };
-constexpr int kPartHashBuckets = 512;
+constexpr int kPartHashBits = 8;                   // hashed tables: groups by the top bits of the cell's mix
+constexpr int kPartHashBuckets = 1 << kPartHashBits;
 // rows per tile of the tile pass (dense and hashed outputs)
 int part_tile_rows(bool hashed);
 // one pass of the launch set: row bytes, direct counts, slice-ordered tiles,
