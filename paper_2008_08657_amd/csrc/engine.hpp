@@ -41,6 +41,10 @@ constexpr int kScanWaves = 8;      // wavefronts per scan block (each holds its 
 constexpr int kLdsBytes = 160 * 1024;            // LDS of one compute unit
 constexpr int64_t kLdsTableMax = 12288;          // int32 count entries privatized in LDS
 constexpr int64_t kPartMinCells = 1;             // smallest SUM(1) table moved from a scan to the partition count
+                                                 // when the scan's LDS tables overflow
+constexpr int64_t kPartSmallCells = 64;          // larger SUM(1) tables are counted by the partition count...
+constexpr int64_t kPartScanCells = 2048;         // ...except, on relations of kPartLargeRows rows or more,
+constexpr int64_t kPartLargeRows = (int64_t)1 << 24;  // tables of up to kPartScanCells cells
 constexpr int kTriangle = (kMaxAtoms + 1) * (kMaxAtoms + 2) / 2;  // incl. (1,1)
 constexpr int64_t kDenseRowsMax = (int64_t)1 << 24;  // larger key spaces go to hash tables
 constexpr int64_t kPickMinCells = (int64_t)1 << 15;  // smaller tables stay dense (one LDS slice)

@@ -1552,14 +1552,32 @@ static bool move_lds_overflow(Plan& P, int gi) {
 
 // Moves the partition-eligible queries of every group into a group of their
 // own at the same node and level (no program; the runtime counts them).
+// Tables past a scan's LDS tables (kLdsTableMax cells) move.  Once a group
+// has such a table (so the partition count's row pass is paid anyway), the
+// tables keyed by the node's own columns move too once they are past what a
+// scan keeps in registers (kPartSmallCells), or, on relations of
+// kPartLargeRows rows or more, past kPartScanCells (smaller ones cost less
+// in the scan's shared pass).  Tables keyed by a code a view carries stay at
+// the LDS threshold: the partition count gathers such codes a row at a
+// time.  (Measured on the Rk-means chain, the grocery star and the CART
+// batch: each choice pays on its side.)
 static void extract_partitioned(Plan& P) {
   const size_t n = P.groups.size();
   for (size_t gi = 0; gi < n; ++gi) {
     GroupDef& G = P.groups[gi];
     if (G.force_rows || G.partitioned) continue;
+    const RelDef& R = P.rels[G.node];
+    bool any_large = false;
+    for (const OutRef& o : G.outs) any_large |= o.kind == 0 && partition_eligible(P, o.id, G.node);
+    auto min_cells = [&](int qid) {
+      if (!any_large) return (double)kLdsTableMax;
+      for (int a : P.queries[qid].groupby)
+        if (!R.has(a)) return (double)kLdsTableMax;
+      return (double)(R.n_rows >= kPartLargeRows ? kPartScanCells : kPartSmallCells);
+    };
     std::vector<OutRef> keep, part;
     for (const OutRef& o : G.outs)
-      (o.kind == 0 && partition_eligible(P, o.id, G.node) ? part : keep).push_back(o);
+      (o.kind == 0 && partition_eligible(P, o.id, G.node, min_cells(o.id)) ? part : keep).push_back(o);
     if (part.empty()) continue;
     if (keep.empty()) {
       G.partitioned = true;
