@@ -131,6 +131,17 @@ def test_rk_means_step1_batch_is_n_queries():
     assert len(d["queries"]) == len(attrs)
 
 
+def test_partition_count_takes_tables_weighted_by_count_views():
+    # SUM(1) grouped by attributes of R2 (or R3) is rooted there; the view
+    # from R1 into R2 holds several R1 tuples per key b, and its count weights
+    # each R2 row: such tables are counted by partition at R2 and R3 (section
+    # 3, Rk-means step 1), not by per-row atomics in a scan
+    p = W.rkmeans_chain(seed=12, n1=400_000, n2=6_000, n3=500, n_x=4, n_y=6, n_z=6, max_dom=1_000_000)
+    d = plan(p, precision="f32", policy="fact")
+    assert {g["node"] for g in d["groups"] if g.get("partitioned")} >= {"R1", "R2", "R3"}
+    assert {q["root"] for q in d["queries"]} == {"R1", "R2", "R3"}
+
+
 @pytest.mark.parametrize("mutate, status", [
     (lambda p: p.update(tree=[(0, 1)]), "EINVAL"),                                   # not connected
     (lambda p: p.update(tree=[(0, 1), (0, 2), (1, 2)]), "EINVAL"),                   # cycle
