@@ -2657,12 +2657,10 @@ __device__ __forceinline__ uint64_t part_mix(uint64_t x) {
 }
 
 // pass 0: the per-row byte (bit 0 filter weight, bits 1.. the views' 0/1
-// counts) for every later pass, the counts of multiplicity views, and zero
-// slice totals
+// counts) for every later pass and the counts of multiplicity views (shared
+// by the launch sets of the node that read the same views)
 __global__ void __launch_bounds__(256) k_part_w8(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < D.n_out * kPartMaxBuckets; i += blockDim.x) D.btotal[i] = 0;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < D.n_rows;
        row += (int64_t)gridDim.x * blockDim.x) {
     PartRow R;
@@ -2845,7 +2843,10 @@ __global__ void __launch_bounds__(kPartMaxBuckets) k_part_bases(const DPartCount
     __syncthreads();
   }
   uint32_t* bs = D.bstart + (int64_t)o * (kPartMaxBuckets + 1);
-  if ((int)threadIdx.x < nb) bs[threadIdx.x] = tmp[threadIdx.x] - v;
+  if ((int)threadIdx.x < nb) {
+    bs[threadIdx.x] = tmp[threadIdx.x] - v;
+    D.btotal[(int64_t)o * kPartMaxBuckets + threadIdx.x] = 0;   // zero again for the next run's tile pass
+  }
   if (threadIdx.x == 0) bs[nb] = tmp[kPartMaxBuckets - 1];
 }
 

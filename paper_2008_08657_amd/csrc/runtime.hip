@@ -134,6 +134,9 @@ struct lmfao_prepared_s {
   lmfao::DHashOut* hash_dev = nullptr;                // device copy of the hash descriptors
   int hash_regrowths = 0;                             // runs repeated after a hash overflow
   std::map<int, int64_t> distinct;                    // distinct values per integer attribute
+  // per (node, row order, views) the partition count's per-row bytes and view
+  // counts: the first launch set that reads them writes them each run
+  std::map<std::string, std::pair<uint8_t*, std::vector<uint32_t*>>> part_rows;
   std::map<std::pair<int, int>, int64_t> distinct_rel; // ... per (attribute, relation)
   int32_t* hash_ovf = nullptr;                        // per table overflow flag
   std::vector<std::vector<const void*>> ecols;       // caller's columns, then derived bucket codes
@@ -787,10 +790,26 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
     d.bstart = (uint32_t*)dalloc(S, (size_t)d.n_out * (kPartMaxBuckets + 1) * 4);
     d.btotal = (uint32_t*)dalloc(S, (size_t)d.n_out * kPartMaxBuckets * 4);
     d.part = n_dense_slots ? (uint16_t*)dalloc(S, (size_t)n_dense_slots * std::max<int64_t>(n, 1) * 2) : nullptr;
-    d.w8 = (uint8_t*)dalloc(S, (size_t)std::max<int64_t>(n, 1));
+    // the slice totals of hashed outputs start at zero (k_part_bases zeroes
+    // them again after each use)
+    launch_fill(d.btotal, (int64_t)d.n_out * kPartMaxBuckets * 4, st);
+    HIP_OK(hipGetLastError());
     d.partw = n_weight_slots ? (uint32_t*)dalloc(S, (size_t)n_weight_slots * std::max<int64_t>(n, 1) * 4) : nullptr;
-    for (int v = 0; v < d.n_views; ++v)
-      if ((d.vmult >> v) & 1u) d.wv[v] = (uint32_t*)dalloc(S, (size_t)std::max<int64_t>(n, 1) * 4);
+    // per-row bytes and view counts: shared with an earlier launch set of the
+    // node that reads the same views in the same row order
+    std::string rows_key = std::to_string(r) + (sorted ? ":sorted" : ":raw");
+    for (int vid : views) rows_key += "," + std::to_string(vid);
+    auto rows_hit = S.part_rows.find(rows_key);
+    const bool shared_rows = rows_hit != S.part_rows.end();
+    if (shared_rows) {
+      d.w8 = rows_hit->second.first;
+      for (int v = 0; v < d.n_views; ++v) d.wv[v] = rows_hit->second.second[v];
+    } else {
+      d.w8 = (uint8_t*)dalloc(S, (size_t)std::max<int64_t>(n, 1));
+      for (int v = 0; v < d.n_views; ++v)
+        if ((d.vmult >> v) & 1u) d.wv[v] = (uint32_t*)dalloc(S, (size_t)std::max<int64_t>(n, 1) * 4);
+      S.part_rows[rows_key] = {d.w8, std::vector<uint32_t*>(d.wv, d.wv + kPartViews)};
+    }
     for (int o = 0; o < d.n_out; ++o) {
       d.keys_cols[o] = 1;
       for (int k = 0; k < d.nkey[o]; ++k) {
@@ -861,7 +880,8 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       if (d.weighted[o]) (d.n_buckets[o] <= 1 ? w_single : w_multi) += 1;
     // weighted outputs: the rows' view counts (4 bytes per view) and, past
     // one slice, each entry's weight written and read back
-    add_phase(kPartPhaseRows, "part_rows", vkeys + (d.w ? (double)n * 4 : 0.0), (double)n * (1 + 4 * nvm));
+    if (!shared_rows)
+      add_phase(kPartPhaseRows, "part_rows", vkeys + (d.w ? (double)n * 4 : 0.0), (double)n * (1 + 4 * nvm));
     if (any_single)
       add_phase(kPartPhaseDirect, "part_direct", key_single + (double)n + (double)n * 4 * nvm * w_single,
                 part_single > 0 ? part_single * 4 : cells_single * 8);
