@@ -122,7 +122,7 @@ void launch_mult_check(const DMultCheck* d, const DMultCheck& h, hipStream_t s);
 // counted in LDS from its tile segments; hash tables (key spaces past 2^24
 // cells) are ordered by 9 bits of a hash of the cell and every group of cells
 // counted in LDS hash tables.
-constexpr int kPartOuts = 16;
+constexpr int kPartOuts = 32;
 constexpr int kPartViews = 4;
 constexpr int kPartShift = 15;
 constexpr int kPartMaxBuckets = 512;
