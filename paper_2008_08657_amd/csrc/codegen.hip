@@ -281,9 +281,18 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
   // small histograms: a private counter per lane and bin, summed over the
   // wavefront when the piece closes (no LDS atomics on skewed codes)
   auto reg_hist = [&](int h) { return d.hists[h].dom <= std::min(kRegHist, (int)F.reg_hist_bins); };
+  // integer register histograms with multiplicities 0 or 1: the bins are
+  // 8-bit fields of one or two 64-bit words (a row adds its multiplicity
+  // shifted to its code's field; a lane adds at most 128 rows of a piece),
+  // unpacked into the per-bin counts when the piece closes
+  auto packed = [&](int h) { return F.mult01 && reg_hist(h) && !((F.hword[h] >> 4) & 1u); };
   for (int h = 0; h < F.n_hist; ++h) {
     if (!reg_hist(h)) continue;
     const bool fl = (F.hword[h] >> 4) & 1u;
+    if (packed(h)) {
+      for (int wi = 0; wi * 8 < d.hists[h].dom; ++wi) e << "      unsigned long long pk" << h << "_" << wi << " = 0ull;\n";
+      continue;
+    }
     for (int b = 0; b < d.hists[h].dom; ++b)
       e << "      " << (fl ? "T" : "int") << " rh" << h << "_" << b << " = " << (fl ? "(T)0" : "0") << ";\n";
   }
@@ -355,6 +364,17 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
         for (int b = 0; b < d.hists[h].dom; ++b)
           e << " rh" << h << "_" << b << " += c" << code << " == " << b << " ? hv : (T)0;";
         e << " }\n";
+      } else if (packed(h)) {
+        const int dom = d.hists[h].dom;
+        // the multiplicity is selected (0 for a code outside the word) before
+        // the shift, whose count is kept below 64
+        e << "        { const unsigned hv = (unsigned)" << mu(m) << "; const unsigned cu = (unsigned)c" << code << ";";
+        for (int wi = 0; wi * 8 < dom; ++wi) {
+          const int lo = wi * 8, n = std::min(8, dom - lo);
+          e << " { const unsigned cw = cu - " << lo << "u; pk" << h << "_" << wi
+            << " += (unsigned long long)(cw < " << n << "u ? hv : 0u) << ((cw & 7u) * 8u); }";
+        }
+        e << " }\n";
       } else {
         e << "        { const int hv = " << mu(m) << ";";
         for (int b = 0; b < d.hists[h].dom; ++b)
@@ -397,7 +417,13 @@ bool gen_scan_kernel(const DScan& d, int NA, bool f64, const std::string& tag, G
     e << "        }\n";
   }
   e << "      }\n";
-  // close the piece
+  // close the piece (packed histograms unpacked into their bins first)
+  for (int h = 0; h < F.n_hist; ++h) {
+    if (!packed(h)) continue;
+    for (int b = 0; b < d.hists[h].dom; ++b)
+      e << "      const int rh" << h << "_" << b << " = (int)((pk" << h << "_" << b / 8 << " >> " << 8 * (b % 8)
+        << ") & 0xffull);\n";
+  }
   e << "      T* prow = psi_f + (long long)p * " << d.psi_f_stride << ";\n";
   e << "      int* irow = psi_i + (long long)p * " << d.psi_i_stride << ";\n";
   // The piece's wavefront totals, each value placed at its destination index

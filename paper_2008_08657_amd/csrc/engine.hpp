@@ -421,6 +421,9 @@ struct DFast {
   double* tab_vals[kGenTables];
   int32_t tab_nv[kGenTables];
   int32_t reg_hist_bins;           // generated scans: histograms this small live in registers
+  int32_t mult01;                  // generated scans: every row's multiplicity is 0 or 1 (the inner
+                                   // views are single-valued), so integer register histograms may
+                                   // keep their bins as 8-bit fields of 64-bit words
 };
 
 struct DScan {

@@ -1299,6 +1299,11 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
       // per-lane register histograms pay off when a piece spans at least one
       // 64-row chunk (their wavefront sums are taken once per piece)
       F.reg_hist_bins = R.n_rows >= 64 * std::max<int64_t>(1, N.n_pieces) ? 16 : 0;
+      // a lane adds at most ceil(kPieceMax / 64) rows of one piece to a bin:
+      // with multiplicities 0 or 1 an 8-bit field holds it (cleared below for
+      // inner views of several tuples per key)
+      static_assert(kPieceMax / 64 < 256, "8-bit register histogram fields");
+      F.mult01 = 1;
       for (int i = 0; i < d.n_hists; ++i) {
         const DHist& H = d.hists[i];
         F.hcode[i] = (int8_t)H.code;
@@ -1346,6 +1351,7 @@ static void build_group(Prep& S, int gi, const void* const* const* cols, hipStre
         int v = scan_view[k];
         if (v < 0) continue;
         const DView& V = d.views[v];
+        if (!P.views[g.views[k]].unique) F.mult01 = 0;
         DImageBuild ib{};
         ib.view = V;
         ib.n_keys = V.n_keys;
