@@ -2701,15 +2701,12 @@ __global__ void __launch_bounds__(kPartCountThreads) k_part_direct(const DPartCo
   const int o = blockIdx.y, c = blockIdx.x;
   if (o >= D.n_out || D.hashed[o] || D.n_buckets[o] != 1 || c >= D.chunks[o] || (D.weighted[o] != 0) != W) return;
   extern __shared__ uint32_t bins[];
-  __shared__ unsigned long long wsum;
   for (int i = threadIdx.x; i < kPartSlice; i += blockDim.x) bins[i] = 0;
-  if (threadIdx.x == 0) wsum = 0;
   __syncthreads();
   const int64_t per = (D.n_rows + D.chunks[o] - 1) / D.chunks[o];
   const int64_t r0 = (int64_t)c * per, r1 = min(D.n_rows, r0 + per);
   const int64_t step = (int64_t)kPartDirectUnroll * blockDim.x;
   bool bad = false, big = false;
-  uint64_t mine = 0;
   for (int64_t base = r0; base < r1; base += step) {
     int32_t cell[kPartDirectUnroll];
     const int32_t first = (int32_t)base + (int32_t)threadIdx.x;
@@ -2719,16 +2716,18 @@ __global__ void __launch_bounds__(kPartCountThreads) k_part_direct(const DPartCo
 #pragma unroll
     for (int u = 0; u < kPartDirectUnroll; ++u)
       if (cell[u] >= 0) {
-        atomicAdd(&bins[cell[u]], W ? wt[u] : 1u);
-        if (W) mine += wt[u];
+        if (W) {
+          // a weighted add that wraps the 32-bit LDS count is reported, not returned wrong
+          const uint32_t old = atomicAdd(&bins[cell[u]], wt[u]);
+          big |= (uint32_t)(old + wt[u]) < old;
+        } else {
+          atomicAdd(&bins[cell[u]], 1u);
+        }
       }
   }
   if (bad) atomicOr(D.err_flag, 2);
-  if (W && mine) atomicAdd(&wsum, (unsigned long long)mine);
-  __syncthreads();
-  // a 32-bit LDS count may have wrapped: reported, not returned wrong
-  if (W && threadIdx.x == 0 && wsum > 0xffffffffull) atomicOr(D.err_flag, 16);
   if (W && big) atomicOr(D.err_flag, 16);
+  __syncthreads();
   part_flush(D, o, c, 0, bins);
 }
 
@@ -2947,19 +2946,20 @@ __global__ void __launch_bounds__(kPartCountThreads) k_part_slice_count(const DP
   __syncthreads();
   const int nt = D.n_tiles[o];
   const int t0 = (int)((int64_t)c * nt / C), t1 = (int)((int64_t)(c + 1) * nt / C);
-  __shared__ unsigned long long wsum;
-  if (threadIdx.x == 0) wsum = 0;
-  uint64_t mine = 0;
+  bool big = false;
   part_segments<uint16_t, W>(D, o, s, t0, t1, D.part + (int64_t)D.slot[o] * D.n_rows,
                              W ? D.partw + (int64_t)D.wslot[o] * D.n_rows : nullptr, sh_start, sh_excl, sh_w,
                              [&](uint16_t v, uint32_t w) {
-                               atomicAdd(&bins[v], w);
-                               if (W) mine += w;
+                               if (W) {
+                                 // a weighted add that wraps the 32-bit LDS count is reported
+                                 const uint32_t old = atomicAdd(&bins[v], w);
+                                 big |= (uint32_t)(old + w) < old;
+                               } else {
+                                 atomicAdd(&bins[v], 1u);
+                               }
                              });
-  if (W && mine) atomicAdd(&wsum, (unsigned long long)mine);
+  if (W && big) atomicOr(D.err_flag, 16);
   __syncthreads();
-  // a 32-bit LDS count may have wrapped: reported, not returned wrong
-  if (W && threadIdx.x == 0 && wsum > 0xffffffffull) atomicOr(D.err_flag, 16);
   part_flush(D, o, c, (int64_t)s << kPartShift, bins);
 }
 

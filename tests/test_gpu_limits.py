@@ -84,3 +84,66 @@ def test_multiplicity_beyond_32_bit_partials_is_reported(eng):
     # the result readers see the same flag
     with pytest.raises(eng.LmfaoError):
         prep.result(0)
+
+
+def one_key_grouped(n, m, dom, all_one_cell=False, seed=0):
+    """A (n rows: key k = 0, g over a domain of `dom` values) joined with B (m
+    rows, all k = 0): SUM(1) GROUP BY g rooted at A counts every A row m
+    times -- the partition count with each row weighted by the count of B
+    tuples per key."""
+    rng = np.random.default_rng(seed)
+    g = np.zeros(n, np.int32) if all_one_cell else rng.integers(0, dom, n).astype(np.int32)
+    schema = [
+        {"name": "A", "n_rows": n, "attrs": [{"name": "k", "dtype": "i32", "domain": 2, "key": False},
+                                              {"name": "g", "dtype": "i32", "domain": dom, "key": False}]},
+        {"name": "B", "n_rows": m, "attrs": [{"name": "k", "dtype": "i32", "domain": 2, "key": False}]},
+    ]
+    data = {"A": {"k": np.zeros(n, np.int32), "g": g}, "B": {"k": np.zeros(m, np.int32)}}
+    batch = [{"groupby": ["g"], "where": [], "aggs": [[]], "root": "A"}]
+    return {"schema": schema, "tree": [(0, 1)], "batch": batch, "data": data, "policy": "groupby"}
+
+
+def test_weighted_partition_count_beyond_2_32_in_total(eng):
+    # 300k A rows over 20,000 cells, each worth 40k B tuples: 1.2e10 tuples
+    # in all, about 6e5 per cell -- exact, with cells and chunks summed in
+    # 64 bits (closed form: rows of the cell times m)
+    n, m, dom = 300_000, 40_000, 20_000
+    p = one_key_grouped(n, m, dom)
+    print(f"[case] weighted partition {n} x {m} over {dom} cells", flush=True)
+    plan = eng.Plan(p, precision="f64")
+    assert any(g.get("partitioned") for g in plan.describe()["groups"])
+    prep = eng.Prepared(plan, eng.device_columns(p))
+    prep.run(sync=True)
+    r = prep.result(0)
+    g = p["data"]["A"]["g"]
+    vals, cnt = np.unique(g, return_counts=True)
+    assert r["keys"][:, 0].tolist() == vals.tolist()
+    assert r["count"].tolist() == (cnt.astype(np.int64) * m).tolist()
+
+
+def test_weighted_partition_one_cell_beyond_2_32(eng):
+    # every one of 200k A rows in one cell, each worth 40k B tuples: 8e9 in
+    # the cell, each of the direct pass's three row chunks below 2^32 in LDS
+    n, m, dom = 200_000, 40_000, 20_000
+    p = one_key_grouped(n, m, dom, all_one_cell=True)
+    print(f"[case] weighted partition, one cell of {n} x {m}", flush=True)
+    plan = eng.Plan(p, precision="f64")
+    prep = eng.Prepared(plan, eng.device_columns(p))
+    prep.run(sync=True)
+    r = prep.result(0)
+    assert r["keys"][:, 0].tolist() == [0] and r["count"].tolist() == [n * m]
+
+
+def test_weighted_partition_cell_beyond_32_bits_is_reported(eng):
+    # the same with 100k B tuples per row: a chunk of about 66.7k rows adds
+    # 6.7e9 to the cell's 32-bit LDS count -- the run must refuse
+    n, m, dom = 200_000, 100_000, 20_000
+    p = one_key_grouped(n, m, dom, all_one_cell=True)
+    print(f"[case] weighted partition, one cell of {n} x {m} (expects LMFAO_EOVERFLOW)", flush=True)
+    plan = eng.Plan(p, precision="f64")
+    prep = eng.Prepared(plan, eng.device_columns(p))
+    with pytest.raises(eng.LmfaoError) as ei:
+        prep.run(sync=True)
+    assert ei.value.status == 5, str(ei.value)
+    with pytest.raises(eng.LmfaoError):
+        prep.result(0)
