@@ -2996,10 +2996,11 @@ constexpr int kPartHashWaves = 16;
 constexpr int kPartSubCells = 256;
 constexpr int kPartMaxSub = 4096;
 constexpr int kPartHashLds = kPartWaveSlots * kPartHashWaves * 12 + (2 * kPartMaxSub + 2) * 4;
+template <bool W>
 __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCount* __restrict__ Dp) {
   const DPartCount& D = *Dp;
   const int o = blockIdx.y;
-  if (o >= D.n_out || !D.hashed[o]) return;
+  if (o >= D.n_out || !D.hashed[o] || (D.weighted[o] != 0) != W) return;
   extern __shared__ unsigned long long lkeys[];
   __shared__ int64_t sh_start[kPartHashWaves * 64];
   __shared__ uint32_t sh_excl[kPartHashWaves * 64];
@@ -3027,6 +3028,9 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
   }
   const uint64_t* part = D.part64 + (int64_t)D.slot[o] * D.n_rows;
   uint64_t* sorted = D.part64b + (int64_t)D.slot[o] * D.n_rows;
+  // weighted outputs: each entry's weight travels with it through the sort
+  const uint32_t* part_w = W ? D.partw + (int64_t)D.wslot[o] * D.n_rows : nullptr;
+  uint32_t* sorted_w = W ? D.partwb + (int64_t)D.wslot[o] * D.n_rows : nullptr;
   constexpr unsigned long long kEmpty = ~0ull;
   auto sub_of = [&](uint64_t cell) {
     return sbits ? (int)((part_mix(cell) >> (64 - kPartHashBits - sbits)) & (uint64_t)(S - 1)) : 0;
@@ -3044,15 +3048,16 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
     __syncthreads();
     for (int i = threadIdx.x; i < S; i += blockDim.x) cursor[i] = suboff[i];
     __syncthreads();
-    part_segments<uint64_t, false>(D, o, b, 0, nt, part, nullptr, sh_start, sh_excl, sh_w, [&](uint64_t cell, uint32_t) {
+    part_segments<uint64_t, W>(D, o, b, 0, nt, part, part_w, sh_start, sh_excl, sh_w, [&](uint64_t cell, uint32_t w) {
       const uint32_t pos = atomicAdd(&cursor[sub_of(cell)], 1u);
       sorted[s0 + pos] = cell;
+      if (W) sorted_w[s0 + pos] = w;
     });
     __threadfence_block();
     __syncthreads();
     unsigned long long* wkeys = lkeys + wid * kPartWaveSlots;
     uint32_t* wcnt = lcnt + wid * kPartWaveSlots;
-    bool full = false;
+    bool full = false, big = false;
     for (int sub = wid; sub < S; sub += kPartHashWaves) {
       const int64_t r0 = s0 + suboff[sub], r1 = s0 + suboff[sub + 1];
       if (r0 >= r1) continue;
@@ -3063,10 +3068,12 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
       __builtin_amdgcn_wave_barrier();
       for (int64_t i0 = r0 + lane; i0 < r1; i0 += 4 * 64) {
         uint64_t cv[4];
+        uint32_t wv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int64_t i = i0 + (int64_t)u * 64;
           cv[u] = sorted[i < r1 ? i : r0];
+          wv[u] = W ? sorted_w[i < r1 ? i : r0] : 1u;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -3077,7 +3084,13 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
           for (int probe = 0; probe < kPartWaveSlots && !done; ++probe) {
             const unsigned long long prev = atomicCAS(&wkeys[slot], kEmpty, (unsigned long long)cell);
             if (prev == kEmpty || prev == cell) {
-              atomicAdd(&wcnt[slot], 1u);
+              if (W) {
+                // a weighted add that wraps the 32-bit LDS count is reported
+                const uint32_t old = atomicAdd(&wcnt[slot], wv[u]);
+                big |= (uint32_t)(old + wv[u]) < old;
+              } else {
+                atomicAdd(&wcnt[slot], 1u);
+              }
               done = true;
             }
             slot = (slot + 1) & (kPartWaveSlots - 1);
@@ -3110,6 +3123,7 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
       atomicOr(H.ovf, 1);
       atomicOr(D.err_flag, 8);
     }
+    if (W && big) atomicOr(D.err_flag, 16);
   }
   __syncthreads();
   // the region's slots past this run's groups hold none: the table was
@@ -3124,16 +3138,19 @@ __global__ void __launch_bounds__(kPartHashWaves * 64) k_part_hash(const DPartCo
 
 constexpr int kPartTileDense = 16384;
 constexpr int kPartTileHash = 16384;
-int part_tile_rows(bool hashed) { return hashed ? kPartTileHash : kPartTileDense; }
+constexpr int kPartTileHashW = 8192;   // weighted hashed tiles stage a 4-byte weight per entry too
+int part_tile_rows(bool hashed, bool weighted) {
+  return hashed ? (weighted ? kPartTileHashW : kPartTileHash) : kPartTileDense;
+}
 
 void launch_part_count(const DPartCount* d, const DPartCount& h, int phase, hipStream_t s) {
   if (h.n_rows <= 0 || h.n_out <= 0) return;
   // grids per kind; [1]: the weighted outputs' kernels
-  int tiles_dense[2] = {0, 0}, slice_chunks[2] = {0, 0}, direct_chunks[2] = {0, 0}, tiles_hash = 0;
+  int tiles_dense[2] = {0, 0}, slice_chunks[2] = {0, 0}, direct_chunks[2] = {0, 0}, tiles_hash[2] = {0, 0};
   for (int o = 0; o < h.n_out; ++o) {
     const int w = h.weighted[o] ? 1 : 0;
     if (h.hashed[o]) {
-      tiles_hash = std::max(tiles_hash, h.n_tiles[o]);
+      tiles_hash[w] = std::max(tiles_hash[w], h.n_tiles[o]);
     } else if (h.n_buckets[o] <= 1) {
       direct_chunks[w] = std::max(direct_chunks[w], h.chunks[o]);
     } else {
@@ -3175,16 +3192,22 @@ void launch_part_count(const DPartCount* d, const DPartCount& h, int phase, hipS
       hipLaunchKernelGGL(k_part_reduce, dim3(256, h.n_out), dim3(256), 0, s, d);
       break;
     case kPartPhaseTileHash:
-      if (tiles_hash) {
-        hipLaunchKernelGGL((k_part_tile<uint64_t, kPartTileHash, false>), dim3(tiles_hash, h.n_out),
+      if (tiles_hash[0])
+        hipLaunchKernelGGL((k_part_tile<uint64_t, kPartTileHash, false>), dim3(tiles_hash[0], h.n_out),
                            dim3(kPartTileThreads), 0, s, d);
+      if (tiles_hash[1])
+        hipLaunchKernelGGL((k_part_tile<uint64_t, kPartTileHashW, true>), dim3(tiles_hash[1], h.n_out),
+                           dim3(kPartTileThreads), 0, s, d);
+      if (tiles_hash[0] || tiles_hash[1])
         hipLaunchKernelGGL(k_part_bases, dim3(h.n_out), dim3(kPartMaxBuckets), 0, s, d);
-      }
       break;
     case kPartPhaseHash:
-      if (tiles_hash)
-        hipLaunchKernelGGL(k_part_hash, dim3(kPartHashBuckets, h.n_out), dim3(kPartHashWaves * 64), kPartHashLds, s,
-                           d);
+      if (tiles_hash[0])
+        hipLaunchKernelGGL(k_part_hash<false>, dim3(kPartHashBuckets, h.n_out), dim3(kPartHashWaves * 64),
+                           kPartHashLds, s, d);
+      if (tiles_hash[1])
+        hipLaunchKernelGGL(k_part_hash<true>, dim3(kPartHashBuckets, h.n_out), dim3(kPartHashWaves * 64),
+                           kPartHashLds, s, d);
       break;
     default:
       break;

@@ -177,12 +177,14 @@ struct DPartCount {
                                            // counts of its multiplicity views (dense tables only)
   int32_t wslot[kPartOuts];                // weighted outputs of several slices: index in partw
   uint32_t* partw;                         // [weighted slot][n_rows] the entries' weights, tile-ordered
+  uint32_t* partwb;                        // [weighted slot][n_rows] hashed outputs: the weights in the
+                                           // group and sub-group order of part64b
   int32_t* err_flag;
 };
 constexpr int kPartHashBits = 8;                   // hashed tables: groups by the top bits of the cell's mix
 constexpr int kPartHashBuckets = 1 << kPartHashBits;
 // rows per tile of the tile pass (dense and hashed outputs)
-int part_tile_rows(bool hashed);
+int part_tile_rows(bool hashed, bool weighted);
 // one pass of the launch set: row bytes, direct counts, slice-ordered tiles,
 // slice counts, partial-table sums, hash-ordered tiles, hashed groups
 enum {

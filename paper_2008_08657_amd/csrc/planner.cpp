@@ -1455,7 +1455,7 @@ static void split_group(Plan& P, int gi, size_t from) {
 // time, in LDS) instead of by global atomics from a scan or a row pass.
 // Views with several subtree tuples per key may join in (carrying no
 // group-by attribute): each row then counts with the product of their
-// counts, and the table stays dense.
+// counts.
 static double query_cells(const Plan& P, int qid) {
   double cells = 1;
   for (int a : P.queries[qid].groupby) cells *= (double)std::max<int64_t>(P.attrs[a].domain, 0);
@@ -1474,20 +1474,14 @@ static bool partition_eligible(const Plan& P, int qid, int node, double min_cell
   // past 2^24 cells) of cells below 2^62
   if (cells <= min_cells || cells >= 4.6e18) return false;
   if (Q.in_view.size() > 4) return false;
-  bool weighted = false;
   for (auto& kv : Q.in_view) {
     const ViewDef& V = P.views[kv.second];
     if (V.key.size() > 2) return false;
-    if (!V.unique) {
-      // a view of several subtree tuples per key weights the row by its
-      // count; it may not carry a group-by attribute (the row would not
-      // determine the cell)
-      if (!V.carried.empty()) return false;
-      weighted = true;
-    }
+    // a view of several subtree tuples per key weights the row by its count;
+    // it may not carry a group-by attribute (the row would not determine
+    // the cell)
+    if (!V.unique && !V.carried.empty()) return false;
   }
-  // weighted counts are kept in dense tables only
-  if (weighted && cells > (double)kDenseRowsMax) return false;
   for (int a : Q.groupby) {
     if (P.rels[node].has(a)) continue;
     bool carried = false;

@@ -720,7 +720,6 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
         d.vmask[o] |= 1u << v;
       }
       d.weighted[o] = (d.vmask[o] & d.vmult) ? 1 : 0;
-      if (d.weighted[o] && d.hashed[o]) throw PlanError{LMFAO_EINVAL, "internal: weighted partitioned count hashed"};
       const std::vector<int64_t> st_ = strides_of(P, Q.groupby);
       d.nkey[o] = (int)Q.groupby.size();
       for (int k = 0; k < d.nkey[o]; ++k) {
@@ -768,7 +767,7 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       if (d.hashed[o] || d.n_buckets[o] > 1) {
         d.slot[o] = d.hashed[o] ? n_hash_slots++ : n_dense_slots++;
         if (d.weighted[o]) d.wslot[o] = n_weight_slots++;
-        d.tile_rows[o] = part_tile_rows(d.hashed[o] != 0);
+        d.tile_rows[o] = part_tile_rows(d.hashed[o] != 0, d.weighted[o] != 0);
         d.n_tiles[o] = (int)((n + d.tile_rows[o] - 1) / d.tile_rows[o]);
         d.toff_base[o] = toff_total;
         toff_total += (int64_t)d.n_tiles[o] * (d.n_buckets[o] + 1);
@@ -795,6 +794,9 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
     launch_fill(d.btotal, (int64_t)d.n_out * kPartMaxBuckets * 4, st);
     HIP_OK(hipGetLastError());
     d.partw = n_weight_slots ? (uint32_t*)dalloc(S, (size_t)n_weight_slots * std::max<int64_t>(n, 1) * 4) : nullptr;
+    bool weighted_hashed = false;
+    for (int o = 0; o < d.n_out; ++o) weighted_hashed |= d.weighted[o] && d.hashed[o];
+    d.partwb = weighted_hashed ? (uint32_t*)dalloc(S, (size_t)n_weight_slots * std::max<int64_t>(n, 1) * 4) : nullptr;
     // per-row bytes and view counts: shared with an earlier launch set of the
     // node that reads the same views in the same row order
     std::string rows_key = std::to_string(r) + (sorted ? ":sorted" : ":raw");
@@ -864,7 +866,7 @@ static void build_partition(Prep& S, int gi, const void* const* const* cols, hip
       s.dev = (void*)ddev;
       s.part = d;
       s.rows = n;
-      s.grid = (int)((n + part_tile_rows(false) - 1) / part_tile_rows(false));
+      s.grid = (int)((n + part_tile_rows(false, false) - 1) / part_tile_rows(false, false));
       s.alg_read = rd;
       s.alg_write = wr;
       s.relation = r;

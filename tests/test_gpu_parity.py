@@ -319,7 +319,8 @@ def test_weighted_partition_count(eng, seed, max_dom):
     # SUM(1) group-bys rooted at R2 and R3 count each row with the count of
     # R1 tuples per key b carried by the view into it (about 65 per key):
     # the partition count multiplies rows by those counts, in tables of one
-    # slice (domains up to 20,000) or of several (up to 10^6)
+    # slice (domains up to 20,000), of several (up to 10^6), and hashed
+    # (pairs past 2^24 cells)
     p = W.rkmeans_chain(seed=seed, n1=400_000, n2=6_000, n3=500, n_x=4, n_y=6, n_z=6, max_dom=max_dom)
     print(f"[case] weighted partition seed {seed} max_dom {max_dom}", flush=True)
     plan = eng.Plan(p, precision="f32", policy="fact")
@@ -329,6 +330,9 @@ def test_weighted_partition_count(eng, seed, max_dom):
     assert any(":R2:part_" in n for n in names) and any(":R3:part_" in n for n in names), names
     if max_dom > 1 << 15:
         assert any(":R2:part_slices" in n for n in names), names
+        # pairs of R2 (R3) attributes past 2^24 cells: weighted hashed tables
+        hashed = [p["batch"][h["query"]]["groupby"] for h in prep.describe()["hash_tables"]]
+        assert any(all(a[0] in "yz" for a in g) for g in hashed), hashed
     compare_all(prep.results(), oracle.evaluate(p), F32_TOL, f"weighted_partition_{seed}")
 
 
