@@ -2993,7 +2993,7 @@ __global__ void k_part_reduce(const DPartCount* __restrict__ Dp) {
 // repeated with a larger table).
 constexpr int kPartWaveSlots = 512;
 constexpr int kPartHashWaves = 16;
-constexpr int kPartSubCells = 256;
+constexpr int kPartSubCells = 384;
 constexpr int kPartMaxSub = 4096;
 constexpr int kPartHashLds = kPartWaveSlots * kPartHashWaves * 12 + (2 * kPartMaxSub + 2) * 4;
 template <bool W>
