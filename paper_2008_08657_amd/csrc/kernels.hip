@@ -1928,6 +1928,25 @@ __device__ __forceinline__ double col_d(const DContract* C, const DColB& B, int6
   return x;
 }
 
+// col_d in two steps: the global load of the piece's partial sum or count,
+// which depends on nothing staged in LDS, and the code tests and factors
+// applied to it afterwards
+template <typename T>
+__device__ __forceinline__ double col_raw(const DContract* C, const DColB& B, int64_t p) {
+  if (B.kind == B_PSI_F) return (double)((const T*)C->psi_f)[p * C->psi_f_stride + B.entry];
+  return (double)(C->row_pieces ? (C->w ? C->w[p] : 1) : C->psi_i[p * C->psi_i_stride + B.entry]);
+}
+__device__ __forceinline__ double col_finish(const DColB& B, double raw, const int32_t* codes, const double* atoms) {
+  if (B.kind == B_PSI_F || B.kind == B_PSI_I) return raw;
+  const DFeat& F = B.feat;
+  double x = raw;
+  if (F.c1 >= 0 && codes[F.c1] != F.v1) x = 0.0;
+  if (F.c2 >= 0 && codes[F.c2] != F.v2) x = 0.0;
+  if (F.a1 >= 0) x *= atoms[F.a1];
+  if (F.a2 >= 0) x *= atoms[F.a2];
+  return x;
+}
+
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kGemmMT = 64;   // features per block: 4 wavefronts x 16 rows
 
@@ -1942,8 +1961,16 @@ int gemm_macro_tiles(int nf, int ng) {
 // of F (features x pieces) and B (columns x pieces) there, and multiplies them
 // on the matrix cores; F and B never travel through HBM.  Block (x, y): K
 // range x, macro-tile y (64 features x 16*TN columns).  Scatter cells are
-// evaluated by the y == 0 blocks.
+// evaluated by the y == 0 blocks.  The loads of a chunk that need nothing
+// from LDS (the piece keys of the outer views and the pieces' partial sums)
+// are issued into registers while the chunk before it is built and
+// multiplied, so a chunk waits on two rounds of dependent loads instead of
+// four.  This holds for the FP64 tile kernels; in the BF16 split kernels
+// the registers it takes would cost a wave per SIMD of occupancy.
 constexpr int kFKC = 16;
+constexpr int kFThreads = 256;   // one B entry per thread and column tile of 16
+static_assert(kFKC * 16 == kFThreads, "each thread builds TN entries of the B slice");
+static_assert(kFKC * kMaxViews <= kFThreads, "each thread looks up at most one view row");
 
 int contract_fused_lds_bytes(const DContract& C, int tn) {
   const int nt = 16 * tn;
@@ -1981,7 +2008,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBKS = kFKC + 4;   // bf16 row stride of the split tiles (8-byte aligned rows of 40 bytes)
 
 template <typename T, int TN, int NS>
-__global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restrict__ C, const DGemm* __restrict__ G) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS > 0 ? 1 : TN < 8 ? 4 : 3))) void k_contract_fused(const DContract* __restrict__ C, const DGemm* __restrict__ G) {
   constexpr int NT = 16 * TN;
   constexpr int SA = kGemmMT + 16;
   constexpr int SB = (NT % 32 == 0) ? NT + 16 : NT;
@@ -2019,16 +2046,52 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
   f64x4 acc[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
-  __syncthreads();
-  for (int64_t cb = kb; cb < ke; cb += kFKC) {
-    const int np = (int)std::min<int64_t>(kFKC, ke - cb);
-    for (int t = threadIdx.x; t < np * NV; t += blockDim.x) {
-      const int pi = t / NV, v = t % NV;
+  // entry i of this thread's (FP64, piece-major) B slice: piece and column
+  // of t = tid + 256 i
+  const int tid = threadIdx.x;
+  int tq = tid;   // made opaque once per chunk: the column records stay in LDS, not in registers
+  auto b_pi = [&](int i) { return (tq + kFThreads * i) / NT; };
+  auto b_gl = [&](int i) { return (tq + kFThreads * i) % NT; };
+  constexpr bool kPreB = NS == 0;
+  int64_t nx_vr = 0;
+  double nx_b[TN];
+  auto prefetch = [&](int64_t c0) {
+    const int npn = (int)std::min<int64_t>(kFKC, ke - c0);
+    if (kPreB && tid < npn * NV) {
+      const int pi = tid / NV, v = tid % NV;
       const DView& V = C->views[v];
       int64_t vr = 0;
-      for (int k = 0; k < V.nkey; ++k) vr += ld_int(C->pcols[V.key_src[k]], cb + pi) * V.key_stride[k];
-      vrow_s[pi * kMaxViews + v] = vr;
-      vcnt_s[pi * kMaxViews + v] = V.cnt[vr];
+      for (int k = 0; k < V.nkey; ++k) vr += ld_int(C->pcols[V.key_src[k]], c0 + pi) * V.key_stride[k];
+      nx_vr = vr;
+    }
+    if constexpr (kPreB) {
+#pragma unroll
+      for (int i = 0; i < TN; ++i) {
+        const int pi = b_pi(i), gl = b_gl(i);
+        nx_b[i] = (pi < npn && g0 + gl < NG) ? col_raw<T>(C, col_s[gl], c0 + pi) : 0.0;
+      }
+    }
+  };
+  __syncthreads();
+  if (kPreB && kb < ke) prefetch(kb);
+  for (int64_t cb = kb; cb < ke; cb += kFKC) {
+    const int np = (int)std::min<int64_t>(kFKC, ke - cb);
+    if constexpr (kPreB) {
+      asm volatile("" : "+v"(tq));
+      if (tid < np * NV) {
+        const int pi = tid / NV, v = tid % NV;
+        vrow_s[pi * kMaxViews + v] = nx_vr;
+        vcnt_s[pi * kMaxViews + v] = C->views[v].cnt[nx_vr];
+      }
+    } else {
+      for (int t = threadIdx.x; t < np * NV; t += blockDim.x) {
+        const int pi = t / NV, v = t % NV;
+        const DView& V = C->views[v];
+        int64_t vr = 0;
+        for (int k = 0; k < V.nkey; ++k) vr += ld_int(C->pcols[V.key_src[k]], cb + pi) * V.key_stride[k];
+        vrow_s[pi * kMaxViews + v] = vr;
+        vcnt_s[pi * kMaxViews + v] = V.cnt[vr];
+      }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < np * NM; t += blockDim.x) {
@@ -2094,12 +2157,22 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
       }
       As[pi * SA + fl] = x;
     }
-    for (int t = threadIdx.x; t < kFKC * NT; t += blockDim.x) {
-      const int pi = t / NT, gl = t % NT, g = g0 + gl;
-      Bs[pi * SB + gl] =
-          (pi < np && g < NG) ? col_d<T>(C, col_s[gl], cb + pi, code_s + pi * NC, atom_s + pi * NA) : 0.0;
+    if constexpr (kPreB) {
+#pragma unroll
+      for (int i = 0; i < TN; ++i) {
+        const int pi = b_pi(i), gl = b_gl(i), g = g0 + gl;
+        Bs[pi * SB + gl] =
+            (pi < np && g < NG) ? col_finish(col_s[gl], nx_b[i], code_s + pi * NC, atom_s + pi * NA) : 0.0;
+      }
+    } else {
+      for (int t = threadIdx.x; t < kFKC * NT; t += blockDim.x) {
+        const int pi = t / NT, gl = t % NT, g = g0 + gl;
+        Bs[pi * SB + gl] =
+            (pi < np && g < NG) ? col_d<T>(C, col_s[gl], cb + pi, code_s + pi * NC, atom_s + pi * NA) : 0.0;
+      }
     }
     }
+    if (kPreB && cb + kFKC < ke) prefetch(cb + kFKC);
     if (do_scatter) {
       const int n_sc = C->n_scatter;
       for (int t = threadIdx.x; t < np * n_sc; t += blockDim.x) {
@@ -2193,7 +2266,7 @@ __global__ __launch_bounds__(256) void k_contract_fused(const DContract* __restr
 template <typename T, int NS>
 static void launch_contract_fused_t(const DContract* c, const DGemm* g, int tn, int gx, int gy, int lds,
                                     hipStream_t s) {
-  dim3 grid(gx, gy), b(256);
+  dim3 grid(gx, gy), b(kFThreads);
   switch (tn) {
 #define CASE(N)                                                               \
   case N:                                                                     \
