@@ -1966,7 +1966,10 @@ int gemm_macro_tiles(int nf, int ng) {
 // are issued into registers while the chunk before it is built and
 // multiplied, so a chunk waits on two rounds of dependent loads instead of
 // four.  This holds for the FP64 tile kernels; in the BF16 split kernels
-// the registers it takes would cost a wave per SIMD of occupancy.
+// the registers it takes would cost a wave per SIMD of occupancy.  The
+// descriptors that lanes index by their own view, atom or column (views,
+// piece columns, outer atoms and codes) are copied to LDS once per block, so
+// that no global load of a descriptor precedes the load of a value.
 constexpr int kFKC = 16;
 constexpr int kFThreads = 256;   // one B entry per thread and column tile of 16
 static_assert(kFKC * 16 == kFThreads, "each thread builds TN entries of the B slice");
@@ -1979,6 +1982,8 @@ int contract_fused_lds_bytes(const DContract& C, int tn) {
   b += (int64_t)kFKC * (2 * kMaxViews * 8 + C.n_masks * 8 + C.n_atoms * 8) + (int64_t)kFKC * C.n_codes * 4;
   b = (b + 15) & ~(int64_t)15;
   b += (int64_t)kGemmMT * sizeof(DFeat) + (int64_t)nt * sizeof(DColB);
+  b += (int64_t)C.n_pcols * sizeof(DCol) + (int64_t)C.n_views * sizeof(DView) +
+       (int64_t)(C.n_atoms + C.n_codes) * sizeof(DAtom);
   return (int)((b + 15) & ~(int64_t)15);
 }
 int contract_fused_chunk() { return kFKC; }
@@ -2026,6 +2031,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS > 0 ? 1 
   dp = (unsigned char*)(((uintptr_t)dp + 15) & ~(uintptr_t)15);
   DFeat* feat_s = (DFeat*)dp;                              // this block's features
   DColB* col_s = (DColB*)(feat_s + kGemmMT);               // this block's columns
+  DCol* pcol_d = (DCol*)(col_s + NT);                      // descriptors: [n_pcols]
+  DView* view_d = (DView*)(pcol_d + C->n_pcols);           // [NV]
+  DAtom* atom_d = (DAtom*)(view_d + NV);                   // [NA]
+  DAtom* code_d = atom_d + NA;                             // [NC]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n_ntiles = (NG + NT - 1) / NT;
   const int f0 = (blockIdx.y / n_ntiles) * kGemmMT;
@@ -2034,6 +2043,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS > 0 ? 1 
     if (f0 + i < NF) feat_s[i] = C->feats[f0 + i];
   for (int i = threadIdx.x; i < NT; i += blockDim.x)
     if (g0 + i < NG) col_s[i] = C->cols[g0 + i];
+  for (int i = threadIdx.x; i < C->n_pcols; i += blockDim.x) pcol_d[i] = C->pcols[i];
+  for (int i = threadIdx.x; i < NV; i += blockDim.x) view_d[i] = C->views[i];
+  for (int i = threadIdx.x; i < NA; i += blockDim.x) atom_d[i] = C->atoms[i];
+  for (int i = threadIdx.x; i < NC; i += blockDim.x) code_d[i] = C->codes[i];
   const int64_t kb = (int64_t)blockIdx.x * G->k_per_block;
   const int64_t ke = std::min<int64_t>(G->n, kb + G->k_per_block);
   const bool do_scatter = blockIdx.y == 0;
@@ -2059,9 +2072,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS > 0 ? 1 
     const int npn = (int)std::min<int64_t>(kFKC, ke - c0);
     if (kPreB && tid < npn * NV) {
       const int pi = tid / NV, v = tid % NV;
-      const DView& V = C->views[v];
+      const DView& V = view_d[v];
       int64_t vr = 0;
-      for (int k = 0; k < V.nkey; ++k) vr += ld_int(C->pcols[V.key_src[k]], c0 + pi) * V.key_stride[k];
+      for (int k = 0; k < V.nkey; ++k) vr += ld_int(pcol_d[V.key_src[k]], c0 + pi) * V.key_stride[k];
       nx_vr = vr;
     }
     if constexpr (kPreB) {
@@ -2081,14 +2094,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS > 0 ? 1 
       if (tid < np * NV) {
         const int pi = tid / NV, v = tid % NV;
         vrow_s[pi * kMaxViews + v] = nx_vr;
-        vcnt_s[pi * kMaxViews + v] = C->views[v].cnt[nx_vr];
+        vcnt_s[pi * kMaxViews + v] = view_d[v].cnt[nx_vr];
       }
     } else {
       for (int t = threadIdx.x; t < np * NV; t += blockDim.x) {
         const int pi = t / NV, v = t % NV;
-        const DView& V = C->views[v];
+        const DView& V = view_d[v];
         int64_t vr = 0;
-        for (int k = 0; k < V.nkey; ++k) vr += ld_int(C->pcols[V.key_src[k]], cb + pi) * V.key_stride[k];
+        for (int k = 0; k < V.nkey; ++k) vr += ld_int(pcol_d[V.key_src[k]], cb + pi) * V.key_stride[k];
         vrow_s[pi * kMaxViews + v] = vr;
         vcnt_s[pi * kMaxViews + v] = V.cnt[vr];
       }
@@ -2104,23 +2117,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS > 0 ? 1 
     }
     for (int t = threadIdx.x; t < np * NA; t += blockDim.x) {
       const int pi = t / NA, a = t % NA;
-      const DAtom& At = C->atoms[a];
+      const DAtom& At = atom_d[a];
       T x;
-      if (At.kind == SRC_COL) x = ld_val<T>(C->pcols[At.src], cb + pi);
+      if (At.kind == SRC_COL) x = ld_val<T>(pcol_d[At.src], cb + pi);
       else {
         const int v = At.src;
-        x = vcnt_s[pi * kMaxViews + v] ? view_val<T>(C->views[v], vrow_s[pi * kMaxViews + v], At.slot) : (T)0;
+        x = vcnt_s[pi * kMaxViews + v] ? view_val<T>(view_d[v], vrow_s[pi * kMaxViews + v], At.slot) : (T)0;
       }
       atom_s[pi * NA + a] = (double)x;
     }
     for (int t = threadIdx.x; t < np * NC; t += blockDim.x) {
       const int pi = t / NC, c = t % NC;
-      const DAtom& Cd = C->codes[c];
+      const DAtom& Cd = code_d[c];
       int32_t x;
-      if (Cd.kind == SRC_COL) x = (int32_t)ld_int(C->pcols[Cd.src], cb + pi);
+      if (Cd.kind == SRC_COL) x = (int32_t)ld_int(pcol_d[Cd.src], cb + pi);
       else {
         const int v = Cd.src;
-        const DView& V = C->views[v];
+        const DView& V = view_d[v];
         x = vcnt_s[pi * kMaxViews + v] ? V.codes[vrow_s[pi * kMaxViews + v] * V.n_codes + Cd.slot] : -1;
       }
       code_s[pi * NC + c] = x;
